@@ -1,0 +1,110 @@
+"""Plant plausible mistakes in the oracle (on the CPU, by monkeypatching) and check
+that at least one pin catches each.  This is evidence that the pins constrain the
+oracle rather than restate it."""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as pins
+from oracle import wc4d_oracle as O
+
+
+def _fails(fn, *a):
+    try:
+        fn(*a)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_wrong_stencil_sign_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "advdiff_step", lambda x, c, r: (c + r) * np.roll(x, -1, 0) + (1 - c - 2 * r) * x + r * np.roll(x, 1, 0))
+    assert _fails(pins.test_advdiff_fourier_multiplier, 0.5, 0.1)
+    assert _fails(pins.test_advdiff_pure_upwind_courant_one_is_exact_shift)
+
+
+def test_wrong_transpose_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "advdiff_step_T", lambda w, c, r: O.advdiff_step(w, c, r))
+    assert _fails(pins.test_advdiff_transpose)
+    assert _fails(pins.test_Linv_adjoint_dot_product, pins.tiny_advdiff)
+
+
+def test_wrong_rk4_weight_is_caught(monkeypatch):
+    def bad(x, F, dt):
+        k1 = O.l96_rhs(x, F); k2 = O.l96_rhs(x + 0.5 * dt * k1, F)
+        k3 = O.l96_rhs(x + 0.5 * dt * k2, F); k4 = O.l96_rhs(x + dt * k3, F)
+        return x + (dt / 6.0) * (k1 + 2.0 * k2 + k3 + 2.0 * k4)
+    monkeypatch.setattr(O, "l96_rk4_step", bad)
+    assert _fails(pins.test_l96_rk4_fourth_order_against_reference_integrator)
+
+
+def test_wrong_l96_sign_is_caught(monkeypatch):
+    orig = O.l96_rhs
+    monkeypatch.setattr(O, "l96_rhs", lambda x, F: orig(x, F) + 2 * np.roll(x, 2, 0) * np.roll(x, 1, 0))
+    assert _fails(pins.test_l96_equilibrium_and_constant_forcing)
+
+
+def test_tlm_missing_stage_term_is_caught(monkeypatch):
+    orig = O._l96_jac
+    monkeypatch.setattr(O, "_l96_jac", lambda y, d: orig(y, d) + d)
+    assert _fails(pins.test_l96_tlm_matches_finite_differences)
+
+
+def test_adjoint_dropped_term_is_caught(monkeypatch):
+    orig = O._l96_jac_T
+    # drop the -y_{j+1} a_{j+2} term of J^T a
+    monkeypatch.setattr(O, "_l96_jac_T", lambda y, a: orig(y, a) + np.roll(y, -1, 0) * np.roll(a, -2, 0))
+    assert _fails(pins.test_l96_adjoint_dot_product)
+
+
+def test_missing_model_error_block_is_caught(monkeypatch):
+    # sweep that forgets p_{i+1}
+    def bad(prob, P):
+        Pl = P.reshape(prob.N + 1, prob.n, -1)
+        Xl = np.empty_like(Pl); Xl[0] = Pl[0]
+        for i in range(prob.N):
+            Xl[i + 1] = prob.M(i, Xl[i])
+        return Xl.reshape(P.shape)
+    monkeypatch.setattr(O, "apply_Linv", bad)
+    assert _fails(pins.test_Linv_equals_block_formula, pins.tiny_advdiff)
+
+
+def test_dsqrt_transposed_blocks_are_caught(monkeypatch):
+    def bad(prob, X):
+        Xl = X.reshape(prob.N + 1, prob.n, -1); Yl = np.empty_like(Xl)
+        Yl[0] = prob.Qsqrt @ Xl[0]
+        for i in range(1, prob.N + 1):
+            Yl[i] = prob.Bsqrt @ Xl[i]
+        return Yl.reshape(X.shape)
+    monkeypatch.setattr(O, "apply_Dsqrt", bad)
+    assert _fails(pins.test_A_equals_transformed_unpreconditioned_hessian, pins.tiny_advdiff)
+
+
+def test_ritzit_without_square_root_is_caught(monkeypatch):
+    orig = O.ritzit
+    def bad(applyA, G, k):
+        U, t = orig(applyA, G, k)
+        return U, t * t
+    monkeypatch.setitem(O.METHODS, "ritzit", bad)
+    assert _fails(pins.test_full_sketch_recovers_exact_spectrum, "ritzit")
+
+
+def test_lmp_wrong_exponent_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "lmp_dense_C", lambda U, th: np.eye(U.shape[0]) + U @ np.diag(1 / th - 1) @ U.T)
+    assert _fails(pins.test_lmp_factor_identities)
+    assert _fails(pins.test_exact_pair_lmp_spectrum_theorem)
+
+
+def test_pcg_wrong_beta_is_caught(monkeypatch):
+    orig = O.pcg
+    def bad(applyA, b, x0=None, lmp=None, tol=1e-6, maxit=100, criterion=0):
+        x = np.zeros_like(b); r = b.copy(); p = r.copy(); rr = r @ r
+        hist = []
+        for it in range(1, maxit + 1):
+            Ap = applyA(p); a = rr / (p @ Ap); x = x + a * p; r = r - a * Ap
+            rn = r @ r; p = r + (rr / rn) * p; rr = rn   # inverted beta
+            hist.append(np.sqrt(rr) / np.linalg.norm(b))
+            if hist[-1] <= tol:
+                break
+        return O.PCGResult(x, it, hist[-1] <= tol, hist[-1], hist[-1], 0.0, hist, hist, [0.0] * it, [], [])
+    monkeypatch.setattr(O, "pcg", bad)
+    assert _fails(pins.test_cg_finite_termination_on_three_distinct_eigenvalues)

@@ -1,0 +1,469 @@
+"""Pins of the FP64 oracle to facts other than itself: sizes printed in the
+paper, closed forms, textbook special cases, invariants the paper states, and
+brute force on tiny inputs.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg as sla
+
+from oracle import wc4d_oracle as O
+from synthetic import (C1, C2, Workload, innovations, l96_initial_state, obs_count, obs_pattern,
+                       random_block, sketch_block)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny_advdiff(n=8, N=4, c=0.5, r=0.1, vs=2, ts=2, m=4, corr="soar", L=2.0):
+    return Workload(name="tiny", model="advdiff", n=n, N=N, c=c, r=r, corr=corr, Lb=L, Lq=L,
+                    sigma_b=1.0, sigma_q=0.3, obs_var_stride=vs, obs_time_stride=ts,
+                    sigma_o2=0.01, m=m, l=2, seed=17)
+
+
+def tiny_l96(n=10, N=4, vs=2, ts=2, m=4):
+    return Workload(name="tinyl96", model="l96", n=n, N=N, F=8.0, dt=0.025, corr="gauss",
+                    Lb=2.0, Lq=2.0, sigma_b=0.2, sigma_q=0.1, obs_var_stride=vs,
+                    obs_time_stride=ts, sigma_o2=0.04, m=m, l=2, seed=29)
+
+
+def build(w):
+    x0 = l96_initial_state(w.n, w.seed) if w.model == "l96" else None
+    return O.make_problem(w, obs_pattern(w), x0=x0)
+
+
+# ----------------------------------------------------------------- sizes
+
+
+def test_paper_sizes_and_observation_counts():
+    cases = json.load(open(os.path.join(GOLDEN, "paper_sizes.json")))["cases"]
+    for c in cases:
+        w = Workload(name="p", model="advdiff", n=c["n"], N=c["N"], obs_var_stride=c["var_stride"],
+                     obs_time_stride=c["time_stride"])
+        assert w.n_A == c.get("n_A", w.n_A)
+        pat = obs_pattern(w)
+        assert obs_count(pat) == c["q"], c["cite"]
+        assert pat[-1][0] == w.N  # the final step is observed
+        prob = O.Problem(n=w.n, N=w.N, model="advdiff", Bsqrt=np.eye(w.n), Qsqrt=np.eye(w.n),
+                         obs=[(i, idx, np.ones(len(idx))) for i, idx in pat])
+        assert prob.n_A == c.get("n_A", prob.n_A) and prob.q == c["q"]
+
+
+# ----------------------------------------------------------------- models
+
+
+def test_advdiff_pure_upwind_courant_one_is_exact_shift():
+    # c = 1, r = 0: the upwind scheme moves the field exactly one cell per step.
+    w = tiny_advdiff(n=12, N=7, c=1.0, r=0.0)
+    prob = build(w)
+    e = np.random.default_rng(0).standard_normal(12)
+    P = np.zeros((prob.n_A, 1))
+    P[:12, 0] = e
+    X = O.apply_Linv(prob, P).reshape(8, 12)
+    for i in range(8):
+        np.testing.assert_array_equal(X[i], np.roll(e, i))
+
+
+@pytest.mark.parametrize("c,r", [(0.5, 0.1), (0.8, 0.0), (0.0, 0.25), (0.3, 0.05)])
+def test_advdiff_fourier_multiplier(c, r):
+    # M e^{i theta j} = g(theta) e^{i theta j}, g = (c+r) e^{-i theta} + (1-c-2r) + r e^{i theta}.
+    n = 16
+    j = np.arange(n)
+    for k in range(n):
+        th = 2 * np.pi * k / n
+        g = (c + r) * np.exp(-1j * th) + (1 - c - 2 * r) + r * np.exp(1j * th)
+        mode = np.exp(1j * th * j)
+        got = O.advdiff_step(mode.real, c, r) + 1j * O.advdiff_step(mode.imag, c, r)
+        np.testing.assert_allclose(got, g * mode, atol=1e-14)
+
+
+def test_advdiff_transpose():
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal((2, 20, 3))
+    lhs = np.sum(O.advdiff_step(x, 0.5, 0.1) * y)
+    rhs = np.sum(x * O.advdiff_step_T(y, 0.5, 0.1))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def test_l96_equilibrium_and_constant_forcing():
+    F = 8.0
+    np.testing.assert_allclose(O.l96_rhs(np.full(12, F), F), 0.0, atol=1e-14)
+    np.testing.assert_allclose(O.l96_rhs(np.zeros(12), F), F)
+    # a one-point state: the product terms vanish, only the damping -X^j remains
+    x = np.zeros(12)
+    x[3] = 2.0
+    f = O.l96_rhs(x, 0.0)
+    expect = np.zeros(12)
+    expect[3] = -2.0
+    np.testing.assert_allclose(f, expect)
+    # a two-point state exercises every product term: X^2 = a, X^3 = b
+    a, b = 1.5, -0.7
+    x = np.zeros(12)
+    x[2], x[3] = a, b
+    f = O.l96_rhs(x, 0.0)
+    # by hand: dX^2/dt = -a, dX^3/dt = -b, dX^4/dt = -X^2 X^3 = -ab, every other tendency is 0
+    expect = np.zeros(12)
+    expect[2], expect[3], expect[4] = -a, -b, -a * b
+    np.testing.assert_allclose(f, expect, atol=1e-15)
+
+
+def test_l96_rk4_fourth_order_against_reference_integrator():
+    x0 = l96_initial_state(20, 123)
+    T = 0.2
+    ref = scipy.integrate.solve_ivp(lambda t, y: O.l96_rhs(y, 8.0), (0, T), x0, method="DOP853",
+                                    rtol=1e-13, atol=1e-13).y[:, -1]
+    errs = []
+    for steps in (8, 16):
+        dt = T / steps
+        x = x0.copy()
+        for _ in range(steps):
+            x = O.l96_rk4_step(x, 8.0, dt)
+        errs.append(np.linalg.norm(x - ref))
+    order = np.log2(errs[0] / errs[1])
+    assert 3.7 < order < 4.4, order
+
+
+def test_l96_tlm_matches_finite_differences():
+    x = l96_initial_state(24, 5)
+    dx = np.random.default_rng(2).standard_normal(24)
+    h = 1e-6
+    fd = (O.l96_rk4_step(x + h * dx, 8.0, 0.025) - O.l96_rk4_step(x - h * dx, 8.0, 0.025)) / (2 * h)
+    tl = O.l96_tlm_step(x, dx, 8.0, 0.025)
+    assert np.linalg.norm(fd - tl) <= 1e-8 * np.linalg.norm(tl)
+
+
+def test_l96_adjoint_dot_product():
+    x = l96_initial_state(24, 6)
+    rng = np.random.default_rng(3)
+    u, v = rng.standard_normal((2, 24))
+    lhs = O.l96_tlm_step(x, u, 8.0, 0.025) @ v
+    rhs = u @ O.l96_adj_step(x, v, 8.0, 0.025)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("maker", [tiny_advdiff, tiny_l96, lambda: C1, lambda: C2])
+def test_Linv_adjoint_dot_product(maker):
+    prob = build(maker())
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((prob.n_A, 3))
+    v = rng.standard_normal((prob.n_A, 3))
+    lhs = np.sum(O.apply_Linv(prob, u) * v)
+    rhs = np.sum(u * O.apply_LinvT(prob, v))
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(O.apply_Linv(prob, u)).max() * np.abs(v).sum()
+
+
+@pytest.mark.parametrize("maker", [tiny_advdiff, tiny_l96])
+def test_Linv_equals_block_formula(maker):
+    prob = build(maker())
+    Lsweep = O.apply_Linv(prob, np.eye(prob.n_A))
+    np.testing.assert_allclose(Lsweep, O.dense_Linv(prob), atol=1e-12)
+
+
+# ----------------------------------------------------------------- covariances
+
+
+def test_chordal_distance_is_euclidean_on_circle():
+    n = 40
+    ang = 2 * np.pi * np.arange(n) / n
+    R = n / (2 * np.pi)
+    pts = R * np.stack([np.cos(ang), np.sin(ang)], 1)
+    eu = np.linalg.norm(pts[:, None, :] - pts[None, :, :], axis=2)
+    np.testing.assert_allclose(O.chordal_distance(n), eu, atol=1e-12)
+
+
+def test_correlation_values():
+    # rho(0) = 1 and the closed forms evaluated at geometric (circle) distances
+    n = 64
+    ang = 2 * np.pi * np.arange(n) / n
+    pts = (n / (2 * np.pi)) * np.stack([np.cos(ang), np.sin(ang)], 1)
+    d = np.linalg.norm(pts[:, None, :] - pts[None, :, :], axis=2)
+    L = 4.0
+    np.testing.assert_allclose(O.correlation_matrix(n, "soar", L), (1 + d / L) * np.exp(-d / L), atol=1e-13)
+    L = 2.0
+    np.testing.assert_allclose(O.correlation_matrix(n, "gauss", L), np.exp(-d * d / (2 * L * L)), atol=1e-13)
+    np.testing.assert_allclose(np.diag(O.correlation_matrix(n, "soar", 3.0)), 1.0)
+
+
+@pytest.mark.parametrize("n,kind,L", [(40, "soar", 4.0), (40, "soar", 10.0), (80, "gauss", 2.0), (64, "soar", 4.0)])
+def test_correlation_spd_circulant_and_sqrt(n, kind, L):
+    C = O.correlation_matrix(n, kind, L)
+    lam = np.linalg.eigvalsh(C)
+    assert lam.min() > 0
+    # circulant: eigenvalues are the DFT of the first row
+    fft_eigs = np.sort(np.fft.fft(C[0]).real)
+    np.testing.assert_allclose(np.sort(lam), fft_eigs, atol=1e-10 * lam.max())
+    S = O.sym_sqrt(C)
+    np.testing.assert_allclose(S, S.T, atol=1e-14)
+    np.testing.assert_allclose(S @ S, C, atol=1e-12)
+    assert np.linalg.eigvalsh(S).min() > 0
+
+
+def test_wrap_distance_soar_would_be_indefinite():
+    # why the chordal distance: SOAR on the wrap-around distance min(k, n-k) is indefinite
+    n, L = 40, 10.0
+    k = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :])
+    dw = np.minimum(k, n - k)
+    Cw = (1 + dw / L) * np.exp(-dw / L)
+    assert np.linalg.eigvalsh(Cw).min() < 0
+    assert np.linalg.eigvalsh(O.correlation_matrix(n, "soar", L)).min() > 0
+
+
+# ----------------------------------------------------------------- the operator
+
+
+@pytest.mark.parametrize("maker", [tiny_advdiff, tiny_l96, lambda: C1])
+def test_A_symmetric_with_unit_cluster_and_q_large_eigenvalues(maker):
+    prob = build(maker())
+    A = O.dense_A(prob)
+    assert np.abs(A - A.T).max() <= 1e-12 * np.abs(A).max()
+    lam = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert abs(lam.min() - 1.0) < 1e-10 * lam.max()
+    assert int(np.sum(lam > 1 + 1e-8 * lam.max())) == prob.q
+    assert int(np.sum(np.abs(lam - 1) <= 1e-8 * lam.max())) == prob.n_A - prob.q
+
+
+@pytest.mark.parametrize("maker", [tiny_advdiff, tiny_l96])
+def test_A_equals_transformed_unpreconditioned_hessian(maker):
+    # A^pr = D^{1/2} (D^{-1} + L^{-T} H^T R^{-1} H L^{-1}) D^{1/2}, D^{-1} from the covariances
+    w = maker()
+    prob = build(w)
+    B = (w.sigma_b ** 2) * O.correlation_matrix(w.n, w.corr, w.Lb)
+    Q = (w.sigma_q ** 2) * O.correlation_matrix(w.n, w.corr, w.Lq)
+    Dinv = sla.block_diag(np.linalg.inv(B), *([np.linalg.inv(Q)] * w.N))
+    Hess = O.dense_hessian_unprec(prob, Dinv)
+    Ds = O.dense_D(prob, "sqrt")
+    Apr = Ds @ Hess @ Ds
+    A = O.dense_A(prob)
+    np.testing.assert_allclose(A, Apr, atol=1e-8 * np.abs(A).max())
+
+
+def test_rhs_matches_dense_formula():
+    w = tiny_advdiff()
+    prob = build(w)
+    d = innovations(prob.q, 3, 0.1)
+    Li = O.dense_Linv(prob)
+    H, Ri = O.dense_H_Rinv(prob)
+    want = O.dense_D(prob, "sqrt") @ Li.T @ H.T @ Ri @ d
+    np.testing.assert_allclose(O.rhs(prob, d), want, atol=1e-12 * np.abs(want).max())
+
+
+def test_dsqrt_squares_to_covariance():
+    w = tiny_advdiff()
+    prob = build(w)
+    Ds = O.dense_D(prob, "sqrt")
+    B = (w.sigma_b ** 2) * O.correlation_matrix(w.n, w.corr, w.Lb)
+    Q = (w.sigma_q ** 2) * O.correlation_matrix(w.n, w.corr, w.Lq)
+    np.testing.assert_allclose(Ds @ Ds, sla.block_diag(B, *([Q] * w.N)), atol=1e-13)
+
+
+# ----------------------------------------------------------------- randomised EVDs
+
+
+def small_problem():
+    w = tiny_advdiff(n=6, N=3, vs=2, ts=1)   # n_A = 24, q = 9
+    return build(w)
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_full_sketch_recovers_exact_spectrum(method):
+    prob = small_problem()
+    A = O.dense_A(prob)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    G = sketch_block(prob.n_A, prob.n_A, 11)
+    U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, prob.n_A)
+    np.testing.assert_allclose(th, lam, rtol=1e-10, atol=1e-10 * lam[0])
+    np.testing.assert_allclose(U.T @ U, np.eye(prob.n_A), atol=1e-10)
+    np.testing.assert_allclose(U @ np.diag(th) @ U.T, A, atol=1e-9 * lam[0])
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_invariant_subspace_gives_exact_pairs(method):
+    # Rayleigh-Ritz is exact on an invariant subspace (Section 3.3)
+    prob = small_problem()
+    A = O.dense_A(prob)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    m = 6
+    G = V[:, :m] @ np.linalg.qr(np.random.default_rng(5).standard_normal((m, m)))[0]
+    U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, 4)
+    np.testing.assert_allclose(th, lam[:4], rtol=1e-11)
+    np.testing.assert_allclose(A @ U, U * th, atol=1e-10 * lam[0])
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_ritz_values_bounds_and_orthonormality(method):
+    prob = build(C1)
+    A = O.dense_A(prob)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+    assert np.all(np.diff(th) <= 1e-12 * th[0])           # decreasing
+    assert th.min() >= 1 - 1e-10                           # A >= I
+    assert np.all(th <= lam[:C1.k_r] * (1 + 1e-10))       # interlacing / A_nys <= A / sigma(AG) <= lambda
+    np.testing.assert_allclose(U.T @ U, np.eye(C1.k_r), atol=1e-10)
+
+
+def test_block_product_counts_match_table_1():
+    prob = build(C1)
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    for method, count in (("revd", 2), ("nystrom", 2), ("ritzit", 1)):
+        prob.n_apply = 0
+        O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+        assert prob.n_apply == count
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_outputs_depend_only_on_range_of_sketch(method):
+    # any orthonormalisation gives the same Ritz pairs: G -> G O changes nothing
+    prob = build(C1)
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    Orot = np.linalg.qr(np.random.default_rng(6).standard_normal((C1.m, C1.m)))[0]
+    U1, t1 = O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+    U2, t2 = O.METHODS[method](lambda X: O.apply_A(prob, X), G @ Orot, C1.k_r)
+    np.testing.assert_allclose(t1, t2, rtol=1e-9)
+    np.testing.assert_allclose(U1 @ U1.T, U2 @ U2.T, atol=1e-8)
+
+
+# ----------------------------------------------------------------- LMP
+
+
+def test_lmp_factor_identities():
+    prob = build(C1)
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.nystrom(lambda X: O.apply_A(prob, X), G, C1.k_r)
+    C = O.lmp_dense_C(U, th)
+    P = O.lmp_dense_P(U, th)
+    np.testing.assert_allclose(C, C.T, atol=1e-14)
+    np.testing.assert_allclose(C @ C.T, P, atol=1e-12)
+    np.testing.assert_allclose(O.lmp_dense_C_product(U, th), C, atol=1e-12)
+    x = random_block(prob.n_A, 3, 1)
+    np.testing.assert_allclose(O.lmp_apply(U, th, x), C @ x, atol=1e-12)
+
+
+def test_exact_pair_lmp_spectrum_theorem():
+    # k exact pairs: at least k unit eigenvalues are added to the n_A - q cluster and the
+    # rest stay within [lambda_min, lambda_max] (Section 3.2).  k at a spectral gap.
+    prob = build(C1)
+    A = O.dense_A(prob)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    gaps = np.where(np.diff(lam[:prob.q]) < -1e-6 * lam[0])[0]
+    k = int(gaps[gaps >= 4][0] + 1)
+    C = O.lmp_dense_C(V[:, :k], lam[:k])
+    mu = np.linalg.eigvalsh(C.T @ A @ C)
+    ones = int(np.sum(np.abs(mu - 1) < 1e-8 * lam[0]))
+    assert ones == prob.n_A - prob.q + k
+    assert mu.min() > 1 - 1e-8 and mu.max() <= lam[k] * (1 + 1e-9)
+
+
+def test_full_rank_exact_lmp_converges_in_one_iteration():
+    prob = build(tiny_advdiff())
+    A = O.dense_A(prob)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    q = prob.q
+    b = O.rhs(prob, innovations(q, 4, 0.1))
+    res = O.pcg(lambda v: A @ v, b, lmp=(V[:, :q], lam[:q]), tol=1e-10, maxit=10)
+    assert res.iters == 1 and res.converged
+
+
+# ----------------------------------------------------------------- PCG
+
+
+def test_cg_finite_termination_on_three_distinct_eigenvalues():
+    rng = np.random.default_rng(7)
+    Qm = np.linalg.qr(rng.standard_normal((30, 30)))[0]
+    lam = np.repeat([1.0, 7.0, 50.0], 10)
+    A = Qm @ np.diag(lam) @ Qm.T
+    b = rng.standard_normal(30)
+    res = O.pcg(lambda v: A @ v, b, tol=1e-10, maxit=10)
+    assert res.iters == 3 and res.converged
+    np.testing.assert_allclose(res.x, np.linalg.solve(A, b), rtol=1e-9)
+
+
+def test_cg_worst_case_bound_and_monotone_cost():
+    prob = build(C1)
+    A = O.dense_A(prob)
+    b = O.rhs(prob, innovations(prob.q, 8, 0.1))
+    xs = np.linalg.solve(A, b)
+    lam = np.linalg.eigvalsh(A)
+    kappa = lam.max() / lam.min()
+    rho = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    xs_list = []
+
+    def applyA(v):
+        return A @ v
+
+    res = O.pcg(applyA, b, tol=1e-9, maxit=200)
+    # recompute iterates through the same recursion to get the A-norm errors
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    e0 = np.sqrt(xs @ A @ xs)
+    for j in range(1, res.iters + 1):
+        Ap = A @ p
+        a = rr / (p @ Ap)
+        x = x + a * p
+        r = r - a * Ap
+        rn = r @ r
+        p = r + (rn / rr) * p
+        rr = rn
+        e = xs - x
+        assert np.sqrt(e @ A @ e) / e0 <= 2 * rho ** j + 1e-12
+        xs_list.append(x)
+    # oracle iterates agree with this textbook CG and its cost decreases monotonically
+    assert np.all(np.diff(res.hist_J) <= 1e-9 * abs(res.hist_J[0]))
+    np.testing.assert_allclose(res.x, xs_list[-1], rtol=1e-8)
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_pcg_converged_solution_matches_direct_solve(method):
+    prob = build(C1)
+    A = O.dense_A(prob)
+    b = O.rhs(prob, innovations(prob.q, 9, 0.1))
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+    res = O.pcg(lambda v: O.apply_A(prob, v), b, lmp=(U, th), tol=1e-12, maxit=500)
+    assert res.converged
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(res.x - xs) <= 1e-8 * np.linalg.norm(xs)
+    # the recursive true residual agrees with an explicit one
+    s = b - A @ res.x
+    assert abs(np.linalg.norm(s) / np.linalg.norm(b) - res.relres_true) < 1e-9
+
+
+def test_pcg_precond_criterion_is_split_residual():
+    prob = build(C1)
+    b = O.rhs(prob, innovations(prob.q, 10, 0.1))
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.nystrom(lambda X: O.apply_A(prob, X), G, C1.k_r)
+    res = O.pcg(lambda v: O.apply_A(prob, v), b, lmp=(U, th), tol=1e-6, maxit=500,
+                criterion=O.RES_PRECOND)
+    Cb = O.lmp_apply(U, th, b)
+    xhat_res = Cb - O.lmp_apply(U, th, O.apply_A(prob, res.x))   # C^T (b - A x)
+    assert abs(np.linalg.norm(xhat_res) / np.linalg.norm(Cb) - res.relres_precond) < 1e-9
+    assert res.relres_precond <= 1e-6
+
+
+# ----------------------------------------------------------------- the paper's qualitative results
+
+
+def test_paper_qualitative_lmp_spectra_on_advection():
+    # Section 5.1: the REVD-LMP pushes the smallest eigenvalue of C^T A C below one, the
+    # Nystrom and ritzit LMPs keep it close to one; ritzit underestimates the largest
+    # eigenvalues most.
+    prob = build(C1)
+    A = O.dense_A(prob)
+    lam_max = np.linalg.eigvalsh(A).max()
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    mins, th0 = {}, {}
+    for method in ("revd", "nystrom", "ritzit"):
+        U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+        C = O.lmp_dense_C(U, th)
+        mins[method] = np.linalg.eigvalsh(C.T @ A @ C).min()
+        th0[method] = th[0]
+    assert mins["revd"] < 0.9
+    assert mins["nystrom"] > mins["revd"] and mins["ritzit"] > mins["revd"]
+    assert th0["ritzit"] < th0["revd"] <= lam_max * (1 + 1e-12) and th0["ritzit"] < th0["nystrom"]
