@@ -1,0 +1,197 @@
+/*
+ * wc4d.h -- C-ABI of libwc4d.so: the inner loop of randomised-LMP preconditioned
+ * forcing-formulation weak-constraint 4D-Var on one AMD MI355X (gfx950) GPU.
+ *
+ * Method: Dauzickaite, Lawless, Scott, van Leeuwen, "Randomised preconditioning
+ * for the forcing formulation of weak constraint 4D-Var".  The library builds the
+ * first-level preconditioned Hessian (Section 2.2, eq. forcing_1stlvl_prec)
+ *     A = I + D^{1/2} L^{-T} H^T R^{-1} H L^{-1} D^{1/2},
+ * estimates its leading eigenpairs with REVD / Nystrom / REVD_ritzit
+ * (Section 4, Algorithms 3-5), forms the spectral LMP (Section 3.2, eqs.
+ * spectral_LMP and spectral_LMP_factor) and solves A x = b with split PCG
+ * (Section 3.1, Algorithm 1).
+ *
+ * Conventions shared by every call
+ *   - n: state size per time level; N: number of model steps (N+1 levels t_0..t_N);
+ *     n_A = n (N+1) is the size of the control vector (x_0, eta_1..eta_N).
+ *   - A block of m vectors is a column-major n_A x m double array with leading
+ *     dimension ld >= n_A.  Row i*n + j holds time level i, grid point j.
+ *   - Host pointers are read during the call and may be freed on return
+ *     (setup data is copied).  Device pointers (hipMalloc'ed, on the problem's
+ *     device) are borrowed: they must stay valid until the stream reaches the
+ *     point where the call's work ends.  Device calls are asynchronous on the
+ *     given stream unless stated otherwise; stream 0 is the null stream.
+ *   - Every function returns a status (WC4D_OK = 0 or a negative WC4D_E* code);
+ *     no C++ exception crosses the ABI.  wc4d_last_error() describes the last
+ *     failure on a handle.  A handle is not thread-safe; use one per thread.
+ *   - Device arithmetic is float64 unless a precision mode says otherwise.
+ */
+#ifndef WC4D_H
+#define WC4D_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wc4d_problem_s* wc4d_problem; /* owns device copies of the setup data and workspaces */
+typedef struct wc4d_lmp_s* wc4d_lmp;         /* owns U (n_A x k_r) and theta (k_r) on the device     */
+
+enum {
+  WC4D_OK = 0,
+  WC4D_EINVAL = -1,     /* invalid argument (shape, index, pointer, enum value)            */
+  WC4D_ENOMEM = -2,     /* device or host allocation failed                                */
+  WC4D_EHIP = -3,       /* a HIP runtime call failed                                       */
+  WC4D_ENOTSPD = -4,    /* Cholesky of a Gram/projected matrix met a non-positive pivot    */
+  WC4D_EBREAKDOWN = -5, /* PCG breakdown: p^T A p <= 0 or not finite                       */
+  WC4D_ENOCONV = -6,    /* PCG reached maxit without meeting the tolerance                 */
+  WC4D_ESTATE = -7      /* call out of order (e.g. apply before finalize)                  */
+};
+
+enum { WC4D_CORR_SOAR = 0, WC4D_CORR_GAUSS = 1 };
+enum { WC4D_REVD = 0, WC4D_NYSTROM = 1, WC4D_RITZIT = 2 };
+enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
+enum { WC4D_PREC_FP64 = 0 };
+
+/* Library version (major*10000 + minor*100 + patch) and status-code names. */
+int wc4d_version(void);
+const char* wc4d_status_string(int status);
+
+/* ---------------------------------------------------------------- setup -- */
+
+/* Create a problem for state size n >= 1 and N >= 1 model steps on HIP device
+ * `device`.  *out receives the handle.  Allocates nothing on the device yet. */
+int wc4d_create(wc4d_problem* out, int n, int N, int device);
+int wc4d_destroy(wc4d_problem p);
+const char* wc4d_last_error(wc4d_problem p); /* valid until the next call on p */
+
+/* Tangent-linear model M_i (Section 2.1, x_{i+1} = M_i x_i + p_{i+1}).
+ * Advection-diffusion (Section 5.1's upwind advection plus explicit diffusion):
+ *   (M x)_j = (c + r) x_{j-1} + (1 - c - 2r) x_j + r x_{j+1}, periodic in j,
+ *   time-invariant; requires c >= 0, r >= 0, c + 2r <= 1. */
+int wc4d_set_model_advdiff(wc4d_problem p, double c, double r);
+
+/* Lorenz-96 (Section 5.2, eq. lorenz96), classical RK4 with step dt and forcing F.
+ * traj: host, (N+1) x n row-major, the nonlinear trajectory x_0..x_N; M_i is the
+ * exact derivative of the RK4 step taken from traj[i].  Requires n >= 4. */
+int wc4d_set_model_l96(wc4d_problem p, const double* traj, double F, double dt);
+
+/* Host helper: nonlinear Lorenz-96 RK4 trajectory from x0 (host, n doubles) into
+ * traj (host, (N+1) x n row-major); traj[0] = x0. */
+int wc4d_l96_trajectory(int n, int N, double F, double dt, const double* x0, double* traj);
+
+/* Host helper: sigma * C^{1/2}, the symmetric square root of sigma^2 C, where C
+ * is the periodic correlation matrix C_ij = rho(d_ij), d_ij = (n/pi) sin(pi|i-j|/n)
+ * (chordal distance, grid units), rho = SOAR (1 + d/L) e^{-d/L} or Gaussian
+ * e^{-d^2/(2L^2)} (Section 5's B and Q families).  C is circulant, so the root
+ * comes from its real discrete Fourier spectrum.  out: host, n x n column-major
+ * (symmetric).  Returns WC4D_ENOTSPD if the spectrum has a negative value beyond
+ * rounding. */
+int wc4d_corr_sqrt(int n, int kind, double L, double sigma, double* out);
+
+/* Symmetric square roots of B and of Q (Q_i = Q for i = 1..N), host, n x n
+ * column-major, copied (Section 2.2: D^{1/2} = blockdiag(B^{1/2}, Q^{1/2}, ...)). */
+int wc4d_set_Bsqrt(wc4d_problem p, const double* Bsqrt);
+int wc4d_set_Qsqrt(wc4d_problem p, const double* Qsqrt);
+
+/* Direct observations at time level i (0 <= i <= N): q_i distinct grid indices
+ * idx[0..q_i) in [0, n) and the diagonal of R_i (rdiag, all > 0), host, copied.
+ * Replaces any earlier observations at i.  Observations are stacked in increasing
+ * i for wc4d_rhs's innovation vector. */
+int wc4d_set_obs(wc4d_problem p, int i, int q_i, const int* idx, const double* rdiag);
+
+/* Upload everything to the device and allocate the operator's fixed data.
+ * prec_mode: WC4D_PREC_FP64.  Synchronous.  Setup calls after finalize return
+ * WC4D_ESTATE. */
+int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s);
+
+/* n_A and q = total number of observations (after finalize). */
+int wc4d_dims(wc4d_problem p, int* n_A, int* q);
+
+/* ------------------------------------------------------------- operator -- */
+
+/* Y = A X for a block of m >= 1 vectors (Section 2.2, eq. forcing_1stlvl_prec):
+ * D^{1/2} product, forward tangent-linear sweep, H^T R^{-1} H, adjoint sweep,
+ * D^{1/2} product, plus X.  X and Y: device, n_A x m, ldx/ldy >= n_A; X and Y must
+ * not overlap.  Uses workspace owned by p (grown on demand, synchronously). */
+int wc4d_apply_A(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+
+/* Pieces of the operator, for testing and composition:
+ *   Y = L^{-1} X   (x_0 = p_0, x_{i+1} = M_i x_i + p_{i+1}; Section 2.1)
+ *   Y = L^{-T} X   (w_N = z_N, w_i = z_i + M_i^T w_{i+1})
+ *   Y = D^{1/2} X  */
+int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+int wc4d_apply_LinvT(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+int wc4d_apply_Dsqrt(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+
+/* Right-hand side of eq. forcing_1stlvl_prec: rhs = bt + D^{1/2} L^{-T} H^T R^{-1} d.
+ * d: device, q innovations stacked by increasing observed time, in each time in
+ * wc4d_set_obs order.  bt: device n_A vector D^{-1/2} b, or NULL for zero (a first
+ * inner loop).  rhs: device n_A. */
+int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hipStream_t s);
+
+/* -------------------------------------------------------- preconditioner -- */
+
+/* Randomised estimate of the k_r leading eigenpairs of A from a sketch of width
+ * m = k_r + l (Section 4): method WC4D_REVD (Algorithm 3), WC4D_NYSTROM
+ * (Algorithm 4) or WC4D_RITZIT (Algorithm 5), then the spectral LMP
+ * C = I + U (Theta^{-1/2} - I) U^T (eq. spectral_LMP_factor in closed form).
+ * G: device n_A x m column-major (ld n_A) start matrix; the library does not
+ * draw random numbers itself.  Orthonormalisation is CholeskyQR2 in float64.
+ * *out receives a new LMP handle.  Synchronises s once at the end to report a
+ * Cholesky failure (WC4D_ENOTSPD).  Requires 1 <= k_r, l >= 0, m <= n_A, m <= 512. */
+int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G,
+                   wc4d_lmp* out, hipStream_t s);
+
+/* Ritz values theta (host, k_r doubles, decreasing).  Synchronous. */
+int wc4d_lmp_theta(wc4d_lmp L, double* theta_host);
+/* Ritz vectors U into device memory (n_A x k_r, ldu >= n_A). */
+int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s);
+/* Y = C X for m vectors (C = C^T).  X, Y device n_A x m; must not overlap. */
+int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+/* Block products with A spent by the build (Table 1: 2 / 2 / 1). */
+int wc4d_lmp_applies(wc4d_lmp L, int* count);
+int wc4d_lmp_destroy(wc4d_lmp L);
+
+/* ---------------------------------------------------------------- solve -- */
+
+typedef struct {
+  double tol;     /* relative residual target (the paper uses 1e-6)                    */
+  int maxit;      /* iteration cap                                                      */
+  int criterion;  /* WC4D_RES_TRUE: ||b - A x|| / ||b|| (recursive, float64);
+                     WC4D_RES_PRECOND: ||r_j|| / ||r_0|| of Algorithm 1's split residual */
+} wc4d_pcg_opts;
+
+typedef struct {
+  int iters;             /* iterations taken                                          */
+  int status;            /* WC4D_OK, WC4D_ENOCONV or WC4D_EBREAKDOWN                  */
+  double relres_true;    /* ||s_j|| / ||b||, s_j the recursively updated b - A x_j     */
+  double relres_precond; /* ||r_j|| / ||r_0||                                          */
+  double J;              /* quadratic cost x^T A x / 2 - b^T x at the returned x        */
+} wc4d_pcg_info;
+
+/* Split preconditioned CG (Algorithm 1) on A x = b with P = C C^T from L (or no
+ * second-level preconditioner when L is NULL).  b: device n_A; x: device n_A,
+ * initial guess on entry, solution on exit.  hist_true / hist_precond / hist_J:
+ * optional host arrays of length opts->maxit receiving the per-iteration
+ * relative residuals and cost (NULL to skip).  Synchronous (returns after the
+ * solve); the iteration itself runs on the device without host round trips
+ * except a convergence poll every few iterations.  Returns the same status as
+ * info->status. */
+int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+             wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
+             hipStream_t s);
+
+/* Per-stage timing of wc4d_apply_A.  With profiling enabled, every apply records
+ * HIP events on its stream around its four stages; wc4d_last_apply_timing waits
+ * for the last apply and returns the elapsed ms of [0] the first D^{1/2} product,
+ * [1] the forward sweep with the observation gather, [2] the adjoint sweep with
+ * the observation scatter, [3] the second D^{1/2} product plus X (ms4: 4 floats). */
+int wc4d_set_profiling(wc4d_problem p, int enable);
+int wc4d_last_apply_timing(wc4d_problem p, float* ms4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WC4D_H */

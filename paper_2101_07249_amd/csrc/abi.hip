@@ -1,0 +1,803 @@
+// C-ABI entry points of libwc4d (declared and documented in include/wc4d.h).
+// Host orchestration only: every step of the operator, the randomised
+// eigendecompositions, the LMP and PCG runs in this library's HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wc4d_internal.h"
+
+using namespace wc4d;
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+
+int fail(wc4d_problem p, int code, const std::string& msg) {
+  if (p != nullptr) p->err = msg;
+  return code;
+}
+
+struct DevGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DevGuard(int d) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != d) {
+      changed = (hipSetDevice(d) == hipSuccess);
+    }
+  }
+  ~DevGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIPCHK(p, call)                                                                         \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail((p), WC4D_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+template <class T>
+int dev_alloc(wc4d_problem p, T** ptr, size_t count) {
+  if (*ptr != nullptr) {
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+  }
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(p, WC4D_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                    " bytes failed: " + hipGetErrorString(e));
+  }
+  return WC4D_OK;
+}
+
+template <class T>
+void dev_free(T** ptr) {
+  if (*ptr != nullptr) (void)hipFree(*ptr);
+  *ptr = nullptr;
+}
+
+int ensure_block(wc4d_problem p, long long m) {
+  if (p->wsBlockCols >= m && p->wsStashCols >= m) return WC4D_OK;
+  int rc = dev_alloc(p, &p->wsBlock, (size_t)p->nA * m);
+  if (rc) return rc;
+  p->wsBlockCols = m;
+  rc = dev_alloc(p, &p->wsStash, (size_t)std::max(p->q, 1) * m);
+  if (rc) return rc;
+  p->wsStashCols = m;
+  return WC4D_OK;
+}
+
+int ensure_gram(wc4d_problem p, size_t doubles) {
+  if (p->wsGramDoubles >= doubles) return WC4D_OK;
+  int rc = dev_alloc(p, &p->wsGram, doubles);
+  if (rc) return rc;
+  p->wsGramDoubles = doubles;
+  return WC4D_OK;
+}
+
+bool is_state_ok(wc4d_problem p) { return p != nullptr && p->finalized; }
+
+// L96 tendency (Section 5.2, eq. lorenz96) on the host, for the trajectory helper
+// and the RK4 stage inputs uploaded at finalize.
+void l96_f(const double* x, double* f, int n, double F) {
+  for (int j = 0; j < n; ++j) {
+    const double xm2 = x[(j - 2 + n) % n], xm1 = x[(j - 1 + n) % n], xp1 = x[(j + 1) % n];
+    f[j] = (xp1 - xm2) * xm1 - x[j] + F;
+  }
+}
+
+void l96_stage_inputs(const double* x, int n, double F, double dt, double* y /* 4 n */) {
+  std::vector<double> k(n), tmp(n);
+  std::memcpy(y, x, sizeof(double) * n);
+  l96_f(x, k.data(), n, F);
+  for (int j = 0; j < n; ++j) y[n + j] = x[j] + 0.5 * dt * k[j];
+  l96_f(y + n, k.data(), n, F);
+  for (int j = 0; j < n; ++j) y[2 * n + j] = x[j] + 0.5 * dt * k[j];
+  l96_f(y + 2 * n, k.data(), n, F);
+  for (int j = 0; j < n; ++j) y[3 * n + j] = x[j] + dt * k[j];
+}
+
+}  // namespace
+
+wc4d::SweepModel wc4d_problem_s::sweep() const {
+  SweepModel md{};
+  md.kind = model;
+  md.n = n;
+  md.N = N;
+  md.ca = c + r;
+  md.cb = 1.0 - c - 2.0 * r;
+  md.cc = r;
+  md.dt = dt;
+  md.stages = dStages;
+  md.obs_off = dObsOff;
+  md.obs_idx = dObsIdx;
+  md.obs_rinv = dObsRinv;
+  return md;
+}
+
+extern "C" {
+
+int wc4d_version(void) { return kVersion; }
+
+const char* wc4d_status_string(int st) {
+  switch (st) {
+    case WC4D_OK: return "WC4D_OK";
+    case WC4D_EINVAL: return "WC4D_EINVAL";
+    case WC4D_ENOMEM: return "WC4D_ENOMEM";
+    case WC4D_EHIP: return "WC4D_EHIP";
+    case WC4D_ENOTSPD: return "WC4D_ENOTSPD";
+    case WC4D_EBREAKDOWN: return "WC4D_EBREAKDOWN";
+    case WC4D_ENOCONV: return "WC4D_ENOCONV";
+    case WC4D_ESTATE: return "WC4D_ESTATE";
+    default: return "unknown status";
+  }
+}
+
+int wc4d_create(wc4d_problem* out, int n, int N, int device) {
+  if (out == nullptr) return WC4D_EINVAL;
+  *out = nullptr;
+  if (n < 1 || N < 1) return WC4D_EINVAL;
+  if ((long long)n * (N + 1) > (1LL << 31) - 1) return WC4D_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return WC4D_EINVAL;
+  wc4d_problem p = new (std::nothrow) wc4d_problem_s();
+  if (p == nullptr) return WC4D_ENOMEM;
+  p->n = n;
+  p->N = N;
+  p->device = device;
+  p->nA = (long long)n * (N + 1);
+  p->obs_idx.assign(N + 1, {});
+  p->obs_r.assign(N + 1, {});
+  *out = p;
+  return WC4D_OK;
+}
+
+int wc4d_destroy(wc4d_problem p) {
+  if (p == nullptr) return WC4D_OK;
+  DevGuard g(p->device);
+  dev_free(&p->dB);
+  dev_free(&p->dQ);
+  dev_free(&p->dStages);
+  dev_free(&p->dObsOff);
+  dev_free(&p->dObsIdx);
+  dev_free(&p->dObsRinv);
+  dev_free(&p->wsBlock);
+  dev_free(&p->wsStash);
+  dev_free(&p->wsGram);
+  dev_free(&p->bufA);
+  dev_free(&p->bufB);
+  dev_free(&p->small);
+  dev_free(&p->dStatus);
+  dev_free(&p->pcgVec);
+  dev_free(&p->pcgHist);
+  dev_free(&p->pcgRed);
+  dev_free(&p->pcgState);
+  if (p->pcgStateHost != nullptr) (void)hipHostFree(p->pcgStateHost);
+  for (auto& e : p->ev)
+    if (e != nullptr) (void)hipEventDestroy(e);
+  delete p;
+  return WC4D_OK;
+}
+
+const char* wc4d_last_error(wc4d_problem p) {
+  if (p == nullptr) return "null problem handle";
+  return p->err.c_str();
+}
+
+int wc4d_set_model_advdiff(wc4d_problem p, double c, double r) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "setup after finalize");
+  if (!(c >= 0.0) || !(r >= 0.0) || !(c + 2.0 * r <= 1.0))
+    return fail(p, WC4D_EINVAL, "advection-diffusion needs c >= 0, r >= 0, c + 2r <= 1");
+  p->model = 0;
+  p->c = c;
+  p->r = r;
+  return WC4D_OK;
+}
+
+int wc4d_set_model_l96(wc4d_problem p, const double* traj, double F, double dt) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "setup after finalize");
+  if (traj == nullptr || p->n < 4 || !(dt > 0.0) || !std::isfinite(F))
+    return fail(p, WC4D_EINVAL, "Lorenz-96 needs a trajectory, n >= 4 and dt > 0");
+  p->model = 1;
+  p->F = F;
+  p->dt = dt;
+  p->traj.assign(traj, traj + (size_t)(p->N + 1) * p->n);
+  return WC4D_OK;
+}
+
+int wc4d_l96_trajectory(int n, int N, double F, double dt, const double* x0, double* traj) {
+  if (n < 4 || N < 0 || x0 == nullptr || traj == nullptr || !(dt > 0.0)) return WC4D_EINVAL;
+  std::vector<double> k1(n), k2(n), k3(n), k4(n), y(n);
+  std::memcpy(traj, x0, sizeof(double) * n);
+  for (int i = 0; i < N; ++i) {
+    const double* x = traj + (size_t)i * n;
+    double* xn = traj + (size_t)(i + 1) * n;
+    l96_f(x, k1.data(), n, F);
+    for (int j = 0; j < n; ++j) y[j] = x[j] + 0.5 * dt * k1[j];
+    l96_f(y.data(), k2.data(), n, F);
+    for (int j = 0; j < n; ++j) y[j] = x[j] + 0.5 * dt * k2[j];
+    l96_f(y.data(), k3.data(), n, F);
+    for (int j = 0; j < n; ++j) y[j] = x[j] + dt * k3[j];
+    l96_f(y.data(), k4.data(), n, F);
+    for (int j = 0; j < n; ++j) xn[j] = x[j] + (dt / 6.0) * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j]);
+  }
+  return WC4D_OK;
+}
+
+int wc4d_corr_sqrt(int n, int kind, double L, double sigma, double* out) {
+  if (n < 1 || out == nullptr || !(L > 0.0) || !(sigma >= 0.0)) return WC4D_EINVAL;
+  if (kind != WC4D_CORR_SOAR && kind != WC4D_CORR_GAUSS) return WC4D_EINVAL;
+  const double pi = 3.14159265358979323846;
+  // first column of the circulant correlation matrix
+  std::vector<double> c(n), ct(n), lam(n), s(n);
+  for (int d = 0; d < n; ++d) {
+    const double dist = (n / pi) * std::sin(pi * d / n);
+    c[d] = (kind == WC4D_CORR_SOAR) ? (1.0 + dist / L) * std::exp(-dist / L)
+                                    : std::exp(-(dist * dist) / (2.0 * L * L));
+    ct[d] = std::cos(2.0 * pi * d / n);
+  }
+  // real spectrum lambda_k = sum_d c_d cos(2 pi k d / n)
+  double lmax = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double acc = 0.0;
+    for (int d = 0; d < n; ++d) acc += c[d] * ct[(int)(((long long)k * d) % n)];
+    lam[k] = acc;
+    lmax = std::max(lmax, acc);
+  }
+  for (int k = 0; k < n; ++k) {
+    if (lam[k] < -1e-10 * lmax) return WC4D_ENOTSPD;
+    lam[k] = std::sqrt(std::max(lam[k], 0.0));
+  }
+  // first column of the root: s_d = (1/n) sum_k sqrt(lambda_k) cos(2 pi k d / n)
+  for (int d = 0; d < n; ++d) {
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc += lam[k] * ct[(int)(((long long)k * d) % n)];
+    s[d] = sigma * acc / n;
+  }
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) out[i + (size_t)j * n] = s[(i - j + n) % n];
+  return WC4D_OK;
+}
+
+int wc4d_set_Bsqrt(wc4d_problem p, const double* B) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "setup after finalize");
+  if (B == nullptr) return fail(p, WC4D_EINVAL, "null B^{1/2}");
+  p->Bsqrt.assign(B, B + (size_t)p->n * p->n);
+  p->haveB = true;
+  return WC4D_OK;
+}
+
+int wc4d_set_Qsqrt(wc4d_problem p, const double* Q) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "setup after finalize");
+  if (Q == nullptr) return fail(p, WC4D_EINVAL, "null Q^{1/2}");
+  p->Qsqrt.assign(Q, Q + (size_t)p->n * p->n);
+  p->haveQ = true;
+  return WC4D_OK;
+}
+
+int wc4d_set_obs(wc4d_problem p, int i, int q_i, const int* idx, const double* rdiag) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "setup after finalize");
+  if (i < 0 || i > p->N || q_i < 0 || q_i > p->n || (q_i > 0 && (idx == nullptr || rdiag == nullptr)))
+    return fail(p, WC4D_EINVAL, "invalid observation time, count or pointers");
+  std::vector<char> seen(p->n, 0);
+  for (int k = 0; k < q_i; ++k) {
+    if (idx[k] < 0 || idx[k] >= p->n) return fail(p, WC4D_EINVAL, "observation index out of range");
+    if (seen[idx[k]]) return fail(p, WC4D_EINVAL, "repeated observation index in one time level");
+    seen[idx[k]] = 1;
+    if (!(rdiag[k] > 0.0) || !std::isfinite(rdiag[k]))
+      return fail(p, WC4D_EINVAL, "observation error variance must be positive");
+  }
+  p->obs_idx[i].assign(idx, idx + q_i);
+  p->obs_r[i].assign(rdiag, rdiag + q_i);
+  return WC4D_OK;
+}
+
+int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "already finalized");
+  if (p->model < 0) return fail(p, WC4D_ESTATE, "no model set");
+  if (!p->haveB || !p->haveQ) return fail(p, WC4D_ESTATE, "B^{1/2} and Q^{1/2} must be set");
+  if (prec_mode != WC4D_PREC_FP64) return fail(p, WC4D_EINVAL, "unknown precision mode");
+  DevGuard g(p->device);
+  const int n = p->n, N = p->N;
+  std::vector<int> off(N + 2, 0), idx;
+  std::vector<double> rinv;
+  for (int i = 0; i <= N; ++i) {
+    off[i + 1] = off[i] + (int)p->obs_idx[i].size();
+    for (size_t k = 0; k < p->obs_idx[i].size(); ++k) {
+      idx.push_back(p->obs_idx[i][k]);
+      rinv.push_back(1.0 / p->obs_r[i][k]);
+    }
+  }
+  p->q = off[N + 1];
+  int rc;
+  if ((rc = dev_alloc(p, &p->dB, (size_t)n * n))) return rc;
+  if ((rc = dev_alloc(p, &p->dQ, (size_t)n * n))) return rc;
+  if ((rc = dev_alloc(p, &p->dObsOff, off.size()))) return rc;
+  if ((rc = dev_alloc(p, &p->dObsIdx, std::max<size_t>(idx.size(), 1)))) return rc;
+  if ((rc = dev_alloc(p, &p->dObsRinv, std::max<size_t>(rinv.size(), 1)))) return rc;
+  HIPCHK(p, hipMemcpyAsync(p->dB, p->Bsqrt.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(p->dQ, p->Qsqrt.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s));
+  HIPCHK(p, hipMemcpyAsync(p->dObsOff, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+  if (!idx.empty()) {
+    HIPCHK(p, hipMemcpyAsync(p->dObsIdx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(p, hipMemcpyAsync(p->dObsRinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice, s));
+  }
+  std::vector<double> stages;
+  if (p->model == 1) {
+    stages.resize((size_t)N * 4 * n);
+    for (int i = 0; i < N; ++i)
+      l96_stage_inputs(p->traj.data() + (size_t)i * n, n, p->F, p->dt, stages.data() + (size_t)i * 4 * n);
+    if ((rc = dev_alloc(p, &p->dStages, stages.size()))) return rc;
+    HIPCHK(p, hipMemcpyAsync(p->dStages, stages.data(), sizeof(double) * stages.size(), hipMemcpyHostToDevice, s));
+  }
+  // LDS the sweeps need must fit the device
+  int maxLds = 0;
+  HIPCHK(p, hipDeviceGetAttribute(&maxLds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  const size_t need = sweep_lds_required(p->sweep());
+  if (need > (size_t)maxLds)
+    return fail(p, WC4D_EINVAL, "state too large for the sweep's LDS (" + std::to_string(need) +
+                                    " > " + std::to_string(maxLds) + " bytes)");
+  if ((rc = dev_alloc(p, &p->dStatus, 16))) return rc;
+  HIPCHK(p, hipMemsetAsync(p->dStatus, 0, 16 * sizeof(int), s));
+  HIPCHK(p, hipStreamSynchronize(s));
+  p->prec = prec_mode;
+  p->finalized = true;
+  return WC4D_OK;
+}
+
+int wc4d_dims(wc4d_problem p, int* nA, int* q) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (nA) *nA = (int)p->nA;
+  if (q) *q = p->q;
+  return WC4D_OK;
+}
+
+int wc4d_set_profiling(wc4d_problem p, int enable) {
+  if (p == nullptr) return WC4D_EINVAL;
+  DevGuard g(p->device);
+  if (enable && p->ev[0] == nullptr)
+    for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
+  p->prof = enable != 0;
+  return WC4D_OK;
+}
+
+int wc4d_last_apply_timing(wc4d_problem p, float* ms4) {
+  if (p == nullptr || ms4 == nullptr) return WC4D_EINVAL;
+  if (!p->prof) return fail(p, WC4D_ESTATE, "profiling is off");
+  DevGuard g(p->device);
+  HIPCHK(p, hipEventSynchronize(p->ev[4]));
+  for (int k = 0; k < 4; ++k) HIPCHK(p, hipEventElapsedTime(&ms4[k], p->ev[k], p->ev[k + 1]));
+  return WC4D_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ operator core
+
+namespace {
+
+// Y(time levels) = D^{1/2} X [+ E]: B^{1/2} on time 0, Q^{1/2} on times 1..N.
+int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
+                const double* E, long long lde, const int* skip, hipStream_t s) {
+  const int n = p->n, N = p->N;
+  HIPCHK(p, gemm_f64(n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y, ColMap{ldy, 1, 0, n}, E,
+                     ColMap{lde, 1, 0, n}, skip, s));
+  HIPCHK(p, gemm_f64(n, m * N, n, 1.0, p->dQ, n, X, ColMap{ldx, N, 1, n}, Y, ColMap{ldy, N, 1, n},
+                     E, ColMap{lde, N, 1, n}, skip, s));
+  return WC4D_OK;
+}
+
+// Y = A X using the problem's block workspace (must hold m columns).
+int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
+                 const int* skip, hipStream_t s) {
+  const long long nA = p->nA;
+  if (p->q == 0) {
+    HIPCHK(p, block_copy(Y, ldy, X, ldx, nA, m, s));
+    return WC4D_OK;
+  }
+  const SweepModel md = p->sweep();
+  double* P = p->wsBlock;
+  if (p->prof) HIPCHK(p, hipEventRecord(p->ev[0], s));
+  int rc = dsqrt_apply(p, X, ldx, P, nA, m, nullptr, 0, skip, s);
+  if (rc) return rc;
+  if (p->prof) HIPCHK(p, hipEventRecord(p->ev[1], s));
+  HIPCHK(p, sweep_fwd(md, P, nA, m, p->wsStash, p->q, nullptr, 0, skip, s));
+  if (p->prof) HIPCHK(p, hipEventRecord(p->ev[2], s));
+  HIPCHK(p, sweep_bwd(md, p->wsStash, p->q, nullptr, 0, m, P, nA, skip, s));
+  if (p->prof) HIPCHK(p, hipEventRecord(p->ev[3], s));
+  rc = dsqrt_apply(p, P, nA, Y, ldy, m, X, ldx, skip, s);
+  if (rc) return rc;
+  if (p->prof) HIPCHK(p, hipEventRecord(p->ev[4], s));
+  return WC4D_OK;
+}
+
+int check_block_args(wc4d_problem p, const void* X, int ldx, const void* Y, int ldy, int m) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (X == nullptr || Y == nullptr || m < 1 || ldx < p->nA || ldy < p->nA)
+    return fail(p, WC4D_EINVAL, "invalid block arguments (null pointer, m < 1 or ld < n_A)");
+  const char* xb = (const char*)X;
+  const char* yb = (const char*)Y;
+  const size_t xs = sizeof(double) * ((size_t)ldx * (m - 1) + p->nA);
+  const size_t ys = sizeof(double) * ((size_t)ldy * (m - 1) + p->nA);
+  if (xb < yb + ys && yb < xb + xs) return fail(p, WC4D_EINVAL, "X and Y overlap");
+  return WC4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wc4d_apply_A(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  int rc = check_block_args(p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(p->device);
+  if ((rc = ensure_block(p, m))) return rc;
+  return apply_A_core(p, X, ldx, Y, ldy, m, nullptr, s);
+}
+
+int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  int rc = check_block_args(p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(p->device);
+  HIPCHK(p, sweep_fwd(p->sweep(), X, ldx, m, nullptr, 0, Y, ldy, nullptr, s));
+  return WC4D_OK;
+}
+
+int wc4d_apply_LinvT(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  int rc = check_block_args(p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(p->device);
+  HIPCHK(p, sweep_bwd(p->sweep(), nullptr, 0, X, ldx, m, Y, ldy, nullptr, s));
+  return WC4D_OK;
+}
+
+int wc4d_apply_Dsqrt(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  int rc = check_block_args(p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(p->device);
+  return dsqrt_apply(p, X, ldx, Y, ldy, m, nullptr, 0, nullptr, s);
+}
+
+int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hipStream_t s) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (rhs == nullptr || (p->q > 0 && d == nullptr)) return fail(p, WC4D_EINVAL, "null pointer");
+  DevGuard g(p->device);
+  int rc = ensure_block(p, 1);
+  if (rc) return rc;
+  const long long nA = p->nA;
+  if (p->q == 0) {
+    if (bt != nullptr) HIPCHK(p, vec_copy(rhs, bt, nA, s));
+    else HIPCHK(p, vec_fill(rhs, 0.0, nA, s));
+    return WC4D_OK;
+  }
+  HIPCHK(p, stash_from_innov(d, p->dObsRinv, p->wsStash, p->q, s));
+  HIPCHK(p, sweep_bwd(p->sweep(), p->wsStash, p->q, nullptr, 0, 1, p->wsBlock, nA, nullptr, s));
+  return dsqrt_apply(p, p->wsBlock, nA, rhs, nA, 1, bt, nA, nullptr, s);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ LMP build
+
+namespace {
+
+int ensure_build(wc4d_problem p, int m) {
+  int rc;
+  if (p->bufCols < m) {
+    if ((rc = dev_alloc(p, &p->bufA, (size_t)p->nA * m))) return rc;
+    if ((rc = dev_alloc(p, &p->bufB, (size_t)p->nA * m))) return rc;
+    p->bufCols = m;
+  }
+  if (p->smallM < m) {
+    if ((rc = dev_alloc(p, &p->small, (size_t)6 * m * m + 2 * (size_t)m))) return rc;
+    p->smallM = m;
+  }
+  if ((rc = ensure_block(p, m))) return rc;
+  if ((rc = ensure_gram(p, gram_ws_doubles(m, m, p->nA)))) return rc;
+  return WC4D_OK;
+}
+
+struct Small {
+  double *G, *R1, *Ri, *R2, *K, *V, *lam;
+  explicit Small(double* base, int m) {
+    const size_t mm = (size_t)m * m;
+    G = base;
+    R1 = base + mm;
+    Ri = base + 2 * mm;
+    R2 = base + 3 * mm;
+    K = base + 4 * mm;
+    V = base + 5 * mm;
+    lam = base + 6 * mm;
+  }
+};
+
+// CholeskyQR2 of the n_A x m block Y (in place): Y = Q R with Q^T Q = I.
+// tmp: n_A x m scratch.  When Rout != null, R = R2 R1 is written there (m x m).
+int cholqr2(wc4d_problem p, double* Y, double* tmp, int m, Small& sm, double* Rout, hipStream_t s) {
+  const long long nA = p->nA;
+  const ColMap cm = plain_cols(nA);
+  int* st = p->dStatus;
+  HIPCHK(p, gram_f64(m, m, nA, Y, cm, Y, cm, sm.G, m, p->wsGram, nullptr, s));
+  HIPCHK(p, chol_upper(m, sm.G, m, st, s));
+  HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
+  HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, Y, nA, sm.Ri, plain_cols(m), tmp, cm, nullptr, cm, nullptr, s));
+  if (Rout != nullptr) HIPCHK(p, vec_copy(sm.R1, sm.G, (long long)m * m, s));
+  HIPCHK(p, gram_f64(m, m, nA, tmp, cm, tmp, cm, sm.G, m, p->wsGram, nullptr, s));
+  HIPCHK(p, chol_upper(m, sm.G, m, st, s));
+  HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
+  HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, tmp, nA, sm.Ri, plain_cols(m), Y, cm, nullptr, cm, nullptr, s));
+  if (Rout != nullptr) HIPCHK(p, small_gemm(m, m, m, 1.0, sm.G, m, 0, sm.R1, m, 0, Rout, m, s));
+  return WC4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
+                   hipStream_t s) {
+  if (out == nullptr) return WC4D_EINVAL;
+  *out = nullptr;
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  const int m = k_r + l;
+  if (method < WC4D_REVD || method > WC4D_RITZIT || k_r < 1 || l < 0 || G == nullptr || m > p->nA ||
+      m > 512)
+    return fail(p, WC4D_EINVAL, "invalid LMP arguments (method, k_r >= 1, l >= 0, m <= min(n_A, 512), G)");
+  DevGuard g(p->device);
+  int rc = ensure_build(p, m);
+  if (rc) return rc;
+  wc4d_lmp L = new (std::nothrow) wc4d_lmp_s();
+  if (L == nullptr) return WC4D_ENOMEM;
+  L->p = p;
+  L->nA = p->nA;
+  L->k = k_r;
+  auto cleanup = [&](int code) {
+    wc4d_lmp_destroy(L);
+    return code;
+  };
+  if ((rc = dev_alloc(p, &L->U, (size_t)p->nA * k_r))) return cleanup(rc);
+  if ((rc = dev_alloc(p, &L->theta, k_r))) return cleanup(rc);
+  if ((rc = dev_alloc(p, &L->dcoef, k_r))) return cleanup(rc);
+
+  const long long nA = p->nA;
+  const ColMap cm = plain_cols(nA);
+  Small sm(p->small, m);
+  double* A_ = p->bufA;
+  double* B_ = p->bufB;
+  hipError_t he = hipMemsetAsync(p->dStatus, 0, sizeof(int), s);
+  if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+  double* Zfinal = nullptr;
+  int mode = 0;
+  if (method == WC4D_REVD) {
+    // Algorithm 3: Y = A G; Z = orth(Y); K = Z^T A Z; EVD; U = Z W
+    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    L->applies = 2;
+    he = gram_f64(m, m, nA, A_, cm, B_, cm, sm.K, m, p->wsGram, nullptr, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    Zfinal = A_;
+  } else if (method == WC4D_NYSTROM) {
+    // Algorithm 4: Y = A G; Z = orth(Y); E1 = A Z; E2 = Z^T E1 = C^T C; F = E1 C^{-1};
+    // SVD F = U Sigma V^T via F = Q_F R_F and the EVD of R_F R_F^T; Theta = Sigma^2
+    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    L->applies = 2;
+    he = gram_f64(m, m, nA, A_, cm, B_, cm, sm.G, m, p->wsGram, nullptr, s);
+    if (he == hipSuccess) he = chol_upper(m, sm.G, m, p->dStatus, s);
+    if (he == hipSuccess) he = tri_inv_upper(m, sm.G, m, sm.Ri, m, s);
+    if (he == hipSuccess)
+      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, plain_cols(m), A_, cm, nullptr, cm, nullptr, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
+    he = small_gemm(m, m, m, 1.0, sm.R2, m, 0, sm.R2, m, 1, sm.K, m, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    Zfinal = A_;
+  } else {
+    // Algorithm 5: G_3 = orth(G); Y_3 = A G_3 = Z_3 R_3; K_3 = R_3 R_3^T = W Theta^2 W^T
+    he = vec_copy(A_, G, nA * m, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    L->applies = 1;
+    if ((rc = cholqr2(p, B_, A_, m, sm, sm.R2, s))) return cleanup(rc);
+    he = small_gemm(m, m, m, 1.0, sm.R2, m, 0, sm.R2, m, 1, sm.K, m, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    Zfinal = B_;
+    mode = 1;
+  }
+  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, s);
+  if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
+  if (he == hipSuccess)
+    he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, cm, nullptr, cm, nullptr, s);
+  if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+  int st = 0;
+  he = hipMemcpyAsync(&st, p->dStatus, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+  if (st != 0)
+    return cleanup(fail(p, WC4D_ENOTSPD, "Cholesky met a non-positive pivot (rank-deficient sketch?)"));
+  *out = L;
+  return WC4D_OK;
+}
+
+int wc4d_lmp_theta(wc4d_lmp L, double* theta_host) {
+  if (L == nullptr || theta_host == nullptr) return WC4D_EINVAL;
+  DevGuard g(L->p->device);
+  HIPCHK(L->p, hipMemcpy(theta_host, L->theta, sizeof(double) * L->k, hipMemcpyDeviceToHost));
+  return WC4D_OK;
+}
+
+int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s) {
+  if (L == nullptr || U == nullptr || ldu < L->nA) return WC4D_EINVAL;
+  DevGuard g(L->p->device);
+  HIPCHK(L->p, block_copy(U, ldu, L->U, L->nA, L->nA, L->k, s));
+  return WC4D_OK;
+}
+
+int wc4d_lmp_applies(wc4d_lmp L, int* count) {
+  if (L == nullptr || count == nullptr) return WC4D_EINVAL;
+  *count = L->applies;
+  return WC4D_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Y = C X = X + U diag(theta^{-1/2} - 1) U^T X
+int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long long ldy, int m,
+                   const int* skip, hipStream_t s) {
+  wc4d_problem p = L->p;
+  int rc;
+  if (L->tcap < m) {
+    if ((rc = dev_alloc(p, &L->T, (size_t)L->k * m))) return rc;
+    L->tcap = m;
+  }
+  const size_t wsn = gram_ws_doubles(L->k, m, L->nA);
+  if (L->wsDoubles < wsn) {
+    if ((rc = dev_alloc(p, &L->ws, wsn))) return rc;
+    L->wsDoubles = wsn;
+  }
+  HIPCHK(p, gram_f64(L->k, m, L->nA, L->U, plain_cols(L->nA), X, plain_cols(ldx), L->T, L->k, L->ws,
+                     skip, s));
+  HIPCHK(p, vec_scale_rows(L->T, L->k, m, L->k, L->dcoef, skip, s));
+  HIPCHK(p, gemm_f64((int)L->nA, m, L->k, 1.0, L->U, L->nA, L->T, plain_cols(L->k), Y,
+                     plain_cols(ldy), X, plain_cols(ldx), skip, s));
+  return WC4D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  if (L == nullptr) return WC4D_EINVAL;
+  int rc = check_block_args(L->p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(L->p->device);
+  return lmp_apply_core(L, X, ldx, Y, ldy, m, nullptr, s);
+}
+
+int wc4d_lmp_destroy(wc4d_lmp L) {
+  if (L == nullptr) return WC4D_OK;
+  DevGuard g(L->p->device);
+  dev_free(&L->U);
+  dev_free(&L->theta);
+  dev_free(&L->dcoef);
+  dev_free(&L->T);
+  dev_free(&L->ws);
+  delete L;
+  return WC4D_OK;
+}
+
+// ------------------------------------------------------------------ PCG
+
+int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+             wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
+             hipStream_t s) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (b == nullptr || x == nullptr || opts == nullptr || info == nullptr || opts->maxit < 1 ||
+      !(opts->tol >= 0.0) || (opts->criterion != WC4D_RES_TRUE && opts->criterion != WC4D_RES_PRECOND))
+    return fail(p, WC4D_EINVAL, "invalid PCG arguments");
+  if (L != nullptr && L->p != p) return fail(p, WC4D_EINVAL, "LMP built for another problem");
+  DevGuard g(p->device);
+  const long long nA = p->nA;
+  int rc;
+  if ((rc = ensure_block(p, 1))) return rc;
+  if (p->pcgVec == nullptr) {
+    if ((rc = dev_alloc(p, &p->pcgVec, (size_t)6 * nA))) return rc;
+    if ((rc = dev_alloc(p, &p->pcgRed, pcg_red_doubles()))) return rc;
+    if ((rc = dev_alloc(p, &p->pcgState, 1))) return rc;
+    HIPCHK(p, hipHostMalloc((void**)&p->pcgStateHost, sizeof(PcgState), hipHostMallocDefault));
+  }
+  if (p->pcgHistCap < opts->maxit) {
+    if ((rc = dev_alloc(p, &p->pcgHist, (size_t)3 * opts->maxit))) return rc;
+    p->pcgHistCap = opts->maxit;
+  }
+  double* r = p->pcgVec;
+  double* pv = r + nA;
+  double* Ap = pv + nA;
+  double* sres = Ap + nA;
+  double* w = sres + nA;
+  double* z = w + nA;
+  PcgState* st = p->pcgState;
+  const int* done = &st->done;
+  int* xzero = p->dStatus + 1;
+  // s_0 = b - A x_0 (the product is skipped for x_0 = 0), r_0 = C^T s_0, p_0 = C r_0
+  HIPCHK(p, pcg_x0_zero_flag(x, nA, p->pcgRed, xzero, s));
+  if ((rc = apply_A_core(p, x, nA, Ap, nA, 1, xzero, s))) return rc;
+  HIPCHK(p, pcg_s0(b, Ap, xzero, sres, nA, s));
+  if (L != nullptr) {
+    if ((rc = lmp_apply_core(L, sres, nA, r, nA, 1, nullptr, s))) return rc;
+    if ((rc = lmp_apply_core(L, r, nA, pv, nA, 1, nullptr, s))) return rc;
+  } else {
+    HIPCHK(p, vec_copy(r, sres, nA, s));
+    HIPCHK(p, vec_copy(pv, r, nA, s));
+  }
+  HIPCHK(p, pcg_kernels_init(st, b, sres, r, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
+  const int poll = 8;
+  int it = 0;
+  bool fin = false;
+  while (!fin) {
+    const int chunk = std::min(poll, opts->maxit - it);
+    for (int c = 0; c < chunk; ++c) {
+      if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
+      HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
+      HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
+      const double* wv = Ap;
+      if (L != nullptr) {
+        if ((rc = lmp_apply_core(L, Ap, nA, w, nA, 1, done, s))) return rc;
+        wv = w;
+      }
+      HIPCHK(p, pcg_update_r(st, r, wv, nA, p->pcgRed, p->pcgHist, s));
+      const double* zv = r;
+      if (L != nullptr) {
+        if ((rc = lmp_apply_core(L, r, nA, z, nA, 1, done, s))) return rc;
+        zv = z;
+      }
+      HIPCHK(p, pcg_update_p(st, pv, zv, nA, s));
+    }
+    it += chunk;
+    HIPCHK(p, hipMemcpyAsync(p->pcgStateHost, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+    fin = p->pcgStateHost->done != 0 || it >= opts->maxit;
+  }
+  const PcgState hs = *p->pcgStateHost;
+  info->iters = hs.iter;
+  info->status = hs.done ? hs.status : WC4D_ENOCONV;
+  info->relres_true = hs.bnorm2 > 0 ? std::sqrt(hs.ss / hs.bnorm2) : 0.0;
+  info->relres_precond = hs.r0norm2 > 0 ? std::sqrt(hs.rr / hs.r0norm2) : 0.0;
+  info->J = -0.5 * hs.xbs;
+  if (hs.iter == 0) {
+    info->relres_true = 0.0;
+    info->relres_precond = 0.0;
+  }
+  const int ni = hs.iter;
+  if (ni > 0) {
+    if (hist_true) HIPCHK(p, hipMemcpy(hist_true, p->pcgHist, sizeof(double) * ni, hipMemcpyDeviceToHost));
+    if (hist_precond)
+      HIPCHK(p, hipMemcpy(hist_precond, p->pcgHist + opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
+    if (hist_J)
+      HIPCHK(p, hipMemcpy(hist_J, p->pcgHist + 2 * opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
+  }
+  return info->status;
+}
+
+}  // extern "C"

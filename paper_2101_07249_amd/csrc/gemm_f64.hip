@@ -1,0 +1,282 @@
+// float64 MFMA GEMMs for gfx950.
+//
+// gemm_f64:  C(:, t) = alpha * A * B(:, t) [+ E(:, t)]  -- the D^{1/2} products
+//            (A = B^{1/2} or Q^{1/2}, B = the time levels of a block of vectors),
+//            the tall-skinny products Y R^{-1}, Z W and the LMP's U * T.
+// gram_f64:  G = X^T Y for tall X, Y (Gram matrices of CholeskyQR2, K = Z^T A Z,
+//            the LMP's U^T X), deterministic split-K.
+//
+// v_mfma_f64_16x16x4_f64 lane layout (wave64): operand a = A[l%16][l/16],
+// operand b = B[l/16][l%16], result register r = D[l/16 + 4r][l%16].
+// gemm_f64 runs the MFMA on the transposed product (rows of the MFMA are the
+// columns t of C), so the 16 lanes that share l/16 hold 16 consecutive rows of
+// one column of C and store 128 contiguous bytes.
+#include "wc4d_internal.h"
+
+namespace wc4d {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+static __device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Tile BM (rows of C) x BN (columns of C), K step BK, 256 threads = WGI x WGJ waves.
+template <int BM, int BN, int BK, int WGI, int WGJ>
+__global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double alpha,
+                                                  const double* __restrict__ A, long long lda,
+                                                  const double* __restrict__ B, ColMap bmap,
+                                                  double* __restrict__ C, ColMap cmap,
+                                                  const double* __restrict__ E, ColMap emap,
+                                                  const int* __restrict__ skip) {
+  static_assert(WGI * WGJ == 4, "4 waves");
+  constexpr int WI = BM / WGI, WJ = BN / WGJ;
+  constexpr int TI = WI / 16, TJ = WJ / 16;
+  static_assert(TI >= 1 && TJ >= 1, "wave tile >= 16x16");
+  constexpr int NA = BM * BK / 256;
+  constexpr int NB = BN * BK / 256;
+  static_assert(NA >= 1 && NB >= 1, "tile too small for 256 threads");
+  constexpr int PA = BM + 4, PB = BN + 4;
+  __shared__ double As[BK][PA];
+  __shared__ double Bs[BK][PB];
+
+  if (skip != nullptr && *skip != 0) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int i0 = blockIdx.x * BM;
+  const int j0 = blockIdx.y * BN;
+  const int wi0 = (wave % WGI) * WI;
+  const int wj0 = (wave / WGI) * WJ;
+
+  d4 acc[TJ][TI];
+#pragma unroll
+  for (int a = 0; a < TJ; ++a)
+#pragma unroll
+    for (int b = 0; b < TI; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+  long long boff[NB];
+  bool bval[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int j = (tid + 256 * e) / BK;
+    bval[e] = (j0 + j) < ncol;
+    boff[e] = bval[e] ? bmap.off(j0 + j) : 0;
+  }
+  double ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + 256 * e;
+      const int gi = i0 + idx % BM, gk = k0 + idx / BM;
+      ra[e] = (gi < M && gk < K) ? A[(long long)gi + (long long)gk * lda] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int gk = k0 + (tid + 256 * e) % BK;
+      rb[e] = (bval[e] && gk < K) ? B[boff[e] + gk] : 0.0;
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + 256 * e;
+      As[idx / BM][idx % BM] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + 256 * e;
+      Bs[idx % BK][idx / BK] = rb[e];
+    }
+    __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double av[TJ], bv[TI];
+#pragma unroll
+      for (int a = 0; a < TJ; ++a) av[a] = Bs[kr][wj0 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TI; ++b) bv[b] = As[kr][wi0 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TJ; ++a)
+#pragma unroll
+        for (int b = 0; b < TI; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < TJ; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + wj0 + a * 16 + (lane >> 4) + 4 * r;
+      if (j >= ncol) continue;
+      const long long co = cmap.off(j);
+      const long long eo = (E != nullptr) ? emap.off(j) : 0;
+#pragma unroll
+      for (int b = 0; b < TI; ++b) {
+        const int i = i0 + wi0 + b * 16 + (lane & 15);
+        if (i < M) {
+          double v = alpha * acc[a][b][r];
+          if (E != nullptr) v += E[eo + i];
+          C[co + i] = v;
+        }
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int WGI, int WGJ>
+static hipError_t launch_gemm(int M, int ncol, int K, double alpha, const double* A, long long lda,
+                              const double* B, ColMap bmap, double* C, ColMap cmap,
+                              const double* E, ColMap emap, const int* skip, hipStream_t s) {
+  dim3 grid((M + BM - 1) / BM, (ncol + BN - 1) / BN);
+  hipLaunchKernelGGL((k_gemm_f64<BM, BN, 16, WGI, WGJ>), grid, dim3(256), 0, s, M, ncol, K, alpha,
+                     A, lda, B, bmap, C, cmap, E, emap, skip);
+  return hipGetLastError();
+}
+
+hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
+                    const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                    ColMap emap, const int* skip, hipStream_t s) {
+  if (M <= 0 || ncol <= 0) return hipSuccess;
+  auto tiles = [&](int bm, int bn) {
+    return (long long)((M + bm - 1) / bm) * (long long)((ncol + bn - 1) / bn);
+  };
+  if (ncol <= 16)
+    return launch_gemm<128, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  if (tiles(128, 128) >= 1024)
+    return launch_gemm<128, 128, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  if (tiles(64, 64) >= 1024)
+    return launch_gemm<64, 64, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  return launch_gemm<32, 32, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+}
+
+// ------------------------------------------------------------------ Gram
+
+constexpr int GT = 64;   // output tile
+constexpr int GBK = 16;  // K step
+
+static int gram_splits(int m1, int m2, long long K) {
+  const long long tiles = (long long)((m1 + GT - 1) / GT) * ((m2 + GT - 1) / GT);
+  long long want = (2048 + tiles - 1) / tiles;          // aim for ~2048 workgroups
+  long long maxs = (K + 255) / 256;                      // at least 256 rows per split
+  long long sp = want < maxs ? want : maxs;
+  if (sp < 1) sp = 1;
+  return (int)sp;
+}
+
+size_t gram_ws_doubles(int m1, int m2, long long K) {
+  return (size_t)gram_splits(m1, m2, K) * (size_t)m1 * (size_t)m2;
+}
+
+// Partial G over rows [kb, ke) of one split, tile (blockIdx.x, blockIdx.y).
+__global__ __launch_bounds__(256) void k_gram_partial(int m1, int m2, long long K, long long kchunk,
+                                                      const double* __restrict__ X, ColMap xmap,
+                                                      const double* __restrict__ Y, ColMap ymap,
+                                                      double* __restrict__ ws,
+                                                      const int* __restrict__ skip) {
+  constexpr int NL = GT * GBK / 256;  // 4 loads per operand per thread
+  __shared__ double Xs[GBK][GT + 4];
+  __shared__ double Ys[GBK][GT + 4];
+  if (skip != nullptr && *skip != 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * GT, j0 = blockIdx.y * GT;
+  const int split = blockIdx.z;
+  const long long kb = (long long)split * kchunk;
+  long long ke = kb + kchunk;
+  if (ke > K) ke = K;
+  const int wi0 = (wave & 1) * 32, wj0 = (wave >> 1) * 32;
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  long long xo[NL], yo[NL];
+  bool xv[NL], yv[NL];
+#pragma unroll
+  for (int e = 0; e < NL; ++e) {
+    const int c = (tid + 256 * e) / GBK;
+    xv[e] = (i0 + c) < m1;
+    yv[e] = (j0 + c) < m2;
+    xo[e] = xv[e] ? xmap.off(i0 + c) : 0;
+    yo[e] = yv[e] ? ymap.off(j0 + c) : 0;
+  }
+  double rx[NL], ry[NL];
+  auto gload = [&](long long k0) {
+#pragma unroll
+    for (int e = 0; e < NL; ++e) {
+      const long long gk = k0 + (tid + 256 * e) % GBK;
+      rx[e] = (xv[e] && gk < ke) ? X[xo[e] + gk] : 0.0;
+      ry[e] = (yv[e] && gk < ke) ? Y[yo[e] + gk] : 0.0;
+    }
+  };
+  if (kb < ke) gload(kb);
+  for (long long k0 = kb; k0 < ke; k0 += GBK) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NL; ++e) {
+      const int idx = tid + 256 * e;
+      Xs[idx % GBK][idx / GBK] = rx[e];
+      Ys[idx % GBK][idx / GBK] = ry[e];
+    }
+    __syncthreads();
+    if (k0 + GBK < ke) gload(k0 + GBK);
+#pragma unroll
+    for (int kk = 0; kk < GBK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Xs[kr][wi0 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Ys[kr][wj0 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+    }
+  }
+  double* out = ws + (size_t)split * m1 * m2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi0 + a * 16 + (lane >> 4) + 4 * r;
+        const int j = j0 + wj0 + b * 16 + (lane & 15);
+        if (i < m1 && j < m2) out[(size_t)i + (size_t)j * m1] = acc[a][b][r];
+      }
+}
+
+__global__ void k_gram_reduce(int m1, int m2, int splits, const double* __restrict__ ws,
+                              double* __restrict__ G, int ldg, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tot = (long long)m1 * m2;
+  if (e >= tot) return;
+  double sum = 0.0;
+  for (int sp = 0; sp < splits; ++sp) sum += ws[(size_t)sp * tot + e];
+  const int i = (int)(e % m1), j = (int)(e / m1);
+  G[(size_t)i + (size_t)j * ldg] = sum;
+}
+
+hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, const double* Y,
+                    ColMap ymap, double* G, int ldg, double* ws, const int* skip, hipStream_t s) {
+  if (m1 <= 0 || m2 <= 0) return hipSuccess;
+  const int sp = gram_splits(m1, m2, K);
+  long long kchunk = (K + sp - 1) / sp;
+  kchunk = (kchunk + GBK - 1) / GBK * GBK;
+  dim3 grid((m1 + GT - 1) / GT, (m2 + GT - 1) / GT, sp);
+  hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, s, m1, m2, K, kchunk, X, xmap, Y, ymap,
+                     ws, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long tot = (long long)m1 * m2;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m1, m2,
+                     sp, ws, G, ldg, skip);
+  return hipGetLastError();
+}
+
+}  // namespace wc4d

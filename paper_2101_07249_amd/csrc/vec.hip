@@ -1,0 +1,347 @@
+// Vector kernels of split preconditioned CG (Section 3.1, Algorithm 1) with the
+// scalar recurrences kept on the device, plus small helpers.
+//
+// Reductions are deterministic: a fixed grid of kRB blocks writes one partial per
+// block (grid-stride order fixed by n), and a single-block kernel sums the
+// partials in index order.  Every kernel returns at once when the solve is done.
+#include "wc4d_internal.h"
+
+#include <cmath>
+
+namespace wc4d {
+
+constexpr int kRB = 1024;   // reduction blocks
+constexpr int kRT = 256;    // threads per reduction block
+
+size_t pcg_red_doubles() { return (size_t)kRB * 4; }
+
+static __device__ inline double block_sum(double v, double* sh) {
+  // wavefront reduction then across the 4 waves of a 256-thread block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+  }
+  return t;  // valid in thread 0
+}
+
+// Sum of kRB partials red[q*kRB ...] in index order (one 256-thread block).
+static __device__ inline double final_sum(const double* red, double* sh) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < kRB; b += blockDim.x) v += red[b];
+  return block_sum(v, sh);
+}
+
+// --------------------------------------------------------------- init
+__global__ __launch_bounds__(kRT) void k_dot2_partial(const double* __restrict__ a,
+                                                      const double* __restrict__ b, long long n,
+                                                      double* __restrict__ red) {
+  __shared__ double sh[16];
+  double v0 = 0.0, v1 = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT) {
+    v0 += a[i] * a[i];
+    v1 += b[i] * b[i];
+  }
+  const double t0 = block_sum(v0, sh);
+  const double t1 = block_sum(v1, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = t0;
+    red[kRB + blockIdx.x] = t1;
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_pcg_init_final(PcgState* st, const double* __restrict__ red,
+                                                        double tol, int maxit, int criterion) {
+  __shared__ double sh[16];
+  const double bb = final_sum(red, sh);
+  const double rr = final_sum(red + kRB, sh);
+  if (threadIdx.x == 0) {
+    st->bnorm2 = bb;
+    st->rr = rr;
+    st->r0norm2 = rr;
+    st->rr_new = rr;
+    st->tol = tol;
+    st->maxit = maxit;
+    st->criterion = criterion;
+    st->iter = 0;
+    st->status = 0;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->ss = 0.0;
+    st->xbs = 0.0;
+    // nothing to do for b = 0 (x = 0 solves it); r_0 = 0 means x_0 already solves it
+    st->done = (bb == 0.0 || rr == 0.0) ? 1 : 0;
+  }
+}
+
+hipError_t pcg_kernels_init(PcgState* st, const double* b, const double* s0, const double* r0,
+                            long long nA, double tol, int maxit, int criterion, double* red,
+                            hipStream_t s) {
+  (void)s0;
+  hipLaunchKernelGGL(k_dot2_partial, dim3(kRB), dim3(kRT), 0, s, b, r0, nA, red);
+  hipLaunchKernelGGL(k_pcg_init_final, dim3(1), dim3(kRT), 0, s, st, red, tol, maxit, criterion);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- alpha
+__global__ __launch_bounds__(kRT) void k_dot_partial(const PcgState* __restrict__ st,
+                                                     const double* __restrict__ a,
+                                                     const double* __restrict__ b, long long n,
+                                                     double* __restrict__ red) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT)
+    v += a[i] * b[i];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRT) void k_alpha_final(PcgState* st, const double* __restrict__ red) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double pap = final_sum(red, sh);
+  if (threadIdx.x == 0) {
+    st->pAp = pap;
+    if (!(pap > 0.0) || !isfinite(pap)) {
+      st->status = WC4D_EBREAKDOWN;
+      st->done = 1;
+    } else {
+      st->alpha = st->rr / pap;
+    }
+  }
+}
+
+hipError_t pcg_dot_alpha(PcgState* st, const double* p, const double* Ap, long long nA,
+                         double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRB), dim3(kRT), 0, s, st, p, Ap, nA, red);
+  hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(kRT), 0, s, st, red);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- x, s updates (+ partials)
+// x += alpha p; s -= alpha Ap; partials of s.s and x.(b + s) into red[0..2 kRB).
+__global__ __launch_bounds__(kRT) void k_update_xs(const PcgState* __restrict__ st,
+                                                   double* __restrict__ x, double* __restrict__ sr,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ Ap, long long n,
+                                                   double* __restrict__ red) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double vs = 0.0, vj = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT) {
+    const double xi = x[i] + alpha * p[i];
+    const double si = sr[i] - alpha * Ap[i];
+    x[i] = xi;
+    sr[i] = si;
+    vs += si * si;
+    vj += xi * (b[i] + si);
+  }
+  const double t0 = block_sum(vs, sh);
+  const double t1 = block_sum(vj, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = t0;
+    red[kRB + blockIdx.x] = t1;
+  }
+}
+
+hipError_t pcg_update_xs(PcgState* st, double* x, double* sres, const double* b, const double* p,
+                         const double* Ap, long long nA, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xs, dim3(kRB), dim3(kRT), 0, s, st, x, sres, b, p, Ap, nA, red);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------- r update, beta, convergence
+__global__ __launch_bounds__(kRT) void k_update_r(const PcgState* __restrict__ st,
+                                                  double* __restrict__ r,
+                                                  const double* __restrict__ w, long long n,
+                                                  double* __restrict__ red) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT) {
+    const double ri = r[i] - alpha * w[i];
+    r[i] = ri;
+    v += ri * ri;
+  }
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRT) void k_beta_final(PcgState* st, const double* __restrict__ red,
+                                                    double* __restrict__ hist) {
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double ss = final_sum(red, sh);
+  const double xbs = final_sum(red + kRB, sh);
+  const double rr = final_sum(red + 2 * kRB, sh);
+  if (threadIdx.x == 0) {
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->ss = ss;
+    st->xbs = xbs;
+    st->beta = rr / st->rr;
+    st->rr_new = rr;
+    st->rr = rr;
+    const double rt = sqrt(ss / st->bnorm2);
+    const double rp = sqrt(rr / st->r0norm2);
+    if (hist != nullptr) {
+      hist[it - 1] = rt;
+      hist[st->maxit + it - 1] = rp;
+      hist[2 * st->maxit + it - 1] = -0.5 * xbs;
+    }
+    const double crit = (st->criterion == WC4D_RES_TRUE) ? rt : rp;
+    if (!isfinite(crit)) {
+      st->status = WC4D_EBREAKDOWN;
+      st->done = 1;
+    } else if (crit <= st->tol) {
+      st->status = WC4D_OK;
+      st->done = 1;
+    } else if (it >= st->maxit) {
+      st->status = WC4D_ENOCONV;
+      st->done = 1;
+    }
+  }
+}
+
+hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, double* red,
+                        double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_r, dim3(kRB), dim3(kRT), 0, s, st, r, w, nA, red);
+  hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
+  return hipGetLastError();
+}
+
+// p = z + beta p
+__global__ void k_update_p(const PcgState* __restrict__ st, double* __restrict__ p,
+                           const double* __restrict__ z, long long n) {
+  if (st->done) return;
+  const double beta = st->beta;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(2048), dim3(256), 0, s, st, p, z, nA);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ helpers
+__global__ void k_copy(double* __restrict__ y, const double* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* __restrict__ y, double v, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+hipError_t vec_fill(double* y, double v, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, s, y, v, n);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_rows(double* __restrict__ T, int k, int m, int ldt,
+                             const double* __restrict__ dcoef, const int* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * m) return;
+  const int i = e % k, j = e / k;
+  T[i + (size_t)j * ldt] *= dcoef[i];
+}
+
+hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef, const int* skip,
+                          hipStream_t s) {
+  if (k * m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_rows, dim3((k * m + 255) / 256), dim3(256), 0, s, T, k, m, ldt, dcoef,
+                     skip);
+  return hipGetLastError();
+}
+
+__global__ void k_stash_innov(const double* __restrict__ d, const double* __restrict__ rinv,
+                              double* __restrict__ st, int q) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < q) st[k] = d[k] * rinv[k];
+}
+
+hipError_t stash_from_innov(const double* d, const double* rinv, double* stash, int q,
+                            hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stash_innov, dim3((q + 255) / 256), dim3(256), 0, s, d, rinv, stash, q);
+  return hipGetLastError();
+}
+
+// s_0 = b - A x_0 (the A x_0 product is skipped when x_0 = 0: flag set by init)
+__global__ void k_s0(const double* __restrict__ b, const double* __restrict__ Ax,
+                     const int* __restrict__ xzero, double* __restrict__ s0, long long n) {
+  const bool z = *xzero != 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    s0[i] = z ? b[i] : b[i] - Ax[i];
+}
+
+__global__ __launch_bounds__(kRT) void k_norm_partial(const double* __restrict__ x, long long n,
+                                                      double* __restrict__ red) {
+  __shared__ double sh[16];
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT)
+    v += x[i] * x[i];
+  const double t = block_sum(v, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kRT) void k_zero_flag(const double* __restrict__ red,
+                                                   int* __restrict__ flag) {
+  __shared__ double sh[16];
+  const double t = final_sum(red, sh);
+  if (threadIdx.x == 0) *flag = (t == 0.0) ? 1 : 0;
+}
+
+hipError_t pcg_x0_zero_flag(const double* x, long long n, double* red, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(kRB), dim3(kRT), 0, s, x, n, red);
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(kRT), 0, s, red, flag);
+  return hipGetLastError();
+}
+
+hipError_t pcg_s0(const double* b, const double* Ax, const int* xzero, double* s0, long long n,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_s0, dim3(2048), dim3(256), 0, s, b, Ax, xzero, s0, n);
+  return hipGetLastError();
+}
+
+// 2-D block copy Y(:, c) = X(:, c), rows < rows.
+__global__ void k_copy2d(double* __restrict__ Y, long long ldy, const double* __restrict__ X,
+                         long long ldx, long long rows, int cols) {
+  const int c = blockIdx.y;
+  if (c >= cols) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
+       i += (long long)gridDim.x * blockDim.x)
+    Y[i + c * ldy] = X[i + c * ldx];
+}
+
+hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, long long rows,
+                      int cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy2d, dim3(256, cols), dim3(256), 0, s, Y, ldy, X, ldx, rows, cols);
+  return hipGetLastError();
+}
+
+}  // namespace wc4d

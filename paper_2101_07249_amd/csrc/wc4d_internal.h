@@ -1,0 +1,187 @@
+// Internal declarations of libwc4d: device data layout, kernel launchers and the
+// problem / LMP handle structs.  Everything here is gfx950 (CDNA4) HIP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wc4d.h"
+
+namespace wc4d {
+
+// Column map of a matrix whose columns are contiguous runs of doubles:
+// column t starts at  (t / per) * ld + (base + t % per) * stride.
+// A block of m vectors of length n_A = n (N+1) (ld >= n_A) viewed as the
+// n x ((N+1) m) matrix of its time levels is {ld, N+1, 0, n}; its time-0
+// columns are {ld, 1, 0, n}; its time-1..N columns are {ld, N, 1, n};
+// a plain column-major matrix is {ld, 1, 0, 0}.
+struct ColMap {
+  long long ld;
+  int per;
+  int base;
+  int stride;
+  __host__ __device__ inline long long off(int t) const {
+    return (long long)(t / per) * ld + (long long)(base + t % per) * stride;
+  }
+};
+
+inline ColMap plain_cols(long long ld) { return ColMap{ld, 1, 0, 0}; }
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return hipError_t of the launch.
+
+// C(:, t) = alpha * A * B(:, t) [+ E(:, t)] for t < ncol; A column-major M x K (lda),
+// B columns K long via bmap, C / E columns M long via cmap / emap.  float64 MFMA.
+// skip: optional device flag; when *skip != 0 the kernel returns immediately.
+hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
+                    const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                    ColMap emap, const int* skip, hipStream_t s);
+
+// G(i, j) = sum_k X(k, i) Y(k, j), i < m1, j < m2, k < K; X / Y columns via maps.
+// Deterministic split-K: partial tiles then a fixed-order sum.  G column-major, ldg.
+// ws must hold gram_ws_doubles(m1, m2, K) doubles.
+size_t gram_ws_doubles(int m1, int m2, long long K);
+hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, const double* Y,
+                    ColMap ymap, double* G, int ldg, double* ws, const int* skip, hipStream_t s);
+
+// Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
+struct SweepModel {
+  int kind;                 // 0 advdiff, 1 l96
+  int n, N;
+  double ca, cb, cc;        // advdiff stencil: x'_j = ca x_{j-1} + cb x_j + cc x_{j+1}
+  double dt;                // l96 RK4 step
+  const double* stages;     // l96: device (N x 4 x n) RK4 stage inputs y1..y4 of every step
+  const int* obs_off;       // device (N+2): time i's observations are [obs_off[i], obs_off[i+1])
+  const int* obs_idx;       // device q grid indices
+  const double* obs_rinv;   // device q values 1 / R_ii
+};
+
+// Forward sweep x_0 = p_0, x_{i+1} = M_i x_i + p_{i+1}.  Writes stash(k, c) =
+// rinv[k] * x_{i(k)}[idx[k]] (ldst >= q) when stash != null, and every x_i into
+// Xout when Xout != null.
+hipError_t sweep_fwd(const SweepModel& md, const double* P, long long ldp, int m, double* stash,
+                     long long ldst, double* Xout, long long ldx, const int* skip, hipStream_t s);
+// Adjoint sweep w_N = z_N, w_i = z_i + M_i^T w_{i+1}.  z from the stash (z_i =
+// H_i^T stash_i) when stash != null, else from the dense block Z.  Writes W.
+hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, const double* Z,
+                     long long ldz, int m, double* W, long long ldw, const int* skip,
+                     hipStream_t s);
+
+// Dynamic LDS bytes the sweeps need for this model.
+size_t sweep_lds_required(const SweepModel& md);
+
+// Small dense float64 kernels (one workgroup unless stated); matrices column-major.
+// Upper Cholesky in place: G = R^T R, strict lower set to 0; *status = 1 on a
+// non-positive or non-finite pivot (status untouched otherwise).
+hipError_t chol_upper(int m, double* G, int ldg, int* status, hipStream_t s);
+// Rinv = R^{-1} for upper triangular R (one wavefront per column).
+hipError_t tri_inv_upper(int m, const double* R, int ldr, double* Rinv, int ldi, hipStream_t s);
+// C = alpha op(A) op(B), op = transpose when t* != 0; M x N result, inner K.
+hipError_t small_gemm(int M, int N, int K, double alpha, const double* A, int lda, int tA,
+                      const double* B, int ldb, int tB, double* C, int ldc, hipStream_t s);
+// Symmetric EVD of the symmetric part of K (m x m) by parallel cyclic Jacobi.
+// Outputs eigenvalues lam (decreasing) and eigenvectors V (m x m, ldv), each
+// vector's largest-magnitude entry positive.  K is overwritten.
+hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, hipStream_t s);
+// theta[i] = f(lam[i]) for i < k: f = identity (mode 0) or sqrt (mode 1);
+// dcoef[i] = theta[i]^{-1/2} - 1 (the LMP's diagonal).
+hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double* dcoef,
+                       hipStream_t s);
+
+// Vector kernels for PCG and the LMP (n_A long).
+struct PcgState {
+  double rr, rr_new, pAp, alpha, beta, bnorm2, r0norm2, ss, xbs;
+  double tol;
+  int iter, done, status, criterion, maxit, pad;
+};
+hipError_t pcg_kernels_init(PcgState* st, const double* b, const double* s0, const double* r0,
+                            long long nA, double tol, int maxit, int criterion, double* red,
+                            hipStream_t s);
+// red: reduction workspace of pcg_red_doubles() doubles.
+size_t pcg_red_doubles();
+hipError_t pcg_dot_alpha(PcgState* st, const double* p, const double* Ap, long long nA,
+                         double* red, hipStream_t s);
+hipError_t pcg_update_xs(PcgState* st, double* x, double* sres, const double* b, const double* p,
+                         const double* Ap, long long nA, double* red, hipStream_t s);
+hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, double* red,
+                        double* hist, hipStream_t s);
+hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s);
+hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
+hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef, const int* skip,
+                          hipStream_t s);
+hipError_t stash_from_innov(const double* d, const double* rinv, double* stash, int q,
+                            hipStream_t s);
+hipError_t vec_fill(double* y, double v, long long n, hipStream_t s);
+hipError_t pcg_x0_zero_flag(const double* x, long long n, double* red, int* flag, hipStream_t s);
+hipError_t pcg_s0(const double* b, const double* Ax, const int* xzero, double* s0, long long n,
+                  hipStream_t s);
+hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, long long rows,
+                      int cols, hipStream_t s);
+
+}  // namespace wc4d
+
+// ------------------------------------------------------------------- handles
+
+struct wc4d_problem_s {
+  int n = 0, N = 0, device = 0;
+  long long nA = 0;
+  int q = 0;
+  int model = -1;  // 0 advdiff, 1 l96
+  double c = 0, r = 0, F = 8, dt = 0.025;
+  std::vector<double> traj;  // (N+1) x n
+  std::vector<double> Bsqrt, Qsqrt;
+  std::vector<std::vector<int>> obs_idx;
+  std::vector<std::vector<double>> obs_r;
+  bool haveB = false, haveQ = false, finalized = false;
+  int prec = 0;
+  // device data
+  double* dB = nullptr;
+  double* dQ = nullptr;
+  double* dStages = nullptr;
+  int* dObsOff = nullptr;
+  int* dObsIdx = nullptr;
+  double* dObsRinv = nullptr;
+  // workspaces (grown on demand)
+  double* wsBlock = nullptr;  // n_A x cap
+  long long wsBlockCols = 0;
+  double* wsStash = nullptr;  // q x cap
+  long long wsStashCols = 0;
+  double* wsGram = nullptr;
+  size_t wsGramDoubles = 0;
+  // LMP build scratch: two n_A x cap blocks and m x m matrices
+  double* bufA = nullptr;
+  double* bufB = nullptr;
+  long long bufCols = 0;
+  double* small = nullptr;  // 6 m x m + 2 m doubles
+  int smallM = 0;
+  int* dStatus = nullptr;   // device status words
+  // PCG vectors and state
+  double* pcgVec = nullptr;  // 6 n_A
+  double* pcgHist = nullptr;
+  int pcgHistCap = 0;
+  double* pcgRed = nullptr;
+  wc4d::PcgState* pcgState = nullptr;
+  wc4d::PcgState* pcgStateHost = nullptr;  // pinned
+  // profiling
+  bool prof = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::string err;
+  wc4d::SweepModel sweep() const;
+};
+
+struct wc4d_lmp_s {
+  wc4d_problem p = nullptr;
+  long long nA = 0;
+  int k = 0;
+  int applies = 0;
+  double* U = nullptr;      // n_A x k
+  double* theta = nullptr;  // k
+  double* dcoef = nullptr;  // k: theta^{-1/2} - 1
+  double* T = nullptr;      // k x tcap scratch for U^T X
+  int tcap = 0;
+  double* ws = nullptr;     // gram workspace
+  size_t wsDoubles = 0;
+};

@@ -1,0 +1,351 @@
+"""Thin Python binding of libwc4d (include/wc4d.h): argument marshalling only.
+
+Every step of the operator, the randomised eigendecompositions, the LMP and PCG
+runs in the HIP library.  torch is used for device memory (tensors' data
+pointers) and streams.  A block of m vectors of length n_A is a float64 CUDA
+tensor of shape (m, n_A), contiguous: row c is vector c, i.e. the column-major
+n_A x m array with leading dimension n_A that the C-ABI expects.
+
+There is no fallback: if the library is missing or a call fails, an exception
+is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwc4d.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EBREAKDOWN, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
+CORR_SOAR, CORR_GAUSS = 0, 1
+REVD, NYSTROM, RITZIT = 0, 1, 2
+METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
+RES_TRUE, RES_PRECOND = 0, 1
+PREC_FP64 = 0
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("criterion", ctypes.c_int)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("relres_true", ctypes.c_double),
+                ("relres_precond", ctypes.c_double), ("J", ctypes.c_double)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "wc4d_version": (ctypes.c_int, []),
+    "wc4d_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "wc4d_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "wc4d_destroy": (ctypes.c_int, [_vp]),
+    "wc4d_last_error": (ctypes.c_char_p, [_vp]),
+    "wc4d_set_model_advdiff": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+    "wc4d_set_model_l96": (ctypes.c_int, [_vp, _c_dbl_p, ctypes.c_double, ctypes.c_double]),
+    "wc4d_l96_trajectory": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           _c_dbl_p, _c_dbl_p]),
+    "wc4d_corr_sqrt": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_dbl_p]),
+    "wc4d_set_Bsqrt": (ctypes.c_int, [_vp, _c_dbl_p]),
+    "wc4d_set_Qsqrt": (ctypes.c_int, [_vp, _c_dbl_p]),
+    "wc4d_set_obs": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_int_p, _c_dbl_p]),
+    "wc4d_finalize": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "wc4d_dims": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
+    "wc4d_apply_A": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_apply_Linv": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_apply_LinvT": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_apply_Dsqrt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_rhs": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "wc4d_lmp_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                      ctypes.POINTER(_vp), _vp]),
+    "wc4d_lmp_theta": (ctypes.c_int, [_vp, _c_dbl_p]),
+    "wc4d_lmp_vectors": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
+    "wc4d_lmp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_lmp_applies": (ctypes.c_int, [_vp, _c_int_p]),
+    "wc4d_lmp_destroy": (ctypes.c_int, [_vp]),
+    "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
+                                _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
+    "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wc4d_last_apply_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
+}
+
+_lib = None
+
+
+class Wc4dError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_status_name(code)}: {msg}")
+        self.code = code
+
+
+def _status_name(code: int) -> str:
+    names = {0: "WC4D_OK", -1: "WC4D_EINVAL", -2: "WC4D_ENOMEM", -3: "WC4D_EHIP", -4: "WC4D_ENOTSPD",
+             -5: "WC4D_EBREAKDOWN", -6: "WC4D_ENOCONV", -7: "WC4D_ESTATE"}
+    return names.get(code, f"status {code}")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libwc4d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2101_07249_amd/build.py "
+                              "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols() -> Sequence[str]:
+    return list(_SIGS)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_c_dbl_p)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is not None:
+        return int(stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _tptr(t) -> int:
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def corr_sqrt(n: int, kind: str, L: float, sigma: float) -> np.ndarray:
+    """sigma * C^{1/2} (host helper of the library), as an (n, n) array."""
+    out = np.empty((n, n), order="F")
+    k = CORR_SOAR if kind == "soar" else CORR_GAUSS
+    rc = lib().wc4d_corr_sqrt(n, k, float(L), float(sigma), _dptr(out))
+    if rc:
+        raise Wc4dError(rc, "wc4d_corr_sqrt")
+    return out
+
+
+def l96_trajectory(x0: np.ndarray, F: float, dt: float, N: int) -> np.ndarray:
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    n = x0.shape[0]
+    out = np.empty((N + 1, n))
+    rc = lib().wc4d_l96_trajectory(n, N, float(F), float(dt), _dptr(x0), _dptr(out))
+    if rc:
+        raise Wc4dError(rc, "wc4d_l96_trajectory")
+    return out
+
+
+class Lmp:
+    def __init__(self, handle: int, prob: "Problem", k: int):
+        self._h = handle
+        self.prob = prob
+        self.k = k
+
+    def theta(self) -> np.ndarray:
+        out = np.empty(self.k)
+        self.prob._chk(lib().wc4d_lmp_theta(self._h, _dptr(out)), "lmp_theta")
+        return out
+
+    def vectors(self, stream=None):
+        import torch
+        U = torch.empty((self.k, self.prob.n_A), dtype=torch.float64, device=self.prob.torch_device)
+        self.prob._chk(lib().wc4d_lmp_vectors(self._h, _tptr(U), self.prob.n_A, _stream(stream)), "lmp_vectors")
+        return U
+
+    def apply(self, X, Y=None, stream=None):
+        import torch
+        if Y is None:
+            Y = torch.empty_like(X)
+        m = X.shape[0] if X.dim() == 2 else 1
+        self.prob._chk(lib().wc4d_lmp_apply(self._h, _tptr(X), self.prob.n_A, _tptr(Y), self.prob.n_A, m,
+                                            _stream(stream)), "lmp_apply")
+        return Y
+
+    @property
+    def applies(self) -> int:
+        c = ctypes.c_int(0)
+        lib().wc4d_lmp_applies(self._h, ctypes.byref(c))
+        return c.value
+
+    def close(self):
+        if self._h:
+            lib().wc4d_lmp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Handle of one inner-loop problem on one GPU."""
+
+    def __init__(self, n: int, N: int, device: int = 0):
+        h = _vp()
+        rc = lib().wc4d_create(ctypes.byref(h), int(n), int(N), int(device))
+        if rc:
+            raise Wc4dError(rc, "wc4d_create")
+        self._h = h.value
+        self.n, self.N, self.device = int(n), int(N), int(device)
+        self.n_A = self.n * (self.N + 1)
+        self.q = 0
+
+    @property
+    def torch_device(self):
+        import torch
+        return torch.device("cuda", self.device)
+
+    def _chk(self, rc: int, what: str):
+        if rc != OK:
+            msg = lib().wc4d_last_error(self._h) if self._h else b""
+            raise Wc4dError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    # ---- setup
+    def set_model_advdiff(self, c: float, r: float):
+        self._chk(lib().wc4d_set_model_advdiff(self._h, float(c), float(r)), "set_model_advdiff")
+
+    def set_model_l96(self, traj: np.ndarray, F: float, dt: float):
+        t = np.ascontiguousarray(traj, dtype=np.float64)
+        if t.shape != (self.N + 1, self.n):
+            raise ValueError("trajectory must be (N+1, n)")
+        self._chk(lib().wc4d_set_model_l96(self._h, _dptr(t), float(F), float(dt)), "set_model_l96")
+
+    def set_Bsqrt(self, B: np.ndarray):
+        b = np.asfortranarray(B, dtype=np.float64)
+        self._chk(lib().wc4d_set_Bsqrt(self._h, _dptr(b)), "set_Bsqrt")
+
+    def set_Qsqrt(self, Q: np.ndarray):
+        q = np.asfortranarray(Q, dtype=np.float64)
+        self._chk(lib().wc4d_set_Qsqrt(self._h, _dptr(q)), "set_Qsqrt")
+
+    def set_obs(self, i: int, idx: np.ndarray, rdiag: np.ndarray):
+        ix = np.ascontiguousarray(idx, dtype=np.int32)
+        rd = np.ascontiguousarray(rdiag, dtype=np.float64)
+        self._chk(lib().wc4d_set_obs(self._h, int(i), int(ix.size), ix.ctypes.data_as(_c_int_p), _dptr(rd)),
+                  "set_obs")
+
+    def finalize(self, prec_mode: int = PREC_FP64, stream=None):
+        self._chk(lib().wc4d_finalize(self._h, int(prec_mode), _stream(stream)), "finalize")
+        nA, q = ctypes.c_int(), ctypes.c_int()
+        self._chk(lib().wc4d_dims(self._h, ctypes.byref(nA), ctypes.byref(q)), "dims")
+        self.n_A, self.q = nA.value, q.value
+
+    @classmethod
+    def from_workload(cls, w, pattern, x0: Optional[np.ndarray] = None, device: int = 0,
+                      sigma_o2: Optional[float] = None) -> "Problem":
+        """Set up a problem from workload parameters with the library's own helpers
+        (covariance square roots, Lorenz-96 trajectory)."""
+        p = cls(w.n, w.N, device)
+        if w.model == "advdiff":
+            p.set_model_advdiff(w.c, w.r)
+        else:
+            if x0 is None:
+                raise ValueError("Lorenz-96 needs an initial state")
+            p.traj = l96_trajectory(x0, w.F, w.dt, w.N)
+            p.set_model_l96(p.traj, w.F, w.dt)
+        p.set_Bsqrt(corr_sqrt(w.n, w.corr, w.Lb, w.sigma_b))
+        p.set_Qsqrt(corr_sqrt(w.n, w.corr, w.Lq, w.sigma_q))
+        s2 = w.sigma_o2 if sigma_o2 is None else sigma_o2
+        for i, idx in pattern:
+            p.set_obs(i, idx, np.full(len(idx), s2))
+        p.finalize()
+        return p
+
+    # ---- operator
+    def _block_call(self, fn, X, Y, stream, what):
+        import torch
+        if X.dim() == 1:
+            X2 = X.view(1, -1)
+        else:
+            X2 = X
+        if X2.shape[-1] != self.n_A:
+            raise ValueError(f"block rows must be n_A = {self.n_A}")
+        if Y is None:
+            Y = torch.empty_like(X)
+        Y2 = Y.view(1, -1) if Y.dim() == 1 else Y
+        self._chk(fn(self._h, _tptr(X2), self.n_A, _tptr(Y2), self.n_A, X2.shape[0], _stream(stream)), what)
+        return Y
+
+    def apply_A(self, X, Y=None, stream=None):
+        return self._block_call(lib().wc4d_apply_A, X, Y, stream, "apply_A")
+
+    def apply_Linv(self, X, Y=None, stream=None):
+        return self._block_call(lib().wc4d_apply_Linv, X, Y, stream, "apply_Linv")
+
+    def apply_LinvT(self, X, Y=None, stream=None):
+        return self._block_call(lib().wc4d_apply_LinvT, X, Y, stream, "apply_LinvT")
+
+    def apply_Dsqrt(self, X, Y=None, stream=None):
+        return self._block_call(lib().wc4d_apply_Dsqrt, X, Y, stream, "apply_Dsqrt")
+
+    def rhs(self, d, bt=None, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.n_A, dtype=torch.float64, device=self.torch_device)
+        bp = _tptr(bt) if bt is not None else None
+        dp = _tptr(d) if self.q > 0 else None
+        self._chk(lib().wc4d_rhs(self._h, dp, bp, _tptr(out), _stream(stream)), "rhs")
+        return out
+
+    # ---- preconditioner and solve
+    def lmp_build(self, method, k_r: int, l: int, G, stream=None) -> Lmp:
+        meth = METHOD[method] if isinstance(method, str) else int(method)
+        h = _vp()
+        self._chk(lib().wc4d_lmp_build(self._h, meth, int(k_r), int(l), _tptr(G), ctypes.byref(h),
+                                       _stream(stream)), "lmp_build")
+        return Lmp(h.value, self, int(k_r))
+
+    def pcg(self, b, x, lmp: Optional[Lmp] = None, tol: float = 1e-6, maxit: int = 100,
+            criterion: int = RES_TRUE, history: bool = True, stream=None):
+        opts = PcgOpts(float(tol), int(maxit), int(criterion))
+        info = PcgInfo()
+        ht = np.zeros(maxit) if history else None
+        hp = np.zeros(maxit) if history else None
+        hj = np.zeros(maxit) if history else None
+        rc = lib().wc4d_pcg(self._h, lmp._h if lmp is not None else None, _tptr(b), _tptr(x),
+                            ctypes.byref(opts), ctypes.byref(info),
+                            _dptr(ht) if history else None, _dptr(hp) if history else None,
+                            _dptr(hj) if history else None, _stream(stream))
+        if rc not in (OK, ENOCONV, EBREAKDOWN):
+            self._chk(rc, "pcg")
+        out = {"iters": info.iters, "status": info.status, "relres_true": info.relres_true,
+               "relres_precond": info.relres_precond, "J": info.J}
+        if history:
+            k = info.iters
+            out.update(hist_true=ht[:k], hist_precond=hp[:k], hist_J=hj[:k])
+        return out
+
+    def set_profiling(self, enable: bool = True):
+        self._chk(lib().wc4d_set_profiling(self._h, int(bool(enable))), "set_profiling")
+
+    def last_apply_timing(self) -> np.ndarray:
+        out = (ctypes.c_float * 4)()
+        self._chk(lib().wc4d_last_apply_timing(self._h, out), "last_apply_timing")
+        return np.array(list(out), dtype=np.float64)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wc4d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,62 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host-only setup helpers agree with the oracle's independent
+routes.  No device compute."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import wc4d_oracle as O
+from synthetic import l96_initial_state
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wc4d.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(wc4d_[A-Za-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_entry_points():
+    names = header_functions()
+    for must in ("wc4d_create", "wc4d_apply_A", "wc4d_lmp_build", "wc4d_pcg", "wc4d_rhs"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2101_07249_amd import wc4d
+    L = wc4d.lib()
+    for name in header_functions():
+        assert hasattr(L, name), name
+    # and the binding knows every one of them
+    assert set(header_functions()) <= set(wc4d.exported_symbols())
+    assert L.wc4d_version() >= 100
+    assert L.wc4d_status_string(-4) == b"WC4D_ENOTSPD"
+
+
+@pytest.mark.parametrize("n,kind,L,sig", [(40, "soar", 4.0, 1.0), (41, "soar", 4.0, 0.1), (80, "gauss", 2.0, 0.2),
+                                          (1, "soar", 4.0, 1.0), (2, "gauss", 2.0, 1.0)])
+def test_corr_sqrt_helper_matches_oracle(n, kind, L, sig):
+    from paper_2101_07249_amd import corr_sqrt
+    S = corr_sqrt(n, kind, L, sig)
+    So = O.cov_sqrt(n, kind, L, sig)
+    tol = 1e-12 if kind == "soar" else 1e-11
+    assert np.abs(S - So).max() <= tol * max(1.0, np.abs(So).max())
+
+
+def test_l96_trajectory_helper_matches_oracle():
+    from paper_2101_07249_amd import l96_trajectory
+    x0 = l96_initial_state(80, 2000)
+    t = l96_trajectory(x0, 8.0, 0.025, 50)
+    to = O.l96_trajectory(x0, 8.0, 0.025, 50)
+    assert np.abs(t - to).max() <= 1e-12 * np.abs(to).max()
+
+
+def test_corr_sqrt_rejects_bad_arguments():
+    from paper_2101_07249_amd import wc4d
+    out = np.empty((4, 4))
+    assert wc4d.lib().wc4d_corr_sqrt(4, 7, 1.0, 1.0, out.ctypes.data_as(wc4d._c_dbl_p)) == wc4d.EINVAL
+    assert wc4d.lib().wc4d_corr_sqrt(4, 0, -1.0, 1.0, out.ctypes.data_as(wc4d._c_dbl_p)) == wc4d.EINVAL

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on the
+same seeded inputs.  FP64 path bar: 1e-10 relative (norm-wise) unless a test
+states and justifies another bound."""
+import numpy as np
+import pytest
+
+from oracle import wc4d_oracle as O
+from synthetic import (C1, C2, Workload, innovations, l96_initial_state, obs_pattern, random_block,
+                       sketch_block)
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev():
+    return _torch().device("cuda", 0)
+
+
+def to_dev(A):
+    """(n_A, m) numpy -> (m, n_A) contiguous CUDA tensor (column-major block)."""
+    t = _torch()
+    A = np.asarray(A, dtype=np.float64)
+    if A.ndim == 1:
+        return t.from_numpy(A.copy()).to(dev())
+    return t.from_numpy(np.ascontiguousarray(A.T)).to(dev())
+
+
+def to_host(T):
+    a = T.cpu().numpy()
+    return a if a.ndim == 1 else a.T
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def tiny(model="advdiff", n=8, N=4, vs=2, ts=2, m=4, **kw):
+    if model == "advdiff":
+        return Workload(name="tiny", model="advdiff", n=n, N=N, c=0.5, r=0.1, corr="soar", Lb=2.0,
+                        Lq=2.0, sigma_b=1.0, sigma_q=0.3, obs_var_stride=vs, obs_time_stride=ts,
+                        sigma_o2=0.01, m=m, l=2, seed=17, **kw)
+    return Workload(name="tinyl96", model="l96", n=n, N=N, F=8.0, dt=0.025, corr="gauss", Lb=2.0,
+                    Lq=2.0, sigma_b=0.2, sigma_q=0.1, obs_var_stride=vs, obs_time_stride=ts,
+                    sigma_o2=0.04, m=m, l=2, seed=29, **kw)
+
+
+def pair(w, pattern=None):
+    from paper_2101_07249_amd import Problem
+    pat = obs_pattern(w) if pattern is None else pattern
+    x0 = l96_initial_state(w.n, w.seed) if w.model == "l96" else None
+    gp = Problem.from_workload(w, pat, x0=x0)
+    op = O.make_problem(w, pat, x0=x0)
+    return gp, op
+
+
+CASES = {
+    "C1": C1,
+    "C2": C2,
+    "tiny_adv": tiny(),
+    "tiny_l96": tiny("l96", n=10),
+    "ragged_adv": tiny(n=37, N=7, vs=3, ts=1),           # n not a multiple of any tile
+    "ragged_l96": tiny("l96", n=67, N=5, vs=5, ts=1),    # several waves, ragged tail
+    "wide_adv": tiny(n=300, N=3, vs=7, ts=3),             # 256 threads x 2 points, ragged
+    "n1_adv": tiny(n=1, N=6, vs=1, ts=2),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("m", [1, 3, 17])
+def test_operator_pieces(name, m):
+    w = CASES[name]
+    say("operator pieces", name, "m", m)
+    gp, op = pair(w)
+    X = random_block(op.n_A, m, 100 + m)
+    Xd = to_dev(X)
+    for what, gfn, ofn in (("Dsqrt", gp.apply_Dsqrt, O.apply_Dsqrt),
+                           ("Linv", gp.apply_Linv, O.apply_Linv),
+                           ("LinvT", gp.apply_LinvT, O.apply_LinvT),
+                           ("A", gp.apply_A, O.apply_A)):
+        Y = to_host(gfn(Xd))
+        Yo = ofn(op, X)
+        e = relerr(Y, Yo)
+        assert e <= TOL, (what, e)
+
+
+@pytest.mark.parametrize("m", [1, 130, 260])
+def test_apply_A_block_widths_C2(m):
+    # widths across the GEMM tile configurations (16 / 32 / 64 / 128 columns) and ragged tails
+    say("apply_A widths C2", m)
+    gp, op = pair(C2)
+    X = sketch_block(op.n_A, m, 7)
+    Y = to_host(gp.apply_A(to_dev(X)))
+    assert relerr(Y, O.apply_A(op, X)) <= TOL
+
+
+def test_rhs_and_no_observation_operator():
+    say("rhs C1")
+    gp, op = pair(C1)
+    d = innovations(op.q, 5, 0.1)
+    b = to_host(gp.rhs(to_dev(d)))
+    assert relerr(b, O.rhs(op, d)) <= TOL
+    bt = random_block(op.n_A, 1, 3)[:, 0]
+    b2 = to_host(gp.rhs(to_dev(d), bt=to_dev(bt)))
+    assert relerr(b2, O.rhs(op, d, bt=bt)) <= TOL
+    # without observations A is the identity
+    say("q = 0")
+    w = tiny()
+    gp0, op0 = pair(w, pattern=[])
+    X = random_block(op0.n_A, 3, 4)
+    np.testing.assert_array_equal(to_host(gp0.apply_A(to_dev(X))), X)
+
+
+def test_symmetry_and_adjoint_on_device():
+    say("symmetry C2")
+    gp, op = pair(C2)
+    U = random_block(op.n_A, 2, 8)
+    AU = to_host(gp.apply_A(to_dev(U)))
+    assert abs(U[:, 0] @ AU[:, 1] - U[:, 1] @ AU[:, 0]) <= 1e-12 * abs(U[:, 0] @ AU[:, 1])
+    LU = to_host(gp.apply_Linv(to_dev(U)))
+    LTU = to_host(gp.apply_LinvT(to_dev(U)))
+    assert abs(LU[:, 0] @ U[:, 1] - U[:, 0] @ LTU[:, 1]) <= 1e-12 * abs(LU[:, 0] @ U[:, 1])
+
+
+def _lmp_check(w, method, G=None):
+    gp, op = pair(w)
+    G = sketch_block(op.n_A, w.m, w.seed) if G is None else G
+    L = gp.lmp_build(method, w.k_r, w.l, to_dev(G))
+    th = L.theta()
+    U = to_host(L.vectors())
+    op.n_apply = 0
+    Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
+    assert L.applies == op.n_apply
+    e_th = relerr(th, tho)
+    assert e_th <= TOL, (method, e_th)
+    assert np.all(np.diff(th) <= 0)
+    np.testing.assert_allclose(U.T @ U, np.eye(w.k_r), atol=1e-10)
+    # the preconditioner's action (independent of the basis chosen inside clusters)
+    V = random_block(op.n_A, 4, 9)
+    CV = to_host(L.apply(to_dev(V)))
+    CVo = O.lmp_apply(Uo, tho, V)
+    e_c = relerr(CV, CVo)
+    return gp, op, L, e_th, e_c
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+@pytest.mark.parametrize("wname", ["C1", "C2"])
+def test_lmp_build_matches_oracle(method, wname):
+    say("lmp build", wname, method)
+    w = CASES[wname]
+    _, _, _, e_th, e_c = _lmp_check(w, method)
+    # C V depends on the Ritz vectors, whose rounding error is eps * ||A|| / gap for
+    # nearly repeated Ritz values; the bound below is that of the oracle itself
+    # under a different (Householder vs CholeskyQR2) orthonormalisation.
+    assert e_c <= 1e-8, (method, e_c)
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_pcg_matches_oracle_C1(method):
+    say("pcg C1", method)
+    w = C1
+    gp, op = pair(w)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    L = gp.lmp_build(method, w.k_r, w.l, to_dev(G))
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    bd = gp.rhs(to_dev(d))
+    x = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
+    info = gp.pcg(bd, x, L, tol=1e-6, maxit=500)
+    Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
+    ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-6, maxit=500)
+    assert info["status"] == 0 and ro.converged
+    assert abs(info["iters"] - ro.iters) <= 2, (info["iters"], ro.iters)
+    # first iterations agree closely (evaluation orders differ after that)
+    k = min(5, info["iters"], ro.iters)
+    np.testing.assert_allclose(info["hist_true"][:k], ro.hist_true[:k], rtol=1e-8)
+    np.testing.assert_allclose(info["hist_J"][:k], ro.hist_J[:k], rtol=1e-8)
+    # solved to tol: the two solutions differ by at most the two solves' errors
+    A = O.dense_A(op)
+    xs = np.linalg.solve(A, b)
+    xg = to_host(x)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(xg - xs) <= kappa * 1e-6 * np.linalg.norm(xs)
+    s = b - A @ xg
+    assert np.linalg.norm(s) / np.linalg.norm(b) <= 1.01e-6
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit", None])
+def test_pcg_tight_solution_C2(method):
+    say("pcg tight C2", method)
+    w = C2
+    gp, op = pair(w)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    L = gp.lmp_build(method, w.k_r, w.l, to_dev(G)) if method else None
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    x = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
+    info = gp.pcg(gp.rhs(to_dev(d)), x, L, tol=1e-11, maxit=3000)
+    assert info["status"] == 0, info
+    if method:
+        Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
+        ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-11, maxit=3000)
+    else:
+        ro = O.pcg(lambda v: O.apply_A(op, v), b, tol=1e-11, maxit=3000)
+    assert ro.converged
+    # both solutions satisfy ||b - A x|| <= 1e-11 ||b||; they agree to kappa-scaled 1e-11
+    xg = to_host(x)
+    assert relerr(xg, ro.x) <= 1e-6
+    assert np.linalg.norm(b - O.apply_A(op, xg)) / np.linalg.norm(b) <= 2e-11
+    # iteration counts at 1e-6 agree within +-2
+    x6 = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
+    i6 = gp.pcg(gp.rhs(to_dev(d)), x6, L, tol=1e-6, maxit=3000)
+    r6 = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho) if method else None, tol=1e-6, maxit=3000)
+    assert abs(i6["iters"] - r6.iters) <= 2, (i6["iters"], r6.iters)
+
+
+def test_pcg_precond_criterion_and_nonzero_start():
+    say("pcg precond criterion / x0")
+    from paper_2101_07249_amd import wc4d
+    w = C1
+    gp, op = pair(w)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    L = gp.lmp_build("nystrom", w.k_r, w.l, to_dev(G))
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    x0 = random_block(op.n_A, 1, 12)[:, 0]
+    x = to_dev(x0)
+    info = gp.pcg(gp.rhs(to_dev(d)), x, L, tol=1e-6, maxit=500, criterion=wc4d.RES_PRECOND)
+    Uo, tho = O.nystrom(lambda Z: O.apply_A(op, Z), G, w.k_r)
+    ro = O.pcg(lambda v: O.apply_A(op, v), b, x0=x0, lmp=(Uo, tho), tol=1e-6, maxit=500,
+               criterion=O.RES_PRECOND)
+    assert info["status"] == 0 and abs(info["iters"] - ro.iters) <= 2
+    assert info["relres_precond"] <= 1e-6
+
+
+def test_error_paths():
+    from paper_2101_07249_amd import Problem, Wc4dError, wc4d
+    t = _torch()
+    say("error paths")
+    # repeated observation index
+    p = Problem(8, 3)
+    with pytest.raises(Wc4dError) as ei:
+        p.set_obs(1, np.array([1, 1]), np.array([0.1, 0.1]))
+    assert ei.value.code == wc4d.EINVAL
+    # apply before finalize
+    with pytest.raises(Wc4dError) as ei:
+        p.apply_A(t.zeros((1, 32), dtype=t.float64, device=dev()))
+    assert ei.value.code == wc4d.ESTATE
+    # rank-deficient sketch: duplicated columns -> Cholesky failure
+    gp, op = pair(C1)
+    G = sketch_block(op.n_A, C1.m, 3)
+    G[:, 1] = G[:, 0]
+    with pytest.raises(Wc4dError) as ei:
+        gp.lmp_build("revd", C1.k_r, C1.l, to_dev(G))
+    assert ei.value.code == wc4d.ENOTSPD
+    # NaN right-hand side -> breakdown; tiny maxit -> no convergence
+    b = t.full((op.n_A,), float("nan"), dtype=t.float64, device=dev())
+    x = t.zeros(op.n_A, dtype=t.float64, device=dev())
+    assert gp.pcg(b, x, None, tol=1e-6, maxit=10)["status"] == wc4d.EBREAKDOWN
+    d = innovations(op.q, 1, 0.1)
+    x = t.zeros(op.n_A, dtype=t.float64, device=dev())
+    assert gp.pcg(gp.rhs(to_dev(d)), x, None, tol=1e-12, maxit=3)["status"] == wc4d.ENOCONV
+    # zero right-hand side: x = 0 in zero iterations
+    x = t.zeros(op.n_A, dtype=t.float64, device=dev())
+    info = gp.pcg(t.zeros(op.n_A, dtype=t.float64, device=dev()), x, None, tol=1e-6, maxit=10)
+    assert info["status"] == 0 and info["iters"] == 0
