@@ -1,0 +1,189 @@
+"""Benchmark: time to a 1e-6 residual of one randomised-LMP preconditioned inner loop.
+
+One step = the whole hot path on one synthetic problem already resident in HBM:
+right-hand side (D^{1/2} L^{-T} H^T R^{-1} d), LMP build from a Gaussian sketch
+(two block Hessian applies, CholeskyQR2, the small eigenproblem, Ritz vectors) and
+split PCG on the exact Hessian until ||b - A x|| <= 1e-6 ||b||.
+
+Default workload: periodic advection-diffusion n = 4096, N = 100 (n_A = 413,696),
+SOAR B / Q, every 4th point observed at every 2nd step (q = 51,200), a sketch of
+m = 256 columns (k_r = 251 Ritz pairs, oversampling 5), Nystrom, float64.
+
+Prints one JSON line (see the fields below).  Only --gpus 1 is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
+    ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--maxit", type=int, default=5000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-cols", type=int, default=8)
+    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, pat, gpu_iters, args):
+    """Time the oracle on a bounded sample of the same workload and scale it to one step:
+    block apply of a few sketch columns (scaled to the 2 m columns of a two-pass build),
+    Householder QR of a 64-column slab (scaled by (m/64)^2 per orthonormalisation, two
+    per build), and a few PCG iterations with a k_r-column LMP (scaled to the GPU run's
+    iteration count)."""
+    import numpy as np
+
+    from oracle import wc4d_oracle as O
+    from synthetic import innovations, random_block, sketch_block
+
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    op = O.make_problem(w, pat)
+    cols = args.cpu_sample_cols
+    G = np.asfortranarray(sketch_block(op.n_A, w.m, w.seed)[:, :cols])
+    t0 = time.perf_counter()
+    O.apply_A(op, G)
+    t_apply_col = (time.perf_counter() - t0) / cols
+    slab = np.asfortranarray(G[:, :min(64, w.m)]) if cols >= 64 else random_block(op.n_A, min(64, w.m), 5)
+    t0 = time.perf_counter()
+    np.linalg.qr(slab, mode="reduced")
+    t_qr = (time.perf_counter() - t0) * (w.m / slab.shape[1]) ** 2
+    # LMP of the right size (values do not change the timing of the sample)
+    U = random_block(op.n_A, w.k_r, 6)
+    theta = np.linspace(1e4, 2.0, w.k_r)
+    b = O.rhs(op, innovations(op.q, w.seed, np.sqrt(w.sigma_o2)))
+    it = args.cpu_sample_iters
+    t0 = time.perf_counter()
+    O.pcg(lambda v: O.apply_A(op, v), b, lmp=(U, theta), tol=0.0, maxit=it)
+    t_iter = (time.perf_counter() - t0) / it
+    est_ms = 1e3 * (2 * w.m * t_apply_col + 2 * t_qr + gpu_iters * t_iter)
+    return {"value": est_ms, "unit": "ms per step (estimated)", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle on the same workload: block apply of {cols} sketch columns "
+                       f"({1e3 * t_apply_col:.1f} ms/column, scaled to 2 x {w.m}), Householder QR of a "
+                       f"{slab.shape[1]}-column slab (scaled by (m/64)^2, two per build: {1e3 * t_qr:.0f} ms), "
+                       f"{it} PCG iterations with a {w.k_r}-vector LMP ({1e3 * t_iter:.0f} ms/iteration, "
+                       f"scaled to {gpu_iters} iterations); EVD of the m x m matrix not included")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd import Problem
+    from synthetic import WORKLOADS, innovations, obs_pattern, sketch_block
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    w = WORKLOADS[args.workload]
+    pat = obs_pattern(w)
+    prob = Problem.from_workload(w, pat)
+    G = torch.from_numpy(np.ascontiguousarray(sketch_block(prob.n_A, w.m, w.seed).T)).to(dev)
+    d = torch.from_numpy(innovations(prob.q, w.seed, np.sqrt(w.sigma_o2))).to(dev)
+    x = torch.zeros(prob.n_A, dtype=torch.float64, device=dev)
+
+    def step():
+        b = prob.rhs(d)
+        L = prob.lmp_build(args.method, w.k_r, w.l, G)
+        x.zero_()
+        info = prob.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
+        L.close()
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.prof_enable(True)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.prof_read()
+    prob.prof_enable(False)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in infos)
+
+    # Hessian apply on the sketch-width block (per-stage HIP events)
+    Y = torch.empty_like(G)
+    prob.set_profiling(True)
+    stages = np.zeros(4)
+    reps = 3
+    for _ in range(reps):
+        prob.apply_A(G, Y)
+        stages += prob.last_apply_timing()
+    prob.set_profiling(False)
+    stages /= reps
+    nA, q, m = prob.n_A, prob.q, w.m
+    sweep_bytes = 8.0 * (nA + q) * m
+    gemm_flops = 2.0 * w.n * w.n * (w.N + 1) * m
+    hess = {"m": m, "ms": float(stages.sum()),
+            "sweep_fwd_GBps": sweep_bytes / (stages[1] * 1e-3) / 1e9,
+            "sweep_adj_GBps": sweep_bytes / (stages[2] * 1e-3) / 1e9,
+            "sweep_hbm_frac": (2 * sweep_bytes / ((stages[1] + stages[2]) * 1e-3) / 1e9) / HBM_PEAK_GBS,
+            "dsqrt_gemm_TFLOPs": 2 * gemm_flops / ((stages[0] + stages[3]) * 1e-3) / 1e12,
+            "stage_ms": [float(v) for v in stages]}
+
+    # roofline of the kernel class that takes the most time in the timed region
+    classes = {k: v for k, v in prof.items() if v["launches"] > 0 and k != "build_other"}
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    dv = classes[dom]
+    if dom == "dsqrt_gemm":
+        achieved = dv["flops"] / (dv["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    else:
+        achieved = dv["bytes"] / (dv["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": dom, "launches": dv["launches"], "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
+                 "algorithmic_per_launch": (dv["flops"] if dom == "dsqrt_gemm" else dv["bytes"]) / dv["launches"]})
+
+    iters = int(np.median([i["iters"] for i in infos]))
+    out = {
+        "metric": "PCG time-to-1e-6 residual (learned/mixed vs plain FP64); Hessian-apply HBM GB/s",
+        "value": ms_per_step, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "variant": "plain FP64 Gaussian sketch", "method": args.method,
+                   "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,
+                   "criterion": "true residual ||b - A x|| / ||b||"},
+        "pcg_iters": iters, "relres_true": max(i["relres_true"] for i in infos), "converged": ok,
+        "hessian_apply": hess,
+        "kernel_classes_ms": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, pat, iters, args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -191,6 +191,21 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
 int wc4d_set_profiling(wc4d_problem p, int enable);
 int wc4d_last_apply_timing(wc4d_problem p, float* ms4);
 
+/* Per-class kernel timing.  When enabled, the library brackets each timed launch
+ * group with HIP events on the stream it launches on and accumulates, per class,
+ * the elapsed device time, the number of launch groups and the algorithmic bytes
+ * and flops of those launches (the minimum traffic and arithmetic the operation
+ * needs, not counter readings).  Classes: 0 D^{1/2} products of the operator,
+ * 1 forward sweep (+ observation gather), 2 adjoint sweep (+ scatter), 3 the U^T x
+ * pass and 4 the x + U t pass of a single-vector LMP application, 5 the other
+ * kernels of an LMP build.  wc4d_prof_enable resets the totals; wc4d_prof_read
+ * waits for the recorded work and reports one class. */
+enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC4D_PROF_LMP_T = 3,
+       WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_NCLASS = 6 };
+int wc4d_prof_enable(wc4d_problem p, int enable);
+int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
+                   double* flops);
+
 #ifdef __cplusplus
 }
 #endif

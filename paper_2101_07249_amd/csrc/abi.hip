@@ -86,6 +86,55 @@ int ensure_gram(wc4d_problem p, size_t doubles) {
 
 bool is_state_ok(wc4d_problem p) { return p != nullptr && p->finalized; }
 
+// ---- per-class kernel timing: an event pair around each timed launch group
+hipEvent_t prof_event(wc4d_problem p) {
+  if (p->evnext == p->evpool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->evpool.push_back(e);
+  }
+  return p->evpool[p->evnext++];
+}
+
+struct ProfScope {
+  wc4d_problem p;
+  hipStream_t s;
+  int cls;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  ProfScope(wc4d_problem p_, hipStream_t s_, int cls_, double bytes_, double flops_)
+      : p(p_), s(s_), cls(cls_), bytes(bytes_), flops(flops_) {
+    if (p->kprof) {
+      a = prof_event(p);
+      if (a != nullptr) (void)hipEventRecord(a, s);
+    }
+  }
+  ~ProfScope() {
+    if (a == nullptr) return;
+    hipEvent_t b = prof_event(p);
+    if (b == nullptr) return;
+    (void)hipEventRecord(b, s);
+    p->recs.push_back(ProfRec{cls, a, b, bytes, flops});
+  }
+};
+
+int prof_collect(wc4d_problem p) {
+  if (p->recs.empty()) return WC4D_OK;
+  hipError_t e = hipEventSynchronize(p->recs.back().b);
+  if (e != hipSuccess) return fail(p, WC4D_EHIP, hipGetErrorString(e));
+  for (const ProfRec& r : p->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    p->profMs[r.cls] += ms;
+    p->profBytes[r.cls] += r.bytes;
+    p->profFlops[r.cls] += r.flops;
+    p->profCalls[r.cls] += 1;
+  }
+  p->recs.clear();
+  p->evnext = 0;
+  return WC4D_OK;
+}
+
 // L96 tendency (Section 5.2, eq. lorenz96) on the host, for the trajectory helper
 // and the RK4 stage inputs uploaded at finalize.
 void l96_f(const double* x, double* f, int n, double F) {
@@ -173,6 +222,7 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->wsBlock);
   dev_free(&p->wsStash);
   dev_free(&p->wsGram);
+  dev_free(&p->wsSplit);
   dev_free(&p->bufA);
   dev_free(&p->bufB);
   dev_free(&p->small);
@@ -184,6 +234,7 @@ int wc4d_destroy(wc4d_problem p) {
   if (p->pcgStateHost != nullptr) (void)hipHostFree(p->pcgStateHost);
   for (auto& e : p->ev)
     if (e != nullptr) (void)hipEventDestroy(e);
+  for (auto& e : p->evpool) (void)hipEventDestroy(e);
   delete p;
   return WC4D_OK;
 }
@@ -353,6 +404,9 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
     return fail(p, WC4D_EINVAL, "state too large for the sweep's LDS (" + std::to_string(need) +
                                     " > " + std::to_string(maxLds) + " bytes)");
   if ((rc = dev_alloc(p, &p->dStatus, 16))) return rc;
+  // split-K partials: up to 512 workgroups' worth of n x 112 tiles
+  p->wsSplitDoubles = std::min<size_t>((size_t)8 * n * 112, (size_t)1 << 24);
+  if ((rc = dev_alloc(p, &p->wsSplit, p->wsSplitDoubles))) return rc;
   HIPCHK(p, hipMemsetAsync(p->dStatus, 0, 16 * sizeof(int), s));
   HIPCHK(p, hipStreamSynchronize(s));
   p->prec = prec_mode;
@@ -364,6 +418,32 @@ int wc4d_dims(wc4d_problem p, int* nA, int* q) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   if (nA) *nA = (int)p->nA;
   if (q) *q = p->q;
+  return WC4D_OK;
+}
+
+int wc4d_prof_enable(wc4d_problem p, int enable) {
+  if (p == nullptr) return WC4D_EINVAL;
+  DevGuard g(p->device);
+  int rc = prof_collect(p);
+  if (rc) return rc;
+  for (int c = 0; c < PROF_NCLASS; ++c) {
+    p->profMs[c] = p->profBytes[c] = p->profFlops[c] = 0.0;
+    p->profCalls[c] = 0;
+  }
+  p->kprof = enable != 0;
+  return WC4D_OK;
+}
+
+int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* calls, double* bytes,
+                   double* flops) {
+  if (p == nullptr || cls < 0 || cls >= PROF_NCLASS) return WC4D_EINVAL;
+  DevGuard g(p->device);
+  int rc = prof_collect(p);
+  if (rc) return rc;
+  if (ms) *ms = p->profMs[cls];
+  if (calls) *calls = p->profCalls[cls];
+  if (bytes) *bytes = p->profBytes[cls];
+  if (flops) *flops = p->profFlops[cls];
   return WC4D_OK;
 }
 
@@ -396,9 +476,9 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
                 const double* E, long long lde, const int* skip, hipStream_t s) {
   const int n = p->n, N = p->N;
   HIPCHK(p, gemm_f64(n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y, ColMap{ldy, 1, 0, n}, E,
-                     ColMap{lde, 1, 0, n}, skip, s));
+                     ColMap{lde, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
   HIPCHK(p, gemm_f64(n, m * N, n, 1.0, p->dQ, n, X, ColMap{ldx, N, 1, n}, Y, ColMap{ldy, N, 1, n},
-                     E, ColMap{lde, N, 1, n}, skip, s));
+                     E, ColMap{lde, N, 1, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
   return WC4D_OK;
 }
 
@@ -412,15 +492,31 @@ int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long
   }
   const SweepModel md = p->sweep();
   double* P = p->wsBlock;
+  const double n2 = (double)p->n * p->n, blk = 8.0 * (double)nA * m, stash = 8.0 * (double)p->q * m;
+  const double gflops = 2.0 * n2 * (p->N + 1) * m;
+  const double traj = (p->model == 1) ? 8.0 * 4.0 * p->n * p->N : 0.0;  // stage inputs, read once
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[0], s));
-  int rc = dsqrt_apply(p, X, ldx, P, nA, m, nullptr, 0, skip, s);
+  int rc;
+  {
+    ProfScope ps(p, s, PROF_DSQRT, 16.0 * n2 + 2.0 * blk, gflops);
+    rc = dsqrt_apply(p, X, ldx, P, nA, m, nullptr, 0, skip, s);
+  }
   if (rc) return rc;
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[1], s));
-  HIPCHK(p, sweep_fwd(md, P, nA, m, p->wsStash, p->q, nullptr, 0, skip, s));
+  {
+    ProfScope ps(p, s, PROF_SWEEP_FWD, blk + stash + traj, 0.0);
+    HIPCHK(p, sweep_fwd(md, P, nA, m, p->wsStash, p->q, nullptr, 0, skip, s));
+  }
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[2], s));
-  HIPCHK(p, sweep_bwd(md, p->wsStash, p->q, nullptr, 0, m, P, nA, skip, s));
+  {
+    ProfScope ps(p, s, PROF_SWEEP_BWD, blk + stash + traj, 0.0);
+    HIPCHK(p, sweep_bwd(md, p->wsStash, p->q, nullptr, 0, m, P, nA, skip, s));
+  }
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[3], s));
-  rc = dsqrt_apply(p, P, nA, Y, ldy, m, X, ldx, skip, s);
+  {
+    ProfScope ps(p, s, PROF_DSQRT, 16.0 * n2 + 3.0 * blk, gflops);
+    rc = dsqrt_apply(p, P, nA, Y, ldy, m, X, ldx, skip, s);
+  }
   if (rc) return rc;
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[4], s));
   return WC4D_OK;
@@ -530,6 +626,7 @@ struct Small {
 // tmp: n_A x m scratch.  When Rout != null, R = R2 R1 is written there (m x m).
 int cholqr2(wc4d_problem p, double* Y, double* tmp, int m, Small& sm, double* Rout, hipStream_t s) {
   const long long nA = p->nA;
+  ProfScope ps(p, s, PROF_BUILD, 8.0 * 6.0 * (double)nA * m, 8.0 * (double)nA * m * m);
   const ColMap cm = plain_cols(nA);
   int* st = p->dStatus;
   HIPCHK(p, gram_f64(m, m, nA, Y, cm, Y, cm, sm.G, m, p->wsGram, nullptr, s));
@@ -622,6 +719,7 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
     Zfinal = B_;
     mode = 1;
   }
+  ProfScope ps_tail(p, s, PROF_BUILD, 8.0 * (double)nA * (m + k_r), 2.0 * (double)nA * m * k_r);
   he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, s);
   if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
   if (he == hipSuccess)
@@ -666,6 +764,24 @@ int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long l
                    const int* skip, hipStream_t s) {
   wc4d_problem p = L->p;
   int rc;
+  if (m <= 2) {
+    const size_t need = lmp_gemv_ws_doubles(L->nA, L->k);
+    if (L->wsvDoubles < need) {
+      if ((rc = dev_alloc(p, &L->wsv, need))) return rc;
+      L->wsvDoubles = need;
+    }
+    const double ub = 8.0 * (double)L->nA * L->k, fl = 2.0 * (double)L->nA * L->k;
+    for (int c = 0; c < m; ++c) {
+      {
+        ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * L->nA, fl);
+        HIPCHK(p, lmp_gemv_t(L->nA, L->k, L->U, L->nA, L->dcoef, X + (size_t)c * ldx, L->wsv, skip, s));
+      }
+      ProfScope ps(p, s, PROF_LMP_N, ub + 16.0 * L->nA, fl);
+      HIPCHK(p, lmp_gemv_n(L->nA, L->k, L->U, L->nA, X + (size_t)c * ldx, Y + (size_t)c * ldy, L->wsv,
+                           skip, s));
+    }
+    return WC4D_OK;
+  }
   if (L->tcap < m) {
     if ((rc = dev_alloc(p, &L->T, (size_t)L->k * m))) return rc;
     L->tcap = m;
@@ -703,6 +819,7 @@ int wc4d_lmp_destroy(wc4d_lmp L) {
   dev_free(&L->dcoef);
   dev_free(&L->T);
   dev_free(&L->ws);
+  dev_free(&L->wsv);
   delete L;
   return WC4D_OK;
 }

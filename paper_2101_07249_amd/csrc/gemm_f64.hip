@@ -13,6 +13,8 @@
 // one column of C and store 128 contiguous bytes.
 #include "wc4d_internal.h"
 
+#include <algorithm>
+
 namespace wc4d {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -22,13 +24,16 @@ static __device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
 }
 
 // Tile BM (rows of C) x BN (columns of C), K step BK, 256 threads = WGI x WGJ waves.
-template <int BM, int BN, int BK, int WGI, int WGJ>
+// SPLIT: blockIdx.z takes K range [z kchunk, (z+1) kchunk) and writes its partial
+// tile to ws + z M ncol (plain M x ncol); k_gemm_splitk_reduce finishes.
+template <int BM, int BN, int BK, int WGI, int WGJ, bool SPLIT>
 __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double alpha,
                                                   const double* __restrict__ A, long long lda,
                                                   const double* __restrict__ B, ColMap bmap,
                                                   double* __restrict__ C, ColMap cmap,
                                                   const double* __restrict__ E, ColMap emap,
-                                                  const int* __restrict__ skip) {
+                                                  const int* __restrict__ skip, int kchunk,
+                                                  double* __restrict__ ws) {
   static_assert(WGI * WGJ == 4, "4 waves");
   constexpr int WI = BM / WGI, WJ = BN / WGJ;
   constexpr int TI = WI / 16, TJ = WJ / 16;
@@ -48,6 +53,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
   const int j0 = blockIdx.y * BN;
   const int wi0 = (wave % WGI) * WI;
   const int wj0 = (wave / WGI) * WJ;
+  const int kbeg = SPLIT ? blockIdx.z * kchunk : 0;
+  const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
 
   d4 acc[TJ][TI];
 #pragma unroll
@@ -69,16 +76,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
     for (int e = 0; e < NA; ++e) {
       const int idx = tid + 256 * e;
       const int gi = i0 + idx % BM, gk = k0 + idx / BM;
-      ra[e] = (gi < M && gk < K) ? A[(long long)gi + (long long)gk * lda] : 0.0;
+      ra[e] = (gi < M && gk < kend) ? A[(long long)gi + (long long)gk * lda] : 0.0;
     }
 #pragma unroll
     for (int e = 0; e < NB; ++e) {
       const int gk = k0 + (tid + 256 * e) % BK;
-      rb[e] = (bval[e] && gk < K) ? B[boff[e] + gk] : 0.0;
+      rb[e] = (bval[e] && gk < kend) ? B[boff[e] + gk] : 0.0;
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < NA; ++e) {
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
       Bs[idx % BK][idx / BK] = rb[e];
     }
     __syncthreads();
-    if (k0 + BK < K) gload(k0 + BK);
+    if (k0 + BK < kend) gload(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -112,6 +119,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
     for (int r = 0; r < 4; ++r) {
       const int j = j0 + wj0 + a * 16 + (lane >> 4) + 4 * r;
       if (j >= ncol) continue;
+      if (SPLIT) {
+        double* wz = ws + (size_t)blockIdx.z * M * ncol + (size_t)j * M;
+#pragma unroll
+        for (int b = 0; b < TI; ++b) {
+          const int i = i0 + wi0 + b * 16 + (lane & 15);
+          if (i < M) wz[i] = acc[a][b][r];
+        }
+        continue;
+      }
       const long long co = cmap.off(j);
       const long long eo = (E != nullptr) ? emap.off(j) : 0;
 #pragma unroll
@@ -127,30 +143,82 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
   }
 }
 
-template <int BM, int BN, int WGI, int WGJ>
+__global__ void k_gemm_splitk_reduce(int M, int ncol, int splits, double alpha,
+                                     const double* __restrict__ ws, double* __restrict__ C,
+                                     ColMap cmap, const double* __restrict__ E, ColMap emap,
+                                     const int* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const int j = blockIdx.y;
+  const long long co = cmap.off(j);
+  const long long eo = (E != nullptr) ? emap.off(j) : 0;
+  const size_t plane = (size_t)M * ncol;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int z = 0; z < splits; ++z) v += ws[z * plane + (size_t)j * M + i];
+    v *= alpha;
+    if (E != nullptr) v += E[eo + i];
+    C[co + i] = v;
+  }
+}
+
+template <int BM, int BN, int BK, int WGI, int WGJ>
 static hipError_t launch_gemm(int M, int ncol, int K, double alpha, const double* A, long long lda,
                               const double* B, ColMap bmap, double* C, ColMap cmap,
                               const double* E, ColMap emap, const int* skip, hipStream_t s) {
   dim3 grid((M + BM - 1) / BM, (ncol + BN - 1) / BN);
-  hipLaunchKernelGGL((k_gemm_f64<BM, BN, 16, WGI, WGJ>), grid, dim3(256), 0, s, M, ncol, K, alpha,
-                     A, lda, B, bmap, C, cmap, E, emap, skip);
+  hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, WGI, WGJ, false>), grid, dim3(256), 0, s, M, ncol, K,
+                     alpha, A, lda, B, bmap, C, cmap, E, emap, skip, K, nullptr);
+  return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WGI, int WGJ>
+static hipError_t launch_gemm_split(int M, int ncol, int K, int splits, double alpha,
+                                    const double* A, long long lda, const double* B, ColMap bmap,
+                                    double* C, ColMap cmap, const double* E, ColMap emap,
+                                    const int* skip, double* ws, hipStream_t s) {
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  splits = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + BM - 1) / BM, (ncol + BN - 1) / BN, splits);
+  hipLaunchKernelGGL((k_gemm_f64<BM, BN, BK, WGI, WGJ, true>), grid, dim3(256), 0, s, M, ncol, K,
+                     alpha, A, lda, B, bmap, C, cmap, E, emap, skip, kchunk, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 rg((M + 255) / 256 < 64 ? (M + 255) / 256 : 64, ncol);
+  hipLaunchKernelGGL(k_gemm_splitk_reduce, rg, dim3(256), 0, s, M, ncol, splits, alpha, ws, C, cmap,
+                     E, emap, skip);
   return hipGetLastError();
 }
 
 hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
                     const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
-                    ColMap emap, const int* skip, hipStream_t s) {
+                    ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles) {
   if (M <= 0 || ncol <= 0) return hipSuccess;
   auto tiles = [&](int bm, int bn) {
     return (long long)((M + bm - 1) / bm) * (long long)((ncol + bn - 1) / bn);
   };
+  // Few output columns and a long K: split K so the launch fills the chip.
+  if (ws != nullptr && ncol <= 112 && K >= 512) {
+    const int bn = ncol <= 16 ? 16 : 112;
+    const long long t = tiles(64, bn);
+    long long splits = (512 + t - 1) / t;
+    splits = std::min<long long>(splits, K / 256);
+    while (splits > 1 && (size_t)splits * M * ncol > ws_doubles) --splits;
+    if (splits >= 2) {
+      if (bn == 16)
+        return launch_gemm_split<64, 16, 32, 4, 1>(M, ncol, K, (int)splits, alpha, A, lda, B, bmap,
+                                                   C, cmap, E, emap, skip, ws, s);
+      return launch_gemm_split<64, 112, 32, 4, 1>(M, ncol, K, (int)splits, alpha, A, lda, B, bmap, C,
+                                                  cmap, E, emap, skip, ws, s);
+    }
+  }
   if (ncol <= 16)
-    return launch_gemm<128, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    return launch_gemm<128, 16, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
   if (tiles(128, 128) >= 1024)
-    return launch_gemm<128, 128, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    return launch_gemm<128, 128, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
   if (tiles(64, 64) >= 1024)
-    return launch_gemm<64, 64, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
-  return launch_gemm<32, 32, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    return launch_gemm<64, 64, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  return launch_gemm<32, 32, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
 }
 
 // ------------------------------------------------------------------ Gram

@@ -37,27 +37,210 @@ static __device__ inline double l96_jacT(const double* y, const double* a, int j
   return y[m2] * a[m1] - y[p1] * a[p2] + (y[p2] - y[m1]) * a[p1] - a[j];
 }
 
-// Observation stash of time level i: stash[k] = rinv[k] * x[idx[k]].
-static __device__ inline void obs_gather(const SweepModel& md, int i, const double* x, double* st,
-                                         int lt, int tpc) {
-  const int kb = md.obs_off[i], ke = md.obs_off[i + 1];
-  for (int k = kb + lt; k < ke; k += tpc) st[k] = md.obs_rinv[k] * x[md.obs_idx[k]];
+// Observations of one time level, prefetched: up to kOB entries per thread
+// (k = kb + lt + o tpc); entries beyond that are read directly.
+constexpr int kOB = 4;
+
+struct ObsBuf {
+  int kb, ke;
+  int idx[kOB];
+  double val[kOB];  // forward: 1 / R_kk; adjoint: the stash value
+};
+
+// Forward: the list of time t (indices and 1/R); beyond N it is empty.
+static __device__ inline void obs_load_fwd(const SweepModel& md, const int* s_off, int t, int N,
+                                           int lt, int tpc, ObsBuf& ob) {
+  ob.kb = (t <= N) ? s_off[t] : 0;
+  ob.ke = (t <= N) ? s_off[t + 1] : 0;
+#pragma unroll
+  for (int o = 0; o < kOB; ++o) {
+    const int k = ob.kb + lt + o * tpc;
+    const bool v = k < ob.ke;
+    ob.idx[o] = v ? md.obs_idx[k] : 0;
+    ob.val[o] = v ? md.obs_rinv[k] : 0.0;
+  }
 }
-// Scatter-add of the stash (H_i^T); indices within one time level are distinct.
-static __device__ inline void obs_scatter(const SweepModel& md, int i, double* w, const double* st,
-                                          int lt, int tpc) {
-  const int kb = md.obs_off[i], ke = md.obs_off[i + 1];
-  for (int k = kb + lt; k < ke; k += tpc) w[md.obs_idx[k]] += st[k];
+// stash[k] = rinv[k] x[idx[k]]
+static __device__ inline void obs_gather(const SweepModel& md, const ObsBuf& ob, const double* x,
+                                         double* st, int lt, int tpc) {
+#pragma unroll
+  for (int o = 0; o < kOB; ++o) {
+    const int k = ob.kb + lt + o * tpc;
+    if (k < ob.ke) st[k] = ob.val[o] * x[ob.idx[o]];
+  }
+  for (int k = ob.kb + lt + kOB * tpc; k < ob.ke; k += tpc) st[k] = md.obs_rinv[k] * x[md.obs_idx[k]];
+}
+// Adjoint: indices and stash values of time t (t >= 0).
+static __device__ inline void obs_load_bwd(const SweepModel& md, const int* s_off, int t,
+                                           const double* st, int lt, int tpc, ObsBuf& ob) {
+  ob.kb = (t >= 0) ? s_off[t] : 0;
+  ob.ke = (t >= 0) ? s_off[t + 1] : 0;
+#pragma unroll
+  for (int o = 0; o < kOB; ++o) {
+    const int k = ob.kb + lt + o * tpc;
+    const bool v = k < ob.ke;
+    ob.idx[o] = v ? md.obs_idx[k] : 0;
+    ob.val[o] = v ? st[k] : 0.0;
+  }
+}
+// w[idx[k]] += stash[k] (H^T); indices within one time level are distinct.
+static __device__ inline void obs_scatter(const SweepModel& md, const ObsBuf& ob, double* w,
+                                          const double* st, int lt, int tpc) {
+#pragma unroll
+  for (int o = 0; o < kOB; ++o) {
+    const int k = ob.kb + lt + o * tpc;
+    if (k < ob.ke) w[ob.idx[o]] += ob.val[o];
+  }
+  for (int k = ob.kb + lt + kOB * tpc; k < ob.ke; k += tpc) w[md.obs_idx[k]] += st[k];
 }
 
 // --------------------------------------------------------------- forward
 
+// Tangent-linear step x_{i+1} = M_i x_i + p_{i+1}: reads cur (LDS), returns xn.
+template <class Ops, int PPT>
+static __device__ inline void tl_step(const SweepModel& md, int i, const double* cur, double* ys,
+                                      double* t1, double* t2, const double (&pf)[PPT],
+                                      double (&xn)[PPT], int lt, int tpc) {
+  const int n = md.n;
+  if constexpr (!Ops::kStages) {
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+        xn[e] = md.ca * cur[jm] + md.cb * cur[j] + md.cc * cur[jp] + pf[e];
+      }
+    }
+  } else {
+    // RK4 tangent-linear step at trajectory point x_i (stage inputs y1..y4).
+    const double dt = md.dt;
+    const double* st = md.stages + (size_t)i * 4 * n;
+    for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) ys[idx] = st[idx];
+    __syncthreads();
+    double dx[PPT], d1[PPT], d2[PPT], d3[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        dx[e] = cur[j];
+        d1[e] = l96_jac(ys, cur, j, n);
+        t1[j] = dx[e] + 0.5 * dt * d1[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        d2[e] = l96_jac(ys + n, t1, j, n);
+        t2[j] = dx[e] + 0.5 * dt * d2[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        d3[e] = l96_jac(ys + 2 * n, t2, j, n);
+        t1[j] = dx[e] + dt * d3[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        const double d4v = l96_jac(ys + 3 * n, t1, j, n);
+        xn[e] = dx[e] + (dt / 6.0) * (d1[e] + 2.0 * d2[e] + 2.0 * d3[e] + d4v) + pf[e];
+      }
+    }
+  }
+}
+
+// Adjoint step w_i = M_i^T w_{i+1} + z_i (z_i dense part only): reads cur, returns wn.
+template <class Ops, int PPT>
+static __device__ inline void adj_step(const SweepModel& md, int i, const double* cur, double* ys,
+                                       double* t1, double* t2, const double (&zf)[PPT],
+                                       double (&wn)[PPT], int lt, int tpc) {
+  const int n = md.n;
+  if constexpr (!Ops::kStages) {
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+        // (M^T w)_j = ca w_{j+1} + cb w_j + cc w_{j-1}
+        wn[e] = md.ca * cur[jp] + md.cb * cur[j] + md.cc * cur[jm] + zf[e];
+      }
+    }
+  } else {
+    // Reverse-mode sweep through the RK4 stages of the step from x_i.
+    const double dt = md.dt;
+    const double* st = md.stages + (size_t)i * 4 * n;
+    for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) ys[idx] = st[idx];
+    __syncthreads();
+    double a[PPT], ax[PPT];
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        a[e] = cur[j];
+        const double u4 = (dt / 6.0) * l96_jacT(ys + 3 * n, cur, j, n);
+        ax[e] = a[e] + u4;
+        t1[j] = (dt / 3.0) * a[e] + dt * u4;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        const double u3 = l96_jacT(ys + 2 * n, t1, j, n);
+        ax[e] += u3;
+        t2[j] = (dt / 3.0) * a[e] + 0.5 * dt * u3;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        const double u2 = l96_jacT(ys + n, t2, j, n);
+        ax[e] += u2;
+        t1[j] = (dt / 6.0) * a[e] + 0.5 * dt * u2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) wn[e] = ax[e] + l96_jacT(ys, t1, j, n) + zf[e];
+    }
+  }
+}
+
+template <int PPT>
+static __device__ inline void load_level(const double* base, int lev, int last, int n, int lt,
+                                         int tpc, bool act, double (&f)[PPT]) {
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int j = lt + e * tpc;
+    f[e] = (act && j < n && lev >= 0 && lev <= last) ? base[(size_t)lev * n + j] : 0.0;
+  }
+}
+
+// LDS layout: [4n stage inputs (L96)] [cpb x (2 + kTmp) n state buffers] [N+2 ints]
+template <class Ops>
+static __device__ inline int* lds_obs_offsets(double* lds, int n, int cpb) {
+  return reinterpret_cast<int*>(lds + (Ops::kStages ? 4 * n : 0) + (size_t)cpb * (2 + Ops::kTmp) * n);
+}
+
 template <class Ops, int PPT>
 __global__ __launch_bounds__(512) void k_sweep_fwd(SweepModel md, const double* __restrict__ P,
-                                                    long long ldp, int m, double* __restrict__ stash,
-                                                    long long ldst, double* __restrict__ Xout,
-                                                    long long ldx, const int* __restrict__ skip,
-                                                    int cpb) {
+                                                   long long ldp, int m, double* __restrict__ stash,
+                                                   long long ldst, double* __restrict__ Xout,
+                                                   long long ldx, const int* __restrict__ skip,
+                                                   int cpb) {
   extern __shared__ double lds[];
   if (skip != nullptr && *skip != 0) return;
   const int n = md.n, N = md.N;
@@ -65,110 +248,67 @@ __global__ __launch_bounds__(512) void k_sweep_fwd(SweepModel md, const double* 
   const int lc = threadIdx.x / tpc, lt = threadIdx.x % tpc;
   const int col = blockIdx.x * cpb + lc;
   const bool act = col < m;
-  double* ys = lds;                                       // 4 n stage inputs (L96)
+  const bool obs = act && stash != nullptr;
+  double* ys = lds;
   double* base = lds + (Ops::kStages ? 4 * n : 0) + (size_t)lc * (2 + Ops::kTmp) * n;
   double* b0 = base;
   double* b1 = base + n;
   double* t1 = base + 2 * n;
   double* t2 = base + 3 * n;
+  int* s_off = lds_obs_offsets<Ops>(lds, n, cpb);
+  for (int t = threadIdx.x; t < N + 2; t += blockDim.x) s_off[t] = md.obs_off[t];
   const double* Pc = P + (size_t)(act ? col : 0) * ldp;
   double* St = stash + (size_t)(act ? col : 0) * ldst;
   double* Xc = Xout + (size_t)(act ? col : 0) * ldx;
 
-  double pc[PPT], pn[PPT];
-#pragma unroll
-  for (int e = 0; e < PPT; ++e) {
-    const int j = lt + e * tpc;
-    pc[e] = (act && j < n) ? Pc[j] : 0.0;
-    pn[e] = (act && j < n && N >= 1) ? Pc[(size_t)n + j] : 0.0;
-  }
+  double fa[PPT], fb[PPT], xn[PPT];
+  load_level<PPT>(Pc, 0, N, n, lt, tpc, act, xn);
 #pragma unroll
   for (int e = 0; e < PPT; ++e) {
     const int j = lt + e * tpc;
     if (j < n) {
-      b0[j] = pc[e];
-      if (act && Xout != nullptr) Xc[j] = pc[e];
+      b0[j] = xn[e];
+      if (act && Xout != nullptr) Xc[j] = xn[e];
     }
   }
+  load_level<PPT>(Pc, 1, N, n, lt, tpc, act, fa);
+  load_level<PPT>(Pc, 2, N, n, lt, tpc, act, fb);
   __syncthreads();
-  if (act && stash != nullptr) obs_gather(md, 0, b0, St, lt, tpc);
+  ObsBuf oa, ob;
+  obs_load_fwd(md, s_off, 0, N, lt, tpc, oa);
+  if (obs) obs_gather(md, oa, b0, St, lt, tpc);
+  obs_load_fwd(md, s_off, 1, N, lt, tpc, oa);
+  obs_load_fwd(md, s_off, 2, N, lt, tpc, ob);
 
-  for (int i = 0; i < N; ++i) {
-    double* cur = (i & 1) ? b1 : b0;
-    double* nxt = (i & 1) ? b0 : b1;
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) pc[e] = pn[e];
-    if (i + 2 <= N) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        pn[e] = (act && j < n) ? Pc[(size_t)(i + 2) * n + j] : 0.0;
-      }
-    }
-    double xn[PPT];
-    if constexpr (!Ops::kStages) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
-          xn[e] = md.ca * cur[jm] + md.cb * cur[j] + md.cc * cur[jp] + pc[e];
-        }
-      }
-    } else {
-      // RK4 tangent-linear step at trajectory point x_i (stage inputs y1..y4).
-      const double dt = md.dt;
-      const double* st = md.stages + (size_t)i * 4 * n;
-      for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) ys[idx] = st[idx];
-      __syncthreads();
-      double dx[PPT], d1[PPT], d2[PPT], d3[PPT];
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          dx[e] = cur[j];
-          d1[e] = l96_jac(ys, cur, j, n);
-          t1[j] = dx[e] + 0.5 * dt * d1[e];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          d2[e] = l96_jac(ys + n, t1, j, n);
-          t2[j] = dx[e] + 0.5 * dt * d2[e];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          d3[e] = l96_jac(ys + 2 * n, t2, j, n);
-          t1[j] = dx[e] + dt * d3[e];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          const double d4v = l96_jac(ys + 3 * n, t1, j, n);
-          xn[e] = dx[e] + (dt / 6.0) * (d1[e] + 2.0 * d2[e] + 2.0 * d3[e] + d4v) + pc[e];
-        }
-      }
-    }
+  // two steps per trip so every prefetch buffer is consumed in place
+  for (int i = 0; i < N; i += 2) {
+    tl_step<Ops, PPT>(md, i, b0, ys, t1, t2, fa, xn, lt, tpc);
+    load_level<PPT>(Pc, i + 3, N, n, lt, tpc, act, fa);
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
       const int j = lt + e * tpc;
       if (j < n) {
-        nxt[j] = xn[e];
+        b1[j] = xn[e];
         if (act && Xout != nullptr) Xc[(size_t)(i + 1) * n + j] = xn[e];
       }
     }
     __syncthreads();
-    if (act && stash != nullptr) obs_gather(md, i + 1, nxt, St, lt, tpc);
+    if (obs) obs_gather(md, oa, b1, St, lt, tpc);
+    obs_load_fwd(md, s_off, i + 3, N, lt, tpc, oa);
+    if (i + 1 >= N) break;
+    tl_step<Ops, PPT>(md, i + 1, b1, ys, t1, t2, fb, xn, lt, tpc);
+    load_level<PPT>(Pc, i + 4, N, n, lt, tpc, act, fb);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) {
+        b0[j] = xn[e];
+        if (act && Xout != nullptr) Xc[(size_t)(i + 2) * n + j] = xn[e];
+      }
+    }
+    __syncthreads();
+    if (obs) obs_gather(md, ob, b0, St, lt, tpc);
+    obs_load_fwd(md, s_off, i + 4, N, lt, tpc, ob);
   }
 }
 
@@ -176,10 +316,10 @@ __global__ __launch_bounds__(512) void k_sweep_fwd(SweepModel md, const double* 
 
 template <class Ops, int PPT>
 __global__ __launch_bounds__(512) void k_sweep_bwd(SweepModel md, const double* __restrict__ stash,
-                                                    long long ldst, const double* __restrict__ Z,
-                                                    long long ldz, int m, double* __restrict__ W,
-                                                    long long ldw, const int* __restrict__ skip,
-                                                    int cpb) {
+                                                   long long ldst, const double* __restrict__ Z,
+                                                   long long ldz, int m, double* __restrict__ W,
+                                                   long long ldw, const int* __restrict__ skip,
+                                                   int cpb) {
   extern __shared__ double lds[];
   if (skip != nullptr && *skip != 0) return;
   const int n = md.n, N = md.N;
@@ -188,118 +328,81 @@ __global__ __launch_bounds__(512) void k_sweep_bwd(SweepModel md, const double* 
   const int col = blockIdx.x * cpb + lc;
   const bool act = col < m;
   const bool dense = (stash == nullptr);
+  const bool obs = act && !dense;
   double* ys = lds;
   double* base = lds + (Ops::kStages ? 4 * n : 0) + (size_t)lc * (2 + Ops::kTmp) * n;
   double* b0 = base;
   double* b1 = base + n;
   double* t1 = base + 2 * n;
   double* t2 = base + 3 * n;
+  int* s_off = lds_obs_offsets<Ops>(lds, n, cpb);
+  for (int t = threadIdx.x; t < N + 2; t += blockDim.x) s_off[t] = md.obs_off[t];
   const double* St = dense ? nullptr : stash + (size_t)(act ? col : 0) * ldst;
   const double* Zc = dense ? Z + (size_t)(act ? col : 0) * ldz : nullptr;
   double* Wc = W + (size_t)(act ? col : 0) * ldw;
 
   // w_N = z_N
-  double zc[PPT], zn[PPT];
+  double za[PPT], zb[PPT], wn[PPT];
+  load_level<PPT>(Zc, N, N, n, lt, tpc, act && dense, wn);
 #pragma unroll
   for (int e = 0; e < PPT; ++e) {
     const int j = lt + e * tpc;
-    zc[e] = (dense && act && j < n) ? Zc[(size_t)N * n + j] : 0.0;
-    zn[e] = (dense && act && j < n && N >= 1) ? Zc[(size_t)(N - 1) * n + j] : 0.0;
-    if (j < n) b0[j] = zc[e];
+    if (j < n) b0[j] = wn[e];
+  }
+  load_level<PPT>(Zc, N - 1, N, n, lt, tpc, act && dense, za);
+  load_level<PPT>(Zc, N - 2, N, n, lt, tpc, act && dense, zb);
+  __syncthreads();
+  ObsBuf oa, ob;
+  if (obs) {
+    obs_load_bwd(md, s_off, N, St, lt, tpc, oa);
+    obs_scatter(md, oa, b0, St, lt, tpc);
+    obs_load_bwd(md, s_off, N - 1, St, lt, tpc, oa);
+    obs_load_bwd(md, s_off, N - 2, St, lt, tpc, ob);
   }
   __syncthreads();
-  if (!dense) {
-    if (act) obs_scatter(md, N, b0, St, lt, tpc);
-    __syncthreads();
-  }
 #pragma unroll
   for (int e = 0; e < PPT; ++e) {
     const int j = lt + e * tpc;
     if (act && j < n) Wc[(size_t)N * n + j] = b0[j];
   }
 
-  int par = 0;
-  for (int i = N - 1; i >= 0; --i, par ^= 1) {
-    double* cur = par ? b1 : b0;
-    double* nxt = par ? b0 : b1;
-#pragma unroll
-    for (int e = 0; e < PPT; ++e) zc[e] = zn[e];
-    if (dense && i >= 1) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        zn[e] = (act && j < n) ? Zc[(size_t)(i - 1) * n + j] : 0.0;
-      }
-    }
-    double wn[PPT];
-    if constexpr (!Ops::kStages) {
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
-          // (M^T w)_j = ca w_{j+1} + cb w_j + cc w_{j-1}
-          wn[e] = md.ca * cur[jp] + md.cb * cur[j] + md.cc * cur[jm] + zc[e];
-        }
-      }
-    } else {
-      // Reverse-mode sweep through the RK4 stages of the step from x_i.
-      const double dt = md.dt;
-      const double* st = md.stages + (size_t)i * 4 * n;
-      for (int idx = threadIdx.x; idx < 4 * n; idx += blockDim.x) ys[idx] = st[idx];
-      __syncthreads();
-      double a[PPT], ax[PPT];
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          a[e] = cur[j];
-          const double u4 = (dt / 6.0) * l96_jacT(ys + 3 * n, cur, j, n);
-          ax[e] = a[e] + u4;
-          t1[j] = (dt / 3.0) * a[e] + dt * u4;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          const double u3 = l96_jacT(ys + 2 * n, t1, j, n);
-          ax[e] += u3;
-          t2[j] = (dt / 3.0) * a[e] + 0.5 * dt * u3;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) {
-          const double u2 = l96_jacT(ys + n, t2, j, n);
-          ax[e] += u2;
-          t1[j] = (dt / 6.0) * a[e] + 0.5 * dt * u2;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int j = lt + e * tpc;
-        if (j < n) wn[e] = ax[e] + l96_jacT(ys, t1, j, n) + zc[e];
-      }
-    }
+  for (int i = N - 1; i >= 0; i -= 2) {
+    adj_step<Ops, PPT>(md, i, b0, ys, t1, t2, za, wn, lt, tpc);
+    load_level<PPT>(Zc, i - 2, N, n, lt, tpc, act && dense, za);
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
       const int j = lt + e * tpc;
-      if (j < n) nxt[j] = wn[e];
+      if (j < n) b1[j] = wn[e];
     }
     __syncthreads();
-    if (!dense) {
-      if (act) obs_scatter(md, i, nxt, St, lt, tpc);
-      __syncthreads();
+    if (obs) {
+      obs_scatter(md, oa, b1, St, lt, tpc);
+      obs_load_bwd(md, s_off, i - 2, St, lt, tpc, oa);
     }
+    __syncthreads();
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
       const int j = lt + e * tpc;
-      if (act && j < n) Wc[(size_t)i * n + j] = nxt[j];
+      if (act && j < n) Wc[(size_t)i * n + j] = b1[j];
+    }
+    if (i - 1 < 0) break;
+    adj_step<Ops, PPT>(md, i - 1, b1, ys, t1, t2, zb, wn, lt, tpc);
+    load_level<PPT>(Zc, i - 3, N, n, lt, tpc, act && dense, zb);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (j < n) b0[j] = wn[e];
+    }
+    __syncthreads();
+    if (obs) {
+      obs_scatter(md, ob, b0, St, lt, tpc);
+      obs_load_bwd(md, s_off, i - 3, St, lt, tpc, ob);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int j = lt + e * tpc;
+      if (act && j < n) Wc[(size_t)(i - 1) * n + j] = b0[j];
     }
   }
 }
@@ -314,7 +417,7 @@ static SweepCfg sweep_cfg(int n, int kind) {
   SweepCfg c;
   if (n <= 64) {
     c.tpc = 64;
-  } else if (n <= (kind == 1 ? 1024 : 4096)) {
+  } else if (n <= (kind == 1 ? 1024 : 2048)) {
     c.tpc = 256;  // Lorenz-96 keeps <= 4 points per thread to stay in registers
   } else {
     c.tpc = 512;  // n <= 8192 (16 points per thread); larger n is rejected at setup
@@ -329,7 +432,8 @@ static SweepCfg sweep_cfg(int n, int kind) {
 
 static size_t sweep_lds_bytes(const SweepModel& md, const SweepCfg& c) {
   const int per = 2 + (md.kind == 1 ? 2 : 0);
-  return sizeof(double) * ((md.kind == 1 ? 4 * (size_t)md.n : 0) + (size_t)c.cpb * per * md.n);
+  return sizeof(double) * ((md.kind == 1 ? 4 * (size_t)md.n : 0) + (size_t)c.cpb * per * md.n) +
+         sizeof(int) * ((size_t)md.N + 2);
 }
 
 #define WC4D_SWEEP_DISPATCH(KERNEL, OPS, ...)                                                   \

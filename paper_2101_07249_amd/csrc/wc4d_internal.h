@@ -36,9 +36,11 @@ inline ColMap plain_cols(long long ld) { return ColMap{ld, 1, 0, 0}; }
 // C(:, t) = alpha * A * B(:, t) [+ E(:, t)] for t < ncol; A column-major M x K (lda),
 // B columns K long via bmap, C / E columns M long via cmap / emap.  float64 MFMA.
 // skip: optional device flag; when *skip != 0 the kernel returns immediately.
+// ws (ws_doubles long, may be null): split-K partials for few-column products.
 hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
                     const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
-                    ColMap emap, const int* skip, hipStream_t s);
+                    ColMap emap, const int* skip, hipStream_t s, double* ws = nullptr,
+                    size_t ws_doubles = 0);
 
 // G(i, j) = sum_k X(k, i) Y(k, j), i < m1, j < m2, k < K; X / Y columns via maps.
 // Deterministic split-K: partial tiles then a fixed-order sum.  G column-major, ldg.
@@ -91,6 +93,15 @@ hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv
 hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double* dcoef,
                        hipStream_t s);
 
+// y = x + U diag(dcoef) U^T x for one vector; ws: lmp_gemv_ws_doubles(nA, k).
+// Single vector: lmp_gemv_t leaves t = dcoef .* (U^T x) in ws, lmp_gemv_n then
+// writes y = x + U t.  ws: lmp_gemv_ws_doubles(nA, k).
+size_t lmp_gemv_ws_doubles(long long nA, int k);
+hipError_t lmp_gemv_t(long long nA, int k, const double* U, long long ldu, const double* dcoef,
+                      const double* x, double* ws, const int* skip, hipStream_t s);
+hipError_t lmp_gemv_n(long long nA, int k, const double* U, long long ldu, const double* x,
+                      double* y, const double* ws, const int* skip, hipStream_t s);
+
 // Vector kernels for PCG and the LMP (n_A long).
 struct PcgState {
   double rr, rr_new, pAp, alpha, beta, bnorm2, r0norm2, ss, xbs;
@@ -125,6 +136,23 @@ hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, 
 
 // ------------------------------------------------------------------- handles
 
+// Kernel classes timed by the in-library profiler (HIP events on the launch stream).
+enum ProfClass {
+  PROF_DSQRT = 0,   // D^{1/2} products inside the operator
+  PROF_SWEEP_FWD,   // tangent-linear sweep + observation gather
+  PROF_SWEEP_BWD,   // adjoint sweep + observation scatter
+  PROF_LMP_T,       // U^T x pass of a single-vector LMP application
+  PROF_LMP_N,       // x + U t pass of a single-vector LMP application
+  PROF_BUILD,       // orthonormalisation, Gram, small dense and Ritz-vector kernels of a build
+  PROF_NCLASS
+};
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+
 struct wc4d_problem_s {
   int n = 0, N = 0, device = 0;
   long long nA = 0;
@@ -151,6 +179,8 @@ struct wc4d_problem_s {
   long long wsStashCols = 0;
   double* wsGram = nullptr;
   size_t wsGramDoubles = 0;
+  double* wsSplit = nullptr;  // split-K partials of the few-column D^{1/2} products
+  size_t wsSplitDoubles = 0;
   // LMP build scratch: two n_A x cap blocks and m x m matrices
   double* bufA = nullptr;
   double* bufB = nullptr;
@@ -165,7 +195,16 @@ struct wc4d_problem_s {
   double* pcgRed = nullptr;
   wc4d::PcgState* pcgState = nullptr;
   wc4d::PcgState* pcgStateHost = nullptr;  // pinned
-  // profiling
+  // per-class kernel timing
+  bool kprof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  double profMs[PROF_NCLASS] = {0};
+  double profBytes[PROF_NCLASS] = {0};
+  double profFlops[PROF_NCLASS] = {0};
+  long long profCalls[PROF_NCLASS] = {0};
+  // profiling of the last apply
   bool prof = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::string err;
@@ -184,4 +223,6 @@ struct wc4d_lmp_s {
   int tcap = 0;
   double* ws = nullptr;     // gram workspace
   size_t wsDoubles = 0;
+  double* wsv = nullptr;    // single-vector workspace
+  size_t wsvDoubles = 0;
 };

@@ -73,6 +73,9 @@ _SIGS = {
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
     "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wc4d_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
+                                      _c_dbl_p, _c_dbl_p]),
     "wc4d_last_apply_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
 }
 
@@ -329,6 +332,21 @@ class Problem:
         if history:
             k = info.iters
             out.update(hist_true=ht[:k], hist_precond=hp[:k], hist_J=hj[:k])
+        return out
+
+    PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other")
+
+    def prof_enable(self, enable: bool = True):
+        self._chk(lib().wc4d_prof_enable(self._h, int(bool(enable))), "prof_enable")
+
+    def prof_read(self) -> dict:
+        out = {}
+        for c, name in enumerate(self.PROF_CLASSES):
+            ms, b, f = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            n = ctypes.c_longlong()
+            self._chk(lib().wc4d_prof_read(self._h, c, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                           ctypes.byref(f)), "prof_read")
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value, "flops": f.value}
         return out
 
     def set_profiling(self, enable: bool = True):
