@@ -173,6 +173,7 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "variant": "plain FP64 Gaussian sketch", "method": args.method,
+                   "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,
                    "criterion": "true residual ||b - A x|| / ||b||"},
         "pcg_iters": iters, "relres_true": max(i["relres_true"] for i in infos), "converged": ok,

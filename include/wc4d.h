@@ -161,7 +161,14 @@ typedef struct {
   int maxit;      /* iteration cap                                                      */
   int criterion;  /* WC4D_RES_TRUE: ||b - A x|| / ||b|| (recursive, float64);
                      WC4D_RES_PRECOND: ||r_j|| / ||r_0|| of Algorithm 1's split residual */
+  int variant;    /* with an LMP: WC4D_PCG_FUSED (default, 0) keeps u = U^T r_j as a
+                     k-vector (u_j = u_{j-1} - alpha_j (t + U^T U diag(theta^{-1/2}-1) t),
+                     t = U^T A p_{j-1}; refreshed from r_j every 50 iterations), so each
+                     iteration streams U twice; WC4D_PCG_PLAIN (1) applies C^T and C
+                     separately (four passes over U).  Both are Algorithm 1 in exact
+                     arithmetic. */
 } wc4d_pcg_opts;
+enum { WC4D_PCG_FUSED = 0, WC4D_PCG_PLAIN = 1 };
 
 typedef struct {
   int iters;             /* iterations taken                                          */

@@ -720,7 +720,7 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
     mode = 1;
   }
   ProfScope ps_tail(p, s, PROF_BUILD, 8.0 * (double)nA * (m + k_r), 2.0 * (double)nA * m * k_r);
-  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, s);
+  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s);
   if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
   if (he == hipSuccess)
     he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, cm, nullptr, cm, nullptr, s);
@@ -731,6 +731,13 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   if (st != 0)
     return cleanup(fail(p, WC4D_ENOTSPD, "Cholesky met a non-positive pivot (rank-deficient sketch?)"));
+  // U^T U for the fused PCG recursion (identity up to rounding for an orthonormal U)
+  if ((rc = dev_alloc(p, &L->GU, (size_t)k_r * k_r))) return cleanup(rc);
+  if ((rc = dev_alloc(p, &L->fu, (size_t)3 * k_r))) return cleanup(rc);
+  if ((rc = ensure_gram(p, gram_ws_doubles(k_r, k_r, nA)))) return cleanup(rc);
+  he = gram_f64(k_r, k_r, nA, L->U, cm, L->U, cm, L->GU, k_r, p->wsGram, nullptr, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   *out = L;
   return WC4D_OK;
 }
@@ -820,6 +827,8 @@ int wc4d_lmp_destroy(wc4d_lmp L) {
   dev_free(&L->T);
   dev_free(&L->ws);
   dev_free(&L->wsv);
+  dev_free(&L->GU);
+  dev_free(&L->fu);
   delete L;
   return WC4D_OK;
 }
@@ -834,6 +843,9 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
       !(opts->tol >= 0.0) || (opts->criterion != WC4D_RES_TRUE && opts->criterion != WC4D_RES_PRECOND))
     return fail(p, WC4D_EINVAL, "invalid PCG arguments");
   if (L != nullptr && L->p != p) return fail(p, WC4D_EINVAL, "LMP built for another problem");
+  if (opts->variant != WC4D_PCG_FUSED && opts->variant != WC4D_PCG_PLAIN)
+    return fail(p, WC4D_EINVAL, "unknown PCG variant");
+  const bool fused = (L != nullptr && opts->variant == WC4D_PCG_FUSED);
   DevGuard g(p->device);
   const long long nA = p->nA;
   int rc;
@@ -869,12 +881,42 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     HIPCHK(p, vec_copy(pv, r, nA, s));
   }
   HIPCHK(p, pcg_kernels_init(st, b, sres, r, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
+  double* u = nullptr;
+  double* d12 = nullptr;
+  double* tvec = nullptr;
+  if (fused) {
+    u = L->fu;
+    d12 = L->fu + L->k;
+    tvec = L->wsv + lmp_gemv_t_offset(nA, L->k);
+    HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, r, L->wsv, nullptr, s, u));
+  }
   const int poll = 8;
   int it = 0;
   bool fin = false;
   while (!fin) {
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
+      if (fused) {
+        const double ub = 8.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
+        if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
+        HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
+        HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
+        {
+          ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * nA, fl);
+          HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, Ap, L->wsv, done, s));
+        }
+        HIPCHK(p, pcg_lmp_coeffs(st, L->k, tvec, L->dcoef, L->GU, u, d12, s));
+        {
+          ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 4.0 * nA, 2.0 * fl);
+          HIPCHK(p, pcg_lmp_dual(st, nA, L->k, L->U, nA, d12, Ap, r, z, p->pcgRed, p->pcgHist, s));
+        }
+        HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
+        // recompute u = U^T r exactly once r.r has dropped by 100x (or after 50 steps):
+        // the recursion's absolute rounding error does not shrink with u
+        HIPCHK(p, pcg_refresh_decide(st, s));
+        HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        continue;
+      }
       if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
       HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
       HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));

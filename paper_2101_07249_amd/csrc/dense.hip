@@ -137,14 +137,8 @@ hipError_t small_gemm(int M, int N, int K, double alpha, const double* A, int ld
 }
 
 // ------------------------------------------------------------ Jacobi EVD
-// Cyclic Jacobi with the round-robin (circle) ordering: each round rotates m'/2
-// disjoint index pairs at once (m' = m rounded up to even; the extra index is a
-// dummy).  A rotation J = [[c, s], [-s, c]] on (p, q) zeroes a_pq of J^T A J
-// (Golub and Van Loan's symmetric Schur step).  All 2x2 blocks of a round are
-// updated independently, upper blocks only, mirrored to keep A exactly symmetric.
-// A pair is skipped when |a_pq| <= tol sqrt(|a_pp a_qq|); a sweep without a
-// rotation ends the iteration.
-constexpr int kJacMaxPairs = 256;  // m <= 512
+// Round-robin (circle) pairing: round r pairs 2 h players into h disjoint pairs,
+// player 0 fixed; over rounds 0 .. 2h - 2 every pair meets once.
 
 static __device__ inline void rr_pair(int r, int k, int mp, int& p, int& q) {
   const int c = mp - 1;
@@ -160,159 +154,203 @@ static __device__ inline void rr_pair(int r, int k, int mp, int& p, int& q) {
   q = a < b ? b : a;
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi(int m, double* __restrict__ A, int lda,
-                                                 double* __restrict__ V, int ldv,
-                                                 double* __restrict__ lam, int max_sweeps,
-                                                 double tol) {
-  __shared__ double sc[kJacMaxPairs], ss[kJacMaxPairs];
-  __shared__ int sp[kJacMaxPairs], sq[kJacMaxPairs];
-  __shared__ int s_rot;
-  __shared__ int rank_of[2 * kJacMaxPairs];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int mp = (m + 1) & ~1;
-  const int np = mp / 2;
-  // symmetrise and set V = I
-  for (long long e = tid; e < (long long)m * m; e += nt) {
+// One-sided (Hestenes) block Jacobi for the SPD m x m matrices of the randomised
+// methods: find orthogonal V with W = K V having orthogonal columns; then
+// K v_i = ||w_i|| v_i.  Columns are split into nblk blocks of bs; in each block
+// round workgroup g takes the block pair (P, Q) of the round-robin schedule, holds
+// those 2 bs columns of W and V in LDS and rotates every pair among them (2 bs - 1
+// local rounds, one pair per wavefront).  A sweep is nblk - 1 block rounds; the
+// iteration stops after a sweep without rotations.  Rotation of columns (a, b)
+// with alpha = |a|^2, beta = |b|^2, gamma = a.b: zeta = (beta - alpha) / (2 gamma),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t,
+// a <- c a - s b, b <- s a + c b, which makes the pair orthogonal.
+constexpr int kOJT = 1024;
+
+struct OjCfg {
+  int bs, nblk;
+};
+
+static OjCfg oj_cfg(int m) {
+  OjCfg c;
+  c.bs = m <= 256 ? 16 : 8;  // 4 bs m doubles of LDS
+  c.nblk = (m + c.bs - 1) / c.bs;
+  if (c.nblk < 2) c.nblk = 2;
+  c.nblk += c.nblk & 1;
+  return c;
+}
+
+__global__ __launch_bounds__(kOJT) void k_oj_init(int m, double* __restrict__ K, int ldk,
+                                                  double* __restrict__ V, int ldv, int* ctrl) {
+  for (long long e = threadIdx.x; e < (long long)m * m; e += kOJT) {
     const int i = (int)(e % m), j = (int)(e / m);
     if (i < j) {
-      const double v = 0.5 * (A[i + (size_t)j * lda] + A[j + (size_t)i * lda]);
-      A[i + (size_t)j * lda] = v;
-      A[j + (size_t)i * lda] = v;
+      const double v = 0.5 * (K[i + (size_t)j * ldk] + K[j + (size_t)i * ldk]);
+      K[i + (size_t)j * ldk] = v;
+      K[j + (size_t)i * ldk] = v;
     }
     V[i + (size_t)j * ldv] = (i == j) ? 1.0 : 0.0;
   }
+  if (threadIdx.x == 0) {
+    ctrl[0] = 0;  // converged
+    ctrl[1] = 0;  // rotations in the current sweep
+  }
+}
+
+__global__ __launch_bounds__(kOJT) void k_oj_round(int m, int bs, int nblk, int r,
+                                                   double* __restrict__ W, int ldw,
+                                                   double* __restrict__ V, int ldv, int* ctrl,
+                                                   double tol) {
+  extern __shared__ double lds[];
+  if (ctrl[0]) return;
+  int P, Q;
+  rr_pair(r, blockIdx.x, nblk, P, Q);
+  const int nloc = 2 * bs;
+  double* Ws = lds;
+  double* Vs = lds + (size_t)nloc * m;
+  auto gcol = [&](int c) { return c < bs ? P * bs + c : Q * bs + (c - bs); };
+  for (long long e = threadIdx.x; e < (long long)nloc * m; e += kOJT) {
+    const int c = (int)(e / m), i = (int)(e % m);
+    const int gc = gcol(c);
+    Ws[e] = gc < m ? W[i + (size_t)gc * ldw] : 0.0;
+    Vs[e] = gc < m ? V[i + (size_t)gc * ldv] : 0.0;
+  }
   __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) s_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < mp - 1; ++r) {
-      // rotation parameters of this round's pairs
-      for (int k = tid; k < np; k += nt) {
-        int p, q;
-        rr_pair(r, k, mp, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < m) {
-          const double app = A[p + (size_t)p * lda], aqq = A[q + (size_t)q * lda];
-          const double apq = A[p + (size_t)q * lda];
-          if (fabs(apq) > tol * sqrt(fabs(app * aqq)) && apq != 0.0) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            atomicAdd(&s_rot, 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int rot = 0;
+  for (int lr = 0; lr < nloc - 1; ++lr) {
+    if (wave < bs) {
+      int a, b;
+      rr_pair(lr, wave, nloc, a, b);
+      if (gcol(a) < m && gcol(b) < m) {
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          const double wa = Ws[(size_t)a * m + i], wb = Ws[(size_t)b * m + i];
+          al += wa * wa;
+          be += wb * wb;
+          ga += wa * wb;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
+        }
+        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          for (int i = lane; i < m; i += 64) {
+            const double wa = Ws[(size_t)a * m + i], wb = Ws[(size_t)b * m + i];
+            Ws[(size_t)a * m + i] = c * wa - sn * wb;
+            Ws[(size_t)b * m + i] = sn * wa + c * wb;
+            const double va = Vs[(size_t)a * m + i], vb = Vs[(size_t)b * m + i];
+            Vs[(size_t)a * m + i] = c * va - sn * vb;
+            Vs[(size_t)b * m + i] = sn * va + c * vb;
           }
-        }
-        sc[k] = c;
-        ss[k] = s;
-        sp[k] = p;
-        sq[k] = q;
-      }
-      __syncthreads();
-      // 2x2 blocks (P, Q) with P <= Q: B = J_P^T A_PQ J_Q
-      const int nblk = np * (np + 1) / 2;
-      for (int e = tid; e < nblk; e += nt) {
-        // decode e -> (P, Q), P <= Q, row-major over the upper triangle
-        int P = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while ((P + 1) * (P + 2) / 2 <= e) ++P;
-        while (P * (P + 1) / 2 > e) --P;
-        const int Qi = e - P * (P + 1) / 2;  // 0..P
-        const int a = Qi, b = P;              // pair a <= pair b
-        const double ca = sc[a], sa = ss[a], cb = sc[b], sb = ss[b];
-        if (sa == 0.0 && sb == 0.0) continue;
-        const int p = sp[a], q = sq[a], u = sp[b], v = sq[b];
-        if (a == b) {
-          if (q >= m) continue;
-          const double app = A[p + (size_t)p * lda], aqq = A[q + (size_t)q * lda];
-          const double apq = A[p + (size_t)q * lda];
-          const double t = sa / ca;
-          A[p + (size_t)p * lda] = app - t * apq;
-          A[q + (size_t)q * lda] = aqq + t * apq;
-          A[p + (size_t)q * lda] = 0.0;
-          A[q + (size_t)p * lda] = 0.0;
-          continue;
-        }
-        // rows {p, q} (pair a), columns {u, v} (pair b); dummy index >= m is absent
-        const bool hq = q < m, hv = v < m;
-        const double x_pu = A[p + (size_t)u * lda];
-        const double x_pv = hv ? A[p + (size_t)v * lda] : 0.0;
-        const double x_qu = hq ? A[q + (size_t)u * lda] : 0.0;
-        const double x_qv = (hq && hv) ? A[q + (size_t)v * lda] : 0.0;
-        // rows: J_a^T
-        const double r_pu = ca * x_pu - sa * x_qu, r_qu = sa * x_pu + ca * x_qu;
-        const double r_pv = ca * x_pv - sa * x_qv, r_qv = sa * x_pv + ca * x_qv;
-        // columns: J_b
-        const double y_pu = cb * r_pu - sb * r_pv, y_pv = sb * r_pu + cb * r_pv;
-        const double y_qu = cb * r_qu - sb * r_qv, y_qv = sb * r_qu + cb * r_qv;
-        A[p + (size_t)u * lda] = y_pu;
-        A[u + (size_t)p * lda] = y_pu;
-        if (hv) {
-          A[p + (size_t)v * lda] = y_pv;
-          A[v + (size_t)p * lda] = y_pv;
-        }
-        if (hq) {
-          A[q + (size_t)u * lda] = y_qu;
-          A[u + (size_t)q * lda] = y_qu;
-        }
-        if (hq && hv) {
-          A[q + (size_t)v * lda] = y_qv;
-          A[v + (size_t)q * lda] = y_qv;
+          ++rot;
         }
       }
-      // V <- V J: columns p, q of every rotated pair
-      for (long long e = tid; e < (long long)m * np; e += nt) {
-        const int i = (int)(e % m), k = (int)(e / m);
-        const double s = ss[k];
-        if (s == 0.0) continue;
-        const double c = sc[k];
-        const int p = sp[k], q = sq[k];
-        const double vp = V[i + (size_t)p * ldv], vq = V[i + (size_t)q * ldv];
-        V[i + (size_t)p * ldv] = c * vp - s * vq;
-        V[i + (size_t)q * ldv] = s * vp + c * vq;
-      }
-      __syncthreads();
     }
-    if (s_rot == 0) break;
     __syncthreads();
   }
-  // sort decreasing (stable by index) and normalise signs
+  for (long long e = threadIdx.x; e < (long long)nloc * m; e += kOJT) {
+    const int c = (int)(e / m), i = (int)(e % m);
+    const int gc = gcol(c);
+    if (gc < m) {
+      W[i + (size_t)gc * ldw] = Ws[e];
+      V[i + (size_t)gc * ldv] = Vs[e];
+    }
+  }
+  if (lane == 0 && rot > 0) atomicAdd(&ctrl[1], rot);
+}
+
+__global__ void k_oj_sweep_end(int* ctrl) {
+  if (threadIdx.x != 0 || ctrl[0]) return;
+  if (ctrl[1] == 0) ctrl[0] = 1;
+  ctrl[1] = 0;
+}
+
+// eigenvalues = column norms of W, sorted decreasing (stable), vectors = columns of V
+// with the largest-magnitude entry made positive; W is reused as scratch.
+__global__ __launch_bounds__(kOJT) void k_oj_finish(int m, double* __restrict__ W, int ldw,
+                                                    double* __restrict__ V, int ldv,
+                                                    double* __restrict__ lam) {
+  __shared__ double nrm[512];
+  __shared__ int rank_of[512];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wave; c < m; c += kOJT / 64) {
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) s += W[i + (size_t)c * ldw] * W[i + (size_t)c * ldw];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) nrm[c] = sqrt(s);
+  }
   __syncthreads();
-  for (int i = tid; i < m; i += nt) {
-    const double li = A[i + (size_t)i * lda];
+  for (int i = threadIdx.x; i < m; i += kOJT) {
+    const double li = nrm[i];
     int rk = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = A[j + (size_t)j * lda];
+      const double lj = nrm[j];
       if (lj > li || (lj == li && j < i)) ++rk;
     }
     rank_of[i] = rk;
     lam[rk] = li;
   }
   __syncthreads();
-  // write sorted vectors into A's storage (A is no longer needed), then copy to V
-  for (int i = tid; i < m; i += nt) {
-    // sign: largest-magnitude entry positive
-    double best = 0.0;
-    int bi = 0;
-    for (int r2 = 0; r2 < m; ++r2) {
-      const double v = fabs(V[r2 + (size_t)i * ldv]);
-      if (v > best) {
-        best = v;
-        bi = r2;
+  for (int c = wave; c < m; c += kOJT / 64) {
+    double best = -1.0, sv = 1.0;
+    for (int i = lane; i < m; i += 64) {
+      const double v = V[i + (size_t)c * ldv];
+      if (fabs(v) > best) {
+        best = fabs(v);
+        sv = v;
       }
     }
-    const double sg = V[bi + (size_t)i * ldv] < 0.0 ? -1.0 : 1.0;
-    const int dst = rank_of[i];
-    for (int r2 = 0; r2 < m; ++r2) A[r2 + (size_t)dst * lda] = sg * V[r2 + (size_t)i * ldv];
+    // lowest index wins ties, so the choice is deterministic
+    int bidx = lane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const double os = __shfl_xor(sv, o, 64);
+      const int oi = __shfl_xor(bidx, o, 64);
+      if (ob > best || (ob == best && oi < bidx)) {
+        best = ob;
+        sv = os;
+        bidx = oi;
+      }
+    }
+    const double sg = sv < 0.0 ? -1.0 : 1.0;
+    const int dst = rank_of[c];
+    for (int i = lane; i < m; i += 64) W[i + (size_t)dst * ldw] = sg * V[i + (size_t)c * ldv];
   }
   __syncthreads();
-  for (long long e = tid; e < (long long)m * m; e += nt) {
+  for (long long e = threadIdx.x; e < (long long)m * m; e += kOJT) {
     const int i = (int)(e % m), j = (int)(e / m);
-    V[i + (size_t)j * ldv] = A[i + (size_t)j * lda];
+    V[i + (size_t)j * ldv] = W[i + (size_t)j * ldw];
   }
 }
 
-hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, hipStream_t s) {
-  if (m > 2 * kJacMaxPairs) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(1024), 0, s, m, K, ldk, V, ldv, lam, 60, 1e-15);
+hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
+                      hipStream_t s) {
+  if (m > 512 || m < 1) return hipErrorInvalidValue;
+  const OjCfg c = oj_cfg(m);
+  const size_t lds = sizeof(double) * 4 * (size_t)c.bs * m;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_oj_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * 4 * 16 * 256));
+    attr_set = true;
+  }
+  const double tol = sqrt((double)m) * 2.220446049250313e-16;
+  hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl);
+  const int max_sweeps = 20;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int r = 0; r < c.nblk - 1; ++r)
+      hipLaunchKernelGGL(k_oj_round, dim3(c.nblk / 2), dim3(kOJT), lds, s, m, c.bs, c.nblk, r, K,
+                         ldk, V, ldv, ctrl, tol);
+    hipLaunchKernelGGL(k_oj_sweep_end, dim3(1), dim3(64), 0, s, ctrl);
+  }
+  hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, lam);
   return hipGetLastError();
 }
 

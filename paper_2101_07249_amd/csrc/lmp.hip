@@ -32,6 +32,7 @@ static inline int lmp_t_splits(long long nA, int k) {
 }
 
 size_t lmp_gemv_ws_doubles(long long nA, int k) { return (size_t)lmp_t_splits(nA, k) * k + k; }
+size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)lmp_t_splits(nA, k) * k; }
 
 // Partial sums of columns [c0, c0 + kTG) over rows [rb, re): each thread runs down
 // its rows with kTG accumulators; one block reduction at the end.
@@ -102,7 +103,7 @@ __global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__
   for (int b = lane; b < splits; b += 64) s += part[(size_t)b * k + c];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) t[c] = dcoef[c] * s;
+  if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
 }
 
 __global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const double* __restrict__ U,
@@ -144,11 +145,11 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const d
 }
 
 hipError_t lmp_gemv_t(long long nA, int k, const double* U, long long ldu, const double* dcoef,
-                      const double* x, double* ws, const int* skip, hipStream_t s) {
+                      const double* x, double* ws, const int* skip, hipStream_t s, double* tout) {
   const int sp = lmp_t_splits(nA, k);
   long long rows_per = (nA + sp - 1) / sp;
   double* part = ws;
-  double* t = ws + (size_t)sp * k;
+  double* t = (tout != nullptr) ? tout : ws + (size_t)sp * k;
   dim3 grid((k + kTG - 1) / kTG, sp);
   hipLaunchKernelGGL(k_lmp_gemv_t_partial, grid, dim3(kLT), 0, s, nA, k, rows_per, U, ldu, x, part,
                      skip);

@@ -407,6 +407,239 @@ __global__ __launch_bounds__(512) void k_sweep_bwd(SweepModel md, const double* 
   }
 }
 
+// ------------------------------------------- time-blocked advection-diffusion
+// For one or a few columns the window's N sequential steps over the whole domain
+// are latency-bound.  The stencil has radius 1, so a workgroup can own W points
+// [j0, j0 + W) and run all N steps on the extended range [j0 - N, j0 + W + N)
+// (periodic indices, n >= E = W + 2N so no point appears twice): after s steps
+// only the outer s points on each side are wrong, so the owned points are exact
+// at every level.  Workgroups never communicate.  512 threads, PE points each.
+constexpr int kTBT = 512;
+constexpr int kMaxTbLevels = 1026;  // N + 2 <= kMaxTbLevels
+
+struct TbCfg {
+  int pe, W;  // points per thread, owned width; pe = 0: not applicable
+};
+
+static TbCfg tb_cfg(int n, int N) {
+  for (int pe = 1; pe <= 4; pe *= 2) {
+    const int E = kTBT * pe;
+    const int W = E - 2 * N;
+    if (2 * W >= E && n >= E) return TbCfg{pe, W};
+  }
+  return TbCfg{0, 0};
+}
+
+// local index of global point j in the extended range starting at g0 (or -1)
+static __device__ inline int tb_local(int j, int g0, int n, int Ec) {
+  int l = j - g0;
+  l %= n;
+  if (l < 0) l += n;
+  return l < Ec ? l : -1;
+}
+
+template <int PE>
+static __device__ inline void tb_load(const double* base, int lev, int last, int n, int g0, int Ec,
+                                      double (&f)[PE]) {
+#pragma unroll
+  for (int e = 0; e < PE; ++e) {
+    const int l = threadIdx.x + e * kTBT;
+    int j = (g0 + l) % n;
+    if (j < 0) j += n;
+    f[e] = (base != nullptr && l < Ec && lev >= 0 && lev <= last) ? base[(size_t)lev * n + j] : 0.0;
+  }
+}
+
+// Observation list of one level for the time-blocked kernels (kTOB entries per
+// thread prefetched; q_i <= kTOB * 512 covers every level of the shipped workloads).
+constexpr int kTOB = 2;
+constexpr int kTD = 8;  // prefetch depth in steps
+
+struct TbObs {
+  int kb, ke;
+  int idx[kTOB];
+  double val[kTOB];
+};
+
+static __device__ inline void tb_obs_fwd(const SweepModel& md, const int* s_off, int t, int N, TbObs& o) {
+  o.kb = (t >= 0 && t <= N) ? s_off[t] : 0;
+  o.ke = (t >= 0 && t <= N) ? s_off[t + 1] : 0;
+#pragma unroll
+  for (int e = 0; e < kTOB; ++e) {
+    const int k = o.kb + (int)threadIdx.x + e * kTBT;
+    const bool v = k < o.ke;
+    o.idx[e] = v ? md.obs_idx[k] : 0;
+    o.val[e] = v ? md.obs_rinv[k] : 0.0;
+  }
+}
+
+static __device__ inline void tb_obs_bwd(const SweepModel& md, const int* s_off, int t, int N,
+                                         const double* st, TbObs& o) {
+  o.kb = (t >= 0 && t <= N) ? s_off[t] : 0;
+  o.ke = (t >= 0 && t <= N) ? s_off[t + 1] : 0;
+#pragma unroll
+  for (int e = 0; e < kTOB; ++e) {
+    const int k = o.kb + (int)threadIdx.x + e * kTBT;
+    const bool v = k < o.ke;
+    o.idx[e] = v ? md.obs_idx[k] : 0;
+    o.val[e] = v ? st[k] : 0.0;
+  }
+}
+
+// Forcing and observation lists are prefetched kTD steps ahead in a register ring;
+// the time loop is unrolled by kTD so every ring slot is consumed in place.
+template <int PE>
+__global__ __launch_bounds__(kTBT) void k_sweep_fwd_tb(SweepModel md, int W, const double* __restrict__ P,
+                                                       long long ldp, double* __restrict__ stash,
+                                                       long long ldst, double* __restrict__ Xout,
+                                                       long long ldx, const int* __restrict__ skip) {
+  constexpr int E = kTBT * PE;
+  __shared__ double b0[E + 2], b1[E + 2];
+  __shared__ int s_off[kMaxTbLevels];
+  if (skip != nullptr && *skip != 0) return;
+  const int n = md.n, N = md.N;
+  const int col = blockIdx.y;
+  const int j0 = blockIdx.x * W;
+  const int Wc = min(W, n - j0);
+  const int Ec = Wc + 2 * N;
+  const int g0 = j0 - N;  // global index of local point 0
+  for (int t = threadIdx.x; t < N + 2; t += kTBT) s_off[t] = md.obs_off[t];
+  const double* Pc = P + (size_t)col * ldp;
+  double* St = stash != nullptr ? stash + (size_t)col * ldst : nullptr;
+  double* Xc = Xout != nullptr ? Xout + (size_t)col * ldx : nullptr;
+  double f[kTD][PE], xn[PE];
+  tb_load<PE>(Pc, 0, N, n, g0, Ec, xn);
+#pragma unroll
+  for (int e = 0; e < PE; ++e) b0[threadIdx.x + e * kTBT] = xn[e];
+#pragma unroll
+  for (int u = 0; u < kTD; ++u) tb_load<PE>(Pc, u + 1, N, n, g0, Ec, f[u]);
+  __syncthreads();
+  TbObs ob[kTD];
+  // observations and outputs of level i from buffer x
+  auto emit = [&](int i, const double* x, const TbObs& o) {
+    if (Xc != nullptr) {
+      for (int l = N + threadIdx.x; l < N + Wc; l += kTBT) Xc[(size_t)i * n + (g0 + l)] = x[l];
+    }
+    if (St != nullptr) {
+#pragma unroll
+      for (int e = 0; e < kTOB; ++e) {
+        const int k = o.kb + (int)threadIdx.x + e * kTBT;
+        const int j = o.idx[e];
+        if (k < o.ke && j >= j0 && j < j0 + Wc) St[k] = o.val[e] * x[j - g0];
+      }
+      for (int k = o.kb + threadIdx.x + kTOB * kTBT; k < o.ke; k += kTBT) {
+        const int j = md.obs_idx[k];
+        if (j >= j0 && j < j0 + Wc) St[k] = md.obs_rinv[k] * x[j - g0];
+      }
+    }
+  };
+  {
+    TbObs o0;
+    tb_obs_fwd(md, s_off, 0, N, o0);
+    emit(0, b0, o0);
+  }
+#pragma unroll
+  for (int u = 0; u < kTD; ++u) tb_obs_fwd(md, s_off, u + 1, N, ob[u]);
+  for (int i = 0; i < N; i += kTD) {
+#pragma unroll
+    for (int u = 0; u < kTD; ++u) {
+      if (i + u < N) {
+        const double* cur = (u & 1) ? b1 : b0;
+        double* nxt = (u & 1) ? b0 : b1;
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+          const int l = threadIdx.x + e * kTBT;
+          const int lm = l > 0 ? l - 1 : l, lp = l + 1 < E ? l + 1 : l;
+          nxt[l] = md.ca * cur[lm] + md.cb * cur[l] + md.cc * cur[lp] + f[u][e];
+        }
+        tb_load<PE>(Pc, i + u + 1 + kTD, N, n, g0, Ec, f[u]);
+        __syncthreads();
+        emit(i + u + 1, nxt, ob[u]);
+        tb_obs_fwd(md, s_off, i + u + 1 + kTD, N, ob[u]);
+      }
+    }
+  }
+}
+
+template <int PE>
+__global__ __launch_bounds__(kTBT) void k_sweep_bwd_tb(SweepModel md, int W, const double* __restrict__ stash,
+                                                       long long ldst, const double* __restrict__ Z,
+                                                       long long ldz, double* __restrict__ Wout,
+                                                       long long ldw, const int* __restrict__ skip) {
+  constexpr int E = kTBT * PE;
+  __shared__ double b0[E + 2], b1[E + 2];
+  __shared__ int s_off[kMaxTbLevels];
+  if (skip != nullptr && *skip != 0) return;
+  const int n = md.n, N = md.N;
+  const int col = blockIdx.y;
+  const int j0 = blockIdx.x * W;
+  const int Wc = min(W, n - j0);
+  const int Ec = Wc + 2 * N;
+  const int g0 = j0 - N;
+  for (int t = threadIdx.x; t < N + 2; t += kTBT) s_off[t] = md.obs_off[t];
+  const double* St = stash != nullptr ? stash + (size_t)col * ldst : nullptr;
+  const double* Zc = (stash == nullptr) ? Z + (size_t)col * ldz : nullptr;
+  double* Wc_ = Wout + (size_t)col * ldw;
+  double z[kTD][PE], wn[PE];
+  tb_load<PE>(Zc, N, N, n, g0, Ec, wn);
+#pragma unroll
+  for (int e = 0; e < PE; ++e) b0[threadIdx.x + e * kTBT] = wn[e];
+#pragma unroll
+  for (int u = 0; u < kTD; ++u) tb_load<PE>(Zc, N - 1 - u, N, n, g0, Ec, z[u]);
+  __syncthreads();
+  // H_i^T stash_i added into the extended range, then the owned points written out
+  auto finish = [&](int i, double* w, const TbObs& o) {
+    if (St != nullptr) {
+#pragma unroll
+      for (int e = 0; e < kTOB; ++e) {
+        const int k = o.kb + (int)threadIdx.x + e * kTBT;
+        if (k < o.ke) {
+          const int l = tb_local(o.idx[e], g0, n, Ec);
+          if (l >= 0) w[l] += o.val[e];
+        }
+      }
+      for (int k = o.kb + threadIdx.x + kTOB * kTBT; k < o.ke; k += kTBT) {
+        const int l = tb_local(md.obs_idx[k], g0, n, Ec);
+        if (l >= 0) w[l] += St[k];
+      }
+      __syncthreads();
+    }
+    for (int l = N + threadIdx.x; l < N + Wc; l += kTBT) Wc_[(size_t)i * n + (g0 + l)] = w[l];
+  };
+  TbObs ob[kTD];
+  {
+    TbObs oN;
+    if (St != nullptr) tb_obs_bwd(md, s_off, N, N, St, oN);
+    else oN.kb = oN.ke = 0;
+    finish(N, b0, oN);
+  }
+#pragma unroll
+  for (int u = 0; u < kTD; ++u) {
+    if (St != nullptr) tb_obs_bwd(md, s_off, N - 1 - u, N, St, ob[u]);
+    else ob[u].kb = ob[u].ke = 0;
+  }
+  for (int i0 = N - 1; i0 >= 0; i0 -= kTD) {
+#pragma unroll
+    for (int u = 0; u < kTD; ++u) {
+      const int i = i0 - u;
+      if (i >= 0) {
+        const double* cur = (u & 1) ? b1 : b0;
+        double* nxt = (u & 1) ? b0 : b1;
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+          const int l = threadIdx.x + e * kTBT;
+          const int lm = l > 0 ? l - 1 : l, lp = l + 1 < E ? l + 1 : l;
+          nxt[l] = md.ca * cur[lp] + md.cb * cur[l] + md.cc * cur[lm] + z[u][e];
+        }
+        tb_load<PE>(Zc, i - kTD, N, n, g0, Ec, z[u]);
+        __syncthreads();
+        finish(i, nxt, ob[u]);
+        if (St != nullptr) tb_obs_bwd(md, s_off, i - kTD, N, St, ob[u]);
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- launch
 
 struct SweepCfg {
@@ -449,6 +682,17 @@ static size_t sweep_lds_bytes(const SweepModel& md, const SweepCfg& c) {
 hipError_t sweep_fwd(const SweepModel& md, const double* P, long long ldp, int m, double* stash,
                      long long ldst, double* Xout, long long ldx, const int* skip, hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  const TbCfg tc = tb_cfg(md.n, md.N);
+  if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
+    dim3 grid((md.n + tc.W - 1) / tc.W, m);
+    if (tc.pe == 1)
+      hipLaunchKernelGGL(k_sweep_fwd_tb<1>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
+    else if (tc.pe == 2)
+      hipLaunchKernelGGL(k_sweep_fwd_tb<2>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
+    else
+      hipLaunchKernelGGL(k_sweep_fwd_tb<4>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
+    return hipGetLastError();
+  }
   const SweepCfg c = sweep_cfg(md.n, md.kind);
   const size_t lds = sweep_lds_bytes(md, c);
   dim3 grid((m + c.cpb - 1) / c.cpb), block(c.tpc * c.cpb);
@@ -464,6 +708,17 @@ hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, 
                      long long ldz, int m, double* W, long long ldw, const int* skip,
                      hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  const TbCfg tc = tb_cfg(md.n, md.N);
+  if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
+    dim3 grid((md.n + tc.W - 1) / tc.W, m);
+    if (tc.pe == 1)
+      hipLaunchKernelGGL(k_sweep_bwd_tb<1>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
+    else if (tc.pe == 2)
+      hipLaunchKernelGGL(k_sweep_bwd_tb<2>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
+    else
+      hipLaunchKernelGGL(k_sweep_bwd_tb<4>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
+    return hipGetLastError();
+  }
   const SweepCfg c = sweep_cfg(md.n, md.kind);
   const size_t lds = sweep_lds_bytes(md, c);
   dim3 grid((m + c.cpb - 1) / c.cpb), block(c.tpc * c.cpb);

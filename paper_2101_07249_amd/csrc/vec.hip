@@ -76,6 +76,9 @@ __global__ __launch_bounds__(kRT) void k_pcg_init_final(PcgState* st, const doub
     st->xbs = 0.0;
     // nothing to do for b = 0 (x = 0 solves it); r_0 = 0 means x_0 already solves it
     st->done = (bb == 0.0 || rr == 0.0) ? 1 : 0;
+    st->rr_ref = rr;
+    st->last_refresh = 0;
+    st->no_refresh = 1;
   }
 }
 
@@ -341,6 +344,125 @@ hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, 
                       int cols, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy2d, dim3(256, cols), dim3(256), 0, s, Y, ldy, X, ldx, rows, cols);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ fused LMP inside PCG
+// With u = U^T r kept as a k-vector, one PCG iteration needs U^T (A p) (one pass
+// over U) and one pass producing both w = C A p and z = C r_new:
+//   t = U^T Ap,  d1 = dcoef .* t,  w = Ap + U d1,  r_new = r - alpha w,
+//   u_new = U^T r_new = u - alpha (t + (U^T U) d1),  d2 = dcoef .* u_new,
+//   z = r_new + U d2.
+// k_pcg_lmp_coeffs forms d1, d2 and u_new (one workgroup).
+__global__ __launch_bounds__(256) void k_pcg_lmp_coeffs(const PcgState* __restrict__ st, int k,
+                                                        const double* __restrict__ t,
+                                                        const double* __restrict__ dcoef,
+                                                        const double* __restrict__ GU,
+                                                        double* __restrict__ u,
+                                                        double* __restrict__ d12) {
+  extern __shared__ double sd1[];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) sd1[c] = dcoef[c] * t[c];
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double g = 0.0;
+    for (int j = 0; j < k; ++j) g += GU[c + (size_t)j * k] * sd1[j];
+    const double un = u[c] - alpha * (t[c] + g);
+    u[c] = un;
+    d12[c] = sd1[c];
+    d12[k + c] = dcoef[c] * un;
+  }
+}
+
+hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
+                          const double* GU, double* u, double* d12, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_lmp_coeffs, dim3(1), dim3(256), sizeof(double) * k, s, st, k, t, dcoef,
+                     GU, u, d12);
+  return hipGetLastError();
+}
+
+// Dual pass: r <- r - alpha (Ap + U d1), z = r + U d2, partials of r.r into red[2 kRB ..).
+constexpr int kDE = 2;  // rows per thread
+constexpr int kDC = 8;  // columns per group
+__global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict__ st, long long nA,
+                                                      int k, const double* __restrict__ U, long long ldu,
+                                                      const double* __restrict__ d12,
+                                                      const double* __restrict__ Ap,
+                                                      double* __restrict__ r, double* __restrict__ z,
+                                                      double* __restrict__ red) {
+  extern __shared__ double sd[];
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  for (int c = threadIdx.x; c < 2 * k; c += kRT) sd[c] = d12[c];
+  __syncthreads();
+  double vsum = 0.0;
+  const long long chunk = (long long)kRT * kDE;
+  for (long long r0 = (long long)blockIdx.x * chunk; r0 < nA; r0 += (long long)kRB * chunk) {
+    long long rr[kDE];
+    bool ok[kDE];
+    double aw[kDE], az[kDE];
+#pragma unroll
+    for (int e = 0; e < kDE; ++e) {
+      rr[e] = r0 + threadIdx.x + (long long)e * kRT;
+      ok[e] = rr[e] < nA;
+      aw[e] = 0.0;
+      az[e] = 0.0;
+    }
+    for (int c0 = 0; c0 < k; c0 += kDC) {
+      double uv[kDC][kDE];
+#pragma unroll
+      for (int c = 0; c < kDC; ++c)
+#pragma unroll
+        for (int e = 0; e < kDE; ++e)
+          uv[c][e] = (c0 + c < k && ok[e]) ? U[(size_t)(c0 + c) * ldu + rr[e]] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kDC; ++c) {
+        const double t1 = (c0 + c < k) ? sd[c0 + c] : 0.0;
+        const double t2 = (c0 + c < k) ? sd[k + c0 + c] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kDE; ++e) {
+          aw[e] += uv[c][e] * t1;
+          az[e] += uv[c][e] * t2;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kDE; ++e) {
+      if (ok[e]) {
+        const double rn = r[rr[e]] - alpha * (Ap[rr[e]] + aw[e]);
+        r[rr[e]] = rn;
+        z[rr[e]] = rn + az[e];
+        vsum += rn * rn;
+      }
+    }
+  }
+  const double tot = block_sum(vsum, sh);
+  if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = tot;
+}
+
+__global__ void k_refresh_decide(PcgState* st) {
+  if (threadIdx.x != 0) return;
+  const bool go = !st->done && (st->rr < 1e-2 * st->rr_ref || st->iter - st->last_refresh >= 50);
+  st->no_refresh = go ? 0 : 1;
+  if (go) {
+    st->rr_ref = st->rr;
+    st->last_refresh = st->iter;
+  }
+}
+
+hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_decide, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
+                        const double* d12, const double* Ap, double* r, double* z, double* red,
+                        double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_lmp_dual, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st, nA, k, U,
+                     ldu, d12, Ap, r, z, red);
+  hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }
 

@@ -84,21 +84,26 @@ hipError_t tri_inv_upper(int m, const double* R, int ldr, double* Rinv, int ldi,
 // C = alpha op(A) op(B), op = transpose when t* != 0; M x N result, inner K.
 hipError_t small_gemm(int M, int N, int K, double alpha, const double* A, int lda, int tA,
                       const double* B, int ldb, int tB, double* C, int ldc, hipStream_t s);
-// Symmetric EVD of the symmetric part of K (m x m) by parallel cyclic Jacobi.
-// Outputs eigenvalues lam (decreasing) and eigenvectors V (m x m, ldv), each
-// vector's largest-magnitude entry positive.  K is overwritten.
-hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, hipStream_t s);
+// EVD of the symmetric positive definite part of K (m x m, m <= 512) by one-sided
+// block Jacobi.  Outputs eigenvalues lam (decreasing) and eigenvectors V (m x m,
+// ldv), each vector's largest-magnitude entry positive.  K is overwritten; ctrl:
+// 2 device ints of scratch.
+hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
+                      hipStream_t s);
 // theta[i] = f(lam[i]) for i < k: f = identity (mode 0) or sqrt (mode 1);
 // dcoef[i] = theta[i]^{-1/2} - 1 (the LMP's diagonal).
 hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double* dcoef,
                        hipStream_t s);
 
 // y = x + U diag(dcoef) U^T x for one vector; ws: lmp_gemv_ws_doubles(nA, k).
-// Single vector: lmp_gemv_t leaves t = dcoef .* (U^T x) in ws, lmp_gemv_n then
-// writes y = x + U t.  ws: lmp_gemv_ws_doubles(nA, k).
+// Single vector: lmp_gemv_t leaves t = dcoef .* (U^T x) (or U^T x when dcoef is
+// null) at ws + lmp_gemv_t_offset(nA, k), lmp_gemv_n then writes y = x + U t.
+// ws: lmp_gemv_ws_doubles(nA, k).
 size_t lmp_gemv_ws_doubles(long long nA, int k);
+size_t lmp_gemv_t_offset(long long nA, int k);
 hipError_t lmp_gemv_t(long long nA, int k, const double* U, long long ldu, const double* dcoef,
-                      const double* x, double* ws, const int* skip, hipStream_t s);
+                      const double* x, double* ws, const int* skip, hipStream_t s,
+                      double* tout = nullptr);
 hipError_t lmp_gemv_n(long long nA, int k, const double* U, long long ldu, const double* x,
                       double* y, const double* ws, const int* skip, hipStream_t s);
 
@@ -107,6 +112,9 @@ struct PcgState {
   double rr, rr_new, pAp, alpha, beta, bnorm2, r0norm2, ss, xbs;
   double tol;
   int iter, done, status, criterion, maxit, pad;
+  double rr_ref;      // r.r at the last exact refresh of u = U^T r (fused variant)
+  int last_refresh;   // iteration of that refresh
+  int no_refresh;     // 1: skip this iteration's refresh
 };
 hipError_t pcg_kernels_init(PcgState* st, const double* b, const double* s0, const double* r0,
                             long long nA, double tol, int maxit, int criterion, double* red,
@@ -121,6 +129,16 @@ hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, 
                         double* hist, hipStream_t s);
 hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s);
 hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
+// Fused LMP inside PCG (see vec.hip): coefficients d1 = dcoef.*t, u <- u - alpha (t + GU d1),
+// d2 = dcoef.*u into d12 (2k); then the dual pass updating r, writing z, and beta.
+hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
+                          const double* GU, double* u, double* d12, hipStream_t s);
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
+                        const double* d12, const double* Ap, double* r, double* z, double* red,
+                        double* hist, hipStream_t s);
+// Decide whether u = U^T r is recomputed this iteration (st->no_refresh = 0 when
+// r.r fell below 1e-2 of its value at the last refresh, or 50 iterations passed).
+hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s);
 hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef, const int* skip,
                           hipStream_t s);
 hipError_t stash_from_innov(const double* d, const double* rinv, double* stash, int q,
@@ -225,4 +243,6 @@ struct wc4d_lmp_s {
   size_t wsDoubles = 0;
   double* wsv = nullptr;    // single-vector workspace
   size_t wsvDoubles = 0;
+  double* GU = nullptr;     // k x k: U^T U (fused PCG)
+  double* fu = nullptr;     // 3 k: u = U^T r, d1, d2 (fused PCG)
 };

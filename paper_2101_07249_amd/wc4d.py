@@ -25,6 +25,7 @@ CORR_SOAR, CORR_GAUSS = 0, 1
 REVD, NYSTROM, RITZIT = 0, 1, 2
 METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
 RES_TRUE, RES_PRECOND = 0, 1
+PCG_FUSED, PCG_PLAIN = 0, 1
 PREC_FP64 = 0
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
@@ -33,7 +34,8 @@ _vp = ctypes.c_void_p
 
 
 class PcgOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("criterion", ctypes.c_int)]
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int), ("criterion", ctypes.c_int),
+                ("variant", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -315,8 +317,8 @@ class Problem:
         return Lmp(h.value, self, int(k_r))
 
     def pcg(self, b, x, lmp: Optional[Lmp] = None, tol: float = 1e-6, maxit: int = 100,
-            criterion: int = RES_TRUE, history: bool = True, stream=None):
-        opts = PcgOpts(float(tol), int(maxit), int(criterion))
+            criterion: int = RES_TRUE, history: bool = True, variant: int = PCG_FUSED, stream=None):
+        opts = PcgOpts(float(tol), int(maxit), int(criterion), int(variant))
         info = PcgInfo()
         ht = np.zeros(maxit) if history else None
         hp = np.zeros(maxit) if history else None

@@ -72,6 +72,10 @@ CASES = {
     "ragged_l96": tiny("l96", n=67, N=5, vs=5, ts=1),    # several waves, ragged tail
     "wide_adv": tiny(n=300, N=3, vs=7, ts=3),             # 256 threads x 2 points, ragged
     "n1_adv": tiny(n=1, N=6, vs=1, ts=2),
+    # time-blocked single-vector sweeps (n >= 512): owned chunks with an N-point halo
+    "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # 2 chunks, ragged last chunk, 1 point/thread
+    "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # 4 chunks of 312
+    "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # 2 points/thread, chunks of 624
 }
 
 
@@ -164,9 +168,10 @@ def test_lmp_build_matches_oracle(method, wname):
     assert e_c <= 1e-8, (method, e_c)
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
-def test_pcg_matches_oracle_C1(method):
-    say("pcg C1", method)
+def test_pcg_matches_oracle_C1(method, variant):
+    say("pcg C1", method, "variant", variant)
     w = C1
     gp, op = pair(w)
     G = sketch_block(op.n_A, w.m, w.seed)
@@ -175,7 +180,7 @@ def test_pcg_matches_oracle_C1(method):
     b = O.rhs(op, d)
     bd = gp.rhs(to_dev(d))
     x = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
-    info = gp.pcg(bd, x, L, tol=1e-6, maxit=500)
+    info = gp.pcg(bd, x, L, tol=1e-6, maxit=500, variant=variant)
     Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
     ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-6, maxit=500)
     assert info["status"] == 0 and ro.converged
@@ -194,9 +199,10 @@ def test_pcg_matches_oracle_C1(method):
     assert np.linalg.norm(s) / np.linalg.norm(b) <= 1.01e-6
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit", None])
-def test_pcg_tight_solution_C2(method):
-    say("pcg tight C2", method)
+def test_pcg_tight_solution_C2(method, variant):
+    say("pcg tight C2", method, "variant", variant)
     w = C2
     gp, op = pair(w)
     G = sketch_block(op.n_A, w.m, w.seed)
@@ -204,7 +210,7 @@ def test_pcg_tight_solution_C2(method):
     d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
     b = O.rhs(op, d)
     x = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
-    info = gp.pcg(gp.rhs(to_dev(d)), x, L, tol=1e-11, maxit=3000)
+    info = gp.pcg(gp.rhs(to_dev(d)), x, L, tol=1e-11, maxit=3000, variant=variant)
     assert info["status"] == 0, info
     if method:
         Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
@@ -218,7 +224,7 @@ def test_pcg_tight_solution_C2(method):
     assert np.linalg.norm(b - O.apply_A(op, xg)) / np.linalg.norm(b) <= 2e-11
     # iteration counts at 1e-6 agree within +-2
     x6 = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
-    i6 = gp.pcg(gp.rhs(to_dev(d)), x6, L, tol=1e-6, maxit=3000)
+    i6 = gp.pcg(gp.rhs(to_dev(d)), x6, L, tol=1e-6, maxit=3000, variant=variant)
     r6 = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho) if method else None, tol=1e-6, maxit=3000)
     assert abs(i6["iters"] - r6.iters) <= 2, (i6["iters"], r6.iters)
 
