@@ -7,7 +7,15 @@ split PCG on the exact Hessian until ||b - A x|| <= 1e-6 ||b||.
 
 Default workload: periodic advection-diffusion n = 4096, N = 100 (n_A = 413,696),
 SOAR B / Q, every 4th point observed at every 2nd step (q = 51,200), a sketch of
-m = 256 columns (k_r = 251 Ritz pairs, oversampling 5), Nystrom, float64.
+m = 256 columns (k_r = 251 Ritz pairs, oversampling 5), Nystrom.
+
+Variants (each timed over the same number of steps):
+  plain  float64 throughout;
+  mixed  the sketch's D^{1/2} products as three bfloat16 MFMA products with float32
+         accumulation and a float32 copy of U for the LMP passes; CholeskyQR2, the
+         small eigenproblem and the whole PCG operator stay float64, and the stop is
+         the float64 true residual.
+`value` is the mixed variant's ms per step; the plain one is reported beside it.
 
 Prints one JSON line (see the fields below).  Only --gpus 1 is supported.
 """
@@ -25,6 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
 
 def parse():
@@ -34,6 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
     ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit"])
+    ap.add_argument("--variants", default="plain,mixed")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -99,39 +109,54 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    from paper_2101_07249_amd import wc4d as W4
+
     dev = torch.device("cuda", 0)
     w = WORKLOADS[args.workload]
     pat = obs_pattern(w)
-    prob = Problem.from_workload(w, pat)
-    G = torch.from_numpy(np.ascontiguousarray(sketch_block(prob.n_A, w.m, w.seed).T)).to(dev)
-    d = torch.from_numpy(innovations(prob.q, w.seed, np.sqrt(w.sigma_o2))).to(dev)
-    x = torch.zeros(prob.n_A, dtype=torch.float64, device=dev)
+    G = torch.from_numpy(np.ascontiguousarray(sketch_block(w.n_A, w.m, w.seed).T)).to(dev)
+    dnp = innovations(sum(len(i) for _, i in pat), w.seed, np.sqrt(w.sigma_o2))
+    d = torch.from_numpy(dnp).to(dev)
+    x = torch.zeros(w.n_A, dtype=torch.float64, device=dev)
+    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32}
+    names = [v for v in args.variants.split(",") if v]
+    results = {}
+    for vname in names:
+        prob = Problem.from_workload(w, pat, prec=precs[vname])
 
-    def step():
-        b = prob.rhs(d)
-        L = prob.lmp_build(args.method, w.k_r, w.l, G)
-        x.zero_()
-        info = prob.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
-        L.close()
-        return info
+        def step():
+            b = prob.rhs(d)
+            L = prob.lmp_build(args.method, w.k_r, w.l, G)
+            x.zero_()
+            info = prob.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
+            L.close()
+            return info
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    prob.prof_enable(True)
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        infos.append(step())
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = prob.prof_read()
-    prob.prof_enable(False)
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
-    ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in infos)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        prob.prof_enable(True)
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            infos.append(step())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = prob.prof_read()
+        prob.prof_enable(False)
+        results[vname] = {"ms_per_step": 1e3 * (t1 - t0) / args.steps,
+                          "pcg_iters": int(np.median([i["iters"] for i in infos])),
+                          "relres_true": max(i["relres_true"] for i in infos),
+                          "converged": all(i["status"] == 0 and i["relres_true"] <= args.tol for i in infos),
+                          "prof": prof, "prob": prob}
+    head = "mixed" if "mixed" in results else names[0]
+    prob = results[head]["prob"]
+    prof = results[head]["prof"]
+    ms_per_step = results[head]["ms_per_step"]
+    ok = results[head]["converged"]
 
-    # Hessian apply on the sketch-width block (per-stage HIP events)
+    # Hessian apply on the sketch-width block in float64 (per-stage HIP events)
+    prob = results["plain"]["prob"] if "plain" in results else prob
     Y = torch.empty_like(G)
     prob.set_profiling(True)
     stages = np.zeros(4)
@@ -155,30 +180,34 @@ def main():
     classes = {k: v for k, v in prof.items() if v["launches"] > 0 and k != "build_other"}
     dom = max(classes, key=lambda k: classes[k]["ms"])
     dv = classes[dom]
-    if dom == "dsqrt_gemm":
+    if dom in ("dsqrt_gemm", "dsqrt_bf16x3"):
+        peak = FP64_PEAK_TFLOPS if dom == "dsqrt_gemm" else BF16_PEAK_TFLOPS
         achieved = dv["flops"] / (dv["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None}
     else:
         achieved = dv["bytes"] / (dv["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
     roof.update({"kernel": dom, "launches": dv["launches"], "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
-                 "algorithmic_per_launch": (dv["flops"] if dom == "dsqrt_gemm" else dv["bytes"]) / dv["launches"]})
+                 "algorithmic_per_launch": (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"]})
 
-    iters = int(np.median([i["iters"] for i in infos]))
+    iters = results[head]["pcg_iters"]
+    variants = {k: {kk: vv for kk, vv in v.items() if kk not in ("prof", "prob")} for k, v in results.items()}
+    for k, v in results.items():
+        variants[k]["kernel_classes_ms"] = {c: round(e["ms"] / args.steps, 3) for c, e in v["prof"].items()}
     out = {
         "metric": "PCG time-to-1e-6 residual (learned/mixed vs plain FP64); Hessian-apply HBM GB/s",
         "value": ms_per_step, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w.name, "variant": "plain FP64 Gaussian sketch", "method": args.method,
+        "dtype": "f64+bf16x3" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": w.name, "variant": head, "method": args.method,
                    "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,
                    "criterion": "true residual ||b - A x|| / ||b||"},
-        "pcg_iters": iters, "relres_true": max(i["relres_true"] for i in infos), "converged": ok,
+        "pcg_iters": iters, "relres_true": results[head]["relres_true"], "converged": ok,
+        "variants": variants,
         "hessian_apply": hess,
-        "kernel_classes_ms": {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

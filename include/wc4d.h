@@ -52,7 +52,14 @@ enum {
 enum { WC4D_CORR_SOAR = 0, WC4D_CORR_GAUSS = 1 };
 enum { WC4D_REVD = 0, WC4D_NYSTROM = 1, WC4D_RITZIT = 2 };
 enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
-enum { WC4D_PREC_FP64 = 0 };
+/* Precision flags (wc4d_finalize).  FP64 everywhere by default.
+ *   WC4D_PREC_SKETCH_BF16X3: the D^{1/2} products of the block applies inside
+ *     wc4d_lmp_build run as three bfloat16 MFMA products with float32 accumulation
+ *     (S_hi X_hi + S_hi X_lo + S_lo X_hi, S = S_hi + S_lo); CholeskyQR2, the m x m
+ *     eigenproblem and everything in wc4d_pcg stay float64.
+ *   WC4D_PREC_LMP_FP32: the LMP keeps a float32 copy of U that wc4d_pcg streams
+ *     (products accumulate in float64; C stays exactly symmetric). */
+enum { WC4D_PREC_FP64 = 0, WC4D_PREC_SKETCH_BF16X3 = 1, WC4D_PREC_LMP_FP32 = 2 };
 
 /* Library version (major*10000 + minor*100 + patch) and status-code names. */
 int wc4d_version(void);
@@ -102,8 +109,8 @@ int wc4d_set_Qsqrt(wc4d_problem p, const double* Qsqrt);
 int wc4d_set_obs(wc4d_problem p, int i, int q_i, const int* idx, const double* rdiag);
 
 /* Upload everything to the device and allocate the operator's fixed data.
- * prec_mode: WC4D_PREC_FP64.  Synchronous.  Setup calls after finalize return
- * WC4D_ESTATE. */
+ * prec_mode: WC4D_PREC_FP64 or an OR of the WC4D_PREC_* flags.  Synchronous.
+ * Setup calls after finalize return WC4D_ESTATE. */
 int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s);
 
 /* n_A and q = total number of observations (after finalize). */
@@ -116,6 +123,12 @@ int wc4d_dims(wc4d_problem p, int* n_A, int* q);
  * D^{1/2} product, plus X.  X and Y: device, n_A x m, ldx/ldy >= n_A; X and Y must
  * not overlap.  Uses workspace owned by p (grown on demand, synchronously). */
 int wc4d_apply_A(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+
+/* Y = A X with the D^{1/2} products in precision `prec` (WC4D_PREC_FP64 or
+ * WC4D_PREC_SKETCH_BF16X3; the latter needs the flag at finalize).  For measuring
+ * the error of the reduced-precision apply against the float64 one. */
+int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, int prec,
+                      hipStream_t s);
 
 /* Pieces of the operator, for testing and composition:
  *   Y = L^{-1} X   (x_0 = p_0, x_{i+1} = M_i x_i + p_{i+1}; Section 2.1)
@@ -205,10 +218,11 @@ int wc4d_last_apply_timing(wc4d_problem p, float* ms4);
  * needs, not counter readings).  Classes: 0 D^{1/2} products of the operator,
  * 1 forward sweep (+ observation gather), 2 adjoint sweep (+ scatter), 3 the U^T x
  * pass and 4 the x + U t pass of a single-vector LMP application, 5 the other
- * kernels of an LMP build.  wc4d_prof_enable resets the totals; wc4d_prof_read
- * waits for the recorded work and reports one class. */
+ * kernels of an LMP build, 6 the split-bfloat16 D^{1/2} products (flops counted as
+ * the three bfloat16 products).  wc4d_prof_enable resets the totals;
+ * wc4d_prof_read waits for the recorded work and reports one class. */
 enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC4D_PROF_LMP_T = 3,
-       WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_NCLASS = 6 };
+       WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_DSQRT_BF16 = 6, WC4D_PROF_NCLASS = 7 };
 int wc4d_prof_enable(wc4d_problem p, int enable);
 int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
                    double* flops);

@@ -215,6 +215,10 @@ int wc4d_destroy(wc4d_problem p) {
   DevGuard g(p->device);
   dev_free(&p->dB);
   dev_free(&p->dQ);
+  dev_free(&p->dBhi);
+  dev_free(&p->dBlo);
+  dev_free(&p->dQhi);
+  dev_free(&p->dQlo);
   dev_free(&p->dStages);
   dev_free(&p->dObsOff);
   dev_free(&p->dObsIdx);
@@ -223,6 +227,7 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->wsStash);
   dev_free(&p->wsGram);
   dev_free(&p->wsSplit);
+
   dev_free(&p->bufA);
   dev_free(&p->bufB);
   dev_free(&p->small);
@@ -362,7 +367,8 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (p->finalized) return fail(p, WC4D_ESTATE, "already finalized");
   if (p->model < 0) return fail(p, WC4D_ESTATE, "no model set");
   if (!p->haveB || !p->haveQ) return fail(p, WC4D_ESTATE, "B^{1/2} and Q^{1/2} must be set");
-  if (prec_mode != WC4D_PREC_FP64) return fail(p, WC4D_EINVAL, "unknown precision mode");
+  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32))
+    return fail(p, WC4D_EINVAL, "unknown precision flags");
   DevGuard g(p->device);
   const int n = p->n, N = p->N;
   std::vector<int> off(N + 2, 0), idx;
@@ -403,10 +409,19 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (need > (size_t)maxLds)
     return fail(p, WC4D_EINVAL, "state too large for the sweep's LDS (" + std::to_string(need) +
                                     " > " + std::to_string(maxLds) + " bytes)");
+  if (prec_mode & WC4D_PREC_SKETCH_BF16X3) {
+    const size_t nn = (size_t)n * n;
+    if ((rc = dev_alloc(p, &p->dBhi, nn)) || (rc = dev_alloc(p, &p->dBlo, nn)) ||
+        (rc = dev_alloc(p, &p->dQhi, nn)) || (rc = dev_alloc(p, &p->dQlo, nn)))
+      return rc;
+    HIPCHK(p, split_bf16_rows(n, n, p->dB, n, p->dBhi, p->dBlo, s));
+    HIPCHK(p, split_bf16_rows(n, n, p->dQ, n, p->dQhi, p->dQlo, s));
+  }
   if ((rc = dev_alloc(p, &p->dStatus, 16))) return rc;
   // split-K partials: up to 512 workgroups' worth of n x 112 tiles
-  p->wsSplitDoubles = std::min<size_t>((size_t)8 * n * 112, (size_t)1 << 24);
+  p->wsSplitDoubles = std::min<size_t>((size_t)8 * n * (112 + 2), (size_t)1 << 24);
   if ((rc = dev_alloc(p, &p->wsSplit, p->wsSplitDoubles))) return rc;
+
   HIPCHK(p, hipMemsetAsync(p->dStatus, 0, 16 * sizeof(int), s));
   HIPCHK(p, hipStreamSynchronize(s));
   p->prec = prec_mode;
@@ -473,8 +488,21 @@ namespace {
 
 // Y(time levels) = D^{1/2} X [+ E]: B^{1/2} on time 0, Q^{1/2} on times 1..N.
 int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
-                const double* E, long long lde, const int* skip, hipStream_t s) {
+                const double* E, long long lde, const int* skip, hipStream_t s, bool mixed = false) {
   const int n = p->n, N = p->N;
+  if (mixed) {
+    HIPCHK(p, gemm_bf16x3(n, m, n, 1.0, p->dBhi, p->dBlo, X, ColMap{ldx, 1, 0, n}, Y,
+                          ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
+    HIPCHK(p, gemm_bf16x3(n, m * N, n, 1.0, p->dQhi, p->dQlo, X, ColMap{ldx, N, 1, n}, Y,
+                          ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
+    return WC4D_OK;
+  }
+  if (m * N <= 112 && n >= 512 && dsqrt2_ws_doubles(n, m * N, m, n) <= p->wsSplitDoubles) {
+    HIPCHK(p, dsqrt2_f64(n, n, X, Y, E, p->dQ, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n},
+                         ColMap{lde, N, 1, n}, m * N, p->dB, ColMap{ldx, 1, 0, n}, ColMap{ldy, 1, 0, n},
+                         ColMap{lde, 1, 0, n}, m, skip, p->wsSplit, p->wsSplitDoubles, s));
+    return WC4D_OK;
+  }
   HIPCHK(p, gemm_f64(n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y, ColMap{ldy, 1, 0, n}, E,
                      ColMap{lde, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
   HIPCHK(p, gemm_f64(n, m * N, n, 1.0, p->dQ, n, X, ColMap{ldx, N, 1, n}, Y, ColMap{ldy, N, 1, n},
@@ -484,7 +512,7 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
 
 // Y = A X using the problem's block workspace (must hold m columns).
 int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
-                 const int* skip, hipStream_t s) {
+                 const int* skip, hipStream_t s, bool mixed = false) {
   const long long nA = p->nA;
   if (p->q == 0) {
     HIPCHK(p, block_copy(Y, ldy, X, ldx, nA, m, s));
@@ -497,9 +525,11 @@ int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long
   const double traj = (p->model == 1) ? 8.0 * 4.0 * p->n * p->N : 0.0;  // stage inputs, read once
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[0], s));
   int rc;
+  const int dcls = mixed ? PROF_DSQRT_BF16 : PROF_DSQRT;
+  const double dfl = mixed ? 3.0 * gflops : gflops;
   {
-    ProfScope ps(p, s, PROF_DSQRT, 16.0 * n2 + 2.0 * blk, gflops);
-    rc = dsqrt_apply(p, X, ldx, P, nA, m, nullptr, 0, skip, s);
+    ProfScope ps(p, s, dcls, (mixed ? 8.0 : 16.0) * n2 + 2.0 * blk, dfl);
+    rc = dsqrt_apply(p, X, ldx, P, nA, m, nullptr, 0, skip, s, mixed);
   }
   if (rc) return rc;
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[1], s));
@@ -514,8 +544,8 @@ int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long
   }
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[3], s));
   {
-    ProfScope ps(p, s, PROF_DSQRT, 16.0 * n2 + 3.0 * blk, gflops);
-    rc = dsqrt_apply(p, P, nA, Y, ldy, m, X, ldx, skip, s);
+    ProfScope ps(p, s, dcls, (mixed ? 8.0 : 16.0) * n2 + 3.0 * blk, dfl);
+    rc = dsqrt_apply(p, P, nA, Y, ldy, m, X, ldx, skip, s, mixed);
   }
   if (rc) return rc;
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[4], s));
@@ -544,6 +574,19 @@ int wc4d_apply_A(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, i
   DevGuard g(p->device);
   if ((rc = ensure_block(p, m))) return rc;
   return apply_A_core(p, X, ldx, Y, ldy, m, nullptr, s);
+}
+
+int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, int prec,
+                      hipStream_t s) {
+  int rc = check_block_args(p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  if (prec != WC4D_PREC_FP64 && prec != WC4D_PREC_SKETCH_BF16X3)
+    return fail(p, WC4D_EINVAL, "prec must be WC4D_PREC_FP64 or WC4D_PREC_SKETCH_BF16X3");
+  if (prec == WC4D_PREC_SKETCH_BF16X3 && p->dBhi == nullptr)
+    return fail(p, WC4D_ESTATE, "finalize without WC4D_PREC_SKETCH_BF16X3");
+  DevGuard g(p->device);
+  if ((rc = ensure_block(p, m))) return rc;
+  return apply_A_core(p, X, ldx, Y, ldy, m, nullptr, s, prec == WC4D_PREC_SKETCH_BF16X3);
 }
 
 int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
@@ -595,8 +638,8 @@ namespace {
 int ensure_build(wc4d_problem p, int m) {
   int rc;
   if (p->bufCols < m) {
-    if ((rc = dev_alloc(p, &p->bufA, (size_t)p->nA * m))) return rc;
-    if ((rc = dev_alloc(p, &p->bufB, (size_t)p->nA * m))) return rc;
+    if ((rc = dev_alloc(p, &p->bufA, (size_t)(p->nA + 4) * m))) return rc;
+    if ((rc = dev_alloc(p, &p->bufB, (size_t)(p->nA + 4) * m))) return rc;
     p->bufCols = m;
   }
   if (p->smallM < m) {
@@ -662,12 +705,13 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (L == nullptr) return WC4D_ENOMEM;
   L->p = p;
   L->nA = p->nA;
+  L->ldu = (p->nA + 3) / 4 * 4;
   L->k = k_r;
   auto cleanup = [&](int code) {
     wc4d_lmp_destroy(L);
     return code;
   };
-  if ((rc = dev_alloc(p, &L->U, (size_t)p->nA * k_r))) return cleanup(rc);
+  if ((rc = dev_alloc(p, &L->U, (size_t)L->ldu * k_r))) return cleanup(rc);
   if ((rc = dev_alloc(p, &L->theta, k_r))) return cleanup(rc);
   if ((rc = dev_alloc(p, &L->dcoef, k_r))) return cleanup(rc);
 
@@ -680,11 +724,12 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   double* Zfinal = nullptr;
   int mode = 0;
+  const bool mx = (p->prec & WC4D_PREC_SKETCH_BF16X3) != 0;
   if (method == WC4D_REVD) {
     // Algorithm 3: Y = A G; Z = orth(Y); K = Z^T A Z; EVD; U = Z W
-    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s, mx))) return cleanup(rc);
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
-    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
     L->applies = 2;
     he = gram_f64(m, m, nA, A_, cm, B_, cm, sm.K, m, p->wsGram, nullptr, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
@@ -692,9 +737,9 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   } else if (method == WC4D_NYSTROM) {
     // Algorithm 4: Y = A G; Z = orth(Y); E1 = A Z; E2 = Z^T E1 = C^T C; F = E1 C^{-1};
     // SVD F = U Sigma V^T via F = Q_F R_F and the EVD of R_F R_F^T; Theta = Sigma^2
-    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s, mx))) return cleanup(rc);
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
-    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
     L->applies = 2;
     he = gram_f64(m, m, nA, A_, cm, B_, cm, sm.G, m, p->wsGram, nullptr, s);
     if (he == hipSuccess) he = chol_upper(m, sm.G, m, p->dStatus, s);
@@ -711,7 +756,7 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
     he = vec_copy(A_, G, nA * m, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
-    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
     L->applies = 1;
     if ((rc = cholqr2(p, B_, A_, m, sm, sm.R2, s))) return cleanup(rc);
     he = small_gemm(m, m, m, 1.0, sm.R2, m, 0, sm.R2, m, 1, sm.K, m, s);
@@ -723,7 +768,8 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s);
   if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
   if (he == hipSuccess)
-    he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, cm, nullptr, cm, nullptr, s);
+    he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, plain_cols(L->ldu), nullptr,
+                  cm, nullptr, s);
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   int st = 0;
   he = hipMemcpyAsync(&st, p->dStatus, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -731,11 +777,24 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   if (st != 0)
     return cleanup(fail(p, WC4D_ENOTSPD, "Cholesky met a non-positive pivot (rank-deficient sketch?)"));
-  // U^T U for the fused PCG recursion (identity up to rounding for an orthonormal U)
+  // U^T U of the U the PCG streams, for the fused recursion (identity up to rounding
+  // for an orthonormal U; computed from the float32 copy when there is one)
   if ((rc = dev_alloc(p, &L->GU, (size_t)k_r * k_r))) return cleanup(rc);
   if ((rc = dev_alloc(p, &L->fu, (size_t)3 * k_r))) return cleanup(rc);
   if ((rc = ensure_gram(p, gram_ws_doubles(k_r, k_r, nA)))) return cleanup(rc);
-  he = gram_f64(k_r, k_r, nA, L->U, cm, L->U, cm, L->GU, k_r, p->wsGram, nullptr, s);
+  const double* Ug = L->U;
+  if (p->prec & WC4D_PREC_LMP_FP32) {
+    // the build's scratch block B_ (n_A x m doubles) holds the rounded copy for the Gram;
+    // the padding rows (n_A .. ldu) of the conversions are never read by any product
+    if ((rc = dev_alloc(p, &L->U32, (size_t)L->ldu * k_r))) return cleanup(rc);
+    he = vec_to_f32(L->U32, L->U, L->ldu * k_r, s);
+    if (he == hipSuccess && L->ldu * k_r <= (nA + 4) * m) he = vec_to_f64(B_, L->U32, L->ldu * k_r, s);
+    if (he != hipSuccess || L->ldu * k_r > (nA + 4) * m)
+      return cleanup(fail(p, WC4D_EHIP, "float32 copy of U failed"));
+    Ug = B_;
+  }
+  he = gram_f64(k_r, k_r, nA, Ug, plain_cols(L->ldu), Ug, plain_cols(L->ldu), L->GU, k_r, p->wsGram,
+                nullptr, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   *out = L;
@@ -752,7 +811,7 @@ int wc4d_lmp_theta(wc4d_lmp L, double* theta_host) {
 int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s) {
   if (L == nullptr || U == nullptr || ldu < L->nA) return WC4D_EINVAL;
   DevGuard g(L->p->device);
-  HIPCHK(L->p, block_copy(U, ldu, L->U, L->nA, L->nA, L->k, s));
+  HIPCHK(L->p, block_copy(U, ldu, L->U, L->ldu, L->nA, L->k, s));
   return WC4D_OK;
 }
 
@@ -777,15 +836,18 @@ int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long l
       if ((rc = dev_alloc(p, &L->wsv, need))) return rc;
       L->wsvDoubles = need;
     }
-    const double ub = 8.0 * (double)L->nA * L->k, fl = 2.0 * (double)L->nA * L->k;
+    const bool u32 = L->U32 != nullptr;
+    const void* Us = u32 ? (const void*)L->U32 : (const void*)L->U;
+    const double ub = (u32 ? 4.0 : 8.0) * (double)L->nA * L->k, fl = 2.0 * (double)L->nA * L->k;
     for (int c = 0; c < m; ++c) {
       {
         ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * L->nA, fl);
-        HIPCHK(p, lmp_gemv_t(L->nA, L->k, L->U, L->nA, L->dcoef, X + (size_t)c * ldx, L->wsv, skip, s));
+        HIPCHK(p, lmp_gemv_t(L->nA, L->k, Us, u32, L->ldu, L->dcoef, X + (size_t)c * ldx, L->wsv,
+                             skip, s));
       }
       ProfScope ps(p, s, PROF_LMP_N, ub + 16.0 * L->nA, fl);
-      HIPCHK(p, lmp_gemv_n(L->nA, L->k, L->U, L->nA, X + (size_t)c * ldx, Y + (size_t)c * ldy, L->wsv,
-                           skip, s));
+      HIPCHK(p, lmp_gemv_n(L->nA, L->k, Us, u32, L->ldu, X + (size_t)c * ldx, Y + (size_t)c * ldy,
+                           L->wsv, skip, s));
     }
     return WC4D_OK;
   }
@@ -798,10 +860,10 @@ int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long l
     if ((rc = dev_alloc(p, &L->ws, wsn))) return rc;
     L->wsDoubles = wsn;
   }
-  HIPCHK(p, gram_f64(L->k, m, L->nA, L->U, plain_cols(L->nA), X, plain_cols(ldx), L->T, L->k, L->ws,
+  HIPCHK(p, gram_f64(L->k, m, L->nA, L->U, plain_cols(L->ldu), X, plain_cols(ldx), L->T, L->k, L->ws,
                      skip, s));
   HIPCHK(p, vec_scale_rows(L->T, L->k, m, L->k, L->dcoef, skip, s));
-  HIPCHK(p, gemm_f64((int)L->nA, m, L->k, 1.0, L->U, L->nA, L->T, plain_cols(L->k), Y,
+  HIPCHK(p, gemm_f64((int)L->nA, m, L->k, 1.0, L->U, L->ldu, L->T, plain_cols(L->k), Y,
                      plain_cols(ldy), X, plain_cols(ldx), skip, s));
   return WC4D_OK;
 }
@@ -829,6 +891,7 @@ int wc4d_lmp_destroy(wc4d_lmp L) {
   dev_free(&L->wsv);
   dev_free(&L->GU);
   dev_free(&L->fu);
+  dev_free(&L->U32);
   delete L;
   return WC4D_OK;
 }
@@ -884,11 +947,13 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
   double* u = nullptr;
   double* d12 = nullptr;
   double* tvec = nullptr;
+  const bool u32 = L != nullptr && L->U32 != nullptr;
+  const void* Us = (L == nullptr) ? nullptr : (u32 ? (const void*)L->U32 : (const void*)L->U);
   if (fused) {
     u = L->fu;
     d12 = L->fu + L->k;
     tvec = L->wsv + lmp_gemv_t_offset(nA, L->k);
-    HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, r, L->wsv, nullptr, s, u));
+    HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, nullptr, s, u));
   }
   const int poll = 8;
   int it = 0;
@@ -897,24 +962,24 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
       if (fused) {
-        const double ub = 8.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
+        const double ub = (u32 ? 4.0 : 8.0) * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
         if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
         HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
         HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
         {
           ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * nA, fl);
-          HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, Ap, L->wsv, done, s));
+          HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, Ap, L->wsv, done, s));
         }
         HIPCHK(p, pcg_lmp_coeffs(st, L->k, tvec, L->dcoef, L->GU, u, d12, s));
         {
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 4.0 * nA, 2.0 * fl);
-          HIPCHK(p, pcg_lmp_dual(st, nA, L->k, L->U, nA, d12, Ap, r, z, p->pcgRed, p->pcgHist, s));
+          HIPCHK(p, pcg_lmp_dual(st, nA, L->k, Us, u32, L->ldu, d12, Ap, r, z, p->pcgRed, p->pcgHist, s));
         }
         HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
         // recompute u = U^T r exactly once r.r has dropped by 100x (or after 50 steps):
         // the recursion's absolute rounding error does not shrink with u
         HIPCHK(p, pcg_refresh_decide(st, s));
-        HIPCHK(p, lmp_gemv_t(nA, L->k, L->U, nA, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, &st->no_refresh, s, u));
         continue;
       }
       if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;

@@ -1,0 +1,194 @@
+// Split-precision GEMM for the D^{1/2} products of the sketch block applies:
+// C = alpha S X [+ E] with float64 inputs and outputs, computed as
+//   S_hi X_hi + S_hi X_lo + S_lo X_hi,   S = S_hi + S_lo, X = X_hi + X_lo (bfloat16 pairs),
+// on v_mfma_f32_16x16x32_bf16 with float32 accumulation.  The dropped S_lo X_lo term
+// and the bfloat16 rounding of the low parts are O(2^-16) relative; the float32 sum
+// over K adds O(sqrt(K) 2^-24).
+//
+// S is pre-split once (split_bf16_rows) into two row-major bf16 arrays (row i holds
+// S(i, 0..K-1) contiguously), so an MFMA operand row is one 16-byte load.  X is
+// split while it is staged into LDS.
+//
+// v_mfma_f32_16x16x32_bf16 lane layout (wave64): operand a = A[l%16][8(l/16) + e],
+// operand b = B[8(l/16) + e][l%16] (e = 0..7), result register r = D[4(l/16) + r][l%16].
+// As in gemm_f64 the product is formed transposed (MFMA rows = columns t of C), so a
+// lane's results are 4 consecutive columns of one row and the 16 lanes sharing l/16
+// store 16 consecutive rows of a column.
+#include "wc4d_internal.h"
+
+namespace wc4d {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+static __device__ inline f4 mfma_bf16(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+static __device__ inline void split2(double x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)(float)x;
+  lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+// Shi/Slo (row-major, ld K): S(i, k) for i < M, k < K from column-major S (lds).
+__global__ void k_split_bf16_rows(int M, int K, const double* __restrict__ S, long long lds,
+                                  __bf16* __restrict__ Shi, __bf16* __restrict__ Slo) {
+  const long long tot = (long long)M * K;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / K), k = (int)(e % K);
+    __bf16 h, l;
+    split2(S[(size_t)i + (size_t)k * lds], h, l);
+    Shi[e] = h;
+    Slo[e] = l;
+  }
+}
+
+hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16* Shi, __bf16* Slo,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_split_bf16_rows, dim3(2048), dim3(256), 0, s, M, K, S, lds, Shi, Slo);
+  return hipGetLastError();
+}
+
+constexpr int XBM = 128, XBN = 128, XBK = 32;
+constexpr int XPK = XBK + 8;  // LDS row pitch in bf16 (80 bytes)
+
+// Tile: XBM rows (i) x XBN columns (j) of C; 4 waves as 2 (i) x 2 (j), each 64 x 64.
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(int M, int ncol, int K, double alpha,
+                                                     const __bf16* __restrict__ Shi,
+                                                     const __bf16* __restrict__ Slo,
+                                                     const double* __restrict__ B, ColMap bmap,
+                                                     double* __restrict__ C, ColMap cmap,
+                                                     const double* __restrict__ E, ColMap emap) {
+  __shared__ __attribute__((aligned(16))) __bf16 Sh[XBM][XPK], Sl[XBM][XPK];
+  __shared__ __attribute__((aligned(16))) __bf16 Xh[XBN][XPK], Xl[XBN][XPK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * XBM, j0 = blockIdx.y * XBN;
+  const int wi0 = (wave & 1) * 64, wj0 = (wave >> 1) * 64;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // loader roles: S rows (2 threads per row, 16 k each); X columns (2 threads per column)
+  const int lr = tid >> 1, lh = (tid & 1) * 16;
+  const bool srow_ok = (i0 + lr) < M;
+  const __bf16* shp = Shi + (size_t)(srow_ok ? i0 + lr : 0) * K;
+  const __bf16* slp = Slo + (size_t)(srow_ok ? i0 + lr : 0) * K;
+  const bool xcol_ok = (j0 + lr) < ncol;
+  const double* xp = B + (xcol_ok ? bmap.off(j0 + lr) : 0);
+  bf8 rsh[2], rsl[2];
+  double rx[16];
+  // 16-byte loads when the row / column start is aligned and the slab is inside K
+  const bool svec = (K % 8) == 0;
+  const bool xvec = ((reinterpret_cast<uintptr_t>(xp) & 15) == 0);
+  auto gload = [&](int k0) {
+    const int kb = k0 + lh;
+    if (svec && kb + 16 <= K) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        rsh[v] = srow_ok ? *reinterpret_cast<const bf8*>(shp + kb + 8 * v) : bf8{};
+        rsl[v] = srow_ok ? *reinterpret_cast<const bf8*>(slp + kb + 8 * v) : bf8{};
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const bool ok = srow_ok && (kb + e) < K;
+        rsh[e / 8][e % 8] = ok ? shp[kb + e] : (__bf16)0.f;
+        rsl[e / 8][e % 8] = ok ? slp[kb + e] : (__bf16)0.f;
+      }
+    }
+    if (xvec && kb + 16 <= K) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const double2 d2 = xcol_ok ? *reinterpret_cast<const double2*>(xp + kb + 2 * v) : double2{0.0, 0.0};
+        rx[2 * v] = d2.x;
+        rx[2 * v + 1] = d2.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) rx[e] = (xcol_ok && (kb + e) < K) ? xp[kb + e] : 0.0;
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += XBK) {
+    __syncthreads();
+    *reinterpret_cast<bf8*>(&Sh[lr][lh]) = rsh[0];
+    *reinterpret_cast<bf8*>(&Sh[lr][lh + 8]) = rsh[1];
+    *reinterpret_cast<bf8*>(&Sl[lr][lh]) = rsl[0];
+    *reinterpret_cast<bf8*>(&Sl[lr][lh + 8]) = rsl[1];
+    {
+      bf8 h0, h1, l0, l1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        __bf16 h, l;
+        split2(rx[e], h, l);
+        h0[e] = h;
+        l0[e] = l;
+        split2(rx[8 + e], h, l);
+        h1[e] = h;
+        l1[e] = l;
+      }
+      *reinterpret_cast<bf8*>(&Xh[lr][lh]) = h0;
+      *reinterpret_cast<bf8*>(&Xh[lr][lh + 8]) = h1;
+      *reinterpret_cast<bf8*>(&Xl[lr][lh]) = l0;
+      *reinterpret_cast<bf8*>(&Xl[lr][lh + 8]) = l1;
+    }
+    __syncthreads();
+    if (k0 + XBK < K) gload(k0 + XBK);
+    const int kk = 8 * (lane >> 4);
+    bf8 xh[4], xl[4], sh[4], sl[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int j = wj0 + a * 16 + (lane & 15);
+      xh[a] = *reinterpret_cast<const bf8*>(&Xh[j][kk]);
+      xl[a] = *reinterpret_cast<const bf8*>(&Xl[j][kk]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = wi0 + b * 16 + (lane & 15);
+      sh[b] = *reinterpret_cast<const bf8*>(&Sh[i][kk]);
+      sl[b] = *reinterpret_cast<const bf8*>(&Sl[i][kk]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc[a][b] = mfma_bf16(xh[a], sh[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(xl[a], sh[b], acc[a][b]);
+        acc[a][b] = mfma_bf16(xh[a], sl[b], acc[a][b]);
+      }
+  }
+  // acc[a][b][r] = C[i = i0 + wi0 + 16 b + l%16][j = j0 + wj0 + 16 a + 4 (l/16) + r]
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + wj0 + a * 16 + 4 * (lane >> 4) + r;
+      if (j >= ncol) continue;
+      const long long co = cmap.off(j);
+      const long long eo = (E != nullptr) ? emap.off(j) : 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + wi0 + b * 16 + (lane & 15);
+        if (i < M) {
+          double v = alpha * (double)acc[a][b][r];
+          if (E != nullptr) v += E[eo + i];
+          C[co + i] = v;
+        }
+      }
+    }
+}
+
+hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
+                       const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                       ColMap emap, hipStream_t s) {
+  if (M <= 0 || ncol <= 0) return hipSuccess;
+  dim3 grid((M + XBM - 1) / XBM, (ncol + XBN - 1) / XBN);
+  hipLaunchKernelGGL(k_gemm_bf16x3, grid, dim3(256), 0, s, M, ncol, K, alpha, Shi, Slo, B, bmap, C,
+                     cmap, E, emap);
+  return hipGetLastError();
+}
+
+}  // namespace wc4d

@@ -221,6 +221,151 @@ hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long 
   return launch_gemm<32, 32, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
 }
 
+// ----------------------------------------------- two-segment few-column product
+// Y = S1 X1 (columns t < n1) and S2 X2 (columns t < n2) in one split-K launch: the
+// D^{1/2} product of one or two vectors (S1 = Q^{1/2} on the N later time levels,
+// S2 = B^{1/2} on time level 0).  blockIdx.z < z1 works on segment 1, the rest on
+// segment 2; MFMA column tiles past a segment's column count are skipped, so the
+// B^{1/2} segment costs a matrix-vector product.  k_dsqrt2_reduce sums the K splits
+// of both segments in a fixed order and applies the epilogue.
+struct Seg {
+  const double* A;
+  ColMap bmap, cmap, emap;
+  int ncol;
+  int splits;
+  int kchunk;
+  size_t wsoff;  // doubles
+};
+
+constexpr int SBM = 64, SBN = 112, SBK = 32;
+
+__global__ __launch_bounds__(256) void k_dsqrt2(int M, int K, long long lda, const double* __restrict__ B,
+                                                Seg s1, Seg s2, double* __restrict__ ws,
+                                                const int* __restrict__ skip) {
+  constexpr int WI = SBM / 4, WJ = SBN;
+  constexpr int TJ = WJ / 16;
+  constexpr int NA = SBM * SBK / 256, NB = SBN * SBK / 256;
+  __shared__ double As[SBK][SBM + 4];
+  __shared__ double Bs[SBK][SBN + 4];
+  if (skip != nullptr && *skip != 0) return;
+  const bool first = (int)blockIdx.z < s1.splits;
+  const Seg& sg = first ? s1 : s2;
+  const int z = first ? blockIdx.z : blockIdx.z - s1.splits;
+  const int ncol = sg.ncol;
+  const double* __restrict__ A = sg.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * SBM;
+  const int wi0 = wave * WI;
+  const int kbeg = z * sg.kchunk;
+  const int kend = min(K, kbeg + sg.kchunk);
+  d4 acc[TJ];
+#pragma unroll
+  for (int a = 0; a < TJ; ++a) acc[a] = d4{0.0, 0.0, 0.0, 0.0};
+  long long boff[NB];
+  bool bval[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int j = (tid + 256 * e) / SBK;
+    bval[e] = j < ncol;
+    boff[e] = bval[e] ? sg.bmap.off(j) : 0;
+  }
+  double ra[NA], rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + 256 * e;
+      const int gi = i0 + idx % SBM, gk = k0 + idx / SBM;
+      ra[e] = (gi < M && gk < kend) ? A[(long long)gi + (long long)gk * lda] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int gk = k0 + (tid + 256 * e) % SBK;
+      rb[e] = (bval[e] && gk < kend) ? B[boff[e] + gk] : 0.0;
+    }
+  };
+  gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += SBK) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + 256 * e;
+      As[idx / SBM][idx % SBM] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + 256 * e;
+      Bs[idx % SBK][idx / SBK] = rb[e];
+    }
+    __syncthreads();
+    if (k0 + SBK < kend) gload(k0 + SBK);
+#pragma unroll
+    for (int kk = 0; kk < SBK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double bv = As[kr][wi0 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TJ; ++a) {
+        if (a * 16 < ncol) acc[a] = mfma16x16x4(Bs[kr][a * 16 + (lane & 15)], bv, acc[a]);
+      }
+    }
+  }
+  double* wz = ws + sg.wsoff + (size_t)z * M * ncol;
+#pragma unroll
+  for (int a = 0; a < TJ; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = a * 16 + (lane >> 4) + 4 * r;
+      const int i = i0 + wi0 + (lane & 15);
+      if (j < ncol && i < M) wz[(size_t)j * M + i] = acc[a][r];
+    }
+  }
+}
+
+__global__ void k_dsqrt2_reduce(int M, Seg s1, Seg s2, double alpha, const double* __restrict__ ws,
+                                double* __restrict__ C, const double* __restrict__ E,
+                                const int* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const bool first = (int)blockIdx.y < s1.ncol;
+  const Seg& sg = first ? s1 : s2;
+  const int j = first ? blockIdx.y : blockIdx.y - s1.ncol;
+  const long long co = sg.cmap.off(j);
+  const long long eo = (E != nullptr) ? sg.emap.off(j) : 0;
+  const size_t plane = (size_t)M * sg.ncol;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int zz = 0; zz < sg.splits; ++zz) v += ws[sg.wsoff + zz * plane + (size_t)j * M + i];
+    v *= alpha;
+    if (E != nullptr) v += E[eo + i];
+    C[co + i] = v;
+  }
+}
+
+size_t dsqrt2_ws_doubles(int M, int n1, int n2, int K) {
+  const int tiles = (M + SBM - 1) / SBM;
+  const int sp = std::max(1, std::min((512 + tiles - 1) / tiles, K / 256));
+  return (size_t)sp * M * (n1 + n2);
+}
+
+hipError_t dsqrt2_f64(int M, int K, const double* B, double* C, const double* E, const double* A1,
+                      ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2, ColMap c2,
+                      ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles, hipStream_t s) {
+  if (n1 > SBN || n2 > SBN || n1 < 1 || n2 < 1) return hipErrorInvalidValue;
+  const int tiles = (M + SBM - 1) / SBM;
+  int sp = std::max(1, std::min((512 + tiles - 1) / tiles, K / 256));
+  if ((size_t)sp * M * (n1 + n2) > ws_doubles) return hipErrorInvalidValue;
+  int kchunk = (K + sp - 1) / sp;
+  kchunk = (kchunk + SBK - 1) / SBK * SBK;
+  sp = (K + kchunk - 1) / kchunk;
+  Seg s1{A1, b1, c1, e1, n1, sp, kchunk, 0};
+  Seg s2{A2, b2, c2, e2, n2, sp, kchunk, (size_t)sp * M * n1};
+  hipLaunchKernelGGL(k_dsqrt2, dim3(tiles, 1, 2 * sp), dim3(256), 0, s, M, K, (long long)M, B, s1, s2,
+                     ws, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 rg((M + 255) / 256 < 64 ? (M + 255) / 256 : 64, n1 + n2);
+  hipLaunchKernelGGL(k_dsqrt2_reduce, rg, dim3(256), 0, s, M, s1, s2, 1.0, ws, C, E, skip);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ Gram
 
 constexpr int GT = 64;   // output tile

@@ -36,8 +36,9 @@ size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)lmp_t_splits(nA, 
 
 // Partial sums of columns [c0, c0 + kTG) over rows [rb, re): each thread runs down
 // its rows with kTG accumulators; one block reduction at the end.
+template <typename T>
 __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k, long long rows_per,
-                                                            const double* __restrict__ U, long long ldu,
+                                                            const T* __restrict__ U, long long ldu,
                                                             const double* __restrict__ x,
                                                             double* __restrict__ part,
                                                             const int* __restrict__ skip) {
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k,
   long long re = rb + rows_per;
   if (re > nA) re = nA;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* Uc[kTG];
+  const T* Uc[kTG];
 #pragma unroll
   for (int c = 0; c < kTG; ++c) Uc[c] = U + (size_t)(c0 + c < k ? c0 + c : 0) * ldu;
   double acc[kTG];
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k,
 #pragma unroll
       for (int u = 0; u < kTU; ++u) {
         const long long rr = r + (long long)u * kLT;
-        if (ok[u]) acc[c] += Uc[c][rr] * xv[u];
+        if (ok[u]) acc[c] += (double)Uc[c][rr] * xv[u];
       }
     }
   }
@@ -106,7 +107,24 @@ __global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
 }
 
-__global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const double* __restrict__ U,
+// 4 consecutive rows per thread: one 16-byte (float) or two 16-byte (double) loads per
+// column; requires ldu % 4 == 0 (U is allocated that way) and 16-byte aligned x, y.
+template <typename T>
+static __device__ inline void load4(const T* p, double (&v)[4]);
+template <>
+__device__ inline void load4<float>(const float* p, double (&v)[4]) {
+  const float4 f = *reinterpret_cast<const float4*>(p);
+  v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+}
+template <>
+__device__ inline void load4<double>(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const T* __restrict__ U,
                                                     long long ldu, const double* __restrict__ t,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ y,
@@ -115,55 +133,66 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const d
   if (skip != nullptr && *skip != 0) return;
   for (int c = threadIdx.x; c < k; c += kLT) ts[c] = t[c];
   __syncthreads();
-  const long long r0 = (long long)blockIdx.x * kLRows;
-  long long rr[kLE];
-  bool ok[kLE];
-  double acc[kLE];
+  const long long r0 = ((long long)blockIdx.x * kLT + threadIdx.x) * 4;
+  if (r0 >= nA) return;
+  const bool full = r0 + 4 <= nA;
+  double acc[4];
 #pragma unroll
-  for (int e = 0; e < kLE; ++e) {
-    rr[e] = r0 + threadIdx.x + (long long)e * kLT;
-    ok[e] = rr[e] < nA;
-    acc[e] = ok[e] ? x[rr[e]] : 0.0;
-  }
+  for (int e = 0; e < 4; ++e) acc[e] = (r0 + e < nA) ? x[r0 + e] : 0.0;
   for (int c0 = 0; c0 < k; c0 += kLC) {
-    double u[kLC][kLE];
+    double u[kLC][4];
 #pragma unroll
-    for (int c = 0; c < kLC; ++c)
+    for (int c = 0; c < kLC; ++c) {
+      if (c0 + c < k && full) {
+        load4<T>(U + (size_t)(c0 + c) * ldu + r0, u[c]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < kLE; ++e)
-        u[c][e] = (c0 + c < k && ok[e]) ? U[(size_t)(c0 + c) * ldu + rr[e]] : 0.0;
+        for (int e = 0; e < 4; ++e)
+          u[c][e] = (c0 + c < k && r0 + e < nA) ? (double)U[(size_t)(c0 + c) * ldu + r0 + e] : 0.0;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < kLC; ++c) {
       const double tc = (c0 + c < k) ? ts[c0 + c] : 0.0;
 #pragma unroll
-      for (int e = 0; e < kLE; ++e) acc[e] += u[c][e] * tc;
+      for (int e = 0; e < 4; ++e) acc[e] += u[c][e] * tc;
     }
   }
 #pragma unroll
-  for (int e = 0; e < kLE; ++e)
-    if (ok[e]) y[rr[e]] = acc[e];
+  for (int e = 0; e < 4; ++e)
+    if (r0 + e < nA) y[r0 + e] = acc[e];
 }
 
-hipError_t lmp_gemv_t(long long nA, int k, const double* U, long long ldu, const double* dcoef,
-                      const double* x, double* ws, const int* skip, hipStream_t s, double* tout) {
+hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
+                      const double* dcoef, const double* x, double* ws, const int* skip,
+                      hipStream_t s, double* tout) {
   const int sp = lmp_t_splits(nA, k);
   long long rows_per = (nA + sp - 1) / sp;
   double* part = ws;
   double* t = (tout != nullptr) ? tout : ws + (size_t)sp * k;
   dim3 grid((k + kTG - 1) / kTG, sp);
-  hipLaunchKernelGGL(k_lmp_gemv_t_partial, grid, dim3(kLT), 0, s, nA, k, rows_per, U, ldu, x, part,
-                     skip);
+  if (u32)
+    hipLaunchKernelGGL(k_lmp_gemv_t_partial<float>, grid, dim3(kLT), 0, s, nA, k, rows_per,
+                       (const float*)U, ldu, x, part, skip);
+  else
+    hipLaunchKernelGGL(k_lmp_gemv_t_partial<double>, grid, dim3(kLT), 0, s, nA, k, rows_per,
+                       (const double*)U, ldu, x, part, skip);
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, part, dcoef, t,
                      skip);
   return hipGetLastError();
 }
 
-hipError_t lmp_gemv_n(long long nA, int k, const double* U, long long ldu, const double* x,
+hipError_t lmp_gemv_n(long long nA, int k, const void* U, bool u32, long long ldu, const double* x,
                       double* y, const double* ws, const int* skip, hipStream_t s) {
-  const long long nch = lmp_chunks(nA);
+  if (ldu % 4 != 0) return hipErrorInvalidValue;
+  const long long nch = (nA + 4LL * kLT - 1) / (4LL * kLT);
   const double* t = ws + (size_t)lmp_t_splits(nA, k) * k;
-  hipLaunchKernelGGL(k_lmp_gemv_n, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s, nA, k, U,
-                     ldu, t, x, y, skip);
+  if (u32)
+    hipLaunchKernelGGL(k_lmp_gemv_n<float>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s, nA,
+                       k, (const float*)U, ldu, t, x, y, skip);
+  else
+    hipLaunchKernelGGL(k_lmp_gemv_n<double>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s,
+                       nA, k, (const double*)U, ldu, t, x, y, skip);
   return hipGetLastError();
 }
 

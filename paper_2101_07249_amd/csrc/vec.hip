@@ -238,6 +238,25 @@ hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, 
 }
 
 // ------------------------------------------------------------ helpers
+__global__ void k_to_f32(float* __restrict__ y, const double* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_to_f64(double* __restrict__ y, const float* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+hipError_t vec_to_f32(float* y, const double* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+hipError_t vec_to_f64(double* y, const float* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f64, dim3(2048), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+
 __global__ void k_copy(double* __restrict__ y, const double* __restrict__ x, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -354,6 +373,7 @@ hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, 
 //   u_new = U^T r_new = u - alpha (t + (U^T U) d1),  d2 = dcoef .* u_new,
 //   z = r_new + U d2.
 // k_pcg_lmp_coeffs forms d1, d2 and u_new (one workgroup).
+// 64 rows per 256-thread block, 4 threads per row splitting the k-long dot product.
 __global__ __launch_bounds__(256) void k_pcg_lmp_coeffs(const PcgState* __restrict__ st, int k,
                                                         const double* __restrict__ t,
                                                         const double* __restrict__ dcoef,
@@ -365,9 +385,15 @@ __global__ __launch_bounds__(256) void k_pcg_lmp_coeffs(const PcgState* __restri
   const double alpha = st->alpha;
   for (int c = threadIdx.x; c < k; c += blockDim.x) sd1[c] = dcoef[c] * t[c];
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    double g = 0.0;
-    for (int j = 0; j < k; ++j) g += GU[c + (size_t)j * k] * sd1[j];
+  const int c = blockIdx.x * 64 + (threadIdx.x >> 2), sub = threadIdx.x & 3;
+  double g = 0.0;
+  if (c < k) {
+#pragma unroll 4
+    for (int j = sub; j < k; j += 4) g += GU[c + (size_t)j * k] * sd1[j];
+  }
+  g += __shfl_xor(g, 1, 64);
+  g += __shfl_xor(g, 2, 64);
+  if (c < k && sub == 0) {
     const double un = u[c] - alpha * (t[c] + g);
     u[c] = un;
     d12[c] = sd1[c];
@@ -377,16 +403,31 @@ __global__ __launch_bounds__(256) void k_pcg_lmp_coeffs(const PcgState* __restri
 
 hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
                           const double* GU, double* u, double* d12, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_lmp_coeffs, dim3(1), dim3(256), sizeof(double) * k, s, st, k, t, dcoef,
-                     GU, u, d12);
+  hipLaunchKernelGGL(k_pcg_lmp_coeffs, dim3((k + 63) / 64), dim3(256), sizeof(double) * k, s, st, k,
+                     t, dcoef, GU, u, d12);
   return hipGetLastError();
 }
 
 // Dual pass: r <- r - alpha (Ap + U d1), z = r + U d2, partials of r.r into red[2 kRB ..).
-constexpr int kDE = 2;  // rows per thread
-constexpr int kDC = 8;  // columns per group
+// 4 consecutive rows per thread, 16-byte loads of U (ldu % 4 == 0).
+constexpr int kDC = 16;  // columns per group
+template <typename T>
+static __device__ inline void ld4(const T* p, double (&v)[4]);
+template <>
+__device__ inline void ld4<float>(const float* p, double (&v)[4]) {
+  const float4 f = *reinterpret_cast<const float4*>(p);
+  v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+}
+template <>
+__device__ inline void ld4<double>(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+template <typename T>
 __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict__ st, long long nA,
-                                                      int k, const double* __restrict__ U, long long ldu,
+                                                      int k, const T* __restrict__ U, long long ldu,
                                                       const double* __restrict__ d12,
                                                       const double* __restrict__ Ap,
                                                       double* __restrict__ r, double* __restrict__ z,
@@ -398,42 +439,41 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict
   for (int c = threadIdx.x; c < 2 * k; c += kRT) sd[c] = d12[c];
   __syncthreads();
   double vsum = 0.0;
-  const long long chunk = (long long)kRT * kDE;
-  for (long long r0 = (long long)blockIdx.x * chunk; r0 < nA; r0 += (long long)kRB * chunk) {
-    long long rr[kDE];
-    bool ok[kDE];
-    double aw[kDE], az[kDE];
-#pragma unroll
-    for (int e = 0; e < kDE; ++e) {
-      rr[e] = r0 + threadIdx.x + (long long)e * kRT;
-      ok[e] = rr[e] < nA;
-      aw[e] = 0.0;
-      az[e] = 0.0;
-    }
+  const long long chunk = (long long)kRT * 4;
+  for (long long rb = (long long)blockIdx.x * chunk; rb < nA; rb += (long long)kRB * chunk) {
+    const long long r0 = rb + 4LL * threadIdx.x;
+    const bool full = r0 + 4 <= nA;
+    double aw[4] = {0.0, 0.0, 0.0, 0.0}, az[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c0 = 0; c0 < k; c0 += kDC) {
-      double uv[kDC][kDE];
+      double uv[kDC][4];
 #pragma unroll
-      for (int c = 0; c < kDC; ++c)
+      for (int c = 0; c < kDC; ++c) {
+        if (c0 + c < k && full) {
+          ld4<T>(U + (size_t)(c0 + c) * ldu + r0, uv[c]);
+        } else {
 #pragma unroll
-        for (int e = 0; e < kDE; ++e)
-          uv[c][e] = (c0 + c < k && ok[e]) ? U[(size_t)(c0 + c) * ldu + rr[e]] : 0.0;
+          for (int e = 0; e < 4; ++e)
+            uv[c][e] = (c0 + c < k && r0 + e < nA) ? (double)U[(size_t)(c0 + c) * ldu + r0 + e] : 0.0;
+        }
+      }
 #pragma unroll
       for (int c = 0; c < kDC; ++c) {
         const double t1 = (c0 + c < k) ? sd[c0 + c] : 0.0;
         const double t2 = (c0 + c < k) ? sd[k + c0 + c] : 0.0;
 #pragma unroll
-        for (int e = 0; e < kDE; ++e) {
+        for (int e = 0; e < 4; ++e) {
           aw[e] += uv[c][e] * t1;
           az[e] += uv[c][e] * t2;
         }
       }
     }
 #pragma unroll
-    for (int e = 0; e < kDE; ++e) {
-      if (ok[e]) {
-        const double rn = r[rr[e]] - alpha * (Ap[rr[e]] + aw[e]);
-        r[rr[e]] = rn;
-        z[rr[e]] = rn + az[e];
+    for (int e = 0; e < 4; ++e) {
+      if (r0 + e < nA) {
+        const long long i = r0 + e;
+        const double rn = r[i] - alpha * (Ap[i] + aw[e]);
+        r[i] = rn;
+        z[i] = rn + az[e];
         vsum += rn * rn;
       }
     }
@@ -457,11 +497,16 @@ hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_lmp_dual, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st, nA, k, U,
-                     ldu, d12, Ap, r, z, red);
+  if (ldu % 4 != 0) return hipErrorInvalidValue;
+  if (u32)
+    hipLaunchKernelGGL(k_pcg_lmp_dual<float>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st, nA,
+                       k, (const float*)U, ldu, d12, Ap, r, z, red);
+  else
+    hipLaunchKernelGGL(k_pcg_lmp_dual<double>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st,
+                       nA, k, (const double*)U, ldu, d12, Ap, r, z, red);
   hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }

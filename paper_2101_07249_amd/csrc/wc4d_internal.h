@@ -42,12 +42,28 @@ hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long 
                     ColMap emap, const int* skip, hipStream_t s, double* ws = nullptr,
                     size_t ws_doubles = 0);
 
+// Two-segment few-column product (both n1, n2 <= 112): C(:, c1(t)) = A1 B(:, b1(t)) [+ E]
+// for t < n1 and C(:, c2(t)) = A2 B(:, b2(t)) [+ E] for t < n2, A1 / A2 M x K with lda = M,
+// one split-K launch plus one reduction.  ws: dsqrt2_ws_doubles(M, n1, n2, K).
+size_t dsqrt2_ws_doubles(int M, int n1, int n2, int K);
+hipError_t dsqrt2_f64(int M, int K, const double* B, double* C, const double* E, const double* A1,
+                      ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2, ColMap c2,
+                      ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles, hipStream_t s);
+
 // G(i, j) = sum_k X(k, i) Y(k, j), i < m1, j < m2, k < K; X / Y columns via maps.
 // Deterministic split-K: partial tiles then a fixed-order sum.  G column-major, ldg.
 // ws must hold gram_ws_doubles(m1, m2, K) doubles.
 size_t gram_ws_doubles(int m1, int m2, long long K);
 hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, const double* Y,
                     ColMap ymap, double* G, int ldg, double* ws, const int* skip, hipStream_t s);
+
+// Split-bfloat16 GEMM (see gemm_bf16x3.hip): C(:, t) = alpha S B(:, t) [+ E(:, t)] with S
+// given as row-major bf16 hi/lo parts (row i = S(i, 0..K-1)).
+hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16* Shi, __bf16* Slo,
+                           hipStream_t s);
+hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
+                       const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                       ColMap emap, hipStream_t s);
 
 // Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
 struct SweepModel {
@@ -101,10 +117,11 @@ hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double
 // ws: lmp_gemv_ws_doubles(nA, k).
 size_t lmp_gemv_ws_doubles(long long nA, int k);
 size_t lmp_gemv_t_offset(long long nA, int k);
-hipError_t lmp_gemv_t(long long nA, int k, const double* U, long long ldu, const double* dcoef,
-                      const double* x, double* ws, const int* skip, hipStream_t s,
-                      double* tout = nullptr);
-hipError_t lmp_gemv_n(long long nA, int k, const double* U, long long ldu, const double* x,
+// U is float64, or float32 when u32 is true (then pass the float array as U).
+hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
+                      const double* dcoef, const double* x, double* ws, const int* skip,
+                      hipStream_t s, double* tout = nullptr);
+hipError_t lmp_gemv_n(long long nA, int k, const void* U, bool u32, long long ldu, const double* x,
                       double* y, const double* ws, const int* skip, hipStream_t s);
 
 // Vector kernels for PCG and the LMP (n_A long).
@@ -133,7 +150,7 @@ hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
 // d2 = dcoef.*u into d12 (2k); then the dual pass updating r, writing z, and beta.
 hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
                           const double* GU, double* u, double* d12, hipStream_t s);
-hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s);
 // Decide whether u = U^T r is recomputed this iteration (st->no_refresh = 0 when
@@ -144,6 +161,8 @@ hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef,
 hipError_t stash_from_innov(const double* d, const double* rinv, double* stash, int q,
                             hipStream_t s);
 hipError_t vec_fill(double* y, double v, long long n, hipStream_t s);
+hipError_t vec_to_f32(float* y, const double* x, long long n, hipStream_t s);
+hipError_t vec_to_f64(double* y, const float* x, long long n, hipStream_t s);
 hipError_t pcg_x0_zero_flag(const double* x, long long n, double* red, int* flag, hipStream_t s);
 hipError_t pcg_s0(const double* b, const double* Ax, const int* xzero, double* s0, long long n,
                   hipStream_t s);
@@ -162,6 +181,7 @@ enum ProfClass {
   PROF_LMP_T,       // U^T x pass of a single-vector LMP application
   PROF_LMP_N,       // x + U t pass of a single-vector LMP application
   PROF_BUILD,       // orthonormalisation, Gram, small dense and Ritz-vector kernels of a build
+  PROF_DSQRT_BF16,  // split-bf16 D^{1/2} products (flops counted as the 3 bf16 products)
   PROF_NCLASS
 };
 
@@ -186,6 +206,10 @@ struct wc4d_problem_s {
   // device data
   double* dB = nullptr;
   double* dQ = nullptr;
+  __bf16* dBhi = nullptr;  // split-bf16 B^{1/2}, Q^{1/2} (row-major), when prec has BF16X3
+  __bf16* dBlo = nullptr;
+  __bf16* dQhi = nullptr;
+  __bf16* dQlo = nullptr;
   double* dStages = nullptr;
   int* dObsOff = nullptr;
   int* dObsIdx = nullptr;
@@ -199,6 +223,7 @@ struct wc4d_problem_s {
   size_t wsGramDoubles = 0;
   double* wsSplit = nullptr;  // split-K partials of the few-column D^{1/2} products
   size_t wsSplitDoubles = 0;
+
   // LMP build scratch: two n_A x cap blocks and m x m matrices
   double* bufA = nullptr;
   double* bufB = nullptr;
@@ -232,6 +257,7 @@ struct wc4d_problem_s {
 struct wc4d_lmp_s {
   wc4d_problem p = nullptr;
   long long nA = 0;
+  long long ldu = 0;        // leading dimension of U and U32: n_A rounded up to 4
   int k = 0;
   int applies = 0;
   double* U = nullptr;      // n_A x k
@@ -243,6 +269,7 @@ struct wc4d_lmp_s {
   size_t wsDoubles = 0;
   double* wsv = nullptr;    // single-vector workspace
   size_t wsvDoubles = 0;
-  double* GU = nullptr;     // k x k: U^T U (fused PCG)
+  float* U32 = nullptr;     // float32 copy of U (WC4D_PREC_LMP_FP32)
+  double* GU = nullptr;     // k x k: U^T U of the U the PCG streams
   double* fu = nullptr;     // 3 k: u = U^T r, d1, d2 (fused PCG)
 };

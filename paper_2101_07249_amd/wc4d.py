@@ -26,7 +26,7 @@ REVD, NYSTROM, RITZIT = 0, 1, 2
 METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
 RES_TRUE, RES_PRECOND = 0, 1
 PCG_FUSED, PCG_PLAIN = 0, 1
-PREC_FP64 = 0
+PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32 = 0, 1, 2
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -61,6 +61,8 @@ _SIGS = {
     "wc4d_finalize": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "wc4d_dims": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
     "wc4d_apply_A": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_apply_A_prec": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _vp]),
     "wc4d_apply_Linv": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_apply_LinvT": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_apply_Dsqrt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
@@ -253,7 +255,7 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, pattern, x0: Optional[np.ndarray] = None, device: int = 0,
-                      sigma_o2: Optional[float] = None) -> "Problem":
+                      sigma_o2: Optional[float] = None, prec: int = PREC_FP64) -> "Problem":
         """Set up a problem from workload parameters with the library's own helpers
         (covariance square roots, Lorenz-96 trajectory)."""
         p = cls(w.n, w.N, device)
@@ -269,7 +271,7 @@ class Problem:
         s2 = w.sigma_o2 if sigma_o2 is None else sigma_o2
         for i, idx in pattern:
             p.set_obs(i, idx, np.full(len(idx), s2))
-        p.finalize()
+        p.finalize(prec)
         return p
 
     # ---- operator
@@ -289,6 +291,16 @@ class Problem:
 
     def apply_A(self, X, Y=None, stream=None):
         return self._block_call(lib().wc4d_apply_A, X, Y, stream, "apply_A")
+
+    def apply_A_prec(self, X, prec: int, Y=None, stream=None):
+        import torch
+        X2 = X.view(1, -1) if X.dim() == 1 else X
+        if Y is None:
+            Y = torch.empty_like(X)
+        Y2 = Y.view(1, -1) if Y.dim() == 1 else Y
+        self._chk(lib().wc4d_apply_A_prec(self._h, _tptr(X2), self.n_A, _tptr(Y2), self.n_A, X2.shape[0],
+                                          int(prec), _stream(stream)), "apply_A_prec")
+        return Y
 
     def apply_Linv(self, X, Y=None, stream=None):
         return self._block_call(lib().wc4d_apply_Linv, X, Y, stream, "apply_Linv")
@@ -336,7 +348,8 @@ class Problem:
             out.update(hist_true=ht[:k], hist_precond=hp[:k], hist_J=hj[:k])
         return out
 
-    PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other")
+    PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other",
+                    "dsqrt_bf16x3")
 
     def prof_enable(self, enable: bool = True):
         self._chk(lib().wc4d_prof_enable(self._h, int(bool(enable))), "prof_enable")
