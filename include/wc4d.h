@@ -219,13 +219,90 @@ int wc4d_last_apply_timing(wc4d_problem p, float* ms4);
  * 1 forward sweep (+ observation gather), 2 adjoint sweep (+ scatter), 3 the U^T x
  * pass and 4 the x + U t pass of a single-vector LMP application, 5 the other
  * kernels of an LMP build, 6 the split-bfloat16 D^{1/2} products (flops counted as
- * the three bfloat16 products).  wc4d_prof_enable resets the totals;
+ * the three bfloat16 products), 7 the learned-sketch network's inference (features and
+ * convolutions; flops of the convolutions).  wc4d_prof_enable resets the totals;
  * wc4d_prof_read waits for the recorded work and reports one class. */
 enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC4D_PROF_LMP_T = 3,
-       WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_DSQRT_BF16 = 6, WC4D_PROF_NCLASS = 7 };
+       WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_DSQRT_BF16 = 6,
+       WC4D_PROF_NET = 7, WC4D_PROF_NCLASS = 8 };
 int wc4d_prof_enable(wc4d_problem p, int enable);
 int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
                    double* flops);
+
+/* ------------------------------------------------------- learned sketch -- */
+/* The randomised eigendecompositions of Section 4 (Algorithms 3-5) start from a
+ * Gaussian block G.  The sketch network replaces it by a block shaped to the problem:
+ * per time level i, a periodic 1-D convolution net along the grid axis j with
+ *   input channels  0..nz-1   the Gaussian block itself, Omega[i n + j, c];
+ *                   nz        (x_i(j) - 2.3) / 3.6 of a Lorenz-96 trajectory (else 0);
+ *                   nz + 1    1 where point j is observed at time i (Section 2.1, H_i);
+ *                   nz + 2    i / N;
+ *                   nz + 3    exp(-(t_next - i) / 5), t_next the first observed time >= i
+ *                             (0 when there is none);
+ *   layers          l = 1..L: H_l[c, j] = b_l[c] + sum_{c', t = -2..2} W_l[c, c', t + 2]
+ *                   A_{l-1}[c', (j + t) mod n], A_l = tanh(H_l) for l < L;
+ *   output          G[i n + j, c] = H_L[c, j], c < 64 (the 64-column start block).
+ * Weights, biases and activations are float16 (weights rounded from a float32 master
+ * copy), products accumulate in float32 on the matrix cores, G is float64.
+ * Parameter vectors (host float32) are ordered per layer: W_l (c_out, c_in, t)
+ * row-major, then b_l.  Training minimises the capture loss below with Adam.
+ * Without a trained network the Gaussian block is the sketch (the fallback). */
+typedef struct wc4d_sketchnet_s* wc4d_sketchnet;
+
+/* layers in [2, 8], channels must be 64, width must be 5, noise_channels (nz) in
+ * [0, 92].  Parameters start at zero (set them with wc4d_sketchnet_set_params). */
+int wc4d_sketchnet_create(wc4d_sketchnet* out, int layers, int channels, int width, int noise_channels,
+                          int device);
+int wc4d_sketchnet_destroy(wc4d_sketchnet net);
+const char* wc4d_sketchnet_last_error(wc4d_sketchnet net);
+int wc4d_sketchnet_nparams(wc4d_sketchnet net, long long* count);
+/* Host float32 parameter vectors (count = wc4d_sketchnet_nparams).  set_params also
+ * resets the Adam moments and step count.  Synchronous. */
+int wc4d_sketchnet_set_params(wc4d_sketchnet net, const float* theta);
+int wc4d_sketchnet_get_params(wc4d_sketchnet net, float* theta);
+/* Gradient of the last backward pass (unscaled), or one set by the caller. */
+int wc4d_sketchnet_get_grad(wc4d_sketchnet net, float* grad);
+int wc4d_sketchnet_set_grad(wc4d_sketchnet net, const float* grad);
+
+/* G (device n_A x 64, ldg >= n_A) = net(features of p, Omega); Omega: device n_A x nz
+ * float64 (ldo >= n_A), the Gaussian block.  Keeps the activations for a following
+ * wc4d_sketchnet_backward.  p must be finalized. */
+int wc4d_sketchnet_infer(wc4d_sketchnet net, wc4d_problem p, const double* Omega, int ldo, double* G,
+                         int ldg, hipStream_t s);
+/* Gradient with respect to the parameters of sum(dG .* G) for the last inference
+ * (dG device n_A x 64).  dG is scaled by a power of two into float16 range for the
+ * backward convolutions and the gradient unscaled in float32. */
+int wc4d_sketchnet_backward(wc4d_sketchnet net, const double* dG, int lddg, hipStream_t s);
+/* One Adam step (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8) with the current
+ * gradient and learning rate lr. */
+int wc4d_sketchnet_adam(wc4d_sketchnet net, double lr, hipStream_t s);
+/* Capture loss of a start block G (device n_A x m, m <= 512) against reference Ritz
+ * pairs (U device n_A x k with ldu, theta device k, theta > 1): with Y = A G,
+ * S = Y^T Y, w = 1 - 1/theta and P_w = U diag(w) U^T,
+ *     f = -trace(S^{-1} Y^T P_w Y) / sum(w),
+ * the weighted share of range(U) captured by range(Y), the block the algorithms
+ * orthonormalise.  Writes f (device double) and dG = df/dG = A (2 / sum w)
+ * (Y S^{-1} T S^{-1} - P_w Y S^{-1}), T = Y^T P_w Y (device n_A x m, lddg), using
+ * the symmetry of A.  Synchronous only on error checks: returns WC4D_ENOTSPD
+ * when S is singular (checked after the call's work completes). */
+int wc4d_sketch_loss(wc4d_problem p, const double* G, int ldg, int m, const double* U, int ldu,
+                     const double* theta, int k, double* f, double* dG, int lddg, hipStream_t s);
+/* One training step on problem p: G = net(p, Omega), the capture loss against the
+ * first k Ritz pairs of the reference LMP ref (built on p from a wider sketch), the
+ * backward pass and an Adam step with rate lr.  *loss (host, may be NULL) receives f
+ * at the step's parameters.  Synchronous. */
+int wc4d_sketchnet_train_step(wc4d_sketchnet net, wc4d_problem p, const double* Omega, int ldo,
+                              wc4d_lmp ref, int k, double lr, double* loss, hipStream_t s);
+/* LMP build from the learned sketch: G = net(p, Omega) (requires k_r + l = 64 and nz =
+ * 64), then wc4d_lmp_build; if that finds the block rank deficient (WC4D_ENOTSPD), or
+ * net is NULL, the build uses the Gaussian block Omega itself.  *used_net (may be
+ * NULL) tells which. */
+int wc4d_lmp_build_sketch(wc4d_problem p, wc4d_sketchnet net, int method, int k_r, int l,
+                          const double* Omega, wc4d_lmp* out, int* used_net, hipStream_t s);
+/* Save / load the parameters (binary: "WC4DSKN1", int32 layers, channels, width,
+ * noise_channels, int64 count, float32 parameters). */
+int wc4d_sketchnet_save(wc4d_sketchnet net, const char* path);
+int wc4d_sketchnet_load(wc4d_sketchnet* out, const char* path, int device);
 
 #ifdef __cplusplus
 }

@@ -10,113 +10,13 @@
 #include <string>
 #include <vector>
 
-#include "wc4d_internal.h"
+#include "abi_common.h"
 
 using namespace wc4d;
 
 namespace {
 
 constexpr int kVersion = 100;  // 0.1.0
-
-int fail(wc4d_problem p, int code, const std::string& msg) {
-  if (p != nullptr) p->err = msg;
-  return code;
-}
-
-struct DevGuard {
-  int prev = -1;
-  bool changed = false;
-  explicit DevGuard(int d) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != d) {
-      changed = (hipSetDevice(d) == hipSuccess);
-    }
-  }
-  ~DevGuard() {
-    if (changed) (void)hipSetDevice(prev);
-  }
-};
-
-#define HIPCHK(p, call)                                                                         \
-  do {                                                                                          \
-    hipError_t e_ = (call);                                                                     \
-    if (e_ != hipSuccess)                                                                       \
-      return fail((p), WC4D_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
-  } while (0)
-
-template <class T>
-int dev_alloc(wc4d_problem p, T** ptr, size_t count) {
-  if (*ptr != nullptr) {
-    (void)hipFree(*ptr);
-    *ptr = nullptr;
-  }
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
-  if (e != hipSuccess) {
-    *ptr = nullptr;
-    return fail(p, WC4D_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
-                                    " bytes failed: " + hipGetErrorString(e));
-  }
-  return WC4D_OK;
-}
-
-template <class T>
-void dev_free(T** ptr) {
-  if (*ptr != nullptr) (void)hipFree(*ptr);
-  *ptr = nullptr;
-}
-
-int ensure_block(wc4d_problem p, long long m) {
-  if (p->wsBlockCols >= m && p->wsStashCols >= m) return WC4D_OK;
-  int rc = dev_alloc(p, &p->wsBlock, (size_t)p->nA * m);
-  if (rc) return rc;
-  p->wsBlockCols = m;
-  rc = dev_alloc(p, &p->wsStash, (size_t)std::max(p->q, 1) * m);
-  if (rc) return rc;
-  p->wsStashCols = m;
-  return WC4D_OK;
-}
-
-int ensure_gram(wc4d_problem p, size_t doubles) {
-  if (p->wsGramDoubles >= doubles) return WC4D_OK;
-  int rc = dev_alloc(p, &p->wsGram, doubles);
-  if (rc) return rc;
-  p->wsGramDoubles = doubles;
-  return WC4D_OK;
-}
-
-bool is_state_ok(wc4d_problem p) { return p != nullptr && p->finalized; }
-
-// ---- per-class kernel timing: an event pair around each timed launch group
-hipEvent_t prof_event(wc4d_problem p) {
-  if (p->evnext == p->evpool.size()) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    p->evpool.push_back(e);
-  }
-  return p->evpool[p->evnext++];
-}
-
-struct ProfScope {
-  wc4d_problem p;
-  hipStream_t s;
-  int cls;
-  double bytes, flops;
-  hipEvent_t a = nullptr;
-  ProfScope(wc4d_problem p_, hipStream_t s_, int cls_, double bytes_, double flops_)
-      : p(p_), s(s_), cls(cls_), bytes(bytes_), flops(flops_) {
-    if (p->kprof) {
-      a = prof_event(p);
-      if (a != nullptr) (void)hipEventRecord(a, s);
-    }
-  }
-  ~ProfScope() {
-    if (a == nullptr) return;
-    hipEvent_t b = prof_event(p);
-    if (b == nullptr) return;
-    (void)hipEventRecord(b, s);
-    p->recs.push_back(ProfRec{cls, a, b, bytes, flops});
-  }
-};
 
 int prof_collect(wc4d_problem p) {
   if (p->recs.empty()) return WC4D_OK;
@@ -220,6 +120,8 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->dQhi);
   dev_free(&p->dQlo);
   dev_free(&p->dStages);
+  dev_free(&p->dTraj);
+  dev_free(&p->lossWs);
   dev_free(&p->dObsOff);
   dev_free(&p->dObsIdx);
   dev_free(&p->dObsRinv);
@@ -401,6 +303,8 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
       l96_stage_inputs(p->traj.data() + (size_t)i * n, n, p->F, p->dt, stages.data() + (size_t)i * 4 * n);
     if ((rc = dev_alloc(p, &p->dStages, stages.size()))) return rc;
     HIPCHK(p, hipMemcpyAsync(p->dStages, stages.data(), sizeof(double) * stages.size(), hipMemcpyHostToDevice, s));
+    if ((rc = dev_alloc(p, &p->dTraj, p->traj.size()))) return rc;
+    HIPCHK(p, hipMemcpyAsync(p->dTraj, p->traj.data(), sizeof(double) * p->traj.size(), hipMemcpyHostToDevice, s));
   }
   // LDS the sweeps need must fit the device
   int maxLds = 0;
@@ -510,9 +414,23 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
   return WC4D_OK;
 }
 
+int check_block_args(wc4d_problem p, const void* X, int ldx, const void* Y, int ldy, int m) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (X == nullptr || Y == nullptr || m < 1 || ldx < p->nA || ldy < p->nA)
+    return fail(p, WC4D_EINVAL, "invalid block arguments (null pointer, m < 1 or ld < n_A)");
+  const char* xb = (const char*)X;
+  const char* yb = (const char*)Y;
+  const size_t xs = sizeof(double) * ((size_t)ldx * (m - 1) + p->nA);
+  const size_t ys = sizeof(double) * ((size_t)ldy * (m - 1) + p->nA);
+  if (xb < yb + ys && yb < xb + xs) return fail(p, WC4D_EINVAL, "X and Y overlap");
+  return WC4D_OK;
+}
+
+}  // namespace
+
 // Y = A X using the problem's block workspace (must hold m columns).
-int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
-                 const int* skip, hipStream_t s, bool mixed = false) {
+int wc4d::apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy,
+                       int m, const int* skip, hipStream_t s, bool mixed) {
   const long long nA = p->nA;
   if (p->q == 0) {
     HIPCHK(p, block_copy(Y, ldy, X, ldx, nA, m, s));
@@ -551,20 +469,6 @@ int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long
   if (p->prof) HIPCHK(p, hipEventRecord(p->ev[4], s));
   return WC4D_OK;
 }
-
-int check_block_args(wc4d_problem p, const void* X, int ldx, const void* Y, int ldy, int m) {
-  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
-  if (X == nullptr || Y == nullptr || m < 1 || ldx < p->nA || ldy < p->nA)
-    return fail(p, WC4D_EINVAL, "invalid block arguments (null pointer, m < 1 or ld < n_A)");
-  const char* xb = (const char*)X;
-  const char* yb = (const char*)Y;
-  const size_t xs = sizeof(double) * ((size_t)ldx * (m - 1) + p->nA);
-  const size_t ys = sizeof(double) * ((size_t)ldy * (m - 1) + p->nA);
-  if (xb < yb + ys && yb < xb + xs) return fail(p, WC4D_EINVAL, "X and Y overlap");
-  return WC4D_OK;
-}
-
-}  // namespace
 
 extern "C" {
 
@@ -633,9 +537,7 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
 
 // ------------------------------------------------------------ LMP build
 
-namespace {
-
-int ensure_build(wc4d_problem p, int m) {
+int wc4d::ensure_build(wc4d_problem p, int m) {
   int rc;
   if (p->bufCols < m) {
     if ((rc = dev_alloc(p, &p->bufA, (size_t)(p->nA + 4) * m))) return rc;
@@ -650,6 +552,9 @@ int ensure_build(wc4d_problem p, int m) {
   if ((rc = ensure_gram(p, gram_ws_doubles(m, m, p->nA)))) return rc;
   return WC4D_OK;
 }
+
+
+namespace {
 
 struct Small {
   double *G, *R1, *Ri, *R2, *K, *V, *lam;

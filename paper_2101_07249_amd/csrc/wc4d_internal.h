@@ -169,6 +169,30 @@ hipError_t pcg_s0(const double* b, const double* Ax, const int* xzero, double* s
 hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, long long rows,
                       int cols, hipStream_t s);
 
+// Learned sketch network (sketchnet.hip).  fp16 = _Float16; layouts there.
+hipError_t net_features(int n, int N, const double* traj, const int* obs_off, const int* obs_idx,
+                        const double* Om, long long ldo, int nz, int cp0, _Float16* X0, hipStream_t s);
+size_t net_conv_lds_bytes(int cp);
+hipError_t net_conv_hidden(int n, int T, int cp, const _Float16* X, const _Float16* W, const _Float16* b,
+                           _Float16* H, hipStream_t s);
+hipError_t net_conv_out(int n, int T, int cp, const _Float16* X, const _Float16* W, const _Float16* b,
+                        double* G, long long ldg, hipStream_t s);
+hipError_t net_conv_bwd_data(int n, int T, const _Float16* dH, const _Float16* Wt, const _Float16* Aprev,
+                             _Float16* dHprev, hipStream_t s);
+int net_wgrad_blocks(int n, int T);
+hipError_t net_wgrad(int n, int T, int cp, const _Float16* X, const _Float16* dH, float* part, hipStream_t s);
+hipError_t net_reduce(int nb, int len, const float* part, const float* scal, float* grad, hipStream_t s);
+size_t net_scale_ws_doubles();
+hipError_t net_loss_scale(long long P, const double* dG, long long ldg, double* ws, float* scal,
+                          _Float16* dH, hipStream_t s);
+hipError_t net_adam(long long len, float* th, float* m, float* v, const float* g, float lr, float b1, float b2,
+                    float eps, float c1, float c2, _Float16* w16, hipStream_t s);
+hipError_t net_to_f16(long long len, const float* th, _Float16* w16, hipStream_t s);
+hipError_t net_pack_t(const _Float16* W, _Float16* Wt, hipStream_t s);
+hipError_t loss_weights(int k, const double* theta, double* w, double* sums, hipStream_t s);
+hipError_t loss_finish(int m, int k, const double* Sinv, const double* Tm, const double* sums, double* f,
+                       double* M1, double* M2, hipStream_t s);
+
 }  // namespace wc4d
 
 // ------------------------------------------------------------------- handles
@@ -182,6 +206,7 @@ enum ProfClass {
   PROF_LMP_N,       // x + U t pass of a single-vector LMP application
   PROF_BUILD,       // orthonormalisation, Gram, small dense and Ritz-vector kernels of a build
   PROF_DSQRT_BF16,  // split-bf16 D^{1/2} products (flops counted as the 3 bf16 products)
+  PROF_NET,         // learned-sketch network inference (features + convolutions)
   PROF_NCLASS
 };
 
@@ -211,6 +236,7 @@ struct wc4d_problem_s {
   __bf16* dQhi = nullptr;
   __bf16* dQlo = nullptr;
   double* dStages = nullptr;
+  double* dTraj = nullptr;  // l96: (N+1) x n trajectory (sketch-network features)
   int* dObsOff = nullptr;
   int* dObsIdx = nullptr;
   double* dObsRinv = nullptr;
@@ -230,7 +256,10 @@ struct wc4d_problem_s {
   long long bufCols = 0;
   double* small = nullptr;  // 6 m x m + 2 m doubles
   int smallM = 0;
-  int* dStatus = nullptr;   // device status words
+  int* dStatus = nullptr;   // device status words (0 build Cholesky, 1 PCG x0 == 0,
+                            // 4-5 Jacobi control, 8 capture-loss Cholesky)
+  double* lossWs = nullptr; // capture-loss small matrices
+  size_t lossWsDoubles = 0;
   // PCG vectors and state
   double* pcgVec = nullptr;  // 6 n_A
   double* pcgHist = nullptr;

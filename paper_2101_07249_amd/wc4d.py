@@ -30,6 +30,7 @@ PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32 = 0, 1, 2
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_c_flt_p = ctypes.POINTER(ctypes.c_float)
 _vp = ctypes.c_void_p
 
 
@@ -81,6 +82,26 @@ _SIGS = {
     "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
                                       _c_dbl_p, _c_dbl_p]),
     "wc4d_last_apply_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "wc4d_sketchnet_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int]),
+    "wc4d_sketchnet_destroy": (ctypes.c_int, [_vp]),
+    "wc4d_sketchnet_last_error": (ctypes.c_char_p, [_vp]),
+    "wc4d_sketchnet_nparams": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_longlong)]),
+    "wc4d_sketchnet_set_params": (ctypes.c_int, [_vp, _c_flt_p]),
+    "wc4d_sketchnet_get_params": (ctypes.c_int, [_vp, _c_flt_p]),
+    "wc4d_sketchnet_get_grad": (ctypes.c_int, [_vp, _c_flt_p]),
+    "wc4d_sketchnet_set_grad": (ctypes.c_int, [_vp, _c_flt_p]),
+    "wc4d_sketchnet_infer": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _vp]),
+    "wc4d_sketchnet_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
+    "wc4d_sketchnet_adam": (ctypes.c_int, [_vp, ctypes.c_double, _vp]),
+    "wc4d_sketch_loss": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp,
+                                        ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]),
+    "wc4d_sketchnet_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int,
+                                                 ctypes.c_double, _c_dbl_p, _vp]),
+    "wc4d_lmp_build_sketch": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                                             ctypes.POINTER(_vp), _c_int_p, _vp]),
+    "wc4d_sketchnet_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "wc4d_sketchnet_load": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_char_p, ctypes.c_int]),
 }
 
 _lib = None
@@ -328,6 +349,30 @@ class Problem:
                                        _stream(stream)), "lmp_build")
         return Lmp(h.value, self, int(k_r))
 
+    def lmp_build_sketch(self, net: Optional["SketchNet"], method, k_r: int, l: int, Omega, stream=None):
+        """LMP from the learned sketch net(self, Omega), or from Omega itself when net is
+        None or the learned block is rank deficient.  Returns (Lmp, used_net)."""
+        meth = METHOD[method] if isinstance(method, str) else int(method)
+        h = _vp()
+        used = ctypes.c_int(0)
+        self._chk(lib().wc4d_lmp_build_sketch(self._h, net._h if net is not None else None, meth, int(k_r),
+                                              int(l), _tptr(Omega), ctypes.byref(h), ctypes.byref(used),
+                                              _stream(stream)), "lmp_build_sketch")
+        return Lmp(h.value, self, int(k_r)), bool(used.value)
+
+    def sketch_loss(self, G, U, theta, dG=None, stream=None):
+        """Capture loss f of the start block G (m, n_A) against Ritz pairs U (k, n_A),
+        theta (k,) (device tensors); returns (f as a 1-element tensor, dG)."""
+        import torch
+        if dG is None:
+            dG = torch.empty_like(G)
+        f = torch.empty(1, dtype=torch.float64, device=self.torch_device)
+        k = U.shape[0]
+        self._chk(lib().wc4d_sketch_loss(self._h, _tptr(G), self.n_A, G.shape[0], _tptr(U), self.n_A,
+                                         _tptr(theta), k, _tptr(f), _tptr(dG), self.n_A, _stream(stream)),
+                  "sketch_loss")
+        return f, dG
+
     def pcg(self, b, x, lmp: Optional[Lmp] = None, tol: float = 1e-6, maxit: int = 100,
             criterion: int = RES_TRUE, history: bool = True, variant: int = PCG_FUSED, stream=None):
         opts = PcgOpts(float(tol), int(maxit), int(criterion), int(variant))
@@ -349,7 +394,7 @@ class Problem:
         return out
 
     PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other",
-                    "dsqrt_bf16x3")
+                    "dsqrt_bf16x3", "sketch_net")
 
     def prof_enable(self, enable: bool = True):
         self._chk(lib().wc4d_prof_enable(self._h, int(bool(enable))), "prof_enable")
@@ -375,6 +420,95 @@ class Problem:
     def close(self):
         if getattr(self, "_h", None):
             lib().wc4d_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SketchNet:
+    """Learned sketch network (see include/wc4d.h): parameters live on the GPU, training
+    and inference run in the library's kernels."""
+
+    def __init__(self, layers: int = 4, noise_channels: int = 64, device: int = 0, _handle=None):
+        if _handle is None:
+            h = _vp()
+            rc = lib().wc4d_sketchnet_create(ctypes.byref(h), int(layers), 64, 5, int(noise_channels), int(device))
+            if rc:
+                raise Wc4dError(rc, "wc4d_sketchnet_create")
+            _handle = h.value
+        self._h = _handle
+        self.device = int(device)
+        c = ctypes.c_longlong()
+        lib().wc4d_sketchnet_nparams(self._h, ctypes.byref(c))
+        self.nparams = c.value
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "SketchNet":
+        h = _vp()
+        rc = lib().wc4d_sketchnet_load(ctypes.byref(h), os.fsencode(path), int(device))
+        if rc:
+            raise Wc4dError(rc, f"wc4d_sketchnet_load({path})")
+        return cls(device=device, _handle=h.value)
+
+    def _chk(self, rc: int, what: str):
+        if rc != OK:
+            msg = lib().wc4d_sketchnet_last_error(self._h) if self._h else b""
+            raise Wc4dError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def save(self, path: str):
+        self._chk(lib().wc4d_sketchnet_save(self._h, os.fsencode(path)), "save")
+
+    def _vec(self, fn, what, src=None) -> np.ndarray:
+        if src is None:
+            out = np.empty(self.nparams, dtype=np.float32)
+            self._chk(fn(self._h, out.ctypes.data_as(_c_flt_p)), what)
+            return out
+        a = np.ascontiguousarray(src, dtype=np.float32)
+        if a.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters")
+        self._chk(fn(self._h, a.ctypes.data_as(_c_flt_p)), what)
+        return a
+
+    def set_params(self, theta):
+        self._vec(lib().wc4d_sketchnet_set_params, "set_params", theta)
+
+    def get_params(self) -> np.ndarray:
+        return self._vec(lib().wc4d_sketchnet_get_params, "get_params")
+
+    def get_grad(self) -> np.ndarray:
+        return self._vec(lib().wc4d_sketchnet_get_grad, "get_grad")
+
+    def set_grad(self, g):
+        self._vec(lib().wc4d_sketchnet_set_grad, "set_grad", g)
+
+    def infer(self, prob: "Problem", Omega, G=None, stream=None):
+        import torch
+        if G is None:
+            G = torch.empty((64, prob.n_A), dtype=torch.float64, device=prob.torch_device)
+        op = _tptr(Omega) if Omega is not None else None
+        self._chk(lib().wc4d_sketchnet_infer(self._h, prob._h, op, prob.n_A, _tptr(G), prob.n_A, _stream(stream)),
+                  "infer")
+        return G
+
+    def backward(self, dG, stream=None):
+        self._chk(lib().wc4d_sketchnet_backward(self._h, _tptr(dG), dG.shape[-1], _stream(stream)), "backward")
+
+    def adam(self, lr: float, stream=None):
+        self._chk(lib().wc4d_sketchnet_adam(self._h, float(lr), _stream(stream)), "adam")
+
+    def train_step(self, prob: "Problem", Omega, ref: Lmp, k: int, lr: float, stream=None) -> float:
+        loss = ctypes.c_double(0.0)
+        self._chk(lib().wc4d_sketchnet_train_step(self._h, prob._h, _tptr(Omega), prob.n_A, ref._h, int(k),
+                                                  float(lr), ctypes.byref(loss), _stream(stream)), "train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().wc4d_sketchnet_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -196,3 +196,20 @@ def random_block(rows: int, cols: int, seed: int, instance: int = 0) -> np.ndarr
 
 
 __all__.append("random_block")
+
+
+def sketchnet_init(layers: int = 4, noise_channels: int = 64, seed: int = 7000, channels: int = 64,
+                   width: int = 5) -> np.ndarray:
+    """Initial parameters of the sketch network, float32, in the library's order (per
+    layer W (c_out, c_in, t) row-major, then the bias): W ~ N(0, 1/(c_in width)), b = 0."""
+    rng = rng_for(seed, "net")
+    parts = []
+    cin = noise_channels + 4
+    for _ in range(layers):
+        parts.append(rng.standard_normal(channels * cin * width) / np.sqrt(cin * width))
+        parts.append(np.zeros(channels))
+        cin = channels
+    return np.concatenate(parts).astype(np.float32)
+
+
+__all__.append("sketchnet_init")

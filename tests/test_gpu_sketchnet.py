@@ -1,0 +1,218 @@
+"""GPU parity of the learned sketch (network inference, backward, Adam, capture loss)
+against the FP64 CPU oracle, plus training and fallback behaviour.
+
+Tolerances: the network runs in float16 with float32 accumulation, so inference is
+checked to 5e-3 relative (Frobenius) and gradients to cosine >= 0.999 and 1e-2
+relative; Adam runs on float32 master weights (1e-5 relative); the capture loss is
+float64 end to end (1e-9 relative)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sketchnet_oracle as S
+from oracle import wc4d_oracle as O
+from synthetic import (Workload, l96_initial_state, obs_pattern, random_block, sketch_block,
+                       sketchnet_init)
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev():
+    return _torch().device("cuda", 0)
+
+
+def to_dev(A):
+    t = _torch()
+    A = np.asarray(A, dtype=np.float64)
+    if A.ndim == 1:
+        return t.from_numpy(A.copy()).to(dev())
+    return t.from_numpy(np.ascontiguousarray(A.T)).to(dev())
+
+
+def to_host(T):
+    a = T.cpu().numpy()
+    return a if a.ndim == 1 else a.T
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def l96(n, N, ts=5, prob=0.5, seed=5100, m=64):
+    return Workload(name=f"l96_n{n}_N{N}", model="l96", n=n, N=N, F=8.0, dt=0.025, corr="gauss", Lb=2.0,
+                    Lq=2.0, sigma_b=0.2, sigma_q=0.1, obs_kind="bernoulli_times", obs_time_stride=ts,
+                    obs_prob=prob, sigma_o2=0.04, m=m, l=5, seed=seed)
+
+
+def pair(w):
+    from paper_2101_07249_amd import Problem
+    pat = obs_pattern(w)
+    x0 = l96_initial_state(w.n, w.seed)
+    return Problem.from_workload(w, pat, x0=x0), O.make_problem(w, pat, x0=x0), pat
+
+
+NET_CASES = {
+    "one_tile": l96(40, 10),            # n < tile: the halo wraps inside one tile
+    "ragged": l96(300, 4, ts=2),        # 3 tiles per level, ragged last tile
+    "advdiff": None,                    # no trajectory: feature channel 0 is zero
+}
+
+
+def _case(name):
+    if name == "advdiff":
+        w = Workload(name="adv", model="advdiff", n=130, N=6, c=0.5, r=0.1, corr="soar", Lb=4.0, Lq=4.0,
+                     sigma_b=1.0, sigma_q=0.1, obs_var_stride=3, obs_time_stride=2, sigma_o2=0.01, m=64, l=5,
+                     seed=5200)
+        from paper_2101_07249_amd import Problem
+        pat = obs_pattern(w)
+        return w, Problem.from_workload(w, pat), O.make_problem(w, pat), pat
+    w = NET_CASES[name]
+    gp, op, pat = pair(w)
+    return w, gp, op, pat
+
+
+def _oracle_input(w, op, pat, Omega):
+    F = S.features(w.n, w.N, pat, op.traj)
+    return S.net_input(F, Omega)
+
+
+@pytest.mark.parametrize("name", list(NET_CASES))
+def test_inference_matches_oracle(name):
+    from paper_2101_07249_amd import SketchNet
+    say("sketchnet inference", name)
+    w, gp, op, pat = _case(name)
+    theta = sketchnet_init(seed=7001)
+    net = SketchNet()
+    net.set_params(theta)
+    np.testing.assert_array_equal(net.get_params(), theta)
+    Om = sketch_block(op.n_A, 64, w.seed)
+    G = to_host(net.infer(gp, to_dev(Om)))
+    Gref, _ = S.forward(theta.astype(np.float64), _oracle_input(w, op, pat, Om))
+    e = relerr(G, Gref)
+    say("  rel err", e)
+    assert e <= 5e-3
+
+
+@pytest.mark.parametrize("name", ["one_tile", "ragged"])
+def test_backward_matches_oracle(name):
+    from paper_2101_07249_amd import SketchNet
+    say("sketchnet backward", name)
+    w, gp, op, pat = _case(name)
+    theta = sketchnet_init(seed=7002)
+    net = SketchNet()
+    net.set_params(theta)
+    Om = sketch_block(op.n_A, 64, w.seed)
+    net.infer(gp, to_dev(Om))
+    dG = random_block(op.n_A, 64, 77) * 1e-5      # gradient-sized values: exercises the loss scaling
+    net.backward(to_dev(dG))
+    g = net.get_grad().astype(np.float64)
+    _, acts = S.forward(theta.astype(np.float64), _oracle_input(w, op, pat, Om))
+    gref = S.backward(theta.astype(np.float64), acts, dG)
+    cos = float(g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref)))
+    e = relerr(g, gref)
+    say("  cos", cos, "rel", e)
+    assert cos >= 0.999 and e <= 1e-2
+    # per layer too (a wrong layer would hide behind the largest one)
+    off = 0
+    for ws, bs in S.param_shapes():
+        nw = int(np.prod(ws)) + bs[0]
+        assert relerr(g[off:off + nw], gref[off:off + nw]) <= 2e-2
+        off += nw
+
+
+def test_adam_matches_oracle():
+    from paper_2101_07249_amd import SketchNet
+    say("sketchnet adam")
+    theta = sketchnet_init(seed=7003)
+    net = SketchNet()
+    net.set_params(theta)
+    rng = np.random.default_rng(9)
+    th = theta.astype(np.float64).copy()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for step, lr in ((1, 1e-3), (2, 5e-4), (3, 1e-3)):
+        g = (rng.standard_normal(th.size) * 10.0 ** rng.uniform(-6, -2, th.size)).astype(np.float32)
+        net.set_grad(g)
+        net.adam(lr)
+        S.adam_step(th, g.astype(np.float64), m, v, step, lr)
+        got = net.get_params().astype(np.float64)
+        assert relerr(got - theta, th - theta) <= 1e-4
+        assert np.abs(got - th).max() <= 1e-6 + 1e-6 * np.abs(th).max()
+
+
+def test_capture_loss_matches_oracle():
+    say("capture loss")
+    w = l96(40, 10)
+    gp, op, pat = pair(w)
+    k, m = 6, 10
+    rng = np.random.default_rng(11)
+    U, _ = np.linalg.qr(random_block(op.n_A, k, 12))
+    theta = np.sort(1.0 + 10.0 ** rng.uniform(0, 3, k))[::-1].copy()
+    G = random_block(op.n_A, m, 13)
+    f, dG = gp.sketch_loss(to_dev(G), to_dev(U), to_dev(theta))
+    fref, dGref = S.capture_loss(lambda X: O.apply_A(op, X), G, U, theta)
+    say("  f", float(f.item()), fref)
+    assert abs(float(f.item()) - fref) <= 1e-10 * abs(fref)
+    assert relerr(to_host(dG), dGref) <= 1e-9
+
+
+def test_capture_loss_rank_deficient_is_an_error():
+    from paper_2101_07249_amd import Wc4dError
+    say("capture loss singular")
+    w = l96(40, 10)
+    gp, op, pat = pair(w)
+    G = random_block(op.n_A, 4, 14)
+    G[:, 3] = G[:, 1]
+    U, _ = np.linalg.qr(random_block(op.n_A, 3, 15))
+    with pytest.raises(Wc4dError) as e:
+        gp.sketch_loss(to_dev(G), to_dev(U), to_dev(np.array([5.0, 3.0, 2.0])))
+    assert e.value.code == -4
+
+
+def test_training_lowers_the_loss_and_fallback():
+    from paper_2101_07249_amd import SketchNet
+    say("sketchnet training")
+    w = l96(64, 20, ts=4)
+    gp, op, pat = pair(w)
+    ref = gp.lmp_build("nystrom", 96, 32, to_dev(sketch_block(op.n_A, 128, w.seed + 1)))
+    net = SketchNet()
+    net.set_params(sketchnet_init(seed=7004))
+    Om = to_dev(sketch_block(op.n_A, 64, w.seed))
+    losses = [net.train_step(gp, Om, ref, 59, 2e-3) for _ in range(40)]
+    say("  loss", losses[0], "->", losses[-1])
+    assert all(np.isfinite(losses)) and -1.0 <= min(losses) and max(losses) <= 0.0
+    assert np.mean(losses[-5:]) < losses[0] - 0.02
+    L, used = gp.lmp_build_sketch(net, "nystrom", 59, 5, Om)
+    assert used and np.all(L.theta() >= 1.0 - 1e-8)
+    # a network that outputs zeros is rank deficient: the build falls back to Omega
+    zero = SketchNet()
+    zero.set_params(np.zeros(zero.nparams, dtype=np.float32))
+    Lz, usedz = gp.lmp_build_sketch(zero, "nystrom", 59, 5, Om)
+    Lg = gp.lmp_build("nystrom", 59, 5, Om)
+    assert not usedz
+    np.testing.assert_array_equal(Lz.theta(), Lg.theta())
+    Ln, usedn = gp.lmp_build_sketch(None, "nystrom", 59, 5, Om)
+    assert not usedn
+    np.testing.assert_array_equal(Ln.theta(), Lg.theta())
+
+
+def test_save_load_roundtrip(tmp_path):
+    from paper_2101_07249_amd import SketchNet
+    say("sketchnet save/load")
+    net = SketchNet()
+    theta = sketchnet_init(seed=7005)
+    net.set_params(theta)
+    path = os.path.join(str(tmp_path), "net.bin")
+    net.save(path)
+    net2 = SketchNet.load(path)
+    np.testing.assert_array_equal(net2.get_params(), theta)
