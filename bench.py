@@ -49,7 +49,103 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-cols", type=int, default=8)
     ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-sketch comparison")
+    ap.add_argument("--learned-steps", type=int, default=2)
+    ap.add_argument("--batched", action="store_true", help="also time the 64-problem batched solve")
+    ap.add_argument("--batched-count", type=int, default=64)
     return ap.parse_args()
+
+
+def learned_section(args):
+    """Gaussian vs learned start block on a held-out Lorenz-96 problem (n = 1024, N = 100,
+    m = 64, Nystrom): ms from the LMP build (net inference included) to the 1e-6 true
+    residual, PCG iterations and the capture of the reference subspace."""
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd.train_sketchnet import DEFAULT_WEIGHTS, EVAL_OFFSET, Instances
+    from paper_2101_07249_amd.wc4d import SketchNet
+
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        return {"error": f"no trained weights at {os.path.relpath(DEFAULT_WEIGHTS, ROOT)}"}
+    net = SketchNet.load(DEFAULT_WEIGHTS)
+    inst = Instances()
+    w = inst.w
+    a = EVAL_OFFSET
+    p = inst.problem(a)
+    d = torch.from_numpy(np.random.default_rng([w.seed, a, 9]).standard_normal(p.q) * np.sqrt(w.sigma_o2)).to(
+        p.torch_device)
+    b = p.rhs(d)
+    Om = inst.omega(p, a, 64, draw=0)
+    ref = p.lmp_build("nystrom", 251, 5, inst.omega(p, a, 256, draw=1))
+    U = ref.vectors()[:w.k_r].contiguous()
+    th = torch.from_numpy(ref.theta()[:w.k_r].copy()).to(U.device)
+    ref.close()
+    out = {"workload": w.name, "method": "nystrom", "instance": a, "steps": args.learned_steps}
+    x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
+    for name, use in (("gaussian", None), ("learned", net)):
+        times, infos, used = [], [], False
+        for rep in range(1 + args.learned_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L, used = p.lmp_build_sketch(use, "nystrom", w.k_r, w.l, Om)
+            x.zero_()
+            info = p.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
+            torch.cuda.synchronize()
+            if rep > 0:
+                times.append(1e3 * (time.perf_counter() - t0))
+                infos.append(info)
+            L.close()
+        G = net.infer(p, Om) if use is not None else Om
+        f, _ = p.sketch_loss(G, U, th)
+        out[name] = {"ms": float(np.median(times)), "pcg_iters": infos[-1]["iters"],
+                     "relres_true": infos[-1]["relres_true"], "used_net": bool(used),
+                     "captured_share": -float(f.item())}
+    out["speedup_vs_gaussian"] = out["gaussian"]["ms"] / out["learned"]["ms"]
+    p.close()
+    return out
+
+
+def batched_section(args):
+    """64 uneven advection-diffusion inner loops (n in [512, 8192], N in [10, 200], m = 64,
+    Nystrom) through wc4d_batch_solve: wall time of the whole batch (tiles autotuned
+    beforehand, not timed) against the same problems solved one after another."""
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd import Problem, batch_solve
+    from synthetic import batched_workloads, innovations, obs_pattern, sketch_block
+
+    ws = batched_workloads(count=args.batched_count)
+    probs, G, b = [], [], []
+    for w in ws:
+        p = Problem.from_workload(w, obs_pattern(w))
+        p.autotune(w.m)
+        p.autotune(1)
+        probs.append(p)
+        G.append(torch.from_numpy(np.ascontiguousarray(sketch_block(p.n_A, w.m, w.seed).T)).to(p.torch_device))
+        b.append(p.rhs(torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device)))
+    x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
+    k_r, l = ws[0].k_r, ws[0].l
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    iters_seq = []
+    for i, p in enumerate(probs):
+        L = p.lmp_build("nystrom", k_r, l, G[i])
+        x[i].zero_()
+        iters_seq.append(p.pcg(b[i], x[i], L, tol=args.tol, maxit=args.maxit, history=False)["iters"])
+        L.close()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return {"problems": len(ws), "sum_n_A": int(sum(p.n_A for p in probs)), "batch_s": t_batch,
+            "sequential_s": t_seq, "speedup": t_seq / t_batch,
+            "iters_total": int(sum(i["iters"] for i in infos)), "iters_equal_sequential":
+            [i["iters"] for i in infos] == iters_seq,
+            "converged": all(s == 0 for s in status) and all(i["relres_true"] <= args.tol for i in infos)}
 
 
 def cpu_baseline(w, pat, gpu_iters, args):
@@ -210,6 +306,10 @@ def main():
         "hessian_apply": hess,
         "roofline": roof,
     }
+    if not args.no_learned:
+        out["learned"] = learned_section(args)
+    if args.batched:
+        out["batched"] = batched_section(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pat, iters, args)
     print(json.dumps(out), flush=True)

@@ -165,6 +165,8 @@ int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s);
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
 /* Block products with A spent by the build (Table 1: 2 / 2 / 1). */
 int wc4d_lmp_applies(wc4d_lmp L, int* count);
+/* Frees L.  wc4d_destroy(p) releases the device memory of the LMPs still alive on p;
+ * their handles then accept only wc4d_lmp_destroy (other calls return WC4D_ESTATE). */
 int wc4d_lmp_destroy(wc4d_lmp L);
 
 /* ---------------------------------------------------------------- solve -- */
@@ -228,6 +230,32 @@ enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC
 int wc4d_prof_enable(wc4d_problem p, int enable);
 int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
                    double* flops);
+
+/* ------------------------------------------------ batched inner loops -- */
+/* Tile autotuner for the D^{1/2} products (Section 2.2, D^{1/2} = blockdiag(B^{1/2},
+ * Q^{1/2}, ..., Q^{1/2})) of p at block width m: times every feasible float64 tile
+ * shape of the B^{1/2} (m columns) and Q^{1/2} (m N columns) products and the
+ * two-segment split-K form, and makes the fastest the one p uses for that width.
+ * Choices are cached per (device, n, N, m) for the life of the process, so later
+ * problems of the same shape reuse them without timing.  Uses p's build scratch;
+ * synchronises s.  wc4d_autotune_info reports the choice (tile codes: 1 split-K 64x16,
+ * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32) and its measured ms. */
+int wc4d_autotune(wc4d_problem p, int m, hipStream_t s);
+int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two_segment, float* ms);
+
+/* Solve `count` independent inner loops (Section 2.2 / Algorithm 1) at once: for each
+ * problem ps[i] (finalized, all on one device, none repeated) an LMP of k_r Ritz pairs
+ * from the start block G[i] (device n_A(i) x (k_r + l)) by `method` (Section 4), then
+ * split PCG on A x = b[i] with x[i] as initial guess and solution (device n_A(i)).
+ * `workers` (1..16) host threads, each with its own non-blocking stream, take the
+ * problems largest first; with autotune != 0 the D^{1/2} tiles of each problem are
+ * tuned for widths k_r + l and 1 first.  infos[i] / status[i] receive each problem's
+ * PCG report and return code.  Synchronous.  Returns WC4D_OK when every problem
+ * returned WC4D_OK, WC4D_ENOCONV or WC4D_EBREAKDOWN (see status), else the first
+ * other error. */
+int wc4d_batch_solve(wc4d_problem* ps, int count, int method, int k_r, int l, const double* const* G,
+                     const double* const* b, double* const* x, const wc4d_pcg_opts* opts,
+                     wc4d_pcg_info* infos, int* status, int workers, int autotune);
 
 /* ------------------------------------------------------- learned sketch -- */
 /* The randomised eigendecompositions of Section 4 (Algorithms 3-5) start from a

@@ -2,4 +2,5 @@
 weak-constraint 4D-Var: a HIP library (libwc4d.so, C-ABI in include/wc4d.h) and
 its thin Python binding."""
 from . import wc4d  # noqa: F401
-from .wc4d import Lmp, Problem, SketchNet, Wc4dError, corr_sqrt, l96_trajectory, lib  # noqa: F401
+from .wc4d import (Lmp, Problem, SketchNet, Wc4dError, batch_solve, corr_sqrt, l96_trajectory,  # noqa: F401
+                   lib)

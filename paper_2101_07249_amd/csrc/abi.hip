@@ -113,6 +113,13 @@ int wc4d_create(wc4d_problem* out, int n, int N, int device) {
 int wc4d_destroy(wc4d_problem p) {
   if (p == nullptr) return WC4D_OK;
   DevGuard g(p->device);
+  // LMPs still alive lose their device memory; their handles stay valid for
+  // wc4d_lmp_destroy and every other call on them returns WC4D_ESTATE
+  for (wc4d_lmp L : p->lmps) {
+    lmp_release(L);
+    L->p = nullptr;
+  }
+  p->lmps.clear();
   dev_free(&p->dB);
   dev_free(&p->dQ);
   dev_free(&p->dBhi);
@@ -328,6 +335,9 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
 
   HIPCHK(p, hipMemsetAsync(p->dStatus, 0, 16 * sizeof(int), s));
   HIPCHK(p, hipStreamSynchronize(s));
+  // the host copies of the square roots are no longer needed once uploaded
+  std::vector<double>().swap(p->Bsqrt);
+  std::vector<double>().swap(p->Qsqrt);
   p->prec = prec_mode;
   p->finalized = true;
   return WC4D_OK;
@@ -401,16 +411,20 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
                           ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
     return WC4D_OK;
   }
-  if (m * N <= 112 && n >= 512 && dsqrt2_ws_doubles(n, m * N, m, n) <= p->wsSplitDoubles) {
+  const DsqrtTune* t = find_tune(p, m);
+  const bool two_ok = (long long)m * N <= 112 && m <= 112 &&
+                      dsqrt2_ws_doubles(n, m * N, m, n) <= p->wsSplitDoubles;
+  const bool two = two_ok && (t != nullptr ? t->twoSeg : n >= 512);
+  if (two) {
     HIPCHK(p, dsqrt2_f64(n, n, X, Y, E, p->dQ, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n},
                          ColMap{lde, N, 1, n}, m * N, p->dB, ColMap{ldx, 1, 0, n}, ColMap{ldy, 1, 0, n},
                          ColMap{lde, 1, 0, n}, m, skip, p->wsSplit, p->wsSplitDoubles, s));
     return WC4D_OK;
   }
-  HIPCHK(p, gemm_f64(n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y, ColMap{ldy, 1, 0, n}, E,
-                     ColMap{lde, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
-  HIPCHK(p, gemm_f64(n, m * N, n, 1.0, p->dQ, n, X, ColMap{ldx, N, 1, n}, Y, ColMap{ldy, N, 1, n},
-                     E, ColMap{lde, N, 1, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
+  HIPCHK(p, gemm_f64_tile(t ? t->tileB : GEMM_AUTO, 0, n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y,
+                          ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
+  HIPCHK(p, gemm_f64_tile(t ? t->tileQ : GEMM_AUTO, 0, n, m * N, n, 1.0, p->dQ, n, X, ColMap{ldx, N, 1, n}, Y,
+                          ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
   return WC4D_OK;
 }
 
@@ -537,6 +551,19 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
 
 // ------------------------------------------------------------ LMP build
 
+// Frees an LMP's device memory (its problem's device must be current).
+void wc4d::lmp_release(wc4d_lmp L) {
+  dev_free(&L->U);
+  dev_free(&L->theta);
+  dev_free(&L->dcoef);
+  dev_free(&L->T);
+  dev_free(&L->ws);
+  dev_free(&L->wsv);
+  dev_free(&L->GU);
+  dev_free(&L->fu);
+  dev_free(&L->U32);
+}
+
 int wc4d::ensure_build(wc4d_problem p, int m) {
   int rc;
   if (p->bufCols < m) {
@@ -557,7 +584,7 @@ int wc4d::ensure_build(wc4d_problem p, int m) {
 namespace {
 
 struct Small {
-  double *G, *R1, *Ri, *R2, *K, *V, *lam;
+  double *G, *R1, *Ri, *R2, *K, *V, *lam, *dg;
   explicit Small(double* base, int m) {
     const size_t mm = (size_t)m * m;
     G = base;
@@ -567,34 +594,54 @@ struct Small {
     K = base + 4 * mm;
     V = base + 5 * mm;
     lam = base + 6 * mm;
+    dg = lam + m;
   }
 };
 
 // CholeskyQR2 of the n_A x m block Y (in place): Y = Q R with Q^T Q = I.
-// tmp: n_A x m scratch.  When Rout != null, R = R2 R1 is written there (m x m).
+// tmp: n_A x m scratch.  When Rout != null, R (the product of the passes' triangular
+// factors) is written there (m x m).  With p->cholShift the first pass Cholesky-factors
+// Y^T Y + s I, s = 11 (n_A m + m (m + 1)) u trace(Y^T Y), and two plain passes follow
+// (shifted CholeskyQR3): the form for blocks too ill-conditioned for CholeskyQR2; it
+// flags the block rank deficient when R's diagonal spans more than 1 / (1e3 u).
 int cholqr2(wc4d_problem p, double* Y, double* tmp, int m, Small& sm, double* Rout, hipStream_t s) {
   const long long nA = p->nA;
-  ProfScope ps(p, s, PROF_BUILD, 8.0 * 6.0 * (double)nA * m, 8.0 * (double)nA * m * m);
+  const bool shifted = p->cholShift;
+  const int passes = shifted ? 3 : 2;
+  ProfScope ps(p, s, PROF_BUILD, 8.0 * 3.0 * passes * (double)nA * m, 4.0 * passes * (double)nA * m * m);
   const ColMap cm = plain_cols(nA);
   int* st = p->dStatus;
-  HIPCHK(p, gram_f64(m, m, nA, Y, cm, Y, cm, sm.G, m, p->wsGram, nullptr, s));
-  HIPCHK(p, chol_upper(m, sm.G, m, st, s));
-  HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
-  HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, Y, nA, sm.Ri, plain_cols(m), tmp, cm, nullptr, cm, nullptr, s));
-  if (Rout != nullptr) HIPCHK(p, vec_copy(sm.R1, sm.G, (long long)m * m, s));
-  HIPCHK(p, gram_f64(m, m, nA, tmp, cm, tmp, cm, sm.G, m, p->wsGram, nullptr, s));
-  HIPCHK(p, chol_upper(m, sm.G, m, st, s));
-  HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
-  HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, tmp, nA, sm.Ri, plain_cols(m), Y, cm, nullptr, cm, nullptr, s));
-  if (Rout != nullptr) HIPCHK(p, small_gemm(m, m, m, 1.0, sm.G, m, 0, sm.R1, m, 0, Rout, m, s));
+  double* src = Y;
+  double* dst = tmp;
+  for (int k = 0; k < passes; ++k) {
+    HIPCHK(p, gram_f64(m, m, nA, src, cm, src, cm, sm.G, m, p->wsGram, nullptr, s));
+    if (shifted && k == 0) {
+      const double c = 11.0 * ((double)nA * m + (double)m * (m + 1)) * 1.1102230246251565e-16;
+      HIPCHK(p, shift_diag_trace(m, sm.G, m, c, s));
+    }
+    HIPCHK(p, chol_upper(m, sm.G, m, st, s));
+    if (shifted) HIPCHK(p, diag_accumulate(m, sm.G, m, sm.dg, k == 0, s));
+    HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
+    HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, src, nA, sm.Ri, plain_cols(m), dst, cm, nullptr, cm, nullptr, s));
+    if (Rout != nullptr) {
+      if (k == 0) {
+        HIPCHK(p, vec_copy(sm.R1, sm.G, (long long)m * m, s));
+      } else {
+        HIPCHK(p, small_gemm(m, m, m, 1.0, sm.G, m, 0, sm.R1, m, 0, sm.K, m, s));
+        HIPCHK(p, vec_copy(sm.R1, sm.K, (long long)m * m, s));
+      }
+    }
+    std::swap(src, dst);
+  }
+  if (src != Y) HIPCHK(p, vec_copy(Y, src, nA * m, s));
+  if (Rout != nullptr) HIPCHK(p, vec_copy(Rout, sm.R1, (long long)m * m, s));
+  // the shift makes any Gram matrix factorable: a block whose R (diagonal = product of
+  // the passes' diagonals) has min/max below 1e3 u is numerically rank deficient
+  if (shifted) HIPCHK(p, rank_check(m, sm.dg, 1e3 * 2.220446049250313e-16, st, s));
   return WC4D_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
+int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
                    hipStream_t s) {
   if (out == nullptr) return WC4D_EINVAL;
   *out = nullptr;
@@ -609,6 +656,7 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   wc4d_lmp L = new (std::nothrow) wc4d_lmp_s();
   if (L == nullptr) return WC4D_ENOMEM;
   L->p = p;
+  p->lmps.push_back(L);
   L->nA = p->nA;
   L->ldu = (p->nA + 3) / 4 * 4;
   L->k = k_r;
@@ -681,7 +729,10 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   if (st != 0)
-    return cleanup(fail(p, WC4D_ENOTSPD, "Cholesky met a non-positive pivot (rank-deficient sketch?)"));
+    return cleanup(fail(p, WC4D_ENOTSPD,
+                        std::string(st == 2 ? "start block numerically rank deficient (R diagonal spans > 1/(1e3 u))"
+                                            : "Cholesky met a non-positive pivot (rank-deficient sketch?)") +
+                            (p->cholShift ? " after shifted CholeskyQR3" : "")));
   // U^T U of the U the PCG streams, for the fused recursion (identity up to rounding
   // for an orthonormal U; computed from the float32 copy when there is one)
   if ((rc = dev_alloc(p, &L->GU, (size_t)k_r * k_r))) return cleanup(rc);
@@ -706,8 +757,24 @@ int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, 
   return WC4D_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
+                   hipStream_t s) {
+  int rc = lmp_build_once(p, method, k_r, l, G, out, s);
+  if (rc != WC4D_ENOTSPD) return rc;
+  // a Cholesky factorisation broke down: once more with shifted CholeskyQR3
+  p->cholShift = true;
+  rc = lmp_build_once(p, method, k_r, l, G, out, s);
+  p->cholShift = false;
+  return rc;
+}
+
 int wc4d_lmp_theta(wc4d_lmp L, double* theta_host) {
   if (L == nullptr || theta_host == nullptr) return WC4D_EINVAL;
+  if (L->p == nullptr) return WC4D_ESTATE;
   DevGuard g(L->p->device);
   HIPCHK(L->p, hipMemcpy(theta_host, L->theta, sizeof(double) * L->k, hipMemcpyDeviceToHost));
   return WC4D_OK;
@@ -715,6 +782,7 @@ int wc4d_lmp_theta(wc4d_lmp L, double* theta_host) {
 
 int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s) {
   if (L == nullptr || U == nullptr || ldu < L->nA) return WC4D_EINVAL;
+  if (L->p == nullptr) return WC4D_ESTATE;
   DevGuard g(L->p->device);
   HIPCHK(L->p, block_copy(U, ldu, L->U, L->ldu, L->nA, L->k, s));
   return WC4D_OK;
@@ -779,6 +847,7 @@ extern "C" {
 
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
   if (L == nullptr) return WC4D_EINVAL;
+  if (L->p == nullptr) return WC4D_ESTATE;
   int rc = check_block_args(L->p, X, ldx, Y, ldy, m);
   if (rc) return rc;
   DevGuard g(L->p->device);
@@ -787,16 +856,12 @@ int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int
 
 int wc4d_lmp_destroy(wc4d_lmp L) {
   if (L == nullptr) return WC4D_OK;
-  DevGuard g(L->p->device);
-  dev_free(&L->U);
-  dev_free(&L->theta);
-  dev_free(&L->dcoef);
-  dev_free(&L->T);
-  dev_free(&L->ws);
-  dev_free(&L->wsv);
-  dev_free(&L->GU);
-  dev_free(&L->fu);
-  dev_free(&L->U32);
+  if (L->p != nullptr) {
+    auto& v = L->p->lmps;
+    v.erase(std::remove(v.begin(), v.end(), L), v.end());
+    DevGuard g(L->p->device);
+    lmp_release(L);
+  }
   delete L;
   return WC4D_OK;
 }
@@ -810,7 +875,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
   if (b == nullptr || x == nullptr || opts == nullptr || info == nullptr || opts->maxit < 1 ||
       !(opts->tol >= 0.0) || (opts->criterion != WC4D_RES_TRUE && opts->criterion != WC4D_RES_PRECOND))
     return fail(p, WC4D_EINVAL, "invalid PCG arguments");
-  if (L != nullptr && L->p != p) return fail(p, WC4D_EINVAL, "LMP built for another problem");
+  if (L != nullptr && L->p != p) return fail(p, WC4D_EINVAL, "LMP built for another problem (or orphaned)");
   if (opts->variant != WC4D_PCG_FUSED && opts->variant != WC4D_PCG_PLAIN)
     return fail(p, WC4D_EINVAL, "unknown PCG variant");
   const bool fused = (L != nullptr && opts->variant == WC4D_PCG_FUSED);

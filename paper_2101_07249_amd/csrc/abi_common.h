@@ -109,6 +109,16 @@ struct ProfScope {
   }
 };
 
+// Autotuned D^{1/2} tiles of block width m on p, or null (then the built-in heuristic).
+inline const DsqrtTune* find_tune(wc4d_problem p, int m) {
+  for (const auto& e : p->tune)
+    if (e.first == m) return &e.second;
+  return nullptr;
+}
+
+// Frees an LMP's device memory (its problem's device must be current).
+void lmp_release(wc4d_lmp L);
+
 // Build scratch: bufA / bufB (n_A + 4) x m, small matrices, block and Gram workspaces.
 int ensure_build(wc4d_problem p, int m);
 

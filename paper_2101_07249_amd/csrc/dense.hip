@@ -2,6 +2,8 @@
 // randomised eigendecompositions (m = sketch width <= 512): Cholesky (CholeskyQR2
 // and Algorithm 4's E2 = C^T C), triangular inverse, small products and the
 // symmetric eigenproblem (Algorithm 2's EVD, Algorithms 3 and 5).
+#include <mutex>
+
 #include "wc4d_internal.h"
 
 #include <cmath>
@@ -330,17 +332,76 @@ __global__ __launch_bounds__(kOJT) void k_oj_finish(int m, double* __restrict__ 
   }
 }
 
+__global__ void k_shift_diag_trace(int m, double* __restrict__ G, int ldg, double c) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) acc += G[i + (size_t)i * ldg];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sft = c * sh[0];
+  for (int i = threadIdx.x; i < m; i += 256) G[i + (size_t)i * ldg] += sft;
+}
+
+__global__ void k_diag_accumulate(int m, const double* __restrict__ R, int ldr, double* __restrict__ d,
+                                  int first) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const double r = fabs(R[i + (size_t)i * ldr]);
+    d[i] = first ? r : d[i] * r;
+  }
+}
+
+hipError_t diag_accumulate(int m, const double* R, int ldr, double* d, bool first, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_accumulate, dim3((m + 255) / 256), dim3(256), 0, s, m, R, ldr, d, first ? 1 : 0);
+  return hipGetLastError();
+}
+
+__global__ void k_rank_check(int m, const double* __restrict__ d, double tol, int* __restrict__ status) {
+  __shared__ double smin[256], smax[256];
+  double lo = INFINITY, hi = 0.0;
+  bool bad = false;
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double v = d[i];
+    if (!isfinite(v)) bad = true;
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  smin[threadIdx.x] = bad ? -1.0 : lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && (smin[0] < 0.0 || !(smin[0] >= tol * smax[0]))) *status = 2;
+}
+
+hipError_t rank_check(int m, const double* d, double tol, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_rank_check, dim3(1), dim3(256), 0, s, m, d, tol, status);
+  return hipGetLastError();
+}
+
+hipError_t shift_diag_trace(int m, double* G, int ldg, double c, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_diag_trace, dim3(1), dim3(256), 0, s, m, G, ldg, c);
+  return hipGetLastError();
+}
+
 hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
                       hipStream_t s) {
   if (m > 512 || m < 1) return hipErrorInvalidValue;
   const OjCfg c = oj_cfg(m);
   const size_t lds = sizeof(double) * 4 * (size_t)c.bs * m;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
     (void)hipFuncSetAttribute((const void*)k_oj_round, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(double) * 4 * 16 * 256));
-    attr_set = true;
-  }
+  });
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
   hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl);
   const int max_sweeps = 20;

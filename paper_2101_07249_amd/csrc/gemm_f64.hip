@@ -190,35 +190,74 @@ static hipError_t launch_gemm_split(int M, int ncol, int K, int splits, double a
   return hipGetLastError();
 }
 
-hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
-                    const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
-                    ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles) {
+// Split count for a split-K launch of `bn`-wide column tiles (0: not possible).
+static long long split_count(int M, int ncol, int K, int bn, size_t ws_doubles, int want) {
+  const long long t = (long long)((M + 63) / 64) * (long long)((ncol + bn - 1) / bn);
+  long long splits = want > 0 ? want : (512 + t - 1) / t;
+  splits = std::min<long long>(splits, K / 256);
+  while (splits > 1 && (size_t)splits * M * ncol > ws_doubles) --splits;
+  return splits >= 2 ? splits : 0;
+}
+
+bool gemm_tile_feasible(int tile, int M, int ncol, int K, const double* ws, size_t ws_doubles) {
+  switch (tile) {
+    case GEMM_AUTO: return true;
+    case GEMM_SPLIT_64x16: return ws != nullptr && ncol <= 16 && split_count(M, ncol, K, 16, ws_doubles, 0) > 0;
+    case GEMM_SPLIT_64x112: return ws != nullptr && ncol <= 112 && split_count(M, ncol, K, 112, ws_doubles, 0) > 0;
+    case GEMM_128x16: case GEMM_128x128: case GEMM_64x64: case GEMM_32x32: return true;
+    default: return false;
+  }
+}
+
+hipError_t gemm_f64_tile(int tile, int splits, int M, int ncol, int K, double alpha, const double* A,
+                         long long lda, const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                         ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles) {
   if (M <= 0 || ncol <= 0) return hipSuccess;
   auto tiles = [&](int bm, int bn) {
     return (long long)((M + bm - 1) / bm) * (long long)((ncol + bn - 1) / bn);
   };
-  // Few output columns and a long K: split K so the launch fills the chip.
-  if (ws != nullptr && ncol <= 112 && K >= 512) {
-    const int bn = ncol <= 16 ? 16 : 112;
-    const long long t = tiles(64, bn);
-    long long splits = (512 + t - 1) / t;
-    splits = std::min<long long>(splits, K / 256);
-    while (splits > 1 && (size_t)splits * M * ncol > ws_doubles) --splits;
-    if (splits >= 2) {
-      if (bn == 16)
-        return launch_gemm_split<64, 16, 32, 4, 1>(M, ncol, K, (int)splits, alpha, A, lda, B, bmap,
-                                                   C, cmap, E, emap, skip, ws, s);
-      return launch_gemm_split<64, 112, 32, 4, 1>(M, ncol, K, (int)splits, alpha, A, lda, B, bmap, C,
-                                                  cmap, E, emap, skip, ws, s);
-    }
+  if (tile == GEMM_AUTO) {
+    // Few output columns and a long K: split K so the launch fills the chip.
+    if (ws != nullptr && ncol <= 112 && K >= 512 &&
+        split_count(M, ncol, K, ncol <= 16 ? 16 : 112, ws_doubles, 0) > 0)
+      tile = ncol <= 16 ? GEMM_SPLIT_64x16 : GEMM_SPLIT_64x112;
+    else if (ncol <= 16)
+      tile = GEMM_128x16;
+    else if (tiles(128, 128) >= 1024)
+      tile = GEMM_128x128;
+    else if (tiles(64, 64) >= 1024)
+      tile = GEMM_64x64;
+    else
+      tile = GEMM_32x32;
   }
-  if (ncol <= 16)
-    return launch_gemm<128, 16, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
-  if (tiles(128, 128) >= 1024)
-    return launch_gemm<128, 128, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
-  if (tiles(64, 64) >= 1024)
-    return launch_gemm<64, 64, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
-  return launch_gemm<32, 32, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  if (!gemm_tile_feasible(tile, M, ncol, K, ws, ws_doubles)) return hipErrorInvalidValue;
+  switch (tile) {
+    case GEMM_SPLIT_64x16: {
+      const long long sp = split_count(M, ncol, K, 16, ws_doubles, splits);
+      return launch_gemm_split<64, 16, 32, 4, 1>(M, ncol, K, (int)sp, alpha, A, lda, B, bmap, C, cmap, E, emap,
+                                                 skip, ws, s);
+    }
+    case GEMM_SPLIT_64x112: {
+      const long long sp = split_count(M, ncol, K, 112, ws_doubles, splits);
+      return launch_gemm_split<64, 112, 32, 4, 1>(M, ncol, K, (int)sp, alpha, A, lda, B, bmap, C, cmap, E,
+                                                  emap, skip, ws, s);
+    }
+    case GEMM_128x16:
+      return launch_gemm<128, 16, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    case GEMM_128x128:
+      return launch_gemm<128, 128, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    case GEMM_64x64:
+      return launch_gemm<64, 64, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+    default:
+      return launch_gemm<32, 32, 16, 2, 2>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);
+  }
+}
+
+hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long long lda,
+                    const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                    ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles) {
+  return gemm_f64_tile(GEMM_AUTO, 0, M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s, ws,
+                       ws_doubles);
 }
 
 // ----------------------------------------------- two-segment few-column product

@@ -42,6 +42,15 @@ hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long 
                     ColMap emap, const int* skip, hipStream_t s, double* ws = nullptr,
                     size_t ws_doubles = 0);
 
+// Explicit tile shapes of gemm_f64 (the autotuner's candidates): split-K with 64 x 16 or
+// 64 x 112 tiles (needs ws), or plain 128 x 16, 128 x 128, 64 x 64, 32 x 32 tiles.
+enum GemmTile { GEMM_AUTO = 0, GEMM_SPLIT_64x16, GEMM_SPLIT_64x112, GEMM_128x16, GEMM_128x128, GEMM_64x64,
+                GEMM_32x32, GEMM_NTILES };
+bool gemm_tile_feasible(int tile, int M, int ncol, int K, const double* ws, size_t ws_doubles);
+hipError_t gemm_f64_tile(int tile, int splits, int M, int ncol, int K, double alpha, const double* A,
+                         long long lda, const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
+                         ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles);
+
 // Two-segment few-column product (both n1, n2 <= 112): C(:, c1(t)) = A1 B(:, b1(t)) [+ E]
 // for t < n1 and C(:, c2(t)) = A2 B(:, b2(t)) [+ E] for t < n2, A1 / A2 M x K with lda = M,
 // one split-K launch plus one reduction.  ws: dsqrt2_ws_doubles(M, n1, n2, K).
@@ -95,6 +104,12 @@ size_t sweep_lds_required(const SweepModel& md);
 // Upper Cholesky in place: G = R^T R, strict lower set to 0; *status = 1 on a
 // non-positive or non-finite pivot (status untouched otherwise).
 hipError_t chol_upper(int m, double* G, int ldg, int* status, hipStream_t s);
+// d[i] = |R(i, i)| (first) or d[i] *= |R(i, i)|, i < m.
+hipError_t diag_accumulate(int m, const double* R, int ldr, double* d, bool first, hipStream_t s);
+// *status = 2 when min d < tol * max d (or d has a non-finite entry).
+hipError_t rank_check(int m, const double* d, double tol, int* status, hipStream_t s);
+// G(i, i) += c * trace(G) for i < m (single workgroup).
+hipError_t shift_diag_trace(int m, double* G, int ldg, double c, hipStream_t s);
 // Rinv = R^{-1} for upper triangular R (one wavefront per column).
 hipError_t tri_inv_upper(int m, const double* R, int ldr, double* Rinv, int ldi, hipStream_t s);
 // C = alpha op(A) op(B), op = transpose when t* != 0; M x N result, inner K.
@@ -216,6 +231,14 @@ struct ProfRec {
   double bytes, flops;
 };
 
+// Tile choice of the D^{1/2} products for one block width m (set by the autotuner).
+struct DsqrtTune {
+  int tileB = 0;      // GemmTile of the B^{1/2} product (m columns)
+  int tileQ = 0;      // GemmTile of the Q^{1/2} product (m N columns)
+  bool twoSeg = false;  // one two-segment split-K launch instead of both
+  float ms = 0.f;     // measured time of the chosen form
+};
+
 struct wc4d_problem_s {
   int n = 0, N = 0, device = 0;
   long long nA = 0;
@@ -279,12 +302,15 @@ struct wc4d_problem_s {
   // profiling of the last apply
   bool prof = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<wc4d_lmp> lmps;  // live LMPs built on this problem
+  bool cholShift = false;       // LMP build: shifted CholeskyQR3 (set for a retry)
+  std::vector<std::pair<int, DsqrtTune>> tune;  // autotuned D^{1/2} tiles per block width
   std::string err;
   wc4d::SweepModel sweep() const;
 };
 
 struct wc4d_lmp_s {
-  wc4d_problem p = nullptr;
+  wc4d_problem p = nullptr;  // null once the problem has been destroyed
   long long nA = 0;
   long long ldu = 0;        // leading dimension of U and U32: n_A rounded up to 4
   int k = 0;

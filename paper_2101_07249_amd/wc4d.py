@@ -82,6 +82,13 @@ _SIGS = {
     "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
                                       _c_dbl_p, _c_dbl_p]),
     "wc4d_last_apply_timing": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float)]),
+    "wc4d_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "wc4d_autotune_info": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p,
+                                          ctypes.POINTER(ctypes.c_float)]),
+    "wc4d_batch_solve": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
+                                        _c_int_p, ctypes.c_int, ctypes.c_int]),
     "wc4d_sketchnet_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int]),
     "wc4d_sketchnet_destroy": (ctypes.c_int, [_vp]),
@@ -123,6 +130,9 @@ def lib() -> ctypes.CDLL:
     """Load libwc4d.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch has loaded, so
+        # both share one runtime (and torch's device memory and streams are valid in it)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2101_07249_amd/build.py "
                               "(there is no fallback implementation)")
@@ -185,7 +195,9 @@ class Lmp:
 
     def theta(self) -> np.ndarray:
         out = np.empty(self.k)
-        self.prob._chk(lib().wc4d_lmp_theta(self._h, _dptr(out)), "lmp_theta")
+        rc = lib().wc4d_lmp_theta(self._h, _dptr(out))
+        if rc:
+            raise Wc4dError(rc, "lmp_theta")
         return out
 
     def vectors(self, stream=None):
@@ -373,6 +385,15 @@ class Problem:
                   "sketch_loss")
         return f, dG
 
+    def autotune(self, m: int, stream=None) -> dict:
+        """Tune the D^{1/2} tile shapes for block width m; returns the choice."""
+        self._chk(lib().wc4d_autotune(self._h, int(m), _stream(stream)), "autotune")
+        tb, tq, two = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ms = ctypes.c_float()
+        self._chk(lib().wc4d_autotune_info(self._h, int(m), ctypes.byref(tb), ctypes.byref(tq), ctypes.byref(two),
+                                           ctypes.byref(ms)), "autotune_info")
+        return {"tile_b": tb.value, "tile_q": tq.value, "two_segment": bool(two.value), "ms": ms.value}
+
     def pcg(self, b, x, lmp: Optional[Lmp] = None, tol: float = 1e-6, maxit: int = 100,
             criterion: int = RES_TRUE, history: bool = True, variant: int = PCG_FUSED, stream=None):
         opts = PcgOpts(float(tol), int(maxit), int(criterion), int(variant))
@@ -427,6 +448,31 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def batch_solve(problems: Sequence[Problem], method, k_r: int, l: int, G, b, x, tol: float = 1e-6,
+                maxit: int = 5000, criterion: int = RES_TRUE, variant: int = PCG_FUSED, workers: int = 4,
+                autotune: bool = True):
+    """Solve independent inner loops at once (wc4d_batch_solve).  G, b, x: lists of
+    device tensors per problem ((m, n_A), (n_A,), (n_A,)).  Returns (infos, status)."""
+    cnt = len(problems)
+    meth = METHOD[method] if isinstance(method, str) else int(method)
+    P = (_vp * cnt)(*[p._h for p in problems])
+    Gp = (_vp * cnt)(*[_tptr(g) for g in G])
+    bp = (_vp * cnt)(*[_tptr(v) for v in b])
+    xp = (_vp * cnt)(*[_tptr(v) for v in x])
+    infos = (PcgInfo * cnt)()
+    status = (ctypes.c_int * cnt)()
+    opts = PcgOpts(float(tol), int(maxit), int(criterion), int(variant))
+    rc = lib().wc4d_batch_solve(P, cnt, meth, int(k_r), int(l), Gp, bp, xp, ctypes.byref(opts), infos, status,
+                                int(workers), int(bool(autotune)))
+    if rc != OK:
+        bad = [i for i in range(cnt) if status[i] not in (OK, ENOCONV, EBREAKDOWN)]
+        msg = lib().wc4d_last_error(problems[bad[0]]._h).decode() if bad else ""
+        raise Wc4dError(rc, f"batch_solve: {msg}")
+    out = [{"iters": i.iters, "status": i.status, "relres_true": i.relres_true, "relres_precond": i.relres_precond,
+            "J": i.J} for i in infos]
+    return out, list(status)
 
 
 class SketchNet:

@@ -1,0 +1,123 @@
+"""Batched inner loops and the tile autotuner.
+
+A batched solve runs the same kernels as one-by-one solves on the same problems, so
+its results must be bit-identical to them; one problem is also checked against the
+oracle's inner loop.  The autotuner may change the D^{1/2} tile shape, which only
+reorders float64 sums: applies before and after tuning agree to 1e-12 relative and
+stay within 1e-10 of the oracle."""
+import numpy as np
+import pytest
+
+from oracle import wc4d_oracle as O
+from synthetic import batched_workloads, innovations, obs_pattern, random_block, sketch_block
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev():
+    return _torch().device("cuda", 0)
+
+
+def to_dev(A):
+    t = _torch()
+    A = np.asarray(A, dtype=np.float64)
+    if A.ndim == 1:
+        return t.from_numpy(A.copy()).to(dev())
+    return t.from_numpy(np.ascontiguousarray(A.T)).to(dev())
+
+
+def to_host(T):
+    a = T.cpu().numpy()
+    return a if a.ndim == 1 else a.T
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def small_batch(count=6, m=16):
+    # uneven advection-diffusion problems shaped like the batched workload, scaled down
+    return batched_workloads(count=count, seed=4100, m=m, n_range=(40, 700), N_range=(5, 40))
+
+
+@pytest.mark.parametrize("m", [1, 7, 64])
+def test_autotune_keeps_the_operator(m):
+    from paper_2101_07249_amd import Problem
+    w = small_batch(1)[0].with_(n=300, N=20)
+    say("autotune", w.n, w.N, "m", m)
+    pat = obs_pattern(w)
+    gp = Problem.from_workload(w, pat)
+    op = O.make_problem(w, pat)
+    X = random_block(op.n_A, m, 31)
+    Y0 = to_host(gp.apply_A(to_dev(X)))
+    t = gp.autotune(m)
+    say("  choice", t)
+    assert 1 <= t["tile_b"] <= 6 and 1 <= t["tile_q"] <= 6 and t["ms"] > 0
+    Y1 = to_host(gp.apply_A(to_dev(X)))
+    assert relerr(Y1, Y0) <= 1e-12
+    assert relerr(Y1, O.apply_A(op, X)) <= 1e-10
+    # a second problem of the same shape takes the cached choice
+    gp2 = Problem.from_workload(w, pat)
+    assert gp2.autotune(m) == t
+
+
+def test_batch_solve_matches_one_by_one_and_oracle():
+    from paper_2101_07249_amd import Problem, batch_solve
+    ws = small_batch(6)
+    k_r, l = 11, 5
+    probs, G, b, pats = [], [], [], []
+    for w in ws:
+        pat = obs_pattern(w)
+        p = Problem.from_workload(w, pat)
+        probs.append(p)
+        pats.append(pat)
+        G.append(to_dev(sketch_block(p.n_A, k_r + l, w.seed)))
+        b.append(p.rhs(to_dev(innovations(p.q, w.seed, 0.1))))
+    say("batch", [(w.n, w.N) for w in ws])
+    x = [_torch().zeros(p.n_A, dtype=_torch().float64, device=dev()) for p in probs]
+    infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=1e-6, maxit=3000, workers=3)
+    assert all(s == 0 for s in status), status
+    for i, (p, w) in enumerate(zip(probs, ws)):
+        say("  problem", i, w.n, w.N, "iters", infos[i]["iters"], infos[i]["relres_true"])
+        assert infos[i]["relres_true"] <= 1e-6
+        L = p.lmp_build("nystrom", k_r, l, G[i])
+        xs = _torch().zeros_like(x[i])
+        info = p.pcg(b[i], xs, L, tol=1e-6, maxit=3000, history=False)
+        L.close()
+        assert info["iters"] == infos[i]["iters"]
+        assert _torch().equal(xs, x[i])
+    # the smallest problem against the oracle's inner loop
+    j = int(np.argmin([p.n_A for p in probs]))
+    w, p = ws[j], probs[j]
+    op = O.make_problem(w, pats[j])
+    bo = O.rhs(op, innovations(p.q, w.seed, 0.1))
+    assert relerr(to_host(b[j]), bo) <= 1e-10
+    _, _, res = O.inner_loop(op, bo, sketch_block(op.n_A, k_r + l, w.seed), "nystrom", k_r, tol=1e-6, maxit=3000)
+    say("  oracle iters", res.iters, "gpu", infos[j]["iters"])
+    assert abs(res.iters - infos[j]["iters"]) <= 2
+    xg = to_host(x[j])
+    assert np.linalg.norm(bo - O.apply_A(op, xg)) / np.linalg.norm(bo) <= 1.01e-6
+    assert relerr(xg, res.x) <= 1e-4
+
+
+def test_batch_solve_rejects_bad_input():
+    from paper_2101_07249_amd import Problem, Wc4dError, batch_solve
+    w = small_batch(1)[0]
+    pat = obs_pattern(w)
+    p = Problem.from_workload(w, pat)
+    G = to_dev(sketch_block(p.n_A, 16, 1))
+    b = p.rhs(to_dev(innovations(p.q, 1, 0.1)))
+    x = _torch().zeros(p.n_A, dtype=_torch().float64, device=dev())
+    with pytest.raises(Wc4dError):
+        batch_solve([p, p], "revd", 11, 5, [G, G], [b, b], [x, x])
+    with pytest.raises(Wc4dError):
+        batch_solve([p], "revd", 11, 5, [G], [b], [x], workers=0)

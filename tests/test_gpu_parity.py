@@ -279,3 +279,36 @@ def test_error_paths():
     x = t.zeros(op.n_A, dtype=t.float64, device=dev())
     info = gp.pcg(t.zeros(op.n_A, dtype=t.float64, device=dev()), x, None, tol=1e-6, maxit=10)
     assert info["status"] == 0 and info["iters"] == 0
+
+
+def test_lmp_outliving_its_problem_is_rejected():
+    from paper_2101_07249_amd import Wc4dError
+    say("lmp after problem destroy")
+    w = tiny()
+    gp, op = pair(w)
+    L = gp.lmp_build("revd", 2, 2, to_dev(sketch_block(op.n_A, 4, 5)))
+    gp.close()
+    with pytest.raises(Wc4dError) as e:
+        L.theta()
+    assert e.value.code == -7
+    L.close()
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_ill_conditioned_sketch_takes_shifted_choleskyqr(method):
+    """Column 1 of G is column 0 plus 1e-9 times an independent Gaussian vector (full
+    rank, condition about 1e9): the Gram matrix of A G is far too
+    ill-conditioned for CholeskyQR2 (its Cholesky breaks down), so the build retries with
+    shifted CholeskyQR3.  The leading Ritz pairs still match the oracle (Householder QR)."""
+    say("shifted CholeskyQR", method)
+    gp, op = pair(C2)
+    G = sketch_block(op.n_A, C2.m, 41)
+    G[:, 1] = G[:, 0] + 1e-9 * random_block(op.n_A, 1, 42)[:, 0]
+    L = gp.lmp_build(method, C2.k_r, C2.l, to_dev(G))
+    th = L.theta()
+    U = to_host(L.vectors())
+    L.close()
+    _, th_o = O.METHODS[method](lambda X: O.apply_A(op, X), G, C2.k_r)
+    assert np.all(th >= 1.0 - 1e-8)
+    np.testing.assert_allclose(th[:5], th_o[:5], rtol=1e-4)
+    assert np.abs(U.T @ U - np.eye(C2.k_r)).max() <= 1e-9
