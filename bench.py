@@ -53,7 +53,24 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--batched", action="store_true", help="also time the 64-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file: loaded when present, written after tuning")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (reference for HBM counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of 2^27 doubles (1 GiB read + 1 GiB written), five
+    times: the reference that scales FETCH_SIZE / WRITE_SIZE counter readings to bytes."""
+    import torch
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copy_probe_bytes_written": y.numel() * 8,
+                      "launches": 5}), flush=True)
 
 
 def learned_section(args):
@@ -196,6 +213,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import numpy as np
     import torch
 
@@ -217,8 +237,16 @@ def main():
     precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32}
     names = [v for v in args.variants.split(",") if v]
     results = {}
+    tunes = {}
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        W4.autotune_load(args.tune_cache)
     for vname in names:
         prob = Problem.from_workload(w, pat, prec=precs[vname])
+        # one-time setup, outside the timed region: tile shapes of the D^{1/2} products for
+        # the single-vector PCG applies and the m-column block applies
+        tunes[vname] = {"m1": prob.autotune(1), f"m{w.m}": prob.autotune(w.m)}
+    if args.tune_cache:
+        W4.autotune_save(args.tune_cache)
 
         def step():
             b = prob.rhs(d)
@@ -300,7 +328,8 @@ def main():
         "config": {"workload": w.name, "variant": head, "method": args.method,
                    "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,
-                   "criterion": "true residual ||b - A x|| / ||b||"},
+                   "criterion": "true residual ||b - A x|| / ||b||",
+                   "autotuned_tiles": tunes.get(head)},
         "pcg_iters": iters, "relres_true": results[head]["relres_true"], "converged": ok,
         "variants": variants,
         "hessian_apply": hess,

@@ -239,9 +239,18 @@ int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, dou
  * Choices are cached per (device, n, N, m) for the life of the process, so later
  * problems of the same shape reuse them without timing.  Uses p's build scratch;
  * synchronises s.  wc4d_autotune_info reports the choice (tile codes: 1 split-K 64x16,
- * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32) and its measured ms. */
+ * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32; two_segment = 0 when the
+ * products run separately, else 1 + variant + 8 * splits of the two-segment launch with
+ * variant 0 = 64 rows / K step 32, 1 = 128 / 16, 2 = 128 / 32 and splits 0 = automatic)
+ * and its measured ms. */
 int wc4d_autotune(wc4d_problem p, int m, hipStream_t s);
 int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two_segment, float* ms);
+/* Write / merge the process-wide autotune cache as text (one line per (device, n, N, m):
+ * "device n N m tile_b tile_q two_segment variant splits ms").  A loaded entry is used
+ * by wc4d_autotune without timing, so separate processes run identical kernels.
+ * WC4D_EINVAL on an unreadable file or a malformed line (nothing is merged then). */
+int wc4d_autotune_save(const char* path);
+int wc4d_autotune_load(const char* path);
 
 /* Solve `count` independent inner loops (Section 2.2 / Algorithm 1) at once: for each
  * problem ps[i] (finalized, all on one device, none repeated) an LMP of k_r Ritz pairs

@@ -412,13 +412,14 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
     return WC4D_OK;
   }
   const DsqrtTune* t = find_tune(p, m);
+  const int var = t ? t->segVariant : 0, spl = t ? t->segSplits : 0;
   const bool two_ok = (long long)m * N <= 112 && m <= 112 &&
-                      dsqrt2_ws_doubles(n, m * N, m, n) <= p->wsSplitDoubles;
+                      dsqrt2_feasible(var, spl, n, m * N, m, n, p->wsSplitDoubles);
   const bool two = two_ok && (t != nullptr ? t->twoSeg : n >= 512);
   if (two) {
-    HIPCHK(p, dsqrt2_f64(n, n, X, Y, E, p->dQ, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n},
-                         ColMap{lde, N, 1, n}, m * N, p->dB, ColMap{ldx, 1, 0, n}, ColMap{ldy, 1, 0, n},
-                         ColMap{lde, 1, 0, n}, m, skip, p->wsSplit, p->wsSplitDoubles, s));
+    HIPCHK(p, dsqrt2_f64_v(var, spl, n, n, X, Y, E, p->dQ, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n},
+                           ColMap{lde, N, 1, n}, m * N, p->dB, ColMap{ldx, 1, 0, n}, ColMap{ldy, 1, 0, n},
+                           ColMap{lde, 1, 0, n}, m, skip, p->wsSplit, p->wsSplitDoubles, s));
     return WC4D_OK;
   }
   HIPCHK(p, gemm_f64_tile(t ? t->tileB : GEMM_AUTO, 0, n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, Y,

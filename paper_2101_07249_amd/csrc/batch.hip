@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -115,14 +116,18 @@ int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
   }
   (void)hipGetLastError();
   if (bestB < 0.f || bestQ < 0.f) return fail(p, WC4D_EHIP, "autotune: no tile shape could be timed");
-  DsqrtTune best{tileB, tileQ, false, bestB + bestQ};
-  if ((long long)m * N <= 112 && m <= 112 && dsqrt2_ws_doubles(n, m * N, m, n) <= p->wsSplitDoubles) {
-    const float ms = time_launch(s, ev, [&] {
-      return dsqrt2_f64(n, n, X, Y, X, p->dQ, xq, xq, xq, m * N, p->dB, x0, x0, x0, m, nullptr, p->wsSplit,
-                        p->wsSplitDoubles, s);
-    });
-    (void)hipGetLastError();
-    if (ms >= 0.f && ms < best.ms) best = DsqrtTune{tileB, tileQ, true, ms};
+  DsqrtTune best{tileB, tileQ, false, 0, 0, bestB + bestQ};
+  if ((long long)m * N <= 112 && m <= 112) {
+    for (int v = 0; v < DSQRT2_NVARIANTS; ++v)
+      for (int sp : {0, 4, 8, 16, 32}) {
+        if (!dsqrt2_feasible(v, sp, n, m * N, m, n, p->wsSplitDoubles)) continue;
+        const float ms = time_launch(s, ev, [&] {
+          return dsqrt2_f64_v(v, sp, n, n, X, Y, X, p->dQ, xq, xq, xq, m * N, p->dB, x0, x0, x0, m, nullptr,
+                              p->wsSplit, p->wsSplitDoubles, s);
+        });
+        (void)hipGetLastError();
+        if (ms >= 0.f && ms < best.ms) best = DsqrtTune{tileB, tileQ, true, v, sp, ms};
+      }
   }
   set_tune(p, m, best);
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -136,8 +141,50 @@ int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two
   if (t == nullptr) return fail(p, WC4D_ESTATE, "no autotuned shape for this block width");
   if (tile_b) *tile_b = t->tileB;
   if (tile_q) *tile_q = t->tileQ;
-  if (two_segment) *two_segment = t->twoSeg ? 1 : 0;
+  if (two_segment) *two_segment = t->twoSeg ? 1 + t->segVariant + 8 * t->segSplits : 0;
   if (ms) *ms = t->ms;
+  return WC4D_OK;
+}
+
+int wc4d_autotune_save(const char* path) {
+  if (path == nullptr) return WC4D_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  FILE* fp = std::fopen(path, "w");
+  if (fp == nullptr) return WC4D_EINVAL;
+  bool ok = std::fprintf(fp, "# wc4d autotune cache: device n N m tile_b tile_q two_segment variant splits ms\n") > 0;
+  for (const auto& e : g_tune_cache) {
+    const DsqrtTune& t = e.second;
+    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %.6f\n", std::get<0>(e.first), std::get<1>(e.first),
+                            std::get<2>(e.first), std::get<3>(e.first), t.tileB, t.tileQ, t.twoSeg ? 1 : 0,
+                            t.segVariant, t.segSplits, (double)t.ms) > 0;
+  }
+  ok = (std::fclose(fp) == 0) && ok;
+  return ok ? WC4D_OK : WC4D_EINVAL;
+}
+
+int wc4d_autotune_load(const char* path) {
+  if (path == nullptr) return WC4D_EINVAL;
+  FILE* fp = std::fopen(path, "r");
+  if (fp == nullptr) return WC4D_EINVAL;
+  std::map<std::tuple<int, int, int, int>, DsqrtTune> got;
+  char line[256];
+  bool ok = true;
+  while (std::fgets(line, sizeof(line), fp) != nullptr) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int d, n, N, m, tb, tq, two, var, spl;
+    double ms;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf", &d, &n, &N, &m, &tb, &tq, &two, &var, &spl, &ms) != 10 ||
+        tb <= GEMM_AUTO || tb >= GEMM_NTILES || tq <= GEMM_AUTO || tq >= GEMM_NTILES || var < 0 ||
+        var >= DSQRT2_NVARIANTS || spl < 0) {
+      ok = false;
+      break;
+    }
+    got[std::make_tuple(d, n, N, m)] = DsqrtTune{tb, tq, two != 0, var, spl, (float)ms};
+  }
+  std::fclose(fp);
+  if (!ok) return WC4D_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : got) g_tune_cache[e.first] = e.second;
   return WC4D_OK;
 }
 

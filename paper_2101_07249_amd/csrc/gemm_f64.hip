@@ -276,12 +276,15 @@ struct Seg {
   size_t wsoff;  // doubles
 };
 
-constexpr int SBM = 64, SBN = 112, SBK = 32;
+constexpr int SBN = 112;
 
+// SBM rows x SBN columns per workgroup, K staged SBK at a time; 4 waves each own SBM / 4
+// rows (SBM / 64 MFMA row blocks) and all SBN columns.
+template <int SBM, int SBK>
 __global__ __launch_bounds__(256) void k_dsqrt2(int M, int K, long long lda, const double* __restrict__ B,
                                                 Seg s1, Seg s2, double* __restrict__ ws,
                                                 const int* __restrict__ skip) {
-  constexpr int WI = SBM / 4, WJ = SBN;
+  constexpr int WI = SBM / 4, RB = WI / 16, WJ = SBN;
   constexpr int TJ = WJ / 16;
   constexpr int NA = SBM * SBK / 256, NB = SBN * SBK / 256;
   __shared__ double As[SBK][SBM + 4];
@@ -297,9 +300,11 @@ __global__ __launch_bounds__(256) void k_dsqrt2(int M, int K, long long lda, con
   const int wi0 = wave * WI;
   const int kbeg = z * sg.kchunk;
   const int kend = min(K, kbeg + sg.kchunk);
-  d4 acc[TJ];
+  d4 acc[RB][TJ];
 #pragma unroll
-  for (int a = 0; a < TJ; ++a) acc[a] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int a = 0; a < TJ; ++a) acc[r][a] = d4{0.0, 0.0, 0.0, 0.0};
   long long boff[NB];
   bool bval[NB];
 #pragma unroll
@@ -340,23 +345,31 @@ __global__ __launch_bounds__(256) void k_dsqrt2(int M, int K, long long lda, con
 #pragma unroll
     for (int kk = 0; kk < SBK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      const double bv = As[kr][wi0 + (lane & 15)];
+      double bv[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) bv[r] = As[kr][wi0 + 16 * r + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < TJ; ++a) {
-        if (a * 16 < ncol) acc[a] = mfma16x16x4(Bs[kr][a * 16 + (lane & 15)], bv, acc[a]);
+        if (a * 16 < ncol) {
+          const double xv = Bs[kr][a * 16 + (lane & 15)];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) acc[r][a] = mfma16x16x4(xv, bv[r], acc[r][a]);
+        }
       }
     }
   }
   double* wz = ws + sg.wsoff + (size_t)z * M * ncol;
 #pragma unroll
-  for (int a = 0; a < TJ; ++a) {
+  for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = a * 16 + (lane >> 4) + 4 * r;
-      const int i = i0 + wi0 + (lane & 15);
-      if (j < ncol && i < M) wz[(size_t)j * M + i] = acc[a][r];
+    for (int a = 0; a < TJ; ++a) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = a * 16 + (lane >> 4) + 4 * q;
+        const int i = i0 + wi0 + 16 * r + (lane & 15);
+        if (j < ncol && i < M) wz[(size_t)j * M + i] = acc[r][a][q];
+      }
     }
-  }
 }
 
 __global__ void k_dsqrt2_reduce(int M, Seg s1, Seg s2, double alpha, const double* __restrict__ ws,
@@ -378,31 +391,61 @@ __global__ void k_dsqrt2_reduce(int M, Seg s1, Seg s2, double alpha, const doubl
   }
 }
 
+static int dsqrt2_rows(int variant) { return variant == 0 ? 64 : 128; }
+
+// K splits of a two-segment launch: the request (or enough to give ~512 workgroups per
+// segment), at most K / 256, and no more than ws holds (0 when even 1 split does not fit).
+static int dsqrt2_splits(int variant, int splits, int M, int n1, int n2, int K, size_t ws_doubles) {
+  const int tiles = (M + dsqrt2_rows(variant) - 1) / dsqrt2_rows(variant);
+  int sp = splits > 0 ? splits : (512 + tiles - 1) / tiles;
+  sp = std::max(1, std::min(sp, std::max(1, K / 256)));
+  while (sp > 1 && (size_t)sp * M * (n1 + n2) > ws_doubles) --sp;
+  return ((size_t)sp * M * (n1 + n2) <= ws_doubles) ? sp : 0;
+}
+
 size_t dsqrt2_ws_doubles(int M, int n1, int n2, int K) {
-  const int tiles = (M + SBM - 1) / SBM;
+  const int tiles = (M + 63) / 64;
   const int sp = std::max(1, std::min((512 + tiles - 1) / tiles, K / 256));
   return (size_t)sp * M * (n1 + n2);
 }
 
-hipError_t dsqrt2_f64(int M, int K, const double* B, double* C, const double* E, const double* A1,
-                      ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2, ColMap c2,
-                      ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles, hipStream_t s) {
-  if (n1 > SBN || n2 > SBN || n1 < 1 || n2 < 1) return hipErrorInvalidValue;
-  const int tiles = (M + SBM - 1) / SBM;
-  int sp = std::max(1, std::min((512 + tiles - 1) / tiles, K / 256));
-  if ((size_t)sp * M * (n1 + n2) > ws_doubles) return hipErrorInvalidValue;
+bool dsqrt2_feasible(int variant, int splits, int M, int n1, int n2, int K, size_t ws_doubles) {
+  if (variant < 0 || variant >= DSQRT2_NVARIANTS || n1 > SBN || n2 > SBN || n1 < 1 || n2 < 1) return false;
+  const int sp = dsqrt2_splits(variant, splits, M, n1, n2, K, ws_doubles);
+  return sp > 0 && (splits <= 0 || sp == splits);
+}
+
+hipError_t dsqrt2_f64_v(int variant, int splits, int M, int K, const double* B, double* C, const double* E,
+                        const double* A1, ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2,
+                        ColMap c2, ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles,
+                        hipStream_t s) {
+  if (!dsqrt2_feasible(variant, splits, M, n1, n2, K, ws_doubles)) return hipErrorInvalidValue;
+  int sp = dsqrt2_splits(variant, splits, M, n1, n2, K, ws_doubles);
+  const int sbk = variant == 1 ? 16 : 32;
   int kchunk = (K + sp - 1) / sp;
-  kchunk = (kchunk + SBK - 1) / SBK * SBK;
+  kchunk = (kchunk + sbk - 1) / sbk * sbk;
   sp = (K + kchunk - 1) / kchunk;
   Seg s1{A1, b1, c1, e1, n1, sp, kchunk, 0};
   Seg s2{A2, b2, c2, e2, n2, sp, kchunk, (size_t)sp * M * n1};
-  hipLaunchKernelGGL(k_dsqrt2, dim3(tiles, 1, 2 * sp), dim3(256), 0, s, M, K, (long long)M, B, s1, s2,
-                     ws, skip);
+  const int rows = dsqrt2_rows(variant);
+  const dim3 grid((M + rows - 1) / rows, 1, 2 * sp);
+  if (variant == 0)
+    hipLaunchKernelGGL((k_dsqrt2<64, 32>), grid, dim3(256), 0, s, M, K, (long long)M, B, s1, s2, ws, skip);
+  else if (variant == 1)
+    hipLaunchKernelGGL((k_dsqrt2<128, 16>), grid, dim3(256), 0, s, M, K, (long long)M, B, s1, s2, ws, skip);
+  else
+    hipLaunchKernelGGL((k_dsqrt2<128, 32>), grid, dim3(256), 0, s, M, K, (long long)M, B, s1, s2, ws, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 rg((M + 255) / 256 < 64 ? (M + 255) / 256 : 64, n1 + n2);
   hipLaunchKernelGGL(k_dsqrt2_reduce, rg, dim3(256), 0, s, M, s1, s2, 1.0, ws, C, E, skip);
   return hipGetLastError();
+}
+
+hipError_t dsqrt2_f64(int M, int K, const double* B, double* C, const double* E, const double* A1,
+                      ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2, ColMap c2,
+                      ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles, hipStream_t s) {
+  return dsqrt2_f64_v(0, 0, M, K, B, C, E, A1, b1, c1, e1, n1, A2, b2, c2, e2, n2, skip, ws, ws_doubles, s);
 }
 
 // ------------------------------------------------------------------ Gram

@@ -407,6 +407,348 @@ __global__ __launch_bounds__(512) void k_sweep_bwd(SweepModel md, const double* 
   }
 }
 
+// ------------------------------------------- single-vector Lorenz-96 sweeps
+// For one column the N RK4 steps are a chain of dependent stencil updates on n points.
+// One wavefront owns the whole state: lane l holds the PPT contiguous points
+// [l PPT, (l + 1) PPT) in registers (n = 64 PPT); neighbour values of the state and the
+// stage increments come from the adjacent lanes by shuffles (periodic: lane 0 and lane
+// 63 are neighbours), so a step needs no workgroup barrier for them.  The RK4 stage
+// inputs y1..y4 of the next step are loaded into registers (coalesced) while the
+// current step computes, then parked in a padded LDS double buffer from which each
+// lane reads its chunk and halo.  Observations use an n-double LDS buffer.
+constexpr int kVL = 64;
+
+template <int PPT>
+static __device__ inline int vpad(int j) {
+  return j + j / PPT;  // one spare double per chunk spreads the lanes over the banks
+}
+
+// u at chunk offsets -2..PPT+1 from the lane's registers and its neighbours'.
+template <int PPT>
+struct Halo {
+  double m2, m1, p1, p2;
+};
+
+template <int PPT>
+static __device__ inline Halo<PPT> halo(const double (&u)[PPT], int lane) {
+  const int lp = (lane + kVL - 1) & (kVL - 1), ln = (lane + 1) & (kVL - 1);
+  Halo<PPT> h;
+  h.m2 = __shfl(u[PPT - 2], lp);
+  h.m1 = __shfl(u[PPT - 1], lp);
+  h.p1 = __shfl(u[0], ln);
+  h.p2 = __shfl(u[1], ln);
+  return h;
+}
+
+template <int PPT>
+static __device__ inline double at(const double (&u)[PPT], const Halo<PPT>& h, int e) {
+  // e in [-2, PPT + 1]; resolved at compile time after unrolling
+  return e == -2 ? h.m2 : e == -1 ? h.m1 : e == PPT ? h.p1 : e == PPT + 1 ? h.p2 : u[e];
+}
+
+// y of one stage over the chunk and a 2-point halo on each side: yv[e + 2], e in [-2, PPT + 1].
+template <int PPT>
+static __device__ inline void load_y(const double* ysb, int n, int j0, double (&yv)[PPT + 4]) {
+#pragma unroll
+  for (int e = -2; e < PPT + 2; ++e) {
+    int j = j0 + e;
+    j = j < 0 ? j + n : (j >= n ? j - n : j);
+    yv[e + 2] = ysb[vpad<PPT>(j)];
+  }
+}
+
+// d = J(y) u at the lane's points: (u_{j+1} - u_{j-2}) y_{j-1} + (y_{j+1} - y_{j-2}) u_{j-1} - u_j.
+template <int PPT>
+static __device__ inline void jac_v(const double (&yv)[PPT + 4], const double (&u)[PPT], int lane,
+                                    double (&d)[PPT]) {
+  const Halo<PPT> h = halo<PPT>(u, lane);
+#pragma unroll
+  for (int e = 0; e < PPT; ++e)
+    d[e] = (at<PPT>(u, h, e + 1) - at<PPT>(u, h, e - 2)) * yv[e + 1] +
+           (yv[e + 3] - yv[e]) * at<PPT>(u, h, e - 1) - u[e];
+}
+
+// d = J(y)^T a: y_{j-2} a_{j-1} - y_{j+1} a_{j+2} + (y_{j+2} - y_{j-1}) a_{j+1} - a_j.
+template <int PPT>
+static __device__ inline void jacT_v(const double (&yv)[PPT + 4], const double (&a)[PPT], int lane,
+                                     double (&d)[PPT]) {
+  const Halo<PPT> h = halo<PPT>(a, lane);
+#pragma unroll
+  for (int e = 0; e < PPT; ++e)
+    d[e] = yv[e] * at<PPT>(a, h, e - 1) - yv[e + 3] * at<PPT>(a, h, e + 2) +
+           (yv[e + 4] - yv[e + 1]) * at<PPT>(a, h, e + 1) - a[e];
+}
+
+template <int PPT>
+size_t l96v_lds_bytes(int n) {
+  // two stage-input buffers (4 padded levels each), the observation buffer, the transpose buffer
+  return sizeof(double) * ((size_t)9 * (n + n / PPT) + n);
+}
+
+// Chunk layout (lane l holds points l PPT + e) <-> coalesced layout (lane l holds l + 64 q),
+// through the padded LDS buffer tr: global loads and stores then cover 64 consecutive
+// doubles per instruction.
+template <int PPT>
+static __device__ inline void to_chunk(double* tr, int lane, const double (&co)[PPT], double (&ch)[PPT]) {
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) tr[vpad<PPT>(lane + kVL * q)] = co[q];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) ch[e] = tr[vpad<PPT>(lane * PPT + e)];
+}
+
+template <int PPT>
+static __device__ inline void to_coalesced(double* tr, int lane, const double (&ch)[PPT], double (&co)[PPT]) {
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) tr[vpad<PPT>(lane * PPT + e)] = ch[e];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) co[q] = tr[vpad<PPT>(lane + kVL * q)];
+}
+
+// One stage (s) of step i's inputs: entries lane + 64 q, q < PPT, of level s.
+template <int PPT>
+static __device__ inline void pfs_load(const double* stages, int i, int s, int n, int lane, double (&pf)[PPT]) {
+  const double* src = stages + (size_t)i * 4 * n + (size_t)s * n;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) pf[q] = src[lane + kVL * q];
+}
+
+template <int PPT>
+static __device__ inline void pfs_store(double* ysb, int s, int n, int lane, const double (&pf)[PPT]) {
+  double* dst = ysb + (size_t)s * (n + n / PPT);
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) dst[vpad<PPT>(lane + kVL * q)] = pf[q];
+}
+
+template <int PPT>
+__global__ __launch_bounds__(64) void k_l96v_fwd(SweepModel md, const double* __restrict__ P,
+                                                 double* __restrict__ stash, double* __restrict__ Xout,
+                                                 const int* __restrict__ skip) {
+  extern __shared__ double vlds[];
+  if (skip != nullptr && *skip != 0) return;
+  const int n = md.n, N = md.N, lane = threadIdx.x;
+  const int sp = n + n / PPT;
+  double* ysb[2] = {vlds, vlds + 4 * sp};
+  double* xs = vlds + 8 * sp;
+  double* tr = xs + n;
+  const double dt = md.dt;
+  double x[PPT], pn[PPT], co[PPT], pf[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) co[q] = P[lane + kVL * q];
+  to_chunk<PPT>(tr, lane, co, x);
+  auto store_x = [&](int lev) {
+    if (Xout == nullptr) return;
+    to_coalesced<PPT>(tr, lane, x, co);
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) Xout[(size_t)lev * n + lane + kVL * q] = co[q];
+  };
+  auto gather = [&](int lev) {
+    const int kb = md.obs_off[lev], ke = md.obs_off[lev + 1];
+    if (stash == nullptr || kb == ke) return;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) xs[lane * PPT + e] = x[e];
+    __syncthreads();
+    for (int k = kb + lane; k < ke; k += kVL) stash[k] = md.obs_rinv[k] * xs[md.obs_idx[k]];
+  };
+  store_x(0);
+  gather(0);
+  for (int st = 0; st < 4 && N > 0; ++st) {
+    pfs_load<PPT>(md.stages, 0, st, n, lane, pf);
+    pfs_store<PPT>(ysb[0], st, n, lane, pf);
+  }
+  __syncthreads();
+  const int j0 = lane * PPT;
+  for (int i = 0; i < N; ++i) {
+    const double* yb = ysb[i & 1];
+    double* ynext = ysb[(i + 1) & 1];
+    const bool more = i + 1 < N;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) co[q] = P[(size_t)(i + 1) * n + lane + kVL * q];
+    double yv[PPT + 4], d[PPT], t[PPT], acc[PPT];
+    if (more) pfs_load<PPT>(md.stages, i + 1, 0, n, lane, pf);
+    load_y<PPT>(yb, n, j0, yv);
+    jac_v<PPT>(yv, x, lane, d);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      acc[e] = d[e];
+      t[e] = x[e] + 0.5 * dt * d[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 0, n, lane, pf);
+      pfs_load<PPT>(md.stages, i + 1, 1, n, lane, pf);
+    }
+    load_y<PPT>(yb + sp, n, j0, yv);
+    jac_v<PPT>(yv, t, lane, d);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      acc[e] += 2.0 * d[e];
+      t[e] = x[e] + 0.5 * dt * d[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 1, n, lane, pf);
+      pfs_load<PPT>(md.stages, i + 1, 2, n, lane, pf);
+    }
+    load_y<PPT>(yb + 2 * sp, n, j0, yv);
+    jac_v<PPT>(yv, t, lane, d);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      acc[e] += 2.0 * d[e];
+      t[e] = x[e] + dt * d[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 2, n, lane, pf);
+      pfs_load<PPT>(md.stages, i + 1, 3, n, lane, pf);
+    }
+    load_y<PPT>(yb + 3 * sp, n, j0, yv);
+    jac_v<PPT>(yv, t, lane, d);
+    if (more) pfs_store<PPT>(ynext, 3, n, lane, pf);
+    to_chunk<PPT>(tr, lane, co, pn);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) x[e] = x[e] + (dt / 6.0) * (acc[e] + d[e]) + pn[e];
+    store_x(i + 1);
+    gather(i + 1);
+    __syncthreads();
+  }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(64) void k_l96v_bwd(SweepModel md, const double* __restrict__ stash,
+                                                 const double* __restrict__ Z, double* __restrict__ W,
+                                                 const int* __restrict__ skip) {
+  extern __shared__ double vlds[];
+  if (skip != nullptr && *skip != 0) return;
+  const int n = md.n, N = md.N, lane = threadIdx.x, j0 = lane * PPT;
+  const int sp = n + n / PPT;
+  double* ysb[2] = {vlds, vlds + 4 * sp};
+  double* xs = vlds + 8 * sp;
+  double* tr = xs + n;
+  const double dt = md.dt;
+  double w[PPT], co[PPT], pf[PPT];
+  // z_i added into w: dense rows of Z, or H_i^T stash_i scattered through LDS
+  auto add_z = [&](int lev) {
+    if (stash == nullptr) {
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) co[q] = Z[(size_t)lev * n + lane + kVL * q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) tr[vpad<PPT>(lane + kVL * q)] = co[q];
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) w[e] += tr[vpad<PPT>(j0 + e)];
+      return;
+    }
+    const int kb = md.obs_off[lev], ke = md.obs_off[lev + 1];
+    if (kb == ke) return;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) xs[j0 + e] = 0.0;
+    __syncthreads();
+    for (int k = kb + lane; k < ke; k += kVL) xs[md.obs_idx[k]] = stash[k];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) w[e] += xs[j0 + e];
+  };
+  auto store_w = [&](int lev) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) tr[vpad<PPT>(j0 + e)] = w[e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) W[(size_t)lev * n + lane + kVL * q] = tr[vpad<PPT>(lane + kVL * q)];
+  };
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) w[e] = 0.0;
+  add_z(N);
+  store_w(N);
+  for (int st = 0; st < 4 && N > 0; ++st) {
+    pfs_load<PPT>(md.stages, N - 1, st, n, lane, pf);
+    pfs_store<PPT>(ysb[(N - 1) & 1], st, n, lane, pf);
+  }
+  __syncthreads();
+  for (int i = N - 1; i >= 0; --i) {
+    const double* yb = ysb[i & 1];
+    double* ynext = ysb[(i - 1) & 1];
+    const bool more = i > 0;
+    double yv[PPT + 4], u[PPT], ax[PPT], t[PPT];
+    if (more) pfs_load<PPT>(md.stages, i - 1, 3, n, lane, pf);
+    load_y<PPT>(yb + 3 * sp, n, j0, yv);
+    jacT_v<PPT>(yv, w, lane, u);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      u[e] *= dt / 6.0;
+      ax[e] = w[e] + u[e];
+      t[e] = (dt / 3.0) * w[e] + dt * u[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 3, n, lane, pf);
+      pfs_load<PPT>(md.stages, i - 1, 2, n, lane, pf);
+    }
+    load_y<PPT>(yb + 2 * sp, n, j0, yv);
+    jacT_v<PPT>(yv, t, lane, u);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      ax[e] += u[e];
+      t[e] = (dt / 3.0) * w[e] + 0.5 * dt * u[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 2, n, lane, pf);
+      pfs_load<PPT>(md.stages, i - 1, 1, n, lane, pf);
+    }
+    load_y<PPT>(yb + sp, n, j0, yv);
+    jacT_v<PPT>(yv, t, lane, u);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      ax[e] += u[e];
+      t[e] = (dt / 6.0) * w[e] + 0.5 * dt * u[e];
+    }
+    if (more) {
+      pfs_store<PPT>(ynext, 1, n, lane, pf);
+      pfs_load<PPT>(md.stages, i - 1, 0, n, lane, pf);
+    }
+    load_y<PPT>(yb, n, j0, yv);
+    jacT_v<PPT>(yv, t, lane, u);
+    if (more) pfs_store<PPT>(ynext, 0, n, lane, pf);
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) w[e] = ax[e] + u[e];
+    add_z(i);
+    store_w(i);
+    __syncthreads();
+  }
+}
+
+// PPT for a single-vector Lorenz-96 sweep (0: not applicable).
+static int l96v_ppt(const SweepModel& md, int m) {
+  if (md.kind != 1 || m != 1 || md.n % kVL != 0) return 0;
+  const int ppt = md.n / kVL;
+  return (ppt == 4 || ppt == 8 || ppt == 16) ? ppt : 0;
+}
+
+template <int PPT>
+static hipError_t l96v_fwd_launch(const SweepModel& md, const double* P, double* stash, double* Xout,
+                                  const int* skip, hipStream_t s) {
+  const size_t lds = l96v_lds_bytes<PPT>(md.n);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_l96v_fwd<PPT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_l96v_fwd<PPT>, dim3(1), dim3(kVL), lds, s, md, P, stash, Xout, skip);
+  return hipGetLastError();
+}
+
+template <int PPT>
+static hipError_t l96v_bwd_launch(const SweepModel& md, const double* stash, const double* Z, double* W,
+                                  const int* skip, hipStream_t s) {
+  const size_t lds = l96v_lds_bytes<PPT>(md.n);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_l96v_bwd<PPT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_l96v_bwd<PPT>, dim3(1), dim3(kVL), lds, s, md, stash, Z, W, skip);
+  return hipGetLastError();
+}
+
 // ------------------------------------------- time-blocked advection-diffusion
 // For one or a few columns the window's N sequential steps over the whole domain
 // are latency-bound.  The stencil has radius 1, so a workgroup can own W points
@@ -682,6 +1024,12 @@ static size_t sweep_lds_bytes(const SweepModel& md, const SweepCfg& c) {
 hipError_t sweep_fwd(const SweepModel& md, const double* P, long long ldp, int m, double* stash,
                      long long ldst, double* Xout, long long ldx, const int* skip, hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  switch (l96v_ppt(md, m)) {
+    case 4: return l96v_fwd_launch<4>(md, P, stash, Xout, skip, s);
+    case 8: return l96v_fwd_launch<8>(md, P, stash, Xout, skip, s);
+    case 16: return l96v_fwd_launch<16>(md, P, stash, Xout, skip, s);
+    default: break;
+  }
   const TbCfg tc = tb_cfg(md.n, md.N);
   if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
     dim3 grid((md.n + tc.W - 1) / tc.W, m);
@@ -708,6 +1056,12 @@ hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, 
                      long long ldz, int m, double* W, long long ldw, const int* skip,
                      hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  switch (l96v_ppt(md, m)) {
+    case 4: return l96v_bwd_launch<4>(md, stash, Z, W, skip, s);
+    case 8: return l96v_bwd_launch<8>(md, stash, Z, W, skip, s);
+    case 16: return l96v_bwd_launch<16>(md, stash, Z, W, skip, s);
+    default: break;
+  }
   const TbCfg tc = tb_cfg(md.n, md.N);
   if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
     dim3 grid((md.n + tc.W - 1) / tc.W, m);

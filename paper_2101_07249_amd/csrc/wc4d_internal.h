@@ -59,6 +59,15 @@ hipError_t dsqrt2_f64(int M, int K, const double* B, double* C, const double* E,
                       ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2, ColMap c2,
                       ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles, hipStream_t s);
 
+// Tile variants of the two-segment product (autotuner candidates): 0 = 64 rows, K step 32;
+// 1 = 128 rows, K step 16; 2 = 128 rows, K step 32.  splits = 0 picks the count.
+constexpr int DSQRT2_NVARIANTS = 3;
+bool dsqrt2_feasible(int variant, int splits, int M, int n1, int n2, int K, size_t ws_doubles);
+hipError_t dsqrt2_f64_v(int variant, int splits, int M, int K, const double* B, double* C, const double* E,
+                        const double* A1, ColMap b1, ColMap c1, ColMap e1, int n1, const double* A2, ColMap b2,
+                        ColMap c2, ColMap e2, int n2, const int* skip, double* ws, size_t ws_doubles,
+                        hipStream_t s);
+
 // G(i, j) = sum_k X(k, i) Y(k, j), i < m1, j < m2, k < K; X / Y columns via maps.
 // Deterministic split-K: partial tiles then a fixed-order sum.  G column-major, ldg.
 // ws must hold gram_ws_doubles(m1, m2, K) doubles.
@@ -236,6 +245,8 @@ struct DsqrtTune {
   int tileB = 0;      // GemmTile of the B^{1/2} product (m columns)
   int tileQ = 0;      // GemmTile of the Q^{1/2} product (m N columns)
   bool twoSeg = false;  // one two-segment split-K launch instead of both
+  int segVariant = 0;   // its tile variant and K splits (0: heuristic)
+  int segSplits = 0;
   float ms = 0.f;     // measured time of the chosen form
 };
 

@@ -85,6 +85,8 @@ _SIGS = {
     "wc4d_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "wc4d_autotune_info": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p, _c_int_p,
                                           ctypes.POINTER(ctypes.c_float)]),
+    "wc4d_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "wc4d_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "wc4d_batch_solve": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                         ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
@@ -392,7 +394,10 @@ class Problem:
         ms = ctypes.c_float()
         self._chk(lib().wc4d_autotune_info(self._h, int(m), ctypes.byref(tb), ctypes.byref(tq), ctypes.byref(two),
                                            ctypes.byref(ms)), "autotune_info")
-        return {"tile_b": tb.value, "tile_q": tq.value, "two_segment": bool(two.value), "ms": ms.value}
+        seg = two.value
+        return {"tile_b": tb.value, "tile_q": tq.value, "two_segment": seg > 0,
+                "segment_variant": (seg - 1) % 8 if seg else None, "segment_splits": (seg - 1) // 8 if seg else None,
+                "ms": ms.value}
 
     def pcg(self, b, x, lmp: Optional[Lmp] = None, tol: float = 1e-6, maxit: int = 100,
             criterion: int = RES_TRUE, history: bool = True, variant: int = PCG_FUSED, stream=None):
@@ -448,6 +453,18 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def autotune_save(path: str):
+    rc = lib().wc4d_autotune_save(os.fsencode(path))
+    if rc:
+        raise Wc4dError(rc, f"wc4d_autotune_save({path})")
+
+
+def autotune_load(path: str):
+    rc = lib().wc4d_autotune_load(os.fsencode(path))
+    if rc:
+        raise Wc4dError(rc, f"wc4d_autotune_load({path})")
 
 
 def batch_solve(problems: Sequence[Problem], method, k_r: int, l: int, G, b, x, tol: float = 1e-6,

@@ -60,3 +60,24 @@ def test_corr_sqrt_rejects_bad_arguments():
     out = np.empty((4, 4))
     assert wc4d.lib().wc4d_corr_sqrt(4, 7, 1.0, 1.0, out.ctypes.data_as(wc4d._c_dbl_p)) == wc4d.EINVAL
     assert wc4d.lib().wc4d_corr_sqrt(4, 0, -1.0, 1.0, out.ctypes.data_as(wc4d._c_dbl_p)) == wc4d.EINVAL
+
+
+def test_autotune_cache_file_roundtrip(tmp_path):
+    """The autotune cache is host-side text: loading validates every line, saving writes
+    what was merged (no GPU call involved)."""
+    from paper_2101_07249_amd import wc4d as W4
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\n0 4096 100 1 1 2 1 1 8 0.116\n0 512 10 64 6 6 0 0 0 1.5\n")
+    W4.autotune_load(str(good))
+    out = tmp_path / "out.txt"
+    W4.autotune_save(str(out))
+    lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert ["0", "4096", "100", "1", "1", "2", "1", "1", "8"] in [l[:9] for l in lines]
+    assert ["0", "512", "10", "64", "6", "6", "0", "0", "0"] in [l[:9] for l in lines]
+    bad = tmp_path / "bad.txt"
+    for text in ("0 4096 100 1 9 2 1 1 8 0.1\n", "0 4096 100 1 1 2 1 7 8 0.1\n", "0 4096 100\n"):
+        bad.write_text(text)
+        with pytest.raises(W4.Wc4dError):
+            W4.autotune_load(str(bad))
+    with pytest.raises(W4.Wc4dError):
+        W4.autotune_load(str(tmp_path / "missing.txt"))

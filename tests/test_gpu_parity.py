@@ -76,6 +76,9 @@ CASES = {
     "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # 2 chunks, ragged last chunk, 1 point/thread
     "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # 4 chunks of 312
     "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # 2 points/thread, chunks of 624
+    # single-vector Lorenz-96 sweeps (m = 1, n = 64 PPT): one wavefront, shuffled halos
+    "l96_v4": tiny("l96", n=256, N=9, vs=3, ts=2),
+    "l96_v16": tiny("l96", n=1024, N=20, vs=5, ts=4),
 }
 
 

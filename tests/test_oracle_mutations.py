@@ -108,3 +108,64 @@ def test_pcg_wrong_beta_is_caught(monkeypatch):
         return O.PCGResult(x, it, hist[-1] <= tol, hist[-1], hist[-1], 0.0, hist, hist, [0.0] * it, [], [])
     monkeypatch.setattr(O, "pcg", bad)
     assert _fails(pins.test_cg_finite_termination_on_three_distinct_eigenvalues)
+
+
+# ------------------------------------------------------------ learned-sketch oracle
+import tests.test_sketchnet_oracle as skpins  # noqa: E402
+from oracle import sketchnet_oracle as SK  # noqa: E402
+
+
+def test_sketchnet_wrong_tap_direction_is_caught(monkeypatch):
+    orig = SK._conv
+    monkeypatch.setattr(SK, "_conv", lambda W, b, A: orig(W[:, :, ::-1], b, A))
+    assert _fails(skpins.test_conv_matches_fft_circular_correlation)
+    assert _fails(skpins.test_conv_tap_direction_hand_example)
+
+
+def test_sketchnet_dropped_tanh_derivative_is_caught(monkeypatch):
+    orig = SK.backward
+
+    def no_deriv(theta, acts, dG, round_fp16=True):
+        params = SK._rounded(theta, acts[0].shape[1], round_fp16)
+        T, _, n = acts[0].shape
+        m = params[-1][0].shape[0]
+        dH = dG.reshape(T, n, m).transpose(0, 2, 1)
+        grads = []
+        for l in range(len(params) - 1, -1, -1):
+            W, b = params[l]
+            A = acts[l]
+            dW = np.zeros_like(W)
+            for t in range(SK.KW):
+                dW[:, :, t] = np.einsum("Ton,Tcn->oc", dH, np.roll(A, -(t - 2), axis=2))
+            grads.append((dW, dH.sum(axis=(0, 2))))
+            if l == 0:
+                break
+            dA = np.zeros_like(A)
+            for t in range(SK.KW):
+                dA += np.roll(np.einsum("oc,Ton->Tcn", W[:, :, t], dH), (t - 2), axis=2)
+            dH = dA                      # missing (1 - A^2)
+        grads.reverse()
+        return np.concatenate([np.concatenate([dW.ravel(), db]) for dW, db in grads])
+    monkeypatch.setattr(SK, "backward", no_deriv)
+    assert _fails(skpins.test_backward_matches_finite_differences)
+    assert orig is not None
+
+
+def test_capture_loss_gradient_sign_is_caught(monkeypatch):
+    orig = SK.capture_loss
+
+    def bad(applyA, G, U, theta):
+        f, g = orig(applyA, G, U, theta)
+        return f, -g
+    monkeypatch.setattr(SK, "capture_loss", bad)
+    assert _fails(skpins.test_capture_loss_through_operator_and_fd)
+
+
+def test_adam_without_bias_correction_is_caught(monkeypatch):
+    def bad(theta, g, mom, vel, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+        mom[:] = b1 * mom + (1 - b1) * g
+        vel[:] = b2 * vel + (1 - b2) * g * g
+        theta -= lr * mom / (np.sqrt(vel) + eps)
+        return theta
+    monkeypatch.setattr(SK, "adam_step", bad)
+    assert _fails(skpins.test_adam_first_steps)
