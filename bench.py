@@ -32,6 +32,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+
+# HBM bytes per launch group of the single-vector float64 D^{1/2} product at n = 4096,
+# N = 100, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each scaled by a 1 GiB copy's
+# reading; profiles/dsqrt_vec_n4096_N100_counters.md).  Valid only for the kernel that was
+# measured: the two-segment launch (variant 1, 8 splits) built from this gemm_f64.hip.
+MEASURED_TRAFFIC = {"n": 4096, "N": 100, "segment_variant": 1, "segment_splits": 8,
+                    "source": "paper_2101_07249_amd/csrc/gemm_f64.hip",
+                    "sha256": "b76fb4edd9477a2fa605577c540bf58487687ad0a9088bf9c5bfe9f7e961482b",
+                    "bytes_per_launch": 351.1e6}
+
+
+def measured_traffic(w, tune):
+    """The counted bytes when this run uses the measured kernel, else None."""
+    import hashlib
+    t = MEASURED_TRAFFIC
+    if tune is None or (w.n, w.N) != (t["n"], t["N"]) or not tune.get("two_segment"):
+        return None
+    if (tune.get("segment_variant"), tune.get("segment_splits")) != (t["segment_variant"], t["segment_splits"]):
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return t["bytes_per_launch"]
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
@@ -245,8 +268,8 @@ def main():
         # one-time setup, outside the timed region: tile shapes of the D^{1/2} products for
         # the single-vector PCG applies and the m-column block applies
         tunes[vname] = {"m1": prob.autotune(1), f"m{w.m}": prob.autotune(w.m)}
-    if args.tune_cache:
-        W4.autotune_save(args.tune_cache)
+        if args.tune_cache:
+            W4.autotune_save(args.tune_cache)
 
         def step():
             b = prob.rhs(d)
@@ -307,13 +330,19 @@ def main():
     if dom in ("dsqrt_gemm", "dsqrt_bf16x3"):
         peak = FP64_PEAK_TFLOPS if dom == "dsqrt_gemm" else BF16_PEAK_TFLOPS
         achieved = dv["flops"] / (dv["ms"] * 1e-3) / 1e12
+        traffic = measured_traffic(w, (tunes.get(head) or {}).get("m1")) if dom == "dsqrt_gemm" else None
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
+                "frac": achieved / peak, "traffic": traffic}
     else:
         achieved = dv["bytes"] / (dv["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    roof.update({"kernel": dom, "launches": dv["launches"], "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
+    names_k = {"dsqrt_gemm": "float64 D^{1/2} products (PCG: k_dsqrt2 + k_dsqrt2_reduce, one vector)",
+               "dsqrt_bf16x3": "k_gemm_bf16x3", "lmp_un": "k_pcg_lmp_dual", "lmp_ut": "k_lmp_gemv_t_partial",
+               "sweep_fwd": "k_sweep_fwd*", "sweep_bwd": "k_sweep_bwd*"}
+    roof.update({"kernel": names_k.get(dom, dom), "class": dom, "launches": dv["launches"],
+                 "traffic_unit": "HBM bytes per launch group (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+                 "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
                  "algorithmic_per_launch": (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"]})
 
     iters = results[head]["pcg_iters"]
