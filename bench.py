@@ -32,31 +32,51 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
 # HBM bytes per launch group of the single-vector float64 D^{1/2} product at n = 4096,
 # N = 100, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each scaled by a 1 GiB copy's
-# reading; profiles/dsqrt_vec_n4096_N100_counters.md).  Valid only for the kernel that was
-# measured: the two-segment launch (variant 1, 8 splits) built from this gemm_f64.hip.
-MEASURED_TRAFFIC = {"n": 4096, "N": 100, "segment_variant": 1, "segment_splits": 8,
-                    "source": "paper_2101_07249_amd/csrc/gemm_f64.hip",
-                    "sha256": "b76fb4edd9477a2fa605577c540bf58487687ad0a9088bf9c5bfe9f7e961482b",
-                    "bytes_per_launch": 351.1e6}
+# reading; profiles/dsqrt_vec_n4096_N100_counters.md).  Valid only for the kernels that were
+# measured: the tuned form below, built from this gemm_f64.hip and vec.hip.
+MEASURED_TRAFFIC = {"n": 4096, "N": 100,
+                    "tune": {"single_product": True, "two_segment": False, "tile_b": 2},
+                    "sources": {"paper_2101_07249_amd/csrc/gemm_f64.hip":
+                                "7f71c95e18e6f871b1af2e7c7e8e26ba5d3440f1a7fa7b45b914207b5adc734a",
+                                "paper_2101_07249_amd/csrc/vec.hip":
+                                "3b96ade541dfaa3068528d983e0919019a9ce12c715429c296a1028792a8cb1c"},
+                    "bytes_per_launch": 216.8e6}
 
 
 def measured_traffic(w, tune):
-    """The counted bytes when this run uses the measured kernel, else None."""
+    """The counted bytes when this run uses the measured kernels, else None."""
     import hashlib
     t = MEASURED_TRAFFIC
-    if tune is None or (w.n, w.N) != (t["n"], t["N"]) or not tune.get("two_segment"):
+    if t["bytes_per_launch"] is None or tune is None or (w.n, w.N) != (t["n"], t["N"]):
         return None
-    if (tune.get("segment_variant"), tune.get("segment_splits")) != (t["segment_variant"], t["segment_splits"]):
+    if any(tune.get(k) != v for k, v in t["tune"].items()):
         return None
-    with open(os.path.join(ROOT, t["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None
+    for path, digest in t["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     return t["bytes_per_launch"]
-FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
-BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+
+
+def dsqrt_kernel_name(tune):
+    """The kernels of one single-vector D^{1/2} launch group for this run's tuned form."""
+    if tune is None:
+        return "float64 D^{1/2} products (PCG, one vector)"
+    rows_k = {0: (64, 32), 1: (128, 16), 2: (128, 32)}
+    if tune.get("two_segment"):
+        r, kk = rows_k.get(tune.get("segment_variant"), (0, 0))
+        core = f"k_dsqrt2<{r}, {kk}> ({tune.get('segment_splits') or 'auto'} splits) + k_dsqrt2_reduce"
+    else:
+        core = f"k_gemm_f64 tile code {tune.get('tile_b')}" + ("" if tune.get("single_product") else
+                                                              f" / {tune.get('tile_q')}")
+    if tune.get("single_product"):
+        return f"Q^(1/2) over all N+1 levels: {core} + k_scale_level0"
+    return f"B^(1/2), Q^(1/2): {core}"
 
 
 def parse():
@@ -148,8 +168,8 @@ def learned_section(args):
 
 def batched_section(args):
     """64 uneven advection-diffusion inner loops (n in [512, 8192], N in [10, 200], m = 64,
-    Nystrom) through wc4d_batch_solve: wall time of the whole batch (tiles autotuned
-    beforehand, not timed) against the same problems solved one after another."""
+    Nystrom) through wc4d_batch_solve: wall time of the whole batch (single-vector tiles
+    autotuned beforehand, not timed) against the same problems solved one after another."""
     import numpy as np
     import torch
 
@@ -160,8 +180,7 @@ def batched_section(args):
     probs, G, b = [], [], []
     for w in ws:
         p = Problem.from_workload(w, obs_pattern(w))
-        p.autotune(w.m)
-        p.autotune(1)
+        p.autotune(1)   # the PCG's single-vector applies dominate; block widths keep the heuristic
         probs.append(p)
         G.append(torch.from_numpy(np.ascontiguousarray(sketch_block(p.n_A, w.m, w.seed).T)).to(p.torch_device))
         b.append(p.rhs(torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device)))
@@ -169,7 +188,8 @@ def batched_section(args):
     k_r, l = ws[0].k_r, ws[0].l
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4)
+    infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4,
+                                autotune=False)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -337,7 +357,7 @@ def main():
         achieved = dv["bytes"] / (dv["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    names_k = {"dsqrt_gemm": "float64 D^{1/2} products (PCG: k_dsqrt2 + k_dsqrt2_reduce, one vector)",
+    names_k = {"dsqrt_gemm": dsqrt_kernel_name((tunes.get(head) or {}).get("m1")),
                "dsqrt_bf16x3": "k_gemm_bf16x3", "lmp_un": "k_pcg_lmp_dual", "lmp_ut": "k_lmp_gemv_t_partial",
                "sweep_fwd": "k_sweep_fwd*", "sweep_bwd": "k_sweep_bwd*"}
     roof.update({"kernel": names_k.get(dom, dom), "class": dom, "launches": dv["launches"],

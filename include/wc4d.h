@@ -242,11 +242,13 @@ int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, dou
  * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32; two_segment = 0 when the
  * products run separately, else 1 + variant + 8 * splits of the two-segment launch with
  * variant 0 = 64 rows / K step 32, 1 = 128 / 16, 2 = 128 / 32 and splits 0 = automatic)
- * and its measured ms. */
+ * and its measured ms.  When finalize found B^{1/2} = c Q^{1/2} (same correlation, other
+ * variance) D^{1/2} is one product with Q^{1/2} over all N + 1 levels plus a rescaling of
+ * level 0; then tile_b is that product's tile and tile_q is 0. */
 int wc4d_autotune(wc4d_problem p, int m, hipStream_t s);
 int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two_segment, float* ms);
-/* Write / merge the process-wide autotune cache as text (one line per (device, n, N, m):
- * "device n N m tile_b tile_q two_segment variant splits ms").  A loaded entry is used
+/* Write / merge the process-wide autotune cache as text (one line per (device, n, N, m,
+ * scaled_b): "device n N m scaled_b tile_b tile_q two_segment variant splits tile_all ms").  A loaded entry is used
  * by wc4d_autotune without timing, so separate processes run identical kernels.
  * WC4D_EINVAL on an unreadable file or a malformed line (nothing is merged then). */
 int wc4d_autotune_save(const char* path);

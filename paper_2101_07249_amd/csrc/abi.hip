@@ -335,6 +335,31 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
 
   HIPCHK(p, hipMemsetAsync(p->dStatus, 0, 16 * sizeof(int), s));
   HIPCHK(p, hipStreamSynchronize(s));
+  // B^{1/2} = c Q^{1/2} (the same correlation with another variance): then D^{1/2} is one
+  // product with Q^{1/2} over all N + 1 time levels and a scaling of level 0
+  {
+    // c from the entry of largest |Q^{1/2}| (one rounding), then every entry checked
+    size_t emax = 0;
+    double bmax = 0.0, qmax = 0.0;
+    for (size_t e = 0; e < (size_t)n * n; ++e) {
+      bmax = std::max(bmax, std::fabs(p->Bsqrt[e]));
+      if (std::fabs(p->Qsqrt[e]) > qmax) {
+        qmax = std::fabs(p->Qsqrt[e]);
+        emax = e;
+      }
+    }
+    p->scaledB = false;
+    if (qmax > 0.0 && bmax > 0.0) {
+      const double c = p->Bsqrt[emax] / p->Qsqrt[emax];
+      double dev = 0.0;
+      for (size_t e = 0; e < (size_t)n * n && dev <= 1e-13 * bmax; ++e)
+        dev = std::max(dev, std::fabs(p->Bsqrt[e] - c * p->Qsqrt[e]));
+      if (dev <= 1e-13 * bmax && c > 0.0) {
+        p->scaledB = true;
+        p->bScale = c;
+      }
+    }
+  }
   // the host copies of the square roots are no longer needed once uploaded
   std::vector<double>().swap(p->Bsqrt);
   std::vector<double>().swap(p->Qsqrt);
@@ -412,6 +437,19 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
     return WC4D_OK;
   }
   const DsqrtTune* t = find_tune(p, m);
+  if (p->scaledB) {
+    // all levels with Q^{1/2} in one product, then level 0 rescaled by c (B^{1/2} = c Q^{1/2})
+    const ColMap xa{ldx, N + 1, 0, n}, ya{ldy, N + 1, 0, n}, ea{lde, N + 1, 0, n};
+    if (t != nullptr && t->twoSeg) {
+      HIPCHK(p, dsqrt2_f64_v(t->segVariant, t->segSplits, n, n, X, Y, E, p->dQ, xa, ya, ea, m * (N + 1), nullptr,
+                             xa, ya, ea, 0, skip, p->wsSplit, p->wsSplitDoubles, s));
+    } else {
+      HIPCHK(p, gemm_f64_tile(t ? t->tileAll : GEMM_AUTO, 0, n, m * (N + 1), n, 1.0, p->dQ, n, X, xa, Y, ya, E, ea,
+                              skip, s, p->wsSplit, p->wsSplitDoubles));
+    }
+    HIPCHK(p, scale_level0(n, m, p->bScale, Y, ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, skip, s));
+    return WC4D_OK;
+  }
   const int var = t ? t->segVariant : 0, spl = t ? t->segSplits : 0;
   const bool two_ok = (long long)m * N <= 112 && m <= 112 &&
                       dsqrt2_feasible(var, spl, n, m * N, m, n, p->wsSplitDoubles);

@@ -28,7 +28,7 @@ using namespace wc4d;
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, DsqrtTune> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int>, DsqrtTune> g_tune_cache;  // (device, n, N, m, scaledB)
 
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
@@ -73,7 +73,7 @@ int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
   if (m < 1 || m > 512) return fail(p, WC4D_EINVAL, "block width must be in [1, 512]");
   DevGuard g(p->device);
   const int n = p->n, N = p->N;
-  const auto key = std::make_tuple(p->device, n, N, m);
+  const auto key = std::make_tuple(p->device, n, N, m, p->scaledB ? 1 : 0);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -89,6 +89,48 @@ int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
   double* Y = p->bufB;
   HIPCHK(p, vec_fill(X, 0.5, nA * m, s));
   EvPair ev;
+  if (p->scaledB) {
+    // one product with Q^{1/2} over all levels
+    const ColMap xa{nA, N + 1, 0, n};
+    DsqrtTune best{};
+    float bestAll = -1.f;
+    for (int t = GEMM_AUTO + 1; t < GEMM_NTILES; ++t) {
+      if (!gemm_tile_feasible(t, n, m * (N + 1), n, p->wsSplit, p->wsSplitDoubles)) continue;
+      const float ms = time_launch(s, ev, [&] {
+        return gemm_f64_tile(t, 0, n, m * (N + 1), n, 1.0, p->dQ, n, X, xa, Y, xa, X, xa, nullptr, s, p->wsSplit,
+                             p->wsSplitDoubles);
+      });
+      if (ms >= 0.f && (bestAll < 0.f || ms < bestAll)) {
+        bestAll = ms;
+        best.tileAll = t;
+      }
+    }
+    (void)hipGetLastError();
+    if (bestAll < 0.f) return fail(p, WC4D_EHIP, "autotune: no tile shape could be timed");
+    best.ms = bestAll;
+    if ((long long)m * (N + 1) <= 112) {
+      // the split-K segment kernel with one segment
+      for (int v = 0; v < DSQRT2_NVARIANTS; ++v)
+        for (int sp : {0, 4, 8, 16, 32}) {
+          if (!dsqrt2_feasible(v, sp, n, m * (N + 1), 0, n, p->wsSplitDoubles)) continue;
+          const float ms = time_launch(s, ev, [&] {
+            return dsqrt2_f64_v(v, sp, n, n, X, Y, X, p->dQ, xa, xa, xa, m * (N + 1), nullptr, xa, xa, xa, 0, nullptr,
+                                p->wsSplit, p->wsSplitDoubles, s);
+          });
+          (void)hipGetLastError();
+          if (ms >= 0.f && ms < best.ms) {
+            best.twoSeg = true;
+            best.segVariant = v;
+            best.segSplits = sp;
+            best.ms = ms;
+          }
+        }
+    }
+    set_tune(p, m, best);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return WC4D_OK;
+  }
   const ColMap x0{nA, 1, 0, n}, xq{nA, N, 1, n};
   float bestB = -1.f, bestQ = -1.f;
   int tileB = GEMM_AUTO, tileQ = GEMM_AUTO;
@@ -116,7 +158,7 @@ int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
   }
   (void)hipGetLastError();
   if (bestB < 0.f || bestQ < 0.f) return fail(p, WC4D_EHIP, "autotune: no tile shape could be timed");
-  DsqrtTune best{tileB, tileQ, false, 0, 0, bestB + bestQ};
+  DsqrtTune best{tileB, tileQ, false, 0, 0, 0, bestB + bestQ};
   if ((long long)m * N <= 112 && m <= 112) {
     for (int v = 0; v < DSQRT2_NVARIANTS; ++v)
       for (int sp : {0, 4, 8, 16, 32}) {
@@ -126,7 +168,7 @@ int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
                               p->wsSplit, p->wsSplitDoubles, s);
         });
         (void)hipGetLastError();
-        if (ms >= 0.f && ms < best.ms) best = DsqrtTune{tileB, tileQ, true, v, sp, ms};
+        if (ms >= 0.f && ms < best.ms) best = DsqrtTune{tileB, tileQ, true, v, sp, 0, ms};
       }
   }
   set_tune(p, m, best);
@@ -139,8 +181,8 @@ int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two
   if (p == nullptr) return WC4D_EINVAL;
   const DsqrtTune* t = find_tune(p, m);
   if (t == nullptr) return fail(p, WC4D_ESTATE, "no autotuned shape for this block width");
-  if (tile_b) *tile_b = t->tileB;
-  if (tile_q) *tile_q = t->tileQ;
+  if (tile_b) *tile_b = t->tileAll ? t->tileAll : t->tileB;
+  if (tile_q) *tile_q = t->tileAll ? 0 : t->tileQ;
   if (two_segment) *two_segment = t->twoSeg ? 1 + t->segVariant + 8 * t->segSplits : 0;
   if (ms) *ms = t->ms;
   return WC4D_OK;
@@ -151,12 +193,13 @@ int wc4d_autotune_save(const char* path) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   FILE* fp = std::fopen(path, "w");
   if (fp == nullptr) return WC4D_EINVAL;
-  bool ok = std::fprintf(fp, "# wc4d autotune cache: device n N m tile_b tile_q two_segment variant splits ms\n") > 0;
+  bool ok = std::fprintf(fp, "# wc4d autotune cache: device n N m scaled_b tile_b tile_q two_segment variant splits "
+                             "tile_all ms\n") > 0;
   for (const auto& e : g_tune_cache) {
     const DsqrtTune& t = e.second;
-    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %.6f\n", std::get<0>(e.first), std::get<1>(e.first),
-                            std::get<2>(e.first), std::get<3>(e.first), t.tileB, t.tileQ, t.twoSeg ? 1 : 0,
-                            t.segVariant, t.segSplits, (double)t.ms) > 0;
+    ok = ok && std::fprintf(fp, "%d %d %d %d %d %d %d %d %d %d %d %.6f\n", std::get<0>(e.first), std::get<1>(e.first),
+                            std::get<2>(e.first), std::get<3>(e.first), std::get<4>(e.first), t.tileB, t.tileQ,
+                            t.twoSeg ? 1 : 0, t.segVariant, t.segSplits, t.tileAll, (double)t.ms) > 0;
   }
   ok = (std::fclose(fp) == 0) && ok;
   return ok ? WC4D_OK : WC4D_EINVAL;
@@ -166,20 +209,22 @@ int wc4d_autotune_load(const char* path) {
   if (path == nullptr) return WC4D_EINVAL;
   FILE* fp = std::fopen(path, "r");
   if (fp == nullptr) return WC4D_EINVAL;
-  std::map<std::tuple<int, int, int, int>, DsqrtTune> got;
+  std::map<std::tuple<int, int, int, int, int>, DsqrtTune> got;
   char line[256];
   bool ok = true;
   while (std::fgets(line, sizeof(line), fp) != nullptr) {
     if (line[0] == '#' || line[0] == '\n') continue;
-    int d, n, N, m, tb, tq, two, var, spl;
+    int d, n, N, m, sc, tb, tq, two, var, spl, ta;
     double ms;
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %lf", &d, &n, &N, &m, &tb, &tq, &two, &var, &spl, &ms) != 10 ||
-        tb <= GEMM_AUTO || tb >= GEMM_NTILES || tq <= GEMM_AUTO || tq >= GEMM_NTILES || var < 0 ||
-        var >= DSQRT2_NVARIANTS || spl < 0) {
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %lf", &d, &n, &N, &m, &sc, &tb, &tq, &two, &var, &spl, &ta,
+                    &ms) != 12 ||
+        (sc != 0 && sc != 1) || tb < GEMM_AUTO || tb >= GEMM_NTILES || tq < GEMM_AUTO || tq >= GEMM_NTILES ||
+        ta < GEMM_AUTO || ta >= GEMM_NTILES || (sc == 0 && ta != GEMM_AUTO) || var < 0 || var >= DSQRT2_NVARIANTS ||
+        spl < 0) {
       ok = false;
       break;
     }
-    got[std::make_tuple(d, n, N, m)] = DsqrtTune{tb, tq, two != 0, var, spl, (float)ms};
+    got[std::make_tuple(d, n, N, m, sc)] = DsqrtTune{tb, tq, two != 0, var, spl, ta, (float)ms};
   }
   std::fclose(fp);
   if (!ok) return WC4D_EINVAL;

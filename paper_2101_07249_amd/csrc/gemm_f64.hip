@@ -410,7 +410,7 @@ size_t dsqrt2_ws_doubles(int M, int n1, int n2, int K) {
 }
 
 bool dsqrt2_feasible(int variant, int splits, int M, int n1, int n2, int K, size_t ws_doubles) {
-  if (variant < 0 || variant >= DSQRT2_NVARIANTS || n1 > SBN || n2 > SBN || n1 < 1 || n2 < 1) return false;
+  if (variant < 0 || variant >= DSQRT2_NVARIANTS || n1 > SBN || n2 > SBN || n1 < 1 || n2 < 0) return false;
   const int sp = dsqrt2_splits(variant, splits, M, n1, n2, K, ws_doubles);
   return sp > 0 && (splits <= 0 || sp == splits);
 }
@@ -428,7 +428,7 @@ hipError_t dsqrt2_f64_v(int variant, int splits, int M, int K, const double* B, 
   Seg s1{A1, b1, c1, e1, n1, sp, kchunk, 0};
   Seg s2{A2, b2, c2, e2, n2, sp, kchunk, (size_t)sp * M * n1};
   const int rows = dsqrt2_rows(variant);
-  const dim3 grid((M + rows - 1) / rows, 1, 2 * sp);
+  const dim3 grid((M + rows - 1) / rows, 1, (n2 > 0 ? 2 : 1) * sp);  // n2 = 0: one segment
   if (variant == 0)
     hipLaunchKernelGGL((k_dsqrt2<64, 32>), grid, dim3(256), 0, s, M, K, (long long)M, B, s1, s2, ws, skip);
   else if (variant == 1)

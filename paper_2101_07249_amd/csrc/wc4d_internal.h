@@ -51,7 +51,7 @@ hipError_t gemm_f64_tile(int tile, int splits, int M, int ncol, int K, double al
                          long long lda, const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                          ColMap emap, const int* skip, hipStream_t s, double* ws, size_t ws_doubles);
 
-// Two-segment few-column product (both n1, n2 <= 112): C(:, c1(t)) = A1 B(:, b1(t)) [+ E]
+// Two-segment few-column product (n1 in [1, 112], n2 in [0, 112]; n2 = 0: one segment): C(:, c1(t)) = A1 B(:, b1(t)) [+ E]
 // for t < n1 and C(:, c2(t)) = A2 B(:, b2(t)) [+ E] for t < n2, A1 / A2 M x K with lda = M,
 // one split-K launch plus one reduction.  ws: dsqrt2_ws_doubles(M, n1, n2, K).
 size_t dsqrt2_ws_doubles(int M, int n1, int n2, int K);
@@ -82,6 +82,11 @@ hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16*
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
                        const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                        ColMap emap, hipStream_t s);
+
+// Level-0 columns after a product with Q^{1/2} over all levels (B^{1/2} = c Q^{1/2}):
+// Y0 = c Y0 when E is null, else Y0 = (1 - c) E0 + c Y0 (Y already holds E0 + Q^{1/2} X0).
+hipError_t scale_level0(int n, int m, double c, double* Y, ColMap ymap, const double* E, ColMap emap,
+                        const int* skip, hipStream_t s);
 
 // Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
 struct SweepModel {
@@ -244,9 +249,10 @@ struct ProfRec {
 struct DsqrtTune {
   int tileB = 0;      // GemmTile of the B^{1/2} product (m columns)
   int tileQ = 0;      // GemmTile of the Q^{1/2} product (m N columns)
-  bool twoSeg = false;  // one two-segment split-K launch instead of both
+  bool twoSeg = false;  // the split-K segment kernel (two segments, or one with scaledB)
   int segVariant = 0;   // its tile variant and K splits (0: heuristic)
   int segSplits = 0;
+  int tileAll = 0;      // GemmTile of the single product over all levels (B^{1/2} = c Q^{1/2})
   float ms = 0.f;     // measured time of the chosen form
 };
 
@@ -315,6 +321,8 @@ struct wc4d_problem_s {
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   std::vector<wc4d_lmp> lmps;  // live LMPs built on this problem
   bool cholShift = false;       // LMP build: shifted CholeskyQR3 (set for a retry)
+  bool scaledB = false;         // B^{1/2} = bScale Q^{1/2} (detected at finalize)
+  double bScale = 1.0;
   std::vector<std::pair<int, DsqrtTune>> tune;  // autotuned D^{1/2} tiles per block width
   std::string err;
   wc4d::SweepModel sweep() const;

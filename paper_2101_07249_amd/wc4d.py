@@ -395,7 +395,7 @@ class Problem:
         self._chk(lib().wc4d_autotune_info(self._h, int(m), ctypes.byref(tb), ctypes.byref(tq), ctypes.byref(two),
                                            ctypes.byref(ms)), "autotune_info")
         seg = two.value
-        return {"tile_b": tb.value, "tile_q": tq.value, "two_segment": seg > 0,
+        return {"tile_b": tb.value, "tile_q": tq.value, "single_product": tq.value == 0, "two_segment": seg > 0,
                 "segment_variant": (seg - 1) % 8 if seg else None, "segment_splits": (seg - 1) // 8 if seg else None,
                 "ms": ms.value}
 

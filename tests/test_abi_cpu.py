@@ -67,17 +67,35 @@ def test_autotune_cache_file_roundtrip(tmp_path):
     what was merged (no GPU call involved)."""
     from paper_2101_07249_amd import wc4d as W4
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n0 4096 100 1 1 2 1 1 8 0.116\n0 512 10 64 6 6 0 0 0 1.5\n")
+    good.write_text("# comment\n0 4096 100 1 0 1 2 1 1 8 0 0.116\n0 512 10 64 1 0 0 0 0 0 3 1.5\n")
     W4.autotune_load(str(good))
     out = tmp_path / "out.txt"
     W4.autotune_save(str(out))
     lines = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert ["0", "4096", "100", "1", "1", "2", "1", "1", "8"] in [l[:9] for l in lines]
-    assert ["0", "512", "10", "64", "6", "6", "0", "0", "0"] in [l[:9] for l in lines]
+    assert ["0", "4096", "100", "1", "0", "1", "2", "1", "1", "8", "0"] in [l[:11] for l in lines]
+    assert ["0", "512", "10", "64", "1", "0", "0", "0", "0", "0", "3"] in [l[:11] for l in lines]
     bad = tmp_path / "bad.txt"
-    for text in ("0 4096 100 1 9 2 1 1 8 0.1\n", "0 4096 100 1 1 2 1 7 8 0.1\n", "0 4096 100\n"):
+    for text in ("0 4096 100 1 0 9 2 1 1 8 0 0.1\n", "0 4096 100 1 0 1 2 1 7 8 0 0.1\n", "0 4096 100\n",
+                 "0 4096 100 1 0 1 2 1 1 8 3 0.1\n"):
         bad.write_text(text)
         with pytest.raises(W4.Wc4dError):
             W4.autotune_load(str(bad))
     with pytest.raises(W4.Wc4dError):
         W4.autotune_load(str(tmp_path / "missing.txt"))
+
+
+def test_bench_helpers_on_cpu():
+    """bench.py's host-side helpers: kernel naming from a tuned form, and the counter
+    traffic only for the measured kernels (sources hashed)."""
+    import bench
+    from synthetic import C3
+    assert bench.FP64_PEAK_TFLOPS == 78.6 and bench.BF16_PEAK_TFLOPS == 2500.0 and bench.HBM_PEAK_GBS == 8000.0
+    tune = {"tile_b": 2, "tile_q": 0, "single_product": True, "two_segment": True, "segment_variant": 1,
+            "segment_splits": 8}
+    name = bench.dsqrt_kernel_name(tune)
+    assert "k_dsqrt2<128, 16>" in name and "k_scale_level0" in name
+    assert "k_gemm_f64" in bench.dsqrt_kernel_name(dict(tune, two_segment=False))
+    t = bench.MEASURED_TRAFFIC
+    other = dict(tune, segment_splits=(t["tune"].get("segment_splits") or 0) + 1)
+    assert bench.measured_traffic(C3, other) is None
+    assert bench.measured_traffic(C3.with_(n=512), tune) is None

