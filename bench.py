@@ -42,10 +42,10 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 MEASURED_TRAFFIC = {"n": 4096, "N": 100,
                     "tune": {"single_product": True, "two_segment": False, "tile_b": 2},
                     "sources": {"paper_2101_07249_amd/csrc/gemm_f64.hip":
-                                "7f71c95e18e6f871b1af2e7c7e8e26ba5d3440f1a7fa7b45b914207b5adc734a",
+                                "68bc6d377244e3394e5b7b5250e9c7f7793ead05b11e920b4fa408f80c4827ac",
                                 "paper_2101_07249_amd/csrc/vec.hip":
-                                "3b96ade541dfaa3068528d983e0919019a9ce12c715429c296a1028792a8cb1c"},
-                    "bytes_per_launch": 216.8e6}
+                                "a4509cb7f2bc75e3df14acd0370293900e2843070f52516e6c48493a8c7fda9f"},
+                    "bytes_per_launch": 216.7e6}
 
 
 def measured_traffic(w, tune):
@@ -75,7 +75,7 @@ def dsqrt_kernel_name(tune):
         core = f"k_gemm_f64 tile code {tune.get('tile_b')}" + ("" if tune.get("single_product") else
                                                               f" / {tune.get('tile_q')}")
     if tune.get("single_product"):
-        return f"Q^(1/2) over all N+1 levels: {core} + k_scale_level0"
+        return f"Q^(1/2) over all N+1 levels, level 0 scaled in the epilogue: {core}"
     return f"B^(1/2), Q^(1/2): {core}"
 
 

@@ -439,7 +439,8 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
   const DsqrtTune* t = find_tune(p, m);
   if (p->scaledB) {
     // all levels with Q^{1/2} in one product, then level 0 rescaled by c (B^{1/2} = c Q^{1/2})
-    const ColMap xa{ldx, N + 1, 0, n}, ya{ldy, N + 1, 0, n}, ea{lde, N + 1, 0, n};
+    // output columns of level 0 are scaled by c in the product's epilogue (before + E)
+    const ColMap xa{ldx, N + 1, 0, n}, ya{ldy, N + 1, 0, n, p->bScale}, ea{lde, N + 1, 0, n};
     if (t != nullptr && t->twoSeg) {
       HIPCHK(p, dsqrt2_f64_v(t->segVariant, t->segSplits, n, n, X, Y, E, p->dQ, xa, ya, ea, m * (N + 1), nullptr,
                              xa, ya, ea, 0, skip, p->wsSplit, p->wsSplitDoubles, s));
@@ -447,7 +448,6 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
       HIPCHK(p, gemm_f64_tile(t ? t->tileAll : GEMM_AUTO, 0, n, m * (N + 1), n, 1.0, p->dQ, n, X, xa, Y, ya, E, ea,
                               skip, s, p->wsSplit, p->wsSplitDoubles));
     }
-    HIPCHK(p, scale_level0(n, m, p->bScale, Y, ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, skip, s));
     return WC4D_OK;
   }
   const int var = t ? t->segVariant : 0, spl = t ? t->segSplits : 0;

@@ -43,12 +43,19 @@ __global__ __launch_bounds__(1024) void k_chol_upper(int m, double* __restrict__
       G[k + (size_t)j * ldg] = v;
     }
     __syncthreads();
-    // trailing update of the upper triangle: G(i, j) -= R(k, i) R(k, j), k < i <= j
+    // trailing update of the upper triangle: G(i, j) -= R(k, i) R(k, j), k < i <= j.
+    // Columns j are spread over the threads (several threads per column when there are
+    // fewer columns than threads), each walking a strided share of rows i <= j.
     const int w = m - k - 1;
-    const long long tot = (long long)w * w;
-    for (long long e = tid; e < tot; e += nt) {
-      const int i = k + 1 + (int)(e % w), j = k + 1 + (int)(e / w);
-      if (i <= j) G[i + (size_t)j * ldg] -= G[k + (size_t)i * ldg] * G[k + (size_t)j * ldg];
+    if (w > 0) {
+      const int tpc = max(1, nt / w);            // threads per column
+      const int col = tid / tpc, sub = tid % tpc;
+      for (int jj = col; jj < w; jj += nt / tpc) {
+        const int j = k + 1 + jj;
+        const double rkj = G[k + (size_t)j * ldg];
+        double* gcol = G + (size_t)j * ldg;
+        for (int i = k + 1 + sub; i <= j; i += tpc) gcol[i] -= G[k + (size_t)i * ldg] * rkj;
+      }
     }
     __syncthreads();
   }

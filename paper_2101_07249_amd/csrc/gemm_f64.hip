@@ -130,11 +130,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
       }
       const long long co = cmap.off(j);
       const long long eo = (E != nullptr) ? emap.off(j) : 0;
+      const double aj = alpha * cmap.colscale(j);
 #pragma unroll
       for (int b = 0; b < TI; ++b) {
         const int i = i0 + wi0 + b * 16 + (lane & 15);
         if (i < M) {
-          double v = alpha * acc[a][b][r];
+          double v = aj * acc[a][b][r];
           if (E != nullptr) v += E[eo + i];
           C[co + i] = v;
         }
@@ -151,11 +152,12 @@ __global__ void k_gemm_splitk_reduce(int M, int ncol, int splits, double alpha,
   const int j = blockIdx.y;
   const long long co = cmap.off(j);
   const long long eo = (E != nullptr) ? emap.off(j) : 0;
+  const double aj = alpha * cmap.colscale(j);
   const size_t plane = (size_t)M * ncol;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
     double v = 0.0;
     for (int z = 0; z < splits; ++z) v += ws[z * plane + (size_t)j * M + i];
-    v *= alpha;
+    v *= aj;
     if (E != nullptr) v += E[eo + i];
     C[co + i] = v;
   }
@@ -381,11 +383,12 @@ __global__ void k_dsqrt2_reduce(int M, Seg s1, Seg s2, double alpha, const doubl
   const int j = first ? blockIdx.y : blockIdx.y - s1.ncol;
   const long long co = sg.cmap.off(j);
   const long long eo = (E != nullptr) ? sg.emap.off(j) : 0;
+  const double aj = alpha * sg.cmap.colscale(j);
   const size_t plane = (size_t)M * sg.ncol;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < M; i += gridDim.x * blockDim.x) {
     double v = 0.0;
     for (int zz = 0; zz < sg.splits; ++zz) v += ws[sg.wsoff + zz * plane + (size_t)j * M + i];
-    v *= alpha;
+    v *= aj;
     if (E != nullptr) v += E[eo + i];
     C[co + i] = v;
   }

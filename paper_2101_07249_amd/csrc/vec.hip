@@ -513,25 +513,4 @@ hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u
   return hipGetLastError();
 }
 
-// --------------------------------------------------------------- level-0 rescale
-__global__ void k_scale_level0(int n, int m, double c, double* __restrict__ Y, ColMap ymap,
-                               const double* __restrict__ E, ColMap emap, const int* __restrict__ skip) {
-  if (skip != nullptr && *skip != 0) return;
-  const long long tot = (long long)n * m;
-  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(e % n), t = (int)(e / n);
-    double* y = Y + ymap.off(t) + j;
-    *y = (E != nullptr) ? (1.0 - c) * E[emap.off(t) + j] + c * *y : c * *y;
-  }
-}
-
-hipError_t scale_level0(int n, int m, double c, double* Y, ColMap ymap, const double* E, ColMap emap,
-                        const int* skip, hipStream_t s) {
-  const long long tot = (long long)n * m;
-  const int blocks = (int)std::min<long long>((tot + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_scale_level0, dim3(blocks), dim3(256), 0, s, n, m, c, Y, ymap, E, emap, skip);
-  return hipGetLastError();
-}
-
 }  // namespace wc4d

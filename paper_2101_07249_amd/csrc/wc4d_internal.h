@@ -23,9 +23,13 @@ struct ColMap {
   int per;
   int base;
   int stride;
+  // product epilogues multiply the columns with t % per == 0 by scale0 (level 0 of a
+  // time-level view; 1 = no scaling)
+  double scale0 = 1.0;
   __host__ __device__ inline long long off(int t) const {
     return (long long)(t / per) * ld + (long long)(base + t % per) * stride;
   }
+  __host__ __device__ inline double colscale(int t) const { return (t % per == 0) ? scale0 : 1.0; }
 };
 
 inline ColMap plain_cols(long long ld) { return ColMap{ld, 1, 0, 0}; }
@@ -82,11 +86,6 @@ hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16*
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
                        const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                        ColMap emap, hipStream_t s);
-
-// Level-0 columns after a product with Q^{1/2} over all levels (B^{1/2} = c Q^{1/2}):
-// Y0 = c Y0 when E is null, else Y0 = (1 - c) E0 + c Y0 (Y already holds E0 + Q^{1/2} X0).
-hipError_t scale_level0(int n, int m, double c, double* Y, ColMap ymap, const double* E, ColMap emap,
-                        const int* skip, hipStream_t s);
 
 // Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
 struct SweepModel {

@@ -93,7 +93,7 @@ def test_bench_helpers_on_cpu():
     tune = {"tile_b": 2, "tile_q": 0, "single_product": True, "two_segment": True, "segment_variant": 1,
             "segment_splits": 8}
     name = bench.dsqrt_kernel_name(tune)
-    assert "k_dsqrt2<128, 16>" in name and "k_scale_level0" in name
+    assert "k_dsqrt2<128, 16>" in name and "level 0" in name
     assert "k_gemm_f64" in bench.dsqrt_kernel_name(dict(tune, two_segment=False))
     t = bench.MEASURED_TRAFFIC
     other = dict(tune, segment_splits=(t["tune"].get("segment_splits") or 0) + 1)
