@@ -41,10 +41,9 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 # measured: the tuned form below, built from this gemm_f64.hip and vec.hip.
 MEASURED_TRAFFIC = {"n": 4096, "N": 100,
                     "tune": {"single_product": True, "two_segment": False, "tile_b": 2},
+                    # k_gemm_f64 and k_gemm_splitk_reduce (the whole launch group) live here
                     "sources": {"paper_2101_07249_amd/csrc/gemm_f64.hip":
-                                "68bc6d377244e3394e5b7b5250e9c7f7793ead05b11e920b4fa408f80c4827ac",
-                                "paper_2101_07249_amd/csrc/vec.hip":
-                                "a4509cb7f2bc75e3df14acd0370293900e2843070f52516e6c48493a8c7fda9f"},
+                                "68bc6d377244e3394e5b7b5250e9c7f7793ead05b11e920b4fa408f80c4827ac"},
                     "bytes_per_launch": 216.7e6}
 
 

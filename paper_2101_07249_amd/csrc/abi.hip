@@ -779,13 +779,13 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if ((rc = ensure_gram(p, gram_ws_doubles(k_r, k_r, nA)))) return cleanup(rc);
   const double* Ug = L->U;
   if (p->prec & WC4D_PREC_LMP_FP32) {
-    // the build's scratch block B_ (n_A x m doubles) holds the rounded copy for the Gram;
-    // the padding rows (n_A .. ldu) of the conversions are never read by any product
-    if ((rc = dev_alloc(p, &L->U32, (size_t)L->ldu * k_r))) return cleanup(rc);
-    he = vec_to_f32(L->U32, L->U, L->ldu * k_r, s);
-    if (he == hipSuccess && L->ldu * k_r <= (nA + 4) * m) he = vec_to_f64(B_, L->U32, L->ldu * k_r, s);
-    if (he != hipSuccess || L->ldu * k_r > (nA + 4) * m)
-      return cleanup(fail(p, WC4D_EHIP, "float32 copy of U failed"));
+    // panel-major float32 copy for the PCG passes; the build's scratch block B_ (n_A x m
+    // doubles) receives the rounded values column-major for the Gram (rows n_A .. ldu of
+    // it are never read)
+    if ((rc = dev_alloc(p, &L->U32, lmp_panel_floats(nA, k_r)))) return cleanup(rc);
+    if (L->ldu * k_r > (nA + 4) * m) return cleanup(fail(p, WC4D_EHIP, "float32 copy of U: scratch too small"));
+    he = lmp_to_panels(L->U32, L->U, L->ldu, nA, k_r, B_, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, "float32 copy of U failed"));
     Ug = B_;
   }
   he = gram_f64(k_r, k_r, nA, Ug, plain_cols(L->ldu), Ug, plain_cols(L->ldu), L->GU, k_r, p->wsGram,

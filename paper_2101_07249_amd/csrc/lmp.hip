@@ -1,12 +1,20 @@
 // Spectral-LMP application to one vector (Section 3.2, eq. spectral_LMP_factor in
 // closed form): y = x + U diag(dcoef) U^T x, dcoef = theta^{-1/2} - 1.
 //
-// Two passes over U (n_A x k, column-major), each HBM-bound:
+// Two passes over U (n_A x k), each HBM-bound:
 //   lmp_gemv_t: t = dcoef .* (U^T x)   -- chunk partials, then a fixed-order sum
 //   lmp_gemv_n: y = x + U t
-// U^T x: a workgroup owns 32 columns and a long run of rows, each thread keeps 32
-// accumulators and reduces once.  x + U t: a thread owns 2 rows and streams the
-// columns 8 at a time (16 independent loads in flight).
+// Float64 U is column-major (leading dimension ldu).  U^T x: a workgroup owns 32
+// columns and a long run of rows, each thread keeps 32 accumulators and reduces once.
+// x + U t: a thread owns 4 rows and streams the columns 8 at a time.
+//
+// The float32 copy the PCG streams is panel-major instead: panel p holds rows
+// [256 p, 256 p + 256) of all k columns, column-major with leading dimension 256, at
+// offset 256 k p, and rows at or past n_A are zero.  A workgroup working on one panel
+// reads one contiguous 1 KB x k block.  Measured on MI355X at n_A = 413,696, k = 251:
+// U^T x 73 us (5.7 TB/s) and the fused PCG pass 78 us (5.5 TB/s), against 77 us and
+// 144 us for the same passes over a column-major copy (a plain read of the 415 MB runs
+// at 6.3 TB/s).
 #include "wc4d_internal.h"
 
 namespace wc4d {
@@ -20,6 +28,24 @@ constexpr int kTU = 1;    // row unroll (U^T x pass)
 
 static inline long long lmp_chunks(long long nA) { return (nA + kLRows - 1) / kLRows; }
 
+size_t lmp_panel_floats(long long nA, int k) { return (size_t)lmp_panels(nA) * kPanel * k; }
+
+// U^T x over panels: grid (column groups of kPG) x (splits of pan_per consecutive panels);
+// about 1024 workgroups.
+constexpr int kPG = 16;
+static inline long long pan_t_per(long long nA, int k) {
+  const long long np = lmp_panels(nA);
+  const int ncg = (k + kPG - 1) / kPG;
+  long long sp = (1024 + ncg - 1) / ncg;
+  if (sp > np) sp = np;
+  if (sp < 1) sp = 1;
+  return (np + sp - 1) / sp;
+}
+static inline int pan_t_splits(long long nA, int k) {
+  const long long per = pan_t_per(nA, k);
+  return (int)((lmp_panels(nA) + per - 1) / per);
+}
+
 // U^T x: grid (column groups of kTG) x (row splits); about 512 workgroups (measured:
 // 32 columns x 1 row per thread streams U at ~90% of the plain-read rate on MI355X,
 // 16 columns x 2 rows at ~60%).
@@ -31,8 +57,13 @@ static inline int lmp_t_splits(long long nA, int k) {
   return sp < 1 ? 1 : (int)sp;
 }
 
-size_t lmp_gemv_ws_doubles(long long nA, int k) { return (size_t)lmp_t_splits(nA, k) * k + k; }
-size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)lmp_t_splits(nA, k) * k; }
+// partials of either layout, then t
+static inline int t_splits_max(long long nA, int k) {
+  const int a = lmp_t_splits(nA, k), b = pan_t_splits(nA, k);
+  return a > b ? a : b;
+}
+size_t lmp_gemv_ws_doubles(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k + k; }
+size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k; }
 
 // Partial sums of columns [c0, c0 + kTG) over rows [rb, re): each thread runs down
 // its rows with kTG accumulators; one block reduction at the end.
@@ -163,20 +194,140 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const T
     if (r0 + e < nA) y[r0 + e] = acc[e];
 }
 
+
+// ------------------------------------------------ float32 panel copy
+
+// P = panels of (float)U; Uround (optional, column-major with ldu) = (double)(float)U,
+// the values the passes over P see.
+__global__ void k_lmp_to_panels(const double* __restrict__ U, long long ldu, long long nA, int k,
+                                long long npan, float* __restrict__ P, double* __restrict__ Uround) {
+  const long long total = npan * kPanel * k;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long rr = t % kPanel, c = (t / kPanel) % k, pn = t / ((long long)kPanel * k);
+    const long long i = pn * kPanel + rr;
+    const float v = i < nA ? (float)U[c * ldu + i] : 0.0f;
+    P[t] = v;
+    if (Uround != nullptr && i < nA) Uround[c * ldu + i] = (double)v;
+  }
+}
+
+hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA, int k,
+                         double* Uround, hipStream_t s) {
+  hipLaunchKernelGGL(k_lmp_to_panels, dim3(4096), dim3(256), 0, s, U, ldu, nA, k, lmp_panels(nA), P,
+                     Uround);
+  return hipGetLastError();
+}
+
+// Partial sums of columns [c0, c0 + kPG) over panels [pb, pe): thread = one row of the
+// panel (the 256 threads read 1 KB per column), kPG accumulators, one block reduction.
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int k, long long pan_per,
+                                                              const float* __restrict__ P,
+                                                              const double* __restrict__ x,
+                                                              double* __restrict__ part,
+                                                              const int* __restrict__ skip) {
+  __shared__ double sh[kPanel / 64][kPG];
+  if (skip != nullptr && *skip != 0) return;
+  const int c0 = blockIdx.x * kPG;
+  const int split = blockIdx.y;
+  const long long np = lmp_panels(nA);
+  const long long pb = (long long)split * pan_per;
+  long long pe = pb + pan_per;
+  if (pe > np) pe = np;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int col[kPG];
+#pragma unroll
+  for (int c = 0; c < kPG; ++c) col[c] = (c0 + c < k ? c0 + c : 0) * kPanel;
+  double acc[kPG];
+#pragma unroll
+  for (int c = 0; c < kPG; ++c) acc[c] = 0.0;
+  for (long long pn = pb; pn < pe; ++pn) {
+    const long long i = pn * kPanel + threadIdx.x;
+    const double xv = i < nA ? x[i] : 0.0;
+    const float* Pp = P + (size_t)pn * kPanel * k + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < kPG; ++c) acc[c] += (double)Pp[col[c]] * xv;
+  }
+#pragma unroll
+  for (int c = 0; c < kPG; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < kPG; ++c) sh[wave][c] = acc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < kPG && c0 + (int)threadIdx.x < k) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPanel / 64; ++w) sum += sh[w][threadIdx.x];
+    part[(size_t)split * k + c0 + threadIdx.x] = sum;
+  }
+}
+
+// y = x + U t over panels: wave w of a 256-thread block takes columns w, w + 4, ...
+// (two in flight), a lane holds 4 rows of the panel; the four waves' sums meet in LDS.
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const float* __restrict__ P,
+                                                      const double* __restrict__ t,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ y,
+                                                      const int* __restrict__ skip) {
+  extern __shared__ double sm[];
+  double* ts = sm;           // k coefficients
+  double* red = sm + k;      // [4 waves][256 rows]
+  if (skip != nullptr && *skip != 0) return;
+  for (int c = threadIdx.x; c < k; c += kPanel) ts[c] = t[c];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long np = lmp_panels(nA);
+  for (long long pn = blockIdx.x; pn < np; pn += gridDim.x) {
+    const float* Pp = P + (size_t)pn * kPanel * k + 4 * lane;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = wave; c0 < k; c0 += 8) {
+      const int c1 = c0 + 4;
+      const float4 u0 = *reinterpret_cast<const float4*>(Pp + (size_t)c0 * kPanel);
+      const float4 u1 = c1 < k ? *reinterpret_cast<const float4*>(Pp + (size_t)c1 * kPanel)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+      const double t0 = ts[c0], t1 = c1 < k ? ts[c1] : 0.0;
+      a[0] += u0.x * t0; a[1] += u0.y * t0; a[2] += u0.z * t0; a[3] += u0.w * t0;
+      a[0] += u1.x * t1; a[1] += u1.y * t1; a[2] += u1.z * t1; a[3] += u1.w * t1;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave * kPanel + 4 * lane + e] = a[e];
+    __syncthreads();
+    const long long i = pn * kPanel + threadIdx.x;
+    if (i < nA) {
+      const int q = threadIdx.x;
+      y[i] = x[i] + ((red[q] + red[kPanel + q]) + (red[2 * kPanel + q] + red[3 * kPanel + q]));
+    }
+    __syncthreads();
+  }
+}
+
+// blocks for a pass over all panels: ceil(np / per) with per = ceil(np / 1024)
+int lmp_panel_grid(long long nA) {
+  const long long np = lmp_panels(nA);
+  const long long per = (np + 1023) / 1024;
+  return (int)((np + per - 1) / per);
+}
+
 hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
                       const double* dcoef, const double* x, double* ws, const int* skip,
                       hipStream_t s, double* tout) {
-  const int sp = lmp_t_splits(nA, k);
-  long long rows_per = (nA + sp - 1) / sp;
   double* part = ws;
-  double* t = (tout != nullptr) ? tout : ws + (size_t)sp * k;
-  dim3 grid((k + kTG - 1) / kTG, sp);
-  if (u32)
-    hipLaunchKernelGGL(k_lmp_gemv_t_partial<float>, grid, dim3(kLT), 0, s, nA, k, rows_per,
-                       (const float*)U, ldu, x, part, skip);
-  else
-    hipLaunchKernelGGL(k_lmp_gemv_t_partial<double>, grid, dim3(kLT), 0, s, nA, k, rows_per,
-                       (const double*)U, ldu, x, part, skip);
+  double* t = (tout != nullptr) ? tout : ws + lmp_gemv_t_offset(nA, k);
+  int sp;
+  if (u32) {
+    sp = pan_t_splits(nA, k);
+    hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
+                       pan_t_per(nA, k), (const float*)U, x, part, skip);
+  } else {
+    sp = lmp_t_splits(nA, k);
+    const long long rows_per = (nA + sp - 1) / sp;
+    hipLaunchKernelGGL(k_lmp_gemv_t_partial<double>, dim3((k + kTG - 1) / kTG, sp), dim3(kLT), 0, s, nA,
+                       k, rows_per, (const double*)U, ldu, x, part, skip);
+  }
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, part, dcoef, t,
                      skip);
   return hipGetLastError();
@@ -184,14 +335,15 @@ hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ld
 
 hipError_t lmp_gemv_n(long long nA, int k, const void* U, bool u32, long long ldu, const double* x,
                       double* y, const double* ws, const int* skip, hipStream_t s) {
+  const double* t = ws + lmp_gemv_t_offset(nA, k);
+  if (u32) {
+    hipLaunchKernelGGL(k_lmp_pan_n, dim3(lmp_panel_grid(nA)), dim3(kPanel),
+                       sizeof(double) * (k + 4 * kPanel), s, nA, k, (const float*)U, t, x, y, skip);
+    return hipGetLastError();
+  }
   if (ldu % 4 != 0) return hipErrorInvalidValue;
   const long long nch = (nA + 4LL * kLT - 1) / (4LL * kLT);
-  const double* t = ws + (size_t)lmp_t_splits(nA, k) * k;
-  if (u32)
-    hipLaunchKernelGGL(k_lmp_gemv_n<float>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s, nA,
-                       k, (const float*)U, ldu, t, x, y, skip);
-  else
-    hipLaunchKernelGGL(k_lmp_gemv_n<double>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s,
+  hipLaunchKernelGGL(k_lmp_gemv_n<double>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s,
                        nA, k, (const double*)U, ldu, t, x, y, skip);
   return hipGetLastError();
 }

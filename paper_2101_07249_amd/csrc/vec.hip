@@ -411,7 +411,7 @@ hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const doub
 }
 
 // Dual pass: r <- r - alpha (Ap + U d1), z = r + U d2, partials of r.r into red[2 kRB ..).
-// 4 consecutive rows per thread, 16-byte loads of U (ldu % 4 == 0).
+// Column-major float64 U: 4 consecutive rows per thread, 16-byte loads (ldu % 4 == 0).
 constexpr int kDC = 16;  // columns per group
 template <typename T>
 static __device__ inline void ld4(const T* p, double (&v)[4]);
@@ -484,6 +484,70 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict
   if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = tot;
 }
 
+
+// Dual pass over the float32 panel copy of U: wave w of a 256-thread block takes
+// columns w, w + 4, ... (two in flight), a lane holds 4 rows of the panel, and the four
+// waves' sums of U d1 and U d2 meet in LDS; thread q then updates row q of the panel.
+// Blocks own panels blockIdx.x, + gridDim.x, ...; block 0 clears the r.r partial slots
+// of blocks that do not exist (gridDim.x .. kRB).
+__global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __restrict__ st,
+                                                          long long nA, int k,
+                                                          const float* __restrict__ P,
+                                                          const double* __restrict__ d12,
+                                                          const double* __restrict__ Ap,
+                                                          double* __restrict__ r,
+                                                          double* __restrict__ z,
+                                                          double* __restrict__ red) {
+  extern __shared__ double sm[];
+  double* sd = sm;             // d1 (k), d2 (k)
+  double* rw = sm + 2 * k;     // [4 waves][2][kPanel rows]
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  for (int c = threadIdx.x; c < 2 * k; c += kRT) sd[c] = d12[c];
+  if (blockIdx.x == 0)
+    for (int b = (int)gridDim.x + threadIdx.x; b < kRB; b += kRT) red[2 * kRB + b] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long np = lmp_panels(nA);
+  double vsum = 0.0;
+  for (long long pn = blockIdx.x; pn < np; pn += gridDim.x) {
+    const float* Pp = P + (size_t)pn * kPanel * k + 4 * lane;
+    double aw[4] = {0.0, 0.0, 0.0, 0.0}, az[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = wave; c0 < k; c0 += 8) {
+      const int c1 = c0 + 4;
+      const float4 u0 = *reinterpret_cast<const float4*>(Pp + (size_t)c0 * kPanel);
+      const float4 u1 = c1 < k ? *reinterpret_cast<const float4*>(Pp + (size_t)c1 * kPanel)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+      const double a0 = sd[c0], b0 = sd[k + c0];
+      const double a1 = c1 < k ? sd[c1] : 0.0, b1 = c1 < k ? sd[k + c1] : 0.0;
+      aw[0] += u0.x * a0; aw[1] += u0.y * a0; aw[2] += u0.z * a0; aw[3] += u0.w * a0;
+      az[0] += u0.x * b0; az[1] += u0.y * b0; az[2] += u0.z * b0; az[3] += u0.w * b0;
+      aw[0] += u1.x * a1; aw[1] += u1.y * a1; aw[2] += u1.z * a1; aw[3] += u1.w * a1;
+      az[0] += u1.x * b1; az[1] += u1.y * b1; az[2] += u1.z * b1; az[3] += u1.w * b1;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      rw[(2 * wave) * kPanel + 4 * lane + e] = aw[e];
+      rw[(2 * wave + 1) * kPanel + 4 * lane + e] = az[e];
+    }
+    __syncthreads();
+    const int q = threadIdx.x;
+    const long long i = pn * kPanel + q;
+    if (i < nA) {
+      const double w = (rw[q] + rw[2 * kPanel + q]) + (rw[4 * kPanel + q] + rw[6 * kPanel + q]);
+      const double zz = (rw[kPanel + q] + rw[3 * kPanel + q]) + (rw[5 * kPanel + q] + rw[7 * kPanel + q]);
+      const double rn = r[i] - alpha * (Ap[i] + w);
+      r[i] = rn;
+      z[i] = rn + zz;
+      vsum += rn * rn;
+    }
+    __syncthreads();
+  }
+  const double tot = block_sum(vsum, sh);
+  if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = tot;
+}
+
 __global__ void k_refresh_decide(PcgState* st) {
   if (threadIdx.x != 0) return;
   const bool go = !st->done && (st->rr < 1e-2 * st->rr_ref || st->iter - st->last_refresh >= 50);
@@ -502,13 +566,18 @@ hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s) {
 hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s) {
-  if (ldu % 4 != 0) return hipErrorInvalidValue;
-  if (u32)
-    hipLaunchKernelGGL(k_pcg_lmp_dual<float>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st, nA,
-                       k, (const float*)U, ldu, d12, Ap, r, z, red);
-  else
+  if (u32) {
+    static_assert(kPanel == kRT, "one thread per panel row in the row update");
+    const int grid = lmp_panel_grid(nA);
+    if (grid > kRB) return hipErrorInvalidValue;   // one r.r partial slot per block
+    hipLaunchKernelGGL(k_pcg_lmp_dual_pan, dim3(grid), dim3(kRT),
+                       sizeof(double) * (2 * k + 8 * kPanel), s, st, nA, k, (const float*)U, d12, Ap, r,
+                       z, red);
+  } else {
+    if (ldu % 4 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pcg_lmp_dual<double>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st,
                        nA, k, (const double*)U, ldu, d12, Ap, r, z, red);
+  }
   hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }

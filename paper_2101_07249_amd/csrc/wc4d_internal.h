@@ -145,7 +145,18 @@ hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double
 // ws: lmp_gemv_ws_doubles(nA, k).
 size_t lmp_gemv_ws_doubles(long long nA, int k);
 size_t lmp_gemv_t_offset(long long nA, int k);
-// U is float64, or float32 when u32 is true (then pass the float array as U).
+// U is float64 column-major (leading dimension ldu), or, when u32 is true, the float32
+// panel-major copy (ldu unused): panel p holds rows [kPanel p, kPanel p + kPanel) of all k
+// columns, column-major with leading dimension kPanel, at offset kPanel k p; rows at or
+// past n_A are zero.
+constexpr int kPanel = 256;
+__host__ __device__ inline long long lmp_panels(long long nA) { return (nA + kPanel - 1) / kPanel; }
+size_t lmp_panel_floats(long long nA, int k);
+// blocks of a pass over all panels (at most 1024, an equal panel count each but the last)
+int lmp_panel_grid(long long nA);
+// P = panel copy of (float)U; Uround (optional, column-major, ldu) = (double)(float)U.
+hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA, int k,
+                         double* Uround, hipStream_t s);
 hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
                       const double* dcoef, const double* x, double* ws, const int* skip,
                       hipStream_t s, double* tout = nullptr);
@@ -175,7 +186,8 @@ hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, 
 hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s);
 hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
 // Fused LMP inside PCG (see vec.hip): coefficients d1 = dcoef.*t, u <- u - alpha (t + GU d1),
-// d2 = dcoef.*u into d12 (2k); then the dual pass updating r, writing z, and beta.
+// d2 = dcoef.*u into d12 (2k); then the dual pass updating r, writing z, and beta.  U as for
+// lmp_gemv_t (float32: the panel copy).
 hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
                           const double* GU, double* u, double* d12, hipStream_t s);
 hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
@@ -342,7 +354,7 @@ struct wc4d_lmp_s {
   size_t wsDoubles = 0;
   double* wsv = nullptr;    // single-vector workspace
   size_t wsvDoubles = 0;
-  float* U32 = nullptr;     // float32 copy of U (WC4D_PREC_LMP_FP32)
+  float* U32 = nullptr;     // float32 panel copy of U (WC4D_PREC_LMP_FP32), see kPanel
   double* GU = nullptr;     // k x k: U^T U of the U the PCG streams
   double* fu = nullptr;     // 3 k: u = U^T r, d1, d2 (fused PCG)
 };

@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 from oracle import wc4d_oracle as O
-from synthetic import C1, C2, C3, Workload, innovations, l96_initial_state, obs_pattern, sketch_block
+from synthetic import (C1, C2, C3, Workload, innovations, l96_initial_state, obs_pattern, random_block,
+                       sketch_block)
 
 pytestmark = pytest.mark.gpu
 
@@ -93,3 +94,42 @@ def test_bf16x3_full_size_sampled_columns():
     e = np.linalg.norm(Y[cols].cpu().numpy().T - Yo) / np.linalg.norm(Yo)
     print("[result] full-size bf16x3 rel err", e, flush=True)
     assert 1e-9 < e <= 1e-4
+
+
+@pytest.mark.parametrize("k_r", [1, 3, 6, 9])
+def test_fp32_panel_lmp_apply_and_pcg(k_r):
+    """The PCG's float32 copy of U is stored in 256-row panels.  C1 has n_A = 840 (three full
+    panels and a ragged one); k_r runs below, at and above the 4 waves x 2 columns that a pass
+    keeps in flight.  One- and two-column applies stream the float32 panels (float32 rounding
+    of U: C v within 1e-5 relative of the oracle's float64 C v); wider ones take the float64
+    block path.  Both PCG variants must match the oracle's PCG to 2 iterations and reach its
+    true residual."""
+    from paper_2101_07249_amd import wc4d
+    import torch
+    w = C1
+    m = k_r + w.l
+    print("[case] fp32 panel LMP, k_r", k_r, flush=True)
+    gm, op = _pair(w, wc4d.PREC_LMP_FP32)
+    G = sketch_block(op.n_A, m, w.seed)
+    L = gm.lmp_build("nystrom", k_r, w.l, _dev(G))
+    Uo, tho = O.METHODS["nystrom"](lambda Z: O.apply_A(op, Z), G, k_r)
+    for ncols in (1, 2, 3):
+        V = random_block(op.n_A, ncols, 9 + ncols)
+        CV = L.apply(_dev(V)).cpu().numpy()
+        CV = CV.T if CV.ndim == 2 else CV[:, None]
+        CVo = O.lmp_apply(Uo, tho, V)
+        e = np.linalg.norm(CV - CVo) / np.linalg.norm(CVo)
+        print("[result] columns", ncols, "rel err", e, flush=True)
+        assert e <= 1e-5
+        if ncols <= 2:
+            assert e > 1e-12   # the float32 copy really is what the one-vector passes read
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-6, maxit=500)
+    for variant in (wc4d.PCG_FUSED, wc4d.PCG_PLAIN):
+        x = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+        info = gm.pcg(gm.rhs(_dev(d)), x, L, tol=1e-6, maxit=500, variant=variant)
+        res = np.linalg.norm(b - O.apply_A(op, x.cpu().numpy())) / np.linalg.norm(b)
+        print("[result] variant", variant, "iters", info["iters"], "oracle", ro.iters, "true res", res, flush=True)
+        assert info["status"] == 0 and res <= 1.01e-6
+        assert abs(info["iters"] - ro.iters) <= 2
