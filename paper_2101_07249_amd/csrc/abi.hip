@@ -70,6 +70,10 @@ wc4d::SweepModel wc4d_problem_s::sweep() const {
   md.obs_off = dObsOff;
   md.obs_idx = dObsIdx;
   md.obs_rinv = dObsRinv;
+  md.tw_pe = twPe;
+  md.tw_W = twW;
+  md.tw_e = dTwE;
+  md.tw_dummy = dTwDummy;
   return md;
 }
 
@@ -132,6 +136,8 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->dObsOff);
   dev_free(&p->dObsIdx);
   dev_free(&p->dObsRinv);
+  dev_free(&p->dTwE);
+  dev_free(&p->dTwDummy);
   dev_free(&p->wsBlock);
   dev_free(&p->wsStash);
   dev_free(&p->wsGram);
@@ -302,6 +308,16 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (!idx.empty()) {
     HIPCHK(p, hipMemcpyAsync(p->dObsIdx, idx.data(), sizeof(int) * idx.size(), hipMemcpyHostToDevice, s));
     HIPCHK(p, hipMemcpyAsync(p->dObsRinv, rinv.data(), sizeof(double) * rinv.size(), hipMemcpyHostToDevice, s));
+  }
+  // per-wavefront observation slots of the single-wave advection-diffusion sweeps
+  int twPe = 0, twW = 0;
+  std::vector<wc4d::TwEntry> went;
+  if (p->model == 0 && tw_setup(n, N, off, idx, rinv, &twPe, &twW, went)) {
+    if ((rc = dev_alloc(p, &p->dTwE, went.size()))) return rc;
+    if ((rc = dev_alloc(p, &p->dTwDummy, 1))) return rc;
+    HIPCHK(p, hipMemcpyAsync(p->dTwE, went.data(), sizeof(TwEntry) * went.size(), hipMemcpyHostToDevice, s));
+    p->twPe = twPe;
+    p->twW = twW;
   }
   std::vector<double> stages;
   if (p->model == 1) {

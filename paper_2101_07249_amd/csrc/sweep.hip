@@ -8,6 +8,9 @@
 // next step's forcing p_{i+1} (or z_i) in registers, loaded one step ahead.
 // HBM traffic per column: the n_A forcing values in, the q stash values out
 // (forward); the q stash values in, the n_A outputs out (adjoint).
+#include <algorithm>
+#include <vector>
+
 #include "wc4d_internal.h"
 
 namespace wc4d {
@@ -749,237 +752,299 @@ static hipError_t l96v_bwd_launch(const SweepModel& md, const double* stash, con
   return hipGetLastError();
 }
 
-// ------------------------------------------- time-blocked advection-diffusion
-// For one or a few columns the window's N sequential steps over the whole domain
-// are latency-bound.  The stencil has radius 1, so a workgroup can own W points
-// [j0, j0 + W) and run all N steps on the extended range [j0 - N, j0 + W + N)
-// (periodic indices, n >= E = W + 2N so no point appears twice): after s steps
-// only the outer s points on each side are wrong, so the owned points are exact
-// at every level.  Workgroups never communicate.  512 threads, PE points each.
-constexpr int kTBT = 512;
-constexpr int kMaxTbLevels = 1026;  // N + 2 <= kMaxTbLevels
+// ------------------------------------ single-wave trapezoids (advection-diffusion)
+// For one or a few columns the window's N sequential steps over the whole domain are
+// latency-bound.  The stencil has radius 1, so a wavefront can own W points [j0, j0 + W)
+// and run all N steps on the extended range [j0 - N, j0 + W + N) (periodic indices;
+// n >= E = 64 PE, so no point appears twice): after s steps only the outer s points on
+// each side are wrong, so the owned points are exact at every level, and wavefronts
+// never communicate.  Lane l holds the PE contiguous local points [l PE, (l + 1) PE) in
+// registers and takes its neighbours' edge points through DPP wavefront shifts, so a
+// step needs no barrier.
+//
+// A step must not wait on memory: loads (and, on this architecture, stores) retire in
+// order through one counter, so any load whose address depends on another load, or a
+// store-heavy step, drains the prefetch queue.  Hence the forcing rows are prefetched TD
+// steps ahead in a register ring; the observations a wavefront touches come from
+// fixed-slot lists built at finalize (no offsets to chase: slot s of (wavefront b,
+// level t) at ((b (N+1) + t) kTS + s), entry {k, local point l, 1 / R_kk}, l < 0 for an
+// empty slot); the adjoint reads its entries 2 TD steps and their stash values TD steps
+// ahead; and the adjoint's output rows leave through LDS as coalesced stores.
+constexpr int kTW = 64;            // one wavefront per workgroup
+constexpr int kTOW = 2;            // entry slots per lane per (wavefront, level)
+constexpr int kTS = kTW * kTOW;    // entry slots per (wavefront, level)
 
-struct TbCfg {
-  int pe, W;  // points per thread, owned width; pe = 0: not applicable
+bool tw_setup(int n, int N, const std::vector<int>& off, const std::vector<int>& idx,
+              const std::vector<double>& rinv, int* pe, int* W, std::vector<TwEntry>& ent) {
+  int q = 4;
+  for (; q <= 16; q *= 2) {
+    const int E = kTW * q, w = E - 2 * N;
+    if (w > 0 && 2 * w >= E && n >= E) break;
+  }
+  if (q > 16 || off[N + 1] == 0) return false;
+  const int E = kTW * q, Wd = E - 2 * N, nb = (n + Wd - 1) / Wd;
+  ent.assign((size_t)nb * (N + 1) * kTS, TwEntry{0, -1, 0.0});
+  for (int b = 0; b < nb; ++b) {
+    const int j0 = b * Wd, Wc = std::min(Wd, n - j0), Ec = Wc + 2 * N, g0 = j0 - N;
+    for (int t = 0; t <= N; ++t) {
+      TwEntry* slot = ent.data() + ((size_t)b * (N + 1) + t) * kTS;
+      int c = 0;
+      for (int k = off[t]; k < off[t + 1]; ++k) {
+        int l = (idx[k] - g0) % n;
+        if (l < 0) l += n;
+        if (l >= Ec) continue;
+        if (c == kTS) return false;  // denser than the slots: the general kernels take it
+        slot[c++] = TwEntry{k, l, rinv[k]};
+      }
+    }
+  }
+  *pe = q;
+  *W = Wd;
+  return true;
+}
+
+// v of lane - 1 (lane 0 keeps its own) and of lane + 1 (lane 63 keeps its own): DPP
+// wavefront shifts (wave_shr:1, wave_shl:1), one per 32-bit half.  The kept edge values
+// only reach points outside the trapezoid.
+static __device__ inline double from_lower_lane(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+static __device__ inline double from_upper_lane(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
+// A lane's local points: byte offsets of their global indices within a level, and which
+// of them the wavefront owns.  Points past the extended range (last wavefront) and rows
+// past the last level are loaded anyway: they hold finite data of other points and,
+// like the trapezoid's edges, never reach an owned point.
+template <int PE>
+struct TwGeom {
+  unsigned off8[PE];
+  bool own[PE];
+  int N, Wc, j0;
+  __device__ TwGeom(int n, int N_, int W, int lane) : N(N_) {
+    j0 = blockIdx.x * W;
+    Wc = min(W, n - j0);
+    const int g0 = j0 - N;
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+      const int l = lane * PE + e;
+      int j = g0 + l;  // in [-N, n + E): one wrap at most
+      j = j < 0 ? j + n : (j >= n ? j - n : j);
+      off8[e] = 8u * (unsigned)j;
+      own[e] = l >= N && l < N + Wc;
+    }
+  }
+  __device__ bool owned(int l) const { return l >= N && l < N + Wc; }
+  // v = row lev (clamped to [0, last]) of the n-long rows at base, at this lane's points
+  __device__ void load(const double* base, int lev, int last, int n, double (&v)[PE]) const {
+    lev = lev < 0 ? 0 : (lev > last ? last : lev);
+    const char* row = reinterpret_cast<const char*>(base + (size_t)lev * n);
+#pragma unroll
+    for (int e = 0; e < PE; ++e) v[e] = *reinterpret_cast<const double*>(row + off8[e]);
+  }
+  __device__ void store(double* base, int lev, int n, const double (&v)[PE]) const {
+    char* row = reinterpret_cast<char*>(base + (size_t)lev * n);
+#pragma unroll
+    for (int e = 0; e < PE; ++e)
+      if (own[e]) *reinterpret_cast<double*>(row + off8[e]) = v[e];
+  }
 };
 
-static TbCfg tb_cfg(int n, int N) {
-  for (int pe = 1; pe <= 4; pe *= 2) {
-    const int E = kTBT * pe;
-    const int W = E - 2 * N;
-    if (2 * W >= E && n >= E) return TbCfg{pe, W};
-  }
-  return TbCfg{0, 0};
+// the kTOW entry slots of (wavefront, level t) this lane reads (t clamped to [0, N])
+static __device__ inline const TwEntry* tw_slots(const SweepModel& md, int t) {
+  t = t < 0 ? 0 : (t > md.N ? md.N : t);
+  return md.tw_e + ((size_t)blockIdx.x * (md.N + 1) + t) * kTS + threadIdx.x;
 }
 
-// local index of global point j in the extended range starting at g0 (or -1)
-static __device__ inline int tb_local(int j, int g0, int n, int Ec) {
-  int l = j - g0;
-  l %= n;
-  if (l < 0) l += n;
-  return l < Ec ? l : -1;
-}
-
-template <int PE>
-static __device__ inline void tb_load(const double* base, int lev, int last, int n, int g0, int Ec,
-                                      double (&f)[PE]) {
-#pragma unroll
-  for (int e = 0; e < PE; ++e) {
-    const int l = threadIdx.x + e * kTBT;
-    int j = (g0 + l) % n;
-    if (j < 0) j += n;
-    f[e] = (base != nullptr && l < Ec && lev >= 0 && lev <= last) ? base[(size_t)lev * n + j] : 0.0;
-  }
-}
-
-// Observation list of one level for the time-blocked kernels (kTOB entries per
-// thread prefetched; q_i <= kTOB * 512 covers every level of the shipped workloads).
-constexpr int kTOB = 2;
-constexpr int kTD = 8;  // prefetch depth in steps
-
-struct TbObs {
-  int kb, ke;
-  int idx[kTOB];
-  double val[kTOB];
-};
-
-static __device__ inline void tb_obs_fwd(const SweepModel& md, const int* s_off, int t, int N, TbObs& o) {
-  o.kb = (t >= 0 && t <= N) ? s_off[t] : 0;
-  o.ke = (t >= 0 && t <= N) ? s_off[t + 1] : 0;
-#pragma unroll
-  for (int e = 0; e < kTOB; ++e) {
-    const int k = o.kb + (int)threadIdx.x + e * kTBT;
-    const bool v = k < o.ke;
-    o.idx[e] = v ? md.obs_idx[k] : 0;
-    o.val[e] = v ? md.obs_rinv[k] : 0.0;
-  }
-}
-
-static __device__ inline void tb_obs_bwd(const SweepModel& md, const int* s_off, int t, int N,
-                                         const double* st, TbObs& o) {
-  o.kb = (t >= 0 && t <= N) ? s_off[t] : 0;
-  o.ke = (t >= 0 && t <= N) ? s_off[t + 1] : 0;
-#pragma unroll
-  for (int e = 0; e < kTOB; ++e) {
-    const int k = o.kb + (int)threadIdx.x + e * kTBT;
-    const bool v = k < o.ke;
-    o.idx[e] = v ? md.obs_idx[k] : 0;
-    o.val[e] = v ? st[k] : 0.0;
-  }
-}
-
-// Forcing and observation lists are prefetched kTD steps ahead in a register ring;
-// the time loop is unrolled by kTD so every ring slot is consumed in place.
-template <int PE>
-__global__ __launch_bounds__(kTBT) void k_sweep_fwd_tb(SweepModel md, int W, const double* __restrict__ P,
-                                                       long long ldp, double* __restrict__ stash,
-                                                       long long ldst, double* __restrict__ Xout,
-                                                       long long ldx, const int* __restrict__ skip) {
-  constexpr int E = kTBT * PE;
-  __shared__ double b0[E + 2], b1[E + 2];
-  __shared__ int s_off[kMaxTbLevels];
+// WX: also write every x_t (owned points) to Xout.  The step count of the main loop is a
+// multiple of TD with no per-step guards and every memory operation of a step is issued
+// unconditionally (the stash store of a slot the wavefront does not own goes to a dummy
+// double), so the compiler can keep the ring's loads in flight across the loop's back edge.
+template <int PE, int TD, bool WX>
+__global__ __launch_bounds__(kTW) void k_sweep_fwd_w(SweepModel md, const double* __restrict__ P,
+                                                     long long ldp, double* __restrict__ stash,
+                                                     long long ldst, double* __restrict__ Xout,
+                                                     long long ldx, const int* __restrict__ skip) {
+  __shared__ double xs[kTW * PE];
   if (skip != nullptr && *skip != 0) return;
-  const int n = md.n, N = md.N;
-  const int col = blockIdx.y;
-  const int j0 = blockIdx.x * W;
-  const int Wc = min(W, n - j0);
-  const int Ec = Wc + 2 * N;
-  const int g0 = j0 - N;  // global index of local point 0
-  for (int t = threadIdx.x; t < N + 2; t += kTBT) s_off[t] = md.obs_off[t];
-  const double* Pc = P + (size_t)col * ldp;
-  double* St = stash != nullptr ? stash + (size_t)col * ldst : nullptr;
-  double* Xc = Xout != nullptr ? Xout + (size_t)col * ldx : nullptr;
-  double f[kTD][PE], xn[PE];
-  tb_load<PE>(Pc, 0, N, n, g0, Ec, xn);
+  const int n = md.n, N = md.N, lane = threadIdx.x;
+  const TwGeom<PE> g(n, N, md.tw_W, lane);
+  const double* Pc = P + (size_t)blockIdx.y * ldp;
+  double* St = stash + (size_t)blockIdx.y * ldst;
+  double* Xc = WX ? Xout + (size_t)blockIdx.y * ldx : nullptr;
+  double x[PE], f[TD][PE];
+  TwEntry ob[TD][kTOW];
+  auto load_obs = [&](int t, TwEntry (&o)[kTOW]) {
+    const TwEntry* sl = tw_slots(md, t);
 #pragma unroll
-  for (int e = 0; e < PE; ++e) b0[threadIdx.x + e * kTBT] = xn[e];
+    for (int r = 0; r < kTOW; ++r) o[r] = sl[kTW * r];
+  };
+  // level t's outputs: stash_k = x_j / R_kk for owned observations (and owned points of x)
+  auto emit = [&](int t, const TwEntry (&o)[kTOW]) {
+    if (WX) g.store(Xc, t, n, x);
 #pragma unroll
-  for (int u = 0; u < kTD; ++u) tb_load<PE>(Pc, u + 1, N, n, g0, Ec, f[u]);
-  __syncthreads();
-  TbObs ob[kTD];
-  // observations and outputs of level i from buffer x
-  auto emit = [&](int i, const double* x, const TbObs& o) {
-    if (Xc != nullptr) {
-      for (int l = N + threadIdx.x; l < N + Wc; l += kTBT) Xc[(size_t)i * n + (g0 + l)] = x[l];
+    for (int e = 0; e < PE; ++e) xs[lane * PE + e] = x[e];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTOW; ++r) {
+      const bool own = g.owned(o[r].l);
+      double* dst = own ? St + o[r].k : md.tw_dummy;
+      *dst = o[r].v * xs[own ? o[r].l : 0];
     }
-    if (St != nullptr) {
+    __syncthreads();
+  };
+  auto step = [&](int i, double (&fu)[PE], TwEntry (&ou)[kTOW]) {
+    const double xm = from_lower_lane(x[PE - 1]), xp = from_upper_lane(x[0]);
+    double nx[PE];
 #pragma unroll
-      for (int e = 0; e < kTOB; ++e) {
-        const int k = o.kb + (int)threadIdx.x + e * kTBT;
-        const int j = o.idx[e];
-        if (k < o.ke && j >= j0 && j < j0 + Wc) St[k] = o.val[e] * x[j - g0];
-      }
-      for (int k = o.kb + threadIdx.x + kTOB * kTBT; k < o.ke; k += kTBT) {
-        const int j = md.obs_idx[k];
-        if (j >= j0 && j < j0 + Wc) St[k] = md.obs_rinv[k] * x[j - g0];
-      }
+    for (int e = 0; e < PE; ++e) {
+      const double left = e > 0 ? x[e - 1] : xm, right = e + 1 < PE ? x[e + 1] : xp;
+      nx[e] = md.ca * left + md.cb * x[e] + md.cc * right + fu[e];
+    }
+#pragma unroll
+    for (int e = 0; e < PE; ++e) x[e] = nx[e];
+    g.load(Pc, i + 1 + TD, N, n, fu);
+    emit(i + 1, ou);
+    load_obs(i + 1 + TD, ou);
+  };
+  g.load(Pc, 0, N, n, x);
+#pragma unroll
+  for (int u = 0; u < TD; ++u) g.load(Pc, u + 1, N, n, f[u]);
+  {
+    TwEntry o0[kTOW];
+    load_obs(0, o0);
+    emit(0, o0);
+  }
+#pragma unroll
+  for (int u = 0; u < TD; ++u) load_obs(u + 1, ob[u]);
+  const int full = N - N % TD;
+  for (int i = 0; i < full; i += TD) {
+#pragma unroll
+    for (int u = 0; u < TD; ++u) step(i + u, f[u], ob[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < TD; ++u)
+    if (full + u < N) step(full + u, f[u], ob[u]);
+}
+
+// Adjoint from the stash (z_t = H_t^T stash_t); a dense adjoint forcing takes the
+// general kernel.
+template <int PE, int TD>
+__global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double* __restrict__ stash,
+                                                     long long ldst, double* __restrict__ Wout,
+                                                     long long ldw, const int* __restrict__ skip) {
+  __shared__ double xs[kTW * PE];
+  if (skip != nullptr && *skip != 0) return;
+  const int n = md.n, N = md.N, lane = threadIdx.x;
+  const TwGeom<PE> g(n, N, md.tw_W, lane);
+  const double* St = stash + (size_t)blockIdx.y * ldst;
+  double* Wc = Wout + (size_t)blockIdx.y * ldw;
+  // n even: every wavefront's owned run starts at an even index (W is even) in a row that
+  // starts at an even index, so with a 16-byte aligned column the stores can be 16 bytes
+  // wide (and the owned count g.Wc is even)
+  const bool vec2 = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(Wc) & 15) == 0;
+  // entries {k, l} of the level 2 TD steps ahead, values (l, stash_k) of the level TD steps
+  // ahead.  Levels below 0 read level 0's slots (no step consumes them).  Nothing may touch
+  // a loaded register before its use, or the step would wait for it: the entries stay
+  // int2 pairs as loaded.
+  int2 ent[TD][kTOW];
+  int bl[TD][kTOW];
+  double bv[TD][kTOW];
+  auto load_ent = [&](int t, int2 (&o)[kTOW]) {
+    const TwEntry* sl = tw_slots(md, t);
+#pragma unroll
+    for (int r = 0; r < kTOW; ++r) o[r] = *reinterpret_cast<const int2*>(sl + kTW * r);
+  };
+  // empty slots hold k = 0, a valid stash entry (q >= 1): every load is issued, so the
+  // number of memory operations per step is fixed
+  auto load_val = [&](const int2 (&o)[kTOW], int (&ol)[kTOW], double (&v)[kTOW]) {
+#pragma unroll
+    for (int r = 0; r < kTOW; ++r) {
+      ol[r] = o[r].y;
+      v[r] = St[o[r].x];
     }
   };
-  {
-    TbObs o0;
-    tb_obs_fwd(md, s_off, 0, N, o0);
-    emit(0, b0, o0);
-  }
+  double w[PE];
+  // H_t^T stash_t added over the extended range, then the owned points of level t written
+  // out through LDS, 64 (n odd) or 128 (n even) consecutive doubles per store instruction
+  auto finish = [&](int t, const int (&ol)[kTOW], const double (&v)[kTOW]) {
 #pragma unroll
-  for (int u = 0; u < kTD; ++u) tb_obs_fwd(md, s_off, u + 1, N, ob[u]);
-  for (int i = 0; i < N; i += kTD) {
+    for (int e = 0; e < PE; ++e) xs[lane * PE + e] = 0.0;
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < kTD; ++u) {
-      if (i + u < N) {
-        const double* cur = (u & 1) ? b1 : b0;
-        double* nxt = (u & 1) ? b0 : b1;
+    for (int r = 0; r < kTOW; ++r)
+      if (ol[r] >= 0) xs[ol[r]] = v[r];
+    __syncthreads();
 #pragma unroll
-        for (int e = 0; e < PE; ++e) {
-          const int l = threadIdx.x + e * kTBT;
-          const int lm = l > 0 ? l - 1 : l, lp = l + 1 < E ? l + 1 : l;
-          nxt[l] = md.ca * cur[lm] + md.cb * cur[l] + md.cc * cur[lp] + f[u][e];
-        }
-        tb_load<PE>(Pc, i + u + 1 + kTD, N, n, g0, Ec, f[u]);
-        __syncthreads();
-        emit(i + u + 1, nxt, ob[u]);
-        tb_obs_fwd(md, s_off, i + u + 1 + kTD, N, ob[u]);
+    for (int e = 0; e < PE; ++e) {
+      w[e] += xs[lane * PE + e];
+      xs[lane * PE + e] = w[e];
+    }
+    __syncthreads();
+    // a fixed number of unconditional stores (W <= 64 PE): lanes past the owned range
+    // repeat the last segment with the same values
+    double* row = Wc + (size_t)t * n + g.j0;
+    const double* src = xs + N;
+    if (vec2) {
+#pragma unroll
+      for (int it = 0; it < PE / 2; ++it) {
+        const int c = min(2 * lane + 2 * kTW * it, g.Wc - 2);
+        *reinterpret_cast<double2*>(row + c) = make_double2(src[c], src[c + 1]);
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < PE; ++it) {
+        const int c = min(lane + kTW * it, g.Wc - 1);
+        row[c] = src[c];
       }
     }
-  }
-}
-
-template <int PE>
-__global__ __launch_bounds__(kTBT) void k_sweep_bwd_tb(SweepModel md, int W, const double* __restrict__ stash,
-                                                       long long ldst, const double* __restrict__ Z,
-                                                       long long ldz, double* __restrict__ Wout,
-                                                       long long ldw, const int* __restrict__ skip) {
-  constexpr int E = kTBT * PE;
-  __shared__ double b0[E + 2], b1[E + 2];
-  __shared__ int s_off[kMaxTbLevels];
-  if (skip != nullptr && *skip != 0) return;
-  const int n = md.n, N = md.N;
-  const int col = blockIdx.y;
-  const int j0 = blockIdx.x * W;
-  const int Wc = min(W, n - j0);
-  const int Ec = Wc + 2 * N;
-  const int g0 = j0 - N;
-  for (int t = threadIdx.x; t < N + 2; t += kTBT) s_off[t] = md.obs_off[t];
-  const double* St = stash != nullptr ? stash + (size_t)col * ldst : nullptr;
-  const double* Zc = (stash == nullptr) ? Z + (size_t)col * ldz : nullptr;
-  double* Wc_ = Wout + (size_t)col * ldw;
-  double z[kTD][PE], wn[PE];
-  tb_load<PE>(Zc, N, N, n, g0, Ec, wn);
-#pragma unroll
-  for (int e = 0; e < PE; ++e) b0[threadIdx.x + e * kTBT] = wn[e];
-#pragma unroll
-  for (int u = 0; u < kTD; ++u) tb_load<PE>(Zc, N - 1 - u, N, n, g0, Ec, z[u]);
-  __syncthreads();
-  // H_i^T stash_i added into the extended range, then the owned points written out
-  auto finish = [&](int i, double* w, const TbObs& o) {
-    if (St != nullptr) {
-#pragma unroll
-      for (int e = 0; e < kTOB; ++e) {
-        const int k = o.kb + (int)threadIdx.x + e * kTBT;
-        if (k < o.ke) {
-          const int l = tb_local(o.idx[e], g0, n, Ec);
-          if (l >= 0) w[l] += o.val[e];
-        }
-      }
-      for (int k = o.kb + threadIdx.x + kTOB * kTBT; k < o.ke; k += kTBT) {
-        const int l = tb_local(md.obs_idx[k], g0, n, Ec);
-        if (l >= 0) w[l] += St[k];
-      }
-      __syncthreads();
-    }
-    for (int l = N + threadIdx.x; l < N + Wc; l += kTBT) Wc_[(size_t)i * n + (g0 + l)] = w[l];
+    __syncthreads();
   };
-  TbObs ob[kTD];
+#pragma unroll
+  for (int e = 0; e < PE; ++e) w[e] = 0.0;
   {
-    TbObs oN;
-    if (St != nullptr) tb_obs_bwd(md, s_off, N, N, St, oN);
-    else oN.kb = oN.ke = 0;
-    finish(N, b0, oN);
+    int2 e0[kTOW];
+    int ol[kTOW];
+    double v0[kTOW];
+    load_ent(N, e0);
+    load_val(e0, ol, v0);
+    finish(N, ol, v0);
   }
 #pragma unroll
-  for (int u = 0; u < kTD; ++u) {
-    if (St != nullptr) tb_obs_bwd(md, s_off, N - 1 - u, N, St, ob[u]);
-    else ob[u].kb = ob[u].ke = 0;
+  for (int u = 0; u < TD; ++u) {
+    int2 e0[kTOW];
+    load_ent(N - 1 - u, e0);
+    load_val(e0, bl[u], bv[u]);
+    load_ent(N - 1 - u - TD, ent[u]);
   }
-  for (int i0 = N - 1; i0 >= 0; i0 -= kTD) {
+  auto step = [&](int i, int2 (&eu)[kTOW], int (&lu)[kTOW], double (&vu)[kTOW]) {
+    const double wm = from_lower_lane(w[PE - 1]), wp = from_upper_lane(w[0]);
+    double nw[PE];
 #pragma unroll
-    for (int u = 0; u < kTD; ++u) {
-      const int i = i0 - u;
-      if (i >= 0) {
-        const double* cur = (u & 1) ? b1 : b0;
-        double* nxt = (u & 1) ? b0 : b1;
-#pragma unroll
-        for (int e = 0; e < PE; ++e) {
-          const int l = threadIdx.x + e * kTBT;
-          const int lm = l > 0 ? l - 1 : l, lp = l + 1 < E ? l + 1 : l;
-          nxt[l] = md.ca * cur[lp] + md.cb * cur[l] + md.cc * cur[lm] + z[u][e];
-        }
-        tb_load<PE>(Zc, i - kTD, N, n, g0, Ec, z[u]);
-        __syncthreads();
-        finish(i, nxt, ob[u]);
-        if (St != nullptr) tb_obs_bwd(md, s_off, i - kTD, N, St, ob[u]);
-      }
+    for (int e = 0; e < PE; ++e) {
+      const double left = e > 0 ? w[e - 1] : wm, right = e + 1 < PE ? w[e + 1] : wp;
+      nw[e] = md.ca * right + md.cb * w[e] + md.cc * left;
     }
+#pragma unroll
+    for (int e = 0; e < PE; ++e) w[e] = nw[e];
+    finish(i, lu, vu);
+    load_val(eu, lu, vu);
+    load_ent(i - 2 * TD, eu);
+  };
+  // full trips of TD steps without guards (levels N-1 down to N % TD), then the rest
+  const int rest = N % TD;
+  for (int i0 = N - 1; i0 >= rest; i0 -= TD) {
+#pragma unroll
+    for (int u = 0; u < TD; ++u) step(i0 - u, ent[u], bl[u], bv[u]);
   }
+#pragma unroll
+  for (int u = 0; u < TD; ++u)
+    if (u < rest) step(rest - 1 - u, ent[u], bl[u], bv[u]);
 }
 
 // --------------------------------------------------------------- launch
@@ -1030,15 +1095,25 @@ hipError_t sweep_fwd(const SweepModel& md, const double* P, long long ldp, int m
     case 16: return l96v_fwd_launch<16>(md, P, stash, Xout, skip, s);
     default: break;
   }
-  const TbCfg tc = tb_cfg(md.n, md.N);
-  if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
-    dim3 grid((md.n + tc.W - 1) / tc.W, m);
-    if (tc.pe == 1)
-      hipLaunchKernelGGL(k_sweep_fwd_tb<1>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
-    else if (tc.pe == 2)
-      hipLaunchKernelGGL(k_sweep_fwd_tb<2>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
-    else
-      hipLaunchKernelGGL(k_sweep_fwd_tb<4>, grid, dim3(kTBT), 0, s, md, tc.W, P, ldp, stash, ldst, Xout, ldx, skip);
+  if (md.kind == 0 && m <= 8 && md.tw_pe > 0 && stash != nullptr) {
+    dim3 grid((md.n + md.tw_W - 1) / md.tw_W, m);
+#define WC4D_TW_FWD(PE, TD)                                                                        \
+  if (Xout != nullptr)                                                                             \
+    hipLaunchKernelGGL((k_sweep_fwd_w<PE, TD, true>), grid, dim3(kTW), 0, s, md, P, ldp, stash, ldst, \
+                       Xout, ldx, skip);                                                           \
+  else                                                                                             \
+    hipLaunchKernelGGL((k_sweep_fwd_w<PE, TD, false>), grid, dim3(kTW), 0, s, md, P, ldp, stash,     \
+                       ldst, Xout, ldx, skip);
+    if (md.tw_pe == 4) {
+      WC4D_TW_FWD(4, 8)
+    } else if (md.tw_pe == 8) {
+      WC4D_TW_FWD(8, 8)
+    } else if (md.tw_pe == 16) {
+      WC4D_TW_FWD(16, 4)
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef WC4D_TW_FWD
     return hipGetLastError();
   }
   const SweepCfg c = sweep_cfg(md.n, md.kind);
@@ -1062,15 +1137,16 @@ hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, 
     case 16: return l96v_bwd_launch<16>(md, stash, Z, W, skip, s);
     default: break;
   }
-  const TbCfg tc = tb_cfg(md.n, md.N);
-  if (md.kind == 0 && m <= 8 && tc.pe > 0 && md.N + 2 <= kMaxTbLevels) {
-    dim3 grid((md.n + tc.W - 1) / tc.W, m);
-    if (tc.pe == 1)
-      hipLaunchKernelGGL(k_sweep_bwd_tb<1>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
-    else if (tc.pe == 2)
-      hipLaunchKernelGGL(k_sweep_bwd_tb<2>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
+  if (md.kind == 0 && m <= 8 && md.tw_pe > 0 && stash != nullptr) {
+    dim3 grid((md.n + md.tw_W - 1) / md.tw_W, m);
+    if (md.tw_pe == 4)
+      hipLaunchKernelGGL((k_sweep_bwd_w<4, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+    else if (md.tw_pe == 8)
+      hipLaunchKernelGGL((k_sweep_bwd_w<8, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+    else if (md.tw_pe == 16)
+      hipLaunchKernelGGL((k_sweep_bwd_w<16, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
     else
-      hipLaunchKernelGGL(k_sweep_bwd_tb<4>, grid, dim3(kTBT), 0, s, md, tc.W, stash, ldst, Z, ldz, W, ldw, skip);
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
   const SweepCfg c = sweep_cfg(md.n, md.kind);

@@ -88,6 +88,12 @@ hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, 
                        ColMap emap, hipStream_t s);
 
 // Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
+// observation k at local point l of a sweep wavefront's extended range (l < 0: empty)
+struct alignas(16) TwEntry {
+  int k, l;
+  double v;  // 1 / R_kk
+};
+
 struct SweepModel {
   int kind;                 // 0 advdiff, 1 l96
   int n, N;
@@ -97,7 +103,19 @@ struct SweepModel {
   const int* obs_off;       // device (N+2): time i's observations are [obs_off[i], obs_off[i+1])
   const int* obs_idx;       // device q grid indices
   const double* obs_rinv;   // device q values 1 / R_ii
+  // advection-diffusion single-wave trapezoids (tw_pe = 0: not used): PE points per lane,
+  // W owned points per wavefront, fixed-slot observation entries (see sweep.hip)
+  int tw_pe, tw_W;
+  const TwEntry* tw_e;
+  double* tw_dummy;   // one device double: target of the stores of unowned slots
 };
+
+// Trapezoid shape for the advection-diffusion sweeps of one or a few columns (the
+// smallest PE in {4, 8, 16} with E = 64 PE, W = E - 2N, 2W >= E and n >= E) and the
+// per (wavefront, level) observation slots; false when no shape fits or a wavefront's
+// level holds more observations than its slots.
+bool tw_setup(int n, int N, const std::vector<int>& off, const std::vector<int>& idx,
+              const std::vector<double>& rinv, int* pe, int* W, std::vector<TwEntry>& ent);
 
 // Forward sweep x_0 = p_0, x_{i+1} = M_i x_i + p_{i+1}.  Writes stash(k, c) =
 // rinv[k] * x_{i(k)}[idx[k]] (ldst >= q) when stash != null, and every x_i into
@@ -291,6 +309,9 @@ struct wc4d_problem_s {
   int* dObsOff = nullptr;
   int* dObsIdx = nullptr;
   double* dObsRinv = nullptr;
+  int twPe = 0, twW = 0;     // single-wave sweep shape (advection-diffusion), 0: none
+  wc4d::TwEntry* dTwE = nullptr;
+  double* dTwDummy = nullptr;
   // workspaces (grown on demand)
   double* wsBlock = nullptr;  // n_A x cap
   long long wsBlockCols = 0;

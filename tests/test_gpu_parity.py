@@ -70,12 +70,13 @@ CASES = {
     "tiny_l96": tiny("l96", n=10),
     "ragged_adv": tiny(n=37, N=7, vs=3, ts=1),           # n not a multiple of any tile
     "ragged_l96": tiny("l96", n=67, N=5, vs=5, ts=1),    # several waves, ragged tail
-    "wide_adv": tiny(n=300, N=3, vs=7, ts=3),             # 256 threads x 2 points, ragged
+    "wide_adv": tiny(n=300, N=3, vs=7, ts=3),             # PE 4, W 250 (m > 8: 2 points/thread)
     "n1_adv": tiny(n=1, N=6, vs=1, ts=2),
-    # time-blocked single-vector sweeps (n >= 512): owned chunks with an N-point halo
-    "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # 2 chunks, ragged last chunk, 1 point/thread
-    "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # 4 chunks of 312
-    "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # 2 points/thread, chunks of 624
+    # single-wave trapezoid sweeps (m <= 8): each wavefront owns W points and runs the
+    # extended range of 64 PE points, W = 64 PE - 2N; the last wavefront owns fewer
+    "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # PE 4, W 196: 4 wavefronts, last owns 12
+    "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # PE 8, W 312: 4 wavefronts, last owns 164
+    "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # PE 16, W 624: 2 wavefronts, last owns 476
     # B and Q with different length scales: D^{1/2} as two products (no B = c Q shortcut)
     "bq_adv": tiny(n=600, N=30, vs=5, ts=3).with_(Lq=3.0),
     # (Gaussian L = 1.5: smallest correlation eigenvalue 1.5e-5; a longer scale on n = 256
