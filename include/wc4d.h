@@ -222,11 +222,14 @@ int wc4d_last_apply_timing(wc4d_problem p, float* ms4);
  * pass and 4 the x + U t pass of a single-vector LMP application, 5 the other
  * kernels of an LMP build, 6 the split-bfloat16 D^{1/2} products (flops counted as
  * the three bfloat16 products), 7 the learned-sketch network's inference (features and
- * convolutions; flops of the convolutions).  wc4d_prof_enable resets the totals;
- * wc4d_prof_read waits for the recorded work and reports one class. */
+ * convolutions; flops of the convolutions).  wc4d_prof_enable resets the totals and
+ * times the classes whose bits are set in enable (bit c: class c; WC4D_PROF_ALL every
+ * class, 0 none; each timed launch group adds two event records to the stream);
+ * wc4d_prof_read waits for the recorded work and reports one class.  enable < 0 is
+ * WC4D_EINVAL. */
 enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC4D_PROF_LMP_T = 3,
        WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_DSQRT_BF16 = 6,
-       WC4D_PROF_NET = 7, WC4D_PROF_NCLASS = 8 };
+       WC4D_PROF_NET = 7, WC4D_PROF_NCLASS = 8, WC4D_PROF_ALL = 0xFF };
 int wc4d_prof_enable(wc4d_problem p, int enable);
 int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
                    double* flops);

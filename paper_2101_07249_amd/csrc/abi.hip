@@ -392,7 +392,7 @@ int wc4d_dims(wc4d_problem p, int* nA, int* q) {
 }
 
 int wc4d_prof_enable(wc4d_problem p, int enable) {
-  if (p == nullptr) return WC4D_EINVAL;
+  if (p == nullptr || enable < 0) return WC4D_EINVAL;
   DevGuard g(p->device);
   int rc = prof_collect(p);
   if (rc) return rc;
@@ -400,7 +400,7 @@ int wc4d_prof_enable(wc4d_problem p, int enable) {
     p->profMs[c] = p->profBytes[c] = p->profFlops[c] = 0.0;
     p->profCalls[c] = 0;
   }
-  p->kprof = enable != 0;
+  p->kprof = enable & ((1 << PROF_NCLASS) - 1);
   return WC4D_OK;
 }
 
@@ -986,8 +986,28 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
   while (!fin) {
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
+      if (fused && u32) {
+        // 7 launches after the operator: U^T Ap (+ p.Ap), coefficients (+ alpha), the dual
+        // pass (+ x, s), beta (+ the refresh decision), p, and the refresh of u = U^T r
+        const double ub = 4.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
+        if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
+        {
+          ProfScope ps(p, s, PROF_LMP_T, ub + 16.0 * nA, fl + 2.0 * nA);
+          HIPCHK(p, lmp_pan_t_partials(nA, L->k, L->U32, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), s));
+        }
+        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), L->wsv, p->pcgRed, L->dcoef, L->GU, u,
+                                     d12, s));
+        {
+          ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 9.0 * nA, 2.0 * fl);
+          HIPCHK(p, pcg_lmp_dual_pan(st, nA, L->k, L->U32, d12, Ap, r, z, x, sres, b, pv, p->pcgRed, p->pcgHist,
+                                     s));
+        }
+        HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
+        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        continue;
+      }
       if (fused) {
-        const double ub = (u32 ? 4.0 : 8.0) * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
+        const double ub = 8.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
         if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
         HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
         HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
@@ -998,12 +1018,10 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
         HIPCHK(p, pcg_lmp_coeffs(st, L->k, tvec, L->dcoef, L->GU, u, d12, s));
         {
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 4.0 * nA, 2.0 * fl);
-          HIPCHK(p, pcg_lmp_dual(st, nA, L->k, Us, u32, L->ldu, d12, Ap, r, z, p->pcgRed, p->pcgHist, s));
+          HIPCHK(p, pcg_lmp_dual(st, nA, L->k, L->U, L->ldu, d12, Ap, r, z, p->pcgRed, p->pcgHist, s));
         }
         HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
-        // recompute u = U^T r exactly once r.r has dropped by 100x (or after 50 steps):
-        // the recursion's absolute rounding error does not shrink with u
-        HIPCHK(p, pcg_refresh_decide(st, s));
+        // u = U^T r recomputed exactly when beta's kernel decided so (no_refresh = 0)
         HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, &st->no_refresh, s, u));
         continue;
       }

@@ -95,7 +95,7 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   ProfScope(wc4d_problem p_, hipStream_t s_, int cls_, double bytes_, double flops_)
       : p(p_), s(s_), cls(cls_), bytes(bytes_), flops(flops_) {
-    if (p->kprof) {
+    if ((p->kprof >> cls) & 1) {
       a = prof_event(p);
       if (a != nullptr) (void)hipEventRecord(a, s);
     }

@@ -221,13 +221,20 @@ hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA,
 
 // Partial sums of columns [c0, c0 + kPG) over panels [pb, pe): thread = one row of the
 // panel (the 256 threads read 1 KB per column), kPG accumulators, one block reduction.
+// With pdot (PCG): the column-group-0 workgroups also sum pdot . x over their panels into
+// dotpart[split].
 __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int k, long long pan_per,
                                                               const float* __restrict__ P,
                                                               const double* __restrict__ x,
                                                               double* __restrict__ part,
-                                                              const int* __restrict__ skip) {
+                                                              const int* __restrict__ skip,
+                                                              const double* __restrict__ pdot,
+                                                              double* __restrict__ dotpart) {
   __shared__ double sh[kPanel / 64][kPG];
+  __shared__ double shd[kPanel / 64];
   if (skip != nullptr && *skip != 0) return;
+  const bool dot = pdot != nullptr && blockIdx.x == 0;
+  double dv = 0.0;
   const int c0 = blockIdx.x * kPG;
   const int split = blockIdx.y;
   const long long np = lmp_panels(nA);
@@ -244,9 +251,15 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
   for (long long pn = pb; pn < pe; ++pn) {
     const long long i = pn * kPanel + threadIdx.x;
     const double xv = i < nA ? x[i] : 0.0;
+    if (dot && i < nA) dv += pdot[i] * xv;
     const float* Pp = P + (size_t)pn * kPanel * k + threadIdx.x;
 #pragma unroll
     for (int c = 0; c < kPG; ++c) acc[c] += (double)Pp[col[c]] * xv;
+  }
+  if (dot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dv += __shfl_down(dv, o, 64);
+    if (lane == 0) shd[wave] = dv;
   }
 #pragma unroll
   for (int c = 0; c < kPG; ++c) {
@@ -263,6 +276,12 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
 #pragma unroll
     for (int w = 0; w < kPanel / 64; ++w) sum += sh[w][threadIdx.x];
     part[(size_t)split * k + c0 + threadIdx.x] = sum;
+  }
+  if (dot && threadIdx.x == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPanel / 64; ++w) sum += shd[w];
+    dotpart[split] = sum;
   }
 }
 
@@ -305,6 +324,16 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const
   }
 }
 
+int lmp_pan_t_splits(long long nA, int k) { return pan_t_splits(nA, k); }
+
+hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
+                              double* part, double* dotpart, hipStream_t s) {
+  const int sp = pan_t_splits(nA, k);
+  hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
+                     pan_t_per(nA, k), P, x, part, nullptr, pdot, dotpart);
+  return hipGetLastError();
+}
+
 // blocks for a pass over all panels: ceil(np / per) with per = ceil(np / 1024)
 int lmp_panel_grid(long long nA) {
   const long long np = lmp_panels(nA);
@@ -321,7 +350,7 @@ hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ld
   if (u32) {
     sp = pan_t_splits(nA, k);
     hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
-                       pan_t_per(nA, k), (const float*)U, x, part, skip);
+                       pan_t_per(nA, k), (const float*)U, x, part, skip, nullptr, nullptr);
   } else {
     sp = lmp_t_splits(nA, k);
     const long long rows_per = (nA + sp - 1) / sp;

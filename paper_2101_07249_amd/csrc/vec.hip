@@ -116,6 +116,7 @@ __global__ __launch_bounds__(kRT) void k_alpha_final(PcgState* st, const double*
     if (!(pap > 0.0) || !isfinite(pap)) {
       st->status = WC4D_EBREAKDOWN;
       st->done = 1;
+      st->no_refresh = 1;
     } else {
       st->alpha = st->rr / pap;
     }
@@ -213,6 +214,15 @@ __global__ __launch_bounds__(kRT) void k_beta_final(PcgState* st, const double* 
     } else if (it >= st->maxit) {
       st->status = WC4D_ENOCONV;
       st->done = 1;
+    }
+    // fused variant: recompute u = U^T r exactly once r.r has dropped by 100x since the
+    // last refresh (or after 50 steps), since the recursion's absolute rounding error does
+    // not shrink with u
+    const bool go = !st->done && (rr < 1e-2 * st->rr_ref || it - st->last_refresh >= 50);
+    st->no_refresh = go ? 0 : 1;
+    if (go) {
+      st->rr_ref = rr;
+      st->last_refresh = it;
     }
   }
 }
@@ -490,6 +500,85 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict
 // waves' sums of U d1 and U d2 meet in LDS; thread q then updates row q of the panel.
 // Blocks own panels blockIdx.x, + gridDim.x, ...; block 0 clears the r.r partial slots
 // of blocks that do not exist (gridDim.x .. kRB).
+// ------------------------------- fused LMP inside PCG, float32 panel copy of U
+// One kernel after the U^T Ap pass: p.Ap from that pass's partials (every block sums them
+// in the same order, block 0 records pAp and alpha), t = U^T Ap from its partials (sp x k,
+// summed in split order), d1 = dcoef .* t, and for 8 rows c per block (32 threads each)
+// u_c <- u_c - alpha (t_c + (GU d1)_c) with GU's row c (GU = U^T U is symmetric),
+// d12 = [d1, dcoef .* u].
+constexpr int kCR = 8;  // rows of u per block
+__global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ st, int k, int sp,
+                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ dotpart,
+                                                        const double* __restrict__ dcoef,
+                                                        const double* __restrict__ GU,
+                                                        double* __restrict__ u,
+                                                        double* __restrict__ d12) {
+  extern __shared__ double sm[];
+  double* sd1 = sm;       // d1 (k)
+  double* stv = sm + k;   // t (k)
+  __shared__ double sh[16];
+  __shared__ double s_alpha;
+  __shared__ int s_done;
+  // block 0 may set done during this kernel: each block reads it once
+  if (threadIdx.x == 0) s_done = st->done;
+  __syncthreads();
+  if (s_done) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < sp; b += kRT) v += dotpart[b];
+  const double pap = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    const bool ok = pap > 0.0 && isfinite(pap);
+    s_alpha = ok ? st->rr / pap : 0.0;
+    if (blockIdx.x == 0) {
+      st->pAp = pap;
+      if (ok) {
+        st->alpha = s_alpha;
+      } else {
+        st->status = WC4D_EBREAKDOWN;
+        st->done = 1;
+        st->no_refresh = 1;
+      }
+    }
+    if (!ok) s_alpha = -1.0;  // flag: nothing more to do
+  }
+  __syncthreads();
+  const double alpha = s_alpha;
+  if (alpha < 0.0) return;
+  for (int c = threadIdx.x; c < k; c += kRT) {
+    double t = 0.0;
+    for (int b = 0; b < sp; ++b) t += part[(size_t)b * k + c];
+    stv[c] = t;
+    sd1[c] = dcoef[c] * t;
+  }
+  __syncthreads();
+  const int c = blockIdx.x * kCR + (threadIdx.x >> 5), sub = threadIdx.x & 31;
+  double g = 0.0;
+  if (c < k) {
+    const double* row = GU + (size_t)c * k;
+    for (int j = sub; j < k; j += 32) g += row[j] * sd1[j];
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
+  if (c < k && sub == 0) {
+    const double un = u[c] - alpha * (stv[c] + g);
+    u[c] = un;
+    d12[c] = sd1[c];
+    d12[k + c] = dcoef[c] * un;
+  }
+}
+
+hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* part, const double* red,
+                              const double* dcoef, const double* GU, double* u, double* d12,
+                              hipStream_t s) {
+  if (sp > kRB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pcg_coeffs_pan, dim3((k + kCR - 1) / kCR), dim3(kRT), sizeof(double) * 2 * k, s, st,
+                     k, sp, part, red + 3 * kRB, dcoef, GU, u, d12);
+  return hipGetLastError();
+}
+
+double* pcg_dot_slots(double* red) { return red + 3 * kRB; }
+
 __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __restrict__ st,
                                                           long long nA, int k,
                                                           const float* __restrict__ P,
@@ -497,7 +586,11 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __rest
                                                           const double* __restrict__ Ap,
                                                           double* __restrict__ r,
                                                           double* __restrict__ z,
-                                                          double* __restrict__ red) {
+                                                          double* __restrict__ red,
+                                                          double* __restrict__ x,
+                                                          double* __restrict__ sr,
+                                                          const double* __restrict__ b,
+                                                          const double* __restrict__ p) {
   extern __shared__ double sm[];
   double* sd = sm;             // d1 (k), d2 (k)
   double* rw = sm + 2 * k;     // [4 waves][2][kPanel rows]
@@ -506,11 +599,15 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __rest
   const double alpha = st->alpha;
   for (int c = threadIdx.x; c < 2 * k; c += kRT) sd[c] = d12[c];
   if (blockIdx.x == 0)
-    for (int b = (int)gridDim.x + threadIdx.x; b < kRB; b += kRT) red[2 * kRB + b] = 0.0;
+    for (int q = (int)gridDim.x + threadIdx.x; q < kRB; q += kRT) {
+      red[q] = 0.0;
+      red[kRB + q] = 0.0;
+      red[2 * kRB + q] = 0.0;
+    }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long np = lmp_panels(nA);
-  double vsum = 0.0;
+  double vsum = 0.0, vs = 0.0, vj = 0.0;
   for (long long pn = blockIdx.x; pn < np; pn += gridDim.x) {
     const float* Pp = P + (size_t)pn * kPanel * k + 4 * lane;
     double aw[4] = {0.0, 0.0, 0.0, 0.0}, az[4] = {0.0, 0.0, 0.0, 0.0};
@@ -537,47 +634,50 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __rest
     if (i < nA) {
       const double w = (rw[q] + rw[2 * kPanel + q]) + (rw[4 * kPanel + q] + rw[6 * kPanel + q]);
       const double zz = (rw[kPanel + q] + rw[3 * kPanel + q]) + (rw[5 * kPanel + q] + rw[7 * kPanel + q]);
-      const double rn = r[i] - alpha * (Ap[i] + w);
+      const double api = Ap[i];
+      const double rn = r[i] - alpha * (api + w);
       r[i] = rn;
       z[i] = rn + zz;
       vsum += rn * rn;
+      // x += alpha p, s -= alpha Ap (true residual) with the partials of s.s and x.(b + s)
+      const double xi = x[i] + alpha * p[i];
+      const double si = sr[i] - alpha * api;
+      x[i] = xi;
+      sr[i] = si;
+      vs += si * si;
+      vj += xi * (b[i] + si);
     }
     __syncthreads();
   }
-  const double tot = block_sum(vsum, sh);
-  if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = tot;
-}
-
-__global__ void k_refresh_decide(PcgState* st) {
-  if (threadIdx.x != 0) return;
-  const bool go = !st->done && (st->rr < 1e-2 * st->rr_ref || st->iter - st->last_refresh >= 50);
-  st->no_refresh = go ? 0 : 1;
-  if (go) {
-    st->rr_ref = st->rr;
-    st->last_refresh = st->iter;
+  const double t0 = block_sum(vs, sh);
+  const double t1 = block_sum(vj, sh);
+  const double t2 = block_sum(vsum, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = t0;
+    red[kRB + blockIdx.x] = t1;
+    red[2 * kRB + blockIdx.x] = t2;
   }
 }
 
-hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_refresh_decide, dim3(1), dim3(64), 0, s, st);
+
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
+                        const double* d12, const double* Ap, double* r, double* z, double* red,
+                        double* hist, hipStream_t s) {
+  if (ldu % 4 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pcg_lmp_dual<double>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st, nA, k,
+                     U, ldu, d12, Ap, r, z, red);
+  hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }
 
-hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
-                        const double* d12, const double* Ap, double* r, double* z, double* red,
-                        double* hist, hipStream_t s) {
-  if (u32) {
-    static_assert(kPanel == kRT, "one thread per panel row in the row update");
-    const int grid = lmp_panel_grid(nA);
-    if (grid > kRB) return hipErrorInvalidValue;   // one r.r partial slot per block
-    hipLaunchKernelGGL(k_pcg_lmp_dual_pan, dim3(grid), dim3(kRT),
-                       sizeof(double) * (2 * k + 8 * kPanel), s, st, nA, k, (const float*)U, d12, Ap, r,
-                       z, red);
-  } else {
-    if (ldu % 4 != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pcg_lmp_dual<double>, dim3(kRB), dim3(kRT), sizeof(double) * 2 * k, s, st,
-                       nA, k, (const double*)U, ldu, d12, Ap, r, z, red);
-  }
+hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const float* P, const double* d12,
+                            const double* Ap, double* r, double* z, double* x, double* sres,
+                            const double* b, const double* p, double* red, double* hist, hipStream_t s) {
+  static_assert(kPanel == kRT, "one thread per panel row in the row update");
+  const int grid = lmp_panel_grid(nA);
+  if (grid > kRB) return hipErrorInvalidValue;  // one partial slot per block
+  hipLaunchKernelGGL(k_pcg_lmp_dual_pan, dim3(grid), dim3(kRT), sizeof(double) * (2 * k + 8 * kPanel), s, st,
+                     nA, k, P, d12, Ap, r, z, red, x, sres, b, p);
   hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }

@@ -208,12 +208,22 @@ hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
 // lmp_gemv_t (float32: the panel copy).
 hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const double* dcoef,
                           const double* GU, double* u, double* d12, hipStream_t s);
-hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const void* U, bool u32, long long ldu,
+hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s);
-// Decide whether u = U^T r is recomputed this iteration (st->no_refresh = 0 when
-// r.r fell below 1e-2 of its value at the last refresh, or 50 iterations passed).
-hipError_t pcg_refresh_decide(PcgState* st, hipStream_t s);
+// Float32 panel copy: one U^T Ap pass that also sums p.Ap (lmp_pan_t_partials with pdot = p,
+// dotpart = pcg_dot_slots(red)), then pcg_lmp_coeffs_pan (p.Ap -> alpha, t, u, d12), then
+// the dual pass that also updates x and s (the true residual) and ends with beta.
+int lmp_pan_t_splits(long long nA, int k);
+hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
+                              double* part, double* dotpart, hipStream_t s);
+double* pcg_dot_slots(double* red);
+hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* part, const double* red,
+                              const double* dcoef, const double* GU, double* u, double* d12,
+                              hipStream_t s);
+hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const float* P, const double* d12,
+                            const double* Ap, double* r, double* z, double* x, double* sres,
+                            const double* b, const double* p, double* red, double* hist, hipStream_t s);
 hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef, const int* skip,
                           hipStream_t s);
 hipError_t stash_from_innov(const double* d, const double* rinv, double* stash, int q,
@@ -340,7 +350,7 @@ struct wc4d_problem_s {
   wc4d::PcgState* pcgState = nullptr;
   wc4d::PcgState* pcgStateHost = nullptr;  // pinned
   // per-class kernel timing
-  bool kprof = false;
+  int kprof = 0;           // classes timed by ProfScope (bit c: class c)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;

@@ -422,8 +422,17 @@ class Problem:
     PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other",
                     "dsqrt_bf16x3", "sketch_net")
 
-    def prof_enable(self, enable: bool = True):
-        self._chk(lib().wc4d_prof_enable(self._h, int(bool(enable))), "prof_enable")
+    def prof_enable(self, enable: bool = True, classes=None):
+        """Reset the per-class totals and time the given classes (names or indices of
+        PROF_CLASSES; all when None) while enable is true."""
+        mask = 0
+        if enable:
+            if classes is None:
+                mask = (1 << len(self.PROF_CLASSES)) - 1
+            else:
+                for c in classes:
+                    mask |= 1 << (self.PROF_CLASSES.index(c) if isinstance(c, str) else int(c))
+        self._chk(lib().wc4d_prof_enable(self._h, mask), "prof_enable")
 
     def prof_read(self) -> dict:
         out = {}
