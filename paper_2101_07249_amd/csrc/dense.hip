@@ -71,9 +71,127 @@ __global__ __launch_bounds__(1024) void k_chol_upper(int m, double* __restrict__
   }
 }
 
+// The same factorisation blocked by 32 columns (still one workgroup): block row J of R
+// (32 rows, columns c0 .. m) is factored in LDS (pivot, row scaling, and the update of the
+// block's later rows, one step per column), written back, and then the trailing upper
+// triangle takes the block's rank-32 update in 4 x 4 register tiles with the k terms in
+// ascending order.  Every element therefore sees the same sequence of floating-point
+// updates as in the kernel above; only the number of barriers per column changes.
+constexpr int kCBK = 32;   // block width
+__global__ __launch_bounds__(1024) void k_chol_upper_blk(int m, double* __restrict__ G, int ldg,
+                                                         int* __restrict__ status) {
+  extern __shared__ double sR[];   // kCBK x m: row r of the block row at sR[r m + j]
+  __shared__ double s_diag0[512];
+  __shared__ double s_piv;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) s_bad = 0;
+  for (int k = tid; k < m; k += nt) s_diag0[k] = G[k + (size_t)k * ldg];
+  __syncthreads();
+  const double floor_rel = (double)m * 2.220446049250313e-16;
+  for (int c0 = 0; c0 < m; c0 += kCBK) {
+    const int bw = min(kCBK, m - c0), w = m - c0;
+    // block row J of the current matrix (upper part)
+    for (int e = tid; e < bw * w; e += nt) {
+      const int r = e / w, j = c0 + e % w;
+      sR[r * m + j] = (j >= c0 + r) ? G[(c0 + r) + (size_t)j * ldg] : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < bw; ++kk) {
+      const int k = c0 + kk;
+      double* rk = sR + kk * m;
+      if (tid == 0) {
+        const double d = rk[k];
+        if (!(d > floor_rel * s_diag0[k]) || !isfinite(d)) {
+          s_bad = 1;
+          s_piv = 1.0;
+        } else {
+          s_piv = sqrt(d);
+        }
+      }
+      __syncthreads();
+      if (s_bad) break;
+      const double piv = s_piv;
+      for (int j = k + tid; j < m; j += nt) rk[j] = (j == k) ? piv : rk[j] / piv;
+      __syncthreads();
+      // the block's later rows: G(i, j) -= R(k, i) R(k, j), k < i < c0 + bw, j >= i
+      const int rows = bw - kk - 1;
+      for (int e = tid; e < rows * w; e += nt) {
+        const int r = kk + 1 + e / w, j = c0 + e % w;
+        if (j >= c0 + r) sR[r * m + j] -= rk[c0 + r] * rk[j];
+      }
+      __syncthreads();
+    }
+    if (s_bad) break;
+    // R's block row back to G
+    for (int e = tid; e < bw * w; e += nt) {
+      const int r = e / w, j = c0 + e % w;
+      if (j >= c0 + r) G[(c0 + r) + (size_t)j * ldg] = sR[r * m + j];
+    }
+    // trailing update of rows and columns >= c1 (upper triangle), 4 x 4 tiles
+    const int c1 = c0 + bw, wt = m - c1;
+    if (wt > 0) {
+      const int ntl = (wt + 3) / 4;
+      for (int t = tid; t < ntl * ntl; t += nt) {
+        const int ti = t / ntl, tj = t % ntl;
+        if (ti > tj) continue;
+        const int i0 = c1 + 4 * ti, j0 = c1 + 4 * tj;
+        double acc[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            acc[r][c] = (i < m && j < m && i <= j) ? G[i + (size_t)j * ldg] : 0.0;
+          }
+        for (int kk = 0; kk < bw; ++kk) {
+          const double* rk = sR + kk * m;
+          double ri[4], rj[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) ri[r] = (i0 + r < m) ? rk[i0 + r] : 0.0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rj[c] = (j0 + c < m) ? rk[j0 + c] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] -= ri[r] * rj[c];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int i = i0 + r, j = j0 + c;
+            if (i < m && j < m && i <= j) G[i + (size_t)j * ldg] = acc[r][c];
+          }
+      }
+    }
+    __syncthreads();
+  }
+  if (s_bad) {
+    if (tid == 0) *status = 1;
+    return;
+  }
+  const long long tot = (long long)m * m;
+  for (long long e = tid; e < tot; e += nt) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    if (i > j) G[i + (size_t)j * ldg] = 0.0;
+  }
+}
+
 hipError_t chol_upper(int m, double* G, int ldg, int* status, hipStream_t s) {
   if (m > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, s, m, G, ldg, status);
+  const size_t lds = sizeof(double) * kCBK * (size_t)m;  // <= 128 KB
+  static std::once_flag once;
+  static hipError_t attr = hipSuccess;
+  std::call_once(once, [] {
+    attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_upper_blk),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double) * kCBK * 512));
+  });
+  if (attr == hipSuccess) {
+    hipLaunchKernelGGL(k_chol_upper_blk, dim3(1), dim3(1024), lds, s, m, G, ldg, status);
+  } else {
+    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(1024), 0, s, m, G, ldg, status);
+  }
   return hipGetLastError();
 }
 
