@@ -40,11 +40,11 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 # reading; profiles/dsqrt_vec_n4096_N100_counters.md).  Valid only for the kernels that were
 # measured: the tuned form below, built from this gemm_f64.hip and vec.hip.
 MEASURED_TRAFFIC = {"n": 4096, "N": 100,
-                    "tune": {"single_product": True, "two_segment": False, "tile_b": 2},
-                    # k_gemm_f64 and k_gemm_splitk_reduce (the whole launch group) live here
+                    "tune": {"single_product": True, "two_segment": False, "tile_b": 7},
+                    # k_gemm_f64_pa and k_gemm_splitk_reduce (the whole launch group) live here
                     "sources": {"paper_2101_07249_amd/csrc/gemm_f64.hip":
-                                "68bc6d377244e3394e5b7b5250e9c7f7793ead05b11e920b4fa408f80c4827ac"},
-                    "bytes_per_launch": 216.7e6}
+                                "7d77e6e0c0c0a03f8aa5b42f710c13d72289138b95b47149a76721ecbe82e54d"},
+                    "bytes_per_launch": 216.6e6}
 
 
 def dominant_class(prof):
@@ -77,8 +77,10 @@ def dsqrt_kernel_name(tune):
         r, kk = rows_k.get(tune.get("segment_variant"), (0, 0))
         core = f"k_dsqrt2<{r}, {kk}> ({tune.get('segment_splits') or 'auto'} splits) + k_dsqrt2_reduce"
     else:
-        core = f"k_gemm_f64 tile code {tune.get('tile_b')}" + ("" if tune.get("single_product") else
-                                                              f" / {tune.get('tile_q')}")
+        names = {2: "k_gemm_f64<64, 112, 32, 4, 1, true> + k_gemm_splitk_reduce",
+                 7: "k_gemm_f64_pa<112, 32> + k_gemm_splitk_reduce"}
+        core = (names.get(tune.get("tile_b"), f"k_gemm_f64 tile code {tune.get('tile_b')}")
+                + ("" if tune.get("single_product") else f" / tile code {tune.get('tile_q')}"))
     if tune.get("single_product"):
         return f"Q^(1/2) over all N+1 levels, level 0 scaled in the epilogue: {core}"
     return f"B^(1/2), Q^(1/2): {core}"
@@ -105,7 +107,21 @@ def parse():
                     help="autotune cache file: loaded when present, written after tuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM counters)")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="only measure the float64 MFMA rate of a register-only stream (roofline reference)")
     return ap.parse_args()
+
+
+def mfma_probe():
+    """Float64 matrix rate the part sustains: a register-only v_mfma_f64_16x16x4 stream with
+    1, 2 and 4 waves per SIMD, in short (about 1 ms) and long (about 10-40 ms) launches."""
+    from paper_2101_07249_amd import wc4d as W4
+    rows = []
+    for waves in (1, 2, 4):
+        for iters in (2000, 20000):
+            rows.append({"waves_per_simd": waves, "mfma_per_wave": iters * 8,
+                         "tflops": round(W4.probe_mfma_f64(waves, iters, 5), 2)})
+    print(json.dumps({"mfma_f64_probe": rows, "published_peak_tflops": FP64_PEAK_TFLOPS}), flush=True)
 
 
 def copy_probe():
@@ -261,6 +277,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.mfma_probe:
+        mfma_probe()
+        return
     if args.copy_probe:
         copy_probe()
         return

@@ -242,11 +242,12 @@ int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, dou
  * Choices are cached per (device, n, N, m) for the life of the process, so later
  * problems of the same shape reuse them without timing.  Uses p's build scratch;
  * synchronises s.  wc4d_autotune_info reports the choice (tile codes: 1 split-K 64x16,
- * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32; two_segment = 0 when the
+ * 2 split-K 64x112, 3 128x16, 4 128x128, 5 64x64, 6 32x32, 7 split-K 64x112 with A read
+ * straight into registers and a double-buffered B tile; two_segment = 0 when the
  * products run separately, else 1 + variant + 8 * splits of the two-segment launch with
  * variant 0 = 64 rows / K step 32, 1 = 128 / 16, 2 = 128 / 32 and splits 0 = automatic)
  * and its measured ms.  When finalize found B^{1/2} = c Q^{1/2} (same correlation, other
- * variance) D^{1/2} is one product with Q^{1/2} over all N + 1 levels plus a rescaling of
+ * variance) D^{1/2} is one product with Q^{1/2} over all N + 1 levels whose epilogue scales
  * level 0; then tile_b is that product's tile and tile_q is 0. */
 int wc4d_autotune(wc4d_problem p, int m, hipStream_t s);
 int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two_segment, float* ms);
@@ -256,6 +257,14 @@ int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two
  * WC4D_EINVAL on an unreadable file or a malformed line (nothing is merged then). */
 int wc4d_autotune_save(const char* path);
 int wc4d_autotune_load(const char* path);
+
+/* Hardware reference for the float64 roofline (not part of the method): runs a
+ * register-only stream of v_mfma_f64_16x16x4_f64 on `device` (waves_per_simd 1..8 waves on
+ * every SIMD, each issuing iters x 8 MFMAs; one warm-up launch, then reps timed launches on
+ * the null stream) and reports the achieved float64 matrix rate in *tflops.  Allocates and
+ * frees its own output buffer; synchronises the device.  WC4D_EINVAL on bad arguments,
+ * WC4D_EHIP on a HIP failure. */
+int wc4d_probe_mfma_f64(int device, int waves_per_simd, int iters, int reps, double* tflops);
 
 /* Solve `count` independent inner loops (Section 2.2 / Algorithm 1) at once: for each
  * problem ps[i] (finalized, all on one device, none repeated) an LMP of k_r Ritz pairs

@@ -987,15 +987,15 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
       if (fused && u32) {
-        // 7 launches after the operator: U^T Ap (+ p.Ap), coefficients (+ alpha), the dual
-        // pass (+ x, s), beta (+ the refresh decision), p, and the refresh of u = U^T r
+        // after the operator: U^T Ap (+ p.Ap) and its partials' sum, coefficients (+ alpha),
+        // the dual pass (+ x, s), beta (+ the refresh decision), p, the refresh of u = U^T r
         const double ub = 4.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
         if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
         {
           ProfScope ps(p, s, PROF_LMP_T, ub + 16.0 * nA, fl + 2.0 * nA);
-          HIPCHK(p, lmp_pan_t_partials(nA, L->k, L->U32, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), s));
+          HIPCHK(p, lmp_pan_t_partials(nA, L->k, L->U32, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
         }
-        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), L->wsv, p->pcgRed, L->dcoef, L->GU, u,
+        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), tvec, p->pcgRed, L->dcoef, L->GU, u,
                                      d12, s));
         {
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 9.0 * nA, 2.0 * fl);

@@ -163,6 +163,122 @@ __global__ void k_gemm_splitk_reduce(int M, int ncol, int splits, double alpha,
   }
 }
 
+// Split-K variant for few columns (ncol <= BN) in which each wave owns 16 rows of A:
+// a wave's A fragments (MFMA operand layout) come straight from global memory one K step
+// ahead, only the B tile (shared by the 4 waves) is staged in LDS, double-buffered, so a
+// K step needs one barrier and the next step's loads are in flight during the MFMAs.
+template <int BN, int BK>
+__global__ __launch_bounds__(256) void k_gemm_f64_pa(int M, int ncol, int K, const double* __restrict__ A,
+                                                     long long lda, const double* __restrict__ B, ColMap bmap,
+                                                     int kchunk, double* __restrict__ ws,
+                                                     const int* __restrict__ skip) {
+  constexpr int BM = 64, TJ = BN / 16, KS = BK / 4;
+  constexpr int NB = BN * BK / 256;
+  static_assert(BN % 16 == 0 && (BN * BK) % 256 == 0 && BK % 4 == 0, "tile shape");
+  constexpr int PB = BN + 4;
+  __shared__ double Bs[2][BK][PB];
+  if (skip != nullptr && *skip != 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * BM;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  // this lane's A row and the K offset of its MFMA operand within a 4-step
+  const int ai = i0 + wave * 16 + (lane & 15);
+  const bool arow = ai < M;
+  const double* Ar = A + (arow ? ai : 0);
+  const int ak = lane >> 4;
+  d4 acc[TJ];
+#pragma unroll
+  for (int a = 0; a < TJ; ++a) acc[a] = d4{0.0, 0.0, 0.0, 0.0};
+  long long boff[NB];
+  bool bval[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int j = (tid + 256 * e) / BK;
+    bval[e] = j < ncol;
+    boff[e] = bval[e] ? bmap.off(j) : 0;
+  }
+  double ra[KS], rb[NB];
+  auto load_a = [&](int k0, double (&v)[KS]) {
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int gk = k0 + 4 * q + ak;
+      v[q] = (arow && gk < kend) ? Ar[(long long)gk * lda] : 0.0;
+    }
+  };
+  auto load_b = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int gk = k0 + (tid + 256 * e) % BK;
+      rb[e] = (bval[e] && gk < kend) ? B[boff[e] + gk] : 0.0;
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + 256 * e;
+      Bs[buf][idx % BK][idx / BK] = rb[e];
+    }
+  };
+  load_b(kbeg);
+  load_a(kbeg, ra);
+  store_b(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    double na[KS];
+    if (more) {
+      load_b(k0 + BK);
+      load_a(k0 + BK, na);
+    }
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int kr = 4 * q + ak;
+      double av[TJ];
+#pragma unroll
+      for (int a = 0; a < TJ; ++a) av[a] = Bs[buf][kr][a * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TJ; ++a) acc[a] = mfma16x16x4(av[a], ra[q], acc[a]);
+    }
+    if (more) {
+      store_b(buf ^ 1);
+#pragma unroll
+      for (int q = 0; q < KS; ++q) ra[q] = na[q];
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* wz = ws + (size_t)blockIdx.z * M * ncol;
+#pragma unroll
+  for (int a = 0; a < TJ; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = a * 16 + (lane >> 4) + 4 * r;
+      if (j < ncol && arow) wz[(size_t)j * M + ai] = acc[a][r];
+    }
+  }
+}
+
+template <int BN, int BK>
+static hipError_t launch_gemm_split_pa(int M, int ncol, int K, int splits, double alpha, const double* A,
+                                       long long lda, const double* B, ColMap bmap, double* C, ColMap cmap,
+                                       const double* E, ColMap emap, const int* skip, double* ws,
+                                       hipStream_t s) {
+  int kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  splits = (K + kchunk - 1) / kchunk;
+  dim3 grid((M + 63) / 64, 1, splits);
+  hipLaunchKernelGGL((k_gemm_f64_pa<BN, BK>), grid, dim3(256), 0, s, M, ncol, K, A, lda, B, bmap, kchunk, ws,
+                     skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 rg((M + 255) / 256 < 64 ? (M + 255) / 256 : 64, ncol);
+  hipLaunchKernelGGL(k_gemm_splitk_reduce, rg, dim3(256), 0, s, M, ncol, splits, alpha, ws, C, cmap, E, emap,
+                     skip);
+  return hipGetLastError();
+}
+
 template <int BM, int BN, int BK, int WGI, int WGJ>
 static hipError_t launch_gemm(int M, int ncol, int K, double alpha, const double* A, long long lda,
                               const double* B, ColMap bmap, double* C, ColMap cmap,
@@ -205,7 +321,8 @@ bool gemm_tile_feasible(int tile, int M, int ncol, int K, const double* ws, size
   switch (tile) {
     case GEMM_AUTO: return true;
     case GEMM_SPLIT_64x16: return ws != nullptr && ncol <= 16 && split_count(M, ncol, K, 16, ws_doubles, 0) > 0;
-    case GEMM_SPLIT_64x112: return ws != nullptr && ncol <= 112 && split_count(M, ncol, K, 112, ws_doubles, 0) > 0;
+    case GEMM_SPLIT_64x112:
+    case GEMM_SPLIT_64x112_PA: return ws != nullptr && ncol <= 112 && split_count(M, ncol, K, 112, ws_doubles, 0) > 0;
     case GEMM_128x16: case GEMM_128x128: case GEMM_64x64: case GEMM_32x32: return true;
     default: return false;
   }
@@ -243,6 +360,11 @@ hipError_t gemm_f64_tile(int tile, int splits, int M, int ncol, int K, double al
       const long long sp = split_count(M, ncol, K, 112, ws_doubles, splits);
       return launch_gemm_split<64, 112, 32, 4, 1>(M, ncol, K, (int)sp, alpha, A, lda, B, bmap, C, cmap, E,
                                                   emap, skip, ws, s);
+    }
+    case GEMM_SPLIT_64x112_PA: {
+      const long long sp = split_count(M, ncol, K, 112, ws_doubles, splits);
+      return launch_gemm_split_pa<112, 32>(M, ncol, K, (int)sp, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, ws,
+                                           s);
     }
     case GEMM_128x16:
       return launch_gemm<128, 16, 16, 4, 1>(M, ncol, K, alpha, A, lda, B, bmap, C, cmap, E, emap, skip, s);

@@ -327,10 +327,12 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const
 int lmp_pan_t_splits(long long nA, int k) { return pan_t_splits(nA, k); }
 
 hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
-                              double* part, double* dotpart, hipStream_t s) {
+                              double* ws, double* dotpart, const int* skip, hipStream_t s) {
   const int sp = pan_t_splits(nA, k);
   hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
-                     pan_t_per(nA, k), P, x, part, nullptr, pdot, dotpart);
+                     pan_t_per(nA, k), P, x, ws, skip, pdot, dotpart);
+  hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, ws, nullptr,
+                     ws + lmp_gemv_t_offset(nA, k), skip);
   return hipGetLastError();
 }
 

@@ -501,14 +501,14 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict
 // Blocks own panels blockIdx.x, + gridDim.x, ...; block 0 clears the r.r partial slots
 // of blocks that do not exist (gridDim.x .. kRB).
 // ------------------------------- fused LMP inside PCG, float32 panel copy of U
-// One kernel after the U^T Ap pass: p.Ap from that pass's partials (every block sums them
-// in the same order, block 0 records pAp and alpha), t = U^T Ap from its partials (sp x k,
-// summed in split order), d1 = dcoef .* t, and for 8 rows c per block (32 threads each)
+// After the U^T Ap pass and the fixed-order sum of its partials into t: p.Ap from that
+// pass's partials (every block sums them in the same order, block 0 records pAp and
+// alpha), d1 = dcoef .* t, and for 8 rows c per block (32 threads each)
 // u_c <- u_c - alpha (t_c + (GU d1)_c) with GU's row c (GU = U^T U is symmetric),
 // d12 = [d1, dcoef .* u].
 constexpr int kCR = 8;  // rows of u per block
 __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ st, int k, int sp,
-                                                        const double* __restrict__ part,
+                                                        const double* __restrict__ tv,
                                                         const double* __restrict__ dotpart,
                                                         const double* __restrict__ dcoef,
                                                         const double* __restrict__ GU,
@@ -546,8 +546,7 @@ __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ s
   const double alpha = s_alpha;
   if (alpha < 0.0) return;
   for (int c = threadIdx.x; c < k; c += kRT) {
-    double t = 0.0;
-    for (int b = 0; b < sp; ++b) t += part[(size_t)b * k + c];
+    const double t = tv[c];
     stv[c] = t;
     sd1[c] = dcoef[c] * t;
   }
@@ -568,12 +567,12 @@ __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ s
   }
 }
 
-hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* part, const double* red,
+hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* t, const double* red,
                               const double* dcoef, const double* GU, double* u, double* d12,
                               hipStream_t s) {
   if (sp > kRB) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_pcg_coeffs_pan, dim3((k + kCR - 1) / kCR), dim3(kRT), sizeof(double) * 2 * k, s, st,
-                     k, sp, part, red + 3 * kRB, dcoef, GU, u, d12);
+                     k, sp, t, red + 3 * kRB, dcoef, GU, u, d12);
   return hipGetLastError();
 }
 

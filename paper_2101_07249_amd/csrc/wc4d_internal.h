@@ -47,9 +47,10 @@ hipError_t gemm_f64(int M, int ncol, int K, double alpha, const double* A, long 
                     size_t ws_doubles = 0);
 
 // Explicit tile shapes of gemm_f64 (the autotuner's candidates): split-K with 64 x 16 or
-// 64 x 112 tiles (needs ws), or plain 128 x 16, 128 x 128, 64 x 64, 32 x 32 tiles.
+// 64 x 112 tiles (needs ws), plain 128 x 16, 128 x 128, 64 x 64, 32 x 32 tiles, or split-K
+// 64 x 112 with each wave's A rows loaded straight into registers and a double-buffered B.
 enum GemmTile { GEMM_AUTO = 0, GEMM_SPLIT_64x16, GEMM_SPLIT_64x112, GEMM_128x16, GEMM_128x128, GEMM_64x64,
-                GEMM_32x32, GEMM_NTILES };
+                GEMM_32x32, GEMM_SPLIT_64x112_PA, GEMM_NTILES };
 bool gemm_tile_feasible(int tile, int M, int ncol, int K, const double* ws, size_t ws_doubles);
 hipError_t gemm_f64_tile(int tile, int splits, int M, int ncol, int K, double alpha, const double* A,
                          long long lda, const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
@@ -212,13 +213,14 @@ hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s);
 // Float32 panel copy: one U^T Ap pass that also sums p.Ap (lmp_pan_t_partials with pdot = p,
-// dotpart = pcg_dot_slots(red)), then pcg_lmp_coeffs_pan (p.Ap -> alpha, t, u, d12), then
-// the dual pass that also updates x and s (the true residual) and ends with beta.
+// dotpart = pcg_dot_slots(red); t = U^T Ap left at ws + lmp_gemv_t_offset), then
+// pcg_lmp_coeffs_pan (p.Ap -> alpha, u, d12), then the dual pass that also updates x and s
+// (the true residual) and ends with beta.
 int lmp_pan_t_splits(long long nA, int k);
 hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
-                              double* part, double* dotpart, hipStream_t s);
+                              double* ws, double* dotpart, const int* skip, hipStream_t s);
 double* pcg_dot_slots(double* red);
-hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* part, const double* red,
+hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* t, const double* red,
                               const double* dcoef, const double* GU, double* u, double* d12,
                               hipStream_t s);
 hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const float* P, const double* d12,

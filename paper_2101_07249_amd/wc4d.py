@@ -78,6 +78,7 @@ _SIGS = {
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
     "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "wc4d_probe_mfma_f64": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_dbl_p]),
     "wc4d_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
                                       _c_dbl_p, _c_dbl_p]),
@@ -462,6 +463,16 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def probe_mfma_f64(waves_per_simd: int = 2, iters: int = 2000, reps: int = 5, device: int = 0) -> float:
+    """Float64 matrix rate (TFLOP/s) of a register-only MFMA stream on the device: the
+    hardware reference for the float64 roofline."""
+    out = ctypes.c_double()
+    rc = lib().wc4d_probe_mfma_f64(int(device), int(waves_per_simd), int(iters), int(reps), ctypes.byref(out))
+    if rc:
+        raise Wc4dError(rc, "probe_mfma_f64")
+    return out.value
 
 
 def autotune_save(path: str):
