@@ -93,7 +93,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
     ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit"])
-    ap.add_argument("--variants", default="plain,mixed")
+    ap.add_argument("--variants", default="plain,mixed,mixed_fp16",
+                    help="comma list of plain (FP64), mixed (split-bf16 block products, FP32 U), mixed_fp16 (split-float16)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -301,7 +302,8 @@ def main():
     dnp = innovations(sum(len(i) for _, i in pat), w.seed, np.sqrt(w.sigma_o2))
     d = torch.from_numpy(dnp).to(dev)
     x = torch.zeros(w.n_A, dtype=torch.float64, device=dev)
-    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32}
+    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32,
+             "mixed_fp16": W4.PREC_SKETCH_FP16X3 | W4.PREC_LMP_FP32}
     names = [v for v in args.variants.split(",") if v]
     results = {}
     tunes = {}

@@ -57,9 +57,13 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *     wc4d_lmp_build run as three bfloat16 MFMA products with float32 accumulation
  *     (S_hi X_hi + S_hi X_lo + S_lo X_hi, S = S_hi + S_lo); CholeskyQR2, the m x m
  *     eigenproblem and everything in wc4d_pcg stay float64.
+ *   WC4D_PREC_SKETCH_FP16X3: the same three products in float16 (11 significant bits
+ *     per part instead of 8), with power-of-two scaling per row of S and per column of X
+ *     (largest magnitude brought to [2^14, 2^15)) so that the parts fit float16's range;
+ *     excludes WC4D_PREC_SKETCH_BF16X3.
  *   WC4D_PREC_LMP_FP32: the LMP keeps a float32 copy of U that wc4d_pcg streams
  *     (products accumulate in float64; C stays exactly symmetric). */
-enum { WC4D_PREC_FP64 = 0, WC4D_PREC_SKETCH_BF16X3 = 1, WC4D_PREC_LMP_FP32 = 2 };
+enum { WC4D_PREC_FP64 = 0, WC4D_PREC_SKETCH_BF16X3 = 1, WC4D_PREC_LMP_FP32 = 2, WC4D_PREC_SKETCH_FP16X3 = 4 };
 
 /* Library version (major*10000 + minor*100 + patch) and status-code names. */
 int wc4d_version(void);
@@ -124,8 +128,9 @@ int wc4d_dims(wc4d_problem p, int* n_A, int* q);
  * not overlap.  Uses workspace owned by p (grown on demand, synchronously). */
 int wc4d_apply_A(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
 
-/* Y = A X with the D^{1/2} products in precision `prec` (WC4D_PREC_FP64 or
- * WC4D_PREC_SKETCH_BF16X3; the latter needs the flag at finalize).  For measuring
+/* Y = A X with the D^{1/2} products in precision `prec` (WC4D_PREC_FP64,
+ * WC4D_PREC_SKETCH_BF16X3 or WC4D_PREC_SKETCH_FP16X3; a split form needs its flag at
+ * finalize, else WC4D_ESTATE).  For measuring
  * the error of the reduced-precision apply against the float64 one. */
 int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, int prec,
                       hipStream_t s);

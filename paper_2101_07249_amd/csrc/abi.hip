@@ -127,6 +127,13 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->dB);
   dev_free(&p->dQ);
   dev_free(&p->dBhi);
+  dev_free(&p->dBh16);
+  dev_free(&p->dBl16);
+  dev_free(&p->dQh16);
+  dev_free(&p->dQl16);
+  dev_free(&p->dBexp);
+  dev_free(&p->dQexp);
+  dev_free(&p->dColExp);
   dev_free(&p->dBlo);
   dev_free(&p->dQhi);
   dev_free(&p->dQlo);
@@ -282,8 +289,10 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (p->finalized) return fail(p, WC4D_ESTATE, "already finalized");
   if (p->model < 0) return fail(p, WC4D_ESTATE, "no model set");
   if (!p->haveB || !p->haveQ) return fail(p, WC4D_ESTATE, "B^{1/2} and Q^{1/2} must be set");
-  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32))
+  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32 | WC4D_PREC_SKETCH_FP16X3))
     return fail(p, WC4D_EINVAL, "unknown precision flags");
+  if ((prec_mode & WC4D_PREC_SKETCH_BF16X3) && (prec_mode & WC4D_PREC_SKETCH_FP16X3))
+    return fail(p, WC4D_EINVAL, "WC4D_PREC_SKETCH_BF16X3 and WC4D_PREC_SKETCH_FP16X3 exclude each other");
   DevGuard g(p->device);
   const int n = p->n, N = p->N;
   std::vector<int> off(N + 2, 0), idx;
@@ -343,6 +352,15 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
       return rc;
     HIPCHK(p, split_bf16_rows(n, n, p->dB, n, p->dBhi, p->dBlo, s));
     HIPCHK(p, split_bf16_rows(n, n, p->dQ, n, p->dQhi, p->dQlo, s));
+  }
+  if (prec_mode & WC4D_PREC_SKETCH_FP16X3) {
+    const size_t nn = (size_t)n * n;
+    if ((rc = dev_alloc(p, &p->dBh16, nn)) || (rc = dev_alloc(p, &p->dBl16, nn)) ||
+        (rc = dev_alloc(p, &p->dQh16, nn)) || (rc = dev_alloc(p, &p->dQl16, nn)) ||
+        (rc = dev_alloc(p, &p->dBexp, (size_t)n)) || (rc = dev_alloc(p, &p->dQexp, (size_t)n)))
+      return rc;
+    HIPCHK(p, split_f16_rows(n, n, p->dB, n, p->dBh16, p->dBl16, p->dBexp, s));
+    HIPCHK(p, split_f16_rows(n, n, p->dQ, n, p->dQh16, p->dQl16, p->dQexp, s));
   }
   if ((rc = dev_alloc(p, &p->dStatus, 16))) return rc;
   // split-K partials: up to 512 workgroups' worth of n x 112 tiles
@@ -443,9 +461,22 @@ namespace {
 
 // Y(time levels) = D^{1/2} X [+ E]: B^{1/2} on time 0, Q^{1/2} on times 1..N.
 int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
-                const double* E, long long lde, const int* skip, hipStream_t s, bool mixed = false) {
+                const double* E, long long lde, const int* skip, hipStream_t s, int mixed = SPLIT_NONE) {
   const int n = p->n, N = p->N;
-  if (mixed) {
+  if (mixed == SPLIT_FP16) {
+    const size_t need = (size_t)m * (N + 1);
+    if (p->colExpCap < need) {
+      int rc = dev_alloc(p, &p->dColExp, need);
+      if (rc) return rc;
+      p->colExpCap = need;
+    }
+    HIPCHK(p, gemm_fp16x3(n, m, n, 1.0, p->dBh16, p->dBl16, p->dBexp, X, ColMap{ldx, 1, 0, n}, p->dColExp, Y,
+                          ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
+    HIPCHK(p, gemm_fp16x3(n, m * N, n, 1.0, p->dQh16, p->dQl16, p->dQexp, X, ColMap{ldx, N, 1, n},
+                          p->dColExp + m, Y, ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
+    return WC4D_OK;
+  }
+  if (mixed == SPLIT_BF16) {
     HIPCHK(p, gemm_bf16x3(n, m, n, 1.0, p->dBhi, p->dBlo, X, ColMap{ldx, 1, 0, n}, Y,
                           ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
     HIPCHK(p, gemm_bf16x3(n, m * N, n, 1.0, p->dQhi, p->dQlo, X, ColMap{ldx, N, 1, n}, Y,
@@ -499,7 +530,7 @@ int check_block_args(wc4d_problem p, const void* X, int ldx, const void* Y, int 
 
 // Y = A X using the problem's block workspace (must hold m columns).
 int wc4d::apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy,
-                       int m, const int* skip, hipStream_t s, bool mixed) {
+                       int m, const int* skip, hipStream_t s, int mixed) {
   const long long nA = p->nA;
   if (p->q == 0) {
     HIPCHK(p, block_copy(Y, ldy, X, ldx, nA, m, s));
@@ -553,13 +584,16 @@ int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int l
                       hipStream_t s) {
   int rc = check_block_args(p, X, ldx, Y, ldy, m);
   if (rc) return rc;
-  if (prec != WC4D_PREC_FP64 && prec != WC4D_PREC_SKETCH_BF16X3)
-    return fail(p, WC4D_EINVAL, "prec must be WC4D_PREC_FP64 or WC4D_PREC_SKETCH_BF16X3");
+  if (prec != WC4D_PREC_FP64 && prec != WC4D_PREC_SKETCH_BF16X3 && prec != WC4D_PREC_SKETCH_FP16X3)
+    return fail(p, WC4D_EINVAL, "prec must be WC4D_PREC_FP64, WC4D_PREC_SKETCH_BF16X3 or WC4D_PREC_SKETCH_FP16X3");
   if (prec == WC4D_PREC_SKETCH_BF16X3 && p->dBhi == nullptr)
     return fail(p, WC4D_ESTATE, "finalize without WC4D_PREC_SKETCH_BF16X3");
+  if (prec == WC4D_PREC_SKETCH_FP16X3 && p->dBh16 == nullptr)
+    return fail(p, WC4D_ESTATE, "finalize without WC4D_PREC_SKETCH_FP16X3");
   DevGuard g(p->device);
   if ((rc = ensure_block(p, m))) return rc;
-  return apply_A_core(p, X, ldx, Y, ldy, m, nullptr, s, prec == WC4D_PREC_SKETCH_BF16X3);
+  const int mode = prec == WC4D_PREC_SKETCH_BF16X3 ? SPLIT_BF16 : prec == WC4D_PREC_SKETCH_FP16X3 ? SPLIT_FP16 : SPLIT_NONE;
+  return apply_A_core(p, X, ldx, Y, ldy, m, nullptr, s, mode);
 }
 
 int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
@@ -732,7 +766,8 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   double* Zfinal = nullptr;
   int mode = 0;
-  const bool mx = (p->prec & WC4D_PREC_SKETCH_BF16X3) != 0;
+  const int mx = (p->prec & WC4D_PREC_SKETCH_BF16X3) ? SPLIT_BF16
+                 : (p->prec & WC4D_PREC_SKETCH_FP16X3) ? SPLIT_FP16 : SPLIT_NONE;
   if (method == WC4D_REVD) {
     // Algorithm 3: Y = A G; Z = orth(Y); K = Z^T A Z; EVD; U = Z W
     if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s, mx))) return cleanup(rc);

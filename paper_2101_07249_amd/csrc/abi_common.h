@@ -125,6 +125,6 @@ int ensure_build(wc4d_problem p, int m);
 // Y = A X (Section 2.2, the first-level preconditioned Hessian) using the problem's
 // block workspace, which must hold m columns (ensure_block).  mixed: split-bf16 D^{1/2}.
 int apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
-                 const int* skip, hipStream_t s, bool mixed = false);
+                 const int* skip, hipStream_t s, int mixed = SPLIT_NONE);
 
 }  // namespace wc4d

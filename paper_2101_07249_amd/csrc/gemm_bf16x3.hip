@@ -9,6 +9,17 @@
 // S(i, 0..K-1) contiguously), so an MFMA operand row is one 16-byte load.  X is
 // split while it is staged into LDS.
 //
+// The float16 form (gemm_fp16x3) has 11 significant bits per part instead of 8 but a
+// narrow exponent range, so both operands are scaled by powers of two: row i of S by
+// 2^-eS_i and column j of X by 2^-eX_j, chosen so the row's / column's largest magnitude
+// lands in [2^14, 2^15).  With S = 2^eS (Sh + Sl) and X likewise (Sl, Xl the float16
+// rounding residuals),
+//   S X ~ 2^(eS + eX) (Sh Xh + Sh Xl + Sl Xh)
+// in one float32 accumulator; the dropped Sl Xl term is O(2^-22) relative.  A residual is
+// subnormal only for an element more than 2^17 below its row's / column's largest, whose
+// share of the product is below 2^-17, so the loss stays below 2^-28 relative.  The
+// column exponents of X come from a pre-pass (k_col_exponents).
+//
 // v_mfma_f32_16x16x32_bf16 lane layout (wave64): operand a = A[l%16][8(l/16) + e],
 // operand b = B[8(l/16) + e][l%16] (e = 0..7), result register r = D[4(l/16) + r][l%16].
 // As in gemm_f64 the product is formed transposed (MFMA rows = columns t of C), so a
@@ -48,6 +59,69 @@ hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16*
                            hipStream_t s) {
   hipLaunchKernelGGL(k_split_bf16_rows, dim3(2048), dim3(256), 0, s, M, K, S, lds, Shi, Slo);
   return hipGetLastError();
+}
+
+// Power-of-two exponent e with max |v| 2^-e in [2^14, 2^15) (0 for an all-zero set).
+static __device__ inline int scale_exponent(double amax) {
+  if (!(amax > 0.0)) return 0;
+  return ilogb(amax) - 14;
+}
+
+static __device__ inline void split_f16(double x, int e, _Float16& hi, _Float16& lo) {
+  const double y = ldexp(x, -e);
+  hi = (_Float16)y;
+  lo = (_Float16)(y - (double)hi);
+}
+
+// Row exponents of S and its float16 parts (row-major, ld K): one workgroup per row.
+__global__ __launch_bounds__(256) void k_split_f16_rows(int M, int K, const double* __restrict__ S, long long lds,
+                                                         _Float16* __restrict__ Shi, _Float16* __restrict__ Slo,
+                                                         int* __restrict__ rowexp) {
+  __shared__ double sh[256];
+  for (int i = blockIdx.x; i < M; i += gridDim.x) {
+    double m = 0.0;
+    for (int k = threadIdx.x; k < K; k += 256) m = fmax(m, fabs(S[(size_t)i + (size_t)k * lds]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      __syncthreads();
+    }
+    const int e = scale_exponent(sh[0]);
+    __syncthreads();
+    if (threadIdx.x == 0) rowexp[i] = e;
+    for (int k = threadIdx.x; k < K; k += 256) {
+      _Float16 h, l;
+      split_f16(S[(size_t)i + (size_t)k * lds], e, h, l);
+      Shi[(size_t)i * K + k] = h;
+      Slo[(size_t)i * K + k] = l;
+    }
+  }
+}
+
+hipError_t split_f16_rows(int M, int K, const double* S, long long lds, _Float16* Shi, _Float16* Slo, int* rowexp,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_split_f16_rows, dim3(M < 2048 ? M : 2048), dim3(256), 0, s, M, K, S, lds, Shi, Slo, rowexp);
+  return hipGetLastError();
+}
+
+// Column exponents of X (K rows, columns through bmap): one workgroup per column.
+__global__ __launch_bounds__(256) void k_col_exponents(int ncol, int K, const double* __restrict__ B, ColMap bmap,
+                                                        int* __restrict__ colexp) {
+  __shared__ double sh[256];
+  for (int j = blockIdx.x; j < ncol; j += gridDim.x) {
+    const double* x = B + bmap.off(j);
+    double m = 0.0;
+    for (int k = threadIdx.x; k < K; k += 256) m = fmax(m, fabs(x[k]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) colexp[j] = scale_exponent(sh[0]);
+    __syncthreads();
+  }
 }
 
 constexpr int XBM = 128, XBN = 128, XBK = 32;
@@ -179,6 +253,151 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(int M, int ncol, int K, dou
         }
       }
     }
+}
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+static __device__ inline f4 mfma_f16(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Same tiling as k_gemm_bf16x3, with the row and column exponents applied in the epilogue.
+__global__ __launch_bounds__(256) void k_gemm_fp16x3(int M, int ncol, int K, double alpha,
+                                                     const _Float16* __restrict__ Shi,
+                                                     const _Float16* __restrict__ Slo,
+                                                     const int* __restrict__ rowexp,
+                                                     const double* __restrict__ B, ColMap bmap,
+                                                     const int* __restrict__ colexp,
+                                                     double* __restrict__ C, ColMap cmap,
+                                                     const double* __restrict__ E, ColMap emap) {
+  __shared__ __attribute__((aligned(16))) _Float16 Sh[XBM][XPK], Sl[XBM][XPK];
+  __shared__ __attribute__((aligned(16))) _Float16 Xh[XBN][XPK], Xl[XBN][XPK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = blockIdx.x * XBM, j0 = blockIdx.y * XBN;
+  const int wi0 = (wave & 1) * 64, wj0 = (wave >> 1) * 64;
+  f4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 1, lh = (tid & 1) * 16;
+  const bool srow_ok = (i0 + lr) < M;
+  const _Float16* shp = Shi + (size_t)(srow_ok ? i0 + lr : 0) * K;
+  const _Float16* slp = Slo + (size_t)(srow_ok ? i0 + lr : 0) * K;
+  const bool xcol_ok = (j0 + lr) < ncol;
+  const double* xp = B + (xcol_ok ? bmap.off(j0 + lr) : 0);
+  const int xe = xcol_ok ? colexp[j0 + lr] : 0;
+  h8 rsh[2], rsl[2];
+  double rx[16];
+  const bool svec = (K % 8) == 0;
+  const bool xvec = ((reinterpret_cast<uintptr_t>(xp) & 15) == 0);
+  auto gload = [&](int k0) {
+    const int kb = k0 + lh;
+    if (svec && kb + 16 <= K) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        rsh[v] = srow_ok ? *reinterpret_cast<const h8*>(shp + kb + 8 * v) : h8{};
+        rsl[v] = srow_ok ? *reinterpret_cast<const h8*>(slp + kb + 8 * v) : h8{};
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const bool ok = srow_ok && (kb + e) < K;
+        rsh[e / 8][e % 8] = ok ? shp[kb + e] : (_Float16)0.f;
+        rsl[e / 8][e % 8] = ok ? slp[kb + e] : (_Float16)0.f;
+      }
+    }
+    if (xvec && kb + 16 <= K) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const double2 d2 = xcol_ok ? *reinterpret_cast<const double2*>(xp + kb + 2 * v) : double2{0.0, 0.0};
+        rx[2 * v] = d2.x;
+        rx[2 * v + 1] = d2.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) rx[e] = (xcol_ok && (kb + e) < K) ? xp[kb + e] : 0.0;
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += XBK) {
+    __syncthreads();
+    *reinterpret_cast<h8*>(&Sh[lr][lh]) = rsh[0];
+    *reinterpret_cast<h8*>(&Sh[lr][lh + 8]) = rsh[1];
+    *reinterpret_cast<h8*>(&Sl[lr][lh]) = rsl[0];
+    *reinterpret_cast<h8*>(&Sl[lr][lh + 8]) = rsl[1];
+    {
+      h8 h0, h1, l0, l1;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        _Float16 h, l;
+        split_f16(rx[e], xe, h, l);
+        h0[e] = h;
+        l0[e] = l;
+        split_f16(rx[8 + e], xe, h, l);
+        h1[e] = h;
+        l1[e] = l;
+      }
+      *reinterpret_cast<h8*>(&Xh[lr][lh]) = h0;
+      *reinterpret_cast<h8*>(&Xh[lr][lh + 8]) = h1;
+      *reinterpret_cast<h8*>(&Xl[lr][lh]) = l0;
+      *reinterpret_cast<h8*>(&Xl[lr][lh + 8]) = l1;
+    }
+    __syncthreads();
+    if (k0 + XBK < K) gload(k0 + XBK);
+    const int kk = 8 * (lane >> 4);
+    h8 xh[4], xl[4], sh[4], sl[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int j = wj0 + a * 16 + (lane & 15);
+      xh[a] = *reinterpret_cast<const h8*>(&Xh[j][kk]);
+      xl[a] = *reinterpret_cast<const h8*>(&Xl[j][kk]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = wi0 + b * 16 + (lane & 15);
+      sh[b] = *reinterpret_cast<const h8*>(&Sh[i][kk]);
+      sl[b] = *reinterpret_cast<const h8*>(&Sl[i][kk]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc[a][b] = mfma_f16(xh[a], sh[b], acc[a][b]);
+        acc[a][b] = mfma_f16(xl[a], sh[b], acc[a][b]);
+        acc[a][b] = mfma_f16(xh[a], sl[b], acc[a][b]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + wj0 + a * 16 + 4 * (lane >> 4) + r;
+      if (j >= ncol) continue;
+      const long long co = cmap.off(j);
+      const long long eo = (E != nullptr) ? emap.off(j) : 0;
+      const int ej = colexp[j];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + wi0 + b * 16 + (lane & 15);
+        if (i < M) {
+          double v = alpha * ldexp((double)acc[a][b][r], rowexp[i] + ej);
+          if (E != nullptr) v += E[eo + i];
+          C[co + i] = v;
+        }
+      }
+    }
+}
+
+hipError_t gemm_fp16x3(int M, int ncol, int K, double alpha, const _Float16* Shi, const _Float16* Slo,
+                       const int* rowexp, const double* B, ColMap bmap, int* colexp, double* C, ColMap cmap,
+                       const double* E, ColMap emap, hipStream_t s) {
+  if (M <= 0 || ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_col_exponents, dim3(ncol < 4096 ? ncol : 4096), dim3(256), 0, s, ncol, K, B, bmap, colexp);
+  dim3 grid((M + XBM - 1) / XBM, (ncol + XBN - 1) / XBN);
+  hipLaunchKernelGGL(k_gemm_fp16x3, grid, dim3(256), 0, s, M, ncol, K, alpha, Shi, Slo, rowexp, B, bmap, colexp, C,
+                     cmap, E, emap);
+  return hipGetLastError();
 }
 
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,

@@ -87,6 +87,15 @@ hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16*
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
                        const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                        ColMap emap, hipStream_t s);
+// Float16 form: S split per row with power-of-two row exponents (rowexp, M ints), X per
+// column (colexp: ncol ints of workspace, filled by the call).  See gemm_bf16x3.hip.
+hipError_t split_f16_rows(int M, int K, const double* S, long long lds, _Float16* Shi, _Float16* Slo, int* rowexp,
+                          hipStream_t s);
+hipError_t gemm_fp16x3(int M, int ncol, int K, double alpha, const _Float16* Shi, const _Float16* Slo,
+                       const int* rowexp, const double* B, ColMap bmap, int* colexp, double* C, ColMap cmap,
+                       const double* E, ColMap emap, hipStream_t s);
+// D^{1/2} product precision of an operator apply: float64, split bfloat16 x3, split float16 x3
+enum SplitMode { SPLIT_NONE = 0, SPLIT_BF16 = 1, SPLIT_FP16 = 2 };
 
 // Tangent-linear sweeps.  P/X/W are blocks of m columns (leading dimension ld*).
 // observation k at local point l of a sweep wavefront's extended range (l < 0: empty)
@@ -316,6 +325,14 @@ struct wc4d_problem_s {
   __bf16* dBlo = nullptr;
   __bf16* dQhi = nullptr;
   __bf16* dQlo = nullptr;
+  _Float16* dBh16 = nullptr;  // split-float16 B^{1/2}, Q^{1/2} (row-major, scaled rows), when prec has FP16X3
+  _Float16* dBl16 = nullptr;
+  _Float16* dQh16 = nullptr;
+  _Float16* dQl16 = nullptr;
+  int* dBexp = nullptr;       // their row exponents
+  int* dQexp = nullptr;
+  int* dColExp = nullptr;     // column exponents of a float16 product's right operand
+  size_t colExpCap = 0;
   double* dStages = nullptr;
   double* dTraj = nullptr;  // l96: (N+1) x n trajectory (sketch-network features)
   int* dObsOff = nullptr;

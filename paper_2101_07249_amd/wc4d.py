@@ -26,7 +26,7 @@ REVD, NYSTROM, RITZIT = 0, 1, 2
 METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
 RES_TRUE, RES_PRECOND = 0, 1
 PCG_FUSED, PCG_PLAIN = 0, 1
-PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32 = 0, 1, 2
+PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32, PREC_SKETCH_FP16X3 = 0, 1, 2, 4
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)

@@ -133,3 +133,100 @@ def test_fp32_panel_lmp_apply_and_pcg(k_r):
         print("[result] variant", variant, "iters", info["iters"], "oracle", ro.iters, "true res", res, flush=True)
         assert info["status"] == 0 and res <= 1.01e-6
         assert abs(info["iters"] - ro.iters) <= 2
+
+
+# ---------------------------------------------------------------- split float16 x 3
+# Three float16 products with float32 accumulation and power-of-two scaling (rows of S,
+# columns of X): per part 11 significant bits, so the dropped Sl Xl term is ~2^-22 relative
+# and the float32 sums over K = n add ~sqrt(n) 2^-24; the bound used is 1e-5 (the bfloat16
+# form's is 1e-4), and the float16 form must be the more accurate of the two.
+@pytest.mark.parametrize("w", [C1, C2, MEDIUM], ids=["C1", "C2", "adv700"])
+def test_fp16x3_apply_error(w):
+    from paper_2101_07249_amd import wc4d
+    print("[case] fp16x3 apply", w.name, flush=True)
+    gh, op = _pair(w, wc4d.PREC_SKETCH_FP16X3)
+    gb, _ = _pair(w, wc4d.PREC_SKETCH_BF16X3)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    Yo = O.apply_A(op, G)
+    Yh = gh.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_FP16X3).cpu().numpy().T
+    Yb = gb.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_BF16X3).cpu().numpy().T
+    e_h = np.linalg.norm(Yh - Yo) / np.linalg.norm(Yo)
+    e_b = np.linalg.norm(Yb - Yo) / np.linalg.norm(Yo)
+    print("[result] rel err fp16x3", e_h, "bf16x3", e_b, flush=True)
+    assert 1e-12 < e_h <= 1e-5
+    assert e_h < e_b
+
+
+def test_fp16x3_scaling_extremes_and_zero_column():
+    """Column exponents follow the data: blocks scaled by 1e-150 or 1e150 keep the same
+    relative error, and an all-zero column maps to an all-zero column."""
+    from paper_2101_07249_amd import wc4d
+    w = MEDIUM
+    print("[case] fp16x3 scaling", flush=True)
+    gh, op = _pair(w, wc4d.PREC_SKETCH_FP16X3)
+    G = sketch_block(op.n_A, 6, w.seed + 3)
+    G[:, 2] = 0.0
+    Yo = O.apply_A(op, G)
+    for scale in (1e-150, 1.0, 1e150):
+        Y = gh.apply_A_prec(_dev(G * scale), wc4d.PREC_SKETCH_FP16X3).cpu().numpy().T / scale
+        e = np.linalg.norm(Y - Yo) / np.linalg.norm(Yo)
+        print("[result] scale", scale, "rel err", e, flush=True)
+        assert e <= 1e-5
+        np.testing.assert_array_equal(Y[:, 2], 0.0)
+
+
+def test_fp16x3_lmp_and_pcg():
+    from paper_2101_07249_amd import wc4d
+    import torch
+    w = C2
+    print("[case] fp16x3 lmp + pcg", flush=True)
+    gm, op = _pair(w, wc4d.PREC_SKETCH_FP16X3 | wc4d.PREC_LMP_FP32)
+    gd, _ = _pair(w, wc4d.PREC_FP64)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    Lm = gm.lmp_build("nystrom", w.k_r, w.l, _dev(G))
+    Ld = gd.lmp_build("nystrom", w.k_r, w.l, _dev(G))
+    _, tho = O.METHODS["nystrom"](lambda Z: O.apply_A(op, Z), G, w.k_r)
+    e = np.linalg.norm(Lm.theta() - tho) / np.linalg.norm(tho)
+    print("[result] theta rel err", e, flush=True)
+    assert e <= 1e-5
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    xm = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+    xd = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+    im = gm.pcg(gm.rhs(_dev(d)), xm, Lm, tol=1e-6, maxit=3000)
+    idd = gd.pcg(gd.rhs(_dev(d)), xd, Ld, tol=1e-6, maxit=3000)
+    assert im["status"] == 0 and idd["status"] == 0
+    res = np.linalg.norm(b - O.apply_A(op, xm.cpu().numpy())) / np.linalg.norm(b)
+    print("[result] iters fp16x3", im["iters"], "fp64", idd["iters"], "true res", res, flush=True)
+    assert res <= 1.05e-6
+    assert im["iters"] <= 1.05 * idd["iters"] + 2
+
+
+def test_fp16x3_flag_errors():
+    from paper_2101_07249_amd import Problem, Wc4dError, wc4d
+    w = C1
+    pat = obs_pattern(w)
+    with pytest.raises(Wc4dError) as e:
+        Problem.from_workload(w, pat, prec=wc4d.PREC_SKETCH_FP16X3 | wc4d.PREC_SKETCH_BF16X3)
+    assert e.value.code == -1
+    gb = Problem.from_workload(w, pat, prec=wc4d.PREC_SKETCH_BF16X3)
+    G = sketch_block(gb.n_A, 3, 5)
+    with pytest.raises(Wc4dError) as e:
+        gb.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_FP16X3)
+    assert e.value.code == -7
+
+
+def test_fp16x3_full_size_sampled_columns():
+    from paper_2101_07249_amd import wc4d
+    print("[case] fp16x3 full size", flush=True)
+    pat = obs_pattern(C3)
+    from paper_2101_07249_amd import Problem
+    gp = Problem.from_workload(C3, pat, prec=wc4d.PREC_SKETCH_FP16X3 | wc4d.PREC_LMP_FP32)
+    op = O.make_problem(C3, pat)
+    G = sketch_block(gp.n_A, C3.m, C3.seed)
+    Y = gp.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_FP16X3)
+    cols = [3, 200]
+    Yo = O.apply_A(op, G[:, cols])
+    e = np.linalg.norm(Y[cols].cpu().numpy().T - Yo) / np.linalg.norm(Yo)
+    print("[result] full-size fp16x3 rel err", e, flush=True)
+    assert 1e-12 < e <= 1e-5
