@@ -214,6 +214,7 @@ def batched_section(args):
                                 autotune=False)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    print(f"batched: {len(probs)} problems in {t_batch:.1f} s; now one after another", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     iters_seq = []
     for i, p in enumerate(probs):
@@ -221,6 +222,8 @@ def batched_section(args):
         x[i].zero_()
         iters_seq.append(p.pcg(b[i], x[i], L, tol=args.tol, maxit=args.maxit, history=False)["iters"])
         L.close()
+        if (i + 1) % 16 == 0:
+            print(f"batched: one after another, {i + 1} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     return {"problems": len(ws), "sum_n_A": int(sum(p.n_A for p in probs)), "batch_s": t_batch,

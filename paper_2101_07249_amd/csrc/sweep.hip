@@ -776,12 +776,14 @@ constexpr int kTS = kTW * kTOW;    // entry slots per (wavefront, level)
 
 bool tw_setup(int n, int N, const std::vector<int>& off, const std::vector<int>& idx,
               const std::vector<double>& rinv, int* pe, int* W, std::vector<TwEntry>& ent) {
+  // 4 or 8 points per lane (16 would leave the step's registers spilling into AGPRs);
+  // the owned width W must be at least a quarter of the range, else redundancy dominates
   int q = 4;
-  for (; q <= 16; q *= 2) {
+  for (; q <= 8; q *= 2) {
     const int E = kTW * q, w = E - 2 * N;
-    if (w > 0 && 2 * w >= E && n >= E) break;
+    if (4 * w >= E && n >= E) break;
   }
-  if (q > 16 || off[N + 1] == 0) return false;
+  if (q > 8 || off[N + 1] == 0) return false;
   const int E = kTW * q, Wd = E - 2 * N, nb = (n + Wd - 1) / Wd;
   ent.assign((size_t)nb * (N + 1) * kTS, TwEntry{0, -1, 0.0});
   for (int b = 0; b < nb; ++b) {
@@ -1108,8 +1110,6 @@ hipError_t sweep_fwd(const SweepModel& md, const double* P, long long ldp, int m
       WC4D_TW_FWD(4, 8)
     } else if (md.tw_pe == 8) {
       WC4D_TW_FWD(8, 8)
-    } else if (md.tw_pe == 16) {
-      WC4D_TW_FWD(16, 4)
     } else {
       return hipErrorInvalidValue;
     }
@@ -1143,8 +1143,6 @@ hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, 
       hipLaunchKernelGGL((k_sweep_bwd_w<4, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
     else if (md.tw_pe == 8)
       hipLaunchKernelGGL((k_sweep_bwd_w<8, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
-    else if (md.tw_pe == 16)
-      hipLaunchKernelGGL((k_sweep_bwd_w<16, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();

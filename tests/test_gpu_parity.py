@@ -76,7 +76,8 @@ CASES = {
     # extended range of 64 PE points, W = 64 PE - 2N; the last wavefront owns fewer
     "tb_adv": tiny(n=600, N=30, vs=5, ts=3),      # PE 4, W 196: 4 wavefronts, last owns 12
     "tb_adv2": tiny(n=1100, N=100, vs=7, ts=2),   # PE 8, W 312: 4 wavefronts, last owns 164
-    "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # PE 16, W 624: 2 wavefronts, last owns 476
+    "tb_adv4": tiny(n=1100, N=150, vs=9, ts=5),   # PE 8, W 212: 6 wavefronts, last owns 40
+    "tb_adv3": tiny(n=1100, N=200, vs=9, ts=5),   # N = 200 leaves W < 128: the general kernel
     # B and Q with different length scales: D^{1/2} as two products (no B = c Q shortcut)
     "bq_adv": tiny(n=600, N=30, vs=5, ts=3).with_(Lq=3.0),
     # (Gaussian L = 1.5: smallest correlation eigenvalue 1.5e-5; a longer scale on n = 256
