@@ -108,6 +108,8 @@ def parse():
                     help="autotune cache file: loaded when present, written after tuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM counters)")
+    ap.add_argument("--prof-every", type=int, default=8,
+                    help="time one launch group in this many of the dominant class in the timed steps")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="only measure the float64 MFMA rate of a register-only stream (roofline reference)")
     return ap.parse_args()
@@ -341,6 +343,7 @@ def main():
             dom_cls = dominant_class(prof_all)
         torch.cuda.synchronize()
         prob.prof_enable(True, classes=None if prof_all is None else [dom_cls])
+        prob.prof_stride(args.prof_every)
         infos = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -349,6 +352,7 @@ def main():
         t1 = time.perf_counter()
         prof = prob.prof_read()
         prob.prof_enable(False)
+        prob.prof_stride(1)
         results[vname] = {"ms_per_step": 1e3 * (t1 - t0) / args.steps,
                           "pcg_iters": int(np.median([i["iters"] for i in infos])),
                           "relres_true": max(i["relres_true"] for i in infos),
@@ -401,6 +405,7 @@ def main():
     roof.update({"kernel": names_k.get(dom, dom), "class": dom, "launches": dv["launches"],
                  "traffic_unit": "HBM bytes per launch group (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                  "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
+                 "sampled": f"HIP events around 1 in {args.prof_every} launch groups of the timed steps",
                  "algorithmic_per_launch": (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"]})
 
     iters = results[head]["pcg_iters"]

@@ -236,6 +236,11 @@ enum { WC4D_PROF_DSQRT = 0, WC4D_PROF_SWEEP_FWD = 1, WC4D_PROF_SWEEP_BWD = 2, WC
        WC4D_PROF_LMP_N = 4, WC4D_PROF_BUILD = 5, WC4D_PROF_DSQRT_BF16 = 6,
        WC4D_PROF_NET = 7, WC4D_PROF_NCLASS = 8, WC4D_PROF_ALL = 0xFF };
 int wc4d_prof_enable(wc4d_problem p, int enable);
+/* Time one launch group in `every` (>= 1, default 1) of each class enabled above, counted
+ * per class from the last wc4d_prof_enable: wc4d_prof_read then reports the bracketed groups
+ * only (launches, ms, bytes, flops), an unbiased sample when the groups are alike.
+ * WC4D_EINVAL for every < 1. */
+int wc4d_prof_stride(wc4d_problem p, int every);
 int wc4d_prof_read(wc4d_problem p, int cls, double* ms, long long* launches, double* bytes,
                    double* flops);
 

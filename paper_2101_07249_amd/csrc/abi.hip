@@ -159,6 +159,10 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->pcgRed);
   dev_free(&p->pcgState);
   if (p->pcgStateHost != nullptr) (void)hipHostFree(p->pcgStateHost);
+  for (int q = 0; q < 2; ++q) {
+    if (p->pcgPoll[q] != nullptr) (void)hipHostFree(p->pcgPoll[q]);
+    if (p->pcgPollEv[q] != nullptr) (void)hipEventDestroy(p->pcgPollEv[q]);
+  }
   for (auto& e : p->ev)
     if (e != nullptr) (void)hipEventDestroy(e);
   for (auto& e : p->evpool) (void)hipEventDestroy(e);
@@ -419,6 +423,13 @@ int wc4d_prof_enable(wc4d_problem p, int enable) {
     p->profCalls[c] = 0;
   }
   p->kprof = enable & ((1 << PROF_NCLASS) - 1);
+  for (auto& q : p->kprofSeq) q = 0;
+  return WC4D_OK;
+}
+
+int wc4d_prof_stride(wc4d_problem p, int every) {
+  if (p == nullptr || every < 1) return WC4D_EINVAL;
+  p->kprofEvery = every;
   return WC4D_OK;
 }
 
@@ -439,7 +450,7 @@ int wc4d_set_profiling(wc4d_problem p, int enable) {
   if (p == nullptr) return WC4D_EINVAL;
   DevGuard g(p->device);
   if (enable && p->ev[0] == nullptr)
-    for (auto& e : p->ev) HIPCHK(p, hipEventCreate(&e));
+    for (auto& e : p->ev) HIPCHK(p, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   p->prof = enable != 0;
   return WC4D_OK;
 }
@@ -978,6 +989,10 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     if ((rc = dev_alloc(p, &p->pcgRed, pcg_red_doubles()))) return rc;
     if ((rc = dev_alloc(p, &p->pcgState, 1))) return rc;
     HIPCHK(p, hipHostMalloc((void**)&p->pcgStateHost, sizeof(PcgState), hipHostMallocDefault));
+    for (int q = 0; q < 2; ++q) {
+      HIPCHK(p, hipHostMalloc((void**)&p->pcgPoll[q], sizeof(PcgState), hipHostMallocDefault));
+      HIPCHK(p, hipEventCreateWithFlags(&p->pcgPollEv[q], hipEventDisableTiming));
+    }
   }
   if (p->pcgHistCap < opts->maxit) {
     if ((rc = dev_alloc(p, &p->pcgHist, (size_t)3 * opts->maxit))) return rc;
@@ -1015,10 +1030,14 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     tvec = L->wsv + lmp_gemv_t_offset(nA, L->k);
     HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, nullptr, s, u));
   }
+  // The host enqueues chunks of `poll` iterations and reads the device state after each
+  // chunk; the next chunk is already enqueued while it waits (two pinned copies of the
+  // state, one event each), so the stream does not idle during the poll.  Kernels return
+  // at once after the solve is done, so the chunk in flight at that point costs launches only.
   const int poll = 8;
-  int it = 0;
-  bool fin = false;
-  while (!fin) {
+  int it = 0, issued = 0, pending = 0;
+  for (;;) {
+   while (pending < 2 && it < opts->maxit) {
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
       if (fused && u32) {
@@ -1077,10 +1096,20 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
       HIPCHK(p, pcg_update_p(st, pv, zv, nA, s));
     }
     it += chunk;
-    HIPCHK(p, hipMemcpyAsync(p->pcgStateHost, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    HIPCHK(p, hipStreamSynchronize(s));
-    fin = p->pcgStateHost->done != 0 || it >= opts->maxit;
+    const int slot = issued & 1;
+    HIPCHK(p, hipMemcpyAsync(p->pcgPoll[slot], st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(p, hipEventRecord(p->pcgPollEv[slot], s));
+    ++issued;
+    ++pending;
+   }
+   if (pending == 0) break;  // maxit iterations enqueued and read back
+   const int oldest = (issued - pending) & 1;
+   HIPCHK(p, hipEventSynchronize(p->pcgPollEv[oldest]));
+   --pending;
+   if (p->pcgPoll[oldest]->done != 0) break;
   }
+  HIPCHK(p, hipMemcpyAsync(p->pcgStateHost, st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(p, hipStreamSynchronize(s));
   const PcgState hs = *p->pcgStateHost;
   info->iters = hs.iter;
   info->status = hs.done ? hs.status : WC4D_ENOCONV;

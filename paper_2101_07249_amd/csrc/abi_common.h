@@ -81,7 +81,8 @@ inline bool is_state_ok(wc4d_problem p) { return p != nullptr && p->finalized; }
 inline hipEvent_t prof_event(wc4d_problem p) {
   if (p->evnext == p->evpool.size()) {
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence on record (it stalls the stream for several us)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     p->evpool.push_back(e);
   }
   return p->evpool[p->evnext++];
@@ -95,7 +96,9 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   ProfScope(wc4d_problem p_, hipStream_t s_, int cls_, double bytes_, double flops_)
       : p(p_), s(s_), cls(cls_), bytes(bytes_), flops(flops_) {
-    if ((p->kprof >> cls) & 1) {
+    // one launch group in kprofEvery of each timed class is bracketed (the others run
+    // without event records: each record leaves the stream idle for a few us)
+    if (((p->kprof >> cls) & 1) && (p->kprofSeq[cls]++ % p->kprofEvery) == 0) {
       a = prof_event(p);
       if (a != nullptr) (void)hipEventRecord(a, s);
     }

@@ -33,8 +33,8 @@ std::map<std::tuple<int, int, int, int, int>, DsqrtTune> g_tune_cache;  // (devi
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
   EvPair() {
-    (void)hipEventCreate(&a);
-    (void)hipEventCreate(&b);
+    (void)hipEventCreateWithFlags(&a, hipEventDisableSystemFence);
+    (void)hipEventCreateWithFlags(&b, hipEventDisableSystemFence);
   }
   ~EvPair() {
     if (a) (void)hipEventDestroy(a);

@@ -368,8 +368,12 @@ struct wc4d_problem_s {
   double* pcgRed = nullptr;
   wc4d::PcgState* pcgState = nullptr;
   wc4d::PcgState* pcgStateHost = nullptr;  // pinned
+  wc4d::PcgState* pcgPoll[2] = {nullptr, nullptr};  // pinned copies read while the next chunk runs
+  hipEvent_t pcgPollEv[2] = {nullptr, nullptr};
   // per-class kernel timing
   int kprof = 0;           // classes timed by ProfScope (bit c: class c)
+  int kprofEvery = 1;      // ... one launch group in kprofEvery per class
+  long long kprofSeq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;

@@ -79,6 +79,7 @@ _SIGS = {
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
     "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_probe_mfma_f64": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_dbl_p]),
+    "wc4d_prof_stride": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
                                       _c_dbl_p, _c_dbl_p]),
@@ -434,6 +435,10 @@ class Problem:
                 for c in classes:
                     mask |= 1 << (self.PROF_CLASSES.index(c) if isinstance(c, str) else int(c))
         self._chk(lib().wc4d_prof_enable(self._h, mask), "prof_enable")
+
+    def prof_stride(self, every: int = 1):
+        """Time one launch group in `every` of each enabled class."""
+        self._chk(lib().wc4d_prof_stride(self._h, int(every)), "prof_stride")
 
     def prof_read(self) -> dict:
         out = {}
