@@ -324,3 +324,47 @@ def test_ill_conditioned_sketch_takes_shifted_choleskyqr(method):
     assert np.all(th >= 1.0 - 1e-8)
     np.testing.assert_allclose(th[:5], th_o[:5], rtol=1e-4)
     assert np.abs(U.T @ U - np.eye(C2.k_r)).max() <= 1e-9
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_pcg_maxit_at_chunk_boundaries(variant):
+    """The host enqueues iterations in chunks of 8 and reads the state of one chunk while the
+    next runs: a solve that cannot converge stops after exactly maxit iterations for maxit on
+    either side of the chunk boundaries, and its first iterations follow the oracle's."""
+    from paper_2101_07249_amd import wc4d
+    t = _torch()
+    say("pcg maxit chunks, variant", variant)
+    w = C1
+    gp, op = pair(w)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    L = gp.lmp_build("nystrom", w.k_r, w.l, to_dev(G))
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    Uo, tho = O.METHODS["nystrom"](lambda Z: O.apply_A(op, Z), G, w.k_r)
+    ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-14, maxit=17)
+    for maxit in (1, 7, 8, 9, 16, 17):
+        x = t.zeros(op.n_A, dtype=t.float64, device=dev())
+        info = gp.pcg(gp.rhs(to_dev(d)), x, L, tol=1e-14, maxit=maxit, variant=variant)
+        assert info["status"] == wc4d.ENOCONV and info["iters"] == maxit, (maxit, info["status"], info["iters"])
+        k = min(maxit, 5)
+        np.testing.assert_allclose(info["hist_true"][:k], ro.hist_true[:k], rtol=1e-8)
+
+
+def test_prof_stride_samples_launch_groups():
+    """With stride s only every s-th launch group of a timed class is bracketed by events."""
+    say("prof stride")
+    t = _torch()
+    gp, op = pair(C2)
+    X = to_dev(random_block(op.n_A, 3, 5))
+    Y = t.empty_like(X)
+    for every, want in ((1, 16), (4, 4), (5, 4)):
+        gp.prof_enable(True, classes=["dsqrt_gemm"])
+        gp.prof_stride(every)
+        for _ in range(8):   # two D^{1/2} launch groups per apply
+            gp.apply_A(X, Y)
+        prof = gp.prof_read()
+        gp.prof_enable(False)
+        gp.prof_stride(1)
+        assert prof["dsqrt_gemm"]["launches"] == want, (every, prof["dsqrt_gemm"])
+        assert prof["sweep_fwd"]["launches"] == 0
+        assert prof["dsqrt_gemm"]["ms"] > 0
