@@ -10,12 +10,14 @@ SOAR B / Q, every 4th point observed at every 2nd step (q = 51,200), a sketch of
 m = 256 columns (k_r = 251 Ritz pairs, oversampling 5), Nystrom.
 
 Variants (each timed over the same number of steps):
-  plain  float64 throughout;
-  mixed  the sketch's D^{1/2} products as three bfloat16 MFMA products with float32
-         accumulation and a float32 copy of U for the LMP passes; CholeskyQR2, the
-         small eigenproblem and the whole PCG operator stay float64, and the stop is
-         the float64 true residual.
-`value` is the mixed variant's ms per step; the plain one is reported beside it.
+  plain       float64 throughout;
+  mixed       the sketch's D^{1/2} products as three bfloat16 MFMA products with float32
+              accumulation and a float16 copy of U (power-of-two column scaling) for the
+              PCG's LMP passes; CholeskyQR2, the small eigenproblem and the whole PCG
+              operator stay float64, and the stop is the float64 true residual;
+  mixed_u32   the same with a float32 copy of U;
+  mixed_fp16  split-float16 instead of split-bfloat16 sketch products, float16 U.
+`value` is the mixed variant's ms per step; the others are reported beside it.
 
 Prints one JSON line (see the fields below).  Only --gpus 1 is supported.
 """
@@ -93,8 +95,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
     ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit"])
-    ap.add_argument("--variants", default="plain,mixed,mixed_fp16",
-                    help="comma list of plain (FP64), mixed (split-bf16 block products, FP32 U), mixed_fp16 (split-float16)")
+    ap.add_argument("--variants", default="plain,mixed,mixed_u32,mixed_fp16",
+                    help="comma list of plain (FP64), mixed (split-bf16 block products, float16 U), "
+                         "mixed_u32 (float32 U), mixed_fp16 (split-float16 products, float16 U)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -307,8 +310,9 @@ def main():
     dnp = innovations(sum(len(i) for _, i in pat), w.seed, np.sqrt(w.sigma_o2))
     d = torch.from_numpy(dnp).to(dev)
     x = torch.zeros(w.n_A, dtype=torch.float64, device=dev)
-    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32,
-             "mixed_fp16": W4.PREC_SKETCH_FP16X3 | W4.PREC_LMP_FP32}
+    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP16,
+             "mixed_u32": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32,
+             "mixed_fp16": W4.PREC_SKETCH_FP16X3 | W4.PREC_LMP_FP16}
     names = [v for v in args.variants.split(",") if v]
     results = {}
     tunes = {}
@@ -327,6 +331,7 @@ def main():
             L = prob.lmp_build(args.method, w.k_r, w.l, G)
             x.zero_()
             info = prob.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
+            info["lmp_copy"] = L.copy_format()
             L.close()
             return info
 
@@ -357,6 +362,7 @@ def main():
                           "pcg_iters": int(np.median([i["iters"] for i in infos])),
                           "relres_true": max(i["relres_true"] for i in infos),
                           "converged": all(i["status"] == 0 and i["relres_true"] <= args.tol for i in infos),
+                          "lmp_copy": {0: "f64", W4.PREC_LMP_FP32: "f32", W4.PREC_LMP_FP16: "f16"}[infos[-1]["lmp_copy"]],
                           "prof": prof, "prof_classes": prof_all if prof_all is not None else prof,
                           "classes_steps": 1 if prof_all is not None else args.steps, "prob": prob}
     head = "mixed" if "mixed" in results else names[0]
@@ -419,7 +425,7 @@ def main():
         "metric": "PCG time-to-1e-6 residual (learned/mixed vs plain FP64); Hessian-apply HBM GB/s",
         "value": ms_per_step, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+bf16x3" if head == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f64+bf16x3+f16" if head == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "variant": head, "method": args.method,
                    "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,

@@ -62,8 +62,18 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *     (largest magnitude brought to [2^14, 2^15)) so that the parts fit float16's range;
  *     excludes WC4D_PREC_SKETCH_BF16X3.
  *   WC4D_PREC_LMP_FP32: the LMP keeps a float32 copy of U that wc4d_pcg streams
- *     (products accumulate in float64; C stays exactly symmetric). */
-enum { WC4D_PREC_FP64 = 0, WC4D_PREC_SKETCH_BF16X3 = 1, WC4D_PREC_LMP_FP32 = 2, WC4D_PREC_SKETCH_FP16X3 = 4 };
+ *     (products accumulate in float64; C stays exactly symmetric).
+ *   WC4D_PREC_LMP_FP16: the same with a float16 copy, each column scaled by a power of
+ *     two (largest magnitude brought to [2^14, 2^15)), half the bytes per pass; excludes
+ *     WC4D_PREC_LMP_FP32.  Either copy changes the preconditioner by its rounding only, so
+ *     PCG still solves A x = b; the iteration count may differ. */
+enum {
+  WC4D_PREC_FP64 = 0,
+  WC4D_PREC_SKETCH_BF16X3 = 1,
+  WC4D_PREC_LMP_FP32 = 2,
+  WC4D_PREC_SKETCH_FP16X3 = 4,
+  WC4D_PREC_LMP_FP16 = 8
+};
 
 /* Library version (major*10000 + minor*100 + patch) and status-code names. */
 int wc4d_version(void);
@@ -170,6 +180,12 @@ int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s);
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
 /* Block products with A spent by the build (Table 1: 2 / 2 / 1). */
 int wc4d_lmp_applies(wc4d_lmp L, int* count);
+/* The copy of U that the one- and two-vector passes stream (and wc4d_pcg with it):
+ * *prec_flag = WC4D_PREC_LMP_FP16, WC4D_PREC_LMP_FP32 or 0 (U itself, float64).  A
+ * problem finalized with WC4D_PREC_LMP_FP16 gets the float32 copy instead when the
+ * float16 copy's Gram defect ||U~^T U~ - I||_F exceeds half of theta_max^{-1/2} (the
+ * smallest eigenvalue of C for an orthonormal U), so that C stays positive definite. */
+int wc4d_lmp_copy_format(wc4d_lmp L, int* prec_flag);
 /* Frees L.  wc4d_destroy(p) releases the device memory of the LMPs still alive on p;
  * their handles then accept only wc4d_lmp_destroy (other calls return WC4D_ESTATE). */
 int wc4d_lmp_destroy(wc4d_lmp L);

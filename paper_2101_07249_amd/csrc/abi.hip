@@ -293,8 +293,10 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (p->finalized) return fail(p, WC4D_ESTATE, "already finalized");
   if (p->model < 0) return fail(p, WC4D_ESTATE, "no model set");
   if (!p->haveB || !p->haveQ) return fail(p, WC4D_ESTATE, "B^{1/2} and Q^{1/2} must be set");
-  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32 | WC4D_PREC_SKETCH_FP16X3))
+  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32 | WC4D_PREC_SKETCH_FP16X3 | WC4D_PREC_LMP_FP16))
     return fail(p, WC4D_EINVAL, "unknown precision flags");
+  if ((prec_mode & WC4D_PREC_LMP_FP32) && (prec_mode & WC4D_PREC_LMP_FP16))
+    return fail(p, WC4D_EINVAL, "WC4D_PREC_LMP_FP32 and WC4D_PREC_LMP_FP16 exclude each other");
   if ((prec_mode & WC4D_PREC_SKETCH_BF16X3) && (prec_mode & WC4D_PREC_SKETCH_FP16X3))
     return fail(p, WC4D_EINVAL, "WC4D_PREC_SKETCH_BF16X3 and WC4D_PREC_SKETCH_FP16X3 exclude each other");
   DevGuard g(p->device);
@@ -661,7 +663,8 @@ void wc4d::lmp_release(wc4d_lmp L) {
   dev_free(&L->wsv);
   dev_free(&L->GU);
   dev_free(&L->fu);
-  dev_free(&L->U32);
+  dev_free(&L->Up);
+  dev_free(&L->cexp);
 }
 
 int wc4d::ensure_build(wc4d_problem p, int m) {
@@ -835,25 +838,58 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
                                             : "Cholesky met a non-positive pivot (rank-deficient sketch?)") +
                             (p->cholShift ? " after shifted CholeskyQR3" : "")));
   // U^T U of the U the PCG streams, for the fused recursion (identity up to rounding
-  // for an orthonormal U; computed from the float32 copy when there is one)
+  // for an orthonormal U; computed from the values of the panel copy when there is one)
   if ((rc = dev_alloc(p, &L->GU, (size_t)k_r * k_r))) return cleanup(rc);
   if ((rc = dev_alloc(p, &L->fu, (size_t)3 * k_r))) return cleanup(rc);
   if ((rc = ensure_gram(p, gram_ws_doubles(k_r, k_r, nA)))) return cleanup(rc);
-  const double* Ug = L->U;
-  if (p->prec & WC4D_PREC_LMP_FP32) {
-    // panel-major float32 copy for the PCG passes; the build's scratch block B_ (n_A x m
-    // doubles) receives the rounded values column-major for the Gram (rows n_A .. ldu of
-    // it are never read)
-    if ((rc = dev_alloc(p, &L->U32, lmp_panel_floats(nA, k_r)))) return cleanup(rc);
-    if (L->ldu * k_r > (nA + 4) * m) return cleanup(fail(p, WC4D_EHIP, "float32 copy of U: scratch too small"));
-    he = lmp_to_panels(L->U32, L->U, L->ldu, nA, k_r, B_, s);
-    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, "float32 copy of U failed"));
-    Ug = B_;
+  // panel-major float32 or float16 copy for the PCG passes; the build's scratch block B_
+  // (n_A x m doubles) receives the rounded values column-major for the Gram (rows n_A .. ldu
+  // of it are never read)
+  auto make_copy = [&](LmpFmt fmt) -> int {
+    dev_free(&L->Up);
+    dev_free(&L->cexp);
+    L->ufmt = fmt;
+    const double* Ug = L->U;
+    if (fmt != LMP_F64) {
+      if (L->ldu * k_r > (nA + 4) * m) return fail(p, WC4D_EHIP, "panel copy of U: scratch too small");
+      int r;
+      if (fmt == LMP_P16) {
+        _Float16* P16 = nullptr;
+        if ((r = dev_alloc(p, &P16, lmp_panel_elems(nA, k_r)))) return r;
+        L->Up = P16;
+        if ((r = dev_alloc(p, &L->cexp, (size_t)k_r))) return r;
+        he = lmp_to_panels16(P16, L->cexp, L->U, L->ldu, nA, k_r, B_, s);
+      } else {
+        float* P32 = nullptr;
+        if ((r = dev_alloc(p, &P32, lmp_panel_elems(nA, k_r)))) return r;
+        L->Up = P32;
+        he = lmp_to_panels(P32, L->U, L->ldu, nA, k_r, B_, s);
+      }
+      if (he != hipSuccess) return fail(p, WC4D_EHIP, "panel copy of U failed");
+      Ug = B_;
+    }
+    he = gram_f64(k_r, k_r, nA, Ug, plain_cols(L->ldu), Ug, plain_cols(L->ldu), L->GU, k_r, p->wsGram,
+                  nullptr, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return fail(p, WC4D_EHIP, hipGetErrorString(he));
+    return WC4D_OK;
+  };
+  const LmpFmt want = (p->prec & WC4D_PREC_LMP_FP16) ? LMP_P16 : (p->prec & WC4D_PREC_LMP_FP32) ? LMP_P32 : LMP_F64;
+  if ((rc = make_copy(want))) return cleanup(rc);
+  if (want == LMP_P16) {
+    // C = I + Ũ diag(d) Ũ^T with d_i = theta_i^{-1/2} - 1 > -1 has smallest eigenvalue at
+    // least 1 + d_min (1 + ||Ũ^T Ũ - I||_2) (1 + d_min for an orthonormal U).  Keep the
+    // float16 copy while its Gram defect (Frobenius bound) is at most half of 1 + d_min,
+    // so C stays positive definite with at least half its exact smallest eigenvalue;
+    // otherwise stream the float32 copy.
+    double chk[2] = {0.0, 0.0};
+    he = lmp_copy_check(k_r, L->GU, L->dcoef, L->fu, s);
+    if (he == hipSuccess) he = hipMemcpyAsync(chk, L->fu, sizeof chk, hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    const double dmin = chk[1] < 0.0 ? chk[1] : 0.0;
+    if (!(chk[0] <= 0.5 * (1.0 + dmin)) && (rc = make_copy(LMP_P32))) return cleanup(rc);
   }
-  he = gram_f64(k_r, k_r, nA, Ug, plain_cols(L->ldu), Ug, plain_cols(L->ldu), L->GU, k_r, p->wsGram,
-                nullptr, s);
-  if (he == hipSuccess) he = hipStreamSynchronize(s);
-  if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   *out = L;
   return WC4D_OK;
 }
@@ -889,6 +925,13 @@ int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s) {
   return WC4D_OK;
 }
 
+int wc4d_lmp_copy_format(wc4d_lmp L, int* prec_flag) {
+  if (L == nullptr || prec_flag == nullptr) return WC4D_EINVAL;
+  if (L->p == nullptr) return WC4D_ESTATE;
+  *prec_flag = L->Up == nullptr ? 0 : (L->ufmt == LMP_P16 ? WC4D_PREC_LMP_FP16 : WC4D_PREC_LMP_FP32);
+  return WC4D_OK;
+}
+
 int wc4d_lmp_applies(wc4d_lmp L, int* count) {
   if (L == nullptr || count == nullptr) return WC4D_EINVAL;
   *count = L->applies;
@@ -910,18 +953,15 @@ int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long l
       if ((rc = dev_alloc(p, &L->wsv, need))) return rc;
       L->wsvDoubles = need;
     }
-    const bool u32 = L->U32 != nullptr;
-    const void* Us = u32 ? (const void*)L->U32 : (const void*)L->U;
-    const double ub = (u32 ? 4.0 : 8.0) * (double)L->nA * L->k, fl = 2.0 * (double)L->nA * L->k;
+    const LmpU Us = L->streamed();
+    const double ub = lmp_elem_bytes(Us.fmt) * (double)L->nA * L->k, fl = 2.0 * (double)L->nA * L->k;
     for (int c = 0; c < m; ++c) {
       {
         ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * L->nA, fl);
-        HIPCHK(p, lmp_gemv_t(L->nA, L->k, Us, u32, L->ldu, L->dcoef, X + (size_t)c * ldx, L->wsv,
-                             skip, s));
+        HIPCHK(p, lmp_gemv_t(L->nA, L->k, Us, L->dcoef, X + (size_t)c * ldx, L->wsv, skip, s));
       }
       ProfScope ps(p, s, PROF_LMP_N, ub + 16.0 * L->nA, fl);
-      HIPCHK(p, lmp_gemv_n(L->nA, L->k, Us, u32, L->ldu, X + (size_t)c * ldx, Y + (size_t)c * ldy,
-                           L->wsv, skip, s));
+      HIPCHK(p, lmp_gemv_n(L->nA, L->k, Us, X + (size_t)c * ldx, Y + (size_t)c * ldy, L->wsv, skip, s));
     }
     return WC4D_OK;
   }
@@ -1022,13 +1062,13 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
   double* u = nullptr;
   double* d12 = nullptr;
   double* tvec = nullptr;
-  const bool u32 = L != nullptr && L->U32 != nullptr;
-  const void* Us = (L == nullptr) ? nullptr : (u32 ? (const void*)L->U32 : (const void*)L->U);
+  const LmpU Us = (L == nullptr) ? LmpU() : L->streamed();
+  const bool panels = Us.fmt != LMP_F64;
   if (fused) {
     u = L->fu;
     d12 = L->fu + L->k;
     tvec = L->wsv + lmp_gemv_t_offset(nA, L->k);
-    HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, nullptr, s, u));
+    HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, r, L->wsv, nullptr, s, u));
   }
   // The host enqueues chunks of `poll` iterations and reads the device state after each
   // chunk; the next chunk is already enqueued while it waits (two pinned copies of the
@@ -1040,24 +1080,23 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
    while (pending < 2 && it < opts->maxit) {
     const int chunk = std::min(poll, opts->maxit - it);
     for (int c = 0; c < chunk; ++c) {
-      if (fused && u32) {
+      if (fused && panels) {
         // after the operator: U^T Ap (+ p.Ap) and its partials' sum, coefficients (+ alpha),
         // the dual pass (+ x, s), beta (+ the refresh decision), p, the refresh of u = U^T r
-        const double ub = 4.0 * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
+        const double ub = lmp_elem_bytes(Us.fmt) * (double)nA * L->k, fl = 2.0 * (double)nA * L->k;
         if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
         {
           ProfScope ps(p, s, PROF_LMP_T, ub + 16.0 * nA, fl + 2.0 * nA);
-          HIPCHK(p, lmp_pan_t_partials(nA, L->k, L->U32, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
+          HIPCHK(p, lmp_pan_t_partials(nA, L->k, Us, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
         }
-        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), tvec, p->pcgRed, L->dcoef, L->GU, u,
-                                     d12, s));
+        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), tvec, p->pcgRed, L->dcoef,
+                                     L->GU, u, d12, s));
         {
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 9.0 * nA, 2.0 * fl);
-          HIPCHK(p, pcg_lmp_dual_pan(st, nA, L->k, L->U32, d12, Ap, r, z, x, sres, b, pv, p->pcgRed, p->pcgHist,
-                                     s));
+          HIPCHK(p, pcg_lmp_dual_pan(st, nA, L->k, Us, d12, Ap, r, z, x, sres, b, pv, p->pcgRed, p->pcgHist, s));
         }
         HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
-        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, r, L->wsv, &st->no_refresh, s, u));
         continue;
       }
       if (fused) {
@@ -1067,7 +1106,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
         HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
         {
           ProfScope ps(p, s, PROF_LMP_T, ub + 8.0 * nA, fl);
-          HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, Ap, L->wsv, done, s));
+          HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, Ap, L->wsv, done, s));
         }
         HIPCHK(p, pcg_lmp_coeffs(st, L->k, tvec, L->dcoef, L->GU, u, d12, s));
         {
@@ -1076,7 +1115,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
         }
         HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
         // u = U^T r recomputed exactly when beta's kernel decided so (no_refresh = 0)
-        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, u32, L->ldu, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, r, L->wsv, &st->no_refresh, s, u));
         continue;
       }
       if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;

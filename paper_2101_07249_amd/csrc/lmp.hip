@@ -8,10 +8,11 @@
 // columns and a long run of rows, each thread keeps 32 accumulators and reduces once.
 // x + U t: a thread owns 4 rows and streams the columns 8 at a time.
 //
-// The float32 copy the PCG streams is panel-major instead: panel p holds rows
+// The float32 or float16 copy the PCG streams is panel-major instead: panel p holds rows
 // [256 p, 256 p + 256) of all k columns, column-major with leading dimension 256, at
 // offset 256 k p, and rows at or past n_A are zero.  A workgroup working on one panel
-// reads one contiguous 1 KB x k block.  Measured on MI355X at n_A = 413,696, k = 251:
+// reads one contiguous block (1 KB or 512 bytes per column).  The float16 copy scales
+// each column by a power of two (exact), undone in the coefficients the passes apply.  Measured on MI355X at n_A = 413,696, k = 251:
 // U^T x 73 us (5.7 TB/s) and the fused PCG pass 78 us (5.5 TB/s), against 77 us and
 // 144 us for the same passes over a column-major copy (a plain read of the 415 MB runs
 // at 6.3 TB/s).
@@ -28,10 +29,10 @@ constexpr int kTU = 1;    // row unroll (U^T x pass)
 
 static inline long long lmp_chunks(long long nA) { return (nA + kLRows - 1) / kLRows; }
 
-size_t lmp_panel_floats(long long nA, int k) { return (size_t)lmp_panels(nA) * kPanel * k; }
+size_t lmp_panel_elems(long long nA, int k) { return (size_t)lmp_panels(nA) * kPanel * k; }
 
-// U^T x over panels: grid (column groups of kPG) x (splits of pan_per consecutive panels);
-// about 1024 workgroups.
+// U^T x over panels (either precision): grid (column groups of kPG) x (splits of pan_per
+// consecutive panels); about 1024 workgroups.
 constexpr int kPG = 16;
 static inline long long pan_t_per(long long nA, int k) {
   const long long np = lmp_panels(nA);
@@ -59,8 +60,7 @@ static inline int lmp_t_splits(long long nA, int k) {
 
 // partials of either layout, then t
 static inline int t_splits_max(long long nA, int k) {
-  const int a = lmp_t_splits(nA, k), b = pan_t_splits(nA, k);
-  return a > b ? a : b;
+  return std::max(lmp_t_splits(nA, k), pan_t_splits(nA, k));
 }
 size_t lmp_gemv_ws_doubles(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k + k; }
 size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k; }
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_n(long long nA, int k, const T
 }
 
 
-// ------------------------------------------------ float32 panel copy
+// ------------------------------------------------ panel copies
 
 // P = panels of (float)U; Uround (optional, column-major with ldu) = (double)(float)U,
 // the values the passes over P see.
@@ -216,6 +216,79 @@ hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA,
                          double* Uround, hipStream_t s) {
   hipLaunchKernelGGL(k_lmp_to_panels, dim3(4096), dim3(256), 0, s, U, ldu, nA, k, lmp_panels(nA), P,
                      Uround);
+  return hipGetLastError();
+}
+
+// cexp[c] = ilogb(max_i |U_ic|) - 14 (0 for a zero column): one workgroup per column.
+__global__ __launch_bounds__(256) void k_lmp_col_exp(const double* __restrict__ U, long long ldu, long long nA,
+                                                     int k, int* __restrict__ cexp) {
+  __shared__ double sh[256];
+  for (int c = blockIdx.x; c < k; c += gridDim.x) {
+    double m = 0.0;
+    for (long long i = threadIdx.x; i < nA; i += 256) m = fmax(m, fabs(U[c * ldu + i]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) cexp[c] = sh[0] > 0.0 ? ilogb(sh[0]) - 14 : 0;
+    __syncthreads();
+  }
+}
+
+__global__ void k_lmp_to_panels16(const double* __restrict__ U, long long ldu, long long nA, int k,
+                                  long long npan, const int* __restrict__ cexp, _Float16* __restrict__ P,
+                                  double* __restrict__ Uround) {
+  const long long total = npan * kPanel * k;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long rr = t % kPanel, c = (t / kPanel) % k, pn = t / ((long long)kPanel * k);
+    const long long i = pn * kPanel + rr;
+    const int e = cexp[c];
+    const _Float16 h = i < nA ? (_Float16)ldexp(U[c * ldu + i], -e) : (_Float16)0.0f;
+    P[t] = h;
+    if (Uround != nullptr && i < nA) Uround[c * ldu + i] = ldexp((double)h, e);
+  }
+}
+
+hipError_t lmp_to_panels16(_Float16* P, int* cexp, const double* U, long long ldu, long long nA, int k,
+                           double* Uround, hipStream_t s) {
+  hipLaunchKernelGGL(k_lmp_col_exp, dim3(k), dim3(256), 0, s, U, ldu, nA, k, cexp);
+  hipLaunchKernelGGL(k_lmp_to_panels16, dim3(4096), dim3(256), 0, s, U, ldu, nA, k, lmp_panels(nA), cexp, P,
+                     Uround);
+  return hipGetLastError();
+}
+
+// out[0] = ||GU - I||_F, out[1] = min(0, min_i dcoef_i): one workgroup.
+__global__ __launch_bounds__(256) void k_lmp_copy_check(int k, const double* __restrict__ GU,
+                                                        const double* __restrict__ dcoef, double* __restrict__ out) {
+  __shared__ double sa[256], sb[256];
+  double a = 0.0, b = 0.0;
+  for (long long t = threadIdx.x; t < (long long)k * k; t += 256) {
+    const long long i = t % k, j = t / k;
+    const double v = GU[t] - (i == j ? 1.0 : 0.0);
+    a += v * v;
+  }
+  for (int i = threadIdx.x; i < k; i += 256) b = fmin(b, dcoef[i]);
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] = fmin(sb[threadIdx.x], sb[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(sa[0]);
+    out[1] = sb[0];
+  }
+}
+
+hipError_t lmp_copy_check(int k, const double* GU, const double* dcoef, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_lmp_copy_check, dim3(1), dim3(256), 0, s, k, GU, dcoef, out);
   return hipGetLastError();
 }
 
@@ -285,32 +358,124 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
   }
 }
 
+// The same over the float16 copy: a thread takes R adjacent rows (one 2R-byte load per
+// column), kPanel / R threads a panel, so the block works on R panels side by side; a
+// column's sum is scaled back by 2^cexp[c].  Used with R = 2, PG = 16 (inside the PCG at
+// n_A = 413,696, k = 251: 57 us per pass; 4 rows x 16 columns ran the same, 4 x 8 and
+// 8 x 8 slower at 66 and 85 us).
+template <int R, int PG>
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial16(long long nA, int k, long long pan_per,
+                                                                const _Float16* __restrict__ P,
+                                                                const int* __restrict__ cexp,
+                                                                const double* __restrict__ x,
+                                                                double* __restrict__ part,
+                                                                const int* __restrict__ skip,
+                                                                const double* __restrict__ pdot,
+                                                                double* __restrict__ dotpart) {
+  typedef _Float16 hv __attribute__((ext_vector_type(R)));
+  constexpr int TPP = kPanel / R;  // threads per panel
+  __shared__ double sh[kPanel / 64][PG];
+  __shared__ double shd[kPanel / 64];
+  if (skip != nullptr && *skip != 0) return;
+  const bool dot = pdot != nullptr && blockIdx.x == 0;
+  double dv = 0.0;
+  const int c0 = blockIdx.x * PG;
+  const int split = blockIdx.y;
+  const long long np = lmp_panels(nA);
+  const long long pb = (long long)split * pan_per;
+  long long pe = pb + pan_per;
+  if (pe > np) pe = np;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = threadIdx.x / TPP, rr = R * (threadIdx.x % TPP);
+  int col[PG];
+#pragma unroll
+  for (int c = 0; c < PG; ++c) col[c] = (c0 + c < k ? c0 + c : 0) * kPanel;
+  double acc[PG];
+#pragma unroll
+  for (int c = 0; c < PG; ++c) acc[c] = 0.0;
+  for (long long pn = pb + sub; pn < pe; pn += R) {
+    const long long i = pn * kPanel + rr;
+    double xv[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) xv[e] = i + e < nA ? x[i + e] : 0.0;
+    if (dot) {
+#pragma unroll
+      for (int e = 0; e < R; ++e)
+        if (i + e < nA) dv += pdot[i + e] * xv[e];
+    }
+    const _Float16* Pp = P + (size_t)pn * kPanel * k + rr;
+#pragma unroll
+    for (int c = 0; c < PG; ++c) {
+      const hv u = *reinterpret_cast<const hv*>(Pp + col[c]);
+      double a = 0.0;
+#pragma unroll
+      for (int e = 0; e < R; ++e) a += (double)(float)u[e] * xv[e];
+      acc[c] += a;
+    }
+  }
+  if (dot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dv += __shfl_down(dv, o, 64);
+    if (lane == 0) shd[wave] = dv;
+  }
+#pragma unroll
+  for (int c = 0; c < PG; ++c) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int c = 0; c < PG; ++c) sh[wave][c] = acc[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < PG && c0 + (int)threadIdx.x < k) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPanel / 64; ++w) sum += sh[w][threadIdx.x];
+    part[(size_t)split * k + c0 + threadIdx.x] = ldexp(sum, cexp[c0 + threadIdx.x]);
+  }
+  if (dot && threadIdx.x == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPanel / 64; ++w) sum += shd[w];
+    dotpart[split] = sum;
+  }
+}
+
 // y = x + U t over panels: wave w of a 256-thread block takes columns w, w + 4, ...
-// (two in flight), a lane holds 4 rows of the panel; the four waves' sums meet in LDS.
-__global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const float* __restrict__ P,
+// (CU in flight: 2 float32 columns of 16-byte loads, 4 float16 columns of 8-byte loads), a
+// lane holds 4 rows of the panel; the four waves' sums meet in LDS.
+template <typename T, int CU>
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const T* __restrict__ P,
+                                                      const int* __restrict__ cexp,
                                                       const double* __restrict__ t,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ y,
                                                       const int* __restrict__ skip) {
   extern __shared__ double sm[];
-  double* ts = sm;           // k coefficients
+  double* ts = sm;           // k coefficients (times 2^cexp for float16)
   double* red = sm + k;      // [4 waves][256 rows]
   if (skip != nullptr && *skip != 0) return;
-  for (int c = threadIdx.x; c < k; c += kPanel) ts[c] = t[c];
+  for (int c = threadIdx.x; c < k; c += kPanel) ts[c] = cexp != nullptr ? ldexp(t[c], cexp[c]) : t[c];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long np = lmp_panels(nA);
   for (long long pn = blockIdx.x; pn < np; pn += gridDim.x) {
-    const float* Pp = P + (size_t)pn * kPanel * k + 4 * lane;
+    const T* Pp = P + (size_t)pn * kPanel * k + 4 * lane;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c0 = wave; c0 < k; c0 += 8) {
-      const int c1 = c0 + 4;
-      const float4 u0 = *reinterpret_cast<const float4*>(Pp + (size_t)c0 * kPanel);
-      const float4 u1 = c1 < k ? *reinterpret_cast<const float4*>(Pp + (size_t)c1 * kPanel)
-                               : make_float4(0.f, 0.f, 0.f, 0.f);
-      const double t0 = ts[c0], t1 = c1 < k ? ts[c1] : 0.0;
-      a[0] += u0.x * t0; a[1] += u0.y * t0; a[2] += u0.z * t0; a[3] += u0.w * t0;
-      a[0] += u1.x * t1; a[1] += u1.y * t1; a[2] += u1.z * t1; a[3] += u1.w * t1;
+    for (int c0 = wave; c0 < k; c0 += 4 * CU) {
+      float4 u[CU];
+      double tc[CU];
+#pragma unroll
+      for (int j = 0; j < CU; ++j) {
+        const int c = c0 + 4 * j;
+        u[j] = c < k ? pan_ld4(Pp + (size_t)c * kPanel) : make_float4(0.f, 0.f, 0.f, 0.f);
+        tc[j] = c < k ? ts[c] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < CU; ++j) {
+        a[0] += u[j].x * tc[j]; a[1] += u[j].y * tc[j]; a[2] += u[j].z * tc[j]; a[3] += u[j].w * tc[j];
+      }
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) red[wave * kPanel + 4 * lane + e] = a[e];
@@ -326,11 +491,24 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const
 
 int lmp_pan_t_splits(long long nA, int k) { return pan_t_splits(nA, k); }
 
-hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
-                              double* ws, double* dotpart, const int* skip, hipStream_t s) {
+// partials of U^T x over the panel copy (either precision); returns the split count
+static int launch_pan_t_partial(long long nA, int k, const LmpU& U, const double* x, double* part,
+                                const int* skip, const double* pdot, double* dotpart, hipStream_t s) {
   const int sp = pan_t_splits(nA, k);
-  hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
-                     pan_t_per(nA, k), P, x, ws, skip, pdot, dotpart);
+  const dim3 grid((k + kPG - 1) / kPG, sp);
+  if (U.fmt == LMP_P16)
+    hipLaunchKernelGGL((k_lmp_pan_t_partial16<2, kPG>), grid, dim3(kPanel), 0, s, nA, k, pan_t_per(nA, k),
+                       (const _Float16*)U.p, U.cexp, x, part, skip, pdot, dotpart);
+  else
+    hipLaunchKernelGGL(k_lmp_pan_t_partial, grid, dim3(kPanel), 0, s, nA, k, pan_t_per(nA, k), (const float*)U.p, x,
+                       part, skip, pdot, dotpart);
+  return sp;
+}
+
+hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
+                              double* ws, double* dotpart, const int* skip, hipStream_t s) {
+  if (U.fmt == LMP_F64) return hipErrorInvalidValue;
+  const int sp = launch_pan_t_partial(nA, k, U, x, ws, skip, pdot, dotpart, s);
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, ws, nullptr,
                      ws + lmp_gemv_t_offset(nA, k), skip);
   return hipGetLastError();
@@ -343,39 +521,42 @@ int lmp_panel_grid(long long nA) {
   return (int)((np + per - 1) / per);
 }
 
-hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
-                      const double* dcoef, const double* x, double* ws, const int* skip,
-                      hipStream_t s, double* tout) {
+hipError_t lmp_gemv_t(long long nA, int k, const LmpU& U, const double* dcoef, const double* x, double* ws,
+                      const int* skip, hipStream_t s, double* tout) {
   double* part = ws;
   double* t = (tout != nullptr) ? tout : ws + lmp_gemv_t_offset(nA, k);
   int sp;
-  if (u32) {
-    sp = pan_t_splits(nA, k);
-    hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
-                       pan_t_per(nA, k), (const float*)U, x, part, skip, nullptr, nullptr);
+  if (U.fmt != LMP_F64) {
+    sp = launch_pan_t_partial(nA, k, U, x, part, skip, nullptr, nullptr, s);
   } else {
     sp = lmp_t_splits(nA, k);
     const long long rows_per = (nA + sp - 1) / sp;
     hipLaunchKernelGGL(k_lmp_gemv_t_partial<double>, dim3((k + kTG - 1) / kTG, sp), dim3(kLT), 0, s, nA,
-                       k, rows_per, (const double*)U, ldu, x, part, skip);
+                       k, rows_per, (const double*)U.p, U.ldu, x, part, skip);
   }
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, part, dcoef, t,
                      skip);
   return hipGetLastError();
 }
 
-hipError_t lmp_gemv_n(long long nA, int k, const void* U, bool u32, long long ldu, const double* x,
-                      double* y, const double* ws, const int* skip, hipStream_t s) {
+hipError_t lmp_gemv_n(long long nA, int k, const LmpU& U, const double* x, double* y, const double* ws,
+                      const int* skip, hipStream_t s) {
   const double* t = ws + lmp_gemv_t_offset(nA, k);
-  if (u32) {
-    hipLaunchKernelGGL(k_lmp_pan_n, dim3(lmp_panel_grid(nA)), dim3(kPanel),
-                       sizeof(double) * (k + 4 * kPanel), s, nA, k, (const float*)U, t, x, y, skip);
+  const size_t lds = sizeof(double) * (k + 4 * kPanel);
+  if (U.fmt == LMP_P16) {
+    hipLaunchKernelGGL((k_lmp_pan_n<_Float16, 4>), dim3(lmp_panel_grid(nA)), dim3(kPanel), lds, s, nA, k,
+                       (const _Float16*)U.p, U.cexp, t, x, y, skip);
     return hipGetLastError();
   }
-  if (ldu % 4 != 0) return hipErrorInvalidValue;
+  if (U.fmt == LMP_P32) {
+    hipLaunchKernelGGL((k_lmp_pan_n<float, 2>), dim3(lmp_panel_grid(nA)), dim3(kPanel), lds, s, nA, k,
+                       (const float*)U.p, (const int*)nullptr, t, x, y, skip);
+    return hipGetLastError();
+  }
+  if (U.ldu % 4 != 0) return hipErrorInvalidValue;
   const long long nch = (nA + 4LL * kLT - 1) / (4LL * kLT);
   hipLaunchKernelGGL(k_lmp_gemv_n<double>, dim3((unsigned)nch), dim3(kLT), sizeof(double) * k, s,
-                       nA, k, (const double*)U, ldu, t, x, y, skip);
+                       nA, k, (const double*)U.p, U.ldu, t, x, y, skip);
   return hipGetLastError();
 }
 

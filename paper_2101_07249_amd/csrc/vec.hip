@@ -495,12 +495,29 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual(const PcgState* __restrict
 }
 
 
-// Dual pass over the float32 panel copy of U: wave w of a 256-thread block takes
-// columns w, w + 4, ... (two in flight), a lane holds 4 rows of the panel, and the four
-// waves' sums of U d1 and U d2 meet in LDS; thread q then updates row q of the panel.
-// Blocks own panels blockIdx.x, + gridDim.x, ...; block 0 clears the r.r partial slots
-// of blocks that do not exist (gridDim.x .. kRB).
-// ------------------------------- fused LMP inside PCG, float32 panel copy of U
+// ------------------------------- fused LMP inside PCG, panel copy of U
+
+// Row i of the dual pass: r -= alpha (Ap + w), z = r + zz, x += alpha p, s -= alpha Ap
+// (the true residual), with the partials of r.r, s.s and x.(b + s).
+static __device__ inline void pcg_dual_row(long long i, double alpha, double w, double zz,
+                                           const double* __restrict__ Ap, double* __restrict__ r,
+                                           double* __restrict__ z, double* __restrict__ x,
+                                           double* __restrict__ sr, const double* __restrict__ b,
+                                           const double* __restrict__ p, double& vsum, double& vs,
+                                           double& vj) {
+  const double api = Ap[i];
+  const double rn = r[i] - alpha * (api + w);
+  r[i] = rn;
+  z[i] = rn + zz;
+  vsum += rn * rn;
+  const double xi = x[i] + alpha * p[i];
+  const double si = sr[i] - alpha * api;
+  x[i] = xi;
+  sr[i] = si;
+  vs += si * si;
+  vj += xi * (b[i] + si);
+}
+
 // After the U^T Ap pass and the fixed-order sum of its partials into t: p.Ap from that
 // pass's partials (every block sums them in the same order, block 0 records pAp and
 // alpha), d1 = dcoef .* t, and for 8 rows c per block (32 threads each)
@@ -578,6 +595,11 @@ hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* t, cons
 
 double* pcg_dot_slots(double* red) { return red + 3 * kRB; }
 
+// Dual pass over the float32 panel copy of U: wave w of a 256-thread block takes
+// columns w, w + 4, ... (two in flight), a lane holds 4 rows of the panel, and the four
+// waves' sums of U d1 and U d2 meet in LDS; thread q then updates row q of the panel.
+// Blocks own panels blockIdx.x, + gridDim.x, ...; block 0 clears the r.r partial slots
+// of blocks that do not exist (gridDim.x .. kRB).
 __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __restrict__ st,
                                                           long long nA, int k,
                                                           const float* __restrict__ P,
@@ -633,18 +655,90 @@ __global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan(const PcgState* __rest
     if (i < nA) {
       const double w = (rw[q] + rw[2 * kPanel + q]) + (rw[4 * kPanel + q] + rw[6 * kPanel + q]);
       const double zz = (rw[kPanel + q] + rw[3 * kPanel + q]) + (rw[5 * kPanel + q] + rw[7 * kPanel + q]);
-      const double api = Ap[i];
-      const double rn = r[i] - alpha * (api + w);
-      r[i] = rn;
-      z[i] = rn + zz;
-      vsum += rn * rn;
-      // x += alpha p, s -= alpha Ap (true residual) with the partials of s.s and x.(b + s)
-      const double xi = x[i] + alpha * p[i];
-      const double si = sr[i] - alpha * api;
-      x[i] = xi;
-      sr[i] = si;
-      vs += si * si;
-      vj += xi * (b[i] + si);
+      pcg_dual_row(i, alpha, w, zz, Ap, r, z, x, sr, b, p, vsum, vs, vj);
+    }
+    __syncthreads();
+  }
+  const double t0 = block_sum(vs, sh);
+  const double t1 = block_sum(vj, sh);
+  const double t2 = block_sum(vsum, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = t0;
+    red[kRB + blockIdx.x] = t1;
+    red[2 * kRB + blockIdx.x] = t2;
+  }
+}
+
+// The same over the float16 copy: a lane holds 8 rows (one 16-byte load per column), a
+// half-wave covers a panel column, so the 8 half-waves g = 2 wave + lane / 32 take columns
+// g, g + 8, ... (two in flight); their sums meet in LDS.  A column's coefficients carry
+// its 2^cexp.  (Measured at n_A = 413,696, k = 251: 42 us, against 53 us for 4 rows per
+// lane.)
+__global__ __launch_bounds__(kRT) void k_pcg_lmp_dual_pan16(const PcgState* __restrict__ st,
+                                                            long long nA, int k,
+                                                            const _Float16* __restrict__ P,
+                                                            const int* __restrict__ cexp,
+                                                            const double* __restrict__ d12,
+                                                            const double* __restrict__ Ap,
+                                                            double* __restrict__ r,
+                                                            double* __restrict__ z,
+                                                            double* __restrict__ red,
+                                                            double* __restrict__ x,
+                                                            double* __restrict__ sr,
+                                                            const double* __restrict__ b,
+                                                            const double* __restrict__ p) {
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  extern __shared__ double sm[];
+  double* sd = sm;             // d1 (k), d2 (k), times 2^cexp
+  double* rw = sm + 2 * k;     // [8 half-waves][2][kPanel rows]
+  __shared__ double sh[16];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  for (int c = threadIdx.x; c < 2 * k; c += kRT) sd[c] = ldexp(d12[c], cexp[c < k ? c : c - k]);
+  if (blockIdx.x == 0)
+    for (int q = (int)gridDim.x + threadIdx.x; q < kRB; q += kRT) {
+      red[q] = 0.0;
+      red[kRB + q] = 0.0;
+      red[2 * kRB + q] = 0.0;
+    }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = 2 * wave + (lane >> 5), r8 = 8 * (lane & 31);
+  const long long np = lmp_panels(nA);
+  double vsum = 0.0, vs = 0.0, vj = 0.0;
+  for (long long pn = blockIdx.x; pn < np; pn += gridDim.x) {
+    const _Float16* Pp = P + (size_t)pn * kPanel * k + r8;
+    double aw[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, az[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = g; c0 < k; c0 += 16) {
+      const int c1 = c0 + 8;
+      const h8 u0 = *reinterpret_cast<const h8*>(Pp + (size_t)c0 * kPanel);
+      const h8 u1 = c1 < k ? *reinterpret_cast<const h8*>(Pp + (size_t)c1 * kPanel) : h8{};
+      const double a0 = sd[c0], b0 = sd[k + c0];
+      const double a1 = c1 < k ? sd[c1] : 0.0, b1 = c1 < k ? sd[k + c1] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double v0 = (double)(float)u0[e], v1 = (double)(float)u1[e];
+        aw[e] += v0 * a0;
+        az[e] += v0 * b0;
+        aw[e] += v1 * a1;
+        az[e] += v1 * b1;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      rw[(2 * g) * kPanel + r8 + e] = aw[e];
+      rw[(2 * g + 1) * kPanel + r8 + e] = az[e];
+    }
+    __syncthreads();
+    const int q = threadIdx.x;
+    const long long i = pn * kPanel + q;
+    if (i < nA) {
+      const double* w0 = rw + q;
+      const double w = ((w0[0] + w0[2 * kPanel]) + (w0[4 * kPanel] + w0[6 * kPanel])) +
+                       ((w0[8 * kPanel] + w0[10 * kPanel]) + (w0[12 * kPanel] + w0[14 * kPanel]));
+      const double zz = ((w0[kPanel] + w0[3 * kPanel]) + (w0[5 * kPanel] + w0[7 * kPanel])) +
+                        ((w0[9 * kPanel] + w0[11 * kPanel]) + (w0[13 * kPanel] + w0[15 * kPanel]));
+      pcg_dual_row(i, alpha, w, zz, Ap, r, z, x, sr, b, p, vsum, vs, vj);
     }
     __syncthreads();
   }
@@ -669,14 +763,20 @@ hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long
   return hipGetLastError();
 }
 
-hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const float* P, const double* d12,
+hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const LmpU& U, const double* d12,
                             const double* Ap, double* r, double* z, double* x, double* sres,
                             const double* b, const double* p, double* red, double* hist, hipStream_t s) {
   static_assert(kPanel == kRT, "one thread per panel row in the row update");
   const int grid = lmp_panel_grid(nA);
   if (grid > kRB) return hipErrorInvalidValue;  // one partial slot per block
-  hipLaunchKernelGGL(k_pcg_lmp_dual_pan, dim3(grid), dim3(kRT), sizeof(double) * (2 * k + 8 * kPanel), s, st,
-                     nA, k, P, d12, Ap, r, z, red, x, sres, b, p);
+  if (U.fmt == LMP_P16)
+    hipLaunchKernelGGL(k_pcg_lmp_dual_pan16, dim3(grid), dim3(kRT), sizeof(double) * (2 * k + 16 * kPanel), s, st,
+                       nA, k, (const _Float16*)U.p, U.cexp, d12, Ap, r, z, red, x, sres, b, p);
+  else if (U.fmt == LMP_P32)
+    hipLaunchKernelGGL(k_pcg_lmp_dual_pan, dim3(grid), dim3(kRT), sizeof(double) * (2 * k + 8 * kPanel), s, st,
+                       nA, k, (const float*)U.p, d12, Ap, r, z, red, x, sres, b, p);
+  else
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
   return hipGetLastError();
 }

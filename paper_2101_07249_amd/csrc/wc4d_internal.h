@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -173,23 +174,45 @@ hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double
 // ws: lmp_gemv_ws_doubles(nA, k).
 size_t lmp_gemv_ws_doubles(long long nA, int k);
 size_t lmp_gemv_t_offset(long long nA, int k);
-// U is float64 column-major (leading dimension ldu), or, when u32 is true, the float32
-// panel-major copy (ldu unused): panel p holds rows [kPanel p, kPanel p + kPanel) of all k
+// The U a pass streams: float64 column-major (leading dimension ldu), or a panel-major
+// copy in float32 or float16: panel p holds rows [kPanel p, kPanel p + kPanel) of all k
 // columns, column-major with leading dimension kPanel, at offset kPanel k p; rows at or
-// past n_A are zero.
+// past n_A are zero.  The float16 copy stores column c as U * 2^-cexp[c], cexp[c] chosen
+// so that the column's largest magnitude lands in [2^14, 2^15).
 constexpr int kPanel = 256;
 __host__ __device__ inline long long lmp_panels(long long nA) { return (nA + kPanel - 1) / kPanel; }
-size_t lmp_panel_floats(long long nA, int k);
+enum LmpFmt { LMP_F64 = 0, LMP_P32 = 1, LMP_P16 = 2 };
+struct LmpU {
+  const void* p = nullptr;
+  LmpFmt fmt = LMP_F64;
+  long long ldu = 0;          // LMP_F64 only
+  const int* cexp = nullptr;  // LMP_P16 only (k)
+};
+inline double lmp_elem_bytes(LmpFmt f) { return f == LMP_P16 ? 2.0 : (f == LMP_P32 ? 4.0 : 8.0); }
+// 4 consecutive panel rows of one column (a 16-byte float32 or 8-byte float16 load)
+__device__ inline float4 pan_ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ inline float4 pan_ld4(const _Float16* p) {
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+  const h4 v = *reinterpret_cast<const h4*>(p);
+  return make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+}
+// elements of a panel copy (either precision)
+size_t lmp_panel_elems(long long nA, int k);
 // blocks of a pass over all panels (at most 1024, an equal panel count each but the last)
 int lmp_panel_grid(long long nA);
 // P = panel copy of (float)U; Uround (optional, column-major, ldu) = (double)(float)U.
 hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA, int k,
                          double* Uround, hipStream_t s);
-hipError_t lmp_gemv_t(long long nA, int k, const void* U, bool u32, long long ldu,
-                      const double* dcoef, const double* x, double* ws, const int* skip,
-                      hipStream_t s, double* tout = nullptr);
-hipError_t lmp_gemv_n(long long nA, int k, const void* U, bool u32, long long ldu, const double* x,
-                      double* y, const double* ws, const int* skip, hipStream_t s);
+// P = float16 panel copy of U with column exponents cexp (k ints, written here); Uround as
+// above with the values the float16 copy represents.
+hipError_t lmp_to_panels16(_Float16* P, int* cexp, const double* U, long long ldu, long long nA, int k,
+                           double* Uround, hipStream_t s);
+// out[0] = ||GU - I||_F and out[1] = min(0, min_i dcoef_i) (2 device doubles).
+hipError_t lmp_copy_check(int k, const double* GU, const double* dcoef, double* out, hipStream_t s);
+hipError_t lmp_gemv_t(long long nA, int k, const LmpU& U, const double* dcoef, const double* x, double* ws,
+                      const int* skip, hipStream_t s, double* tout = nullptr);
+hipError_t lmp_gemv_n(long long nA, int k, const LmpU& U, const double* x, double* y, const double* ws,
+                      const int* skip, hipStream_t s);
 
 // Vector kernels for PCG and the LMP (n_A long).
 struct PcgState {
@@ -221,18 +244,18 @@ hipError_t pcg_lmp_coeffs(const PcgState* st, int k, const double* t, const doub
 hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long long ldu,
                         const double* d12, const double* Ap, double* r, double* z, double* red,
                         double* hist, hipStream_t s);
-// Float32 panel copy: one U^T Ap pass that also sums p.Ap (lmp_pan_t_partials with pdot = p,
-// dotpart = pcg_dot_slots(red); t = U^T Ap left at ws + lmp_gemv_t_offset), then
-// pcg_lmp_coeffs_pan (p.Ap -> alpha, u, d12), then the dual pass that also updates x and s
-// (the true residual) and ends with beta.
+// Panel copy (either precision): one U^T Ap pass that also sums p.Ap (lmp_pan_t_partials
+// with pdot = p, dotpart = pcg_dot_slots(red); t = U^T Ap left at ws + lmp_gemv_t_offset),
+// then pcg_lmp_coeffs_pan (p.Ap -> alpha, u, d12; sp = lmp_pan_t_splits), then the dual
+// pass that also updates x and s (the true residual) and ends with beta.
 int lmp_pan_t_splits(long long nA, int k);
-hipError_t lmp_pan_t_partials(long long nA, int k, const float* P, const double* x, const double* pdot,
+hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
                               double* ws, double* dotpart, const int* skip, hipStream_t s);
 double* pcg_dot_slots(double* red);
 hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* t, const double* red,
                               const double* dcoef, const double* GU, double* u, double* d12,
                               hipStream_t s);
-hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const float* P, const double* d12,
+hipError_t pcg_lmp_dual_pan(PcgState* st, long long nA, int k, const LmpU& U, const double* d12,
                             const double* Ap, double* r, double* z, double* x, double* sres,
                             const double* b, const double* p, double* red, double* hist, hipStream_t s);
 hipError_t vec_scale_rows(double* T, int k, int m, int ldt, const double* dcoef, const int* skip,
@@ -396,7 +419,7 @@ struct wc4d_problem_s {
 struct wc4d_lmp_s {
   wc4d_problem p = nullptr;  // null once the problem has been destroyed
   long long nA = 0;
-  long long ldu = 0;        // leading dimension of U and U32: n_A rounded up to 4
+  long long ldu = 0;        // leading dimension of U: n_A rounded up to 4
   int k = 0;
   int applies = 0;
   double* U = nullptr;      // n_A x k
@@ -408,7 +431,18 @@ struct wc4d_lmp_s {
   size_t wsDoubles = 0;
   double* wsv = nullptr;    // single-vector workspace
   size_t wsvDoubles = 0;
-  float* U32 = nullptr;     // float32 panel copy of U (WC4D_PREC_LMP_FP32), see kPanel
+  void* Up = nullptr;       // panel copy of U (WC4D_PREC_LMP_FP32 / _FP16), see kPanel
+  wc4d::LmpFmt ufmt = wc4d::LMP_F64;  // format of the U the PCG streams
+  int* cexp = nullptr;      // float16 copy: column exponents (k)
   double* GU = nullptr;     // k x k: U^T U of the U the PCG streams
   double* fu = nullptr;     // 3 k: u = U^T r, d1, d2 (fused PCG)
+  // the U the passes stream: the panel copy when there is one, else U itself
+  wc4d::LmpU streamed() const {
+    wc4d::LmpU u;
+    u.p = (Up != nullptr) ? (const void*)Up : (const void*)U;
+    u.fmt = (Up != nullptr) ? ufmt : wc4d::LMP_F64;
+    u.ldu = ldu;
+    u.cexp = cexp;
+    return u;
+  }
 };

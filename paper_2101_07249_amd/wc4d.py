@@ -26,7 +26,7 @@ REVD, NYSTROM, RITZIT = 0, 1, 2
 METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
 RES_TRUE, RES_PRECOND = 0, 1
 PCG_FUSED, PCG_PLAIN = 0, 1
-PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32, PREC_SKETCH_FP16X3 = 0, 1, 2, 4
+PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32, PREC_SKETCH_FP16X3, PREC_LMP_FP16 = 0, 1, 2, 4, 8
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -74,6 +74,7 @@ _SIGS = {
     "wc4d_lmp_vectors": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
     "wc4d_lmp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_lmp_applies": (ctypes.c_int, [_vp, _c_int_p]),
+    "wc4d_lmp_copy_format": (ctypes.c_int, [_vp, _c_int_p]),
     "wc4d_lmp_destroy": (ctypes.c_int, [_vp]),
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
@@ -223,6 +224,14 @@ class Lmp:
     def applies(self) -> int:
         c = ctypes.c_int(0)
         lib().wc4d_lmp_applies(self._h, ctypes.byref(c))
+        return c.value
+
+    def copy_format(self) -> int:
+        """PREC_LMP_FP16, PREC_LMP_FP32 or 0: the copy of U the passes stream."""
+        c = ctypes.c_int(0)
+        rc = lib().wc4d_lmp_copy_format(self._h, ctypes.byref(c))
+        if rc:
+            raise Wc4dError(rc, "lmp_copy_format")
         return c.value
 
     def close(self):

@@ -62,3 +62,25 @@ def test_revd_rayleigh_quotients_and_pcg_residual(c3):
     res = np.linalg.norm(bo - O.apply_A(op, xo)) / np.linalg.norm(bo)
     assert res <= 1.05e-6, res
     assert abs(res - info["relres_true"]) <= 1e-8
+
+
+def test_mixed_precision_pcg_true_residual(c3):
+    """The benchmark's headline configuration (split-bf16 sketch products, float16 copy of
+    U for the PCG): the solution's true residual from the oracle's float64 operator, and
+    the iteration count against the float64 build's (within 5% + 2)."""
+    import torch
+    from paper_2101_07249_amd import Problem, wc4d
+    gp, op, G, Gd = c3
+    print("[case] full-size mixed pcg", flush=True)
+    gm = Problem.from_workload(C3, obs_pattern(C3), prec=wc4d.PREC_SKETCH_BF16X3 | wc4d.PREC_LMP_FP16)
+    d = torch.from_numpy(innovations(gp.q, C3.seed, np.sqrt(C3.sigma_o2))).to("cuda")
+    xm = torch.zeros(gp.n_A, dtype=torch.float64, device="cuda")
+    im = gm.pcg(gm.rhs(d), xm, gm.lmp_build("nystrom", C3.k_r, C3.l, Gd), tol=1e-6, maxit=3000)
+    xd = torch.zeros(gp.n_A, dtype=torch.float64, device="cuda")
+    idd = gp.pcg(gp.rhs(d), xd, gp.lmp_build("nystrom", C3.k_r, C3.l, Gd), tol=1e-6, maxit=3000)
+    assert im["status"] == 0 and idd["status"] == 0
+    bo = O.rhs(op, innovations(op.q, C3.seed, np.sqrt(C3.sigma_o2)))
+    res = np.linalg.norm(bo - O.apply_A(op, xm.cpu().numpy())) / np.linalg.norm(bo)
+    print("[result] iters mixed", im["iters"], "fp64", idd["iters"], "true res", res, flush=True)
+    assert res <= 1.05e-6, res
+    assert im["iters"] <= 1.05 * idd["iters"] + 2

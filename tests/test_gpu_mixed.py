@@ -135,6 +135,107 @@ def test_fp32_panel_lmp_apply_and_pcg(k_r):
         assert abs(info["iters"] - ro.iters) <= 2
 
 
+@pytest.mark.parametrize("k_r", [1, 3, 17, 33, 40])
+def test_fp16_panel_lmp_apply_and_pcg(k_r):
+    """Float16 panel copy of U, each column scaled by a power of two.  k_r runs below, at and
+    above the 16 columns a float16 pass keeps in flight per block and the 32-column groups of
+    its U^T x pass; C1's n_A = 840 leaves a ragged last panel.  Rounding: |du| <= 2^-11 |u|
+    per entry, so ||dU||_2 <= 2^-11 sqrt(k) and C v moves by at most 2 ||dU||_2 ||v|| (the
+    coefficients theta^{-1/2} - 1 lie in (-1, 0]); the bound is that, relative to ||C v||
+    (~||v|| for a random v).  PCG must still reach the float64 true residual, within
+    5% + 2 iterations of the oracle's PCG."""
+    from paper_2101_07249_amd import wc4d
+    import torch
+    w = C1
+    m = k_r + w.l
+    print("[case] fp16 panel LMP, k_r", k_r, flush=True)
+    gm, op = _pair(w, wc4d.PREC_LMP_FP16)
+    G = sketch_block(op.n_A, m, w.seed)
+    L = gm.lmp_build("nystrom", k_r, w.l, _dev(G))
+    Uo, tho = O.METHODS["nystrom"](lambda Z: O.apply_A(op, Z), G, k_r)
+    bound = 2.0 * 2.0 ** -11 * np.sqrt(k_r)
+    for ncols in (1, 2, 3):
+        V = random_block(op.n_A, ncols, 9 + ncols)
+        CV = L.apply(_dev(V)).cpu().numpy()
+        CV = CV.T if CV.ndim == 2 else CV[:, None]
+        CVo = O.lmp_apply(Uo, tho, V)
+        e = np.linalg.norm(CV - CVo) / np.linalg.norm(CVo)
+        print("[result] columns", ncols, "rel err", e, "bound", bound, flush=True)
+        assert e <= bound
+        if ncols <= 2:
+            assert e > 1e-9   # the float16 copy really is what the one-vector passes read
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    ro = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho), tol=1e-6, maxit=500)
+    for variant in (wc4d.PCG_FUSED, wc4d.PCG_PLAIN):
+        x = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+        info = gm.pcg(gm.rhs(_dev(d)), x, L, tol=1e-6, maxit=500, variant=variant)
+        res = np.linalg.norm(b - O.apply_A(op, x.cpu().numpy())) / np.linalg.norm(b)
+        print("[result] variant", variant, "iters", info["iters"], "oracle", ro.iters, "true res", res, flush=True)
+        assert info["status"] == 0 and res <= 1.01e-6
+        assert info["iters"] <= 1.05 * ro.iters + 2
+
+
+def test_fp16_panel_lmp_pcg_c2_and_flag_errors():
+    """C2 (n_A = 4,080, k_r = 45): the float16 copy's PCG against the float64 LMP's, same
+    sketch; LMP_FP32 and LMP_FP16 together are rejected."""
+    from paper_2101_07249_amd import Problem, Wc4dError, wc4d
+    import torch
+    w = C2
+    print("[case] fp16 panel LMP, C2", flush=True)
+    gm, op = _pair(w, wc4d.PREC_LMP_FP16)
+    gd, _ = _pair(w, wc4d.PREC_FP64)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    Lm = gm.lmp_build("nystrom", w.k_r, w.l, _dev(G))
+    Ld = gd.lmp_build("nystrom", w.k_r, w.l, _dev(G))
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    b = O.rhs(op, d)
+    xm = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+    xd = torch.zeros(op.n_A, dtype=torch.float64, device="cuda")
+    im = gm.pcg(gm.rhs(_dev(d)), xm, Lm, tol=1e-6, maxit=3000)
+    idd = gd.pcg(gd.rhs(_dev(d)), xd, Ld, tol=1e-6, maxit=3000)
+    assert im["status"] == 0 and idd["status"] == 0
+    res = np.linalg.norm(b - O.apply_A(op, xm.cpu().numpy())) / np.linalg.norm(b)
+    print("[result] iters fp16 U", im["iters"], "fp64", idd["iters"], "true res", res, flush=True)
+    assert res <= 1.05e-6
+    assert im["iters"] <= 1.05 * idd["iters"] + 2
+    with pytest.raises(Wc4dError) as e:
+        Problem.from_workload(C1, obs_pattern(C1), prec=wc4d.PREC_LMP_FP32 | wc4d.PREC_LMP_FP16)
+    assert e.value.code == -1
+
+
+def test_fp16_copy_keeps_c_positive_definite():
+    """The float16 copy is kept only while its Gram defect is at most half of theta_max^{-1/2}
+    (C's smallest eigenvalue for an orthonormal U).  At C1 (theta_max ~ 5e3) the float16
+    copy is used; with observation variance 1e-12 theta_max ~ 5e13 and the float16 rounding
+    (Gram defect ~1e-5) would leave too little margin, so the build streams the float32 copy,
+    whose C v still matches the oracle's to the float32 bound."""
+    from paper_2101_07249_amd import wc4d
+    w = C1
+    gm, op = _pair(w, wc4d.PREC_LMP_FP16)
+    G = sketch_block(op.n_A, w.m, w.seed)
+    L = gm.lmp_build("nystrom", w.k_r, w.l, _dev(G))
+    print("[result] C1 theta_max", L.theta()[0], "copy", L.copy_format(), flush=True)
+    assert L.copy_format() == wc4d.PREC_LMP_FP16
+    wx = w.with_(sigma_o2=1e-12)
+    gx, opx = _pair(wx, wc4d.PREC_LMP_FP16)
+    Lx = gx.lmp_build("nystrom", wx.k_r, wx.l, _dev(G))
+    th = Lx.theta()
+    print("[result] sigma_o2 1e-12 theta_max", th[0], "copy", Lx.copy_format(), flush=True)
+    assert th[0] > 1e10
+    assert Lx.copy_format() == wc4d.PREC_LMP_FP32
+    Uo, tho = O.METHODS["nystrom"](lambda Z: O.apply_A(opx, Z), G, wx.k_r)
+    V = random_block(opx.n_A, 1, 11)
+    CV = Lx.apply(_dev(V)).cpu().numpy()
+    CV = CV.T if CV.ndim == 2 else CV[:, None]
+    CVo = O.lmp_apply(Uo, tho, V)
+    e = np.linalg.norm(CV - CVo) / np.linalg.norm(CVo)
+    print("[result] fallback C v rel err", e, flush=True)
+    assert e <= 1e-5
+    gd, _ = _pair(w, wc4d.PREC_FP64)
+    assert gd.lmp_build("nystrom", w.k_r, w.l, _dev(G)).copy_format() == 0
+
+
 # ---------------------------------------------------------------- split float16 x 3
 # Three float16 products with float32 accumulation and power-of-two scaling (rows of S,
 # columns of X): per part 11 significant bits, so the dropped Sl Xl term is ~2^-22 relative
