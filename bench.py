@@ -39,14 +39,17 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 
 # HBM bytes per launch group of the single-vector float64 D^{1/2} product at n = 4096,
 # N = 100, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each scaled by a 1 GiB copy's
-# reading; profiles/dsqrt_vec_n4096_N100_counters.md).  Valid only for the kernels that were
-# measured: the tuned form below, built from this gemm_f64.hip and vec.hip.
+# reading; profiles/dsqrt_vec_n4096_N100_counters.md), per tuned tile code of the one
+# product with Q^{1/2} over all levels.  Valid only for the kernels that were measured:
+# those tile codes, built from this gemm_f64.hip (product and split-K reduction).
 MEASURED_TRAFFIC = {"n": 4096, "N": 100,
-                    "tune": {"single_product": True, "two_segment": False, "tile_b": 7},
-                    # k_gemm_f64_pa and k_gemm_splitk_reduce (the whole launch group) live here
+                    "tune": {"single_product": True, "two_segment": False},
                     "sources": {"paper_2101_07249_amd/csrc/gemm_f64.hip":
                                 "7d77e6e0c0c0a03f8aa5b42f710c13d72289138b95b47149a76721ecbe82e54d"},
-                    "bytes_per_launch": 216.6e6}
+                    "bytes_per_launch": {2: 216.7e6, 7: 216.6e6}}
+
+# Measured tile choices for MI355X (loaded unless --tune-cache or --retune is given).
+TUNING_TABLE = os.path.join(ROOT, "paper_2101_07249_amd", "tuning", "mi355x.txt")
 
 
 def dominant_class(prof):
@@ -59,7 +62,7 @@ def measured_traffic(w, tune):
     """The counted bytes when this run uses the measured kernels, else None."""
     import hashlib
     t = MEASURED_TRAFFIC
-    if t["bytes_per_launch"] is None or tune is None or (w.n, w.N) != (t["n"], t["N"]):
+    if tune is None or (w.n, w.N) != (t["n"], t["N"]):
         return None
     if any(tune.get(k) != v for k, v in t["tune"].items()):
         return None
@@ -67,7 +70,7 @@ def measured_traffic(w, tune):
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
-    return t["bytes_per_launch"]
+    return t["bytes_per_launch"].get(tune.get("tile_b"))
 
 
 def dsqrt_kernel_name(tune):
@@ -107,6 +110,8 @@ def parse():
     ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--batched", action="store_true", help="also time the 64-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune every product shape instead of loading the MI355X tuning table")
     ap.add_argument("--tune-cache", default=None,
                     help="autotune cache file: loaded when present, written after tuning")
     ap.add_argument("--copy-probe", action="store_true",
@@ -316,8 +321,13 @@ def main():
     names = [v for v in args.variants.split(",") if v]
     results = {}
     tunes = {}
+    tile_source = "autotuned at set-up"
     if args.tune_cache and os.path.exists(args.tune_cache):
         W4.autotune_load(args.tune_cache)
+        tile_source = "tune cache " + os.path.basename(args.tune_cache) + " (autotuned where absent)"
+    elif not args.tune_cache and not args.retune and os.path.exists(TUNING_TABLE):
+        W4.autotune_load(TUNING_TABLE)
+        tile_source = "MI355X tuning table paper_2101_07249_amd/tuning/mi355x.txt (autotuned where absent)"
     for vname in names:
         prob = Problem.from_workload(w, pat, prec=precs[vname])
         # one-time setup, outside the timed region: tile shapes of the D^{1/2} products for
@@ -430,7 +440,7 @@ def main():
                    "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,
                    "criterion": "true residual ||b - A x|| / ||b||",
-                   "autotuned_tiles": tunes.get(head)},
+                   "autotuned_tiles": tunes.get(head), "tile_source": tile_source},
         "pcg_iters": iters, "relres_true": results[head]["relres_true"], "converged": ok,
         "variants": variants,
         "hessian_apply": hess,

@@ -44,15 +44,28 @@ struct EvPair {
 
 // Mean ms of `reps` runs of launch() after one warm-up run; < 0 on a launch error.
 template <class F>
-float time_launch(hipStream_t s, EvPair& ev, F&& launch, int reps = 3) {
-  if (launch() != hipSuccess) return -1.f;
-  if (hipEventRecord(ev.a, s) != hipSuccess) return -1.f;
-  for (int r = 0; r < reps; ++r)
-    if (launch() != hipSuccess) return -1.f;
-  if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess) return -1.f;
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) return -1.f;
-  return ms / reps;
+float time_launch(hipStream_t s, EvPair& ev, F&& launch) {
+  // one warm launch, timed alone to size the batches; then the best of three batches of
+  // about 2 ms each (tile shapes of the one-vector products differ by ~1%)
+  auto batch = [&](int reps) -> float {
+    if (hipEventRecord(ev.a, s) != hipSuccess) return -1.f;
+    for (int r = 0; r < reps; ++r)
+      if (launch() != hipSuccess) return -1.f;
+    if (hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) != hipSuccess) return -1.f;
+    return ms / reps;
+  };
+  const float one = batch(1);
+  if (one < 0.f) return -1.f;
+  const int reps = one > 0.f ? std::max(1, std::min(20, (int)(2.0f / one))) : 20;
+  float best = -1.f;
+  for (int t = 0; t < 3; ++t) {
+    const float ms = batch(reps);
+    if (ms < 0.f) return -1.f;
+    if (best < 0.f || ms < best) best = ms;
+  }
+  return best;
 }
 
 void set_tune(wc4d_problem p, int m, const DsqrtTune& t) {
