@@ -1089,7 +1089,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
           ProfScope ps(p, s, PROF_LMP_T, ub + 16.0 * nA, fl + 2.0 * nA);
           HIPCHK(p, lmp_pan_t_partials(nA, L->k, Us, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
         }
-        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k), tvec, p->pcgRed, L->dcoef,
+        HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k, Us.fmt), tvec, p->pcgRed, L->dcoef,
                                      L->GU, u, d12, s));
         {
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 9.0 * nA, 2.0 * fl);

@@ -12,10 +12,11 @@
 // [256 p, 256 p + 256) of all k columns, column-major with leading dimension 256, at
 // offset 256 k p, and rows at or past n_A are zero.  A workgroup working on one panel
 // reads one contiguous block (1 KB or 512 bytes per column).  The float16 copy scales
-// each column by a power of two (exact), undone in the coefficients the passes apply.  Measured on MI355X at n_A = 413,696, k = 251:
-// U^T x 73 us (5.7 TB/s) and the fused PCG pass 78 us (5.5 TB/s), against 77 us and
-// 144 us for the same passes over a column-major copy (a plain read of the 415 MB runs
-// at 6.3 TB/s).
+// each column by a power of two (exact), undone in the coefficients the passes apply.
+// Measured on MI355X at n_A = 413,696, k = 251 over the float32 copy (isolated): U^T x
+// 73 us (5.7 TB/s) and the fused PCG pass 78 us (5.5 TB/s), against 77 us and 144 us for
+// the same passes over a column-major copy (a plain read of the 415 MB runs at 6.3 TB/s);
+// over the float16 copy inside the PCG: U^T x 45 us, the fused pass 41 us.
 #include "wc4d_internal.h"
 
 namespace wc4d {
@@ -31,7 +32,7 @@ static inline long long lmp_chunks(long long nA) { return (nA + kLRows - 1) / kL
 
 size_t lmp_panel_elems(long long nA, int k) { return (size_t)lmp_panels(nA) * kPanel * k; }
 
-// U^T x over panels (either precision): grid (column groups of kPG) x (splits of pan_per
+// U^T x over the float32 panels: grid (column groups of kPG) x (splits of pan_per
 // consecutive panels); about 1024 workgroups.
 constexpr int kPG = 16;
 static inline long long pan_t_per(long long nA, int k) {
@@ -44,6 +45,20 @@ static inline long long pan_t_per(long long nA, int k) {
 }
 static inline int pan_t_splits(long long nA, int k) {
   const long long per = pan_t_per(nA, k);
+  return (int)((lmp_panels(nA) + per - 1) / per);
+}
+
+// Row-owning float16 pass: panels per workgroup.  At most 404 workgroups (1.6 per CU, and at
+// most 1024: one dot partial each) so that the whole grid is resident at once at the
+// kernel's occupancy (3 waves per SIMD); at n_A = 413,696 (1,616 panels) 4 panels each.
+static inline long long rows_pan_per(long long nA) {
+  const long long np = lmp_panels(nA);
+  long long per = (np + 403) / 404;
+  if (per < (np + 1023) / 1024) per = (np + 1023) / 1024;
+  return per < 1 ? 1 : per;
+}
+static inline int rows_grid(long long nA) {
+  const long long per = rows_pan_per(nA);
   return (int)((lmp_panels(nA) + per - 1) / per);
 }
 
@@ -60,7 +75,7 @@ static inline int lmp_t_splits(long long nA, int k) {
 
 // partials of either layout, then t
 static inline int t_splits_max(long long nA, int k) {
-  return std::max(lmp_t_splits(nA, k), pan_t_splits(nA, k));
+  return std::max(std::max(lmp_t_splits(nA, k), pan_t_splits(nA, k)), rows_grid(nA));
 }
 size_t lmp_gemv_ws_doubles(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k + k; }
 size_t lmp_gemv_t_offset(long long nA, int k) { return (size_t)t_splits_max(nA, k) * k; }
@@ -123,16 +138,18 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k,
   }
 }
 
+// Partial (split b, column c) at part[b sb + c sc]: (sb, sc) = (k, 1) for the split-major
+// partials, (1, splits) for the column-major ones of the row-owning float16 pass.
 __global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__ part,
                                    const double* __restrict__ dcoef, double* __restrict__ t,
-                                   const int* __restrict__ skip) {
+                                   const int* __restrict__ skip, long long sb, long long sc) {
   if (skip != nullptr && *skip != 0) return;
   // one wavefront per column: lanes stride the splits, then a fixed-order tree
   const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= k) return;
   double s = 0.0;
-  for (int b = lane; b < splits; b += 64) s += part[(size_t)b * k + c];
+  for (int b = lane; b < splits; b += 64) s += part[(size_t)b * sb + (size_t)c * sc];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
@@ -358,87 +375,106 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
   }
 }
 
-// The same over the float16 copy: a thread takes R adjacent rows (one 2R-byte load per
-// column), kPanel / R threads a panel, so the block works on R panels side by side; a
-// column's sum is scaled back by 2^cexp[c].  Used with R = 2, PG = 16 (inside the PCG at
-// n_A = 413,696, k = 251: 57 us per pass; 4 rows x 16 columns ran the same, 4 x 8 and
-// 8 x 8 slower at 66 and 85 us).
-template <int R, int PG>
-__global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial16(long long nA, int k, long long pan_per,
-                                                                const _Float16* __restrict__ P,
-                                                                const int* __restrict__ cexp,
-                                                                const double* __restrict__ x,
-                                                                double* __restrict__ part,
-                                                                const int* __restrict__ skip,
-                                                                const double* __restrict__ pdot,
-                                                                double* __restrict__ dotpart) {
-  typedef _Float16 hv __attribute__((ext_vector_type(R)));
-  constexpr int TPP = kPanel / R;  // threads per panel
-  __shared__ double sh[kPanel / 64][PG];
+// U^T x over the float16 copy with x read once: workgroup b owns panels [b per, b per + per)
+// and all columns.  x of up to kXP panels at a time is staged in LDS; then, chunk by chunk of
+// 64 columns, lane l of half-wave g (g = 2 wave + lane / 32) holds rows 8 (l % 32) .. + 7 of
+// each staged panel (one 16-byte load per column) for columns cc + g + 8 j, j < 8.  A 3-step
+// butterfly and a 2-step sum across the half-wave leave column cc + g + 8 ((l % 32) / 4)'s
+// sum in lanes with l % 4 = 0, which add it to the workgroup's column totals in LDS; the
+// totals go out column-major (part[c G + b], G workgroups) scaled back by 2^cexp[c].  With
+// pdot (PCG) every workgroup also sums pdot . x over its rows into dotpart[b].  Used with
+// JC = 4 columns per half-wave per chunk (8 converted columns per lane would take all the
+// registers: the compiler converts a chunk's halves to double before its FMAs).  Inside the
+// PCG at n_A = 413,696, k = 251: 45.2 us with 4 panels per workgroup, against 53.1 us for 16
+// columns x 2 rows per thread (x re-read by every column group); JC = 2 with 2 panels
+// each ran 46.3 us, shapes whose grid is not resident at once 55-60 us.
+constexpr int kXP = 4;
+template <int JC>
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k, long long pan_per,
+                                                             const _Float16* __restrict__ P,
+                                                             const int* __restrict__ cexp,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ part,
+                                                             const int* __restrict__ skip,
+                                                             const double* __restrict__ pdot,
+                                                             double* __restrict__ dotpart) {
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  constexpr int CW = 8 * JC;        // columns per chunk
+  constexpr int LPC = 32 / JC;      // lanes that end up holding one column's sum
+  __shared__ double xs[kXP][kPanel];
+  __shared__ double tsum[512];
   __shared__ double shd[kPanel / 64];
   if (skip != nullptr && *skip != 0) return;
-  const bool dot = pdot != nullptr && blockIdx.x == 0;
-  double dv = 0.0;
-  const int c0 = blockIdx.x * PG;
-  const int split = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = 2 * wave + (lane >> 5), l32 = lane & 31, r8 = 8 * l32;
   const long long np = lmp_panels(nA);
-  const long long pb = (long long)split * pan_per;
+  const long long pb = (long long)blockIdx.x * pan_per;
   long long pe = pb + pan_per;
   if (pe > np) pe = np;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int sub = threadIdx.x / TPP, rr = R * (threadIdx.x % TPP);
-  int col[PG];
-#pragma unroll
-  for (int c = 0; c < PG; ++c) col[c] = (c0 + c < k ? c0 + c : 0) * kPanel;
-  double acc[PG];
-#pragma unroll
-  for (int c = 0; c < PG; ++c) acc[c] = 0.0;
-  for (long long pn = pb + sub; pn < pe; pn += R) {
-    const long long i = pn * kPanel + rr;
-    double xv[R];
-#pragma unroll
-    for (int e = 0; e < R; ++e) xv[e] = i + e < nA ? x[i + e] : 0.0;
-    if (dot) {
-#pragma unroll
-      for (int e = 0; e < R; ++e)
-        if (i + e < nA) dv += pdot[i + e] * xv[e];
+  for (int c = threadIdx.x; c < k; c += kPanel) tsum[c] = 0.0;
+  double dv = 0.0;
+  for (long long g0 = pb; g0 < pe; g0 += kXP) {
+    const int ng = (int)(pe - g0 < kXP ? pe - g0 : kXP);
+    __syncthreads();  // previous group's reads of xs (and the tsum clear) are done
+    for (int q = 0; q < ng; ++q) {
+      const long long i = (g0 + q) * kPanel + threadIdx.x;
+      const double xv = i < nA ? x[i] : 0.0;
+      xs[q][threadIdx.x] = xv;
+      if (pdot != nullptr && i < nA) dv += pdot[i] * xv;
     }
-    const _Float16* Pp = P + (size_t)pn * kPanel * k + rr;
+    __syncthreads();
+#pragma unroll 1
+    for (int cc = 0; cc < k; cc += CW) {
+      double aj[JC];
 #pragma unroll
-    for (int c = 0; c < PG; ++c) {
-      const hv u = *reinterpret_cast<const hv*>(Pp + col[c]);
-      double a = 0.0;
+      for (int j = 0; j < JC; ++j) aj[j] = 0.0;
+#pragma unroll 1
+      for (int q = 0; q < ng; ++q) {
+        const _Float16* Pp = P + (size_t)(g0 + q) * kPanel * k + r8;
+        // columns past k read column k - 1; their sums are never written out
+        h8 u[JC];
 #pragma unroll
-      for (int e = 0; e < R; ++e) a += (double)(float)u[e] * xv[e];
-      acc[c] += a;
+        for (int j = 0; j < JC; ++j) {
+          const int c = min(cc + g + 8 * j, k - 1);
+          u[j] = *reinterpret_cast<const h8*>(Pp + (size_t)c * kPanel);
+        }
+        double xr[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xr[e] = xs[q][r8 + e];
+#pragma unroll
+        for (int j = 0; j < JC; ++j) {
+          double a = 0.0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a += (double)(float)u[j][e] * xr[e];
+          aj[j] += a;
+        }
+      }
+      // butterfly from width 16 down: a lane keeps the lower (bit clear) or upper half of its
+      // remaining sums and adds the partner's copy; then the lanes sharing a column add up
+#pragma unroll
+      for (int w = 16, nv = JC; nv > 1; w >>= 1, nv >>= 1) {
+        const bool hi = (l32 & w) != 0;
+#pragma unroll
+        for (int t = 0; t < nv / 2; ++t) {
+          const double send = hi ? aj[t] : aj[t + nv / 2];
+          const double keep = hi ? aj[t + nv / 2] : aj[t];
+          aj[t] = keep + __shfl_xor(send, w, 64);
+        }
+      }
+#pragma unroll
+      for (int w = LPC / 2; w > 0; w >>= 1) aj[0] += __shfl_xor(aj[0], w, 64);
+      const int c = cc + g + 8 * (l32 / LPC);
+      if (l32 % LPC == 0 && c < k) tsum[c] += aj[0];
     }
   }
-  if (dot) {
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += kPanel) part[(size_t)c * gridDim.x + blockIdx.x] = ldexp(tsum[c], cexp[c]);
+  if (pdot != nullptr) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dv += __shfl_down(dv, o, 64);
     if (lane == 0) shd[wave] = dv;
-  }
-#pragma unroll
-  for (int c = 0; c < PG; ++c) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < PG; ++c) sh[wave][c] = acc[c];
-  }
-  __syncthreads();
-  if (threadIdx.x < PG && c0 + (int)threadIdx.x < k) {
-    double sum = 0.0;
-#pragma unroll
-    for (int w = 0; w < kPanel / 64; ++w) sum += sh[w][threadIdx.x];
-    part[(size_t)split * k + c0 + threadIdx.x] = ldexp(sum, cexp[c0 + threadIdx.x]);
-  }
-  if (dot && threadIdx.x == 0) {
-    double sum = 0.0;
-#pragma unroll
-    for (int w = 0; w < kPanel / 64; ++w) sum += shd[w];
-    dotpart[split] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) dotpart[blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
   }
 }
 
@@ -489,28 +525,39 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_n(long long nA, int k, const
   }
 }
 
-int lmp_pan_t_splits(long long nA, int k) { return pan_t_splits(nA, k); }
+int lmp_pan_t_splits(long long nA, int k, LmpFmt fmt) {
+  return fmt == LMP_P16 ? rows_grid(nA) : pan_t_splits(nA, k);
+}
 
 // partials of U^T x over the panel copy (either precision); returns the split count
+// partials of U^T x over the panel copy (either precision); returns the split count and the
+// partials' strides (split, column)
 static int launch_pan_t_partial(long long nA, int k, const LmpU& U, const double* x, double* part,
-                                const int* skip, const double* pdot, double* dotpart, hipStream_t s) {
-  const int sp = pan_t_splits(nA, k);
-  const dim3 grid((k + kPG - 1) / kPG, sp);
-  if (U.fmt == LMP_P16)
-    hipLaunchKernelGGL((k_lmp_pan_t_partial16<2, kPG>), grid, dim3(kPanel), 0, s, nA, k, pan_t_per(nA, k),
+                                const int* skip, const double* pdot, double* dotpart, hipStream_t s,
+                                long long* sb, long long* sc) {
+  if (U.fmt == LMP_P16) {
+    const int G = rows_grid(nA);
+    hipLaunchKernelGGL(k_lmp_pan_t16_rows<4>, dim3(G), dim3(kPanel), 0, s, nA, k, rows_pan_per(nA),
                        (const _Float16*)U.p, U.cexp, x, part, skip, pdot, dotpart);
-  else
-    hipLaunchKernelGGL(k_lmp_pan_t_partial, grid, dim3(kPanel), 0, s, nA, k, pan_t_per(nA, k), (const float*)U.p, x,
-                       part, skip, pdot, dotpart);
+    *sb = 1;
+    *sc = G;
+    return G;
+  }
+  const int sp = pan_t_splits(nA, k);
+  hipLaunchKernelGGL(k_lmp_pan_t_partial, dim3((k + kPG - 1) / kPG, sp), dim3(kPanel), 0, s, nA, k,
+                     pan_t_per(nA, k), (const float*)U.p, x, part, skip, pdot, dotpart);
+  *sb = k;
+  *sc = 1;
   return sp;
 }
 
 hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
                               double* ws, double* dotpart, const int* skip, hipStream_t s) {
   if (U.fmt == LMP_F64) return hipErrorInvalidValue;
-  const int sp = launch_pan_t_partial(nA, k, U, x, ws, skip, pdot, dotpart, s);
+  long long sb, sc;
+  const int sp = launch_pan_t_partial(nA, k, U, x, ws, skip, pdot, dotpart, s, &sb, &sc);
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, ws, nullptr,
-                     ws + lmp_gemv_t_offset(nA, k), skip);
+                     ws + lmp_gemv_t_offset(nA, k), skip, sb, sc);
   return hipGetLastError();
 }
 
@@ -526,8 +573,9 @@ hipError_t lmp_gemv_t(long long nA, int k, const LmpU& U, const double* dcoef, c
   double* part = ws;
   double* t = (tout != nullptr) ? tout : ws + lmp_gemv_t_offset(nA, k);
   int sp;
+  long long sb = k, sc = 1;
   if (U.fmt != LMP_F64) {
-    sp = launch_pan_t_partial(nA, k, U, x, part, skip, nullptr, nullptr, s);
+    sp = launch_pan_t_partial(nA, k, U, x, part, skip, nullptr, nullptr, s, &sb, &sc);
   } else {
     sp = lmp_t_splits(nA, k);
     const long long rows_per = (nA + sp - 1) / sp;
@@ -535,7 +583,7 @@ hipError_t lmp_gemv_t(long long nA, int k, const LmpU& U, const double* dcoef, c
                        k, rows_per, (const double*)U.p, U.ldu, x, part, skip);
   }
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, part, dcoef, t,
-                     skip);
+                     skip, sb, sc);
   return hipGetLastError();
 }
 

@@ -248,7 +248,7 @@ hipError_t pcg_lmp_dual(PcgState* st, long long nA, int k, const double* U, long
 // with pdot = p, dotpart = pcg_dot_slots(red); t = U^T Ap left at ws + lmp_gemv_t_offset),
 // then pcg_lmp_coeffs_pan (p.Ap -> alpha, u, d12; sp = lmp_pan_t_splits), then the dual
 // pass that also updates x and s (the true residual) and ends with beta.
-int lmp_pan_t_splits(long long nA, int k);
+int lmp_pan_t_splits(long long nA, int k, LmpFmt fmt);
 hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
                               double* ws, double* dotpart, const int* skip, hipStream_t s);
 double* pcg_dot_slots(double* red);
