@@ -780,6 +780,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
   double* Zfinal = nullptr;
   int mode = 0;
+  bool evd_sym = true;
   const int mx = (p->prec & WC4D_PREC_SKETCH_BF16X3) ? SPLIT_BF16
                  : (p->prec & WC4D_PREC_SKETCH_FP16X3) ? SPLIT_FP16 : SPLIT_NONE;
   if (method == WC4D_REVD) {
@@ -805,7 +806,11 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
       he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, plain_cols(m), A_, cm, nullptr, cm, nullptr, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
-    he = small_gemm(m, m, m, 1.0, sm.R2, m, 0, sm.R2, m, 1, sm.K, m, s);
+    // the EVD of R_F R_F^T as the one-sided Jacobi SVD of R_F^T (no squared condition
+    // number): singular values sigma, left singular vectors of R_F; Theta = sigma^2
+    he = transpose_small(m, sm.R2, m, sm.K, m, s);
+    evd_sym = false;
+    mode = 2;
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     Zfinal = A_;
   } else {
@@ -816,13 +821,15 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
     L->applies = 1;
     if ((rc = cholqr2(p, B_, A_, m, sm, sm.R2, s))) return cleanup(rc);
-    he = small_gemm(m, m, m, 1.0, sm.R2, m, 0, sm.R2, m, 1, sm.K, m, s);
+    // W Theta^2 W^T = R_3 R_3^T as the one-sided Jacobi SVD of R_3^T: Theta = sigma
+    he = transpose_small(m, sm.R2, m, sm.K, m, s);
+    evd_sym = false;
+    mode = 0;
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     Zfinal = B_;
-    mode = 1;
   }
   ProfScope ps_tail(p, s, PROF_BUILD, 8.0 * (double)nA * (m + k_r), 2.0 * (double)nA * m * k_r);
-  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s);
+  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s, evd_sym);
   if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
   if (he == hipSuccess)
     he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, plain_cols(L->ldu), nullptr,

@@ -307,10 +307,10 @@ static OjCfg oj_cfg(int m) {
 }
 
 __global__ __launch_bounds__(kOJT) void k_oj_init(int m, double* __restrict__ K, int ldk,
-                                                  double* __restrict__ V, int ldv, int* ctrl) {
+                                                  double* __restrict__ V, int ldv, int* ctrl, int sym) {
   for (long long e = threadIdx.x; e < (long long)m * m; e += kOJT) {
     const int i = (int)(e % m), j = (int)(e / m);
-    if (i < j) {
+    if (sym && i < j) {
       const double v = 0.5 * (K[i + (size_t)j * ldk] + K[j + (size_t)i * ldk]);
       K[i + (size_t)j * ldk] = v;
       K[j + (size_t)i * ldk] = v;
@@ -518,7 +518,7 @@ hipError_t shift_diag_trace(int m, double* G, int ldg, double c, hipStream_t s) 
 }
 
 hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
-                      hipStream_t s) {
+                      hipStream_t s, bool sym) {
   if (m > 512 || m < 1) return hipErrorInvalidValue;
   const OjCfg c = oj_cfg(m);
   const size_t lds = sizeof(double) * 4 * (size_t)c.bs * m;
@@ -528,7 +528,7 @@ hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv
                               (int)(sizeof(double) * 4 * 16 * 256));
   });
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
-  hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl);
+  hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl, sym ? 1 : 0);
   const int max_sweeps = 20;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < c.nblk - 1; ++r)
@@ -546,8 +546,19 @@ __global__ void k_ritz_finish(int k, const double* __restrict__ lam, int mode,
   if (i >= k) return;
   double t = lam[i];
   if (mode == 1) t = sqrt(t > 0.0 ? t : 0.0);
+  if (mode == 2) t = t * t;
   theta[i] = t;
   dcoef[i] = 1.0 / sqrt(t) - 1.0;
+}
+
+__global__ void k_transpose_small(int m, const double* __restrict__ A, int lda, double* __restrict__ B, int ldb) {
+  const int i = blockIdx.x * 16 + (threadIdx.x & 15), j = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (i < m && j < m) B[j + (size_t)i * ldb] = A[i + (size_t)j * lda];
+}
+
+hipError_t transpose_small(int m, const double* A, int lda, double* B, int ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_small, dim3((m + 15) / 16, (m + 15) / 16), dim3(256), 0, s, m, A, lda, B, ldb);
+  return hipGetLastError();
 }
 
 hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double* dcoef,

@@ -160,10 +160,14 @@ hipError_t small_gemm(int M, int N, int K, double alpha, const double* A, int ld
 // EVD of the symmetric positive definite part of K (m x m, m <= 512) by one-sided
 // block Jacobi.  Outputs eigenvalues lam (decreasing) and eigenvectors V (m x m,
 // ldv), each vector's largest-magnitude entry positive.  K is overwritten; ctrl:
-// 2 device ints of scratch.
+// 2 device ints of scratch.  With sym = false K is taken as it is (any square F): the
+// same iteration then gives the singular values of F in lam and its right singular
+// vectors in V, i.e. the eigenpairs (lam^2, V) of F^T F without forming it.
 hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
-                      hipStream_t s);
-// theta[i] = f(lam[i]) for i < k: f = identity (mode 0) or sqrt (mode 1);
+                      hipStream_t s, bool sym = true);
+// B = A^T for m x m matrices (column-major).
+hipError_t transpose_small(int m, const double* A, int lda, double* B, int ldb, hipStream_t s);
+// theta[i] = f(lam[i]) for i < k: f = identity (mode 0), sqrt (mode 1) or square (mode 2);
 // dcoef[i] = theta[i]^{-1/2} - 1 (the LMP's diagonal).
 hipError_t ritz_finish(int k, const double* lam, int mode, double* theta, double* dcoef,
                        hipStream_t s);
