@@ -323,6 +323,26 @@ __global__ __launch_bounds__(kOJT) void k_oj_init(int m, double* __restrict__ K,
   }
 }
 
+// Sum over the wavefront, the same value in every lane: DPP within rows of 16 (xor 1, xor 2,
+// half-row and row mirrors), then two lane shuffles across the rows.
+template <int CTRL>
+static __device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+}
+static __device__ inline double wave_sum_d(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// MR = rows per lane (m <= 64 MR).
+template <int MR>
 __global__ __launch_bounds__(kOJT) void k_oj_round(int m, int bs, int nblk, int r,
                                                    double* __restrict__ W, int ldw,
                                                    double* __restrict__ V, int ldv, int* ctrl,
@@ -349,30 +369,38 @@ __global__ __launch_bounds__(kOJT) void k_oj_round(int m, int bs, int nblk, int 
       int a, b;
       rr_pair(lr, wave, nloc, a, b);
       if (gcol(a) < m && gcol(b) < m) {
+        double* wa_p = Ws + (size_t)a * m;
+        double* wb_p = Ws + (size_t)b * m;
+        double wa[MR], wb[MR];
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < m; i += 64) {
-          const double wa = Ws[(size_t)a * m + i], wb = Ws[(size_t)b * m + i];
-          al += wa * wa;
-          be += wb * wb;
-          ga += wa * wb;
-        }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 64);
-          be += __shfl_xor(be, o, 64);
-          ga += __shfl_xor(ga, o, 64);
+        for (int t = 0; t < MR; ++t) {
+          const int i = lane + 64 * t;
+          wa[t] = i < m ? wa_p[i] : 0.0;
+          wb[t] = i < m ? wb_p[i] : 0.0;
+          al += wa[t] * wa[t];
+          be += wb[t] * wb[t];
+          ga += wa[t] * wb[t];
         }
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        al = wave_sum_d(al);
+        be = wave_sum_d(be);
+        ga = wave_sum_d(ga);
+        if (ga != 0.0 && ga * ga > tol * tol * (al * be)) {  // |ga| > tol sqrt(al be)
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          for (int i = lane; i < m; i += 64) {
-            const double wa = Ws[(size_t)a * m + i], wb = Ws[(size_t)b * m + i];
-            Ws[(size_t)a * m + i] = c * wa - sn * wb;
-            Ws[(size_t)b * m + i] = sn * wa + c * wb;
-            const double va = Vs[(size_t)a * m + i], vb = Vs[(size_t)b * m + i];
-            Vs[(size_t)a * m + i] = c * va - sn * vb;
-            Vs[(size_t)b * m + i] = sn * va + c * vb;
+          double* va_p = Vs + (size_t)a * m;
+          double* vb_p = Vs + (size_t)b * m;
+#pragma unroll
+          for (int q = 0; q < MR; ++q) {
+            const int i = lane + 64 * q;
+            if (i < m) {
+              wa_p[i] = c * wa[q] - sn * wb[q];
+              wb_p[i] = sn * wa[q] + c * wb[q];
+              const double va = va_p[i], vb = vb_p[i];
+              va_p[i] = c * va - sn * vb;
+              vb_p[i] = sn * va + c * vb;
+            }
           }
           ++rot;
         }
@@ -524,16 +552,23 @@ hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv
   const size_t lds = sizeof(double) * 4 * (size_t)c.bs * m;
   static std::once_flag attr_once;
   std::call_once(attr_once, [] {
-    (void)hipFuncSetAttribute((const void*)k_oj_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_oj_round<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(double) * 4 * 16 * 256));
+    (void)hipFuncSetAttribute((const void*)k_oj_round<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * 4 * 8 * 512));
   });
   const double tol = sqrt((double)m) * 2.220446049250313e-16;
   hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl, sym ? 1 : 0);
   const int max_sweeps = 20;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int r = 0; r < c.nblk - 1; ++r)
-      hipLaunchKernelGGL(k_oj_round, dim3(c.nblk / 2), dim3(kOJT), lds, s, m, c.bs, c.nblk, r, K,
-                         ldk, V, ldv, ctrl, tol);
+    for (int r = 0; r < c.nblk - 1; ++r) {
+      if (m <= 256)
+        hipLaunchKernelGGL(k_oj_round<4>, dim3(c.nblk / 2), dim3(kOJT), lds, s, m, c.bs, c.nblk, r, K, ldk, V, ldv,
+                           ctrl, tol);
+      else
+        hipLaunchKernelGGL(k_oj_round<8>, dim3(c.nblk / 2), dim3(kOJT), lds, s, m, c.bs, c.nblk, r, K, ldk, V, ldv,
+                           ctrl, tol);
+    }
     hipLaunchKernelGGL(k_oj_sweep_end, dim3(1), dim3(64), 0, s, ctrl);
   }
   hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, lam);
