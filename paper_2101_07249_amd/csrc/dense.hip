@@ -323,24 +323,6 @@ __global__ __launch_bounds__(kOJT) void k_oj_init(int m, double* __restrict__ K,
   }
 }
 
-// Sum over the wavefront, the same value in every lane: DPP within rows of 16 (xor 1, xor 2,
-// half-row and row mirrors), then two lane shuffles across the rows.
-template <int CTRL>
-static __device__ inline double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
-}
-static __device__ inline double wave_sum_d(double v) {
-  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_d<0x141>(v);  // row_half_mirror
-  v += dpp_d<0x140>(v);  // row_mirror
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
 // MR = rows per lane (m <= 64 MR).
 template <int MR>
 __global__ __launch_bounds__(kOJT) void k_oj_round(int m, int bs, int nblk, int r,

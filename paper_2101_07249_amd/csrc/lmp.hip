@@ -122,8 +122,7 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k,
   }
 #pragma unroll
   for (int c = 0; c < kTG; ++c) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
+    acc[c] = wave_sum_d(acc[c]);
   }
   if (lane == 0) {
 #pragma unroll
@@ -150,8 +149,7 @@ __global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__
   if (c >= k) return;
   double s = 0.0;
   for (int b = lane; b < splits; b += 64) s += part[(size_t)b * sb + (size_t)c * sc];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  s = wave_sum_d(s);
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
 }
 
@@ -347,14 +345,12 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
     for (int c = 0; c < kPG; ++c) acc[c] += (double)Pp[col[c]] * xv;
   }
   if (dot) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dv += __shfl_down(dv, o, 64);
+    dv = wave_sum_d(dv);
     if (lane == 0) shd[wave] = dv;
   }
 #pragma unroll
   for (int c = 0; c < kPG; ++c) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_down(acc[c], o, 64);
+    acc[c] = wave_sum_d(acc[c]);
   }
   if (lane == 0) {
 #pragma unroll
@@ -470,8 +466,7 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k
   __syncthreads();
   for (int c = threadIdx.x; c < k; c += kPanel) part[(size_t)c * gridDim.x + blockIdx.x] = ldexp(tsum[c], cexp[c]);
   if (pdot != nullptr) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dv += __shfl_down(dv, o, 64);
+    dv = wave_sum_d(dv);
     if (lane == 0) shd[wave] = dv;
     __syncthreads();
     if (threadIdx.x == 0) dotpart[blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);

@@ -19,8 +19,7 @@ size_t pcg_red_doubles() { return (size_t)kRB * 4; }
 
 static __device__ inline double block_sum(double v, double* sh) {
   // wavefront reduction then across the 4 waves of a 256-thread block
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  v = wave_sum_d(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wave] = v;

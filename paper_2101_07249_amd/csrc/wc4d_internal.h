@@ -193,6 +193,23 @@ struct LmpU {
   const int* cexp = nullptr;  // LMP_P16 only (k)
 };
 inline double lmp_elem_bytes(LmpFmt f) { return f == LMP_P16 ? 2.0 : (f == LMP_P32 ? 4.0 : 8.0); }
+// Sum over the wavefront, the same value in every lane: DPP within rows of 16 (xor 1, xor 2,
+// half-row and row mirrors), then two lane shuffles across the rows.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+}
+__device__ inline double wave_sum_d(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
 // 4 consecutive panel rows of one column (a 16-byte float32 or 8-byte float16 load)
 __device__ inline float4 pan_ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
 __device__ inline float4 pan_ld4(const _Float16* p) {
