@@ -867,6 +867,12 @@ static __device__ inline const TwEntry* tw_slots(const SweepModel& md, int t) {
 // multiple of TD with no per-step guards and every memory operation of a step is issued
 // unconditionally (the stash store of a slot the wavefront does not own goes to a dummy
 // double), so the compiler can keep the ring's loads in flight across the loop's back edge.
+// The single-wave sweeps hand values between lanes through LDS.  A workgroup is one
+// wavefront and a wavefront's LDS operations complete in issue order, so a wave-level
+// code-motion barrier is enough (a workgroup barrier would also make the wave wait for
+// every LDS operation in flight).
+static __device__ inline void lds_order() { __builtin_amdgcn_wave_barrier(); }
+
 template <int PE, int TD, bool WX>
 __global__ __launch_bounds__(kTW) void k_sweep_fwd_w(SweepModel md, const double* __restrict__ P,
                                                      long long ldp, double* __restrict__ stash,
@@ -891,14 +897,14 @@ __global__ __launch_bounds__(kTW) void k_sweep_fwd_w(SweepModel md, const double
     if (WX) g.store(Xc, t, n, x);
 #pragma unroll
     for (int e = 0; e < PE; ++e) xs[lane * PE + e] = x[e];
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int r = 0; r < kTOW; ++r) {
       const bool own = g.owned(o[r].l);
       double* dst = own ? St + o[r].k : md.tw_dummy;
       *dst = o[r].v * xs[own ? o[r].l : 0];
     }
-    __syncthreads();
+    lds_order();
   };
   auto step = [&](int i, double (&fu)[PE], TwEntry (&ou)[kTOW]) {
     const double xm = from_lower_lane(x[PE - 1]), xp = from_upper_lane(x[0]);
@@ -977,17 +983,17 @@ __global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double
   auto finish = [&](int t, const int (&ol)[kTOW], const double (&v)[kTOW]) {
 #pragma unroll
     for (int e = 0; e < PE; ++e) xs[lane * PE + e] = 0.0;
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int r = 0; r < kTOW; ++r)
       if (ol[r] >= 0) xs[ol[r]] = v[r];
-    __syncthreads();
+    lds_order();
 #pragma unroll
     for (int e = 0; e < PE; ++e) {
       w[e] += xs[lane * PE + e];
       xs[lane * PE + e] = w[e];
     }
-    __syncthreads();
+    lds_order();
     // a fixed number of unconditional stores (W <= 64 PE): lanes past the owned range
     // repeat the last segment with the same values
     double* row = Wc + (size_t)t * n + g.j0;
@@ -1005,7 +1011,7 @@ __global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double
         row[c] = src[c];
       }
     }
-    __syncthreads();
+    lds_order();
   };
 #pragma unroll
   for (int e = 0; e < PE; ++e) w[e] = 0.0;
