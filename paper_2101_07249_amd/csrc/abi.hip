@@ -329,7 +329,7 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   std::vector<wc4d::TwEntry> went;
   if (p->model == 0 && tw_setup(n, N, off, idx, rinv, &twPe, &twW, went)) {
     if ((rc = dev_alloc(p, &p->dTwE, went.size()))) return rc;
-    if ((rc = dev_alloc(p, &p->dTwDummy, 1))) return rc;
+    if ((rc = dev_alloc(p, &p->dTwDummy, 2))) return rc;  // 16 bytes: a double2 store target
     HIPCHK(p, hipMemcpyAsync(p->dTwE, went.data(), sizeof(TwEntry) * went.size(), hipMemcpyHostToDevice, s));
     p->twPe = twPe;
     p->twW = twW;

@@ -942,7 +942,11 @@ __global__ __launch_bounds__(kTW) void k_sweep_fwd_w(SweepModel md, const double
 
 // Adjoint from the stash (z_t = H_t^T stash_t); a dense adjoint forcing takes the
 // general kernel.
-template <int PE, int TD>
+// DIRECT (n and N even, the output columns 16-byte aligned with even ldw): a lane stores
+// its owned point pairs straight from registers (pairs outside the owned run go to
+// md.tw_dummy), and the H^T stash scatter buffer is cleared after it is read, so a level
+// costs one LDS round trip.  Otherwise the owned run is staged through LDS.
+template <int PE, int TD, bool DIRECT>
 __global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double* __restrict__ stash,
                                                      long long ldst, double* __restrict__ Wout,
                                                      long long ldw, const int* __restrict__ skip) {
@@ -981,6 +985,26 @@ __global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double
   // H_t^T stash_t added over the extended range, then the owned points of level t written
   // out through LDS, 64 (n odd) or 128 (n even) consecutive doubles per store instruction
   auto finish = [&](int t, const int (&ol)[kTOW], const double (&v)[kTOW]) {
+    if (DIRECT) {
+#pragma unroll
+      for (int r = 0; r < kTOW; ++r)
+        if (ol[r] >= 0) xs[ol[r]] = v[r];
+      lds_order();
+#pragma unroll
+      for (int e = 0; e < PE; ++e) {
+        w[e] += xs[lane * PE + e];
+        xs[lane * PE + e] = 0.0;  // read before cleared (in-order LDS), clean for the next level
+      }
+      lds_order();
+#pragma unroll
+      for (int q = 0; q < PE / 2; ++q) {
+        const int l = lane * PE + 2 * q;  // extended index of the pair; owned ones map to j0 + l - N
+        const bool own = l >= N && l + 2 <= N + g.Wc;
+        double* dst = own ? Wc + ((size_t)t * n + g.j0 + (l - N)) : md.tw_dummy;
+        *reinterpret_cast<double2*>(dst) = make_double2(w[2 * q], w[2 * q + 1]);
+      }
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < PE; ++e) xs[lane * PE + e] = 0.0;
     lds_order();
@@ -1015,6 +1039,11 @@ __global__ __launch_bounds__(kTW) void k_sweep_bwd_w(SweepModel md, const double
   };
 #pragma unroll
   for (int e = 0; e < PE; ++e) w[e] = 0.0;
+  if (DIRECT) {
+#pragma unroll
+    for (int e = 0; e < PE; ++e) xs[lane * PE + e] = 0.0;
+    lds_order();
+  }
   {
     int2 e0[kTOW];
     int ol[kTOW];
@@ -1145,10 +1174,16 @@ hipError_t sweep_bwd(const SweepModel& md, const double* stash, long long ldst, 
   }
   if (md.kind == 0 && m <= 8 && md.tw_pe > 0 && stash != nullptr) {
     dim3 grid((md.n + md.tw_W - 1) / md.tw_W, m);
-    if (md.tw_pe == 4)
-      hipLaunchKernelGGL((k_sweep_bwd_w<4, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+    const bool direct = (md.n & 1) == 0 && (md.N & 1) == 0 && (ldw & 1) == 0 &&
+                        (reinterpret_cast<uintptr_t>(W) & 15) == 0;
+    if (md.tw_pe == 4 && direct)
+      hipLaunchKernelGGL((k_sweep_bwd_w<4, 8, true>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+    else if (md.tw_pe == 4)
+      hipLaunchKernelGGL((k_sweep_bwd_w<4, 8, false>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+    else if (md.tw_pe == 8 && direct)
+      hipLaunchKernelGGL((k_sweep_bwd_w<8, 8, true>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
     else if (md.tw_pe == 8)
-      hipLaunchKernelGGL((k_sweep_bwd_w<8, 8>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
+      hipLaunchKernelGGL((k_sweep_bwd_w<8, 8, false>), grid, dim3(kTW), 0, s, md, stash, ldst, W, ldw, skip);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();

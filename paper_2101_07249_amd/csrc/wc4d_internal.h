@@ -118,7 +118,7 @@ struct SweepModel {
   // W owned points per wavefront, fixed-slot observation entries (see sweep.hip)
   int tw_pe, tw_W;
   const TwEntry* tw_e;
-  double* tw_dummy;   // one device double: target of the stores of unowned slots
+  double* tw_dummy;   // two device doubles (16-byte aligned): target of the stores of unowned slots
 };
 
 // Trapezoid shape for the advection-diffusion sweeps of one or a few columns (the
