@@ -19,6 +19,8 @@
 // over the float16 copy inside the PCG: U^T x 45 us, the fused pass 41 us.
 #include "wc4d_internal.h"
 
+#include <climits>
+
 namespace wc4d {
 
 constexpr int kLT = 256;  // threads per block
@@ -234,22 +236,35 @@ hipError_t lmp_to_panels(float* P, const double* U, long long ldu, long long nA,
   return hipGetLastError();
 }
 
-// cexp[c] = ilogb(max_i |U_ic|) - 14 (0 for a zero column): one workgroup per column.
-__global__ __launch_bounds__(256) void k_lmp_col_exp(const double* __restrict__ U, long long ldu, long long nA,
-                                                     int k, int* __restrict__ cexp) {
-  __shared__ double sh[256];
-  for (int c = blockIdx.x; c < k; c += gridDim.x) {
-    double m = 0.0;
-    for (long long i = threadIdx.x; i < nA; i += 256) m = fmax(m, fabs(U[c * ldu + i]));
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) cexp[c] = sh[0] > 0.0 ? ilogb(sh[0]) - 14 : 0;
-    __syncthreads();
+// cexp[c] = ilogb(max_i |U_ic|) - 14 (0 for a zero column): cexp starts at INT_MIN, each
+// workgroup of a (column, row slab) grid raises it to its slab's exponent (ilogb is monotonic,
+// so the largest slab exponent is the column's), then zero columns get 0.
+__global__ void k_lmp_col_exp_init(int k, int* __restrict__ cexp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < k) cexp[c] = INT_MIN;
+}
+
+__global__ __launch_bounds__(256) void k_lmp_col_exp_slab(const double* __restrict__ U, long long ldu, long long nA,
+                                                          long long rows, int* __restrict__ cexp) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  const long long rb = (long long)blockIdx.y * rows;
+  const long long re = rb + rows < nA ? rb + rows : nA;
+  double m = 0.0;
+  for (long long i = rb + threadIdx.x; i < re; i += 256) m = fmax(m, fabs(U[c * ldu + i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    if (m > 0.0) atomicMax(&cexp[c], ilogb(m) - 14);
   }
+}
+
+__global__ void k_lmp_col_exp_fix(int k, int* __restrict__ cexp) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < k && cexp[c] == INT_MIN) cexp[c] = 0;
 }
 
 __global__ void k_lmp_to_panels16(const double* __restrict__ U, long long ldu, long long nA, int k,
@@ -269,7 +284,11 @@ __global__ void k_lmp_to_panels16(const double* __restrict__ U, long long ldu, l
 
 hipError_t lmp_to_panels16(_Float16* P, int* cexp, const double* U, long long ldu, long long nA, int k,
                            double* Uround, hipStream_t s) {
-  hipLaunchKernelGGL(k_lmp_col_exp, dim3(k), dim3(256), 0, s, U, ldu, nA, k, cexp);
+  constexpr int kSlabs = 16;
+  const long long rows = (nA + kSlabs - 1) / kSlabs;
+  hipLaunchKernelGGL(k_lmp_col_exp_init, dim3((k + 255) / 256), dim3(256), 0, s, k, cexp);
+  hipLaunchKernelGGL(k_lmp_col_exp_slab, dim3(k, kSlabs), dim3(256), 0, s, U, ldu, nA, rows, cexp);
+  hipLaunchKernelGGL(k_lmp_col_exp_fix, dim3((k + 255) / 256), dim3(256), 0, s, k, cexp);
   hipLaunchKernelGGL(k_lmp_to_panels16, dim3(4096), dim3(256), 0, s, U, ldu, nA, k, lmp_panels(nA), cexp, P,
                      Uround);
   return hipGetLastError();
