@@ -776,12 +776,17 @@ constexpr int kTS = kTW * kTOW;    // entry slots per (wavefront, level)
 
 bool tw_setup(int n, int N, const std::vector<int>& off, const std::vector<int>& idx,
               const std::vector<double>& rinv, int* pe, int* W, std::vector<TwEntry>& ent) {
-  // 4 or 8 points per lane (16 would leave the step's registers spilling into AGPRs);
-  // the owned width W must be at least a quarter of the range, else redundancy dominates
+  // 4 or 8 points per lane (16 would leave the step's registers spilling into AGPRs).  A
+  // step is bound by one wavefront's instruction issue, so fewer points per lane run each
+  // step faster on more wavefronts, at the price of redundant halo points: 4 points per
+  // lane while the owned width W is at least an eighth of the range (at n = 4096, N = 100:
+  // 74 wavefronts; the forward and adjoint sweeps of the PCG took 15.4 and 14.3 ms per
+  // inner loop against 19.4 and 18.9 ms with 8 points on 14), 8 points while W is at least
+  // a quarter
   int q = 4;
   for (; q <= 8; q *= 2) {
     const int E = kTW * q, w = E - 2 * N;
-    if (4 * w >= E && n >= E) break;
+    if (w > 0 && (q == 4 ? 8 : 4) * w >= E && n >= E) break;
   }
   if (q > 8 || off[N + 1] == 0) return false;
   const int E = kTW * q, Wd = E - 2 * N, nb = (n + Wd - 1) / Wd;

@@ -122,7 +122,8 @@ struct SweepModel {
 };
 
 // Trapezoid shape for the advection-diffusion sweeps of one or a few columns (the
-// smallest PE in {4, 8} with E = 64 PE, W = E - 2N, 4W >= E and n >= E) and the
+// smallest PE in {4, 8} with E = 64 PE, W = E - 2N > 0, n >= E and 8W >= E for PE = 4,
+// 4W >= E for PE = 8) and the
 // per (wavefront, level) observation slots; false when no shape fits or a wavefront's
 // level holds more observations than its slots.
 bool tw_setup(int n, int N, const std::vector<int>& off, const std::vector<int>& idx,
