@@ -166,9 +166,12 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
  * (Algorithm 4) or WC4D_RITZIT (Algorithm 5), then the spectral LMP
  * C = I + U (Theta^{-1/2} - I) U^T (eq. spectral_LMP_factor in closed form).
  * G: device n_A x m column-major (ld n_A) start matrix; the library does not
- * draw random numbers itself.  Orthonormalisation is CholeskyQR2 in float64.
- * *out receives a new LMP handle.  Synchronises s once at the end to report a
- * Cholesky failure (WC4D_ENOTSPD).  Requires 1 <= k_r, l >= 0, m <= n_A, m <= 512. */
+ * draw random numbers itself.  Orthonormalisation is CholeskyQR2 in float64; the
+ * small problem is solved by one-sided Jacobi on the device (the m x m EVD for REVD,
+ * the SVD of the triangular factor for Nystrom and ritzit).  *out receives a new LMP
+ * handle.  Synchronises s at the end to report a Cholesky failure (WC4D_ENOTSPD), and
+ * with WC4D_PREC_LMP_FP16 once more to check the float16 copy of U.  Requires
+ * 1 <= k_r, l >= 0, m <= n_A, m <= 512. */
 int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G,
                    wc4d_lmp* out, hipStream_t s);
 
