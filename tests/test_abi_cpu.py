@@ -99,3 +99,21 @@ def test_bench_helpers_on_cpu():
     other = dict(tune, segment_splits=(t["tune"].get("segment_splits") or 0) + 1)
     assert bench.measured_traffic(C3, other) is None
     assert bench.measured_traffic(C3.with_(n=512), tune) is None
+
+
+def test_committed_tuning_table_loads():
+    """The MI355X tile table shipped with the package (the benchmark's default tile
+    source) parses line by line with the library's own validating loader, and saving
+    writes back every tile choice it holds."""
+    import bench
+    from paper_2101_07249_amd import wc4d as W4
+    W4.autotune_load(bench.TUNING_TABLE)
+    rows = [l.split()[:11] for l in open(bench.TUNING_TABLE) if l.strip() and not l.startswith("#")]
+    assert rows
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "saved.txt")
+        W4.autotune_save(out)
+        saved = [l.split()[:11] for l in open(out) if not l.startswith("#")]
+    for r in rows:
+        assert r in saved, r
