@@ -110,6 +110,119 @@ def test_pcg_wrong_beta_is_caught(monkeypatch):
     assert _fails(pins.test_cg_finite_termination_on_three_distinct_eigenvalues)
 
 
+
+def test_nystrom_without_square_is_caught(monkeypatch):
+    orig = O.nystrom
+    def bad(applyA, G, k):
+        U, t = orig(applyA, G, k)
+        return U, np.sqrt(t)
+    monkeypatch.setitem(O.METHODS, "nystrom", bad)
+    assert _fails(pins.test_full_sketch_recovers_exact_spectrum, "nystrom")
+
+
+def test_nystrom_wrong_triangular_side_is_caught(monkeypatch):
+    # F C^T = E1 in place of F C = E1 (Algorithm 4's triangular solve)
+    import scipy.linalg as sla
+    def bad(applyA, G, k):
+        Z1 = O._orth(applyA(G))
+        E1 = applyA(Z1)
+        E2 = Z1.T @ E1
+        C = np.linalg.cholesky(0.5 * (E2 + E2.T)).T
+        F = sla.solve_triangular(C, E1.T, lower=False).T
+        U2, sig, _ = np.linalg.svd(F, full_matrices=False)
+        return U2[:, :k], sig[:k] ** 2
+    monkeypatch.setitem(O.METHODS, "nystrom", bad)
+    assert _fails(pins.test_full_sketch_recovers_exact_spectrum, "nystrom")
+
+
+def test_revd_keeping_smallest_pairs_is_caught(monkeypatch):
+    def bad(applyA, G, k):
+        Z1 = O._orth(applyA(G))
+        K1 = Z1.T @ applyA(Z1)
+        lam, W = np.linalg.eigh(0.5 * (K1 + K1.T))      # increasing order kept as is
+        return Z1 @ W[:, :k], lam[:k]
+    monkeypatch.setitem(O.METHODS, "revd", bad)
+    assert _fails(pins.test_invariant_subspace_gives_exact_pairs, "revd")
+    assert _fails(pins.test_ritz_values_bounds_and_orthonormality, "revd")
+
+
+def test_ritzit_wrong_gram_side_is_caught(monkeypatch):
+    # R^T R in place of R R^T: same eigenvalues, wrong eigenvectors (Algorithm 5)
+    def bad(applyA, G, k):
+        Z3, R3 = np.linalg.qr(applyA(O._orth(G)), mode="reduced")
+        th2, W3 = O._eig_desc(R3.T @ R3)
+        return Z3 @ W3[:, :k], np.sqrt(np.clip(th2[:k], 0.0, None))
+    monkeypatch.setitem(O.METHODS, "ritzit", bad)
+    assert _fails(pins.test_invariant_subspace_gives_exact_pairs, "ritzit")
+
+
+def test_observation_variance_in_place_of_its_inverse_is_caught(monkeypatch):
+    def bad(prob, X):
+        Xl = O._levels(prob, X)
+        Zl = np.zeros_like(Xl)
+        for i, idx, rdiag in prob.obs:
+            np.add.at(Zl[i], idx, Xl[i][idx] * rdiag[:, None])
+        return Zl.reshape(X.shape)
+    monkeypatch.setattr(O, "apply_HtRinvH", bad)
+    assert _fails(pins.test_A_equals_transformed_unpreconditioned_hessian, pins.tiny_advdiff)
+
+
+def test_lmp_apply_with_projector_coefficients_is_caught(monkeypatch):
+    # theta^{-1} - 1 (the projector P of eq. spectral_LMP) in place of theta^{-1/2} - 1
+    def bad(U, th, X):
+        d = 1.0 / th - 1.0
+        return X + U @ ((d if X.ndim == 1 else d[:, None]) * (U.T @ X))
+    monkeypatch.setattr(O, "lmp_apply", bad)
+    assert _fails(pins.test_lmp_factor_identities)
+
+
+def _split_pcg(c_in_r, c_in_p):
+    """Algorithm 1 with switches that drop the preconditioner from the residual update
+    (r_j = r_{j-1} - alpha A p) or from the direction (p = r + beta p)."""
+    def pcg(applyA, b, x0=None, lmp=None, tol=1e-6, maxit=100, criterion=0):
+        C = (lambda v: v) if lmp is None else (lambda v: O.lmp_apply(lmp[0], lmp[1], v))
+        x = np.zeros_like(b)
+        s = b.copy()
+        r = C(s)
+        p = C(r) if c_in_p else r.copy()
+        r0 = np.linalg.norm(r)
+        rr = r @ r
+        ht, hp = [], []
+        for it in range(1, maxit + 1):
+            Ap = applyA(p)
+            a = rr / (p @ Ap)
+            x = x + a * p
+            s = s - a * Ap
+            r = r - a * (C(Ap) if c_in_r else Ap)
+            rn = r @ r
+            p = (C(r) if c_in_p else r) + (rn / rr) * p
+            rr = rn
+            ht.append(np.linalg.norm(s) / np.linalg.norm(b))
+            hp.append(np.sqrt(rr) / r0)
+            if (ht[-1] if criterion == O.RES_TRUE else hp[-1]) <= tol:
+                break
+        ok = (ht[-1] if criterion == O.RES_TRUE else hp[-1]) <= tol
+        return O.PCGResult(x, it, ok, ht[-1], hp[-1], 0.0, ht, hp, [0.0] * it, [], [])
+    return pcg
+
+
+def test_split_pcg_rewrite_passes_the_pins(monkeypatch):
+    # the switch-free rewrite is Algorithm 1 itself: it passes the pins the mutations fail
+    monkeypatch.setattr(O, "pcg", _split_pcg(True, True))
+    pins.test_full_rank_exact_lmp_converges_in_one_iteration()
+    pins.test_pcg_precond_criterion_is_split_residual()
+
+
+def test_pcg_residual_without_preconditioner_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "pcg", _split_pcg(False, True))
+    assert _fails(pins.test_pcg_precond_criterion_is_split_residual)
+
+
+def test_pcg_direction_without_second_preconditioner_is_caught(monkeypatch):
+    monkeypatch.setattr(O, "pcg", _split_pcg(True, False))
+    assert _fails(pins.test_full_rank_exact_lmp_converges_in_one_iteration)
+
+
 # ------------------------------------------------------------ learned-sketch oracle
 import tests.test_sketchnet_oracle as skpins  # noqa: E402
 from oracle import sketchnet_oracle as SK  # noqa: E402
