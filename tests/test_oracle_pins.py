@@ -450,6 +450,50 @@ def test_pcg_precond_criterion_is_split_residual():
 # ----------------------------------------------------------------- the paper's qualitative results
 
 
+def section51_workload():
+    # Section 5.1's advection experiment: n = 40, N = 50, Courant number 0.8 with the pure
+    # upwind scheme, sigma_o = 0.05, sigma_q = 0.05, sigma_b = 0.1, length scales of 10 grid
+    # spacings, every 4th variable at every 5th step (100 observations), l = 5, k = 25.
+    return Workload(name="sec51", model="advdiff", n=40, N=50, c=0.8, r=0.0, corr="soar", Lb=10.0,
+                    Lq=10.0, sigma_b=0.1, sigma_q=0.05, obs_var_stride=4, obs_time_stride=5,
+                    sigma_o2=0.05 ** 2, m=30, l=5, seed=5100)
+
+
+@pytest.mark.parametrize("seed", [5100, 5101])
+def test_paper_section51_configuration_statements(seed):
+    """Statements of Section 5.1 about its own configuration that a seeded Gaussian start
+    block reproduces: Nystrom's leading Ritz values are the most accurate, REVD's slightly
+    worse and ritzit's far too small; every preconditioned spectrum drops below one at its
+    lower end (REVD furthest, ritzit least) and its largest eigenvalue is far below A's;
+    the Nystrom and ritzit LMPs give a smaller condition number than the REVD one; and with
+    either of them the quadratic cost falls faster than without preconditioning."""
+    w = section51_workload()
+    prob = build(w)
+    assert (prob.n_A, prob.q) == (2040, 100)
+    A = O.dense_A(prob)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    G = sketch_block(prob.n_A, w.m, seed)
+    k = w.m - w.l
+    top5, mu_min, mu_max, J = {}, {}, {}, {}
+    b = O.rhs(prob, innovations(prob.q, seed, 0.05))
+    J[None] = O.pcg(lambda v: A @ v, b, tol=1e-14, maxit=5).hist_J
+    for method in ("revd", "nystrom", "ritzit"):
+        U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, k)
+        assert np.all(th <= lam[:k] * (1 + 1e-10))
+        top5[method] = np.max(np.abs(th[:5] - lam[:5]) / lam[:5])
+        C = O.lmp_dense_C(U, th)
+        mu = np.linalg.eigvalsh(C @ A @ C)
+        mu_min[method], mu_max[method] = mu.min(), mu.max()
+        J[method] = O.pcg(lambda v: A @ v, b, lmp=(U, th), tol=1e-14, maxit=5).hist_J
+    assert top5["nystrom"] < 1e-3 and top5["nystrom"] < top5["revd"] < 0.1 and top5["ritzit"] > 0.5
+    assert mu_min["revd"] < mu_min["nystrom"] < mu_min["ritzit"] < 1.0 and mu_min["revd"] < 0.5
+    assert max(mu_max.values()) < 0.05 * lam[0]
+    cond = {m_: mu_max[m_] / mu_min[m_] for m_ in mu_max}
+    assert cond["nystrom"] < cond["revd"] and cond["ritzit"] < cond["revd"]
+    for method in ("nystrom", "ritzit"):
+        assert np.all(np.array(J[method][:5]) < np.array(J[None][:5]))
+
+
 def test_paper_qualitative_lmp_spectra_on_advection():
     # Section 5.1: the REVD-LMP pushes the smallest eigenvalue of C^T A C below one, the
     # Nystrom and ritzit LMPs keep it close to one; ritzit underestimates the largest
