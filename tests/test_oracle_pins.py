@@ -453,7 +453,8 @@ def test_pcg_precond_criterion_is_split_residual():
 def section51_workload():
     # Section 5.1's advection experiment: n = 40, N = 50, Courant number 0.8 with the pure
     # upwind scheme, sigma_o = 0.05, sigma_q = 0.05, sigma_b = 0.1, length scales of 10 grid
-    # spacings, every 4th variable at every 5th step (100 observations), l = 5, k = 25.
+    # spacings, every 4th variable at every 5th step (100 observations), l = 5, k = 25.  SOAR
+    # stands in for Q's Laplacian correlation, which the paper does not specify.
     return Workload(name="sec51", model="advdiff", n=40, N=50, c=0.8, r=0.0, corr="soar", Lb=10.0,
                     Lq=10.0, sigma_b=0.1, sigma_q=0.05, obs_var_stride=4, obs_time_stride=5,
                     sigma_o2=0.05 ** 2, m=30, l=5, seed=5100)
