@@ -117,3 +117,15 @@ def test_committed_tuning_table_loads():
         saved = [l.split()[:11] for l in open(out) if not l.startswith("#")]
     for r in rows:
         assert r in saved, r
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message and status 2
+    before any device work."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
