@@ -304,13 +304,53 @@ def test_ritz_values_bounds_and_orthonormality(method):
     np.testing.assert_allclose(U.T @ U, np.eye(C1.k_r), atol=1e-10)
 
 
+def _table1():
+    with open(os.path.join(GOLDEN, "table1.json")) as f:
+        return json.load(f)["methods"]
+
+
 def test_block_product_counts_match_table_1():
     prob = build(C1)
     G = sketch_block(prob.n_A, C1.m, C1.seed)
-    for method, count in (("revd", 2), ("nystrom", 2), ("ritzit", 1)):
+    for method, row in _table1().items():
         prob.n_apply = 0
         O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
-        assert prob.n_apply == count
+        assert prob.n_apply == row["products_with_A"]
+
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_dense_operations_match_table_1(method, monkeypatch):
+    """Every dense factorisation the oracle performs, by kind and operand shape, is the one
+    Table 1 lists for the method: orthogonalisation and QR of n_A x (k+l) blocks, Cholesky,
+    EVD of (k+l) x (k+l) matrices, the triangular solve and SVD of Nystrom's F."""
+    prob = build(C1)
+    m = C1.m
+    G = sketch_block(prob.n_A, m, C1.seed)
+    calls = []
+
+    def shape_of(a):
+        return {(prob.n_A, m): "nA", (m, prob.n_A): "nA", (m, m): "small"}[tuple(np.shape(a))]
+
+    def spy(kind, fn, arg=0):
+        def wrapped(*a, **kw):
+            calls.append((kind, shape_of(a[arg]), a[arg]))
+            return fn(*a, **kw)
+        return wrapped
+
+    monkeypatch.setattr(np.linalg, "qr", spy("qr", np.linalg.qr))
+    monkeypatch.setattr(np.linalg, "cholesky", spy("cholesky", np.linalg.cholesky))
+    monkeypatch.setattr(np.linalg, "eigh", spy("evd", np.linalg.eigh))
+    monkeypatch.setattr(np.linalg, "svd", spy("svd", np.linalg.svd))
+    monkeypatch.setattr(sla, "solve_triangular", spy("triangular_solve", sla.solve_triangular, 1))
+    O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.k_r)
+    row = _table1()[method]
+    # the first QR-type call orthogonalises G itself (ritzit) or Y = A G (REVD, Nystrom)
+    first = calls[0]
+    assert first[0] == "qr" and first[1] == "nA"
+    assert np.array_equal(first[2], G) == (row["orthogonalise"] == "G")
+    rest = calls[1:]
+    for kind in ("qr", "cholesky", "triangular_solve", "evd", "svd"):
+        assert sorted(s_ for k_, s_, _ in rest if k_ == kind) == sorted(row[kind]), (method, kind)
 
 
 @pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
