@@ -535,6 +535,38 @@ def test_paper_section51_configuration_statements(seed):
         assert np.all(np.array(J[method][:5]) < np.array(J[None][:5]))
 
 
+def test_paper_section52_lorenz96_statements():
+    """Section 5.2's Lorenz-96 configuration (n = 80, N = 150, F = 8, RK4 with dt = 0.025,
+    sigma_o = 0.15, sigma_b = 0.2, sigma_q = 0.1, length scales 2 grid spacings, every 10th
+    variable at every 10th step: 120 observations; k = 5, l = 5; SOAR stands in for Q's
+    unspecified Laplacian correlation).  The section reports that ritzit gives the worst
+    estimate of the largest eigenvalue, and that the smallest eigenvalue of C^T A C is one
+    for the Nystrom and ritzit LMPs but below one for REVD's.  A - I has rank q, so every
+    eigenvalue of C^T A C other than one lies in span(U, range(A - I)); the test takes them
+    from that subspace, exactly, without forming the 12080 x 12080 matrix."""
+    w = Workload(name="sec52", model="l96", n=80, N=150, F=8.0, dt=0.025, corr="soar", Lb=2.0, Lq=2.0,
+                 sigma_b=0.2, sigma_q=0.1, obs_var_stride=10, obs_time_stride=10, sigma_o2=0.15 ** 2,
+                 m=10, l=5, seed=5200)
+    prob = build(w)
+    assert (prob.n_A, prob.q) == (12080, 120)
+    HtR = np.stack([O.apply_HtRinv(prob, e) for e in np.eye(prob.q)], axis=1)
+    QW, _ = np.linalg.qr(O.apply_Dsqrt(prob, O.apply_LinvT(prob, HtR)))   # range(A - I)
+    lam = np.linalg.eigvalsh(QW.T @ O.apply_A(prob, QW))
+    lam_max = lam.max()
+    G = sketch_block(prob.n_A, w.m, w.seed)
+    err, mu_min = {}, {}
+    for method in ("revd", "nystrom", "ritzit"):
+        U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, w.m - w.l)
+        err[method] = abs(th[0] - lam_max) / lam_max
+        S, _ = np.linalg.qr(np.hstack([U, QW]))
+        M = S.T @ O.lmp_apply(U, th, O.apply_A(prob, O.lmp_apply(U, th, S)))
+        mu_min[method] = min(1.0, np.linalg.eigvalsh(0.5 * (M + M.T)).min())
+    assert err["ritzit"] > 0.5 and max(err["revd"], err["nystrom"]) < 1e-3
+    # "equal to one" as an iterative eigensolver reports it: to three digits
+    assert mu_min["nystrom"] >= 1.0 - 1e-3 and mu_min["ritzit"] >= 1.0 - 1e-3
+    assert mu_min["revd"] < 0.99
+
+
 def test_paper_qualitative_lmp_spectra_on_advection():
     # Section 5.1: the REVD-LMP pushes the smallest eigenvalue of C^T A C below one, the
     # Nystrom and ritzit LMPs keep it close to one; ritzit underestimates the largest
