@@ -543,7 +543,6 @@ int lmp_pan_t_splits(long long nA, int k, LmpFmt fmt) {
   return fmt == LMP_P16 ? rows_grid(nA) : pan_t_splits(nA, k);
 }
 
-// partials of U^T x over the panel copy (either precision); returns the split count
 // partials of U^T x over the panel copy (either precision); returns the split count and the
 // partials' strides (split, column)
 static int launch_pan_t_partial(long long nA, int k, const LmpU& U, const double* x, double* part,
