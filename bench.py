@@ -289,7 +289,7 @@ def cpu_baseline(w, pat, gpu_iters, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.mfma_probe:
         mfma_probe()
