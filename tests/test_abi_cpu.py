@@ -129,3 +129,12 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; there is no fallback path."""
+    from paper_2101_07249_amd import wc4d as W4
+    monkeypatch.setattr(W4, "_lib", None)
+    monkeypatch.setattr(W4, "LIB_PATH", str(tmp_path / "libwc4d.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        W4.lib()
