@@ -24,13 +24,9 @@
 namespace wc4d {
 
 constexpr int kLT = 256;  // threads per block
-constexpr int kLE = 2;    // rows per thread (x + U t pass)
 constexpr int kLC = 8;    // columns per group (x + U t pass)
-constexpr int kLRows = kLT * kLE;
 constexpr int kTG = 32;   // columns per workgroup (U^T x pass)
 constexpr int kTU = 1;    // row unroll (U^T x pass)
-
-static inline long long lmp_chunks(long long nA) { return (nA + kLRows - 1) / kLRows; }
 
 size_t lmp_panel_elems(long long nA, int k) { return (size_t)lmp_panels(nA) * kPanel * k; }
 
@@ -155,15 +151,10 @@ __global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
 }
 
-// 4 consecutive rows per thread: one 16-byte (float) or two 16-byte (double) loads per
-// column; requires ldu % 4 == 0 (U is allocated that way) and 16-byte aligned x, y.
+// 4 consecutive rows per thread: two 16-byte loads per column; requires ldu % 4 == 0
+// (U is allocated that way) and 16-byte aligned x, y.
 template <typename T>
 static __device__ inline void load4(const T* p, double (&v)[4]);
-template <>
-__device__ inline void load4<float>(const float* p, double (&v)[4]) {
-  const float4 f = *reinterpret_cast<const float4*>(p);
-  v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
-}
 template <>
 __device__ inline void load4<double>(const double* p, double (&v)[4]) {
   const double2 a = *reinterpret_cast<const double2*>(p);

@@ -425,11 +425,6 @@ constexpr int kDC = 16;  // columns per group
 template <typename T>
 static __device__ inline void ld4(const T* p, double (&v)[4]);
 template <>
-__device__ inline void ld4<float>(const float* p, double (&v)[4]) {
-  const float4 f = *reinterpret_cast<const float4*>(p);
-  v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
-}
-template <>
 __device__ inline void ld4<double>(const double* p, double (&v)[4]) {
   const double2 a = *reinterpret_cast<const double2*>(p);
   const double2 b = *reinterpret_cast<const double2*>(p + 2);
