@@ -248,6 +248,47 @@ def test_rhs_matches_dense_formula():
     np.testing.assert_allclose(O.rhs(prob, d), want, atol=1e-12 * np.abs(want).max())
 
 
+
+@pytest.mark.parametrize("maker", [tiny_advdiff, tiny_l96])
+def test_solution_minimises_the_forcing_cost_function(maker):
+    """A x = rhs is the stationarity condition of the forcing-formulation cost (Section 2.1,
+    its quadratic inner-loop form; Section 2.2's variable change p = D^{1/2} x):
+    J(p) = p^T D^{-1} p / 2 + (H L^{-1} p - d)^T R^{-1} (H L^{-1} p - d) / 2.  The minimiser
+    is found here as a stacked least-squares problem, independently of A and rhs, and the
+    PCG cost diagnostic plus d^T R^{-1} d / 2 equals J at every iterate."""
+    prob = build(maker())
+    d = innovations(prob.q, 21, 0.1)
+    Ds = O.dense_D(prob, "sqrt")
+    Dmh = np.linalg.inv(Ds)
+    Li = O.dense_Linv(prob)
+    H, Ri = O.dense_H_Rinv(prob)
+    Rmh = np.diag(np.sqrt(np.diag(Ri)))
+    M = np.vstack([Dmh, Rmh @ H @ Li])
+    t = np.concatenate([np.zeros(prob.n_A), Rmh @ d])
+    p_star = np.linalg.lstsq(M, t, rcond=None)[0]
+    x = np.linalg.solve(O.dense_A(prob), O.rhs(prob, d))
+    np.testing.assert_allclose(Ds @ x, p_star, atol=1e-9 * np.abs(p_star).max())
+
+    def cost(p):
+        e = H @ Li @ p - d
+        return 0.5 * p @ np.linalg.solve(Ds @ Ds, p) + 0.5 * e @ Ri @ e
+
+    res = O.pcg(lambda v: O.apply_A(prob, v), O.rhs(prob, d), tol=1e-12, maxit=3)
+    xs = [np.zeros(prob.n_A)]
+    r = O.rhs(prob, d)
+    pvec = r.copy()
+    A = O.dense_A(prob)
+    for _ in range(res.iters):          # the textbook CG iterates, to evaluate J on each
+        a = (r @ r) / (pvec @ A @ pvec)
+        xs.append(xs[-1] + a * pvec)
+        rn = r - a * (A @ pvec)
+        pvec = rn + (rn @ rn) / (r @ r) * pvec
+        r = rn
+    c0 = 0.5 * d @ Ri @ d
+    for j in range(res.iters):
+        np.testing.assert_allclose(res.hist_J[j] + c0, cost(Ds @ xs[j + 1]), rtol=1e-9)
+
+
 def test_dsqrt_squares_to_covariance():
     w = tiny_advdiff()
     prob = build(w)
