@@ -138,3 +138,30 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(W4, "LIB_PATH", str(tmp_path / "libwc4d.so"))
     with pytest.raises(ImportError, match="no fallback"):
         W4.lib()
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle imports nothing from the library package, the package never imports the
+    oracle, and the seeded input module imports neither."""
+    import ast
+    import glob
+
+    def imported(path):
+        tree = ast.parse(open(path).read())
+        mods = set()
+        for node in ast.walk(tree):
+            if isinstance(node, ast.Import):
+                mods.update(a.name.split(".")[0] for a in node.names)
+            elif isinstance(node, ast.ImportFrom) and node.module and node.level == 0:
+                mods.add(node.module.split(".")[0])
+        return mods
+
+    for path in glob.glob(os.path.join(ROOT, "oracle", "*.py")):
+        assert not imported(path) & {"paper_2101_07249_amd", "synthetic"}, path
+        assert "libwc4d" not in open(path).read(), path
+    for path in glob.glob(os.path.join(ROOT, "paper_2101_07249_amd", "*.py")):
+        assert "oracle" not in imported(path), path
+    for path in glob.glob(os.path.join(ROOT, "synthetic", "*.py")):
+        assert not imported(path) & {"oracle", "paper_2101_07249_amd"}, path
+    for path in glob.glob(os.path.join(ROOT, "paper_2101_07249_amd", "csrc", "*")):
+        assert "oracle" not in open(path).read(), path
