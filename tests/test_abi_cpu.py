@@ -165,3 +165,31 @@ def test_oracle_and_library_share_no_code():
         assert not imported(path) & {"oracle", "paper_2101_07249_amd"}, path
     for path in glob.glob(os.path.join(ROOT, "paper_2101_07249_amd", "csrc", "*")):
         assert "oracle" not in open(path).read(), path
+
+
+
+def test_profile_commands_run_committed_files_with_known_flags():
+    """Every command recorded in profiles/ runs a file of the repository (never a scratch
+    script) and passes bench.py only options its --help lists."""
+    import glob
+    import re
+    import shlex
+    import subprocess
+    import sys
+    helptext = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                              capture_output=True, text=True, timeout=300).stdout
+    opts = set(re.findall(r"(--[a-z0-9-]+)", helptext))
+    assert "--steps" in opts and "--copy-probe" in opts
+    cmds = [l.strip() for p in glob.glob(os.path.join(ROOT, "profiles", "*.md"))
+            for l in open(p) if l.startswith("    ") and ("python" in l or "rocprofv3" in l)]
+    assert cmds
+    for c in cmds:
+        toks = shlex.split(c.replace("<out>", "OUT"))
+        paths = [t for t in toks if t.startswith("/root/repo/")]
+        assert paths, c
+        for t in paths:
+            rel = os.path.relpath(t, "/root/repo")
+            assert not rel.startswith("_work") and os.path.exists(os.path.join(ROOT, rel)), c
+        for t in toks[toks.index(paths[0]) + 1:]:
+            if t.startswith("--"):
+                assert t in opts, (t, c)
