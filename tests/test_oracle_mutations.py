@@ -133,6 +133,7 @@ def test_nystrom_wrong_triangular_side_is_caught(monkeypatch):
         return U2[:, :k], sig[:k] ** 2
     monkeypatch.setitem(O.METHODS, "nystrom", bad)
     assert _fails(pins.test_full_sketch_recovers_exact_spectrum, "nystrom")
+    assert _fails(pins.test_untruncated_outputs_equal_closed_forms, "nystrom")
 
 
 def test_revd_keeping_smallest_pairs_is_caught(monkeypatch):
@@ -154,6 +155,7 @@ def test_ritzit_wrong_gram_side_is_caught(monkeypatch):
         return Z3 @ W3[:, :k], np.sqrt(np.clip(th2[:k], 0.0, None))
     monkeypatch.setitem(O.METHODS, "ritzit", bad)
     assert _fails(pins.test_invariant_subspace_gives_exact_pairs, "ritzit")
+    assert _fails(pins.test_untruncated_outputs_equal_closed_forms, "ritzit")
 
 
 def test_observation_variance_in_place_of_its_inverse_is_caught(monkeypatch):

@@ -350,6 +350,31 @@ def _table1():
         return json.load(f)["methods"]
 
 
+
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+def test_untruncated_outputs_equal_closed_forms(method):
+    """Keeping all m pairs, each method's U diag(.) U^T is a matrix with a closed form in the
+    sketch (Section 4): REVD the Rayleigh-Ritz projection P_Z A P_Z with Z = orth(A G);
+    Nystrom the approximation (A Z)(Z^T A Z)^{-1}(A Z)^T; ritzit Y Y^T = U Theta^2 U^T with
+    Y = A orth(G).  The closed forms use a plain solve, not the algorithms' Cholesky,
+    triangular solve, SVD or EVD."""
+    prob = build(C1)
+    A = O.dense_A(prob)
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.METHODS[method](lambda X: O.apply_A(prob, X), G, C1.m)
+    if method == "revd":
+        Z = np.linalg.qr(A @ G)[0]
+        want, got = Z @ (Z.T @ A @ Z) @ Z.T, U @ np.diag(th) @ U.T
+    elif method == "nystrom":
+        Z = np.linalg.qr(A @ G)[0]
+        E1 = A @ Z
+        want, got = E1 @ np.linalg.solve(Z.T @ E1, E1.T), U @ np.diag(th) @ U.T
+    else:
+        Y = A @ np.linalg.qr(G)[0]
+        want, got = Y @ Y.T, U @ np.diag(th ** 2) @ U.T
+    np.testing.assert_allclose(got, want, atol=1e-9 * np.abs(want).max())
+
+
 def test_block_product_counts_match_table_1():
     prob = build(C1)
     G = sketch_block(prob.n_A, C1.m, C1.seed)
