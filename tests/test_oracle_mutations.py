@@ -284,3 +284,43 @@ def test_adam_without_bias_correction_is_caught(monkeypatch):
         return theta
     monkeypatch.setattr(SK, "adam_step", bad)
     assert _fails(skpins.test_adam_first_steps)
+
+
+# ---- the counter-based Gaussian generator (oracle/philox.py)
+
+def _philox_pins():
+    import tests.test_philox_oracle as pp
+    return pp
+
+
+def test_philox_key_bumped_before_first_round_is_caught(monkeypatch):
+    from oracle import philox as P
+    pp = _philox_pins()
+    orig = P.philox4x32_10
+    monkeypatch.setattr(P, "philox4x32_10",
+                        lambda ctr, key: orig(ctr, ((int(key[0]) + P.W0) & P.MASK32, (int(key[1]) + P.W1) & P.MASK32)))
+    assert _fails(pp.test_philox_known_answer_vectors, 0)
+
+
+def test_philox_swapped_multipliers_are_caught(monkeypatch):
+    from oracle import philox as P
+    pp = _philox_pins()
+    monkeypatch.setattr(P, "M0", 0xCD9E8D57)
+    monkeypatch.setattr(P, "M1", 0xD2511F53)
+    assert _fails(pp.test_philox_known_answer_vectors, 2)
+
+
+def test_box_muller_same_angle_function_is_caught(monkeypatch):
+    from oracle import philox as P
+    pp = _philox_pins()
+    monkeypatch.setattr(P, "box_muller", lambda u1, u2: (np.sqrt(-2 * np.log(u1)) * np.cos(P.TWO_PI * u2),) * 2)
+    assert _fails(pp.test_box_muller_closed_forms)
+    assert _fails(pp.test_block_is_standard_normal)
+
+
+def test_uniform_without_half_offset_is_caught(monkeypatch):
+    from oracle import philox as P
+    pp = _philox_pins()
+    orig = P.uniform52
+    monkeypatch.setattr(P, "uniform52", lambda a, b: orig(a, b) - 0.5 / 2.0 ** 52)
+    assert _fails(pp.test_uniform52_closed_forms)
