@@ -104,8 +104,6 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-cols", type=int, default=8)
-    ap.add_argument("--cpu-sample-iters", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sketch comparison")
     ap.add_argument("--learned-steps", type=int, default=2)
     ap.add_argument("--batched", action="store_true", help="also time the 64-problem batched solve")
@@ -118,21 +116,7 @@ def parse():
                     help="only run a plain 1 GiB device copy 5 times (reference for HBM counters)")
     ap.add_argument("--prof-every", type=int, default=8,
                     help="time one launch group in this many of the dominant class in the timed steps")
-    ap.add_argument("--mfma-probe", action="store_true",
-                    help="only measure the float64 MFMA rate of a register-only stream (roofline reference)")
     return ap.parse_args()
-
-
-def mfma_probe():
-    """Float64 matrix rate the part sustains: a register-only v_mfma_f64_16x16x4 stream with
-    1, 2 and 4 waves per SIMD, in short (about 1 ms) and long (about 10-40 ms) launches."""
-    from paper_2101_07249_amd import wc4d as W4
-    rows = []
-    for waves in (1, 2, 4):
-        for iters in (2000, 20000):
-            rows.append({"waves_per_simd": waves, "mfma_per_wave": iters * 8,
-                         "tflops": round(W4.probe_mfma_f64(waves, iters, 5), 2)})
-    print(json.dumps({"mfma_f64_probe": rows, "published_peak_tflops": FP64_PEAK_TFLOPS}), flush=True)
 
 
 def copy_probe():
@@ -244,15 +228,15 @@ def batched_section(args):
 
 
 def cpu_baseline(w, pat, gpu_iters, args):
-    """Time the oracle on a bounded sample of the same workload and scale it to one step:
-    block apply of a few sketch columns (scaled to the 2 m columns of a two-pass build),
-    Householder QR of a 64-column slab (scaled by (m/64)^2 per orthonormalisation, two
-    per build), and a few PCG iterations with a k_r-column LMP (scaled to the GPU run's
-    iteration count)."""
+    """The oracle's whole inner loop on the same workload, measured (not extrapolated):
+    the right-hand side, the randomised build from the same seeded Gaussian block (the
+    oracle draws it with its own Philox-4x32-10 + Box-Muller) and PCG with the LMP until
+    the true relative residual reaches the tolerance."""
     import numpy as np
 
+    from oracle import philox as PX
     from oracle import wc4d_oracle as O
-    from synthetic import innovations, random_block, sketch_block
+    from synthetic import innovations
 
     try:
         from threadpoolctl import threadpool_info
@@ -260,30 +244,27 @@ def cpu_baseline(w, pat, gpu_iters, args):
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
     op = O.make_problem(w, pat)
-    cols = args.cpu_sample_cols
-    G = np.asfortranarray(sketch_block(op.n_A, w.m, w.seed)[:, :cols])
+    d = innovations(op.q, w.seed, np.sqrt(w.sigma_o2))
+    print(f"cpu_baseline: oracle inner loop on {w.name} ({cores} threads): build", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    O.apply_A(op, G)
-    t_apply_col = (time.perf_counter() - t0) / cols
-    slab = np.asfortranarray(G[:, :min(64, w.m)]) if cols >= 64 else random_block(op.n_A, min(64, w.m), 5)
-    t0 = time.perf_counter()
-    np.linalg.qr(slab, mode="reduced")
-    t_qr = (time.perf_counter() - t0) * (w.m / slab.shape[1]) ** 2
-    # LMP of the right size (values do not change the timing of the sample)
-    U = random_block(op.n_A, w.k_r, 6)
-    theta = np.linspace(1e4, 2.0, w.k_r)
-    b = O.rhs(op, innovations(op.q, w.seed, np.sqrt(w.sigma_o2)))
-    it = args.cpu_sample_iters
-    t0 = time.perf_counter()
-    O.pcg(lambda v: O.apply_A(op, v), b, lmp=(U, theta), tol=0.0, maxit=it)
-    t_iter = (time.perf_counter() - t0) / it
-    est_ms = 1e3 * (2 * w.m * t_apply_col + 2 * t_qr + gpu_iters * t_iter)
-    return {"value": est_ms, "unit": "ms per step (estimated)", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle on the same workload: block apply of {cols} sketch columns "
-                       f"({1e3 * t_apply_col:.1f} ms/column, scaled to 2 x {w.m}), Householder QR of a "
-                       f"{slab.shape[1]}-column slab (scaled by (m/64)^2, two per build: {1e3 * t_qr:.0f} ms), "
-                       f"{it} PCG iterations with a {w.k_r}-vector LMP ({1e3 * t_iter:.0f} ms/iteration, "
-                       f"scaled to {gpu_iters} iterations); EVD of the m x m matrix not included")}
+    b = O.rhs(op, d)
+    G = PX.gaussian_block(w.seed, op.n_A, w.m)
+    t1 = time.perf_counter()
+    U, theta = O.METHODS[args.method](lambda X: O.apply_A(op, X), G, w.k_r)
+    t2 = time.perf_counter()
+    print(f"cpu_baseline: build {t2 - t1:.1f} s; PCG", file=sys.stderr, flush=True)
+    res = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(U, theta), tol=args.tol, maxit=args.maxit)
+    t3 = time.perf_counter()
+    print(f"cpu_baseline: PCG {t3 - t2:.1f} s, {res.iters} iterations", file=sys.stderr, flush=True)
+    return {"value": 1e3 * (t3 - t0), "unit": "ms per step", "cores": int(cores), "kind": "oracle",
+            "scope": "measured in full: one whole inner loop, not extrapolated",
+            "sample": (f"one inner loop of {w.name} (the benchmark's workload and seed): rhs + Gaussian block "
+                       f"{1e3 * (t1 - t0):.0f} ms, {args.method} build with m = {w.m} "
+                       f"{1e3 * (t2 - t1):.0f} ms, PCG to a true relative residual of {args.tol:g} "
+                       f"{1e3 * (t3 - t2):.0f} ms ({res.iters} iterations, {1e3 * (t3 - t2) / max(res.iters, 1):.0f} "
+                       f"ms/iteration)"),
+            "oracle_pcg_iters": int(res.iters), "oracle_relres_true": float(res.relres_true),
+            "oracle_converged": bool(res.converged), "gpu_pcg_iters_fp64": gpu_iters}
 
 
 def main():
@@ -291,9 +272,6 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    if args.mfma_probe:
-        mfma_probe()
-        return
     if args.copy_probe:
         copy_probe()
         return
@@ -301,7 +279,7 @@ def main():
     import torch
 
     from paper_2101_07249_amd import Problem
-    from synthetic import WORKLOADS, innovations, obs_pattern, sketch_block
+    from synthetic import WORKLOADS, innovations, obs_pattern
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -311,7 +289,7 @@ def main():
     dev = torch.device("cuda", 0)
     w = WORKLOADS[args.workload]
     pat = obs_pattern(w)
-    G = torch.from_numpy(np.ascontiguousarray(sketch_block(w.n_A, w.m, w.seed).T)).to(dev)
+    G = W4.gaussian_block(w.seed, w.n_A, w.m)   # the start block the seeded builds draw
     dnp = innovations(sum(len(i) for _, i in pat), w.seed, np.sqrt(w.sigma_o2))
     d = torch.from_numpy(dnp).to(dev)
     x = torch.zeros(w.n_A, dtype=torch.float64, device=dev)
@@ -338,7 +316,8 @@ def main():
 
         def step():
             b = prob.rhs(d)
-            L = prob.lmp_build(args.method, w.k_r, w.l, G)
+            # the Gaussian start block is drawn on the device inside the build (seeded)
+            L = prob.lmp_build(args.method, w.k_r, w.l, seed=w.seed)
             x.zero_()
             info = prob.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
             info["lmp_copy"] = L.copy_format()
@@ -451,7 +430,8 @@ def main():
     if args.batched:
         out["batched"] = batched_section(args)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, pat, iters, args)
+        out["cpu_baseline"] = cpu_baseline(w, pat, results["plain"]["pcg_iters"] if "plain" in results else None,
+                                           args)
     print(json.dumps(out), flush=True)
 
 

@@ -161,19 +161,40 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
 
 /* -------------------------------------------------------- preconditioner -- */
 
+/* Gaussian start block of Section 4 (Algorithms 3-5: G has independent N(0, 1) entries),
+ * drawn on the device with Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) and
+ * the Box-Muller transform.  Entry (r, c) of the block of `seed` uses key (seed mod 2^32,
+ * seed >> 32) and counter (r >> 1, c, 0, 0); the words w0..w3 give the uniforms
+ * u1 = ((w0 >> 6) 2^26 + (w1 >> 6) + 1/2) 2^-52 and u2 from (w2, w3) likewise; even
+ * rows hold sqrt(-2 ln u1) cos(2 pi u2), odd rows sqrt(-2 ln u1) sin(2 pi u2).
+ * wc4d_gaussian_block writes entries (r, col0 + c), r < n_rows, c < n_cols, into G
+ * (device on `device`, column-major, ldg >= n_rows), so a column range of a block can be
+ * drawn separately with the same values.  WC4D_EINVAL for negative sizes, ldg < n_rows, a
+ * null G with a non-empty block, col0 + n_cols > 2^32 or an invalid device. */
+int wc4d_gaussian_block(int device, unsigned long long seed, long long n_rows, int n_cols, long long col0,
+                        double* G, long long ldg, hipStream_t s);
+/* The generator's raw words, for checking against its published known-answer vectors:
+ * for t < count, out[4t..4t+3] = Philox-4x32-10 of counter ctr_key[6t..6t+3] under key
+ * (ctr_key[6t+4], ctr_key[6t+5]).  ctr_key, out: device arrays on `device`. */
+int wc4d_philox4x32_10(int device, const unsigned int* ctr_key, unsigned int* out, long long count,
+                       hipStream_t s);
+
 /* Randomised estimate of the k_r leading eigenpairs of A from a sketch of width
  * m = k_r + l (Section 4): method WC4D_REVD (Algorithm 3), WC4D_NYSTROM
  * (Algorithm 4) or WC4D_RITZIT (Algorithm 5), then the spectral LMP
  * C = I + U (Theta^{-1/2} - I) U^T (eq. spectral_LMP_factor in closed form).
- * G: device n_A x m column-major (ld n_A) start matrix; the library does not
- * draw random numbers itself.  Orthonormalisation is CholeskyQR2 in float64; the
+ * G: device n_A x m column-major (ld n_A) start matrix supplied by the caller, or NULL:
+ * the build then draws the n_A x m Gaussian block of `seed` (wc4d_gaussian_block) on the
+ * device into its own scratch (seed is ignored when G is given).
+ * Orthonormalisation is CholeskyQR2 in float64; the
  * small problem is solved by one-sided Jacobi on the device (the m x m EVD for REVD,
  * the SVD of the triangular factor for Nystrom and ritzit).  *out receives a new LMP
- * handle.  Synchronises s at the end to report a Cholesky failure (WC4D_ENOTSPD), and
- * with WC4D_PREC_LMP_FP16 once more to check the float16 copy of U.  Requires
- * 1 <= k_r, l >= 0, m <= n_A, m <= 512. */
+ * handle.  Synchronises s at the end to report a Cholesky failure (WC4D_ENOTSPD) or a
+ * Jacobi iteration that has not converged after 20 sweeps (WC4D_ENOCONV; no LMP is
+ * returned then), and with WC4D_PREC_LMP_FP16 once more to check the float16 copy of U.
+ * Requires 1 <= k_r, l >= 0, m <= n_A, m <= 512. */
 int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G,
-                   wc4d_lmp* out, hipStream_t s);
+                   unsigned long long seed, wc4d_lmp* out, hipStream_t s);
 
 /* Ritz values theta (host, k_r doubles, decreasing).  Synchronous. */
 int wc4d_lmp_theta(wc4d_lmp L, double* theta_host);
@@ -286,14 +307,6 @@ int wc4d_autotune_info(wc4d_problem p, int m, int* tile_b, int* tile_q, int* two
  * WC4D_EINVAL on an unreadable file or a malformed line (nothing is merged then). */
 int wc4d_autotune_save(const char* path);
 int wc4d_autotune_load(const char* path);
-
-/* Hardware reference for the float64 roofline (not part of the method): runs a
- * register-only stream of v_mfma_f64_16x16x4_f64 on `device` (waves_per_simd 1..8 waves on
- * every SIMD, each issuing iters x 8 MFMAs; one warm-up launch, then reps timed launches on
- * the null stream) and reports the achieved float64 matrix rate in *tflops.  Allocates and
- * frees its own output buffer; synchronises the device.  WC4D_EINVAL on bad arguments,
- * WC4D_EHIP on a HIP failure. */
-int wc4d_probe_mfma_f64(int device, int waves_per_simd, int iters, int reps, double* tflops);
 
 /* Solve `count` independent inner loops (Section 2.2 / Algorithm 1) at once: for each
  * problem ps[i] (finalized, all on one device, none repeated) an LMP of k_r Ritz pairs

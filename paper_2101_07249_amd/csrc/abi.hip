@@ -744,15 +744,25 @@ int cholqr2(wc4d_problem p, double* Y, double* tmp, int m, Small& sm, double* Ro
   return WC4D_OK;
 }
 
-int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
-                   hipStream_t s) {
+// The start block G of Algorithms 3-5: the caller's (G != null), or the n_A x m Gaussian
+// block of `seed` drawn on the device into dst (*Guse then points at dst).
+int start_block(wc4d_problem p, const double* G, unsigned long long seed, int m, double* dst,
+                const double** Guse, hipStream_t s) {
+  *Guse = G;
+  if (G != nullptr) return WC4D_OK;
+  HIPCHK(p, gauss_block(seed, p->nA, m, 0, dst, p->nA, s));
+  *Guse = dst;
+  return WC4D_OK;
+}
+
+int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, unsigned long long seed,
+                   wc4d_lmp* out, hipStream_t s) {
   if (out == nullptr) return WC4D_EINVAL;
   *out = nullptr;
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   const int m = k_r + l;
-  if (method < WC4D_REVD || method > WC4D_RITZIT || k_r < 1 || l < 0 || G == nullptr || m > p->nA ||
-      m > 512)
-    return fail(p, WC4D_EINVAL, "invalid LMP arguments (method, k_r >= 1, l >= 0, m <= min(n_A, 512), G)");
+  if (method < WC4D_REVD || method > WC4D_RITZIT || k_r < 1 || l < 0 || m > p->nA || m > 512)
+    return fail(p, WC4D_EINVAL, "invalid LMP arguments (method, k_r >= 1, l >= 0, m <= min(n_A, 512))");
   DevGuard g(p->device);
   int rc = ensure_build(p, m);
   if (rc) return rc;
@@ -785,6 +795,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
                  : (p->prec & WC4D_PREC_SKETCH_FP16X3) ? SPLIT_FP16 : SPLIT_NONE;
   if (method == WC4D_REVD) {
     // Algorithm 3: Y = A G; Z = orth(Y); K = Z^T A Z; EVD; U = Z W
+    if ((rc = start_block(p, G, seed, m, B_, &G, s))) return cleanup(rc);
     if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s, mx))) return cleanup(rc);
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
     if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
@@ -795,6 +806,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
   } else if (method == WC4D_NYSTROM) {
     // Algorithm 4: Y = A G; Z = orth(Y); E1 = A Z; E2 = Z^T E1 = C^T C; F = E1 C^{-1};
     // SVD F = U Sigma V^T via F = Q_F R_F and the EVD of R_F R_F^T; Theta = Sigma^2
+    if ((rc = start_block(p, G, seed, m, B_, &G, s))) return cleanup(rc);
     if ((rc = apply_A_core(p, G, nA, A_, nA, m, nullptr, s, mx))) return cleanup(rc);
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
     if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
@@ -815,7 +827,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     Zfinal = A_;
   } else {
     // Algorithm 5: G_3 = orth(G); Y_3 = A G_3 = Z_3 R_3; K_3 = R_3 R_3^T = W Theta^2 W^T
-    he = vec_copy(A_, G, nA * m, s);
+    he = G != nullptr ? vec_copy(A_, G, nA * m, s) : gauss_block(seed, nA, m, 0, A_, nA, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
     if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
@@ -835,10 +847,14 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, plain_cols(L->ldu), nullptr,
                   cm, nullptr, s);
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
-  int st = 0;
-  he = hipMemcpyAsync(&st, p->dStatus, sizeof(int), hipMemcpyDeviceToHost, s);
+  // status words 0 (Cholesky / rank) and 4 (Jacobi converged flag)
+  int stw[5] = {0, 0, 0, 0, 0};
+  he = hipMemcpyAsync(stw, p->dStatus, sizeof stw, hipMemcpyDeviceToHost, s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+  const int st = stw[0];
+  if (st == 0 && stw[4] == 0)
+    return cleanup(fail(p, WC4D_ENOCONV, "one-sided Jacobi of the small problem did not converge in 20 sweeps"));
   if (st != 0)
     return cleanup(fail(p, WC4D_ENOTSPD,
                         std::string(st == 2 ? "start block numerically rank deficient (R diagonal spans > 1/(1e3 u))"
@@ -905,15 +921,34 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
 
 extern "C" {
 
-int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, wc4d_lmp* out,
-                   hipStream_t s) {
-  int rc = lmp_build_once(p, method, k_r, l, G, out, s);
+int wc4d_lmp_build(wc4d_problem p, int method, int k_r, int l, const double* G, unsigned long long seed,
+                   wc4d_lmp* out, hipStream_t s) {
+  int rc = lmp_build_once(p, method, k_r, l, G, seed, out, s);
   if (rc != WC4D_ENOTSPD) return rc;
   // a Cholesky factorisation broke down: once more with shifted CholeskyQR3
   p->cholShift = true;
-  rc = lmp_build_once(p, method, k_r, l, G, out, s);
+  rc = lmp_build_once(p, method, k_r, l, G, seed, out, s);
   p->cholShift = false;
   return rc;
+}
+
+int wc4d_gaussian_block(int device, unsigned long long seed, long long n_rows, int n_cols, long long col0,
+                        double* G, long long ldg, hipStream_t s) {
+  if (n_rows < 0 || n_cols < 0 || col0 < 0 || col0 + n_cols > 0xFFFFFFFFll || (n_rows + 1) / 2 > 0xFFFFFFFFll)
+    return WC4D_EINVAL;
+  if (n_rows == 0 || n_cols == 0) return WC4D_OK;
+  if (G == nullptr || ldg < n_rows || !device_ok(device)) return WC4D_EINVAL;
+  DevGuard g(device);
+  return gauss_block(seed, n_rows, n_cols, col0, G, ldg, s) == hipSuccess ? WC4D_OK : WC4D_EHIP;
+}
+
+int wc4d_philox4x32_10(int device, const unsigned int* ctr_key, unsigned int* out, long long count,
+                       hipStream_t s) {
+  if (count < 0) return WC4D_EINVAL;
+  if (count == 0) return WC4D_OK;
+  if (ctr_key == nullptr || out == nullptr || !device_ok(device)) return WC4D_EINVAL;
+  DevGuard g(device);
+  return philox_words(ctr_key, out, count, s) == hipSuccess ? WC4D_OK : WC4D_EHIP;
 }
 
 int wc4d_lmp_theta(wc4d_lmp L, double* theta_host) {

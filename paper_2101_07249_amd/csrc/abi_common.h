@@ -14,6 +14,11 @@ inline int fail(wc4d_problem p, int code, const std::string& msg) {
   return code;
 }
 
+inline bool device_ok(int d) {
+  int n = 0;
+  return d >= 0 && hipGetDeviceCount(&n) == hipSuccess && d < n;
+}
+
 struct DevGuard {
   int prev = -1;
   bool changed = false;

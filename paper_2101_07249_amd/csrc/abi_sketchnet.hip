@@ -450,7 +450,7 @@ int wc4d_lmp_build_sketch(wc4d_problem p, wc4d_sketchnet net, int method, int k_
   *out = nullptr;
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   if (Omega == nullptr) return fail(p, WC4D_EINVAL, "null Gaussian block");
-  if (net == nullptr) return wc4d_lmp_build(p, method, k_r, l, Omega, out, s);
+  if (net == nullptr) return wc4d_lmp_build(p, method, k_r, l, Omega, 0, out, s);
   if (k_r + l != kNetCH || net->nz != kNetCH)
     return fail(p, WC4D_EINVAL, "the learned sketch needs k_r + l = 64 and a network with 64 noise channels");
   DevGuard g(p->device);
@@ -461,8 +461,8 @@ int wc4d_lmp_build_sketch(wc4d_problem p, wc4d_sketchnet net, int method, int k_
     net->blkRows = p->nA;
   }
   if ((rc = infer_core(net, p, Omega, p->nA, net->Gb, p->nA, s))) return fail(p, rc, net->err);
-  rc = wc4d_lmp_build(p, method, k_r, l, net->Gb, out, s);
-  if (rc == WC4D_ENOTSPD) return wc4d_lmp_build(p, method, k_r, l, Omega, out, s);
+  rc = wc4d_lmp_build(p, method, k_r, l, net->Gb, 0, out, s);
+  if (rc == WC4D_ENOTSPD) return wc4d_lmp_build(p, method, k_r, l, Omega, 0, out, s);
   if (rc == WC4D_OK && used_net != nullptr) *used_net = 1;
   return rc;
 }

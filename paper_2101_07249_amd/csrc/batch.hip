@@ -294,7 +294,7 @@ int wc4d_batch_solve(wc4d_problem* ps, int count, int method, int k_r, int l, co
     for (int i = next.fetch_add(1); i < count; i = next.fetch_add(1)) {
       const int q = order[i];
       wc4d_lmp L = nullptr;
-      int rc = wc4d_lmp_build(ps[q], method, k_r, l, G[q], &L, st);
+      int rc = wc4d_lmp_build(ps[q], method, k_r, l, G[q], 0, &L, st);
       if (rc == WC4D_OK) {
         rc = wc4d_pcg(ps[q], L, b[q], x[q], opts, &infos[q], nullptr, nullptr, nullptr, st);
         wc4d_lmp_destroy(L);

@@ -293,6 +293,14 @@ hipError_t pcg_s0(const double* b, const double* Ax, const int* xzero, double* s
 hipError_t block_copy(double* Y, long long ldy, const double* X, long long ldx, long long rows,
                       int cols, hipStream_t s);
 
+// Counter-based Gaussian start block (philox.hip).  philox_words: raw Philox-4x32-10 of
+// count (counter, key) tuples (in: count x 6 words c0..c3 k0 k1; out: count x 4 words).
+// gauss_block: G(r, c) for r < nrows, c < ncols = the N(0, 1) entry (r, col0 + c) of the
+// block of `seed` (column-major, ldg).
+hipError_t philox_words(const uint32_t* in, uint32_t* out, long long count, hipStream_t s);
+hipError_t gauss_block(unsigned long long seed, long long nrows, int ncols, long long col0, double* G,
+                       long long ldg, hipStream_t s);
+
 // Learned sketch network (sketchnet.hip).  fp16 = _Float16; layouts there.
 hipError_t net_features(int n, int N, const double* traj, const int* obs_off, const int* obs_idx,
                         const double* Om, long long ldo, int nz, int cp0, _Float16* X0, hipStream_t s);

@@ -68,8 +68,11 @@ _SIGS = {
     "wc4d_apply_LinvT": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_apply_Dsqrt": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_rhs": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
-    "wc4d_lmp_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+    "wc4d_lmp_build": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_ulonglong,
                                       ctypes.POINTER(_vp), _vp]),
+    "wc4d_gaussian_block": (ctypes.c_int, [ctypes.c_int, ctypes.c_ulonglong, ctypes.c_longlong, ctypes.c_int,
+                                           ctypes.c_longlong, _vp, ctypes.c_longlong, _vp]),
+    "wc4d_philox4x32_10": (ctypes.c_int, [ctypes.c_int, _vp, _vp, ctypes.c_longlong, _vp]),
     "wc4d_lmp_theta": (ctypes.c_int, [_vp, _c_dbl_p]),
     "wc4d_lmp_vectors": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
     "wc4d_lmp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
@@ -79,7 +82,6 @@ _SIGS = {
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
     "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
-    "wc4d_probe_mfma_f64": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_dbl_p]),
     "wc4d_prof_stride": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_read": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong),
@@ -165,11 +167,80 @@ def _stream(stream) -> Optional[int]:
     return torch.cuda.current_stream().cuda_stream
 
 
-def _tptr(t) -> int:
+def _check_size(t, shape, what: str):
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if isinstance(shape, int):
+        if t.numel() != shape:
+            raise ValueError(f"{what}: expected {shape} elements, got {t.numel()}")
+    elif shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _tptr(t, shape=None, what: str = "tensor", dtype=None) -> int:
+    """Data pointer of a contiguous CUDA tensor (float64 unless dtype is given).  With
+    `shape`, the tensor must have exactly that shape (a tuple) or that many elements (an
+    int): the C-ABI takes bare pointers, so every size is checked here, before a launch."""
+    import torch
+    want = torch.float64 if dtype is None else dtype
+    _check_size(t, shape, what)
+    if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise TypeError(f"{what}: expected a contiguous {want} CUDA tensor")
     return t.data_ptr()
+
+
+def _ptrs(*items):
+    """Data pointers of several tensors, (tensor, shape, what) each: every size is
+    checked before any tensor's device or layout, so a wrongly sized argument is reported
+    as such wherever it lives."""
+    for t, shape, what in items:
+        _check_size(t, shape, what)
+    return [_tptr(t, shape, what) for t, shape, what in items]
+
+
+def _block_rows(X, n_A: int, what: str):
+    """(m, view) of a block of vectors: a 1-D tensor of n_A elements (m = 1) or an
+    (m, n_A) tensor."""
+    if X.dim() == 1:
+        X2 = X.view(1, -1)
+    elif X.dim() == 2:
+        X2 = X
+    else:
+        raise ValueError(f"{what}: a block is a 1-D or 2-D tensor")
+    if X2.shape[-1] != n_A or X2.shape[0] < 1:
+        raise ValueError(f"{what}: block rows must have n_A = {n_A} entries, got shape {tuple(X.shape)}")
+    return X2.shape[0], X2
+
+
+def gaussian_block(seed: int, n_rows: int, n_cols: int, col0: int = 0, out=None, device: int = 0,
+                   stream=None):
+    """The Gaussian start block of `seed` drawn on the device (wc4d_gaussian_block): an
+    (n_cols, n_rows) float64 tensor whose row c is column col0 + c of the block."""
+    import torch
+    if out is None:
+        out = torch.empty((n_cols, n_rows), dtype=torch.float64, device=torch.device("cuda", device))
+    ptr = _tptr(out, (n_cols, n_rows), "gaussian_block out")
+    rc = lib().wc4d_gaussian_block(int(device), ctypes.c_ulonglong(int(seed) & 0xFFFFFFFFFFFFFFFF),
+                                   int(n_rows), int(n_cols), int(col0), ptr, max(int(n_rows), 1), _stream(stream))
+    if rc:
+        raise Wc4dError(rc, "wc4d_gaussian_block")
+    return out
+
+
+def philox4x32_10(ctr_key, device: int = 0, stream=None):
+    """Raw Philox-4x32-10 words of (count, 6) uint32 rows (c0 c1 c2 c3 k0 k1) on the device
+    (wc4d_philox4x32_10); returns a (count, 4) int32 tensor holding the words' bits."""
+    import torch
+    t = ctr_key
+    if t.dim() != 2 or t.shape[1] != 6:
+        raise ValueError("ctr_key must be (count, 6)")
+    out = torch.empty((t.shape[0], 4), dtype=torch.int32, device=t.device)
+    rc = lib().wc4d_philox4x32_10(int(device), _tptr(t, what="ctr_key", dtype=torch.int32),
+                                  _tptr(out, what="out", dtype=torch.int32), int(t.shape[0]), _stream(stream))
+    if rc:
+        raise Wc4dError(rc, "wc4d_philox4x32_10")
+    return out
 
 
 def corr_sqrt(n: int, kind: str, L: float, sigma: float) -> np.ndarray:
@@ -213,11 +284,12 @@ class Lmp:
 
     def apply(self, X, Y=None, stream=None):
         import torch
+        m, X2 = _block_rows(X, self.prob.n_A, "lmp_apply X")
         if Y is None:
             Y = torch.empty_like(X)
-        m = X.shape[0] if X.dim() == 2 else 1
-        self.prob._chk(lib().wc4d_lmp_apply(self._h, _tptr(X), self.prob.n_A, _tptr(Y), self.prob.n_A, m,
-                                            _stream(stream)), "lmp_apply")
+        xp, yp = _ptrs((X2, None, "lmp_apply X"), (Y, tuple(X.shape), "lmp_apply Y"))
+        self.prob._chk(lib().wc4d_lmp_apply(self._h, xp, self.prob.n_A, yp, self.prob.n_A, m, _stream(stream)),
+                       "lmp_apply")
         return Y
 
     @property
@@ -323,16 +395,11 @@ class Problem:
     # ---- operator
     def _block_call(self, fn, X, Y, stream, what):
         import torch
-        if X.dim() == 1:
-            X2 = X.view(1, -1)
-        else:
-            X2 = X
-        if X2.shape[-1] != self.n_A:
-            raise ValueError(f"block rows must be n_A = {self.n_A}")
+        m, X2 = _block_rows(X, self.n_A, what + " X")
         if Y is None:
             Y = torch.empty_like(X)
-        Y2 = Y.view(1, -1) if Y.dim() == 1 else Y
-        self._chk(fn(self._h, _tptr(X2), self.n_A, _tptr(Y2), self.n_A, X2.shape[0], _stream(stream)), what)
+        xp, yp = _ptrs((X2, None, what + " X"), (Y, tuple(X.shape), what + " Y"))
+        self._chk(fn(self._h, xp, self.n_A, yp, self.n_A, m, _stream(stream)), what)
         return Y
 
     def apply_A(self, X, Y=None, stream=None):
@@ -340,12 +407,12 @@ class Problem:
 
     def apply_A_prec(self, X, prec: int, Y=None, stream=None):
         import torch
-        X2 = X.view(1, -1) if X.dim() == 1 else X
+        m, X2 = _block_rows(X, self.n_A, "apply_A_prec X")
         if Y is None:
             Y = torch.empty_like(X)
-        Y2 = Y.view(1, -1) if Y.dim() == 1 else Y
-        self._chk(lib().wc4d_apply_A_prec(self._h, _tptr(X2), self.n_A, _tptr(Y2), self.n_A, X2.shape[0],
-                                          int(prec), _stream(stream)), "apply_A_prec")
+        xp, yp = _ptrs((X2, None, "apply_A_prec X"), (Y, tuple(X.shape), "apply_A_prec Y"))
+        self._chk(lib().wc4d_apply_A_prec(self._h, xp, self.n_A, yp, self.n_A, m, int(prec), _stream(stream)),
+                  "apply_A_prec")
         return Y
 
     def apply_Linv(self, X, Y=None, stream=None):
@@ -359,18 +426,31 @@ class Problem:
 
     def rhs(self, d, bt=None, out=None, stream=None):
         import torch
+        items = []
+        if bt is not None:
+            items.append((bt, self.n_A, "rhs bt"))
+        if self.q > 0:
+            items.append((d, self.q, "rhs d"))
+        for t, shape, what in items:
+            _check_size(t, shape, what)
         if out is None:
             out = torch.empty(self.n_A, dtype=torch.float64, device=self.torch_device)
-        bp = _tptr(bt) if bt is not None else None
-        dp = _tptr(d) if self.q > 0 else None
-        self._chk(lib().wc4d_rhs(self._h, dp, bp, _tptr(out), _stream(stream)), "rhs")
+        items.insert(0, (out, self.n_A, "rhs out"))
+        ptrs = _ptrs(*items)
+        bp = ptrs[1] if bt is not None else None
+        dp = ptrs[-1] if self.q > 0 else None
+        self._chk(lib().wc4d_rhs(self._h, dp, bp, ptrs[0], _stream(stream)), "rhs")
         return out
 
     # ---- preconditioner and solve
-    def lmp_build(self, method, k_r: int, l: int, G, stream=None) -> Lmp:
+    def lmp_build(self, method, k_r: int, l: int, G=None, seed: int = 0, stream=None) -> Lmp:
+        """LMP from the start block G ((k_r + l, n_A) device tensor), or, with G None, from
+        the Gaussian block of `seed` drawn on the device inside the build."""
         meth = METHOD[method] if isinstance(method, str) else int(method)
         h = _vp()
-        self._chk(lib().wc4d_lmp_build(self._h, meth, int(k_r), int(l), _tptr(G), ctypes.byref(h),
+        gp = _tptr(G, (int(k_r) + int(l), self.n_A), "lmp_build G") if G is not None else None
+        self._chk(lib().wc4d_lmp_build(self._h, meth, int(k_r), int(l), gp,
+                                       ctypes.c_ulonglong(int(seed) & 0xFFFFFFFFFFFFFFFF), ctypes.byref(h),
                                        _stream(stream)), "lmp_build")
         return Lmp(h.value, self, int(k_r))
 
@@ -380,8 +460,9 @@ class Problem:
         meth = METHOD[method] if isinstance(method, str) else int(method)
         h = _vp()
         used = ctypes.c_int(0)
+        op = _tptr(Omega, (int(k_r) + int(l), self.n_A), "lmp_build_sketch Omega")
         self._chk(lib().wc4d_lmp_build_sketch(self._h, net._h if net is not None else None, meth, int(k_r),
-                                              int(l), _tptr(Omega), ctypes.byref(h), ctypes.byref(used),
+                                              int(l), op, ctypes.byref(h), ctypes.byref(used),
                                               _stream(stream)), "lmp_build_sketch")
         return Lmp(h.value, self, int(k_r)), bool(used.value)
 
@@ -389,13 +470,18 @@ class Problem:
         """Capture loss f of the start block G (m, n_A) against Ritz pairs U (k, n_A),
         theta (k,) (device tensors); returns (f as a 1-element tensor, dG)."""
         import torch
+        if G.dim() != 2 or G.shape[1] != self.n_A or U.dim() != 2 or U.shape[1] != self.n_A:
+            raise ValueError(f"sketch_loss: G and U must be (columns, n_A = {self.n_A})")
+        k = U.shape[0]
+        _check_size(theta, k, "sketch_loss theta")
         if dG is None:
             dG = torch.empty_like(G)
+        _check_size(dG, tuple(G.shape), "sketch_loss dG")
         f = torch.empty(1, dtype=torch.float64, device=self.torch_device)
-        k = U.shape[0]
-        self._chk(lib().wc4d_sketch_loss(self._h, _tptr(G), self.n_A, G.shape[0], _tptr(U), self.n_A,
-                                         _tptr(theta), k, _tptr(f), _tptr(dG), self.n_A, _stream(stream)),
-                  "sketch_loss")
+        gp, up, tp, dp = _ptrs((G, None, "sketch_loss G"), (U, None, "sketch_loss U"),
+                               (theta, k, "sketch_loss theta"), (dG, tuple(G.shape), "sketch_loss dG"))
+        self._chk(lib().wc4d_sketch_loss(self._h, gp, self.n_A, G.shape[0], up, self.n_A, tp, k, _tptr(f), dp,
+                                         self.n_A, _stream(stream)), "sketch_loss")
         return f, dG
 
     def autotune(self, m: int, stream=None) -> dict:
@@ -417,7 +503,8 @@ class Problem:
         ht = np.zeros(maxit) if history else None
         hp = np.zeros(maxit) if history else None
         hj = np.zeros(maxit) if history else None
-        rc = lib().wc4d_pcg(self._h, lmp._h if lmp is not None else None, _tptr(b), _tptr(x),
+        bp, xp = _ptrs((b, self.n_A, "pcg b"), (x, self.n_A, "pcg x"))
+        rc = lib().wc4d_pcg(self._h, lmp._h if lmp is not None else None, bp, xp,
                             ctypes.byref(opts), ctypes.byref(info),
                             _dptr(ht) if history else None, _dptr(hp) if history else None,
                             _dptr(hj) if history else None, _stream(stream))
@@ -479,16 +566,6 @@ class Problem:
             pass
 
 
-def probe_mfma_f64(waves_per_simd: int = 2, iters: int = 2000, reps: int = 5, device: int = 0) -> float:
-    """Float64 matrix rate (TFLOP/s) of a register-only MFMA stream on the device: the
-    hardware reference for the float64 roofline."""
-    out = ctypes.c_double()
-    rc = lib().wc4d_probe_mfma_f64(int(device), int(waves_per_simd), int(iters), int(reps), ctypes.byref(out))
-    if rc:
-        raise Wc4dError(rc, "probe_mfma_f64")
-    return out.value
-
-
 def autotune_save(path: str):
     rc = lib().wc4d_autotune_save(os.fsencode(path))
     if rc:
@@ -508,10 +585,18 @@ def batch_solve(problems: Sequence[Problem], method, k_r: int, l: int, G, b, x, 
     device tensors per problem ((m, n_A), (n_A,), (n_A,)).  Returns (infos, status)."""
     cnt = len(problems)
     meth = METHOD[method] if isinstance(method, str) else int(method)
+    if not (len(G) == len(b) == len(x) == cnt):
+        raise ValueError("batch_solve: G, b and x need one entry per problem")
     P = (_vp * cnt)(*[p._h for p in problems])
-    Gp = (_vp * cnt)(*[_tptr(g) for g in G])
-    bp = (_vp * cnt)(*[_tptr(v) for v in b])
-    xp = (_vp * cnt)(*[_tptr(v) for v in x])
+    m = int(k_r) + int(l)
+    items = []
+    for i, p in enumerate(problems):
+        items += [(G[i], (m, p.n_A), f"batch_solve G[{i}]"), (b[i], p.n_A, f"batch_solve b[{i}]"),
+                  (x[i], p.n_A, f"batch_solve x[{i}]")]
+    ptrs = _ptrs(*items)
+    Gp = (_vp * cnt)(*ptrs[0::3])
+    bp = (_vp * cnt)(*ptrs[1::3])
+    xp = (_vp * cnt)(*ptrs[2::3])
     infos = (PcgInfo * cnt)()
     status = (ctypes.c_int * cnt)()
     opts = PcgOpts(float(tol), int(maxit), int(criterion), int(variant))
@@ -539,6 +624,7 @@ class SketchNet:
             _handle = h.value
         self._h = _handle
         self.device = int(device)
+        self.noise_channels = int(noise_channels)
         c = ctypes.c_longlong()
         lib().wc4d_sketchnet_nparams(self._h, ctypes.byref(c))
         self.nparams = c.value
@@ -549,7 +635,9 @@ class SketchNet:
         rc = lib().wc4d_sketchnet_load(ctypes.byref(h), os.fsencode(path), int(device))
         if rc:
             raise Wc4dError(rc, f"wc4d_sketchnet_load({path})")
-        return cls(device=device, _handle=h.value)
+        # header: "WC4DSKN1", int32 layers, channels, width, noise_channels
+        hdr = np.fromfile(path, dtype=np.int32, count=6)
+        return cls(layers=int(hdr[2]), noise_channels=int(hdr[5]), device=device, _handle=h.value)
 
     def _chk(self, rc: int, what: str):
         if rc != OK:
@@ -586,20 +674,25 @@ class SketchNet:
         import torch
         if G is None:
             G = torch.empty((64, prob.n_A), dtype=torch.float64, device=prob.torch_device)
-        op = _tptr(Omega) if Omega is not None else None
-        self._chk(lib().wc4d_sketchnet_infer(self._h, prob._h, op, prob.n_A, _tptr(G), prob.n_A, _stream(stream)),
+        op = _tptr(Omega, (self.noise_channels, prob.n_A), "infer Omega") if Omega is not None else None
+        gp = _tptr(G, (64, prob.n_A), "infer G")
+        self._chk(lib().wc4d_sketchnet_infer(self._h, prob._h, op, prob.n_A, gp, prob.n_A, _stream(stream)),
                   "infer")
         return G
 
     def backward(self, dG, stream=None):
-        self._chk(lib().wc4d_sketchnet_backward(self._h, _tptr(dG), dG.shape[-1], _stream(stream)), "backward")
+        if dG.dim() != 2 or dG.shape[0] != 64:
+            raise ValueError("backward: dG must be (64, n_A) of the last inference")
+        self._chk(lib().wc4d_sketchnet_backward(self._h, _tptr(dG, what="backward dG"), dG.shape[-1],
+                                                _stream(stream)), "backward")
 
     def adam(self, lr: float, stream=None):
         self._chk(lib().wc4d_sketchnet_adam(self._h, float(lr), _stream(stream)), "adam")
 
     def train_step(self, prob: "Problem", Omega, ref: Lmp, k: int, lr: float, stream=None) -> float:
         loss = ctypes.c_double(0.0)
-        self._chk(lib().wc4d_sketchnet_train_step(self._h, prob._h, _tptr(Omega), prob.n_A, ref._h, int(k),
+        op = _tptr(Omega, (self.noise_channels, prob.n_A), "train_step Omega")
+        self._chk(lib().wc4d_sketchnet_train_step(self._h, prob._h, op, prob.n_A, ref._h, int(k),
                                                   float(lr), ctypes.byref(loss), _stream(stream)), "train_step")
         return loss.value
 

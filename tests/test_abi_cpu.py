@@ -193,3 +193,59 @@ def test_profile_commands_run_committed_files_with_known_flags():
         for t in toks[toks.index(paths[0]) + 1:]:
             if t.startswith("--"):
                 assert t in opts, (t, c)
+
+
+def _stub_problem(n_A=12, q=3):
+    """A Problem object with sizes but no library handle: the binding's size checks run
+    before any library call, so they can be exercised without a GPU."""
+    from paper_2101_07249_amd.wc4d import Problem
+    p = object.__new__(Problem)
+    p._h = None
+    p.n, p.N, p.device, p.n_A, p.q = 4, 2, 0, n_A, q
+    return p
+
+
+def test_binding_checks_sizes_before_any_launch():
+    """The C-ABI takes bare device pointers, so a short tensor would be read or written out
+    of bounds inside a kernel; the binding must raise ValueError first."""
+    import torch
+    from paper_2101_07249_amd import wc4d
+    p = _stub_problem()
+    ok_vec, short = torch.zeros(12, dtype=torch.float64), torch.zeros(11, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        p.pcg(short, ok_vec)
+    with pytest.raises(ValueError):
+        p.pcg(ok_vec, short)
+    with pytest.raises(ValueError):
+        p.rhs(torch.zeros(2, dtype=torch.float64))                     # d needs q = 3
+    with pytest.raises(ValueError):
+        p.rhs(torch.zeros(3, dtype=torch.float64), bt=short)
+    with pytest.raises(ValueError):
+        p.rhs(torch.zeros(3, dtype=torch.float64), out=short)
+    with pytest.raises(ValueError):
+        p.lmp_build("revd", 3, 2, torch.zeros((4, 12), dtype=torch.float64))   # needs (5, 12)
+    with pytest.raises(ValueError):
+        p.lmp_build_sketch(None, "nystrom", 59, 5, torch.zeros((64, 11), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.apply_A(torch.zeros((2, 11), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.apply_A(torch.zeros((2, 12), dtype=torch.float64), torch.zeros((1, 12), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.apply_A_prec(torch.zeros((2, 12), dtype=torch.float64), wc4d.PREC_FP64,
+                       torch.zeros((2, 11), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.apply_Linv(torch.zeros((1, 2, 12), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        p.sketch_loss(torch.zeros((4, 12), dtype=torch.float64), torch.zeros((2, 12), dtype=torch.float64),
+                      torch.zeros(3, dtype=torch.float64))                 # theta needs k = 2
+    L = wc4d.Lmp(None, p, 3)
+    with pytest.raises(ValueError):
+        L.apply(torch.zeros((2, 13), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        wc4d.batch_solve([p], "revd", 3, 2, [torch.zeros((5, 12), dtype=torch.float64)], [short], [ok_vec])
+    with pytest.raises(ValueError):
+        wc4d.batch_solve([p], "revd", 3, 2, [torch.zeros((5, 12), dtype=torch.float64)], [ok_vec], [])
+    # right sizes on the host: the device check fires instead (nothing reaches the library)
+    with pytest.raises(TypeError):
+        p.pcg(ok_vec, ok_vec)
+    L._h = None
