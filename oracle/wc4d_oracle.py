@@ -25,6 +25,7 @@ Conventions (readings of the paper where it is silent):
 """
 from __future__ import annotations
 
+import functools
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Tuple
 
@@ -178,9 +179,17 @@ def sym_sqrt(C: np.ndarray) -> np.ndarray:
     return (V * np.sqrt(lam)) @ V.T
 
 
+@functools.lru_cache(maxsize=2)
+def _corr_sqrt(n: int, kind: str, L: float) -> np.ndarray:
+    """C^{1/2} of one correlation family (kept for reuse: B and Q often share it)."""
+    S = sym_sqrt(correlation_matrix(n, kind, L))
+    S.setflags(write=False)
+    return S
+
+
 def cov_sqrt(n: int, kind: str, L: float, sigma: float) -> np.ndarray:
     """sigma * C^{1/2}: the symmetric square root of sigma^2 C."""
-    return sigma * sym_sqrt(correlation_matrix(n, kind, L))
+    return sigma * _corr_sqrt(int(n), str(kind), float(L))
 
 
 # ---------------------------------------------------------------------------
@@ -431,7 +440,23 @@ def ritzit(applyA: Callable, G: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndar
     return Z3 @ W3[:, :k], np.sqrt(np.clip(theta2[:k], 0.0, None))
 
 
-METHODS = {"revd": revd, "nystrom": nystrom, "ritzit": ritzit}
+def nystrom_single_pass(applyA: Callable, G: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Single-pass Nystrom, the variant Section 6 names as future work (the single-pass
+    Nystrom of Halko, Martinsson and Tropp 2011, Section 5.5): the Nystrom approximation
+    A ~ Y (G_4^T Y)^{-1} Y^T built on the start block's own range, so A is applied once.
+    G_4 = orth(G); Y = A G_4; E = G_4^T Y = C^T C (Cholesky); solve F C = Y;
+    SVD F = U Sigma V^T; keep k; Theta = Sigma^2."""
+    G4 = _orth(G)
+    Y = applyA(G4)
+    E = G4.T @ Y
+    E = 0.5 * (E + E.T)
+    C = np.linalg.cholesky(E).T             # upper triangular, E = C^T C
+    F = sla.solve_triangular(C, Y.T, trans="T", lower=False).T    # F C = Y
+    U, sig, _ = np.linalg.svd(F, full_matrices=False)
+    return U[:, :k], sig[:k] ** 2
+
+
+METHODS = {"revd": revd, "nystrom": nystrom, "ritzit": ritzit, "nystrom1p": nystrom_single_pass}
 
 
 # ---------------------------------------------------------------------------

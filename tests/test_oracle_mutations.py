@@ -324,3 +324,28 @@ def test_uniform_without_half_offset_is_caught(monkeypatch):
     orig = P.uniform52
     monkeypatch.setattr(P, "uniform52", lambda a, b: orig(a, b) - 0.5 / 2.0 ** 52)
     assert _fails(pp.test_uniform52_closed_forms)
+
+
+def test_single_pass_nystrom_mutations_are_caught(monkeypatch):
+    """Single-pass Nystrom without the square of the singular values, or with the triangular
+    solve on the wrong side (F C^T = Y), fails its pins."""
+    import scipy.linalg as sla
+    orig = O.nystrom_single_pass
+
+    def no_square(applyA, G, k):
+        U, t = orig(applyA, G, k)
+        return U, np.sqrt(t)
+
+    def wrong_side(applyA, G, k):
+        G4 = O._orth(G)
+        Y = applyA(G4)
+        E = G4.T @ Y
+        C = np.linalg.cholesky(0.5 * (E + E.T)).T
+        F = sla.solve_triangular(C, Y.T, lower=False).T
+        U, sig, _ = np.linalg.svd(F, full_matrices=False)
+        return U[:, :k], sig[:k] ** 2
+
+    for bad in (no_square, wrong_side):
+        monkeypatch.setattr(O, "nystrom_single_pass", bad)
+        assert _fails(pins.test_single_pass_nystrom_full_sketch_and_invariant_subspace)
+        assert _fails(pins.test_single_pass_nystrom_closed_form_bounds_and_one_product)

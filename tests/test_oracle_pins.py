@@ -650,3 +650,43 @@ def test_paper_qualitative_lmp_spectra_on_advection():
     assert mins["revd"] < 0.9
     assert mins["nystrom"] > mins["revd"] and mins["ritzit"] > mins["revd"]
     assert th0["ritzit"] < th0["revd"] <= lam_max * (1 + 1e-12) and th0["ritzit"] < th0["nystrom"]
+
+
+# ----------------------------------------------------------------- single-pass Nystrom
+
+
+def test_single_pass_nystrom_full_sketch_and_invariant_subspace():
+    """With a full sketch (m = n_A) the Nystrom approximation is A itself, so every
+    eigenvalue comes back; on an invariant subspace the pairs are exact."""
+    prob = small_problem()
+    A = O.dense_A(prob)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    G = sketch_block(prob.n_A, prob.n_A, 12)
+    U, th = O.nystrom_single_pass(lambda X: O.apply_A(prob, X), G, prob.n_A)
+    np.testing.assert_allclose(th, lam, rtol=1e-10, atol=1e-10 * lam[0])
+    np.testing.assert_allclose(U @ np.diag(th) @ U.T, A, atol=1e-9 * lam[0])
+    m = 6
+    Gi = V[:, :m] @ np.linalg.qr(np.random.default_rng(5).standard_normal((m, m)))[0]
+    U, th = O.nystrom_single_pass(lambda X: O.apply_A(prob, X), Gi, 4)
+    np.testing.assert_allclose(th, lam[:4], rtol=1e-11)
+    np.testing.assert_allclose(A @ U, U * th, atol=1e-10 * lam[0])
+
+
+def test_single_pass_nystrom_closed_form_bounds_and_one_product():
+    """All m pairs kept: U Theta U^T equals Y (G^T Y)^{-1} Y^T with Y = A G (a plain solve; the
+    approximation depends on range(G) only).  It is A^{1/2} P A^{1/2} with P an orthogonal
+    projector, so 1 <= theta_i <= lambda_i (A >= I); A is applied once."""
+    prob = build(C1)
+    A = O.dense_A(prob)
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    prob.n_apply = 0
+    U, th = O.nystrom_single_pass(lambda X: O.apply_A(prob, X), G, C1.m)
+    assert prob.n_apply == 1
+    Y = A @ G
+    want = Y @ np.linalg.solve(G.T @ Y, Y.T)
+    np.testing.assert_allclose(U @ np.diag(th) @ U.T, want, atol=1e-9 * np.abs(want).max())
+    assert np.all(np.diff(th) <= 1e-12 * th[0]) and th.min() >= 1 - 1e-10
+    assert np.all(th <= lam[:C1.m] * (1 + 1e-10))
+    np.testing.assert_allclose(U.T @ U, np.eye(C1.m), atol=1e-10)
