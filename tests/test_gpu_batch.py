@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import wc4d_oracle as O
+from parity import assert_cols_close
 from synthetic import batched_workloads, innovations, obs_pattern, random_block, sketch_block
 
 pytestmark = pytest.mark.gpu
@@ -64,14 +65,14 @@ def test_autotune_keeps_the_operator(m, same_corr):
     op = O.make_problem(w, pat)
     X = random_block(op.n_A, m, 31)
     Y0 = to_host(gp.apply_A(to_dev(X)))
-    assert relerr(Y0, O.apply_A(op, X)) <= 1e-10
+    assert_cols_close(Y0, O.apply_A(op, X), 1e-10, "A before tuning")
     t = gp.autotune(m)
     say("  choice", t)
     assert t["single_product"] == same_corr and t["ms"] > 0
     assert 1 <= t["tile_b"] <= 7 and (t["tile_q"] == 0 if same_corr else 1 <= t["tile_q"] <= 7)
     Y1 = to_host(gp.apply_A(to_dev(X)))
-    assert relerr(Y1, Y0) <= 1e-12
-    assert relerr(Y1, O.apply_A(op, X)) <= 1e-10
+    assert_cols_close(Y1, Y0, 1e-12, "A after tuning vs before")
+    assert_cols_close(Y1, O.apply_A(op, X), 1e-10, "A after tuning")
     # a second problem of the same shape takes the cached choice
     gp2 = Problem.from_workload(w, pat)
     assert gp2.autotune(m) == t
@@ -107,14 +108,17 @@ def test_batch_solve_matches_one_by_one_and_oracle():
     w, p = ws[j], probs[j]
     op = O.make_problem(w, pats[j])
     bo = O.rhs(op, innovations(p.q, w.seed, 0.1))
-    assert relerr(to_host(b[j]), bo) <= 1e-10
+    assert_cols_close(to_host(b[j]), bo, 1e-10, "rhs")
     _, _, res = O.inner_loop(op, bo, sketch_block(op.n_A, k_r + l, w.seed), "nystrom", k_r, tol=1e-6, maxit=3000)
     say("  oracle iters", res.iters, "gpu", infos[j]["iters"])
     xg = to_host(x[j])
     assert np.linalg.norm(bo - O.apply_A(op, xg)) / np.linalg.norm(bo) <= 1.01e-6
-    assert relerr(xg, res.x) <= 1e-4
-    # rounding-level differences of the operator move the 1e-6 crossing of a flat residual
-    # curve by a few iterations
+    # both solutions meet ||b - A x|| <= 1e-6 ||b||: they differ by up to kappa * 2e-6
+    assert_cols_close(xg, res.x, 1e-4, "x")
+    # the LMP keeps k_r = 11 of the q (~n_A / 8) eigenvalues above one, so this is a long,
+    # CG-like solve (about a hundred iterations): as for plain CG (the Lanczos process of
+    # Section 3.4), rounding-level differences of the operator move the 1e-6 crossing of
+    # its flat residual curve by a few iterations (measured: 111 against 108)
     assert abs(res.iters - infos[j]["iters"]) <= max(2, int(0.03 * res.iters))
 
 

@@ -1,10 +1,12 @@
 """GPU parity: the HIP path (through the C-ABI) against the FP64 CPU oracle on the
-same seeded inputs.  FP64 path bar: 1e-10 relative (norm-wise) unless a test
+same seeded inputs.  FP64 path bar: every column within 1e-10 of its largest entry
+(max-abs per column) and every Ritz value within 1e-10 of itself, unless a test
 states and justifies another bound."""
 import numpy as np
 import pytest
 
 from oracle import wc4d_oracle as O
+from parity import assert_cols_close, assert_entries_rel
 from synthetic import (C1, C2, Workload, innovations, l96_initial_state, obs_pattern, random_block,
                        sketch_block)
 
@@ -103,8 +105,7 @@ def test_operator_pieces(name, m):
                            ("A", gp.apply_A, O.apply_A)):
         Y = to_host(gfn(Xd))
         Yo = ofn(op, X)
-        e = relerr(Y, Yo)
-        assert e <= TOL, (what, e)
+        assert_cols_close(Y, Yo, TOL, what)
 
 
 @pytest.mark.parametrize("m", [1, 130, 260])
@@ -114,7 +115,7 @@ def test_apply_A_block_widths_C2(m):
     gp, op = pair(C2)
     X = sketch_block(op.n_A, m, 7)
     Y = to_host(gp.apply_A(to_dev(X)))
-    assert relerr(Y, O.apply_A(op, X)) <= TOL
+    assert_cols_close(Y, O.apply_A(op, X), TOL, "A")
 
 
 def test_rhs_and_no_observation_operator():
@@ -122,10 +123,10 @@ def test_rhs_and_no_observation_operator():
     gp, op = pair(C1)
     d = innovations(op.q, 5, 0.1)
     b = to_host(gp.rhs(to_dev(d)))
-    assert relerr(b, O.rhs(op, d)) <= TOL
+    assert_cols_close(b, O.rhs(op, d), TOL, "rhs")
     bt = random_block(op.n_A, 1, 3)[:, 0]
     b2 = to_host(gp.rhs(to_dev(d), bt=to_dev(bt)))
-    assert relerr(b2, O.rhs(op, d, bt=bt)) <= TOL
+    assert_cols_close(b2, O.rhs(op, d, bt=bt), TOL, "rhs + bt")
     # without observations A is the identity
     say("q = 0")
     w = tiny()
@@ -154,32 +155,30 @@ def _lmp_check(w, method, G=None):
     op.n_apply = 0
     Uo, tho = O.METHODS[method](lambda Z: O.apply_A(op, Z), G, w.k_r)
     assert L.applies == op.n_apply
-    e_th = relerr(th, tho)
-    assert e_th <= TOL, (method, e_th)
+    e_th = assert_entries_rel(th, tho, TOL, f"{method} theta")
     assert np.all(np.diff(th) <= 0)
     np.testing.assert_allclose(U.T @ U, np.eye(w.k_r), atol=1e-10)
     # the preconditioner's action (independent of the basis chosen inside clusters)
     V = random_block(op.n_A, 4, 9)
     CV = to_host(L.apply(to_dev(V)))
     CVo = O.lmp_apply(Uo, tho, V)
-    e_c = relerr(CV, CVo)
-    return gp, op, L, e_th, e_c
+    return gp, op, L, e_th, (CV, CVo)
 
 
-@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit", "nystrom1p"])
 @pytest.mark.parametrize("wname", ["C1", "C2"])
 def test_lmp_build_matches_oracle(method, wname):
     say("lmp build", wname, method)
     w = CASES[wname]
-    _, _, _, e_th, e_c = _lmp_check(w, method)
+    _, _, _, e_th, (CV, CVo) = _lmp_check(w, method)
     # C V depends on the Ritz vectors, whose rounding error is eps * ||A|| / gap for
     # nearly repeated Ritz values; the bound below is that of the oracle itself
     # under a different (Householder vs CholeskyQR2) orthonormalisation.
-    assert e_c <= 1e-8, (method, e_c)
+    assert_cols_close(CV, CVo, 1e-8, f"{method} C V")
 
 
 @pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit"])
+@pytest.mark.parametrize("method", ["revd", "nystrom", "ritzit", "nystrom1p"])
 def test_pcg_matches_oracle_C1(method, variant):
     say("pcg C1", method, "variant", variant)
     w = C1
@@ -230,15 +229,18 @@ def test_pcg_tight_solution_C2(method, variant):
     assert ro.converged
     # both solutions satisfy ||b - A x|| <= 1e-11 ||b||; they agree to kappa-scaled 1e-11
     xg = to_host(x)
-    assert relerr(xg, ro.x) <= 1e-6
+    # measured on the CPU: two FP64 solves to 1e-11 differ by ~1e-11 of the largest entry
+    assert_cols_close(xg, ro.x, 1e-8, "x")
     assert np.linalg.norm(b - O.apply_A(op, xg)) / np.linalg.norm(b) <= 2e-11
-    # iteration counts at 1e-6 agree within max(2, 3%): without a second-level preconditioner
-    # CG loses orthogonality at a rate set by rounding, so rounding-level operator
-    # differences move the 1e-6 crossing by a few iterations
+    # iteration counts at 1e-6: within 2 with an LMP; without a second-level preconditioner
+    # (177 iterations here) within max(2, 3%): plain CG is the Lanczos process (Section 3.4)
+    # and loses orthogonality at a rate set by rounding, so rounding-level differences of
+    # the operator move the 1e-6 crossing of its flat residual curve by a few iterations
     x6 = _torch().zeros(op.n_A, dtype=_torch().float64, device=dev())
     i6 = gp.pcg(gp.rhs(to_dev(d)), x6, L, tol=1e-6, maxit=3000, variant=variant)
     r6 = O.pcg(lambda v: O.apply_A(op, v), b, lmp=(Uo, tho) if method else None, tol=1e-6, maxit=3000)
-    assert abs(i6["iters"] - r6.iters) <= max(2, int(0.03 * r6.iters)), (i6["iters"], r6.iters)
+    slack = 2 if method else max(2, int(0.03 * r6.iters))
+    assert abs(i6["iters"] - r6.iters) <= slack, (i6["iters"], r6.iters)
 
 
 def test_pcg_precond_criterion_and_nonzero_start():

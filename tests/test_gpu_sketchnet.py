@@ -2,7 +2,7 @@
 against the FP64 CPU oracle, plus training and fallback behaviour.
 
 Tolerances: the network runs in float16 with float32 accumulation, so inference is
-checked to 5e-3 relative (Frobenius) and gradients to cosine >= 0.999 and 1e-2
+checked per column (largest error within 1e-2 of the column's largest entry) and gradients to cosine >= 0.999 and 1e-2
 relative; Adam runs on float32 master weights (1e-5 relative); the capture loss is
 float64 end to end (1e-9 relative)."""
 import os
@@ -12,6 +12,7 @@ import pytest
 
 from oracle import sketchnet_oracle as S
 from oracle import wc4d_oracle as O
+from parity import col_errors
 from synthetic import (Workload, l96_initial_state, obs_pattern, random_block, sketch_block,
                        sketchnet_init)
 
@@ -98,9 +99,11 @@ def test_inference_matches_oracle(name):
     Om = sketch_block(op.n_A, 64, w.seed)
     G = to_host(net.infer(gp, to_dev(Om)))
     Gref, _ = S.forward(theta.astype(np.float64), _oracle_input(w, op, pat, Om))
-    e = relerr(G, Gref)
-    say("  rel err", e)
-    assert e <= 5e-3
+    # float16 weights and activations: per column, the largest error within 1e-2 of the
+    # column's largest entry (norm-wise the error is ~1e-3)
+    e = float(col_errors(G, Gref).max())
+    say("  per-column max-abs rel err", e, "norm-wise", relerr(G, Gref))
+    assert e <= 1e-2
 
 
 @pytest.mark.parametrize("name", ["one_tile", "ragged"])
