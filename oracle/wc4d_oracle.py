@@ -497,6 +497,23 @@ def lmp_dense_C_product(U: np.ndarray, theta: np.ndarray) -> np.ndarray:
 # Split preconditioned CG (Algorithm 1)
 # ---------------------------------------------------------------------------
 
+def ritz_lmp_dense(U: np.ndarray, theta: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """The Ritz-LMP of eq. Ritz_LMP written out densely:
+    P = (I - U Theta^{-1} U^T A)(I - A U Theta^{-1} U^T) + U Theta^{-1} U^T."""
+    n = A.shape[0]
+    T = U @ np.diag(1.0 / theta) @ U.T
+    return (np.eye(n) - T @ A) @ (np.eye(n) - A @ T) + T
+
+
+def ritz_lmp_apply(U: np.ndarray, theta: np.ndarray, AU: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """P r for the Ritz-LMP of eq. Ritz_LMP, with A U given (A symmetric):
+    c = Theta^{-1} U^T r; w = r - (A U) c; e = Theta^{-1} (A U)^T w; P r = w - U e + U c."""
+    c = (U.T @ r) / theta
+    w = r - AU @ c
+    e = (AU.T @ w) / theta
+    return w - U @ e + U @ c
+
+
 RES_TRUE = 0
 RES_PRECOND = 1
 
@@ -567,6 +584,47 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
             converged = True
             break
     return PCGResult(x, it, converged, ht[-1], hp[-1], hJ[-1], ht, hp, hJ, al, be)
+
+
+def pcg_standard(applyA: Callable, b: np.ndarray, precond: Callable, tol: float = 1e-6,
+                 maxit: int = 100) -> PCGResult:
+    """Preconditioned CG with a symmetric positive definite preconditioner P given as a
+    function (for an LMP that has no split factor C, such as the Ritz-LMP):
+        r_0 = b, z_0 = P r_0, p_0 = z_0;  alpha = r^T z / p^T A p;  x += alpha p;
+        r -= alpha A p;  z = P r;  beta = r_new^T z_new / r^T z;  p = z + beta p.
+    With P = C C^T this is Algorithm 1 in exact arithmetic (x_j are the same iterates).
+    Stops when ||r_j|| / ||b|| <= tol (r is the true residual's recursion) or after maxit."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    rz = r @ z
+    bnorm = np.linalg.norm(b)
+    ht, hJ, al, be = [], [], [], []
+    it = 0
+    converged = False
+    if bnorm == 0.0:
+        return PCGResult(x, 0, True, 0.0, 0.0, 0.0, [], [], [], [], [])
+    for it in range(1, maxit + 1):
+        Ap = applyA(p)
+        alpha = rz / (p @ Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        z = precond(r)
+        rz_new = r @ z
+        beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+        rt = np.linalg.norm(r) / bnorm
+        ht.append(rt)
+        hJ.append(-0.5 * (x @ (b + r)))
+        al.append(alpha)
+        be.append(beta)
+        if rt <= tol:
+            converged = True
+            break
+    return PCGResult(x, it, converged, ht[-1], float("nan"), hJ[-1], ht, [], hJ, al, be)
 
 
 # ---------------------------------------------------------------------------

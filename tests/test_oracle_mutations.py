@@ -349,3 +349,55 @@ def test_single_pass_nystrom_mutations_are_caught(monkeypatch):
         monkeypatch.setattr(O, "nystrom_single_pass", bad)
         assert _fails(pins.test_single_pass_nystrom_full_sketch_and_invariant_subspace)
         assert _fails(pins.test_single_pass_nystrom_closed_form_bounds_and_one_product)
+
+
+def test_ritz_lmp_mutations_are_caught(monkeypatch):
+    """The Ritz-LMP without its last term U Theta^{-1} U^T, or with Theta^{-1/2} for
+    Theta^{-1}, and standard PCG with beta from r^T r instead of r^T z, fail their pins."""
+    orig_dense, orig_apply, orig_pcg = O.ritz_lmp_dense, O.ritz_lmp_apply, O.pcg_standard
+
+    def no_last_term(U, th, A):
+        T = U @ np.diag(1.0 / th) @ U.T
+        n = A.shape[0]
+        return (np.eye(n) - T @ A) @ (np.eye(n) - A @ T)
+
+    def half_power(U, th, A):
+        return orig_dense(U, np.sqrt(th), A)
+
+    for bad in (no_last_term, half_power):
+        monkeypatch.setattr(O, "ritz_lmp_dense", bad)
+        assert _fails(pins.test_ritz_lmp_identities)
+    monkeypatch.setattr(O, "ritz_lmp_dense", orig_dense)
+
+    def wrong_apply(U, th, AU, r):
+        return orig_apply(U, th, AU, r) - U @ ((U.T @ r) / th)
+
+    monkeypatch.setattr(O, "ritz_lmp_apply", wrong_apply)
+    assert _fails(pins.test_ritz_lmp_identities)
+    monkeypatch.setattr(O, "ritz_lmp_apply", orig_apply)
+
+    def wrong_beta(applyA, b, precond, tol=1e-6, maxit=100):
+        x = np.zeros_like(b)
+        r = b.copy()
+        z = precond(r)
+        p = z.copy()
+        rz = r @ z
+        hJ = []
+        for it in range(1, maxit + 1):
+            Ap = applyA(p)
+            alpha = rz / (p @ Ap)
+            x = x + alpha * p
+            r_new = r - alpha * Ap
+            z = precond(r_new)
+            beta = (r_new @ r_new) / (r @ r)
+            r = r_new
+            rz = r @ z
+            p = z + beta * p
+            hJ.append(-0.5 * (x @ (b + r)))
+            if np.linalg.norm(r) <= tol * np.linalg.norm(b):
+                break
+        return O.PCGResult(x, it, True, np.linalg.norm(r) / np.linalg.norm(b), float("nan"), hJ[-1],
+                           [], [], hJ, [], [])
+
+    monkeypatch.setattr(O, "pcg_standard", wrong_beta)
+    assert _fails(pins.test_standard_pcg_equals_split_pcg_and_cg)

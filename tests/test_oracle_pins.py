@@ -690,3 +690,55 @@ def test_single_pass_nystrom_closed_form_bounds_and_one_product():
     assert np.all(np.diff(th) <= 1e-12 * th[0]) and th.min() >= 1 - 1e-10
     assert np.all(th <= lam[:C1.m] * (1 + 1e-10))
     np.testing.assert_allclose(U.T @ U, np.eye(C1.m), atol=1e-10)
+
+
+# ----------------------------------------------------------------- Ritz-LMP
+
+
+def test_ritz_lmp_identities():
+    """eq. Ritz_LMP with Rayleigh-Ritz pairs (REVD: U^T A U = Theta) is the general LMP of
+    eq. LMP_general with S = U: symmetric, P A U = U, and with exact eigenpairs it equals the
+    spectral LMP (eq. spectral_LMP); with all n_A exact pairs it is A^{-1}.  The applied form
+    (with A U precomputed) equals the dense formula."""
+    prob = small_problem()
+    A = O.dense_A(prob)
+    G = sketch_block(prob.n_A, 8, 21)
+    U, th = O.revd(lambda X: O.apply_A(prob, X), G, 6)
+    np.testing.assert_allclose(U.T @ A @ U, np.diag(th), atol=1e-10 * th[0])
+    P = O.ritz_lmp_dense(U, th, A)
+    np.testing.assert_allclose(P, P.T, atol=1e-12)
+    np.testing.assert_allclose(P @ A @ U, U, atol=1e-10)
+    S = U @ np.linalg.inv(U.T @ A @ U) @ U.T
+    general = (np.eye(prob.n_A) - S @ A) @ (np.eye(prob.n_A) - A @ S) + S
+    np.testing.assert_allclose(P, general, atol=1e-10)
+    assert np.linalg.eigvalsh(0.5 * (P + P.T)).min() > 0
+    v = random_block(prob.n_A, 1, 3)[:, 0]
+    np.testing.assert_allclose(O.ritz_lmp_apply(U, th, A @ U, v), P @ v, atol=1e-12)
+    lam, V = np.linalg.eigh(A)
+    lam, V = lam[::-1], V[:, ::-1]
+    np.testing.assert_allclose(O.ritz_lmp_dense(V[:, :5], lam[:5], A), O.lmp_dense_P(V[:, :5], lam[:5]),
+                               atol=1e-10)
+    np.testing.assert_allclose(O.ritz_lmp_dense(V, lam, A), np.linalg.inv(A), atol=1e-10)
+
+
+def test_standard_pcg_equals_split_pcg_and_cg():
+    """Preconditioned CG with P = C C^T produces Algorithm 1's iterates (exact arithmetic);
+    with P = I it is plain CG; with the Ritz-LMP it solves A x = b."""
+    prob = build(C1)
+    b = O.rhs(prob, innovations(prob.q, C1.seed, np.sqrt(C1.sigma_o2)))
+    G = sketch_block(prob.n_A, C1.m, C1.seed)
+    U, th = O.revd(lambda X: O.apply_A(prob, X), G, C1.k_r)
+    Aop = lambda v: O.apply_A(prob, v)  # noqa: E731
+    split = O.pcg(Aop, b, lmp=(U, th), tol=1e-10, maxit=500)
+    std = O.pcg_standard(Aop, b, lambda r: O.lmp_apply(U, th, O.lmp_apply(U, th, r)), tol=1e-10, maxit=500)
+    k = min(8, split.iters)
+    np.testing.assert_allclose(std.hist_J[:k], split.hist_J[:k], rtol=1e-9)
+    assert abs(std.iters - split.iters) <= 2
+    plain = O.pcg(Aop, b, tol=1e-8, maxit=500)
+    ident = O.pcg_standard(Aop, b, lambda r: r, tol=1e-8, maxit=500)
+    np.testing.assert_allclose(ident.hist_true[:6], plain.hist_true[:6], rtol=1e-9)
+    AU = O.apply_A(prob, U)
+    rl = O.pcg_standard(Aop, b, lambda r: O.ritz_lmp_apply(U, th, AU, r), tol=1e-10, maxit=500)
+    A = O.dense_A(prob)
+    assert rl.converged
+    np.testing.assert_allclose(rl.x, np.linalg.solve(A, b), rtol=0, atol=1e-7 * np.abs(np.linalg.solve(A, b)).max())
