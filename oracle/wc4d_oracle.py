@@ -531,11 +531,12 @@ class PCGResult:
     hist_J: List[float]
     alphas: List[float]
     betas: List[float]
+    residuals: Optional[List[np.ndarray]] = None   # r_0, r_1, ... when asked for
 
 
 def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
         lmp: Optional[Tuple[np.ndarray, np.ndarray]] = None, tol: float = 1e-6,
-        maxit: int = 100, criterion: int = RES_TRUE) -> PCGResult:
+        maxit: int = 100, criterion: int = RES_TRUE, keep_residuals: bool = False) -> PCGResult:
     """Algorithm 1, split preconditioned CG on C^T A C xhat = C^T b with P = C C^T:
         r_0 = C^T (b - A x_0), p_0 = C r_0;
         alpha_j = r^T r / p^T A p;  x_j = x_{j-1} + alpha_j p_{j-1};
@@ -559,16 +560,19 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
     r0norm = np.linalg.norm(r)
     rr = r @ r
     ht, hp, hJ, al, be = [], [], [], [], []
+    res = [r.copy()] if keep_residuals else None
     it = 0
     converged = False
     if bnorm == 0.0:
-        return PCGResult(x, 0, True, 0.0, 0.0, 0.0, [], [], [], [], [])
+        return PCGResult(x, 0, True, 0.0, 0.0, 0.0, [], [], [], [], [], res)
     for it in range(1, maxit + 1):
         Ap = applyA(p)
         alpha = rr / (p @ Ap)
         x = x + alpha * p
         s = s - alpha * Ap
         r = r - alpha * C(Ap)
+        if keep_residuals:
+            res.append(r.copy())
         rr_new = r @ r
         beta = rr_new / rr
         rr = rr_new
@@ -583,7 +587,7 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
         if (rt if criterion == RES_TRUE else rp) <= tol:
             converged = True
             break
-    return PCGResult(x, it, converged, ht[-1], hp[-1], hJ[-1], ht, hp, hJ, al, be)
+    return PCGResult(x, it, converged, ht[-1], hp[-1], hJ[-1], ht, hp, hJ, al, be, res)
 
 
 def pcg_standard(applyA: Callable, b: np.ndarray, precond: Callable, tol: float = 1e-6,
@@ -625,6 +629,130 @@ def pcg_standard(applyA: Callable, b: np.ndarray, precond: Callable, tol: float 
             converged = True
             break
     return PCGResult(x, it, converged, ht[-1], float("nan"), hJ[-1], ht, [], hJ, al, be)
+
+
+# ---------------------------------------------------------------------------
+# Spectral information from CG (Section 3.4): the Lanczos tridiagonal T_j
+# ---------------------------------------------------------------------------
+
+
+def cg_tridiagonal(alphas: List[float], betas: List[float], j: int) -> np.ndarray:
+    """T_j of Section 3.4 from the first j CG coefficients: gamma_1 = 1/alpha_1,
+    gamma_i = 1/alpha_i + beta_{i-1}/alpha_{i-1}; tau_i = sqrt(beta_i)/alpha_i."""
+    T = np.zeros((j, j))
+    for i in range(j):
+        T[i, i] = 1.0 / alphas[i] + (betas[i - 1] / alphas[i - 1] if i > 0 else 0.0)
+        if i + 1 < j:
+            T[i, i + 1] = T[i + 1, i] = np.sqrt(betas[i]) / alphas[i]
+    return T
+
+
+def cg_lanczos_pairs(res: PCGResult, k: int, j: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """The k largest Ritz pairs of A from j iterations of CG (Section 3.4): Ritz values are
+    the eigenvalues of T_j, Ritz vectors u_i = F_j w_i with w_i the eigenvectors of T_j and
+    F_j = (f_0, ..., f_{j-1}).  The Lanczos vectors are f_i = (-1)^i r_i / ||r_i|| (the signs
+    make F_j^T A F_j = T_j with T_j's positive off-diagonal; Section 3.4 writes r_i / ||r_i||)."""
+    j = res.iters if j is None else j
+    T = cg_tridiagonal(res.alphas, res.betas, j)
+    F = np.stack([(-1.0) ** i * res.residuals[i] / np.linalg.norm(res.residuals[i]) for i in range(j)], axis=1)
+    theta, W = _eig_desc(T)
+    return F @ W[:, :k], theta[:k]
+
+
+# ---------------------------------------------------------------------------
+# Gauss-Newton outer loop (Section 2.1, eqs. error_update and incr_wc4d-var_forcing)
+# ---------------------------------------------------------------------------
+
+
+def innovations_from_state(prob: Problem, y: List[np.ndarray], X: np.ndarray) -> np.ndarray:
+    """d = (y_i - H_i x_i) stacked over the observed times (direct observations); y[a] are
+    the observations of the a-th observed time of prob.obs, X the (N+1, n) state."""
+    if not prob.obs:
+        return np.zeros(0)
+    return np.concatenate([y[a] - X[i][idx] for a, (i, idx, _) in enumerate(prob.obs)])
+
+
+def model_step(prob: Problem, x: np.ndarray) -> np.ndarray:
+    """One step of the nonlinear model M (eq. model): the advection-diffusion stencil (a
+    linear model) or one RK4 step of Lorenz-96."""
+    if prob.model == "advdiff":
+        return advdiff_step(x, prob.c, prob.r)
+    return l96_rk4_step(x, prob.F, prob.dt)
+
+
+def forced_trajectory(prob: Problem, x0: np.ndarray, eta: np.ndarray) -> np.ndarray:
+    """x_{i+1} = M(x_i) + eta_{i+1} (eq. model); eta: (N, n), row i is eta_{i+1}."""
+    out = np.empty((prob.N + 1, prob.n))
+    out[0] = x0
+    for i in range(prob.N):
+        out[i + 1] = model_step(prob, out[i]) + eta[i]
+    return out
+
+
+def nonlinear_cost(prob: Problem, xb: np.ndarray, y: List[np.ndarray], x0: np.ndarray, eta: np.ndarray) -> float:
+    """J(x_0, eta_1..eta_N) of eq. 4D-var_error for direct observations."""
+    X = forced_trajectory(prob, x0, eta)
+    Binv = np.linalg.inv(prob.Bsqrt @ prob.Bsqrt)
+    Qinv = np.linalg.inv(prob.Qsqrt @ prob.Qsqrt)
+    J = 0.5 * (x0 - xb) @ Binv @ (x0 - xb)
+    for a, (i, idx, rd) in enumerate(prob.obs):
+        dv = y[a] - X[i][idx]
+        J += 0.5 * dv @ (dv / rd)
+    for i in range(prob.N):
+        J += 0.5 * eta[i] @ Qinv @ eta[i]
+    return float(J)
+
+
+def twin_experiment(prob: Problem, draws) -> Tuple[np.ndarray, List[np.ndarray], np.ndarray]:
+    """Identical twin (Section 5): the truth x^t from draws['x0'] with model errors
+    Q^{1/2} xi_model, the background x^b = x^t_0 + B^{1/2} xi_b and observations
+    y_i = H_i x^t_i + sigma_o zeta.  Returns (x^b, y, truth trajectory)."""
+    eta_t = draws["xi_model"] @ prob.Qsqrt.T
+    Xt = forced_trajectory(prob, draws["x0"], eta_t)
+    xb = Xt[0] + prob.Bsqrt @ draws["xi_b"]
+    y, off = [], 0
+    for i, idx, rd in prob.obs:
+        y.append(Xt[i][idx] + np.sqrt(rd) * draws["zeta"][off:off + len(idx)])
+        off += len(idx)
+    return xb, y, Xt
+
+
+def gauss_newton(prob: Problem, xb: np.ndarray, y: List[np.ndarray], n_outer: int, inner: Callable):
+    """The incremental outer loop (Section 2.1): p^(0) = (x^b, 0, ..., 0); for j = 0, 1, ...
+    the state x^(j) from p^(j) by eq. model, the problem linearised about it, b^(j), d^(j),
+    the inner loop on eq. forcing_1stlvl_prec (rhs = D^{-1/2} b + D^{1/2} L^{-T} H^T R^{-1} d)
+    by inner(prob_j, rhs, j) -> delta p~, and p^(j+1) = p^(j) + D^{1/2} delta p~ (eq.
+    error_update).  Returns per-loop records (rhs, delta p~, nonlinear cost before the loop)."""
+    n, N = prob.n, prob.N
+    p = np.zeros((N + 1) * n)
+    p[:n] = xb
+    pb = p.copy()
+    recs = []
+    for j in range(n_outer):
+        x0, eta = p[:n], p[n:].reshape(N, n)
+        X = forced_trajectory(prob, x0, eta)
+        pj = Problem(n=n, N=N, model=prob.model, Bsqrt=prob.Bsqrt, Qsqrt=prob.Qsqrt, obs=prob.obs, c=prob.c,
+                     r=prob.r, F=prob.F, dt=prob.dt, traj=X)
+        d = innovations_from_state(pj, y, X)
+        b = pb - p                                   # (x^b - x_0^(j), -eta_1^(j), ..., -eta_N^(j))
+        rhs_j = rhs(pj, d, bt=dinv_sqrt(pj, b))
+        recs.append({"J": nonlinear_cost(pj, xb, y, x0, eta), "rhs": rhs_j, "prob": pj, "b": b})
+        dpt = inner(pj, rhs_j, j)
+        recs[-1]["dpt"] = dpt
+        p = p + apply_Dsqrt(pj, dpt[:, None])[:, 0]
+    x0, eta = p[:n], p[n:].reshape(N, n)
+    recs.append({"J": nonlinear_cost(prob, xb, y, x0, eta), "p": p})
+    return recs
+
+
+def dinv_sqrt(prob: Problem, v: np.ndarray) -> np.ndarray:
+    """D^{-1/2} v by solving with the symmetric square roots level by level."""
+    Lv = _levels(prob, v[:, None])[:, :, 0]
+    out = np.empty_like(Lv)
+    out[0] = np.linalg.solve(prob.Bsqrt, Lv[0])
+    for i in range(1, prob.N + 1):
+        out[i] = np.linalg.solve(prob.Qsqrt, Lv[i])
+    return out.reshape(-1)
 
 
 # ---------------------------------------------------------------------------

@@ -18,13 +18,13 @@ from typing import List, Tuple
 import numpy as np
 
 __all__ = [
-    "Workload", "C1", "C2", "C3", "C5", "WORKLOADS", "batched_workloads",
+    "Workload", "C1", "C2", "C3", "C5", "SEC52", "WORKLOADS", "batched_workloads",
     "obs_pattern", "obs_count", "sketch_block", "innovations", "l96_initial_state",
     "rng_for",
 ]
 
 # purpose tags for independent random substreams of one seed
-_PURPOSE = {"sketch": 1, "innov": 2, "x0": 3, "obsmask": 4, "sizes": 5, "vec": 6, "net": 7}
+_PURPOSE = {"sketch": 1, "innov": 2, "x0": 3, "obsmask": 4, "sizes": 5, "vec": 6, "net": 7, "twin": 8}
 
 
 def rng_for(seed: int, purpose: str) -> np.random.Generator:
@@ -111,7 +111,14 @@ C5 = Workload(name="l96_n1024_N100_m64", model="l96", n=1024, N=100, F=8.0, dt=0
               obs_kind="bernoulli_times", obs_time_stride=5, obs_prob=0.5,
               sigma_o2=0.04, m=64, l=5, seed=5000)
 
-WORKLOADS = {"C1": C1, "C2": C2, "C3": C3, "C5": C5}
+# Section 5.2's own Lorenz-96 configuration (n = 80, N = 150, 120 observations: every 10th
+# variable at every 10th step; sigma_o = 0.15, sigma_b = 0.2, sigma_q = 0.1, length scales
+# 2 grid spacings; k = 15 of the oversampling study), SOAR for both covariances.
+SEC52 = Workload(name="l96_n80_N150_sec52", model="l96", n=80, N=150, F=8.0, dt=0.025, corr="soar", Lb=2.0,
+                 Lq=2.0, sigma_b=0.2, sigma_q=0.1, obs_var_stride=10, obs_time_stride=10, sigma_o2=0.15 ** 2,
+                 m=20, l=5, seed=5200)
+
+WORKLOADS = {"C1": C1, "C2": C2, "C3": C3, "C5": C5, "SEC52": SEC52}
 
 
 def batched_workloads(count: int = 64, seed: int = 4000, m: int = 64,
@@ -196,6 +203,20 @@ def random_block(rows: int, cols: int, seed: int, instance: int = 0) -> np.ndarr
 
 
 __all__.append("random_block")
+
+
+def twin_draws(w: Workload, q: int, instance: int = 0):
+    """Standard normal draws of an identical-twin experiment (Section 5): the truth's initial
+    state x0 (climatology-sized, as l96_initial_state), its model errors xi_model (N, n),
+    the background error xi_b (n,) and the observation errors zeta (q,).  Scaling by
+    Q^{1/2}, B^{1/2} and sigma_o is left to the caller."""
+    rng = rng_for(w.seed + 7919 * instance, "twin")
+    return {"x0": l96_initial_state(w.n, w.seed, instance) if w.model == "l96" else None,
+            "xi_model": rng.standard_normal((w.N, w.n)), "xi_b": rng.standard_normal(w.n),
+            "zeta": rng.standard_normal(q)}
+
+
+__all__.append("twin_draws")
 
 
 def sketchnet_init(layers: int = 4, noise_channels: int = 64, seed: int = 7000, channels: int = 64,

@@ -401,3 +401,47 @@ def test_ritz_lmp_mutations_are_caught(monkeypatch):
 
     monkeypatch.setattr(O, "pcg_standard", wrong_beta)
     assert _fails(pins.test_standard_pcg_equals_split_pcg_and_cg)
+
+
+def test_lanczos_and_outer_loop_mutations_are_caught(monkeypatch):
+    """Lanczos vectors without the alternating signs, T_j without the beta/alpha term on its
+    diagonal, the outer loop's b with the wrong sign, and a trajectory that ignores the model
+    error each fail a pin."""
+    orig_tri, orig_pairs, orig_traj = O.cg_tridiagonal, O.cg_lanczos_pairs, O.forced_trajectory
+
+    def no_signs(res, k, j=None):
+        j = res.iters if j is None else j
+        T = O.cg_tridiagonal(res.alphas, res.betas, j)
+        F = np.stack([res.residuals[i] / np.linalg.norm(res.residuals[i]) for i in range(j)], axis=1)
+        th, W = O._eig_desc(T)
+        return F @ W[:, :k], th[:k]
+
+    monkeypatch.setattr(O, "cg_lanczos_pairs", no_signs)
+    assert _fails(pins.test_cg_tridiagonal_is_the_lanczos_projection)
+    assert _fails(pins.test_cg_lanczos_pairs_converge_to_the_largest_eigenpairs)
+    monkeypatch.setattr(O, "cg_lanczos_pairs", orig_pairs)
+
+    def short_diag(alphas, betas, j):
+        T = orig_tri(alphas, betas, j)
+        return T - np.diag([0.0] + [betas[i - 1] / alphas[i - 1] for i in range(1, j)])
+
+    monkeypatch.setattr(O, "cg_tridiagonal", short_diag)
+    assert _fails(pins.test_cg_tridiagonal_is_the_lanczos_projection)
+    monkeypatch.setattr(O, "cg_tridiagonal", orig_tri)
+
+    orig_gn = O.gauss_newton
+
+    def wrong_b_sign(prob, xb, y, n_outer, inner):
+        orig_dinv = O.dinv_sqrt
+        monkeypatch.setattr(O, "dinv_sqrt", lambda pr, v: -orig_dinv(pr, v))
+        try:
+            return orig_gn(prob, xb, y, n_outer, inner)
+        finally:
+            monkeypatch.setattr(O, "dinv_sqrt", orig_dinv)
+
+    monkeypatch.setattr(O, "gauss_newton", wrong_b_sign)
+    assert _fails(pins.test_gauss_newton_linear_model_converges_in_one_outer_loop)
+    monkeypatch.setattr(O, "gauss_newton", orig_gn)
+
+    monkeypatch.setattr(O, "forced_trajectory", lambda prob, x0, eta: orig_traj(prob, x0, 0.0 * eta))
+    assert _fails(pins.test_gauss_newton_linear_model_converges_in_one_outer_loop)

@@ -10,7 +10,7 @@ import scipy.integrate
 import scipy.linalg as sla
 
 from oracle import wc4d_oracle as O
-from synthetic import (C1, C2, Workload, innovations, l96_initial_state, obs_count, obs_pattern,
+from synthetic import (C1, C2, Workload, innovations, l96_initial_state, obs_count, obs_pattern, twin_draws,
                        random_block, sketch_block)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -742,3 +742,78 @@ def test_standard_pcg_equals_split_pcg_and_cg():
     A = O.dense_A(prob)
     assert rl.converged
     np.testing.assert_allclose(rl.x, np.linalg.solve(A, b), rtol=0, atol=1e-7 * np.abs(np.linalg.solve(A, b)).max())
+
+
+# ----------------------------------------------------------------- Lanczos-CG and the outer loop
+
+
+def test_cg_tridiagonal_is_the_lanczos_projection():
+    """Section 3.4: T_j built from the CG coefficients is F_j^T A F_j for the normalised
+    residuals taken with alternating signs, and its eigenvalues are the Ritz values of A on
+    the Krylov space K_j(A, b) (an orthonormal Krylov basis computed independently by QR)."""
+    prob = small_problem()
+    A = O.dense_A(prob)
+    b = random_block(prob.n_A, 1, 31)[:, 0]
+    j = 6
+    res = O.pcg(lambda v: O.apply_A(prob, v), b, tol=0.0, maxit=j, keep_residuals=True)
+    T = O.cg_tridiagonal(res.alphas, res.betas, j)
+    F = np.stack([(-1.0) ** i * res.residuals[i] / np.linalg.norm(res.residuals[i]) for i in range(j)], axis=1)
+    # the three-term (tridiagonal) relation holds to rounding; entries off the band grow
+    # as CG's residuals lose orthogonality, so the full projection is compared for j = 4
+    D = F.T @ A @ F - T
+    assert np.abs(np.triu(np.tril(D, 1), -1)).max() <= 1e-12 * np.abs(T).max()
+    np.testing.assert_allclose(D[:4, :4], 0.0, atol=1e-12 * np.abs(T).max())
+    K = np.stack([np.linalg.matrix_power(A, i) @ b for i in range(j)], axis=1)
+    Qk = np.linalg.qr(K)[0]
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(T)), np.sort(np.linalg.eigvalsh(Qk.T @ A @ Qk)),
+                               rtol=1e-8)
+    U, th = O.cg_lanczos_pairs(res, 3, j)
+    np.testing.assert_allclose(np.einsum("ij,ij->j", U, A @ U), th, rtol=1e-9)   # Rayleigh quotients
+
+
+def test_cg_lanczos_pairs_converge_to_the_largest_eigenpairs():
+    w = tiny_l96(n=20, N=6, vs=2, ts=2)
+    prob = build(w)
+    A = O.dense_A(prob)
+    lam, V = np.linalg.eigh(A)
+    b = random_block(prob.n_A, 1, 32)[:, 0]
+    res = O.pcg(lambda v: O.apply_A(prob, v), b, tol=0.0, maxit=40, keep_residuals=True)
+    U, th = O.cg_lanczos_pairs(res, 2, 40)
+    assert abs(th[0] - lam[-1]) <= 1e-8 * lam[-1]
+    assert abs(abs(U[:, 0] @ V[:, -1]) - 1.0) <= 1e-6
+
+
+def _twin(w, n_outer, inner):
+    prob = build(w)
+    draws = twin_draws(w, prob.q)
+    if draws["x0"] is None:
+        draws["x0"] = np.sin(2 * np.pi * np.arange(w.n) / w.n)
+    xb, y, _ = O.twin_experiment(prob, draws)
+    return prob, O.gauss_newton(prob, xb, y, n_outer, inner)
+
+
+def _exact_inner(prob, b, j):
+    return np.linalg.solve(O.dense_A(prob), b)
+
+
+def test_gauss_newton_linear_model_converges_in_one_outer_loop():
+    """With a linear model and direct observations the incremental cost is the exact cost,
+    so one exact inner solve reaches the minimum: the second loop's right-hand side vanishes
+    and the nonlinear cost stays at its minimum."""
+    w = tiny_advdiff(n=8, N=4)
+    prob, recs = _twin(w, 2, _exact_inner)
+    assert np.linalg.norm(recs[1]["rhs"]) <= 1e-10 * np.linalg.norm(recs[0]["rhs"])
+    assert recs[1]["J"] < recs[0]["J"]
+    assert abs(recs[2]["J"] - recs[1]["J"]) <= 1e-10 * recs[1]["J"]
+
+
+def test_gauss_newton_lorenz96_decreases_the_cost_and_tracks_b():
+    """Lorenz-96: each exact Gauss-Newton step lowers the nonlinear cost, the steps shrink,
+    and D^{-1/2} b^(1) = -delta p~^(0) (b^(1) = p^(0) - p^(1) with p^(0) = (x^b, 0, ..., 0))."""
+    w = tiny_l96(n=12, N=5, vs=2, ts=1)
+    prob, recs = _twin(w, 3, _exact_inner)
+    Js = [r["J"] for r in recs]
+    assert Js[1] < Js[0] and Js[2] < Js[1] and Js[3] <= Js[2] * (1 + 1e-12)
+    assert np.linalg.norm(recs[2]["dpt"]) < np.linalg.norm(recs[1]["dpt"]) < np.linalg.norm(recs[0]["dpt"])
+    np.testing.assert_allclose(O.dinv_sqrt(recs[1]["prob"], recs[1]["b"]), -recs[0]["dpt"],
+                               atol=1e-9 * np.abs(recs[0]["dpt"]).max())
