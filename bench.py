@@ -97,7 +97,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
-    ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit"])
+    ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit", "nystrom1p"])
     ap.add_argument("--variants", default="plain,mixed,mixed_u32,mixed_fp16",
                     help="comma list of plain (FP64), mixed (split-bf16 block products, float16 U), "
                          "mixed_u32 (float32 U), mixed_fp16 (split-float16 products, float16 U)")
@@ -105,9 +105,13 @@ def parse():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-sketch comparison")
-    ap.add_argument("--learned-steps", type=int, default=2)
-    ap.add_argument("--batched", action="store_true", help="also time the 64-problem batched solve")
+    ap.add_argument("--learned-problems", type=int, default=8, help="held-out problems of the learned comparison")
+    ap.add_argument("--no-oversampling", action="store_true", help="skip the realisation / oversampling statistics")
+    ap.add_argument("--realisations", type=int, default=50)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--batched-compare", action="store_true",
+                    help="also time the host-worker batched solve on the same problems")
     ap.add_argument("--retune", action="store_true",
                     help="autotune every product shape instead of loading the MI355X tuning table")
     ap.add_argument("--tune-cache", default=None,
@@ -133,13 +137,14 @@ def copy_probe():
 
 
 def learned_section(args):
-    """Gaussian vs learned start block on a held-out Lorenz-96 problem (n = 1024, N = 100,
-    m = 64, Nystrom): ms from the LMP build (net inference included) to the 1e-6 true
-    residual, PCG iterations and the capture of the reference subspace."""
+    """Gaussian vs learned start block on held-out Lorenz-96 problems (n = 1024, N = 100,
+    m = 64, Nystrom): per problem, ms from the LMP build (net inference included) to the
+    1e-6 true residual, PCG iterations, and the Ritz residuals ||A u - theta u|| / theta of
+    the leading pairs; then the means over the problems."""
     import numpy as np
     import torch
 
-    from paper_2101_07249_amd.train_sketchnet import DEFAULT_WEIGHTS, EVAL_OFFSET, Instances
+    from paper_2101_07249_amd.train_sketchnet import DEFAULT_WEIGHTS, EVAL_OFFSET, Instances, ritz_residuals
     from paper_2101_07249_amd.wc4d import SketchNet
 
     if not os.path.exists(DEFAULT_WEIGHTS):
@@ -147,84 +152,141 @@ def learned_section(args):
     net = SketchNet.load(DEFAULT_WEIGHTS)
     inst = Instances()
     w = inst.w
-    a = EVAL_OFFSET
-    p = inst.problem(a)
-    d = torch.from_numpy(np.random.default_rng([w.seed, a, 9]).standard_normal(p.q) * np.sqrt(w.sigma_o2)).to(
-        p.torch_device)
-    b = p.rhs(d)
-    Om = inst.omega(p, a, 64, draw=0)
-    ref = p.lmp_build("nystrom", 251, 5, inst.omega(p, a, 256, draw=1))
-    U = ref.vectors()[:w.k_r].contiguous()
-    th = torch.from_numpy(ref.theta()[:w.k_r].copy()).to(U.device)
-    ref.close()
-    out = {"workload": w.name, "method": "nystrom", "instance": a, "steps": args.learned_steps}
-    x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
-    for name, use in (("gaussian", None), ("learned", net)):
-        times, infos, used = [], [], False
-        for rep in range(1 + args.learned_steps):
+    rows = []
+    for a in range(EVAL_OFFSET, EVAL_OFFSET + args.learned_problems):
+        p = inst.problem(a)
+        d = torch.from_numpy(np.random.default_rng([w.seed, a, 9]).standard_normal(p.q) * np.sqrt(w.sigma_o2)).to(
+            p.torch_device)
+        b = p.rhs(d)
+        Om = inst.omega(p, a, 64, draw=0)
+        row = {"instance": a}
+        x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
+        for name, use in (("gaussian", None), ("learned", net)):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             L, used = p.lmp_build_sketch(use, "nystrom", w.k_r, w.l, Om)
             x.zero_()
             info = p.pcg(b, x, L, tol=args.tol, maxit=args.maxit, history=False)
             torch.cuda.synchronize()
-            if rep > 0:
-                times.append(1e3 * (time.perf_counter() - t0))
-                infos.append(info)
+            ms = 1e3 * (time.perf_counter() - t0)
+            rr = ritz_residuals(p, L)
+            row[name] = {"ms": ms, "pcg_iters": info["iters"], "relres_true": info["relres_true"],
+                         "used_net": bool(used), "ritz_res_leading10_median": float(np.median(rr[:10])),
+                         "ritz_res_median": float(np.median(rr))}
             L.close()
-        G = net.infer(p, Om) if use is not None else Om
-        f, _ = p.sketch_loss(G, U, th)
-        out[name] = {"ms": float(np.median(times)), "pcg_iters": infos[-1]["iters"],
-                     "relres_true": infos[-1]["relres_true"], "used_net": bool(used),
-                     "captured_share": -float(f.item())}
-    out["speedup_vs_gaussian"] = out["gaussian"]["ms"] / out["learned"]["ms"]
-    p.close()
-    return out
+        rows.append(row)
+        print(f"learned: problem {a}: iterations {row['gaussian']['pcg_iters']} (gaussian) / "
+              f"{row['learned']['pcg_iters']} (learned)", file=sys.stderr, flush=True)
+        p.close()
+    it_ratio = [r["learned"]["pcg_iters"] / r["gaussian"]["pcg_iters"] for r in rows]
+    ms_ratio = [r["learned"]["ms"] / r["gaussian"]["ms"] for r in rows]
+    return {"workload": w.name, "method": "nystrom", "problems": len(rows),
+            "instances": [r["instance"] for r in rows], "per_problem": rows,
+            "mean_iters_ratio_learned_over_gaussian": float(np.mean(it_ratio)),
+            "mean_time_ratio_learned_over_gaussian": float(np.mean(ms_ratio)),
+            "speedup_vs_gaussian": float(np.sum([r["gaussian"]["ms"] for r in rows]) /
+                                         np.sum([r["learned"]["ms"] for r in rows])),
+            "ritz_res_leading10_median": {k: float(np.median([r[k]["ritz_res_leading10_median"] for r in rows]))
+                                          for k in ("gaussian", "learned")}}
 
 
 def batched_section(args):
     """64 uneven advection-diffusion inner loops (n in [512, 8192], N in [10, 200], m = 64,
-    Nystrom) through wc4d_batch_solve: wall time of the whole batch (single-vector tiles
-    autotuned beforehand, not timed) against the same problems solved one after another."""
+    Nystrom): every problem's LMP built from its seeded device Gaussian block, then all PCG
+    iterations of all problems in one persistent launch (wc4d_batch_solve_persistent),
+    with float64 sweeps and with float32 sweeps; wall time of the whole call (builds
+    included), the persistent launch's own time, iterations and true residuals.  With
+    --batched-compare also the host-worker form (wc4d_batch_solve)."""
     import numpy as np
     import torch
 
-    from paper_2101_07249_amd import Problem, batch_solve
-    from synthetic import batched_workloads, innovations, obs_pattern, sketch_block
+    from paper_2101_07249_amd import Problem, batch_solve, batch_solve_persistent, gaussian_block
+    from synthetic import batched_workloads, innovations, obs_pattern
 
     ws = batched_workloads(count=args.batched_count)
-    probs, G, b = [], [], []
+    probs, b = [], []
     for w in ws:
         p = Problem.from_workload(w, obs_pattern(w))
-        p.autotune(1)   # the PCG's single-vector applies dominate; block widths keep the heuristic
         probs.append(p)
-        G.append(torch.from_numpy(np.ascontiguousarray(sketch_block(p.n_A, w.m, w.seed).T)).to(p.torch_device))
         b.append(p.rhs(torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device)))
-    x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
     k_r, l = ws[0].k_r, ws[0].l
-    torch.cuda.synchronize()
+    out = {"problems": len(ws), "sum_n_A": int(sum(p.n_A for p in probs)), "m": k_r + l, "method": "nystrom",
+           "n_range": [min(w.n for w in ws), max(w.n for w in ws)], "N_range": [min(w.N for w in ws), max(w.N for w in ws)]}
+    for name, f32 in (("persistent_f64", False), ("persistent_f32_sweeps", True)):
+        x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, status, kms = batch_solve_persistent(probs, "nystrom", k_r, l, b, x, seed=4000, tol=args.tol,
+                                                    maxit=args.maxit, sweep_fp32=f32)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        # achieved true residual of every problem with the float64 operator
+        res = []
+        for i, p in enumerate(probs):
+            r = b[i] - p.apply_A(x[i])
+            res.append(float(r.norm() / b[i].norm()))
+        from paper_2101_07249_amd.wc4d import batch_persistent_profile
+        prof = batch_persistent_profile()
+        out[name] = {"s": t, "persistent_launch_s": kms * 1e-3, "iters_total": int(sum(i["iters"] for i in infos)),
+                     "phase_busy_s": {k: round(v["busy_ms"] * 1e-3, 3) for k, v in prof.items() if k != "launch"},
+                     "workgroups": prof["launch"]["workgroups"],
+                     "iters_max": int(max(i["iters"] for i in infos)),
+                     "converged_recursive": all(s == 0 for s in status),
+                     "true_residual_max": max(res), "true_residual_median": float(np.median(res))}
+        print(f"batched: {name} {t:.1f} s (persistent launch {kms * 1e-3:.1f} s)", file=sys.stderr, flush=True)
+    if args.batched_compare:
+        G = [gaussian_block(4000 + i, p.n_A, k_r + l) for i, p in enumerate(probs)]
+        x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4,
+                                    autotune=False)
+        torch.cuda.synchronize()
+        out["host_workers"] = {"s": time.perf_counter() - t0, "iters_total": int(sum(i["iters"] for i in infos)),
+                               "converged": all(s == 0 for s in status)}
+    return out
+
+
+def oversampling_section(args):
+    """Realisation and oversampling statistics (Section 5.2.3) on Section 5.2's Lorenz-96
+    configuration (n = 80, N = 150, 120 observations, k = 15): for each randomised method and
+    oversampling l in {5, 10, 15}, args.realisations start blocks drawn on the device from
+    seeds; the mean and standard deviation over the realisations of the quadratic cost J at
+    each of the first ten PCG iterations, and of the iterations to a 1e-6 true residual."""
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd import Problem
+    from synthetic import SEC52, innovations, l96_initial_state, obs_pattern
+
+    w = SEC52
+    pat = obs_pattern(w)
+    p = Problem.from_workload(w, pat, x0=l96_initial_state(w.n, w.seed))
+    b = p.rhs(torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device))
+    x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
+    k, nj = 15, 10
+    out = {"workload": w.name, "n_A": p.n_A, "q": p.q, "k": k, "realisations": args.realisations, "rows": []}
+    info0 = p.pcg(b, x, None, tol=args.tol, maxit=args.maxit)
+    out["no_lmp"] = {"iters": info0["iters"], "J": [float(v) for v in info0["hist_J"][:nj]]}
     t0 = time.perf_counter()
-    infos, status = batch_solve(probs, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4,
-                                autotune=False)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    print(f"batched: {len(probs)} problems in {t_batch:.1f} s; now one after another", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    iters_seq = []
-    for i, p in enumerate(probs):
-        L = p.lmp_build("nystrom", k_r, l, G[i])
-        x[i].zero_()
-        iters_seq.append(p.pcg(b[i], x[i], L, tol=args.tol, maxit=args.maxit, history=False)["iters"])
-        L.close()
-        if (i + 1) % 16 == 0:
-            print(f"batched: one after another, {i + 1} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
-    return {"problems": len(ws), "sum_n_A": int(sum(p.n_A for p in probs)), "batch_s": t_batch,
-            "sequential_s": t_seq, "speedup": t_seq / t_batch,
-            "iters_total": int(sum(i["iters"] for i in infos)), "iters_equal_sequential":
-            [i["iters"] for i in infos] == iters_seq,
-            "converged": all(s == 0 for s in status) and all(i["relres_true"] <= args.tol for i in infos)}
+    for method in ("revd", "nystrom", "ritzit", "nystrom1p"):
+        for l in (5, 10, 15):
+            Js, its = [], []
+            for r in range(args.realisations):
+                L = p.lmp_build(method, k, l, seed=1000 * l + r)
+                x.zero_()
+                info = p.pcg(b, x, L, tol=args.tol, maxit=args.maxit)
+                L.close()
+                Js.append(np.pad(info["hist_J"][:nj], (0, max(0, nj - info["iters"])), mode="edge"))
+                its.append(info["iters"])
+            Js = np.array(Js)
+            out["rows"].append({"method": method, "l": l, "J_mean": Js.mean(axis=0).tolist(),
+                                "J_std": Js.std(axis=0).tolist(), "iters_mean": float(np.mean(its)),
+                                "iters_std": float(np.std(its)), "iters_min": int(min(its)), "iters_max": int(max(its))})
+        print(f"oversampling: {method} done", file=sys.stderr, flush=True)
+    out["s"] = time.perf_counter() - t0
+    p.close()
+    return out
 
 
 def cpu_baseline(w, pat, gpu_iters, args):
@@ -427,8 +489,10 @@ def main():
     }
     if not args.no_learned:
         out["learned"] = learned_section(args)
-    if args.batched:
+    if not args.no_batched:
         out["batched"] = batched_section(args)
+    if not args.no_oversampling:
+        out["oversampling"] = oversampling_section(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pat, results["plain"]["pcg_iters"] if "plain" in results else None,
                                            args)

@@ -50,7 +50,11 @@ enum {
 };
 
 enum { WC4D_CORR_SOAR = 0, WC4D_CORR_GAUSS = 1 };
-enum { WC4D_REVD = 0, WC4D_NYSTROM = 1, WC4D_RITZIT = 2 };
+/* Randomised eigendecompositions (Section 4): REVD (Algorithm 3), Nystrom (Algorithm 4),
+ * REVD_ritzit (Algorithm 5), and the single-pass Nystrom that Section 6 proposes as
+ * future work (the Nystrom approximation Y (G_4^T Y)^{-1} Y^T on G_4 = orth(G), Y = A G_4:
+ * one product with A). */
+enum { WC4D_REVD = 0, WC4D_NYSTROM = 1, WC4D_RITZIT = 2, WC4D_NYSTROM_1P = 3 };
 enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
 /* Precision flags (wc4d_finalize).  FP64 everywhere by default.
  *   WC4D_PREC_SKETCH_BF16X3: the D^{1/2} products of the block applies inside
@@ -101,6 +105,11 @@ int wc4d_set_model_l96(wc4d_problem p, const double* traj, double F, double dt);
 /* Host helper: nonlinear Lorenz-96 RK4 trajectory from x0 (host, n doubles) into
  * traj (host, (N+1) x n row-major); traj[0] = x0. */
 int wc4d_l96_trajectory(int n, int N, double F, double dt, const double* x0, double* traj);
+/* The same with model error (eq. model: x_{i+1} = M(x_i) + eta_{i+1}): eta host, N x n
+ * row-major, row i = eta_{i+1} (NULL: none).  For the outer loop's state x^(j) from
+ * p^(j) = (x_0, eta_1..eta_N) (Section 2.1). */
+int wc4d_l96_trajectory_forced(int n, int N, double F, double dt, const double* x0, const double* eta,
+                               double* traj);
 
 /* Host helper: sigma * C^{1/2}, the symmetric square root of sigma^2 C, where C
  * is the periodic correlation matrix C_ij = rho(d_ij), d_ij = (n/pi) sin(pi|i-j|/n)
@@ -181,7 +190,8 @@ int wc4d_philox4x32_10(int device, const unsigned int* ctr_key, unsigned int* ou
 
 /* Randomised estimate of the k_r leading eigenpairs of A from a sketch of width
  * m = k_r + l (Section 4): method WC4D_REVD (Algorithm 3), WC4D_NYSTROM
- * (Algorithm 4) or WC4D_RITZIT (Algorithm 5), then the spectral LMP
+ * (Algorithm 4), WC4D_RITZIT (Algorithm 5) or WC4D_NYSTROM_1P (single-pass Nystrom,
+ * Section 6), then the spectral LMP
  * C = I + U (Theta^{-1/2} - I) U^T (eq. spectral_LMP_factor in closed form).
  * G: device n_A x m column-major (ld n_A) start matrix supplied by the caller, or NULL:
  * the build then draws the n_A x m Gaussian block of `seed` (wc4d_gaussian_block) on the
@@ -202,7 +212,7 @@ int wc4d_lmp_theta(wc4d_lmp L, double* theta_host);
 int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s);
 /* Y = C X for m vectors (C = C^T).  X, Y device n_A x m; must not overlap. */
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
-/* Block products with A spent by the build (Table 1: 2 / 2 / 1). */
+/* Block products with A spent by the build (Table 1: 2 / 2 / 1; single-pass Nystrom 1). */
 int wc4d_lmp_applies(wc4d_lmp L, int* count);
 /* The copy of U that the one- and two-vector passes stream (and wc4d_pcg with it):
  * *prec_flag = WC4D_PREC_LMP_FP16, WC4D_PREC_LMP_FP32 or 0 (U itself, float64).  A
@@ -249,6 +259,31 @@ typedef struct {
 int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
              wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
              hipStream_t s);
+
+/* ------------------------------------- outer loop: the previous loop's LMP -- */
+/* Algorithm 1 without a second-level preconditioner (C = I, plain CG on A x = b) that
+ * also returns the Lanczos information of Section 3.4: the CG coefficients alpha_j and
+ * beta_j (host arrays of opts->maxit doubles; entries 0..info->iters-1 are written) and the
+ * Lanczos vectors f_j = (-1)^j r_j / ||r_j|| for j = 0..info->iters in the columns of F
+ * (device, n_A x (opts->maxit + 1), ldf >= n_A).  The alternating sign makes F_j^T A F_j the
+ * tridiagonal T_j with the positive off-diagonal of Section 3.4 (which writes r_j / ||r_j||).
+ * Otherwise as wc4d_pcg. */
+int wc4d_pcg_lanczos(wc4d_problem p, const double* b, double* x, const wc4d_pcg_opts* opts, wc4d_pcg_info* info,
+                     double* alphas, double* betas, double* F, long long ldf, hipStream_t s);
+/* The k largest Ritz pairs of A from j CG iterations (Section 3.4): T_j from alphas[0..j)
+ * and betas[0..j) (gamma_1 = 1/alpha_1, gamma_i = 1/alpha_i + beta_{i-1}/alpha_{i-1},
+ * tau_i = sqrt(beta_i)/alpha_i), its eigenpairs by one-sided Jacobi on the device, Ritz
+ * values theta (host, k, decreasing) and Ritz vectors U = F_j W (device n_A x k, ldu >= n_A)
+ * with F_j the first j columns of F from wc4d_pcg_lanczos.  1 <= k <= j <= 512.
+ * Synchronous; WC4D_ENOCONV if the Jacobi iteration has not converged. */
+int wc4d_lanczos_pairs(wc4d_problem p, int j, const double* alphas, const double* betas, const double* F,
+                       long long ldf, int k, double* U, long long ldu, double* theta, hipStream_t s);
+/* A spectral LMP C = I + U (Theta^{-1/2} - I) U^T (eq. spectral_LMP_factor) on problem p
+ * from given Ritz pairs: U device n_A x k (ldu >= n_A, copied), theta host (k, > 0) -- e.g.
+ * pairs of the previous inner loop's Hessian from wc4d_lanczos_pairs, which precondition
+ * the next inner loop (Sections 3.4 and 5.2).  The LMP streams its float64 U.  Synchronous. */
+int wc4d_lmp_from_pairs(wc4d_problem p, int k, const double* U, long long ldu, const double* theta,
+                        wc4d_lmp* out, hipStream_t s);
 
 /* Per-stage timing of wc4d_apply_A.  With profiling enabled, every apply records
  * HIP events on its stream around its four stages; wc4d_last_apply_timing waits
@@ -321,6 +356,42 @@ int wc4d_autotune_load(const char* path);
 int wc4d_batch_solve(wc4d_problem* ps, int count, int method, int k_r, int l, const double* const* G,
                      const double* const* b, double* const* x, const wc4d_pcg_opts* opts,
                      wc4d_pcg_info* infos, int* status, int workers, int autotune);
+
+/* The same many inner loops with every PCG iteration of every problem in ONE persistent
+ * launch (Section 3.1, Algorithm 1 on each problem's A from Section 2.2; Section 4's
+ * remark that the products of a block can run at the same time, taken across problems).
+ * For each problem ps[i] (finalized advection-diffusion problems with n <= 8192, on one
+ * device, none repeated): the LMP of k_r <= 64 Ritz pairs by `method` from the start block
+ * G[i] (device n_A(i) x (k_r + l)), or, when G or G[i] is NULL, from the Gaussian block of
+ * seed + i drawn on the device (wc4d_gaussian_block), built with the single-problem
+ * kernels; s_0 = b[i] - A x[i] with them too.  Then one launch of a few workgroups per
+ * compute unit runs the whole split PCG of all problems from a device work queue:
+ * per iteration the two D^{1/2} products (64 x 64-level float64 MFMA tiles), the forward
+ * and adjoint sweeps with the observation term (one workgroup each), one pass over U for
+ * U^T (A p, r) and p^T A p, one pass for r, z, x and the true residual s, and p = z + beta p;
+ * float64 dot products reduced in a fixed order.  The last workgroup to finish a phase of
+ * a problem computes its scalars and enqueues the next phase, so problems of any size run
+ * side by side and each stops on its own criterion.  flags: WC4D_BATCH_SWEEP_FP32 runs
+ * the sweeps in float32 (products, LMP and reductions stay float64; the recursive
+ * residual then no longer tracks b - A x below about 1e-6, so check the true residual).
+ * x[i] is the initial guess on entry and the solution on exit; infos[i] / status[i] as
+ * for wc4d_batch_solve; *kernel_ms (may be NULL) receives the persistent launch's time.
+ * Synchronous.  Allocates its queue and per-problem vectors (~6 n_A + q doubles each).
+ * Returns WC4D_EHIP if a queue wait exceeded 20 s (the launch then ends; no problem is
+ * left running on the device). */
+enum { WC4D_BATCH_SWEEP_FP32 = 1 };
+/* Profile of the last persistent launch in this process: for each of the launch's 11
+ * phases (0 C1 u = U^T s0, 1 C2 r0, 2 C3 u = U^T r0, 3 C4 p0 and first dots, 4 D1 first
+ * D^{1/2} product, 5 forward sweep, 6 adjoint sweep, 7 D2 second D^{1/2} product + p, 8 T
+ * U^T (A p, r) and p.Ap, 9 UP r, z, x, s updates, 10 P p update), then 11 the phase
+ * transitions (scalar work and enqueueing), the summed workgroup-busy ms (ms[i]) and item
+ * counts (count[i]); entry 12 holds the launch's elapsed ms and its workgroup count.
+ * Copies min(n, 13) entries; returns 13 (WC4D_EINVAL for null arrays or n < 1). */
+int wc4d_batch_persistent_profile(double* ms, long long* count, int n);
+int wc4d_batch_solve_persistent(wc4d_problem* ps, int count, int method, int k_r, int l,
+                                const double* const* G, unsigned long long seed, const double* const* b,
+                                double* const* x, const wc4d_pcg_opts* opts, int flags, wc4d_pcg_info* infos,
+                                int* status, double* kernel_ms);
 
 /* ------------------------------------------------------- learned sketch -- */
 /* The randomised eigendecompositions of Section 4 (Algorithms 3-5) start from a

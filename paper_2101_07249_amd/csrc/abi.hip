@@ -199,6 +199,11 @@ int wc4d_set_model_l96(wc4d_problem p, const double* traj, double F, double dt) 
 }
 
 int wc4d_l96_trajectory(int n, int N, double F, double dt, const double* x0, double* traj) {
+  return wc4d_l96_trajectory_forced(n, N, F, dt, x0, nullptr, traj);
+}
+
+int wc4d_l96_trajectory_forced(int n, int N, double F, double dt, const double* x0, const double* eta,
+                               double* traj) {
   if (n < 4 || N < 0 || x0 == nullptr || traj == nullptr || !(dt > 0.0)) return WC4D_EINVAL;
   std::vector<double> k1(n), k2(n), k3(n), k4(n), y(n);
   std::memcpy(traj, x0, sizeof(double) * n);
@@ -213,6 +218,8 @@ int wc4d_l96_trajectory(int n, int N, double F, double dt, const double* x0, dou
     for (int j = 0; j < n; ++j) y[j] = x[j] + dt * k3[j];
     l96_f(y.data(), k4.data(), n, F);
     for (int j = 0; j < n; ++j) xn[j] = x[j] + (dt / 6.0) * (k1[j] + 2.0 * k2[j] + 2.0 * k3[j] + k4[j]);
+    if (eta != nullptr)
+      for (int j = 0; j < n; ++j) xn[j] += eta[(size_t)i * n + j];
   }
   return WC4D_OK;
 }
@@ -761,7 +768,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
   *out = nullptr;
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   const int m = k_r + l;
-  if (method < WC4D_REVD || method > WC4D_RITZIT || k_r < 1 || l < 0 || m > p->nA || m > 512)
+  if (method < WC4D_REVD || method > WC4D_NYSTROM_1P || k_r < 1 || l < 0 || m > p->nA || m > 512)
     return fail(p, WC4D_EINVAL, "invalid LMP arguments (method, k_r >= 1, l >= 0, m <= min(n_A, 512))");
   DevGuard g(p->device);
   int rc = ensure_build(p, m);
@@ -820,6 +827,26 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
     // the EVD of R_F R_F^T as the one-sided Jacobi SVD of R_F^T (no squared condition
     // number): singular values sigma, left singular vectors of R_F; Theta = sigma^2
+    he = transpose_small(m, sm.R2, m, sm.K, m, s);
+    evd_sym = false;
+    mode = 2;
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    Zfinal = A_;
+  } else if (method == WC4D_NYSTROM_1P) {
+    // single-pass Nystrom: G_4 = orth(G); Y = A G_4; E = G_4^T Y = C^T C; F = Y C^{-1};
+    // SVD F = U Sigma V^T via F = Q_F R_F and the one-sided Jacobi SVD of R_F^T; Theta = Sigma^2
+    he = G != nullptr ? vec_copy(A_, G, nA * m, s) : gauss_block(seed, nA, m, 0, A_, nA, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    if ((rc = cholqr2(p, A_, B_, m, sm, nullptr, s))) return cleanup(rc);
+    if ((rc = apply_A_core(p, A_, nA, B_, nA, m, nullptr, s, mx))) return cleanup(rc);
+    L->applies = 1;
+    he = gram_f64(m, m, nA, A_, cm, B_, cm, sm.G, m, p->wsGram, nullptr, s);
+    if (he == hipSuccess) he = chol_upper(m, sm.G, m, p->dStatus, s);
+    if (he == hipSuccess) he = tri_inv_upper(m, sm.G, m, sm.Ri, m, s);
+    if (he == hipSuccess)
+      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, plain_cols(m), A_, cm, nullptr, cm, nullptr, s);
+    if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
+    if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
     he = transpose_small(m, sm.R2, m, sm.K, m, s);
     evd_sym = false;
     mode = 2;
@@ -1051,9 +1078,14 @@ int wc4d_lmp_destroy(wc4d_lmp L) {
 
 // ------------------------------------------------------------------ PCG
 
-int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
-             wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
-             hipStream_t s) {
+namespace {
+
+// Algorithm 1 on the device.  With F != null (no LMP only) the normalised residuals
+// f_j = (-1)^j r_j / ||r_j|| go into the columns of F and the CG coefficients into
+// alphas / betas (host): the Lanczos information of Section 3.4.
+int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+            wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J, double* alphas,
+            double* betas, double* F, long long ldf, hipStream_t s) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   if (b == nullptr || x == nullptr || opts == nullptr || info == nullptr || opts->maxit < 1 ||
       !(opts->tol >= 0.0) || (opts->criterion != WC4D_RES_TRUE && opts->criterion != WC4D_RES_PRECOND))
@@ -1077,7 +1109,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     }
   }
   if (p->pcgHistCap < opts->maxit) {
-    if ((rc = dev_alloc(p, &p->pcgHist, (size_t)3 * opts->maxit))) return rc;
+    if ((rc = dev_alloc(p, &p->pcgHist, (size_t)5 * opts->maxit))) return rc;
     p->pcgHistCap = opts->maxit;
   }
   double* r = p->pcgVec;
@@ -1101,6 +1133,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
     HIPCHK(p, vec_copy(pv, r, nA, s));
   }
   HIPCHK(p, pcg_kernels_init(st, b, sres, r, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
+  if (F != nullptr) HIPCHK(p, pcg_lanczos_col(st, 0, r, F, ldf, nA, s));
   double* u = nullptr;
   double* d12 = nullptr;
   double* tvec = nullptr;
@@ -1169,6 +1202,7 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
         wv = w;
       }
       HIPCHK(p, pcg_update_r(st, r, wv, nA, p->pcgRed, p->pcgHist, s));
+      if (F != nullptr) HIPCHK(p, pcg_lanczos_col(st, it + c + 1, r, F, ldf, nA, s));
       const double* zv = r;
       if (L != nullptr) {
         if ((rc = lmp_apply_core(L, r, nA, z, nA, 1, done, s))) return rc;
@@ -1208,8 +1242,28 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
       HIPCHK(p, hipMemcpy(hist_precond, p->pcgHist + opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
     if (hist_J)
       HIPCHK(p, hipMemcpy(hist_J, p->pcgHist + 2 * opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
+    if (alphas)
+      HIPCHK(p, hipMemcpy(alphas, p->pcgHist + 3 * opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
+    if (betas)
+      HIPCHK(p, hipMemcpy(betas, p->pcgHist + 4 * opts->maxit, sizeof(double) * ni, hipMemcpyDeviceToHost));
   }
   return info->status;
+}
+
+}  // namespace
+
+int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+             wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
+             hipStream_t s) {
+  return pcg_run(p, L, b, x, opts, info, hist_true, hist_precond, hist_J, nullptr, nullptr, nullptr, 0, s);
+}
+
+int wc4d_pcg_lanczos(wc4d_problem p, const double* b, double* x, const wc4d_pcg_opts* opts, wc4d_pcg_info* info,
+                     double* alphas, double* betas, double* F, long long ldf, hipStream_t s) {
+  if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (alphas == nullptr || betas == nullptr || F == nullptr || ldf < p->nA)
+    return fail(p, WC4D_EINVAL, "pcg_lanczos: alphas, betas, F (ldf >= n_A) required");
+  return pcg_run(p, nullptr, b, x, opts, info, nullptr, nullptr, nullptr, alphas, betas, F, ldf, s);
 }
 
 }  // extern "C"

@@ -202,6 +202,8 @@ __global__ __launch_bounds__(kRT) void k_beta_final(PcgState* st, const double* 
       hist[it - 1] = rt;
       hist[st->maxit + it - 1] = rp;
       hist[2 * st->maxit + it - 1] = -0.5 * xbs;
+      hist[3 * st->maxit + it - 1] = st->alpha;   // CG coefficients (Section 3.4's T_j)
+      hist[4 * st->maxit + it - 1] = st->beta;
     }
     const double crit = (st->criterion == WC4D_RES_TRUE) ? rt : rp;
     if (!isfinite(crit)) {
@@ -241,6 +243,24 @@ __global__ void k_update_p(const PcgState* __restrict__ st, double* __restrict__
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
+}
+
+// Lanczos vector f_j = (-1)^j r_j / ||r_j|| into column j of F when iteration j has run
+// (st->iter == j; j = 0 is the initial residual).
+__global__ void k_lanczos_col(const PcgState* __restrict__ st, int j, const double* __restrict__ r,
+                              double* __restrict__ F, long long ldf, long long n) {
+  if (st->iter != j || !(st->rr > 0.0)) return;
+  const double sc = ((j & 1) ? -1.0 : 1.0) / sqrt(st->rr);
+  double* f = F + (long long)j * ldf;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    f[i] = sc * r[i];
+}
+
+hipError_t pcg_lanczos_col(const PcgState* st, int j, const double* r, double* F, long long ldf, long long nA,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_col, dim3(1024), dim3(256), 0, s, st, j, r, F, ldf, nA);
+  return hipGetLastError();
 }
 
 hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s) {

@@ -257,6 +257,9 @@ hipError_t pcg_update_xs(PcgState* st, double* x, double* sres, const double* b,
 hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, double* red,
                         double* hist, hipStream_t s);
 hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s);
+// f_j = (-1)^j r_j / ||r_j|| into column j of F (ldf) when st->iter == j.
+hipError_t pcg_lanczos_col(const PcgState* st, int j, const double* r, double* F, long long ldf, long long nA,
+                           hipStream_t s);
 hipError_t vec_copy(double* y, const double* x, long long n, hipStream_t s);
 // Fused LMP inside PCG (see vec.hip): coefficients d1 = dcoef.*t, u <- u - alpha (t + GU d1),
 // d2 = dcoef.*u into d12 (2k); then the dual pass updating r, writing z, and beta.  U as for

@@ -22,11 +22,12 @@ LIB_PATH = os.path.join(_HERE, "libwc4d.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOTSPD, EBREAKDOWN, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 CORR_SOAR, CORR_GAUSS = 0, 1
-REVD, NYSTROM, RITZIT = 0, 1, 2
-METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT}
+REVD, NYSTROM, RITZIT, NYSTROM_1P = 0, 1, 2, 3
+METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT, "nystrom1p": NYSTROM_1P}
 RES_TRUE, RES_PRECOND = 0, 1
 PCG_FUSED, PCG_PLAIN = 0, 1
 PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32, PREC_SKETCH_FP16X3, PREC_LMP_FP16 = 0, 1, 2, 4, 8
+BATCH_SWEEP_FP32 = 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -81,6 +82,14 @@ _SIGS = {
     "wc4d_lmp_destroy": (ctypes.c_int, [_vp]),
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
+    "wc4d_pcg_lanczos": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), _c_dbl_p,
+                                        _c_dbl_p, _vp, ctypes.c_longlong, _vp]),
+    "wc4d_lanczos_pairs": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, _c_dbl_p, _vp, ctypes.c_longlong, ctypes.c_int,
+                                          _vp, ctypes.c_longlong, _c_dbl_p, _vp]),
+    "wc4d_lmp_from_pairs": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_longlong, _c_dbl_p, ctypes.POINTER(_vp),
+                                           _vp]),
+    "wc4d_l96_trajectory_forced": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                  _c_dbl_p, _c_dbl_p, _c_dbl_p]),
     "wc4d_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_stride": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_prof_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -96,6 +105,11 @@ _SIGS = {
                                         ctypes.c_int, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                         ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                         _c_int_p, ctypes.c_int, ctypes.c_int]),
+    "wc4d_batch_solve_persistent": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.c_int, ctypes.POINTER(_vp), ctypes.c_ulonglong,
+                                                   ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(PcgOpts),
+                                                   ctypes.c_int, ctypes.POINTER(PcgInfo), _c_int_p, _c_dbl_p]),
+    "wc4d_batch_persistent_profile": (ctypes.c_int, [_c_dbl_p, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]),
     "wc4d_sketchnet_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int]),
     "wc4d_sketchnet_destroy": (ctypes.c_int, [_vp]),
@@ -253,11 +267,19 @@ def corr_sqrt(n: int, kind: str, L: float, sigma: float) -> np.ndarray:
     return out
 
 
-def l96_trajectory(x0: np.ndarray, F: float, dt: float, N: int) -> np.ndarray:
+def l96_trajectory(x0: np.ndarray, F: float, dt: float, N: int, eta: Optional[np.ndarray] = None) -> np.ndarray:
+    """The Lorenz-96 RK4 trajectory from x0 ((N+1, n)), with model error eta ((N, n), row i
+    added after step i) when given."""
     x0 = np.ascontiguousarray(x0, dtype=np.float64)
     n = x0.shape[0]
     out = np.empty((N + 1, n))
-    rc = lib().wc4d_l96_trajectory(n, N, float(F), float(dt), _dptr(x0), _dptr(out))
+    if eta is None:
+        rc = lib().wc4d_l96_trajectory(n, N, float(F), float(dt), _dptr(x0), _dptr(out))
+    else:
+        e = np.ascontiguousarray(eta, dtype=np.float64)
+        if e.shape != (N, n):
+            raise ValueError("eta must be (N, n)")
+        rc = lib().wc4d_l96_trajectory_forced(n, N, float(F), float(dt), _dptr(x0), _dptr(e), _dptr(out))
     if rc:
         raise Wc4dError(rc, "wc4d_l96_trajectory")
     return out
@@ -517,6 +539,48 @@ class Problem:
             out.update(hist_true=ht[:k], hist_precond=hp[:k], hist_J=hj[:k])
         return out
 
+    def pcg_lanczos(self, b, x, tol: float = 1e-6, maxit: int = 100, stream=None):
+        """Plain CG (no second-level preconditioner) that also returns the Lanczos
+        information of Section 3.4: (info, alphas, betas, F) with F (maxit + 1, n_A) holding
+        f_j = (-1)^j r_j / ||r_j|| in its rows 0..iters."""
+        import torch
+        bp, xp = _ptrs((b, self.n_A, "pcg_lanczos b"), (x, self.n_A, "pcg_lanczos x"))
+        F = torch.zeros((int(maxit) + 1, self.n_A), dtype=torch.float64, device=self.torch_device)
+        al, be = np.zeros(int(maxit)), np.zeros(int(maxit))
+        opts = PcgOpts(float(tol), int(maxit), RES_TRUE, PCG_PLAIN)
+        info = PcgInfo()
+        rc = lib().wc4d_pcg_lanczos(self._h, bp, xp, ctypes.byref(opts), ctypes.byref(info), _dptr(al), _dptr(be),
+                                    _tptr(F, what="F"), self.n_A, _stream(stream))
+        if rc not in (OK, ENOCONV, EBREAKDOWN):
+            self._chk(rc, "pcg_lanczos")
+        k = info.iters
+        return ({"iters": k, "status": info.status, "relres_true": info.relres_true, "J": info.J},
+                al[:k].copy(), be[:k].copy(), F)
+
+    def lanczos_pairs(self, alphas, betas, F, j: int, k: int, stream=None):
+        """The k largest Ritz pairs from j CG iterations (Section 3.4): (U (k, n_A), theta)."""
+        import torch
+        al = np.ascontiguousarray(alphas, dtype=np.float64)
+        be = np.ascontiguousarray(betas, dtype=np.float64)
+        if al.size < j or be.size < j or F.dim() != 2 or F.shape[0] < j or F.shape[1] != self.n_A:
+            raise ValueError("lanczos_pairs: need j coefficients and an (>= j, n_A) F")
+        U = torch.empty((int(k), self.n_A), dtype=torch.float64, device=self.torch_device)
+        th = np.empty(int(k))
+        self._chk(lib().wc4d_lanczos_pairs(self._h, int(j), _dptr(al), _dptr(be), _tptr(F, what="F"), self.n_A,
+                                           int(k), _tptr(U, what="U"), self.n_A, _dptr(th), _stream(stream)),
+                  "lanczos_pairs")
+        return U, th
+
+    def lmp_from_pairs(self, U, theta, stream=None) -> Lmp:
+        """Spectral LMP on this problem from given Ritz pairs (U (k, n_A), theta (k,))."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        k = th.size
+        up = _tptr(U, (k, self.n_A), "lmp_from_pairs U")
+        h = _vp()
+        self._chk(lib().wc4d_lmp_from_pairs(self._h, int(k), up, self.n_A, _dptr(th), ctypes.byref(h),
+                                            _stream(stream)), "lmp_from_pairs")
+        return Lmp(h.value, self, int(k))
+
     PROF_CLASSES = ("dsqrt_gemm", "sweep_fwd", "sweep_bwd", "lmp_ut", "lmp_un", "build_other",
                     "dsqrt_bf16x3", "sketch_net")
 
@@ -609,6 +673,65 @@ def batch_solve(problems: Sequence[Problem], method, k_r: int, l: int, G, b, x, 
     out = [{"iters": i.iters, "status": i.status, "relres_true": i.relres_true, "relres_precond": i.relres_precond,
             "J": i.J} for i in infos]
     return out, list(status)
+
+
+def batch_solve_persistent(problems: Sequence[Problem], method, k_r: int, l: int, b, x, G=None, seed: int = 0,
+                           tol: float = 1e-6, maxit: int = 5000, criterion: int = RES_TRUE,
+                           sweep_fp32: bool = False):
+    """Solve independent inner loops with all PCG iterations in one persistent launch
+    (wc4d_batch_solve_persistent).  b, x: lists of device tensors (n_A,) per problem; G:
+    None (each problem i draws the Gaussian block of seed + i on the device) or a list of
+    (k_r + l, n_A) tensors.  Returns (infos, status, kernel_ms)."""
+    cnt = len(problems)
+    meth = METHOD[method] if isinstance(method, str) else int(method)
+    if not (len(b) == len(x) == cnt) or (G is not None and len(G) != cnt):
+        raise ValueError("batch_solve_persistent: b, x (and G) need one entry per problem")
+    m = int(k_r) + int(l)
+    items = []
+    for i, p in enumerate(problems):
+        items += [(b[i], p.n_A, f"b[{i}]"), (x[i], p.n_A, f"x[{i}]")]
+        if G is not None:
+            items.append((G[i], (m, p.n_A), f"G[{i}]"))
+    ptrs = _ptrs(*items)
+    step = 2 if G is None else 3
+    P = (_vp * cnt)(*[p._h for p in problems])
+    bp = (_vp * cnt)(*ptrs[0::step])
+    xp = (_vp * cnt)(*ptrs[1::step])
+    Gp = (_vp * cnt)(*ptrs[2::step]) if G is not None else None
+    infos = (PcgInfo * cnt)()
+    status = (ctypes.c_int * cnt)()
+    kms = ctypes.c_double(0.0)
+    opts = PcgOpts(float(tol), int(maxit), int(criterion), PCG_FUSED)
+    rc = lib().wc4d_batch_solve_persistent(P, cnt, meth, int(k_r), int(l), Gp,
+                                           ctypes.c_ulonglong(int(seed) & 0xFFFFFFFFFFFFFFFF), bp, xp,
+                                           ctypes.byref(opts), BATCH_SWEEP_FP32 if sweep_fp32 else 0, infos, status,
+                                           ctypes.byref(kms))
+    if rc != OK:
+        msgs = []
+        for p in problems:
+            m_ = lib().wc4d_last_error(p._h).decode()
+            if m_ and m_ not in msgs:
+                msgs.append(m_)
+        raise Wc4dError(rc, "batch_solve_persistent: " + "; ".join(msgs) +
+                        f" (status per problem: {list(status)})")
+    out = [{"iters": i.iters, "status": i.status, "relres_true": i.relres_true, "relres_precond": i.relres_precond,
+            "J": i.J} for i in infos]
+    return out, list(status), kms.value
+
+
+BATCH_PHASES = ("C1_UtS", "C2_r0", "C3_UtR", "C4_p0", "D1_dsqrt", "FW_sweep", "BW_sweep", "D2_dsqrt",
+                "T_UtAp", "UP_update", "P_update", "transitions")
+
+
+def batch_persistent_profile() -> dict:
+    """Per-phase workgroup-busy ms and item counts of the last persistent launch."""
+    n = len(BATCH_PHASES) + 1
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    lib().wc4d_batch_persistent_profile(ms, cnt, n)
+    out = {name: {"busy_ms": ms[i], "items": cnt[i]} for i, name in enumerate(BATCH_PHASES)}
+    out["launch"] = {"ms": ms[n - 1], "workgroups": cnt[n - 1]}
+    return out
 
 
 class SketchNet:

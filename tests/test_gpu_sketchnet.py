@@ -221,13 +221,14 @@ def test_save_load_roundtrip(tmp_path):
     np.testing.assert_array_equal(net2.get_params(), theta)
 
 
-def test_trained_net_against_gaussian_sketch():
-    """What the committed network (trained on 2000 seeded Lorenz-96 n = 1024, N = 100 inner
-    loops) gains over the Gaussian start block on held-out problems: PCG iterations to the
-    1e-6 true residual with a Nystrom LMP of 59 pairs, and the captured share of the
-    reference subspace.  The measured gain is small (about 1% fewer iterations; a perfect
-    start block gains 7% on this workload), so the assertions guard against a regression:
-    the learned build is used, converges, and needs at most 2% more iterations in total."""
+def test_trained_net_no_regression_against_gaussian_sketch():
+    """A no-regression check, not a gain test: the committed network (trained on 2000 seeded
+    Lorenz-96 n = 1024, N = 100 inner loops) against the Gaussian start block on eight
+    held-out problems, PCG iterations to the 1e-6 true residual with a Nystrom LMP of 59
+    pairs.  The measured gain is within noise (about 1% fewer iterations; even a perfect
+    start block, the reference Ritz vectors themselves, gains only 7% on this workload), so
+    the assertions are that the learned build is used, converges, and needs at most 2% more
+    iterations in total than the Gaussian block."""
     import torch
 
     from paper_2101_07249_amd import SketchNet
@@ -237,7 +238,7 @@ def test_trained_net_against_gaussian_sketch():
     inst = Instances()
     w = inst.w
     tot = {"gaussian": 0, "learned": 0}
-    for a in (EVAL_OFFSET, EVAL_OFFSET + 1):
+    for a in range(EVAL_OFFSET, EVAL_OFFSET + 8):
         say("trained net vs gaussian, instance", a)
         p = inst.problem(a)
         d = torch.from_numpy(np.random.default_rng([w.seed, a, 9]).standard_normal(p.q) * np.sqrt(w.sigma_o2)).to(dev())
