@@ -212,6 +212,17 @@ int wc4d_lmp_theta(wc4d_lmp L, double* theta_host);
 int wc4d_lmp_vectors(wc4d_lmp L, double* U, int ldu, hipStream_t s);
 /* Y = C X for m vectors (C = C^T).  X, Y device n_A x m; must not overlap. */
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+/* wc4d_lmp_apply for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): Y = C X for m = 1 or 2
+ * vectors, X, Y device n_A x m (ldx, ldy >= n_A), not overlapping; the same kernels and
+ * the same result bit for bit.  Allocates nothing: the partial sums of U^T x live in a
+ * fixed 4 MiB device array (one per GPU, held until the process ends; its address is
+ * looked up on the first call on each device).  The LMP needs at most that much
+ * (lmp_gemv scratch for n_A and k_r), else WC4D_EINVAL; m > 2 or overlapping X and Y
+ * give WC4D_EINVAL.  Every call on a GPU shares that GPU's array: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be serialised by the
+ * caller; calls on one stream are ordered. */
+int wc4d_lmp_apply_noalloc(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
 /* Block products with A spent by the build (Table 1: 2 / 2 / 1; single-pass Nystrom 1). */
 int wc4d_lmp_applies(wc4d_lmp L, int* count);
 /* The copy of U that the one- and two-vector passes stream (and wc4d_pcg with it):

@@ -77,6 +77,7 @@ _SIGS = {
     "wc4d_lmp_theta": (ctypes.c_int, [_vp, _c_dbl_p]),
     "wc4d_lmp_vectors": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp]),
     "wc4d_lmp_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_lmp_apply_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
     "wc4d_lmp_applies": (ctypes.c_int, [_vp, _c_int_p]),
     "wc4d_lmp_copy_format": (ctypes.c_int, [_vp, _c_int_p]),
     "wc4d_lmp_destroy": (ctypes.c_int, [_vp]),
@@ -312,6 +313,15 @@ class Lmp:
         xp, yp = _ptrs((X2, None, "lmp_apply X"), (Y, tuple(X.shape), "lmp_apply Y"))
         self.prob._chk(lib().wc4d_lmp_apply(self._h, xp, self.prob.n_A, yp, self.prob.n_A, m, _stream(stream)),
                        "lmp_apply")
+        return Y
+
+    def apply_noalloc(self, X, Y, stream=None):
+        """Y = C X (one or two vectors) through wc4d_lmp_apply_noalloc: no device allocation;
+        Y must be given."""
+        m, X2 = _block_rows(X, self.prob.n_A, "lmp_apply_noalloc X")
+        xp, yp = _ptrs((X2, None, "lmp_apply_noalloc X"), (Y, tuple(X.shape), "lmp_apply_noalloc Y"))
+        self.prob._chk(lib().wc4d_lmp_apply_noalloc(self._h, xp, self.prob.n_A, yp, self.prob.n_A, m,
+                                                    _stream(stream)), "lmp_apply_noalloc")
         return Y
 
     @property
