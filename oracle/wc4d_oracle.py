@@ -536,7 +536,8 @@ class PCGResult:
 
 def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
         lmp: Optional[Tuple[np.ndarray, np.ndarray]] = None, tol: float = 1e-6,
-        maxit: int = 100, criterion: int = RES_TRUE, keep_residuals: bool = False) -> PCGResult:
+        maxit: int = 100, criterion: int = RES_TRUE, keep_residuals: bool = False,
+        reorth: bool = False) -> PCGResult:
     """Algorithm 1, split preconditioned CG on C^T A C xhat = C^T b with P = C C^T:
         r_0 = C^T (b - A x_0), p_0 = C r_0;
         alpha_j = r^T r / p^T A p;  x_j = x_{j-1} + alpha_j p_{j-1};
@@ -545,8 +546,16 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
     Alongside it keeps s_j = b - A x_j by the recursion s_j = s_{j-1} - alpha_j A p_{j-1}
     (the true residual) and the quadratic cost J(x) = x^T A x / 2 - b^T x = -x^T (b + s) / 2.
     Stops when ||s_j|| / ||b|| <= tol (criterion RES_TRUE) or ||r_j|| / ||r_0|| <= tol
-    (RES_PRECOND), or after maxit iterations."""
+    (RES_PRECOND), or after maxit iterations.
+
+    reorth (no LMP only): complete reorthogonalisation, Section 3.4's remedy for the repeated
+    ('ghost') Ritz values that loss of orthogonality brings: each new r_j is orthogonalised
+    against all earlier normalised residuals r_i / ||r_i|| (classical Gram-Schmidt, applied
+    twice) before r_j^T r_j and beta_j are formed.  In exact arithmetic the residuals are
+    already orthogonal and the iterates are those of CG."""
     b = np.asarray(b, dtype=np.float64)
+    if reorth and lmp is not None:
+        raise ValueError("pcg: reorthogonalisation is defined here for CG without an LMP")
     if lmp is None:
         C = lambda v: v  # noqa: E731
     else:
@@ -561,6 +570,7 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
     rr = r @ r
     ht, hp, hJ, al, be = [], [], [], [], []
     res = [r.copy()] if keep_residuals else None
+    Q = [r / np.sqrt(rr)] if reorth and rr > 0.0 else []
     it = 0
     converged = False
     if bnorm == 0.0:
@@ -571,6 +581,11 @@ def pcg(applyA: Callable, b: np.ndarray, x0: Optional[np.ndarray] = None,
         x = x + alpha * p
         s = s - alpha * Ap
         r = r - alpha * C(Ap)
+        if reorth:
+            Qm = np.stack(Q, axis=1)
+            for _ in range(2):
+                r = r - Qm @ (Qm.T @ r)
+            Q.append(r / np.linalg.norm(r))
         if keep_residuals:
             res.append(r.copy())
         rr_new = r @ r

@@ -403,6 +403,67 @@ def test_ritz_lmp_mutations_are_caught(monkeypatch):
     assert _fails(pins.test_standard_pcg_equals_split_pcg_and_cg)
 
 
+def test_reorthogonalisation_mutations_are_caught(monkeypatch):
+    """Reorthogonalisation against the last residual only, or a single projection with the
+    earlier vectors unnormalised, each fail the ghost pin."""
+    orig = O.pcg
+
+    def last_only(applyA, b, x0=None, lmp=None, tol=1e-6, maxit=100, criterion=O.RES_TRUE,
+                  keep_residuals=False, reorth=False):
+        if not reorth:
+            return orig(applyA, b, x0, lmp, tol, maxit, criterion, keep_residuals)
+        x = np.zeros_like(b)
+        r = b.copy()
+        p = r.copy()
+        rr = r @ r
+        res, al, be = [r.copy()], [], []
+        for _ in range(maxit):
+            Ap = applyA(p)
+            a = rr / (p @ Ap)
+            x = x + a * p
+            q = r / np.linalg.norm(r)
+            r = r - a * Ap
+            r = r - q * (q @ r)
+            res.append(r.copy())
+            rn = r @ r
+            be.append(rn / rr)
+            al.append(a)
+            p = r + (rn / rr) * p
+            rr = rn
+        return O.PCGResult(x, maxit, False, 0.0, 0.0, 0.0, [], [], [], al, be, res)
+
+    monkeypatch.setattr(O, "pcg", last_only)
+    assert _fails(pins.test_cg_reorthogonalisation_removes_ghost_ritz_values)
+    monkeypatch.setattr(O, "pcg", orig)
+
+    def unnormalised(applyA, b, x0=None, lmp=None, tol=1e-6, maxit=100, criterion=O.RES_TRUE,
+                     keep_residuals=False, reorth=False):
+        if not reorth:
+            return orig(applyA, b, x0, lmp, tol, maxit, criterion, keep_residuals)
+        x = np.zeros_like(b)
+        r = b.copy()
+        p = r.copy()
+        rr = r @ r
+        res, al, be = [r.copy()], [], []
+        for _ in range(maxit):
+            Ap = applyA(p)
+            a = rr / (p @ Ap)
+            x = x + a * p
+            r = r - a * Ap
+            R = np.stack(res, axis=1)
+            r = r - R @ (R.T @ r)
+            res.append(r.copy())
+            rn = r @ r
+            be.append(rn / rr)
+            al.append(a)
+            p = r + (rn / rr) * p
+            rr = rn
+        return O.PCGResult(x, maxit, False, 0.0, 0.0, 0.0, [], [], [], al, be, res)
+
+    monkeypatch.setattr(O, "pcg", unnormalised)
+    assert _fails(pins.test_cg_reorthogonalisation_removes_ghost_ritz_values)
+
+
 def test_lanczos_and_outer_loop_mutations_are_caught(monkeypatch):
     """Lanczos vectors without the alternating signs, T_j without the beta/alpha term on its
     diagonal, the outer loop's b with the wrong sign, and a trajectory that ignores the model

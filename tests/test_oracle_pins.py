@@ -783,6 +783,41 @@ def test_cg_lanczos_pairs_converge_to_the_largest_eigenpairs():
     assert abs(abs(U[:, 0] @ V[:, -1]) - 1.0) <= 1e-6
 
 
+def _ghost_matrix():
+    """A symmetric matrix with five large, well separated eigenvalues over a bulk in [1, 50]
+    (the shape of the Hessian's spectrum: a few large eigenvalues above a cluster)."""
+    rng = np.random.default_rng(7)
+    n = 300
+    lam = np.concatenate([[1e4, 5e3, 2.5e3, 1.2e3, 600.0], np.geomspace(1.0, 50.0, n - 5)])
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), lam, Q, rng.standard_normal(n)
+
+
+def test_cg_reorthogonalisation_removes_ghost_ritz_values():
+    """Section 3.4: without reorthogonalisation, 60 CG iterations repeat the converged largest
+    eigenvalue as 'ghost' Ritz values (the normalised residuals lose orthogonality); with
+    complete reorthogonalisation the residuals stay orthonormal, the five largest Ritz values
+    and vectors are A's five largest eigenpairs, and the first iterates are CG's."""
+    A, lam, Q, b = _ghost_matrix()
+    plain = O.pcg(lambda v: A @ v, b, tol=0.0, maxit=60, keep_residuals=True)
+    _, thp = O.cg_lanczos_pairs(plain, 2, 60)
+    assert abs(thp[1] - lam[0]) <= 1e-6 * lam[0]          # a ghost of the largest
+    res = O.pcg(lambda v: A @ v, b, tol=0.0, maxit=60, keep_residuals=True, reorth=True)
+    F = np.stack([r / np.linalg.norm(r) for r in res.residuals[:60]], axis=1)
+    np.testing.assert_allclose(F.T @ F, np.eye(60), atol=1e-13)
+    U, th = O.cg_lanczos_pairs(res, 5, 60)
+    np.testing.assert_allclose(th, lam[:5], rtol=1e-10)
+    for i in range(5):
+        assert abs(abs(U[:, i] @ Q[:, i]) - 1.0) <= 1e-10
+    # the same iterates as CG while the residuals are still orthogonal
+    x5 = O.pcg(lambda v: A @ v, b, tol=0.0, maxit=5).x
+    x5r = O.pcg(lambda v: A @ v, b, tol=0.0, maxit=5, reorth=True).x
+    np.testing.assert_allclose(x5r, x5, rtol=0.0, atol=1e-13 * np.abs(x5).max())
+    with pytest.raises(ValueError):
+        O.pcg(lambda v: A @ v, b, lmp=(Q[:, :2], lam[:2]), reorth=True)
+
+
 def _twin(w, n_outer, inner):
     prob = build(w)
     draws = twin_draws(w, prob.q)
