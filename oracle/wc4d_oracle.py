@@ -326,6 +326,64 @@ def rhs(prob: Problem, d: np.ndarray, bt: Optional[np.ndarray] = None) -> np.nda
     return out
 
 
+# --- strong-constraint counterpart (Section 6: the approach carries over) ---
+# With a perfect model there is no forcing: the control is x_0 alone, the trajectory is
+# x_i = M_{i-1} ... M_0 x_0, and the B^{1/2}-preconditioned Hessian is
+#     A_sc = I + B^{1/2} (sum_i M_{0->i}^T H_i^T R_i^{-1} H_i M_{0->i}) B^{1/2},
+# of size n.  It is the weak-constraint operator with the model-error blocks removed.
+
+
+def apply_A_sc(prob: Problem, X: np.ndarray) -> np.ndarray:
+    """A_sc X: x_0 = B^{1/2} X, x_{i+1} = M_i x_i; z_i = H_i^T R_i^{-1} H_i x_i; w_N = z_N,
+    w_i = z_i + M_i^T w_{i+1}; A_sc X = X + B^{1/2} w_0."""
+    X = np.asarray(X, dtype=np.float64)
+    squeeze = X.ndim == 1
+    if squeeze:
+        X = X[:, None]
+    prob.n_apply += 1
+    xs = [prob.Bsqrt @ X]
+    for i in range(prob.N):
+        xs.append(prob.M(i, xs[-1]))
+    Z = apply_HtRinvH(prob, np.concatenate(xs, axis=0))
+    Zl = _levels(prob, Z)
+    w = Zl[prob.N]
+    for i in range(prob.N - 1, -1, -1):
+        w = Zl[i] + prob.MT(i, w)
+    Y = X + prob.Bsqrt @ w
+    return Y[:, 0] if squeeze else Y
+
+
+def rhs_sc(prob: Problem, d: np.ndarray, bt: Optional[np.ndarray] = None) -> np.ndarray:
+    """Right-hand side of the strong-constraint system: B^{1/2} w_0 with w the adjoint sweep of
+    H^T R^{-1} d (plus bt = B^{-1/2} (x^b - x_0) in later outer loops)."""
+    Zl = _levels(prob, apply_HtRinv(prob, d)[:, None])
+    w = Zl[prob.N]
+    for i in range(prob.N - 1, -1, -1):
+        w = Zl[i] + prob.MT(i, w)
+    out = (prob.Bsqrt @ w)[:, 0]
+    if bt is not None:
+        out = out + bt
+    return out
+
+
+def dense_A_sc(prob: Problem) -> np.ndarray:
+    """A_sc assembled from explicit products M_{0->i} = M_{i-1} ... M_0 (tiny problems)."""
+    n = prob.n
+    H = np.zeros((n, n))
+    Mp = np.eye(n)
+    obs_by_t = {}
+    for i, idx, rdiag in prob.obs:
+        obs_by_t.setdefault(i, []).append((idx, rdiag))
+    for i in range(prob.N + 1):
+        if i > 0:
+            Mp = dense_M(prob, i - 1) @ Mp
+        for idx, rdiag in obs_by_t.get(i, []):
+            Hi = np.zeros((len(idx), n))
+            Hi[np.arange(len(idx)), idx] = 1.0
+            H += Mp.T @ Hi.T @ np.diag(1.0 / rdiag) @ Hi @ Mp
+    return np.eye(n) + prob.Bsqrt @ H @ prob.Bsqrt
+
+
 # --- dense assembly from the block definitions (tiny problems only) ---
 
 

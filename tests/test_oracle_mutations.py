@@ -403,6 +403,34 @@ def test_ritz_lmp_mutations_are_caught(monkeypatch):
     assert _fails(pins.test_standard_pcg_equals_split_pcg_and_cg)
 
 
+def test_strong_constraint_mutations_are_caught(monkeypatch):
+    """The strong-constraint adjoint sweep with M_i for M_i^T, or without B^{1/2} on its
+    output, fails a pin."""
+    orig = O.apply_A_sc
+
+    def forward_in_adjoint(prob, X):
+        X = np.asarray(X, dtype=np.float64)
+        xs = [prob.Bsqrt @ X]
+        for i in range(prob.N):
+            xs.append(prob.M(i, xs[-1]))
+        Zl = O._levels(prob, O.apply_HtRinvH(prob, np.concatenate(xs, axis=0)))
+        w = Zl[prob.N]
+        for i in range(prob.N - 1, -1, -1):
+            w = Zl[i] + prob.M(i, w)
+        return X + prob.Bsqrt @ w
+
+    monkeypatch.setattr(O, "apply_A_sc", forward_in_adjoint)
+    assert _fails(lambda: pins.test_strong_constraint_is_weak_constraint_without_model_error("advdiff"))
+    assert _fails(pins.test_strong_constraint_dense_assembly_and_spectrum)
+
+    def no_output_sqrt(prob, X):
+        X = np.asarray(X, dtype=np.float64)
+        return X + np.linalg.solve(prob.Bsqrt, orig(prob, X) - X)
+
+    monkeypatch.setattr(O, "apply_A_sc", no_output_sqrt)
+    assert _fails(lambda: pins.test_strong_constraint_is_weak_constraint_without_model_error("l96"))
+
+
 def test_reorthogonalisation_mutations_are_caught(monkeypatch):
     """Reorthogonalisation against the last residual only, or a single projection with the
     earlier vectors unnormalised, each fail the ghost pin."""

@@ -783,6 +783,55 @@ def test_cg_lanczos_pairs_converge_to_the_largest_eigenpairs():
     assert abs(abs(U[:, 0] @ V[:, -1]) - 1.0) <= 1e-6
 
 
+# ----------------------------------------------------------------- strong constraint
+
+
+def _no_model_error(prob):
+    import copy
+    q = copy.copy(prob)
+    q.Qsqrt = np.zeros_like(prob.Qsqrt)
+    return q
+
+
+@pytest.mark.parametrize("model", ["advdiff", "l96"])
+def test_strong_constraint_is_weak_constraint_without_model_error(model):
+    """Section 6's strong-constraint counterpart: with Q^{1/2} = 0 the weak-constraint operator
+    maps (x_0, 0, ..., 0) to (A_sc x_0, 0, ..., 0) and its right-hand side is (b_sc, 0, ..., 0)."""
+    w = tiny_advdiff(n=8, N=4, vs=2, ts=1) if model == "advdiff" else tiny_l96(n=10, N=4)
+    prob = build(w)
+    pz = _no_model_error(prob)
+    n, N = prob.n, prob.N
+    X = random_block(n, 3, 41)
+    Xp = np.zeros((prob.n_A, 3))
+    Xp[:n] = X
+    Yw = O.apply_A(pz, Xp)
+    Ys = O.apply_A_sc(prob, X)
+    np.testing.assert_allclose(Yw[:n], Ys, rtol=0, atol=1e-12 * np.abs(Ys).max())
+    np.testing.assert_allclose(Yw[n:], 0.0, atol=1e-12 * np.abs(Ys).max())
+    d = innovations(prob.q, 42, 0.2)
+    bw = O.rhs(pz, d)
+    bs = O.rhs_sc(prob, d)
+    np.testing.assert_allclose(bw[:n], bs, rtol=0, atol=1e-12 * np.abs(bs).max())
+    np.testing.assert_allclose(bw[n:], 0.0, atol=1e-12 * np.abs(bs).max())
+
+
+def test_strong_constraint_dense_assembly_and_spectrum():
+    """A_sc from the sweeps equals I + B^{1/2} (sum_i M_{0->i}^T H_i^T R_i^{-1} H_i M_{0->i}) B^{1/2}
+    built from explicit matrix products; it is symmetric with eigenvalues >= 1, at most
+    min(n, q) of them above one, and a full sketch recovers its spectrum."""
+    prob = build(tiny_advdiff(n=12, N=5, vs=3, ts=2))
+    n = prob.n
+    A = O.apply_A_sc(prob, np.eye(n))
+    Ad = O.dense_A_sc(prob)
+    np.testing.assert_allclose(A, Ad, rtol=0, atol=1e-12 * np.abs(Ad).max())
+    np.testing.assert_allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+    lam = np.sort(np.linalg.eigvalsh(A))[::-1]
+    assert lam[-1] >= 1.0 - 1e-12
+    assert int(np.sum(lam > 1.0 + 1e-9)) <= min(n, prob.q)
+    U, th = O.nystrom(lambda Z: O.apply_A_sc(prob, Z), sketch_block(n, n, 5), n)
+    np.testing.assert_allclose(th, lam, rtol=1e-10, atol=1e-10 * lam[0])
+
+
 def _ghost_matrix():
     """A symmetric matrix with five large, well separated eigenvalues over a bulk in [1, 50]
     (the shape of the Hessian's spectrum: a few large eigenvalues above a cluster)."""
