@@ -108,6 +108,11 @@ def parse():
     ap.add_argument("--learned-problems", type=int, default=8, help="held-out problems of the learned comparison")
     ap.add_argument("--no-oversampling", action="store_true", help="skip the realisation / oversampling statistics")
     ap.add_argument("--realisations", type=int, default=50)
+    ap.add_argument("--no-second-loop", action="store_true",
+                    help="skip the Gauss-Newton second-loop comparison (Section 5.2)")
+    ap.add_argument("--second-loop-realisations", type=int, default=10)
+    ap.add_argument("--no-strong", action="store_true", help="skip the strong-constraint inner loop")
+    ap.add_argument("--no-ritz", action="store_true", help="skip the Ritz-LMP cost study")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--batched-compare", action="store_true",
@@ -285,6 +290,112 @@ def oversampling_section(args):
                                 "iters_std": float(np.std(its)), "iters_min": int(min(its)), "iters_max": int(max(its))})
         print(f"oversampling: {method} done", file=sys.stderr, flush=True)
     out["s"] = time.perf_counter() - t0
+    p.close()
+    return out
+
+
+def second_loop_section(args):
+    """Section 5.2's headline comparison on its Lorenz-96 configuration, per observation
+    network (120, 480 and 3000 observations: every 10th, 5th and 2nd variable at every 10th,
+    5th and 2nd step): an identical-twin experiment, a first inner loop of CG (100 iterations
+    or 1e-6) with reorthogonalised Lanczos information, then the second loop's PCG without an
+    LMP, with the previous loop's k Ritz pairs (the deterministic LMP) and with the randomised
+    LMPs built on the second loop's Hessian (l = 5; means over the realisations)."""
+    import numpy as np
+
+    from paper_2101_07249_amd.outer_loop import OuterLoopL96, second_loop_study
+    from synthetic import SEC52, obs_count, obs_pattern, twin_draws
+
+    out = {"workload": SEC52.name, "realisations": args.second_loop_realisations, "networks": []}
+    t0 = time.perf_counter()
+    for stride, ks in ((10, (5, 10, 15)), (5, (5, 15)), (2, (5, 15))):
+        w = SEC52.with_(obs_var_stride=stride, obs_time_stride=stride)
+        pat = obs_pattern(w)
+        draws = twin_draws(w, obs_count(pat))
+        exp = OuterLoopL96(w, pat, draws)
+        res = second_loop_study(exp, ks=ks, l=5, tol=args.tol, maxit=args.maxit,
+                                realisations=args.second_loop_realisations, seed=7000)
+        rows = {}
+        for name, r in res["second"].items():
+            rows[name] = {"iters": r.get("iters_mean", r["iters"]), "iters_std": r.get("iters_std", 0.0),
+                          "J": [float(v) for v in r.get("J_mean", r["J"])], "theta_max": r.get("theta_max")}
+        out["networks"].append({"obs": obs_count(pat), "stride": stride, "first_loop_iters": res["first_loop_iters"],
+                                "second_loop": rows})
+        print(f"second loop: {obs_count(pat)} observations done", file=sys.stderr, flush=True)
+    out["s"] = time.perf_counter() - t0
+    return out
+
+
+def strong_section(args):
+    """The strong-constraint counterpart at the benchmark's sizes (n = 4096, N = 100: the
+    control is x_0 alone, the operator I + B^{1/2} (sum_i M_{0->i}^T H_i^T R_i^{-1} H_i
+    M_{0->i}) B^{1/2}): rhs, Nystrom LMP from a device-drawn block, PCG to the tolerance,
+    against PCG without an LMP."""
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd import Problem
+    from synthetic import C3, innovations, obs_pattern
+
+    w = C3
+    p = Problem.from_workload(w, obs_pattern(w), strong=True)
+    d = torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device)
+    out = {"workload": "strong_" + w.name, "n_A": p.n_A, "q": p.q}
+    x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
+    for label, k_r in (("none", 0), ("nystrom", w.m - w.l)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = p.rhs(d)
+        L = p.lmp_build("nystrom", k_r, w.l, seed=w.seed) if k_r else None
+        x.zero_()
+        info = p.pcg(b, x, L, tol=args.tol, maxit=args.maxit)
+        torch.cuda.synchronize()
+        out[label] = {"ms": 1e3 * (time.perf_counter() - t0), "pcg_iters": info["iters"],
+                      "relres_true": info["relres_true"], "converged": info["status"] == 0}
+        if L is not None:
+            out[label]["theta_max"] = float(L.theta()[0])
+            L.close()
+    p.close()
+    return out
+
+
+def ritz_section(args):
+    """The Ritz-LMP of eq. Ritz_LMP against the spectral LMP on the benchmark's workload
+    (float64): one Nystrom LMP (k_r = 251); PCG with the spectral LMP (split, fused: two
+    passes over U per iteration) and with the Ritz-LMP (one extra block product for A U, then
+    four passes over U and A U per iteration); iterations and time of each solve."""
+    import numpy as np
+    import torch
+
+    from paper_2101_07249_amd import Problem
+    from synthetic import C3, innovations, obs_pattern
+
+    w = C3
+    p = Problem.from_workload(w, obs_pattern(w))
+    b = p.rhs(torch.from_numpy(innovations(p.q, w.seed, np.sqrt(w.sigma_o2))).to(p.torch_device))
+    L = p.lmp_build("nystrom", w.m - w.l, w.l, seed=w.seed)
+    x = torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device)
+    out = {"workload": w.name, "k_r": w.m - w.l}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = p.pcg(b, x, L, tol=args.tol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    out["spectral"] = {"ms": ms, "pcg_iters": info["iters"], "ms_per_iter": ms / max(info["iters"], 1),
+                       "relres_true": info["relres_true"]}
+    t0 = time.perf_counter()
+    L.ritz_prepare()
+    torch.cuda.synchronize()
+    prep = 1e3 * (time.perf_counter() - t0)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = p.pcg_ritz(b, x, L, tol=args.tol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0)
+    out["ritz"] = {"prepare_ms": prep, "ms": ms, "pcg_iters": info["iters"], "ms_per_iter": ms / max(info["iters"], 1),
+                   "relres_true": info["relres_true"]}
+    L.close()
     p.close()
     return out
 
@@ -489,6 +600,12 @@ def main():
     }
     if not args.no_learned:
         out["learned"] = learned_section(args)
+    if not args.no_second_loop:
+        out["second_loop"] = second_loop_section(args)
+    if not args.no_strong:
+        out["strong_constraint"] = strong_section(args)
+    if not args.no_ritz:
+        out["ritz_lmp"] = ritz_section(args)
     if not args.no_batched:
         out["batched"] = batched_section(args)
     if not args.no_oversampling:

@@ -70,13 +70,24 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *   WC4D_PREC_LMP_FP16: the same with a float16 copy, each column scaled by a power of
  *     two (largest magnitude brought to [2^14, 2^15)), half the bytes per pass; excludes
  *     WC4D_PREC_LMP_FP32.  Either copy changes the preconditioner by its rounding only, so
- *     PCG still solves A x = b; the iteration count may differ. */
+ *     PCG still solves A x = b; the iteration count may differ.
+ *   WC4D_PREC_DSQRT_OZ7: the one-vector D^{1/2} products (wc4d_pcg's applies of A,
+ *     wc4d_rhs, any wc4d_apply_A with m = 1) run on the int8 matrix cores by an error-free
+ *     splitting into 7 slices of 7 bits per operand (the Ozaki scheme, in its integer
+ *     form): per-row exponents of Q^{1/2} and per-column exponents of the vector's levels,
+ *     exact int32 slice products, the pairs of slices with t + u <= 8 combined in float64.
+ *     Error a few n 2^-49 relative to max|row of Q^{1/2}| max|level| (about 1e-13 of a
+ *     level's largest entry at n = 4096); the int8 slices of Q^{1/2} take 7 n^2 bytes and
+ *     are made once at wc4d_finalize.  Needs B^{1/2} = c Q^{1/2} (one product over all
+ *     levels; WC4D_EINVAL otherwise) and n <= 8192 per K split (always met: splits
+ *     are chosen so). */
 enum {
   WC4D_PREC_FP64 = 0,
   WC4D_PREC_SKETCH_BF16X3 = 1,
   WC4D_PREC_LMP_FP32 = 2,
   WC4D_PREC_SKETCH_FP16X3 = 4,
-  WC4D_PREC_LMP_FP16 = 8
+  WC4D_PREC_LMP_FP16 = 8,
+  WC4D_PREC_DSQRT_OZ7 = 16
 };
 
 /* Library version (major*10000 + minor*100 + patch) and status-code names. */
@@ -131,6 +142,19 @@ int wc4d_set_Qsqrt(wc4d_problem p, const double* Qsqrt);
  * i for wc4d_rhs's innovation vector. */
 int wc4d_set_obs(wc4d_problem p, int i, int q_i, const int* idx, const double* rdiag);
 
+/* Strong-constraint counterpart (the paper's Section 6 names strong-constraint 4D-Var as a
+ * setting the approach carries over to).  With a perfect model the control is x_0 alone
+ * and the operator becomes
+ *     A_sc = I + B^{1/2} (sum_i M_{0->i}^T H_i^T R_i^{-1} H_i M_{0->i}) B^{1/2},
+ * M_{0->i} = M_{i-1} ... M_0, of size n: the weak-constraint operator with the model-error
+ * blocks removed.  Call before wc4d_finalize (WC4D_ESTATE after it) with on = 1: every block
+ * and vector of the problem then has n_A = n rows (wc4d_dims reports it), Q^{1/2} need not
+ * be set and is never applied, wc4d_apply_A / wc4d_rhs / wc4d_lmp_build / wc4d_pcg (and the
+ * calls built on them) use A_sc and its right-hand side B^{1/2} w_0 (w the adjoint sweep of
+ * H^T R^{-1} d) + bt.  Float64 products only: the split sketch flags, wc4d_apply_Linv /
+ * LinvT / Dsqrt, the sketch network, wc4d_autotune and the persistent batch return
+ * WC4D_EINVAL for such a problem.  on = 0 restores the weak-constraint operator. */
+int wc4d_set_strong_constraint(wc4d_problem p, int on);
 /* Upload everything to the device and allocate the operator's fixed data.
  * prec_mode: WC4D_PREC_FP64 or an OR of the WC4D_PREC_* flags.  Synchronous.
  * Setup calls after finalize return WC4D_ESTATE. */
@@ -271,6 +295,28 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
              wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
              hipStream_t s);
 
+/* ------------------------------------------------------------ Ritz-LMP -- */
+/* The Ritz-LMP of eq. Ritz_LMP (Section 3.2), built from an LMP's Ritz pairs (U, Theta):
+ *     P = (I - U Theta^{-1} U^T A)(I - A U Theta^{-1} U^T) + U Theta^{-1} U^T.
+ * It corrects for inexact pairs (P A U = U for Rayleigh-Ritz pairs) at the price of products
+ * with A; the paper describes it and keeps the spectral LMP for its experiments.
+ * wc4d_lmp_ritz_prepare computes and keeps A U (one block product with A over the k_r
+ * Ritz vectors, float64, n_A x k_r extra device memory) and -1/theta; synchronous.  The
+ * other two calls return WC4D_ESTATE until it has run on L. */
+int wc4d_lmp_ritz_prepare(wc4d_lmp L, hipStream_t s);
+/* Y = P X for m vectors (X, Y device n_A x m, not overlapping): per vector four passes over
+ * n_A x k_r (U^T x, (AU) t, (AU)^T y, U t) with A U from wc4d_lmp_ritz_prepare. */
+int wc4d_lmp_ritz_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s);
+/* Preconditioned CG on A x = b with the Ritz-LMP as the preconditioner function (P has no
+ * split factor): r_0 = b - A x_0, z_0 = P r_0, p_0 = z_0; alpha = r^T z / p^T A p;
+ * x += alpha p; r -= alpha A p; z = P r; beta = r_new^T z_new / r^T z; p = z + beta p.
+ * With P = C C^T this is Algorithm 1 in exact arithmetic.  opts->variant is ignored;
+ * WC4D_RES_TRUE stops on ||r|| / ||b|| (r the recursively updated true residual),
+ * WC4D_RES_PRECOND on (r^T P r / r_0^T P r_0)^{1/2}, which info->relres_precond also
+ * reports.  hist_true / hist_J as in wc4d_pcg.  Synchronous. */
+int wc4d_pcg_ritz(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+                  wc4d_pcg_info* info, double* hist_true, double* hist_J, hipStream_t s);
+
 /* ------------------------------------- outer loop: the previous loop's LMP -- */
 /* Algorithm 1 without a second-level preconditioner (C = I, plain CG on A x = b) that
  * also returns the Lanczos information of Section 3.4: the CG coefficients alpha_j and
@@ -278,9 +324,16 @@ int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_
  * Lanczos vectors f_j = (-1)^j r_j / ||r_j|| for j = 0..info->iters in the columns of F
  * (device, n_A x (opts->maxit + 1), ldf >= n_A).  The alternating sign makes F_j^T A F_j the
  * tridiagonal T_j with the positive off-diagonal of Section 3.4 (which writes r_j / ||r_j||).
+ * flags: 0, or WC4D_LANCZOS_REORTH for complete reorthogonalisation (Section 3.4's remedy
+ * for repeated 'ghost' Ritz values): each new residual r_j is orthogonalised twice against
+ * f_0..f_{j-1} (classical Gram-Schmidt over the columns already in F) before r_j^T r_j and
+ * beta_j are formed, which costs two passes over j columns per iteration and needs
+ * opts->maxit <= 512; without it CG's residuals lose orthogonality once a Ritz value has
+ * converged and T_j then repeats converged eigenvalues.  Unknown flags: WC4D_EINVAL.
  * Otherwise as wc4d_pcg. */
+enum { WC4D_LANCZOS_REORTH = 1 };
 int wc4d_pcg_lanczos(wc4d_problem p, const double* b, double* x, const wc4d_pcg_opts* opts, wc4d_pcg_info* info,
-                     double* alphas, double* betas, double* F, long long ldf, hipStream_t s);
+                     double* alphas, double* betas, double* F, long long ldf, int flags, hipStream_t s);
 /* The k largest Ritz pairs of A from j CG iterations (Section 3.4): T_j from alphas[0..j)
  * and betas[0..j) (gamma_1 = 1/alpha_1, gamma_i = 1/alpha_i + beta_{i-1}/alpha_{i-1},
  * tau_i = sqrt(beta_i)/alpha_i), its eigenpairs by one-sided Jacobi on the device, Ritz

@@ -108,6 +108,7 @@ int wc4d_create(wc4d_problem* out, int n, int N, int device) {
   p->N = N;
   p->device = device;
   p->nA = (long long)n * (N + 1);
+  p->nL = p->nA;
   p->obs_idx.assign(N + 1, {});
   p->obs_r.assign(N + 1, {});
   *out = p;
@@ -126,6 +127,11 @@ int wc4d_destroy(wc4d_problem p) {
   p->lmps.clear();
   dev_free(&p->dB);
   dev_free(&p->dQ);
+  dev_free(&p->ozSs);
+  dev_free(&p->ozEs);
+  dev_free(&p->ozXs);
+  dev_free(&p->ozFs);
+  dev_free(&p->ozP);
   dev_free(&p->dBhi);
   dev_free(&p->dBh16);
   dev_free(&p->dBl16);
@@ -295,13 +301,31 @@ int wc4d_set_obs(wc4d_problem p, int i, int q_i, const int* idx, const double* r
   return WC4D_OK;
 }
 
+int wc4d_set_strong_constraint(wc4d_problem p, int on) {
+  if (p == nullptr) return WC4D_EINVAL;
+  if (p->finalized) return fail(p, WC4D_ESTATE, "set_strong_constraint: already finalized");
+  p->strong = on != 0;
+  p->nA = p->strong ? (long long)p->n : p->nL;
+  return WC4D_OK;
+}
+
 int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
   if (p == nullptr) return WC4D_EINVAL;
   if (p->finalized) return fail(p, WC4D_ESTATE, "already finalized");
   if (p->model < 0) return fail(p, WC4D_ESTATE, "no model set");
+  if (p->strong && p->haveB && !p->haveQ) {
+    // no model error: Q^{1/2} is never applied
+    p->Qsqrt.assign((size_t)p->n * p->n, 0.0);
+    p->haveQ = true;
+  }
   if (!p->haveB || !p->haveQ) return fail(p, WC4D_ESTATE, "B^{1/2} and Q^{1/2} must be set");
-  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32 | WC4D_PREC_SKETCH_FP16X3 | WC4D_PREC_LMP_FP16))
+  if (p->strong && (prec_mode & (WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_SKETCH_FP16X3)))
+    return fail(p, WC4D_EINVAL, "strong-constraint problems take float64 products only");
+  if (prec_mode & ~(WC4D_PREC_SKETCH_BF16X3 | WC4D_PREC_LMP_FP32 | WC4D_PREC_SKETCH_FP16X3 | WC4D_PREC_LMP_FP16 |
+                    WC4D_PREC_DSQRT_OZ7))
     return fail(p, WC4D_EINVAL, "unknown precision flags");
+  if (p->strong && (prec_mode & WC4D_PREC_DSQRT_OZ7))
+    return fail(p, WC4D_EINVAL, "strong-constraint problems take float64 products only");
   if ((prec_mode & WC4D_PREC_LMP_FP32) && (prec_mode & WC4D_PREC_LMP_FP16))
     return fail(p, WC4D_EINVAL, "WC4D_PREC_LMP_FP32 and WC4D_PREC_LMP_FP16 exclude each other");
   if ((prec_mode & WC4D_PREC_SKETCH_BF16X3) && (prec_mode & WC4D_PREC_SKETCH_FP16X3))
@@ -407,6 +431,19 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
       }
     }
   }
+  if (prec_mode & WC4D_PREC_DSQRT_OZ7) {
+    // int8 slices of Q^{1/2} for the one-vector products (all levels in one product)
+    if (!p->scaledB)
+      return fail(p, WC4D_EINVAL, "WC4D_PREC_DSQRT_OZ7 needs B^{1/2} = c Q^{1/2} (one product over all levels)");
+    const int L = N + 1;
+    if ((rc = dev_alloc(p, &p->ozSs, oz_slices_bytes(n))) || (rc = dev_alloc(p, &p->ozEs, (size_t)oz_padded(n))) ||
+        (rc = dev_alloc(p, &p->ozXs, oz_xs_bytes(n, L))) || (rc = dev_alloc(p, &p->ozFs, (size_t)oz_lpad(L))) ||
+        (rc = dev_alloc(p, &p->ozP, oz_partials_doubles(n, L))))
+      return rc;
+    HIPCHK(p, oz_set_lds_limit());
+    HIPCHK(p, oz_split_matrix(p->dQ, n, n, p->ozSs, p->ozEs, s));
+    HIPCHK(p, hipStreamSynchronize(s));
+  }
   // the host copies of the square roots are no longer needed once uploaded
   std::vector<double>().swap(p->Bsqrt);
   std::vector<double>().swap(p->Qsqrt);
@@ -503,6 +540,11 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
                           ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
     return WC4D_OK;
   }
+  if (m == 1 && p->ozSs != nullptr) {
+    // one vector: all levels in one int8-sliced product with Q^{1/2}, level 0 scaled by c
+    HIPCHK(p, oz_gemm(n, N + 1, p->ozSs, p->ozEs, X, n, p->bScale, E, Y, p->ozXs, p->ozFs, p->ozP, skip, s));
+    return WC4D_OK;
+  }
   const DsqrtTune* t = find_tune(p, m);
   if (p->scaledB) {
     // all levels with Q^{1/2} in one product, then level 0 rescaled by c (B^{1/2} = c Q^{1/2})
@@ -548,9 +590,51 @@ int check_block_args(wc4d_problem p, const void* X, int ldx, const void* Y, int 
 
 }  // namespace
 
+namespace {
+
+// Strong-constraint operator (control x_0 only): level 0 of the block = B^{1/2} X, the other
+// levels zero (no forcing); the forward sweep with its observation stash, the adjoint sweep,
+// then Y = X + B^{1/2} w_0.
+int apply_A_sc(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m, const int* skip,
+               hipStream_t s) {
+  const int n = p->n;
+  const long long nL = p->nL;
+  if (p->q == 0) {
+    HIPCHK(p, block_copy(Y, ldy, X, ldx, n, m, s));
+    return WC4D_OK;
+  }
+  const SweepModel md = p->sweep();
+  double* P = p->wsBlock;
+  const double n2 = (double)n * n, blk = 8.0 * (double)nL * m, stash = 8.0 * (double)p->q * m;
+  const double gflops = 2.0 * n2 * m;
+  HIPCHK(p, vec_fill(P, 0.0, nL * m, s));
+  {
+    ProfScope ps(p, s, PROF_DSQRT, 8.0 * n2 + 16.0 * n * m, gflops);
+    HIPCHK(p, gemm_f64_tile(GEMM_AUTO, 0, n, m, n, 1.0, p->dB, n, X, ColMap{ldx, 1, 0, n}, P, ColMap{nL, 1, 0, n},
+                            nullptr, ColMap{nL, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
+  }
+  {
+    ProfScope ps(p, s, PROF_SWEEP_FWD, blk + stash, 0.0);
+    HIPCHK(p, sweep_fwd(md, P, nL, m, p->wsStash, p->q, nullptr, 0, skip, s));
+  }
+  {
+    ProfScope ps(p, s, PROF_SWEEP_BWD, blk + stash, 0.0);
+    HIPCHK(p, sweep_bwd(md, p->wsStash, p->q, nullptr, 0, m, P, nL, skip, s));
+  }
+  {
+    ProfScope ps(p, s, PROF_DSQRT, 8.0 * n2 + 24.0 * n * m, gflops);
+    HIPCHK(p, gemm_f64_tile(GEMM_AUTO, 0, n, m, n, 1.0, p->dB, n, P, ColMap{nL, 1, 0, n}, Y, ColMap{ldy, 1, 0, n},
+                            X, ColMap{ldx, 1, 0, n}, skip, s, p->wsSplit, p->wsSplitDoubles));
+  }
+  return WC4D_OK;
+}
+
+}  // namespace
+
 // Y = A X using the problem's block workspace (must hold m columns).
 int wc4d::apply_A_core(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy,
                        int m, const int* skip, hipStream_t s, int mixed) {
+  if (p->strong) return apply_A_sc(p, X, ldx, Y, ldy, m, skip, s);
   const long long nA = p->nA;
   if (p->q == 0) {
     HIPCHK(p, block_copy(Y, ldy, X, ldx, nA, m, s));
@@ -606,6 +690,8 @@ int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int l
   if (rc) return rc;
   if (prec != WC4D_PREC_FP64 && prec != WC4D_PREC_SKETCH_BF16X3 && prec != WC4D_PREC_SKETCH_FP16X3)
     return fail(p, WC4D_EINVAL, "prec must be WC4D_PREC_FP64, WC4D_PREC_SKETCH_BF16X3 or WC4D_PREC_SKETCH_FP16X3");
+  if (p->strong && prec != WC4D_PREC_FP64)
+    return fail(p, WC4D_EINVAL, "strong-constraint problems take float64 products only");
   if (prec == WC4D_PREC_SKETCH_BF16X3 && p->dBhi == nullptr)
     return fail(p, WC4D_ESTATE, "finalize without WC4D_PREC_SKETCH_BF16X3");
   if (prec == WC4D_PREC_SKETCH_FP16X3 && p->dBh16 == nullptr)
@@ -619,6 +705,7 @@ int wc4d_apply_A_prec(wc4d_problem p, const double* X, int ldx, double* Y, int l
 int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
   int rc = check_block_args(p, X, ldx, Y, ldy, m);
   if (rc) return rc;
+  if (p->strong) return fail(p, WC4D_EINVAL, "apply_Linv: not defined for a strong-constraint problem");
   DevGuard g(p->device);
   HIPCHK(p, sweep_fwd(p->sweep(), X, ldx, m, nullptr, 0, Y, ldy, nullptr, s));
   return WC4D_OK;
@@ -627,6 +714,7 @@ int wc4d_apply_Linv(wc4d_problem p, const double* X, int ldx, double* Y, int ldy
 int wc4d_apply_LinvT(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
   int rc = check_block_args(p, X, ldx, Y, ldy, m);
   if (rc) return rc;
+  if (p->strong) return fail(p, WC4D_EINVAL, "apply_LinvT: not defined for a strong-constraint problem");
   DevGuard g(p->device);
   HIPCHK(p, sweep_bwd(p->sweep(), nullptr, 0, X, ldx, m, Y, ldy, nullptr, s));
   return WC4D_OK;
@@ -635,6 +723,7 @@ int wc4d_apply_LinvT(wc4d_problem p, const double* X, int ldx, double* Y, int ld
 int wc4d_apply_Dsqrt(wc4d_problem p, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
   int rc = check_block_args(p, X, ldx, Y, ldy, m);
   if (rc) return rc;
+  if (p->strong) return fail(p, WC4D_EINVAL, "apply_Dsqrt: not defined for a strong-constraint problem");
   DevGuard g(p->device);
   return dsqrt_apply(p, X, ldx, Y, ldy, m, nullptr, 0, nullptr, s);
 }
@@ -652,7 +741,14 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
     return WC4D_OK;
   }
   HIPCHK(p, stash_from_innov(d, p->dObsRinv, p->wsStash, p->q, s));
-  HIPCHK(p, sweep_bwd(p->sweep(), p->wsStash, p->q, nullptr, 0, 1, p->wsBlock, nA, nullptr, s));
+  HIPCHK(p, sweep_bwd(p->sweep(), p->wsStash, p->q, nullptr, 0, 1, p->wsBlock, p->nL, nullptr, s));
+  if (p->strong) {
+    // B^{1/2} w_0 (+ bt)
+    const int n = p->n;
+    HIPCHK(p, gemm_f64_tile(GEMM_AUTO, 0, n, 1, n, 1.0, p->dB, n, p->wsBlock, ColMap{p->nL, 1, 0, n}, rhs,
+                            ColMap{nA, 1, 0, n}, bt, ColMap{nA, 1, 0, n}, nullptr, s, p->wsSplit, p->wsSplitDoubles));
+    return WC4D_OK;
+  }
   return dsqrt_apply(p, p->wsBlock, nA, rhs, nA, 1, bt, nA, nullptr, s);
 }
 
@@ -662,6 +758,9 @@ int wc4d_rhs(wc4d_problem p, const double* d, const double* bt, double* rhs, hip
 
 // Frees an LMP's device memory (its problem's device must be current).
 void wc4d::lmp_release(wc4d_lmp L) {
+  dev_free(&L->AU);
+  dev_free(&L->ninv);
+  dev_free(&L->rzw);
   dev_free(&L->U);
   dev_free(&L->theta);
   dev_free(&L->dcoef);
@@ -1051,9 +1150,78 @@ int lmp_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long l
   return WC4D_OK;
 }
 
+// Y = P X for the Ritz-LMP of eq. Ritz_LMP, P = (I - U Theta^{-1} U^T A)(I - A U Theta^{-1} U^T)
+// + U Theta^{-1} U^T, with A U kept from wc4d_lmp_ritz_prepare (A symmetric: U^T A y = (AU)^T y).
+// Per vector: t1 = -Theta^{-1} U^T x; y1 = x + (AU) t1; t2 = -Theta^{-1} (AU)^T y1;
+// y = y1 + U (t2 - t1).  Four passes over n_A x k.
+int ritz_apply_core(wc4d_lmp L, const double* X, long long ldx, double* Y, long long ldy, int m, const int* skip,
+                    hipStream_t s) {
+  wc4d_problem p = L->p;
+  LmpU Uu, AUu;
+  Uu.p = L->U;
+  Uu.fmt = LMP_F64;
+  Uu.ldu = L->ldu;
+  AUu.p = L->AU;
+  AUu.fmt = LMP_F64;
+  AUu.ldu = L->ldu;
+  const long long nA = L->nA;
+  const int k = L->k;
+  double* y1 = L->rzw;
+  double* t1 = L->rzw + nA;
+  double* t = L->wsv + lmp_gemv_t_offset(nA, k);
+  const double pb = 8.0 * (double)nA * k, fl = 2.0 * (double)nA * k;
+  for (int c = 0; c < m; ++c) {
+    const double* x = X + (size_t)c * ldx;
+    double* y = Y + (size_t)c * ldy;
+    ProfScope ps(p, s, PROF_LMP_T, 4.0 * pb + 5.0 * 8.0 * nA, 4.0 * fl);
+    HIPCHK(p, lmp_gemv_t(nA, k, Uu, L->ninv, x, L->wsv, skip, s));
+    HIPCHK(p, vec_copy_skip(t1, t, k, skip, s));
+    HIPCHK(p, lmp_gemv_n(nA, k, AUu, x, y1, L->wsv, skip, s));
+    HIPCHK(p, lmp_gemv_t(nA, k, AUu, L->ninv, y1, L->wsv, skip, s));
+    HIPCHK(p, vec_sub_small(t, t1, k, skip, s));
+    HIPCHK(p, lmp_gemv_n(nA, k, Uu, y1, y, L->wsv, skip, s));
+  }
+  return WC4D_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int wc4d_lmp_ritz_prepare(wc4d_lmp L, hipStream_t s) {
+  if (L == nullptr) return WC4D_EINVAL;
+  wc4d_problem p = L->p;
+  if (p == nullptr) return WC4D_ESTATE;
+  if (!is_state_ok(p)) return fail(p, WC4D_ESTATE, "not finalized");
+  DevGuard g(p->device);
+  int rc;
+  if (L->AU == nullptr) {
+    if ((rc = dev_alloc(p, &L->AU, (size_t)L->ldu * L->k))) return rc;
+    if ((rc = dev_alloc(p, &L->ninv, L->k))) return rc;
+    if ((rc = dev_alloc(p, &L->rzw, (size_t)L->nA + L->k))) return rc;
+  }
+  const size_t need = lmp_gemv_ws_doubles(L->nA, L->k);
+  if (L->wsvDoubles < need) {
+    if ((rc = dev_alloc(p, &L->wsv, need))) return rc;
+    L->wsvDoubles = need;
+  }
+  if ((rc = ensure_block(p, L->k))) return rc;
+  // one block product with A (the k Ritz vectors), in float64 whatever the problem's mode
+  if ((rc = apply_A_core(p, L->U, L->ldu, L->AU, L->ldu, L->k, nullptr, s))) return rc;
+  HIPCHK(p, vec_neg_inv(L->theta, L->ninv, L->k, s));
+  HIPCHK(p, hipStreamSynchronize(s));
+  return WC4D_OK;
+}
+
+int wc4d_lmp_ritz_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
+  if (L == nullptr) return WC4D_EINVAL;
+  if (L->p == nullptr) return WC4D_ESTATE;
+  if (L->AU == nullptr) return fail(L->p, WC4D_ESTATE, "lmp_ritz_apply: call wc4d_lmp_ritz_prepare first");
+  int rc = check_block_args(L->p, X, ldx, Y, ldy, m);
+  if (rc) return rc;
+  DevGuard g(L->p->device);
+  return ritz_apply_core(L, X, ldx, Y, ldy, m, nullptr, s);
+}
 
 int wc4d_lmp_apply(wc4d_lmp L, const double* X, int ldx, double* Y, int ldy, int m, hipStream_t s) {
   if (L == nullptr) return WC4D_EINVAL;
@@ -1082,10 +1250,11 @@ namespace {
 
 // Algorithm 1 on the device.  With F != null (no LMP only) the normalised residuals
 // f_j = (-1)^j r_j / ||r_j|| go into the columns of F and the CG coefficients into
-// alphas / betas (host): the Lanczos information of Section 3.4.
+// alphas / betas (host): the Lanczos information of Section 3.4.  With reorth each new
+// residual is orthogonalised twice against f_0..f_{j-1} before r_j^T r_j and beta_j.
 int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
             wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J, double* alphas,
-            double* betas, double* F, long long ldf, hipStream_t s) {
+            double* betas, double* F, long long ldf, bool reorth, hipStream_t s, bool ritz = false) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   if (b == nullptr || x == nullptr || opts == nullptr || info == nullptr || opts->maxit < 1 ||
       !(opts->tol >= 0.0) || (opts->criterion != WC4D_RES_TRUE && opts->criterion != WC4D_RES_PRECOND))
@@ -1093,11 +1262,26 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
   if (L != nullptr && L->p != p) return fail(p, WC4D_EINVAL, "LMP built for another problem (or orphaned)");
   if (opts->variant != WC4D_PCG_FUSED && opts->variant != WC4D_PCG_PLAIN)
     return fail(p, WC4D_EINVAL, "unknown PCG variant");
-  const bool fused = (L != nullptr && opts->variant == WC4D_PCG_FUSED);
+  const bool fused = (L != nullptr && opts->variant == WC4D_PCG_FUSED && !ritz);
+  if (ritz && (L == nullptr || L->AU == nullptr))
+    return fail(p, WC4D_ESTATE, "pcg_ritz: the LMP needs wc4d_lmp_ritz_prepare first");
+  if (reorth && (F == nullptr || L != nullptr || opts->maxit > 512))
+    return fail(p, WC4D_EINVAL, "reorthogonalised CG: no LMP, Lanczos vectors kept, maxit <= 512");
   DevGuard g(p->device);
   const long long nA = p->nA;
   int rc;
   if ((rc = ensure_block(p, 1))) return rc;
+  // reorthogonalisation scratch: the partial sums of F^T r for up to maxit columns and t
+  double* rws = nullptr;
+  struct FreeOnExit {
+    double** q;
+    ~FreeOnExit() { dev_free(q); }
+  } rws_guard{&rws};
+  size_t rws_t = 0;
+  if (reorth) {
+    for (int j = 1; j <= opts->maxit; ++j) rws_t = std::max(rws_t, lmp_gemv_ws_doubles(nA, j));
+    if ((rc = dev_alloc(p, &rws, rws_t + (size_t)opts->maxit))) return rc;
+  }
   if (p->pcgVec == nullptr) {
     if ((rc = dev_alloc(p, &p->pcgVec, (size_t)6 * nA))) return rc;
     if ((rc = dev_alloc(p, &p->pcgRed, pcg_red_doubles()))) return rc;
@@ -1125,14 +1309,19 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
   HIPCHK(p, pcg_x0_zero_flag(x, nA, p->pcgRed, xzero, s));
   if ((rc = apply_A_core(p, x, nA, Ap, nA, 1, xzero, s))) return rc;
   HIPCHK(p, pcg_s0(b, Ap, xzero, sres, nA, s));
-  if (L != nullptr) {
+  if (ritz) {
+    // standard preconditioned CG: z_0 = P s_0, p_0 = z_0 (r is the true residual s)
+    if ((rc = ritz_apply_core(L, sres, nA, z, nA, 1, nullptr, s))) return rc;
+    HIPCHK(p, vec_copy(pv, z, nA, s));
+    HIPCHK(p, pcg_kernels_init_std(st, b, sres, z, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
+  } else if (L != nullptr) {
     if ((rc = lmp_apply_core(L, sres, nA, r, nA, 1, nullptr, s))) return rc;
     if ((rc = lmp_apply_core(L, r, nA, pv, nA, 1, nullptr, s))) return rc;
   } else {
     HIPCHK(p, vec_copy(r, sres, nA, s));
     HIPCHK(p, vec_copy(pv, r, nA, s));
   }
-  HIPCHK(p, pcg_kernels_init(st, b, sres, r, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
+  if (!ritz) HIPCHK(p, pcg_kernels_init(st, b, sres, r, nA, opts->tol, opts->maxit, opts->criterion, p->pcgRed, s));
   if (F != nullptr) HIPCHK(p, pcg_lanczos_col(st, 0, r, F, ldf, nA, s));
   double* u = nullptr;
   double* d12 = nullptr;
@@ -1196,12 +1385,36 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
       if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
       HIPCHK(p, pcg_dot_alpha(st, pv, Ap, nA, p->pcgRed, s));
       HIPCHK(p, pcg_update_xs(st, x, sres, b, pv, Ap, nA, p->pcgRed, s));
+      if (ritz) {
+        // z = P s; beta from s^T z; p = z + beta p
+        if ((rc = ritz_apply_core(L, sres, nA, z, nA, 1, done, s))) return rc;
+        HIPCHK(p, pcg_dot_rz(st, sres, z, nA, p->pcgRed, s));
+        HIPCHK(p, pcg_beta_final(st, p->pcgRed, p->pcgHist, s));
+        HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
+        continue;
+      }
       const double* wv = Ap;
       if (L != nullptr) {
         if ((rc = lmp_apply_core(L, Ap, nA, w, nA, 1, done, s))) return rc;
         wv = w;
       }
-      HIPCHK(p, pcg_update_r(st, r, wv, nA, p->pcgRed, p->pcgHist, s));
+      if (reorth) {
+        // r_j -= F_j (F_j^T r_j), twice (classical Gram-Schmidt), over f_0..f_{j-1}
+        const int j = it + c + 1;
+        LmpU Fu;
+        Fu.p = F;
+        Fu.fmt = LMP_F64;
+        Fu.ldu = ldf;
+        double* tj = rws + rws_t;
+        HIPCHK(p, pcg_update_r_only(st, r, wv, nA, p->pcgRed, s));
+        HIPCHK(p, lmp_gemv_t(nA, j, Fu, nullptr, r, rws, done, s, tj));
+        HIPCHK(p, pcg_reorth_sub(st, j, F, ldf, tj, r, z, nA, nullptr, s));
+        HIPCHK(p, lmp_gemv_t(nA, j, Fu, nullptr, z, rws, done, s, tj));
+        HIPCHK(p, pcg_reorth_sub(st, j, F, ldf, tj, z, r, nA, p->pcgRed, s));
+        HIPCHK(p, pcg_beta_final(st, p->pcgRed, p->pcgHist, s));
+      } else {
+        HIPCHK(p, pcg_update_r(st, r, wv, nA, p->pcgRed, p->pcgHist, s));
+      }
       if (F != nullptr) HIPCHK(p, pcg_lanczos_col(st, it + c + 1, r, F, ldf, nA, s));
       const double* zv = r;
       if (L != nullptr) {
@@ -1255,15 +1468,24 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
 int wc4d_pcg(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
              wc4d_pcg_info* info, double* hist_true, double* hist_precond, double* hist_J,
              hipStream_t s) {
-  return pcg_run(p, L, b, x, opts, info, hist_true, hist_precond, hist_J, nullptr, nullptr, nullptr, 0, s);
+  return pcg_run(p, L, b, x, opts, info, hist_true, hist_precond, hist_J, nullptr, nullptr, nullptr, 0, false,
+                 s);
+}
+
+int wc4d_pcg_ritz(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_pcg_opts* opts,
+                  wc4d_pcg_info* info, double* hist_true, double* hist_J, hipStream_t s) {
+  if (L == nullptr) return p ? fail(p, WC4D_EINVAL, "pcg_ritz: an LMP is required") : WC4D_EINVAL;
+  return pcg_run(p, L, b, x, opts, info, hist_true, nullptr, hist_J, nullptr, nullptr, nullptr, 0, false, s, true);
 }
 
 int wc4d_pcg_lanczos(wc4d_problem p, const double* b, double* x, const wc4d_pcg_opts* opts, wc4d_pcg_info* info,
-                     double* alphas, double* betas, double* F, long long ldf, hipStream_t s) {
+                     double* alphas, double* betas, double* F, long long ldf, int flags, hipStream_t s) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
   if (alphas == nullptr || betas == nullptr || F == nullptr || ldf < p->nA)
     return fail(p, WC4D_EINVAL, "pcg_lanczos: alphas, betas, F (ldf >= n_A) required");
-  return pcg_run(p, nullptr, b, x, opts, info, nullptr, nullptr, nullptr, alphas, betas, F, ldf, s);
+  if ((flags & ~WC4D_LANCZOS_REORTH) != 0) return fail(p, WC4D_EINVAL, "pcg_lanczos: unknown flags");
+  return pcg_run(p, nullptr, b, x, opts, info, nullptr, nullptr, nullptr, alphas, betas, F, ldf,
+                 (flags & WC4D_LANCZOS_REORTH) != 0, s);
 }
 
 }  // extern "C"

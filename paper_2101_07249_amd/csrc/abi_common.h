@@ -63,7 +63,7 @@ inline void dev_free(T** ptr) {
 
 inline int ensure_block(wc4d_problem p, long long m) {
   if (p->wsBlockCols >= m && p->wsStashCols >= m) return WC4D_OK;
-  int rc = dev_alloc(p, &p->wsBlock, (size_t)p->nA * m);
+  int rc = dev_alloc(p, &p->wsBlock, (size_t)p->nL * m);
   if (rc) return rc;
   p->wsBlockCols = m;
   rc = dev_alloc(p, &p->wsStash, (size_t)std::max(p->q, 1) * m);

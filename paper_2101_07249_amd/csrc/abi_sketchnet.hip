@@ -384,6 +384,7 @@ int wc4d_sketchnet_infer(wc4d_sketchnet net, wc4d_problem p, const double* Omega
                          hipStream_t s) {
   if (net == nullptr) return WC4D_EINVAL;
   if (!is_state_ok(p)) return nfail(net, WC4D_ESTATE, "problem not finalized");
+  if (p->strong) return nfail(net, WC4D_EINVAL, "the sketch network serves weak-constraint problems");
   if (p->device != net->device) return nfail(net, WC4D_EINVAL, "network and problem on different devices");
   if ((net->nz > 0 && (Omega == nullptr || ldo < p->nA)) || G == nullptr || ldg < p->nA)
     return nfail(net, WC4D_EINVAL, "invalid Omega / G (null or leading dimension < n_A)");
@@ -409,6 +410,7 @@ int wc4d_sketchnet_adam(wc4d_sketchnet net, double lr, hipStream_t s) {
 int wc4d_sketch_loss(wc4d_problem p, const double* G, int ldg, int m, const double* U, int ldu,
                      const double* theta, int k, double* f, double* dG, int lddg, hipStream_t s) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (p->strong) return fail(p, WC4D_EINVAL, "the sketch network serves weak-constraint problems");
   if (G == nullptr || U == nullptr || theta == nullptr || f == nullptr || dG == nullptr || m < 1 || m > 512 ||
       k < 1 || k > 512 || ldg < p->nA || ldu < p->nA || lddg < p->nA || m > p->nA)
     return fail(p, WC4D_EINVAL, "invalid capture-loss arguments");
@@ -422,6 +424,7 @@ int wc4d_sketchnet_train_step(wc4d_sketchnet net, wc4d_problem p, const double* 
                               int k, double lr, double* loss, hipStream_t s) {
   if (net == nullptr) return WC4D_EINVAL;
   if (!is_state_ok(p)) return nfail(net, WC4D_ESTATE, "problem not finalized");
+  if (p->strong) return nfail(net, WC4D_EINVAL, "the sketch network serves weak-constraint problems");
   if (ref == nullptr || ref->p != p || k < 1 || k > ref->k)
     return nfail(net, WC4D_EINVAL, "reference LMP must belong to p and hold at least k pairs");
   if (net->nz > 0 && (Omega == nullptr || ldo < p->nA)) return nfail(net, WC4D_EINVAL, "invalid Omega");
@@ -449,6 +452,7 @@ int wc4d_lmp_build_sketch(wc4d_problem p, wc4d_sketchnet net, int method, int k_
   if (out == nullptr) return WC4D_EINVAL;
   *out = nullptr;
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (p->strong) return fail(p, WC4D_EINVAL, "the sketch network serves weak-constraint problems");
   if (Omega == nullptr) return fail(p, WC4D_EINVAL, "null Gaussian block");
   if (net == nullptr) return wc4d_lmp_build(p, method, k_r, l, Omega, 0, out, s);
   if (k_r + l != kNetCH || net->nz != kNetCH)

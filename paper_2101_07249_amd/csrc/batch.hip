@@ -83,6 +83,7 @@ extern "C" {
 
 int wc4d_autotune(wc4d_problem p, int m, hipStream_t s) {
   if (!is_state_ok(p)) return p ? fail(p, WC4D_ESTATE, "not finalized") : WC4D_EINVAL;
+  if (p->strong) return fail(p, WC4D_EINVAL, "autotune: the tile table covers weak-constraint D^{1/2} products");
   if (m < 1 || m > 512) return fail(p, WC4D_EINVAL, "block width must be in [1, 512]");
   DevGuard g(p->device);
   const int n = p->n, N = p->N;

@@ -48,7 +48,7 @@ constexpr int kBT = 256;          // threads per workgroup
 constexpr int kRows = 4096;       // rows per row item
 constexpr int kTM = 64;           // rows of S per product tile
 constexpr int kTN = 64;           // time levels per product tile
-constexpr int kTK = 16;           // K step of a product tile
+constexpr int kTK = 32;           // K step of a product tile
 constexpr int kMaxK = 64;         // largest k_r the row phases hold in LDS
 constexpr int kMaxPts = 32;       // sweep points per thread (n <= 8192)
 constexpr unsigned kRing = 1u << 16;  // queue entries (power of two)
@@ -136,6 +136,28 @@ __device__ inline unsigned long long now_ticks() { return __builtin_amdgcn_s_mem
 __device__ inline void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 __device__ inline void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 
+// Loads and stores through global-address-space pointers.  The item functions are not
+// inlined into the kernel (each keeps its own register allocation) and their pointers come
+// from the descriptors in memory, so plain pointers would compile to flat accesses, which
+// also count against the LDS wait counter and stall every LDS read behind global loads.
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) double gdouble;
+typedef const __attribute__((address_space(1))) dv2 gdv2;
+typedef const __attribute__((address_space(1))) int gint;
+__device__ inline double gld(const double* p) { return *(gdouble*)p; }
+__device__ inline dv2 gld2(const double* p) { return *(gdv2*)p; }
+__device__ inline int gldi(const int* p) { return *(gint*)p; }
+__device__ inline void gst(double* p, double v) { *(__attribute__((address_space(1))) double*)p = v; }
+// LDS through local-address-space pointers (the item functions receive LDS as plain pointers)
+template <class T>
+__device__ inline T sld(const T* p) {
+  return *(const __attribute__((address_space(3))) T*)p;
+}
+template <class T>
+__device__ inline void sst(T* p, T v) {
+  *(__attribute__((address_space(3))) T*)p = v;
+}
+
 // back off between polls: 8, 16, ..., 128 sleeps of 8 x 64 cycles
 __device__ inline void backoff(int& b) {
   for (int z = 0; z < b; ++z) __builtin_amdgcn_s_sleep(8);
@@ -180,8 +202,8 @@ __device__ inline void block_sums(const double (&v)[Q], double* red, double (&ou
 // Y(:, lev) = alpha_lev S X(:, lev) [+ E(:, lev)] for the 64 rows [64 rt, 64 rt + 64) and
 // the levels [l0, l0 + nl) of one product tile; S is n x n column-major.  float64 MFMA on
 // the transposed product (as in gemm_f64.hip): lanes sharing l/16 hold 16 consecutive rows
-// of one output column.  lds: 2 x 16 x 68 doubles.
-__device__ void product_tile(const double* __restrict__ S, int n, int rt, int l0, int nl, double scale0,
+// of one output column.  lds: 2 x kTK x 68 doubles.
+__device__ __noinline__ void product_tile(const double* __restrict__ S, int n, int rt, int l0, int nl, double scale0,
                              const double* __restrict__ X, const double* __restrict__ E, double* __restrict__ Y,
                              double* lds) {
   constexpr int PA = kTM + 4, PB = kTN + 4;
@@ -195,25 +217,27 @@ __device__ void product_tile(const double* __restrict__ S, int n, int rt, int l0
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  double ra[4], rb[4];
+  constexpr int kLd = kTK * kTM / kBT;  // elements of each operand per thread and K step
+  static_assert(kTM == 64 && kTN == 64 && kLd * kBT == kTK * kTM, "product tile shape");
+  double ra[kLd], rb[kLd];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kLd; ++e) {
       const int idx = tid + kBT * e;
       const int gi = i0 + (idx & 63), gk = k0 + (idx >> 6);
-      ra[e] = (gi < n && gk < n) ? S[(long long)gi + (long long)gk * n] : 0.0;
-      const int j = idx >> 4, kk = k0 + (idx & 15);
-      rb[e] = (j < nl && kk < n) ? X[(long long)(l0 + j) * n + kk] : 0.0;
+      ra[e] = (gi < n && gk < n) ? gld(S + (long long)gi + (long long)gk * n) : 0.0;
+      const int j = idx / kTK, kk = k0 + idx % kTK;
+      rb[e] = (j < nl && kk < n) ? gld(X + (long long)(l0 + j) * n + kk) : 0.0;
     }
   };
   gload(0);
   for (int k0 = 0; k0 < n; k0 += kTK) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < kLd; ++e) {
       const int idx = tid + kBT * e;
-      As[(idx >> 6) * PA + (idx & 63)] = ra[e];
-      Bs[(idx & 15) * PB + (idx >> 4)] = rb[e];
+      sst(As + (idx >> 6) * PA + (idx & 63), ra[e]);
+      sst(Bs + (idx % kTK) * PB + idx / kTK, rb[e]);
     }
     __syncthreads();
     if (k0 + kTK < n) gload(k0 + kTK);
@@ -222,9 +246,9 @@ __device__ void product_tile(const double* __restrict__ S, int n, int rt, int l0
       const int kr = kk + (lane >> 4);
       double av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Bs[kr * PB + wj0 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 2; ++a) av[a] = sld(Bs + kr * PB + wj0 + a * 16 + (lane & 15));
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = As[kr * PA + wi0 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bv[b] = sld(As + kr * PA + wi0 + b * 16 + (lane & 15));
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -245,8 +269,8 @@ __device__ void product_tile(const double* __restrict__ S, int n, int rt, int l0
         if (i < n) {
           const long long o = (long long)lev * n + i;
           double v = sc * acc[a][b][rr];
-          if (E != nullptr) v += E[o];
-          Y[o] = v;
+          if (E != nullptr) v += gld(E + o);
+          gst(Y + o, v);
         }
       }
     }
@@ -273,7 +297,7 @@ __device__ void dsqrt_item(const BpDesc& d, int item, const double* X, const dou
 // reads), neighbours come through LDS.  T: float64, or float32 for the reduced-precision
 // sweep option (state and stencil in float32; inputs and outputs float64).
 template <class T>
-__device__ void sweep_fwd_item(const BpDesc& d, T* xs) {
+__device__ __noinline__ void sweep_fwd_item(const BpDesc& d, T* xs) {
   const int n = d.n, N = d.N, t = threadIdx.x;
   const int E = (n + kBT - 1) / kBT;
   const T ca = (T)d.ca, cb = (T)d.cb, cc = (T)d.cc;
@@ -281,7 +305,7 @@ __device__ void sweep_fwd_item(const BpDesc& d, T* xs) {
 #pragma unroll
   for (int e = 0; e < kMaxPts; ++e) {
     const int j = t + kBT * e;
-    xr[e] = (e < E && j < n) ? (T)d.W[j] : (T)0;
+    xr[e] = (e < E && j < n) ? (T)gld(d.W + j) : (T)0;
   }
   for (int i = 0;; ++i) {
     // observations of level i: stash = R^{-1} H x_i
@@ -289,15 +313,15 @@ __device__ void sweep_fwd_item(const BpDesc& d, T* xs) {
     for (int e = 0; e < kMaxPts; ++e) {
       const int j = t + kBT * e;
       if (e < E && j < n) {
-        const int k = d.slot[(long long)i * n + j];
-        if (k >= 0) d.stash[k] = d.rinv[k] * (double)xr[e];
+        const int k = gldi(d.slot + (long long)i * n + j);
+        if (k >= 0) gst(d.stash + k, gld(d.rinv + k) * (double)xr[e]);
       }
     }
     if (i == N) break;
 #pragma unroll
     for (int e = 0; e < kMaxPts; ++e) {
       const int j = t + kBT * e;
-      if (e < E && j < n) xs[j] = xr[e];
+      if (e < E && j < n) sst(xs + j, xr[e]);
     }
     __syncthreads();
     const double* Wn = d.W + (long long)(i + 1) * n;
@@ -306,7 +330,7 @@ __device__ void sweep_fwd_item(const BpDesc& d, T* xs) {
       const int j = t + kBT * e;
       if (e < E && j < n) {
         const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
-        xr[e] = ca * xs[jm] + cb * xr[e] + cc * xs[jp] + (T)Wn[j];
+        xr[e] = ca * sld(xs + jm) + cb * xr[e] + cc * sld(xs + jp) + (T)gld(Wn + j);
       }
     }
     __syncthreads();
@@ -314,7 +338,7 @@ __device__ void sweep_fwd_item(const BpDesc& d, T* xs) {
 }
 
 template <class T>
-__device__ void sweep_bwd_item(const BpDesc& d, T* xs) {
+__device__ __noinline__ void sweep_bwd_item(const BpDesc& d, T* xs) {
   const int n = d.n, N = d.N, t = threadIdx.x;
   const int E = (n + kBT - 1) / kBT;
   const T ca = (T)d.ca, cb = (T)d.cb, cc = (T)d.cc;
@@ -325,9 +349,9 @@ __device__ void sweep_bwd_item(const BpDesc& d, T* xs) {
     const int j = t + kBT * e;
     T v = (T)0;
     if (e < E && j < n) {
-      const int k = d.slot[(long long)N * n + j];
-      if (k >= 0) v = (T)d.stash[k];
-      d.W[(long long)N * n + j] = (double)v;
+      const int k = gldi(d.slot + (long long)N * n + j);
+      if (k >= 0) v = (T)gld(d.stash + k);
+      gst(d.W + (long long)N * n + j, (double)v);
     }
     wr[e] = v;
   }
@@ -335,7 +359,7 @@ __device__ void sweep_bwd_item(const BpDesc& d, T* xs) {
 #pragma unroll
     for (int e = 0; e < kMaxPts; ++e) {
       const int j = t + kBT * e;
-      if (e < E && j < n) xs[j] = wr[e];
+      if (e < E && j < n) sst(xs + j, wr[e]);
     }
     __syncthreads();
     const long long lo = (long long)i * n;
@@ -344,10 +368,10 @@ __device__ void sweep_bwd_item(const BpDesc& d, T* xs) {
       const int j = t + kBT * e;
       if (e < E && j < n) {
         const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
-        const int k = d.slot[lo + j];
-        const T z = k >= 0 ? (T)d.stash[k] : (T)0;
-        wr[e] = z + ca * xs[jp] + cb * wr[e] + cc * xs[jm];
-        d.W[lo + j] = (double)wr[e];
+        const int k = gldi(d.slot + lo + j);
+        const T z = k >= 0 ? (T)gld(d.stash + k) : (T)0;
+        wr[e] = z + ca * sld(xs + jp) + cb * wr[e] + cc * sld(xs + jm);
+        gst(d.W + lo + j, (double)wr[e]);
       }
     }
     __syncthreads();
@@ -355,43 +379,131 @@ __device__ void sweep_bwd_item(const BpDesc& d, T* xs) {
 }
 
 // ---------------------------------------------------------------- row phases
+// The row phases stream U (n_A x k, ldu % 4 == 0, 16-byte aligned): each thread takes 4
+// consecutive rows per step and loads them as two 16-byte pieces per column, 8 columns at a
+// time, so that a workgroup keeps 16 KB of U loads in flight instead of one row per thread.
+
+
+// rows [i, i + 4) of column q of U; FULL: all four exist, else zeros past r1
+template <bool FULL>
+__device__ inline void u_load4(const BpDesc& d, long long i, int q, long long r1, double (&u)[4]) {
+  const double* up = d.U + i + (long long)q * d.ldu;
+  if (FULL) {
+    const dv2 a = gld2(up);
+    const dv2 b = gld2(up + 2);
+    u[0] = a.x;
+    u[1] = a.y;
+    u[2] = b.x;
+    u[3] = b.y;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) u[e] = (i + e < r1) ? gld(up + e) : 0.0;
+  }
+}
+
+template <bool FULL>
+__device__ inline void v_load4(const double* v, long long i, long long r1, double (&o)[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o[e] = (FULL || i + e < r1) ? gld(v + i + e) : 0.0;
+}
+
+// one quad of rows of U^T a and U^T b over the 8 columns [c0, c0 + 8) (columns past k read
+// as zero)
+template <bool FULL>
+__device__ inline void ut_quad(const BpDesc& d, long long i, long long r1, int c0, const double* a,
+                               const double* bvec, double (&ta)[8], double (&tb)[8]) {
+  double av[4], bv[4] = {0.0, 0.0, 0.0, 0.0};
+  v_load4<FULL>(a, i, r1, av);
+  if (bvec) v_load4<FULL>(bvec, i, r1, bv);
+  double u[8][4];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (c0 + q < d.k) {
+      u_load4<FULL>(d, i, c0 + q, r1, u[q]);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) u[q][e] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ta[q] += u[q][e] * av[e];
+      tb[q] += u[q][e] * bv[e];
+    }
+  }
+}
+
 // Partials of U^T a (columns 0..k), U^T b (k..2k, when b != null) and dot(a2, b2) over the
-// rows of item `c`: written to part[c * kPartStride + ...].
-__device__ void ut_rows(const BpDesc& d, int c, const double* a, const double* bvec, const double* da,
-                        const double* db, double* red) {
+// rows of item `c`: written to part[c * kPartStride + ...].  Whole quads of rows in the
+// loop; the one thread whose quad crosses r1 takes it after the loop.
+__device__ __noinline__ void ut_rows(const BpDesc& d, int c, const double* a, const double* bvec, const double* da,
+                                     const double* db, double* red) {
   const long long r0 = (long long)c * kRows, r1 = min(d.nA, r0 + kRows);
   double* out = d.part + (long long)c * kPartStride;
+#pragma unroll 1
   for (int c0 = 0; c0 < d.k; c0 += 8) {
     double ta[8], tb[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) ta[q] = tb[q] = 0.0;
-    for (long long i = r0 + threadIdx.x; i < r1; i += kBT) {
-      const double av = a[i];
-      const double bv = bvec ? bvec[i] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        if (c0 + q < d.k) {
-          const double u = d.U[i + (long long)(c0 + q) * d.ldu];
-          ta[q] += u * av;
-          tb[q] += u * bv;
-        }
-      }
-    }
+    long long i = r0 + 4LL * threadIdx.x;
+#pragma unroll 1
+    for (; i + 4 <= r1; i += 4LL * kBT) ut_quad<true>(d, i, r1, c0, a, bvec, ta, tb);
+    if (i < r1) ut_quad<false>(d, i, r1, c0, a, bvec, ta, tb);
     double sa[8], sb[8];
     block_sums<8>(ta, red, sa);
     if (bvec) block_sums<8>(tb, red, sb);
     if (threadIdx.x == 0) {
-      for (int q = 0; q < 8 && c0 + q < d.k; ++q) {
-        out[c0 + q] = sa[q];
-        if (bvec) out[d.k + c0 + q] = sb[q];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (c0 + q < d.k) {
+          out[c0 + q] = sa[q];
+          if (bvec) out[d.k + c0 + q] = sb[q];
+        }
       }
     }
   }
   if (da != nullptr) {
     double v[1] = {0.0}, sv[1];
-    for (long long i = r0 + threadIdx.x; i < r1; i += kBT) v[0] += da[i] * db[i];
+    for (long long i = r0 + threadIdx.x; i < r1; i += kBT) v[0] += gld(da + i) * gld(db + i);
     block_sums<1>(v, red, sv);
     if (threadIdx.x == 0) out[2 * d.k] = sv[0];
+  }
+}
+
+// the U coefficient sums of the UP phase for one quad of rows: u1 = U coef[0..k),
+// u2 = U coef[k..2k)
+template <bool FULL>
+__device__ inline void up_quad(const BpDesc& d, long long i, long long r1, const double* coef, double (&u1)[4],
+                               double (&u2)[4]) {
+  const int k = d.k;
+  int q = 0;
+#pragma unroll 1
+  for (; q + 8 <= k; q += 8) {
+    double u[8][4];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) u_load4<FULL>(d, i, q + j, r1, u[j]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double c1 = sld(coef + q + j), c2 = sld(coef + k + q + j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        u1[e] += u[j][e] * c1;
+        u2[e] += u[j][e] * c2;
+      }
+    }
+  }
+#pragma unroll 1
+  for (; q < k; ++q) {
+    double u[4];
+    u_load4<FULL>(d, i, q, r1, u);
+    const double c1 = sld(coef + q), c2 = sld(coef + k + q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      u1[e] += u[e] * c1;
+      u2[e] += u[e] * c2;
+    }
   }
 }
 
@@ -402,7 +514,7 @@ __device__ inline double u_row(const BpDesc& d, long long i, const double* coef)
   return v;
 }
 
-__device__ void row_item(const BpDesc& d, BpState& st, int phase, int c, double* lds) {
+__device__ __noinline__ void row_item(const BpDesc& d, BpState& st, int phase, int c, double* lds) {
   double* red = lds;        // 32 doubles
   double* coef = lds + 32;  // 2 k doubles
   const long long r0 = (long long)c * kRows, r1 = min(d.nA, r0 + kRows);
@@ -454,24 +566,30 @@ __device__ void row_item(const BpDesc& d, BpState& st, int phase, int c, double*
     __syncthreads();
     const double al = st.alpha;
     double rr = 0.0, ss = 0.0, xbs = 0.0;
-    for (long long i = r0 + threadIdx.x; i < r1; i += kBT) {
-      double u1 = 0.0, u2 = 0.0;
-      for (int q = 0; q < d.k; ++q) {
-        const double u = d.U[i + (long long)q * d.ldu];
-        u1 += u * coef[q];
-        u2 += u * coef[d.k + q];
+#pragma unroll 1
+    for (long long i = r0 + 4LL * threadIdx.x; i < r1; i += 4LL * kBT) {
+      double u1[4] = {0.0, 0.0, 0.0, 0.0}, u2[4] = {0.0, 0.0, 0.0, 0.0};
+      if (i + 4 <= r1) {
+        up_quad<true>(d, i, r1, coef, u1, u2);
+      } else {
+        up_quad<false>(d, i, r1, coef, u1, u2);
       }
-      const double a = d.Ap[i];
-      const double rn = d.r[i] - al * (a + u1);
-      d.r[i] = rn;
-      d.z[i] = rn + u2;
-      const double xi = d.x[i] + al * d.p[i];
-      const double si = d.s[i] - al * a;
-      d.x[i] = xi;
-      d.s[i] = si;
-      rr += rn * rn;
-      ss += si * si;
-      xbs += xi * (d.b[i] + si);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const long long ie = i + e;
+        if (ie >= r1) continue;
+        const double a = gld(d.Ap + ie);
+        const double rn = gld(d.r + ie) - al * (a + u1[e]);
+        gst(d.r + ie, rn);
+        gst(d.z + ie, rn + u2[e]);
+        const double xi = gld(d.x + ie) + al * gld(d.p + ie);
+        const double si = gld(d.s + ie) - al * a;
+        gst(d.x + ie, xi);
+        gst(d.s + ie, si);
+        rr += rn * rn;
+        ss += si * si;
+        xbs += xi * (gld(d.b + ie) + si);
+      }
     }
     const double v[3] = {rr, ss, xbs};
     double sv[3];
@@ -486,7 +604,16 @@ __device__ void row_item(const BpDesc& d, BpState& st, int phase, int c, double*
   }
   if (phase == PH_P) {
     const double be = st.beta;
-    for (long long i = r0 + threadIdx.x; i < r1; i += kBT) d.p[i] = d.z[i] + be * d.p[i];
+    long long i = r0 + 4LL * threadIdx.x;
+#pragma unroll 1
+    for (; i + 4 <= r1; i += 4LL * kBT) {
+      double z4[4], p4[4];
+      v_load4<true>(d.z, i, r1, z4);
+      v_load4<true>(d.p, i, r1, p4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) gst(d.p + i + e, z4[e] + be * p4[e]);
+    }
+    for (; i < r1; ++i) gst(d.p + i, gld(d.z + i) + be * gld(d.p + i));
     return;
   }
 }
@@ -504,7 +631,7 @@ __device__ int phase_items(const BpDesc& d, int phase) {
 
 // Enqueue the items of `phase` of problem p (whole workgroup).  Returns false on a wait
 // that ran out of time (the error flag is then set).
-__device__ bool enqueue(const BpArgs& A, int p, int phase, int iter, int* sh) {
+__device__ __noinline__ bool enqueue(const BpArgs& A, int p, int phase, int iter, int* sh) {
   const BpDesc& d = A.D[p];
   const int cnt = phase_items(d, phase);
   if (threadIdx.x == 0) {
@@ -565,7 +692,7 @@ __device__ bool converged(const BpDesc& d, const BpState& st) {
 }
 
 // The work after the last item of a phase (whole workgroup; one problem).
-__device__ bool transition(const BpArgs& A, int p, int phase, int iter, double* lds, int* sh) {
+__device__ __noinline__ bool transition(const BpArgs& A, int p, int phase, int iter, double* lds, int* sh) {
   const BpDesc& d = A.D[p];
   BpState& st = A.S[p];
   const int k = d.k;
@@ -787,6 +914,7 @@ extern "C" int wc4d_batch_solve_persistent(wc4d_problem* ps, int count, int meth
   for (int i = 0; i < count; ++i) {
     wc4d_problem p = ps[i];
     if (!is_state_ok(p) || b[i] == nullptr || x[i] == nullptr) return WC4D_EINVAL;
+    if (p->strong) return fail(p, WC4D_EINVAL, "persistent batch: weak-constraint problems only");
     if (device < 0) device = p->device;
     if (p->device != device) return fail(p, WC4D_EINVAL, "batch problems must share one device");
     if (p->model != 0 || p->n > 8192)
@@ -980,6 +1108,11 @@ extern "C" int wc4d_batch_solve_persistent(wc4d_problem* ps, int count, int meth
     const hipError_t e_ = (call);                  \
     if (e_ != hipSuccess) return bail(#call, e_);  \
   } while (0)
+  for (int i = 0; i < count; ++i)
+    if (desc[i].ldu % 4 != 0 || (reinterpret_cast<uintptr_t>(desc[i].U) & 15) != 0) {
+      free_all();
+      return fail(ps[i], WC4D_EINVAL, "persistent batch: U must have ldu % 4 == 0 and 16-byte alignment");
+    }
   std::vector<BpState> hS(count);
   std::vector<BpItem> hItems(kRing);
   std::vector<unsigned long long> hSeq(kRing);

@@ -228,10 +228,146 @@ __global__ __launch_bounds__(kRT) void k_beta_final(PcgState* st, const double* 
   }
 }
 
+// Preconditioned CG with a preconditioner function (the Ritz-LMP): the numerator of alpha
+// and beta is r^T z, and r is the true residual s itself.
+__global__ __launch_bounds__(kRT) void k_init_std_partial(const double* __restrict__ b, const double* __restrict__ s0,
+                                                          const double* __restrict__ z0, long long n,
+                                                          double* __restrict__ red) {
+  __shared__ double sh[16];
+  double vb = 0.0, vz = 0.0, vs = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT) {
+    vb += b[i] * b[i];
+    vz += s0[i] * z0[i];
+    vs += s0[i] * s0[i];
+  }
+  const double t0 = block_sum(vb, sh);
+  const double t1 = block_sum(vz, sh);
+  const double t2 = block_sum(vs, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x] = t0;
+    red[kRB + blockIdx.x] = t1;
+    red[2 * kRB + blockIdx.x] = t2;
+  }
+}
+
+__global__ __launch_bounds__(kRT) void k_init_std_final(PcgState* st, const double* __restrict__ red, double tol,
+                                                        int maxit, int criterion) {
+  __shared__ double sh[16];
+  const double bb = final_sum(red, sh);
+  const double rz = final_sum(red + kRB, sh);
+  const double ss = final_sum(red + 2 * kRB, sh);
+  if (threadIdx.x == 0) {
+    st->bnorm2 = bb;
+    st->rr = rz;
+    st->r0norm2 = rz;
+    st->rr_new = rz;
+    st->ss = ss;
+    st->tol = tol;
+    st->maxit = maxit;
+    st->criterion = criterion;
+    st->iter = 0;
+    st->status = 0;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->xbs = 0.0;
+    st->done = (bb == 0.0 || ss == 0.0) ? 1 : 0;
+    st->rr_ref = rz;
+    st->last_refresh = 0;
+    st->no_refresh = 1;
+  }
+}
+
+hipError_t pcg_kernels_init_std(PcgState* st, const double* b, const double* s0, const double* z0, long long nA,
+                                double tol, int maxit, int criterion, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_std_partial, dim3(kRB), dim3(kRT), 0, s, b, s0, z0, nA, red);
+  hipLaunchKernelGGL(k_init_std_final, dim3(1), dim3(kRT), 0, s, st, red, tol, maxit, criterion);
+  return hipGetLastError();
+}
+
+// partials of a.b into the third reduction slot (the one k_beta_final reads as r^T z)
+hipError_t pcg_dot_rz(PcgState* st, const double* a, const double* b, long long nA, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kRB), dim3(kRT), 0, s, st, a, b, nA, red + 2 * kRB);
+  return hipGetLastError();
+}
+
+hipError_t pcg_beta_final(PcgState* st, double* red, double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
+  return hipGetLastError();
+}
+
+__global__ void k_neg_inv(const double* __restrict__ th, double* __restrict__ out, int k) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) out[i] = -1.0 / th[i];
+}
+
+hipError_t vec_neg_inv(const double* theta, double* out, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_neg_inv, dim3((k + 255) / 256), dim3(256), 0, s, theta, out, k);
+  return hipGetLastError();
+}
+
+__global__ void k_sub_small(double* __restrict__ a, const double* __restrict__ b, int k, const int* skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) a[i] -= b[i];
+}
+
+hipError_t vec_sub_small(double* a, const double* b, int k, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_small, dim3((k + 255) / 256), dim3(256), 0, s, a, b, k, skip);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_skip(double* __restrict__ y, const double* __restrict__ x, long long n, const int* skip) {
+  if (skip != nullptr && *skip != 0) return;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+hipError_t vec_copy_skip(double* y, const double* x, long long n, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_skip, dim3((unsigned)std::min<long long>((n + 255) / 256, 2048)), dim3(256), 0, s, y, x,
+                     n, skip);
+  return hipGetLastError();
+}
+
 hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, double* red,
                         double* hist, hipStream_t s) {
   hipLaunchKernelGGL(k_update_r, dim3(kRB), dim3(kRT), 0, s, st, r, w, nA, red);
   hipLaunchKernelGGL(k_beta_final, dim3(1), dim3(kRT), 0, s, st, red, hist);
+  return hipGetLastError();
+}
+
+hipError_t pcg_update_r_only(PcgState* st, double* r, const double* w, long long nA, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_r, dim3(kRB), dim3(kRT), 0, s, st, r, w, nA, red);
+  return hipGetLastError();
+}
+
+// y = x - F t over j columns of F (ldf; no alignment assumed), t staged in LDS; with
+// red != null also the partials of y^T y into the slot k_beta_final reads as r^T r.
+__global__ __launch_bounds__(kRT) void k_reorth_sub(const PcgState* __restrict__ st, int j,
+                                                    const double* __restrict__ F, long long ldf,
+                                                    const double* __restrict__ t,
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    long long n, double* __restrict__ red) {
+  __shared__ double ts[512];
+  __shared__ double sh[16];
+  if (st->done) return;
+  for (int c = threadIdx.x; c < j; c += kRT) ts[c] = t[c];
+  __syncthreads();
+  double v = 0.0;
+  for (long long i = (long long)blockIdx.x * kRT + threadIdx.x; i < n; i += (long long)kRB * kRT) {
+    double acc = x[i];
+    for (int c = 0; c < j; ++c) acc -= F[(long long)c * ldf + i] * ts[c];
+    y[i] = acc;
+    v += acc * acc;
+  }
+  if (red == nullptr) return;
+  const double tt = block_sum(v, sh);
+  if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = tt;
+}
+
+hipError_t pcg_reorth_sub(const PcgState* st, int j, const double* F, long long ldf, const double* t,
+                          const double* x, double* y, long long nA, double* red, hipStream_t s) {
+  if (j < 1 || j > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reorth_sub, dim3(kRB), dim3(kRT), 0, s, st, j, F, ldf, t, x, y, nA, red);
   return hipGetLastError();
 }
 

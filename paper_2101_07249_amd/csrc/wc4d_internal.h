@@ -85,6 +85,24 @@ hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, c
 // given as row-major bf16 hi/lo parts (row i = S(i, 0..K-1)).
 hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16* Shi, __bf16* Slo,
                            hipStream_t s);
+// Few-column products Y = S X on the int8 matrix cores by a 7-slice error-free splitting
+// (gemm_oz.hip).  oz_split_matrix: slices of S (n x n, column-major, ld lds) into Ss
+// (oz_slices_bytes(n)) and its row exponents es (oz_padded(n) ints), once.  oz_gemm:
+// Y(:, j) = E(:, j) + sc_j (S X)(:, j) for the L columns X + j ldc (sc_0 = scale0, else 1),
+// with Xs (oz_xs_bytes(n, L)), fs (oz_lpad(L) ints) and P (oz_partials_doubles(n, L))
+// as scratch; every launch returns at once when *skip != 0.  oz_set_lds_limit: once per
+// process, before the first oz_gemm (its LDS exceeds the 64 KB default).
+int oz_padded(int n);
+int oz_lpad(int L);
+size_t oz_slices_bytes(int n);
+size_t oz_xs_bytes(int n, int L);
+size_t oz_partials_doubles(int n, int L);
+hipError_t oz_split_matrix(const double* S, long long lds, int n, signed char* Ss, int* es, hipStream_t s);
+hipError_t oz_gemm(int n, int L, const signed char* Ss, const int* es, const double* X, long long ldc,
+                   double scale0, const double* E, double* Y, signed char* Xs, int* fs, double* P,
+                   const int* skip, hipStream_t s);
+hipError_t oz_set_lds_limit();
+
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
                        const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                        ColMap emap, hipStream_t s);
@@ -257,6 +275,22 @@ hipError_t pcg_update_xs(PcgState* st, double* x, double* sres, const double* b,
 hipError_t pcg_update_r(PcgState* st, double* r, const double* w, long long nA, double* red,
                         double* hist, hipStream_t s);
 hipError_t pcg_update_p(PcgState* st, double* p, const double* z, long long nA, hipStream_t s);
+// r -= alpha w and the partials of r^T r, without the beta kernel (reorthogonalised CG
+// recomputes them); y = x - F t over j <= 512 columns of F (+ the partials of y^T y when
+// red != null); both skipped once st->done.
+hipError_t pcg_update_r_only(PcgState* st, double* r, const double* w, long long nA, double* red, hipStream_t s);
+hipError_t pcg_reorth_sub(const PcgState* st, int j, const double* F, long long ldf, const double* t,
+                          const double* x, double* y, long long nA, double* red, hipStream_t s);
+// Preconditioned CG with a preconditioner function: state from b, s0 and z0 = P s0 (r^T z
+// in st->rr), the r^T z partials of an iteration, and beta / convergence from the partials.
+hipError_t pcg_kernels_init_std(PcgState* st, const double* b, const double* s0, const double* z0, long long nA,
+                                double tol, int maxit, int criterion, double* red, hipStream_t s);
+hipError_t pcg_dot_rz(PcgState* st, const double* a, const double* b, long long nA, double* red, hipStream_t s);
+hipError_t pcg_beta_final(PcgState* st, double* red, double* hist, hipStream_t s);
+// out = -1/theta (k); a -= b (k; skipped when *skip != 0); y = x (n; skipped likewise)
+hipError_t vec_neg_inv(const double* theta, double* out, int k, hipStream_t s);
+hipError_t vec_sub_small(double* a, const double* b, int k, const int* skip, hipStream_t s);
+hipError_t vec_copy_skip(double* y, const double* x, long long n, const int* skip, hipStream_t s);
 // f_j = (-1)^j r_j / ||r_j|| into column j of F (ldf) when st->iter == j.
 hipError_t pcg_lanczos_col(const PcgState* st, int j, const double* r, double* F, long long ldf, long long nA,
                            hipStream_t s);
@@ -364,7 +398,9 @@ struct DsqrtTune {
 
 struct wc4d_problem_s {
   int n = 0, N = 0, device = 0;
-  long long nA = 0;
+  long long nA = 0;          // control vector size: n (N+1), or n for a strong-constraint problem
+  long long nL = 0;          // n (N+1): the time-level blocks of the sweeps
+  bool strong = false;       // strong-constraint operator (control x_0 only)
   int q = 0;
   int model = -1;  // 0 advdiff, 1 l96
   double c = 0, r = 0, F = 8, dt = 0.025;
@@ -388,6 +424,11 @@ struct wc4d_problem_s {
   int* dBexp = nullptr;       // their row exponents
   int* dQexp = nullptr;
   int* dColExp = nullptr;     // column exponents of a float16 product's right operand
+  signed char* ozSs = nullptr;  // int8 slices of Q^{1/2} (WC4D_PREC_DSQRT_OZ7), see gemm_oz.hip
+  int* ozEs = nullptr;          // their row exponents
+  signed char* ozXs = nullptr;  // slices of one vector's levels (per product)
+  int* ozFs = nullptr;
+  double* ozP = nullptr;        // split-K partials
   size_t colExpCap = 0;
   double* dStages = nullptr;
   double* dTraj = nullptr;  // l96: (N+1) x n trajectory (sketch-network features)
@@ -467,6 +508,9 @@ struct wc4d_lmp_s {
   void* Up = nullptr;       // panel copy of U (WC4D_PREC_LMP_FP32 / _FP16), see kPanel
   wc4d::LmpFmt ufmt = wc4d::LMP_F64;  // format of the U the PCG streams
   int* cexp = nullptr;      // float16 copy: column exponents (k)
+  double* AU = nullptr;     // n_A x k (ldu): A U for the Ritz-LMP (wc4d_lmp_ritz_prepare)
+  double* ninv = nullptr;   // k: -1/theta
+  double* rzw = nullptr;    // n_A + k scratch of a Ritz-LMP application
   double* GU = nullptr;     // k x k: U^T U of the U the PCG streams
   double* fu = nullptr;     // 3 k: u = U^T r, d1, d2 (fused PCG)
   // the U the passes stream: the panel copy when there is one, else U itself

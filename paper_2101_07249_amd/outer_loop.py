@@ -89,20 +89,28 @@ class OuterLoopL96:
 
 def second_loop_study(exp: OuterLoopL96, ks=(5, 10, 15), l: int = 5, first_maxit: int = 100, tol: float = 1e-6,
                       maxit: int = 1000, methods=("revd", "nystrom", "ritzit"), seed: int = 11,
-                      n_j: int = 10) -> Dict[str, object]:
+                      n_j: int = 10, reorth: bool = True, realisations: int = 1,
+                      first_tol: Optional[float] = None) -> Dict[str, object]:
     """Section 5.2.1's comparison: the first inner loop runs CG without a second-level
-    preconditioner (first_maxit iterations or tol) and gathers its Lanczos information; the
+    preconditioner (first_maxit iterations or first_tol, default tol) and gathers its Lanczos
+    information; the
     second inner loop is solved without an LMP, with the deterministic LMP of the first
     loop's k largest Ritz pairs, and with each randomised LMP (k pairs, oversampling l)
-    built on the second loop's Hessian.  Returns iterations and the quadratic cost J at the
-    first n_j iterations of the second loop per preconditioner and k."""
+    built on the second loop's Hessian.  The first loop's CG reorthogonalises its residuals
+    (reorth), so that its Ritz pairs are accurate eigenpairs of the first Hessian without
+    repeated ('ghost') values (Section 3.4); the paper takes them from an accurate
+    eigensolver instead.  Returns iterations and the quadratic cost J at the first n_j
+    iterations of the second loop per preconditioner and k; the randomised LMPs are built
+    from `realisations` start blocks (seeds seed, seed + 1, ...), reported for the first and
+    as means over all."""
     import torch
     store = {}
 
     def inner(prob, rhs, j):
         x = torch.zeros(prob.n_A, dtype=torch.float64, device=prob.torch_device)
         if j == 0:
-            info, al, be, F = prob.pcg_lanczos(rhs, x, tol=tol, maxit=first_maxit)
+            info, al, be, F = prob.pcg_lanczos(rhs, x, tol=tol if first_tol is None else first_tol,
+                                               maxit=first_maxit, reorth=reorth)
             store.update(prob0=prob, first=info, alphas=al, betas=be, F=F)
             return x
         store["prob1"], store["rhs1"] = prob, rhs
@@ -128,7 +136,16 @@ def second_loop_study(exp: OuterLoopL96, ks=(5, 10, 15), l: int = 5, first_maxit
             out["second"][f"previous_loop_k{k}"] = dict(solve(Ld), theta_max=float(th[0]))
             Ld.close()
         for m in methods:
-            L = p1.lmp_build(m, k, l, seed=seed)
-            out["second"][f"{m}_k{k}"] = dict(solve(L), theta_max=float(L.theta()[0]))
-            L.close()
+            runs = []
+            for r in range(int(realisations)):
+                L = p1.lmp_build(m, k, l, seed=seed + r)
+                runs.append(dict(solve(L), theta_max=float(L.theta()[0])))
+                L.close()
+            rec = dict(runs[0])
+            rec.update(iters_mean=float(np.mean([q["iters"] for q in runs])),
+                       iters_std=float(np.std([q["iters"] for q in runs])),
+                       J_mean=np.mean([np.pad(q["J"], (0, n_j - len(q["J"])), mode="edge") for q in runs],
+                                      axis=0).tolist(),
+                       realisations=int(realisations))
+            out["second"][f"{m}_k{k}"] = rec
     return out

@@ -27,7 +27,9 @@ METHOD = {"revd": REVD, "nystrom": NYSTROM, "ritzit": RITZIT, "nystrom1p": NYSTR
 RES_TRUE, RES_PRECOND = 0, 1
 PCG_FUSED, PCG_PLAIN = 0, 1
 PREC_FP64, PREC_SKETCH_BF16X3, PREC_LMP_FP32, PREC_SKETCH_FP16X3, PREC_LMP_FP16 = 0, 1, 2, 4, 8
+PREC_DSQRT_OZ7 = 16
 BATCH_SWEEP_FP32 = 1
+LANCZOS_REORTH = 1
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
@@ -60,6 +62,7 @@ _SIGS = {
     "wc4d_set_Bsqrt": (ctypes.c_int, [_vp, _c_dbl_p]),
     "wc4d_set_Qsqrt": (ctypes.c_int, [_vp, _c_dbl_p]),
     "wc4d_set_obs": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_int_p, _c_dbl_p]),
+    "wc4d_set_strong_constraint": (ctypes.c_int, [_vp, ctypes.c_int]),
     "wc4d_finalize": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "wc4d_dims": (ctypes.c_int, [_vp, _c_int_p, _c_int_p]),
     "wc4d_apply_A": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
@@ -83,8 +86,12 @@ _SIGS = {
     "wc4d_lmp_destroy": (ctypes.c_int, [_vp]),
     "wc4d_pcg": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo),
                                 _c_dbl_p, _c_dbl_p, _c_dbl_p, _vp]),
+    "wc4d_lmp_ritz_prepare": (ctypes.c_int, [_vp, _vp]),
+    "wc4d_lmp_ritz_apply": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp]),
+    "wc4d_pcg_ritz": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), _c_dbl_p,
+                                     _c_dbl_p, _vp]),
     "wc4d_pcg_lanczos": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), _c_dbl_p,
-                                        _c_dbl_p, _vp, ctypes.c_longlong, _vp]),
+                                        _c_dbl_p, _vp, ctypes.c_longlong, ctypes.c_int, _vp]),
     "wc4d_lanczos_pairs": (ctypes.c_int, [_vp, ctypes.c_int, _c_dbl_p, _c_dbl_p, _vp, ctypes.c_longlong, ctypes.c_int,
                                           _vp, ctypes.c_longlong, _c_dbl_p, _vp]),
     "wc4d_lmp_from_pairs": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_longlong, _c_dbl_p, ctypes.POINTER(_vp),
@@ -315,6 +322,22 @@ class Lmp:
                        "lmp_apply")
         return Y
 
+    def ritz_prepare(self, stream=None):
+        """Compute and keep A U for the Ritz-LMP (one block product with A)."""
+        self.prob._chk(lib().wc4d_lmp_ritz_prepare(self._h, _stream(stream)), "lmp_ritz_prepare")
+        return self
+
+    def ritz_apply(self, X, Y=None, stream=None):
+        """Y = P X with the Ritz-LMP of eq. Ritz_LMP (after ritz_prepare)."""
+        import torch
+        m, X2 = _block_rows(X, self.prob.n_A, "lmp_ritz_apply X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        xp, yp = _ptrs((X2, None, "lmp_ritz_apply X"), (Y, tuple(X.shape), "lmp_ritz_apply Y"))
+        self.prob._chk(lib().wc4d_lmp_ritz_apply(self._h, xp, self.prob.n_A, yp, self.prob.n_A, m,
+                                                 _stream(stream)), "lmp_ritz_apply")
+        return Y
+
     def apply_noalloc(self, X, Y, stream=None):
         """Y = C X (one or two vectors) through wc4d_lmp_apply_noalloc: no device allocation;
         Y must be given."""
@@ -353,14 +376,18 @@ class Lmp:
 class Problem:
     """Handle of one inner-loop problem on one GPU."""
 
-    def __init__(self, n: int, N: int, device: int = 0):
+    def __init__(self, n: int, N: int, device: int = 0, strong: bool = False):
         h = _vp()
         rc = lib().wc4d_create(ctypes.byref(h), int(n), int(N), int(device))
         if rc:
             raise Wc4dError(rc, "wc4d_create")
         self._h = h.value
         self.n, self.N, self.device = int(n), int(N), int(device)
-        self.n_A = self.n * (self.N + 1)
+        self.strong = bool(strong)
+        if self.strong:
+            self._chk(lib().wc4d_set_strong_constraint(self._h, 1), "set_strong_constraint")
+        # the control vector: (x_0, eta_1..eta_N), or x_0 alone for a strong-constraint problem
+        self.n_A = self.n if self.strong else self.n * (self.N + 1)
         self.q = 0
 
     @property
@@ -405,10 +432,12 @@ class Problem:
 
     @classmethod
     def from_workload(cls, w, pattern, x0: Optional[np.ndarray] = None, device: int = 0,
-                      sigma_o2: Optional[float] = None, prec: int = PREC_FP64) -> "Problem":
+                      sigma_o2: Optional[float] = None, prec: int = PREC_FP64,
+                      strong: bool = False) -> "Problem":
         """Set up a problem from workload parameters with the library's own helpers
-        (covariance square roots, Lorenz-96 trajectory)."""
-        p = cls(w.n, w.N, device)
+        (covariance square roots, Lorenz-96 trajectory); strong: the strong-constraint
+        operator on x_0 alone (Q^{1/2} is then not used)."""
+        p = cls(w.n, w.N, device, strong=strong)
         if w.model == "advdiff":
             p.set_model_advdiff(w.c, w.r)
         else:
@@ -549,10 +578,26 @@ class Problem:
             out.update(hist_true=ht[:k], hist_precond=hp[:k], hist_J=hj[:k])
         return out
 
-    def pcg_lanczos(self, b, x, tol: float = 1e-6, maxit: int = 100, stream=None):
+    def pcg_ritz(self, b, x, lmp: Lmp, tol: float = 1e-6, maxit: int = 100, criterion: int = RES_TRUE,
+                 stream=None):
+        """Preconditioned CG with the Ritz-LMP of lmp (eq. Ritz_LMP; lmp.ritz_prepare() first)."""
+        opts = PcgOpts(float(tol), int(maxit), int(criterion), PCG_PLAIN)
+        info = PcgInfo()
+        ht, hj = np.zeros(maxit), np.zeros(maxit)
+        bp, xp = _ptrs((b, self.n_A, "pcg_ritz b"), (x, self.n_A, "pcg_ritz x"))
+        rc = lib().wc4d_pcg_ritz(self._h, lmp._h, bp, xp, ctypes.byref(opts), ctypes.byref(info), _dptr(ht),
+                                 _dptr(hj), _stream(stream))
+        if rc not in (OK, ENOCONV, EBREAKDOWN):
+            self._chk(rc, "pcg_ritz")
+        k = info.iters
+        return {"iters": k, "status": info.status, "relres_true": info.relres_true,
+                "relres_precond": info.relres_precond, "J": info.J, "hist_true": ht[:k], "hist_J": hj[:k]}
+
+    def pcg_lanczos(self, b, x, tol: float = 1e-6, maxit: int = 100, reorth: bool = False, stream=None):
         """Plain CG (no second-level preconditioner) that also returns the Lanczos
         information of Section 3.4: (info, alphas, betas, F) with F (maxit + 1, n_A) holding
-        f_j = (-1)^j r_j / ||r_j|| in its rows 0..iters."""
+        f_j = (-1)^j r_j / ||r_j|| in its rows 0..iters.  reorth: complete
+        reorthogonalisation of each residual against the earlier ones (maxit <= 512)."""
         import torch
         bp, xp = _ptrs((b, self.n_A, "pcg_lanczos b"), (x, self.n_A, "pcg_lanczos x"))
         F = torch.zeros((int(maxit) + 1, self.n_A), dtype=torch.float64, device=self.torch_device)
@@ -560,7 +605,8 @@ class Problem:
         opts = PcgOpts(float(tol), int(maxit), RES_TRUE, PCG_PLAIN)
         info = PcgInfo()
         rc = lib().wc4d_pcg_lanczos(self._h, bp, xp, ctypes.byref(opts), ctypes.byref(info), _dptr(al), _dptr(be),
-                                    _tptr(F, what="F"), self.n_A, _stream(stream))
+                                    _tptr(F, what="F"), self.n_A, LANCZOS_REORTH if reorth else 0,
+                                    _stream(stream))
         if rc not in (OK, ENOCONV, EBREAKDOWN):
             self._chk(rc, "pcg_lanczos")
         k = info.iters

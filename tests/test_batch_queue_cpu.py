@@ -26,7 +26,7 @@ def kernel_phase_graph():
     phases = [ph for ph in phases if ph != "NPHASE"]
     body = re.search(r"constexpr int next_phase\(int ph\) \{(.*?)\n\}", src, re.S).group(1)
     nxt = {a: b for a, b in re.findall(r"case PH_(\w+): return PH_(\w+);", body)}
-    tr = re.search(r"__device__ bool transition\((.*?)\n\}\n", src, re.S).group(1)
+    tr = re.search(r"__device__ (?:__noinline__ )?bool transition\((.*?)\n\}\n", src, re.S).group(1)
     handled = set(re.findall(r"case PH_(\w+):", tr))
     return phases, nxt, handled
 
