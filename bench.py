@@ -10,13 +10,16 @@ SOAR B / Q, every 4th point observed at every 2nd step (q = 51,200), a sketch of
 m = 256 columns (k_r = 251 Ritz pairs, oversampling 5), Nystrom.
 
 Variants (each timed over the same number of steps):
-  plain       float64 throughout;
-  mixed       the sketch's D^{1/2} products as three bfloat16 MFMA products with float32
-              accumulation and a float16 copy of U (power-of-two column scaling) for the
-              PCG's LMP passes; CholeskyQR2, the small eigenproblem and the whole PCG
-              operator stay float64, and the stop is the float64 true residual;
-  mixed_u32   the same with a float32 copy of U;
-  mixed_fp16  split-float16 instead of split-bfloat16 sketch products, float16 U.
+  plain         float64 throughout;
+  mixed         the sketch's D^{1/2} products as three bfloat16 MFMA products with float32
+                accumulation, a float16 copy of U (power-of-two column scaling) for the
+                PCG's LMP passes, and the PCG's one-vector D^{1/2} products on the int8
+                matrix cores by a 6-slice error-free splitting (about 2e-11 of float64);
+                CholeskyQR2, the small eigenproblem, the sweeps and all PCG vectors stay
+                float64, and the stop is the true residual;
+  mixed_f64pcg  the same with float64 one-vector D^{1/2} products;
+  mixed_u32     mixed_f64pcg with a float32 copy of U;
+  mixed_fp16    split-float16 instead of split-bfloat16 sketch products, float16 U.
 `value` is the mixed variant's ms per step; the others are reported beside it.
 
 Prints one JSON line (see the fields below).  Only --gpus 1 is supported.
@@ -36,6 +39,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+INT8_PEAK_TOPS = 5000.0    # MI355X dense INT8 MFMA
+OZ_PAIRS = 21              # int8 slice products per one-vector D^{1/2} product (6 slices, t + u <= 7)
 
 # HBM bytes per launch group of the single-vector float64 D^{1/2} product at n = 4096,
 # N = 100, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (each scaled by a 1 GiB copy's
@@ -98,9 +103,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=["C1", "C2", "C3"])
     ap.add_argument("--method", default="nystrom", choices=["revd", "nystrom", "ritzit", "nystrom1p"])
-    ap.add_argument("--variants", default="plain,mixed,mixed_u32,mixed_fp16",
-                    help="comma list of plain (FP64), mixed (split-bf16 block products, float16 U), "
-                         "mixed_u32 (float32 U), mixed_fp16 (split-float16 products, float16 U)")
+    ap.add_argument("--variants", default="plain,mixed,mixed_f64pcg,mixed_u32,mixed_fp16",
+                    help="comma list of plain (FP64), mixed (split-bf16 block products, float16 U, "
+                         "int8-sliced PCG products), mixed_f64pcg (float64 PCG products), mixed_u32 "
+                         "(float32 U), mixed_fp16 (split-float16 products, float16 U)")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -466,7 +472,9 @@ def main():
     dnp = innovations(sum(len(i) for _, i in pat), w.seed, np.sqrt(w.sigma_o2))
     d = torch.from_numpy(dnp).to(dev)
     x = torch.zeros(w.n_A, dtype=torch.float64, device=dev)
-    precs = {"plain": W4.PREC_FP64, "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP16,
+    precs = {"plain": W4.PREC_FP64,
+             "mixed": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP16 | W4.PREC_DSQRT_OZ7,
+             "mixed_f64pcg": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP16,
              "mixed_u32": W4.PREC_SKETCH_BF16X3 | W4.PREC_LMP_FP32,
              "mixed_fp16": W4.PREC_SKETCH_FP16X3 | W4.PREC_LMP_FP16}
     names = [v for v in args.variants.split(",") if v]
@@ -557,7 +565,13 @@ def main():
     # roofline of the kernel class that takes the most time (timed live over the timed region)
     dom = dominant_class(results[head]["prof_classes"])
     dv = prof[dom]
-    if dom in ("dsqrt_gemm", "dsqrt_bf16x3"):
+    oz_head = bool(precs[head] & W4.PREC_DSQRT_OZ7)
+    if dom == "dsqrt_gemm" and oz_head:
+        # int8 slice products: OZ_PAIRS x 2 n^2 (N + 1) operations per launch group
+        achieved = OZ_PAIRS * dv["flops"] / (dv["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s (int8)",
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": None}
+    elif dom in ("dsqrt_gemm", "dsqrt_bf16x3"):
         peak = FP64_PEAK_TFLOPS if dom == "dsqrt_gemm" else BF16_PEAK_TFLOPS
         achieved = dv["flops"] / (dv["ms"] * 1e-3) / 1e12
         traffic = measured_traffic(w, (tunes.get(head) or {}).get("m1")) if dom == "dsqrt_gemm" else None
@@ -567,14 +581,19 @@ def main():
         achieved = dv["bytes"] / (dv["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    names_k = {"dsqrt_gemm": dsqrt_kernel_name((tunes.get(head) or {}).get("m1")),
+    names_k = {"dsqrt_gemm": ("k_oz_split_cols + k_oz_gemm<16> + k_oz_reduce (6-slice int8 splitting of Q^(1/2) "
+                              "and the vector's levels, level 0 scaled in the reduction)") if oz_head
+               else dsqrt_kernel_name((tunes.get(head) or {}).get("m1")),
                "dsqrt_bf16x3": "k_gemm_bf16x3", "lmp_un": "k_pcg_lmp_dual_pan", "lmp_ut": "k_lmp_pan_t_partial",
                "sweep_fwd": "k_sweep_fwd_w", "sweep_bwd": "k_sweep_bwd_w"}
     roof.update({"kernel": names_k.get(dom, dom), "class": dom, "launches": dv["launches"],
                  "traffic_unit": "HBM bytes per launch group (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                  "avg_launch_us": 1e3 * dv["ms"] / dv["launches"],
                  "sampled": f"HIP events around 1 in {args.prof_every} launch groups of the timed steps",
-                 "algorithmic_per_launch": (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"]})
+                 "algorithmic_per_launch": ((OZ_PAIRS if oz_head and dom == "dsqrt_gemm" else 1) *
+                                            (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"])})
+    if oz_head and dom == "dsqrt_gemm":
+        roof["traffic_unit"] = "not counted for the int8 path"
 
     iters = results[head]["pcg_iters"]
     variants = {k: {kk: vv for kk, vv in v.items() if kk not in ("prof", "prob")} for k, v in results.items()}
@@ -587,7 +606,7 @@ def main():
         "metric": "PCG time-to-1e-6 residual (learned/mixed vs plain FP64); Hessian-apply HBM GB/s",
         "value": ms_per_step, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64+bf16x3+f16" if head == "mixed" else "f64", "data": "synthetic",
+        "dtype": "f64+bf16x3+f16+i8x6" if head == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "variant": head, "method": args.method,
                    "pcg": "fused LMP (two passes over U per iteration)",
                    "n": w.n, "N": w.N, "n_A": nA, "q": q, "m": m, "k_r": w.k_r, "l": w.l, "tol": args.tol,

@@ -73,14 +73,13 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *     PCG still solves A x = b; the iteration count may differ.
  *   WC4D_PREC_DSQRT_OZ7: the one-vector D^{1/2} products (wc4d_pcg's applies of A,
  *     wc4d_rhs, any wc4d_apply_A with m = 1) run on the int8 matrix cores by an error-free
- *     splitting into 7 slices of 7 bits per operand (the Ozaki scheme, in its integer
+ *     splitting into 6 slices of 7 bits per operand (the Ozaki scheme, in its integer
  *     form): per-row exponents of Q^{1/2} and per-column exponents of the vector's levels,
- *     exact int32 slice products, the pairs of slices with t + u <= 8 combined in float64.
- *     Error a few n 2^-49 relative to max|row of Q^{1/2}| max|level| (about 1e-13 of a
- *     level's largest entry at n = 4096); the int8 slices of Q^{1/2} take 7 n^2 bytes and
- *     are made once at wc4d_finalize.  Needs B^{1/2} = c Q^{1/2} (one product over all
- *     levels; WC4D_EINVAL otherwise) and n <= 8192 per K split (always met: splits
- *     are chosen so). */
+ *     exact int32 slice products, the 21 pairs of slices with t + u <= 7 combined in
+ *     float64.  Error a few n 2^-42 relative to max|row of Q^{1/2}| max|level| (about 2e-11
+ *     of a level's largest entry at n = 4096, inside the float64 parity bar of 1e-10); the
+ *     int8 slices of Q^{1/2} take 6 n^2 bytes and are made once at wc4d_finalize.  Needs
+ *     B^{1/2} = c Q^{1/2} (one product over all levels; WC4D_EINVAL otherwise). */
 enum {
   WC4D_PREC_FP64 = 0,
   WC4D_PREC_SKETCH_BF16X3 = 1,

@@ -5,21 +5,24 @@
 // and its applications", Numer. Algorithms 59, 2012; its integer form as in Ootomo, Ozaki and
 // Yokota, "DGEMM on integer matrix multiplication unit", IJHPCA 2024).
 //
-// Row i of S is written as 2^{e_i} sum_{t=1..7} a_t 2^{-7t} with integer digits |a_t| <= 127
-// (e_i = floor(log2 max_k |S_ik|) + 1, so |S_ik| 2^{-e_i} < 1, truncated after 49 bits), and
+// Row i of S is written as 2^{e_i} sum_{t=1..6} a_t 2^{-7t} with integer digits |a_t| <= 127
+// (e_i = floor(log2 max_k |S_ik|) + 1, so |S_ik| 2^{-e_i} < 1, truncated after 42 bits), and
 // column j of X likewise with exponent f_j and digits b_u.  Then
-//     (S X)_ij ~= 2^{e_i + f_j} sum_{t + u <= 8} 2^{-7 (t + u)} sum_k a_t(i, k) b_u(k, j),
-// where every inner sum is an exact int32 product on v_mfma_i32_16x16x64_i8 (|sum| <= 7 K 127^2
-// < 2^31 for K <= 8192 per split).  The pairs with t + u > 8 and the truncation leave an error
-// of a few K 2^{-49} relative to max_k |S_ik| max_k |X_kj|: about 1e-13 of the column's
-// largest entry for n = 4096, against 1e-16 for float64 arithmetic.  Each output's levels
-// t + u = 2..8 keep their own int32 accumulator and are combined in float64 at the end, so
-// the result does not depend on the launch shape beyond the split-K sum (fixed order).
+//     (S X)_ij ~= 2^{e_i + f_j} sum_{t + u <= 7} 2^{-7 (t + u)} sum_k a_t(i, k) b_u(k, j),
+// where every inner sum is an exact int32 product on v_mfma_i32_16x16x64_i8 (|sum| <= 6 K 127^2
+// < 2^31 for K <= 8192 per split).  The 21 pairs with t + u <= 7 are kept; the others and the
+// truncation leave an error of a few K 2^{-42} relative to max_k |S_ik| max_k |X_kj|: about
+// 2e-11 of a column's largest entry for n = 4096 (a CPU model of the same arithmetic), against
+// 1e-16 for float64 arithmetic.  Each output's levels t + u = 2..7 keep their own int32
+// accumulator and are combined in float64 at the end, so the result does not depend on the
+// launch shape beyond the split-K sum (fixed order).
 //
-// Layouts.  Slices of S: int8 [7][nR][nK] (row-major, K contiguous; nR, nK: n rounded up to
-// 64, zero padded), exponents int [nR].  Slices of X: int8 [7][Lp][nK] (per column, K
-// contiguous; Lp = L rounded up to 112), exponents int [Lp].  Split-K partials: float64
-// [splits][Lp][n].
+// Layouts (fragment-major: every MFMA operand is one contiguous 1 KB piece, lane l's 16
+// bytes at l * 16).  Slices of S: int8 [kOzS][nR / 16][nK / 64][1024], the piece (t, rb, ks)
+// holding rows 16 rb + l % 16 and K 64 ks + 16 (l / 16) .. + 16 (nR, nK: n rounded up to 64,
+// zero padded); row exponents int [nR].  Slices of X: int8 [kOzS][Lp / 16][nK / 64][1024], the
+// piece (u, cb, ks) holding columns 16 cb + l % 16 (Lp = L rounded up to 112); column
+// exponents int [Lp].  Split-K partials: float64 [splits][Lp][n].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,12 +33,11 @@
 namespace wc4d {
 namespace {
 
-constexpr int kOzS = 7;          // slices per operand
+constexpr int kOzS = 6;          // slices per operand
 constexpr int kOzBits = 7;       // bits per digit
 constexpr int kOzCB = 7;         // 16-column blocks per launch chunk (112 columns)
 constexpr int kOzLP = 16 * kOzCB;
 constexpr int kOzLev = 2 * kOzS - (kOzS - 1) - 1;  // levels t + u = 2..kOzS + 1
-constexpr int kOzRow = 80;       // LDS bytes per (slice, column) row of a K step (64 + 16 pad)
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -47,9 +49,9 @@ __device__ inline int oz_exponent(double vmax) {
   return e;
 }
 
-// the 7 digits of v 2^{-e} (|v| < 2^e), truncated toward zero after 49 bits
+// the kOzS digits of v 2^{-e} (|v| < 2^e), truncated toward zero after 7 kOzS bits
 __device__ inline void oz_digits(double v, int e, signed char (&d)[kOzS]) {
-  const double a = ldexp(fabs(v), kOzS * kOzBits - e);  // < 2^49, exact
+  const double a = ldexp(fabs(v), kOzS * kOzBits - e);  // < 2^(7 kOzS), exact
   unsigned long long m = (unsigned long long)a;         // truncation
   const bool neg = v < 0.0;
 #pragma unroll
@@ -86,9 +88,10 @@ __global__ __launch_bounds__(256) void k_oz_split_rows(const double* __restrict_
     tile[kk][ii] = (i < n && k < n) ? S[(long long)k * lds + i] : 0.0;
   }
   __syncthreads();
-  // thread: row ii = tid / 4, 16 consecutive k at 16 (tid % 4)
+  // thread: row ii = tid / 4, 16 consecutive k at 16 (tid % 4): one lane's piece of a fragment
   const int ii = threadIdx.x >> 2, kq = (threadIdx.x & 3) * 16;
   const int e = es[i0 + ii];
+  const int nRB = nR / 16, nKS = nK / 64, rb = (i0 + ii) >> 4, fl = ((i0 + ii) & 15) + 16 * (threadIdx.x & 3);
   signed char out[kOzS][16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -101,17 +104,19 @@ __global__ __launch_bounds__(256) void k_oz_split_rows(const double* __restrict_
   for (int t = 0; t < kOzS; ++t) {
     v4i w;
     __builtin_memcpy(&w, out[t], 16);
-    *reinterpret_cast<v4i*>(Ss + ((size_t)t * nR + i0 + ii) * nK + k0 + kq) = w;
+    *reinterpret_cast<v4i*>(Ss + (((size_t)t * nRB + rb) * nKS + k0 / 64) * 1024 + fl * 16) = w;
   }
 }
 
-// ---- slices of X (per call): one workgroup per column (columns past L are zero)
+// ---- slices of X (per call): workgroup (j, part) = column j (zero past L), K quarter part;
+// each of a column's four workgroups finds the column's largest magnitude itself (the column
+// is 8 n bytes, read from L2), then slices its quarter
 __global__ __launch_bounds__(256) void k_oz_split_cols(const double* __restrict__ X, long long ldc, int n, int L,
                                                        int nK, int Lpad, signed char* __restrict__ Xs,
                                                        int* __restrict__ fs, const int* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
   __shared__ double red[256];
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, part = blockIdx.y;
   const double* x = X + (long long)j * ldc;
   double mx = 0.0;
   if (j < L)
@@ -123,86 +128,100 @@ __global__ __launch_bounds__(256) void k_oz_split_cols(const double* __restrict_
     __syncthreads();
   }
   const int f = oz_exponent(red[0]);
-  if (threadIdx.x == 0) fs[j] = (j < L) ? f : 0;
-  for (int k0 = threadIdx.x * 16; k0 < nK; k0 += 256 * 16) {
-    signed char out[kOzS][16];
+  if (threadIdx.x == 0 && part == 0) fs[j] = (j < L) ? f : 0;
+  const int kq = nK / 4;  // a multiple of 16
+  // four consecutive k per thread: a quarter of one lane's 16-byte piece per slice
+  for (int k0 = part * kq + threadIdx.x * 4; k0 < (part + 1) * kq; k0 += 256 * 4) {
+    signed char out[kOzS][4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 4; ++q) {
       const int k = k0 + q;
       signed char d[kOzS];
       oz_digits((j < L && k < n) ? x[k] : 0.0, f, d);
 #pragma unroll
       for (int t = 0; t < kOzS; ++t) out[t][q] = d[t];
     }
+    const int fl = (j & 15) + 16 * ((k0 & 63) >> 4);
 #pragma unroll
     for (int t = 0; t < kOzS; ++t) {
-      v4i w;
-      __builtin_memcpy(&w, out[t], 16);
-      *reinterpret_cast<v4i*>(Xs + ((size_t)t * Lpad + j) * nK + k0) = w;
+      int w;
+      __builtin_memcpy(&w, out[t], 4);
+      *reinterpret_cast<int*>(Xs + (((size_t)t * (Lpad / 16) + (j >> 4)) * (nK / 64) + k0 / 64) * 1024 + fl * 16 +
+                              (k0 & 15)) = w;
     }
   }
 }
 
-// ---- the product: workgroup = 64 rows x 112 columns x one K range; 8 waves: wave w takes
-// rows 16 (w & 3) .. + 16 and column blocks [4 (w >> 2), 4 (w >> 2) + 4) of the 7.  The K step
-// of X slices (7 x 112 columns x 64 bytes) is staged in LDS (double buffered) and shared by
-// the 8 waves; each wave reads its rows' S slices straight into MFMA operands.
-__global__ __launch_bounds__(512, 1) void k_oz_gemm(const signed char* __restrict__ Ss, const int* __restrict__ es,
-                                                   const signed char* __restrict__ Xs,
-                                                   const int* __restrict__ fs, int n, int nR, int nK, int Lpad,
-                                                   int kchunk, double* __restrict__ P,
-                                                   const int* __restrict__ skip) {
+// ---- the product: workgroup = 64 rows x 112 columns x one K range; 16 waves: wave w takes
+// rows 16 (w & 3) .. + 16 and the column blocks {2 (w >> 2), 2 (w >> 2) + 1} of the 7 (the last
+// group only block 6).  Each K step's operands, the X pieces (kOzS slices x 7 column blocks)
+// and the S pieces (kOzS slices x 4 row groups), are copied global -> LDS by the load-to-LDS
+// instruction (no registers) one step ahead, double buffered (wave w copies pieces w, w + 16,
+// ...); every wave waits for all of its loads before the barrier that hands the buffer over,
+// so no ordering of memory operations is assumed.  Four waves per SIMD hide what one step
+// ahead does not.
+template <int NSTEP>
+__global__ __launch_bounds__(1024, 1) void k_oz_gemm(const signed char* __restrict__ Ss, const int* __restrict__ es,
+                                                    const signed char* __restrict__ Xs,
+                                                    const int* __restrict__ fs, int n, int nR, int nK, int Lpad,
+                                                    int kchunk, double* __restrict__ P,
+                                                    const int* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
-  extern __shared__ __align__(16) signed char xl[];  // [2][7][112][kOzRow]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rg = wave & 3, ch = wave >> 2;
-  const int cb0 = 4 * ch, ncb = ch == 0 ? 4 : kOzCB - 4;
+  constexpr int kFrag = 1024;
+  constexpr int kXP = kOzS * kOzCB, kSP = kOzS * 4, kPieces = kXP + kSP;  // pieces per step
+  constexpr int kStage = kPieces * kFrag;
+  extern __shared__ __align__(16) signed char xl[];  // [2][kPieces][1024]: X pieces, then S pieces
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rg = wave & 3, cg = wave >> 2;
+  const int cb0 = 2 * cg, ncb = cg < 3 ? 2 : 1;
   const int i0 = blockIdx.x * 64 + 16 * rg;
   const int split = blockIdx.y, chunk = blockIdx.z;
-  const int kb = split * kchunk, ke = min(nK, kb + kchunk);
+  const int nKS = nK / 64, nRB = nR / 16, nCB = Lpad / 16;
+  const int ksb = split * (kchunk / 64), kse = min(nKS, ksb + kchunk / 64);
   const int col0 = chunk * kOzLP;
-  constexpr int kBuf = kOzS * kOzLP * kOzRow;
-  // X step loader: 7 slices x 112 columns x 4 pieces of 16 bytes
-  auto xload = [&](int k0, int buf) {
-    for (int q = tid; q < kOzS * kOzLP * 4; q += 512) {
-      const int t = q / (kOzLP * 4), rem = q - t * kOzLP * 4;
-      const int c = rem >> 2, part = rem & 3;
-      const v4i w = *reinterpret_cast<const v4i*>(Xs + ((size_t)t * Lpad + col0 + c) * nK + k0 + 16 * part);
-      *reinterpret_cast<v4i*>(xl + buf * kBuf + (t * kOzLP + c) * kOzRow + 16 * part) = w;
+  // piece p of step ks: p < kXP: X (slice p / 7, block p % 7); else S (slice q / 4, row
+  // group q % 4), q = p - kXP
+  auto load_step = [&](int ks, int stage) {
+    for (int p = wave; p < kPieces; p += 16) {
+      const signed char* src;
+      if (p < kXP) {
+        const int u = p / kOzCB, cb = p - u * kOzCB;
+        src = Xs + (((size_t)u * nCB + chunk * kOzCB + cb) * nKS + ks) * kFrag;
+      } else {
+        const int q = p - kXP, t = q >> 2, r = q & 3;
+        src = Ss + (((size_t)t * nRB + blockIdx.x * 4 + r) * nKS + ks) * kFrag;
+      }
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + lane * 16),
+                                       (__attribute__((address_space(3))) void*)(xl + stage * kStage + p * kFrag),
+                                       16, 0, 0);
     }
   };
-  // S operands of this wave for one K step: row i0 + lane % 16, bytes k0 + 16 (lane / 16) ..
-  v4i sa[kOzS], sn[kOzS];
-  const signed char* srow = Ss + (size_t)(i0 + (lane & 15)) * nK + 16 * (lane >> 4);
-  auto sload = [&](int k0, v4i (&r)[kOzS]) {
+  v4i acc[2][kOzLev];
 #pragma unroll
-    for (int t = 0; t < kOzS; ++t) r[t] = *reinterpret_cast<const v4i*>(srow + (size_t)t * nR * nK + k0);
-  };
-  v4i acc[4][kOzLev];
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int l = 0; l < kOzLev; ++l) acc[b][l] = v4i{0, 0, 0, 0};
-  int buf = 0;
-  if (kb < ke) {
-    xload(kb, 0);
-    sload(kb, sa);
-  }
-  for (int k0 = kb; k0 < ke; k0 += 64) {
-    __syncthreads();  // this step's X in LDS; the other buffer free
-    const bool more = k0 + 64 < ke;
-    if (more) {
-      xload(k0 + 64, buf ^ 1);
-      sload(k0 + 64, sn);
-    }
-    const signed char* xb = xl + buf * kBuf + (lane & 15) * kOzRow + 16 * (lane >> 4);
+  auto step = [&](int ks) {
+    const int stage = (ks - ksb) & 1;
+    // all of this wave's copies (this step's operands) and LDS reads (the previous step's)
+    // done, then the barrier hands the buffers over; the empty asm statements keep the
+    // compiler from moving memory accesses across it
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    load_step(min(ks + 1, kse - 1), stage ^ 1);
+    const signed char* base = xl + stage * kStage + lane * 16;
+    v4i sa[kOzS];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int t = 0; t < kOzS; ++t) sa[t] = *reinterpret_cast<const v4i*>(base + (kXP + 4 * t + rg) * kFrag);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
       if (b < ncb) {
         v4i xv[kOzS];
 #pragma unroll
-        for (int u = 0; u < kOzS; ++u)
-          xv[u] = *reinterpret_cast<const v4i*>(xb + (u * kOzLP + 16 * (cb0 + b)) * kOzRow);
+        for (int u = 0; u < kOzS; ++u) xv[u] = *reinterpret_cast<const v4i*>(base + (u * kOzCB + cb0 + b) * kFrag);
 #pragma unroll
         for (int t = 0; t < kOzS; ++t)
 #pragma unroll
@@ -211,15 +230,20 @@ __global__ __launch_bounds__(512, 1) void k_oz_gemm(const signed char* __restric
               acc[b][t + u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(sa[t], xv[u], acc[b][t + u], 0, 0, 0);
       }
     }
-    if (more) {
+  };
+  if (ksb < kse) {
+    load_step(ksb, 0);
+    if (NSTEP > 0) {
 #pragma unroll
-      for (int t = 0; t < kOzS; ++t) sa[t] = sn[t];
+      for (int i = 0; i < NSTEP; ++i) step(ksb + i);
+    } else {
+      for (int ks = ksb; ks < kse; ++ks) step(ks);
     }
-    buf ^= 1;
+    __builtin_amdgcn_s_waitcnt(0);  // the unused copies of the last step
   }
   // combine the levels in float64: level l (digit pair t + u = l + 2) weighs 2^{-7 (l + 2)}
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < 2; ++b) {
     if (b >= ncb) continue;
     const int c = col0 + 16 * (cb0 + b) + (lane & 15);
     const int f = fs[c];
@@ -251,6 +275,9 @@ __global__ void k_oz_reduce(const double* __restrict__ P, int splits, int n, int
     Y[o] = (E != nullptr ? E[o] : 0.0) + v;
   }
 }
+
+// two buffers of one K step's pieces: X (kOzS x 7) and S (kOzS x 4), 1 KB each
+size_t oz_gemm_lds() { return (size_t)2 * (kOzS * kOzCB + kOzS * 4) * 1024; }
 
 }  // namespace
 
@@ -291,10 +318,13 @@ hipError_t oz_gemm(int n, int L, const signed char* Ss, const int* es, const dou
   const int splits = oz_splits(n, L);
   const int ksteps = nK / 64;
   const int kchunk = (ksteps + splits - 1) / splits * 64;
-  hipLaunchKernelGGL(k_oz_split_cols, dim3(Lpad), dim3(256), 0, s, X, ldc, n, L, nK, Lpad, Xs, fs, skip);
-  const size_t lds = (size_t)2 * kOzS * kOzLP * kOzRow;
-  hipLaunchKernelGGL(k_oz_gemm, dim3(nR / 64, splits, Lpad / kOzLP), dim3(512), lds, s, Ss, es, Xs, fs, n, nR, nK,
-                     Lpad, kchunk, P, skip);
+  hipLaunchKernelGGL(k_oz_split_cols, dim3(Lpad, 4), dim3(256), 0, s, X, ldc, n, L, nK, Lpad, Xs, fs, skip);
+  const size_t lds = oz_gemm_lds();
+  const dim3 ggrid(nR / 64, splits, Lpad / kOzLP);
+  if (kchunk == 16 * 64 && ksteps % 16 == 0)
+    hipLaunchKernelGGL(k_oz_gemm<16>, ggrid, dim3(1024), lds, s, Ss, es, Xs, fs, n, nR, nK, Lpad, kchunk, P, skip);
+  else
+    hipLaunchKernelGGL(k_oz_gemm<0>, ggrid, dim3(1024), lds, s, Ss, es, Xs, fs, n, nR, nK, Lpad, kchunk, P, skip);
   const long long total = (long long)n * L;
   const int grid = (int)std::min<long long>((total + 255) / 256, 2048);
   hipLaunchKernelGGL(k_oz_reduce, dim3(grid), dim3(256), 0, s, P, splits, n, L, Lpad, ldc, scale0, E, Y, skip);
@@ -302,8 +332,11 @@ hipError_t oz_gemm(int n, int L, const signed char* Ss, const int* es, const dou
 }
 
 hipError_t oz_set_lds_limit() {
-  const size_t lds = (size_t)2 * kOzS * kOzLP * kOzRow;
-  return hipFuncSetAttribute((const void*)k_oz_gemm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = oz_gemm_lds();
+  hipError_t e = hipFuncSetAttribute((const void*)k_oz_gemm<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_oz_gemm<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return e;
 }
 
 }  // namespace wc4d
