@@ -108,36 +108,39 @@ __global__ __launch_bounds__(256) void k_oz_split_rows(const double* __restrict_
   }
 }
 
-// ---- slices of X (per call): workgroup (j, part) = column j (zero past L), K quarter part;
-// each of a column's four workgroups finds the column's largest magnitude itself (the column
-// is 8 n bytes, read from L2), then slices its quarter
-__global__ __launch_bounds__(256) void k_oz_split_cols(const double* __restrict__ X, long long ldc, int n, int L,
-                                                       int nK, int Lpad, signed char* __restrict__ Xs,
-                                                       int* __restrict__ fs, const int* __restrict__ skip) {
+// ---- slices of X (per call): one workgroup of 1024 threads per column (zero past L); each
+// thread holds four consecutive k of the column in registers (looping for n > 4096), so the
+// column is read once for its largest magnitude and sliced from registers
+__global__ __launch_bounds__(1024) void k_oz_split_cols(const double* __restrict__ X, long long ldc, int n, int L,
+                                                        int nK, int Lpad, signed char* __restrict__ Xs,
+                                                        int* __restrict__ fs, const int* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
-  __shared__ double red[256];
-  const int j = blockIdx.x, part = blockIdx.y;
+  __shared__ double red[16];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* x = X + (long long)j * ldc;
+  const bool live = j < L;
   double mx = 0.0;
-  if (j < L)
-    for (int k = threadIdx.x; k < n; k += 256) mx = fmax(mx, fabs(x[k]));
-  red[threadIdx.x] = mx;
+  for (int k = 4 * tid; k < n; k += 4096)
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (k + q < n) mx = fmax(mx, fabs(x[k + q]));
+    }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if (lane == 0) red[wave] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const int f = oz_exponent(red[0]);
-  if (threadIdx.x == 0 && part == 0) fs[j] = (j < L) ? f : 0;
-  const int kq = nK / 4;  // a multiple of 16
-  // four consecutive k per thread: a quarter of one lane's 16-byte piece per slice
-  for (int k0 = part * kq + threadIdx.x * 4; k0 < (part + 1) * kq; k0 += 256 * 4) {
+  double m = red[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+  const int f = oz_exponent(m);
+  if (tid == 0) fs[j] = live ? f : 0;
+  for (int k0 = 4 * tid; k0 < nK; k0 += 4096) {
     signed char out[kOzS][4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = k0 + q;
       signed char d[kOzS];
-      oz_digits((j < L && k < n) ? x[k] : 0.0, f, d);
+      oz_digits((live && k < n) ? x[k] : 0.0, f, d);
 #pragma unroll
       for (int t = 0; t < kOzS; ++t) out[t][q] = d[t];
     }
@@ -182,8 +185,12 @@ __global__ __launch_bounds__(1024, 1) void k_oz_gemm(const signed char* __restri
   const int col0 = chunk * kOzLP;
   // piece p of step ks: p < kXP: X (slice p / 7, block p % 7); else S (slice q / 4, row
   // group q % 4), q = p - kXP
+  constexpr int kFull = kPieces / 16;  // pieces every wave copies; the first kPieces % 16 waves one more
   auto load_step = [&](int ks, int stage) {
-    for (int p = wave; p < kPieces; p += 16) {
+#pragma unroll
+    for (int j = 0; j <= kFull; ++j) {
+      const int p = wave + 16 * j;
+      if (j == kFull && p >= kPieces) break;
       const signed char* src;
       if (p < kXP) {
         const int u = p / kOzCB, cb = p - u * kOzCB;
@@ -318,7 +325,7 @@ hipError_t oz_gemm(int n, int L, const signed char* Ss, const int* es, const dou
   const int splits = oz_splits(n, L);
   const int ksteps = nK / 64;
   const int kchunk = (ksteps + splits - 1) / splits * 64;
-  hipLaunchKernelGGL(k_oz_split_cols, dim3(Lpad, 4), dim3(256), 0, s, X, ldc, n, L, nK, Lpad, Xs, fs, skip);
+  hipLaunchKernelGGL(k_oz_split_cols, dim3(Lpad), dim3(1024), 0, s, X, ldc, n, L, nK, Lpad, Xs, fs, skip);
   const size_t lds = oz_gemm_lds();
   const dim3 ggrid(nR / 64, splits, Lpad / kOzLP);
   if (kchunk == 16 * 64 && ksteps % 16 == 0)
