@@ -53,6 +53,14 @@ MEASURED_TRAFFIC = {"n": 4096, "N": 100,
                                 "7d77e6e0c0c0a03f8aa5b42f710c13d72289138b95b47149a76721ecbe82e54d"},
                     "bytes_per_launch": {2: 216.7e6, 7: 216.6e6}}
 
+# HBM bytes per launch group of the int8-sliced one-vector D^{1/2} product at n = 4096, N = 100
+# (k_oz_split_cols + k_oz_gemm<16> + k_oz_reduce), measured the same way
+# (profiles/dsqrt_oz_n4096_N100_kernel_stats.md); valid only for this gemm_oz.hip.
+OZ_MEASURED_TRAFFIC = {"n": 4096, "N": 100,
+                       "sources": {"paper_2101_07249_amd/csrc/gemm_oz.hip":
+                                   "ad5282a403afa4148e09e066f2d7b9e83a81c841a2e5a15945bd652b596de7b0"},
+                       "bytes_per_launch": 163.2e6}
+
 # Measured tile choices for MI355X (loaded unless --tune-cache or --retune is given).
 TUNING_TABLE = os.path.join(ROOT, "paper_2101_07249_amd", "tuning", "mi355x.txt")
 
@@ -76,6 +84,20 @@ def measured_traffic(w, tune):
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
     return t["bytes_per_launch"].get(tune.get("tile_b"))
+
+
+def oz_measured_traffic(w):
+    """The counted bytes of the int8-sliced product group when this run uses the measured
+    gemm_oz.hip, else None."""
+    import hashlib
+    t = OZ_MEASURED_TRAFFIC
+    if (w.n, w.N) != (t["n"], t["N"]):
+        return None
+    for path, digest in t["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return t["bytes_per_launch"]
 
 
 def dsqrt_kernel_name(tune):
@@ -205,9 +227,11 @@ def batched_section(args):
     """64 uneven advection-diffusion inner loops (n in [512, 8192], N in [10, 200], m = 64,
     Nystrom): every problem's LMP built from its seeded device Gaussian block, then all PCG
     iterations of all problems in one persistent launch (wc4d_batch_solve_persistent),
-    with float64 sweeps and with float32 sweeps; wall time of the whole call (builds
-    included), the persistent launch's own time, iterations and true residuals.  With
-    --batched-compare also the host-worker form (wc4d_batch_solve)."""
+    with float64 sweeps and with float32 sweeps; then the host-worker form (wc4d_batch_solve,
+    4 workers) with the PCG's one-vector D^{1/2} products on the int8 matrix cores; wall time
+    of the whole call (builds included), the persistent launch's own time, iterations and
+    true residuals with the float64 operator.  With --batched-compare also the host-worker
+    form in float64."""
     import numpy as np
     import torch
 
@@ -245,6 +269,27 @@ def batched_section(args):
                      "converged_recursive": all(s == 0 for s in status),
                      "true_residual_max": max(res), "true_residual_median": float(np.median(res))}
         print(f"batched: {name} {t:.1f} s (persistent launch {kms * 1e-3:.1f} s)", file=sys.stderr, flush=True)
+    # host workers (a stream each, the single-problem kernels) with the PCG's one-vector D^{1/2}
+    # products on the int8 matrix cores; true residuals with the float64 operator
+    from paper_2101_07249_amd import wc4d as W4
+    probs_i8 = [Problem.from_workload(w, obs_pattern(w), prec=W4.PREC_DSQRT_OZ7) for w in ws]
+    G = [gaussian_block(4000 + i, p.n_A, k_r + l) for i, p in enumerate(probs_i8)]
+    x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs_i8]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, status = batch_solve(probs_i8, "nystrom", k_r, l, G, b, x, tol=args.tol, maxit=args.maxit, workers=4,
+                                autotune=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    res = [float((b[i] - p.apply_A(x[i])).norm() / b[i].norm()) for i, p in enumerate(probs)]
+    out["host_workers_i8"] = {"s": t, "iters_total": int(sum(i["iters"] for i in infos)),
+                              "converged_recursive": all(s_ == 0 for s_ in status),
+                              "true_residual_max": max(res), "true_residual_median": float(np.median(res)),
+                              "workers": 4}
+    print(f"batched: host workers, int8 D^(1/2) {t:.1f} s", file=sys.stderr, flush=True)
+    for p in probs_i8:
+        p.close()
+    del G, x
     if args.batched_compare:
         G = [gaussian_block(4000 + i, p.n_A, k_r + l) for i, p in enumerate(probs)]
         x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
@@ -570,7 +615,7 @@ def main():
         # int8 slice products: OZ_PAIRS x 2 n^2 (N + 1) operations per launch group
         achieved = OZ_PAIRS * dv["flops"] / (dv["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS, "unit": "TOP/s (int8)",
-                "frac": achieved / INT8_PEAK_TOPS, "traffic": None}
+                "frac": achieved / INT8_PEAK_TOPS, "traffic": oz_measured_traffic(w)}
     elif dom in ("dsqrt_gemm", "dsqrt_bf16x3"):
         peak = FP64_PEAK_TFLOPS if dom == "dsqrt_gemm" else BF16_PEAK_TFLOPS
         achieved = dv["flops"] / (dv["ms"] * 1e-3) / 1e12
@@ -593,7 +638,9 @@ def main():
                  "algorithmic_per_launch": ((OZ_PAIRS if oz_head and dom == "dsqrt_gemm" else 1) *
                                             (dv["flops"] if dom.startswith("dsqrt") else dv["bytes"]) / dv["launches"])})
     if oz_head and dom == "dsqrt_gemm":
-        roof["traffic_unit"] = "not counted for the int8 path"
+        roof["traffic_unit"] = ("HBM bytes per launch group of the three kernels (rocprofv3 FETCH_SIZE x2.0 + "
+                                "WRITE_SIZE x1.0); algorithmic: 6 n^2 bytes of slices of Q^(1/2) (100.7 MB) + "
+                                "the vector in and out")
 
     iters = results[head]["pcg_iters"]
     variants = {k: {kk: vv for kk, vv in v.items() if kk not in ("prof", "prob")} for k, v in results.items()}
