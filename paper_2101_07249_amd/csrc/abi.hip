@@ -143,6 +143,9 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->dBlo);
   dev_free(&p->dQhi);
   dev_free(&p->dQlo);
+  dev_free(&p->dQf);
+  dev_free(&p->dXf);
+  p->xfCap = 0;
   dev_free(&p->dStages);
   dev_free(&p->dTraj);
   dev_free(&p->lossWs);
@@ -389,6 +392,9 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
       return rc;
     HIPCHK(p, split_bf16_rows(n, n, p->dB, n, p->dBhi, p->dBlo, s));
     HIPCHK(p, split_bf16_rows(n, n, p->dQ, n, p->dQhi, p->dQlo, s));
+    if ((rc = dev_alloc(p, &p->dQf, bf16_frag_elems(n, n)))) return rc;
+    HIPCHK(p, bf16x3_set_lds_limit());
+    HIPCHK(p, split_bf16_frag_rows(n, n, p->dQ, n, p->dQf, s));
   }
   if (prec_mode & WC4D_PREC_SKETCH_FP16X3) {
     const size_t nn = (size_t)n * n;
@@ -534,11 +540,29 @@ int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long 
     return WC4D_OK;
   }
   if (mixed == SPLIT_BF16) {
+    // products with Q^{1/2}: the fragment-major kernel when the shape has enough tiles
+    auto q_product = [&](int ncol, ColMap xm, ColMap ym, ColMap em) -> int {
+      if (!bf16x3_use_frag(n, ncol)) {
+        HIPCHK(p, gemm_bf16x3(n, ncol, n, 1.0, p->dQhi, p->dQlo, X, xm, Y, ym, E, em, s));
+        return WC4D_OK;
+      }
+      const size_t need = bf16_frag_elems(ncol, n);
+      if (p->xfCap < need) {
+        dev_free(&p->dXf);
+        p->xfCap = 0;
+        int rc = dev_alloc(p, &p->dXf, need);
+        if (rc) return rc;
+        p->xfCap = need;
+      }
+      HIPCHK(p, gemm_bf16x3_frag(n, ncol, n, 1.0, p->dQf, X, xm, p->dXf, Y, ym, E, em, s));
+      return WC4D_OK;
+    };
+    if (p->scaledB)  // all levels in one product with Q^{1/2}, level 0 scaled by c in the epilogue
+      return q_product(m * (N + 1), ColMap{ldx, N + 1, 0, n}, ColMap{ldy, N + 1, 0, n, p->bScale},
+                       ColMap{lde, N + 1, 0, n});
     HIPCHK(p, gemm_bf16x3(n, m, n, 1.0, p->dBhi, p->dBlo, X, ColMap{ldx, 1, 0, n}, Y,
                           ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
-    HIPCHK(p, gemm_bf16x3(n, m * N, n, 1.0, p->dQhi, p->dQlo, X, ColMap{ldx, N, 1, n}, Y,
-                          ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
-    return WC4D_OK;
+    return q_product(m * N, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n}, ColMap{lde, N, 1, n});
   }
   if (m == 1 && p->ozSs != nullptr) {
     // one vector: all levels in one int8-sliced product with Q^{1/2}, level 0 scaled by c

@@ -5,9 +5,13 @@
 // and the bfloat16 rounding of the low parts are O(2^-16) relative; the float32 sum
 // over K adds O(sqrt(K) 2^-24).
 //
-// S is pre-split once (split_bf16_rows) into two row-major bf16 arrays (row i holds
-// S(i, 0..K-1) contiguously), so an MFMA operand row is one 16-byte load.  X is
-// split while it is staged into LDS.
+// Two kernels.  The LDS-tiled one (k_gemm_bf16x3): S is pre-split once (split_bf16_rows)
+// into two row-major bf16 arrays (row i holds S(i, 0..K-1) contiguously), so an MFMA operand
+// row is one 16-byte load, and X is split while it is staged into LDS.  The fragment-major
+// one (k_gemm_bf16x3_frag, products with many 256 x 256 tiles such as the sketch block's
+// all-level product): both operands are pre-split into 1 KB MFMA operand pieces that are
+// copied global -> LDS without passing through registers (layout below).  Both form the same
+// three products in the same K order, so they give the same bits.
 //
 // The float16 form (gemm_fp16x3) has 11 significant bits per part instead of 8 but a
 // narrow exponent range, so both operands are scaled by powers of two: row i of S by
@@ -25,6 +29,9 @@
 // As in gemm_f64 the product is formed transposed (MFMA rows = columns t of C), so a
 // lane's results are 4 consecutive columns of one row and the 16 lanes sharing l/16
 // store 16 consecutive rows of a column.
+#include <cstdlib>
+#include <cstring>
+
 #include "wc4d_internal.h"
 
 namespace wc4d {
@@ -245,11 +252,12 @@ __global__ __launch_bounds__(128 * WR) void k_gemm_bf16x3(int M, int ncol, int K
       if (j >= ncol) continue;
       const long long co = cmap.off(j);
       const long long eo = (E != nullptr) ? emap.off(j) : 0;
+      const double sc = alpha * cmap.colscale(j);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int i = i0 + wi0 + b * 16 + (lane & 15);
         if (i < M) {
-          double v = alpha * (double)acc[a][b][r];
+          double v = sc * (double)acc[a][b][r];
           if (E != nullptr) v += E[eo + i];
           C[co + i] = v;
         }
@@ -379,11 +387,12 @@ __global__ __launch_bounds__(256) void k_gemm_fp16x3(int M, int ncol, int K, dou
       const long long co = cmap.off(j);
       const long long eo = (E != nullptr) ? emap.off(j) : 0;
       const int ej = colexp[j];
+      const double sc = alpha * cmap.colscale(j);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int i = i0 + wi0 + b * 16 + (lane & 15);
         if (i < M) {
-          double v = alpha * ldexp((double)acc[a][b][r], rowexp[i] + ej);
+          double v = sc * ldexp((double)acc[a][b][r], rowexp[i] + ej);
           if (E != nullptr) v += E[eo + i];
           C[co + i] = v;
         }
@@ -418,6 +427,214 @@ hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, 
     hipLaunchKernelGGL(k_gemm_bf16x3<2>, grid, dim3(256), 0, s, M, ncol, K, alpha, Shi, Slo, B, bmap, C, cmap, E,
                        emap);
   }
+  return hipGetLastError();
+}
+
+
+// ---- fragment-major form for large products (the sketch block's all-level D^{1/2} product).
+// Both operands are split once per call (S once per problem) into bf16 hi/lo parts stored as
+// 1 KB pieces in the MFMA operand order: piece (kb, blk, part) holds the 16 rows (columns of X)
+// 16 blk .. + 16 and K 32 kb .. + 32, lane l's 8 values (row 16 blk + l % 16, K 32 kb + 8 (l / 16)
+// + e) at 8 l; pieces ordered [kb][blk][part], rows / columns padded with zeros to a multiple
+// of 256 and K to a multiple of 32.  The product then copies whole pieces global -> LDS with
+// the load-to-LDS instruction (no registers, no LDS writes by the waves) and every lane's
+// operand read is one conflict-free 16-byte LDS load.
+constexpr int kFT = 256;  // tile rows and columns
+constexpr int kFP = 512;  // bf16 per piece
+constexpr int kFStage = 64 * kFP;  // one K step: 16 row blocks x 2 parts, then 16 column blocks x 2 parts
+
+// A(r, k) = XCOL ? A[amap.off(r) + k] : A[r + k lda], for r < R, k < K; zero outside.
+template <bool XCOL>
+__global__ __launch_bounds__(256) void k_split_bf16_frag(int R, int K, int nB, int nKB, const double* __restrict__ A,
+                                                         long long lda, ColMap amap, __bf16* __restrict__ F) {
+  const long long tot = (long long)nB * nKB * 64;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long P = t >> 6;
+    const int lane = (int)(t & 63);
+    const int blk = (int)(P / nKB), kb = (int)(P - (long long)blk * nKB);
+    const int r = 16 * blk + (lane & 15), k0 = 32 * kb + 8 * (lane >> 4);
+    double v[8];
+    if (r < R) {
+      if (XCOL) {
+        const double* col = A + amap.off(r);
+        if (k0 + 8 <= K && (reinterpret_cast<uintptr_t>(col + k0) & 15) == 0) {
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            const double2 d2 = *reinterpret_cast<const double2*>(col + k0 + e);
+            v[e] = d2.x;
+            v[e + 1] = d2.y;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = (k0 + e < K) ? col[k0 + e] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (k0 + e < K) ? A[(size_t)r + (size_t)(k0 + e) * lda] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.0;
+    }
+    bf8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 a, b;
+      split2(v[e], a, b);
+      h[e] = a;
+      l[e] = b;
+    }
+    __bf16* dst = F + ((size_t)kb * nB + blk) * 2 * kFP + (size_t)lane * 8;
+    *reinterpret_cast<bf8*>(dst) = h;
+    *reinterpret_cast<bf8*>(dst + kFP) = l;
+  }
+}
+
+// The product on fragment-major parts: one workgroup per 256 x 256 tile of C (rows of S x
+// columns of X), 8 waves, wave w computing rows 64 (w & 3) .. + 64 and columns 128 (w >> 2) ..
+// + 128 (4 x 8 blocks of 16 x 16, three MFMAs each per K step of 32).  Each K step's 64 pieces
+// (64 KB) are copied into LDS one step ahead, double buffered; every wave waits for all of its
+// copies and LDS reads before the barrier that hands a buffer over, so no ordering between
+// memory operations is assumed.  Tiles are ordered so that the workgroups one XCD runs at a
+// time share 4 row tiles (S) and a run of column tiles (X) in that XCD's L2.
+__global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_frag(int M, int ncol, int nKB, int nRT, int nCT, double alpha,
+                                                            const __bf16* __restrict__ Sf,
+                                                            const __bf16* __restrict__ Xf, double* __restrict__ C,
+                                                            ColMap cmap, const double* __restrict__ E, ColMap emap) {
+  extern __shared__ __align__(16) __bf16 fl[];  // [2][64][kFP]
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  // workgroup w runs on XCD w % 8: give each XCD a contiguous range of the tile order
+  const int G = gridDim.x, wg = blockIdx.x;
+  const int q8 = G >> 3, r8 = G & 7, xcd = wg & 7, loc = wg >> 3;
+  const int L = (xcd < r8) ? xcd * (q8 + 1) + loc : r8 * (q8 + 1) + (xcd - r8) * q8 + loc;
+  // tile order: groups of (up to) 4 row tiles, column tiles within a group
+  const int GR = nRT < 4 ? nRT : 4;
+  const int g = L / (GR * nCT), rem = L - g * GR * nCT;
+  const int gs = (nRT - g * GR) < GR ? (nRT - g * GR) : GR;
+  const int rt = g * GR + rem % gs, ct = rem / gs;
+  const int nRB = 16 * nRT, nCB = 16 * nCT;
+  const int wr = wave & 3, wc = wave >> 2;
+  auto load_step = [&](int kb, int stage) {
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      const int pc = wave + 8 * jj;  // jj < 4: S pieces (row block pc / 2, part pc % 2); else X
+      const __bf16* src =
+          jj < 4 ? Sf + (((size_t)kb * nRB + 16 * rt + (pc >> 1)) * 2 + (pc & 1)) * kFP
+                 : Xf + (((size_t)kb * nCB + 16 * ct + ((pc - 32) >> 1)) * 2 + (pc & 1)) * kFP;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + lane * 8),
+                                       (__attribute__((address_space(3))) void*)(fl + (stage * 64 + pc) * kFP), 16,
+                                       0, 0);
+    }
+  };
+  f4 acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  load_step(0, 0);
+  for (int kb = 0; kb < nKB; ++kb) {
+    const int stage = kb & 1;
+    // this wave's copies of step kb and its LDS reads of step kb - 1 done, then the barrier
+    // hands the buffers over; the empty asm statements keep memory accesses on their side
+    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (kb + 1 < nKB) load_step(kb + 1, stage ^ 1);
+    const __bf16* base = fl + stage * kFStage + lane * 8;
+    bf8 sh[4], sl[4], xh[8], xl[8];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      sh[b] = *reinterpret_cast<const bf8*>(base + (2 * (4 * wr + b)) * kFP);
+      sl[b] = *reinterpret_cast<const bf8*>(base + (2 * (4 * wr + b) + 1) * kFP);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int px = 32 + 2 * (8 * wc + a);
+      xh[a] = *reinterpret_cast<const bf8*>(base + px * kFP);
+      xl[a] = *reinterpret_cast<const bf8*>(base + (px + 1) * kFP);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xh[a], sh[b], acc[a][b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xl[a], sh[b], acc[a][b]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xh[a], sl[b], acc[a][b]);
+    }
+    // instruction order: the S pieces and the first X pair, then the 12 MFMAs of each X pair
+    // with the next pair's two LDS reads issued halfway (measured 2.02 ms per C3 product
+    // against 2.26 ms when every pair's reads wait just before its MFMAs)
+    __builtin_amdgcn_sched_group_barrier(0x100, 10, 0);
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 12, 0);
+  }
+  // acc[a][b][r] = C[i = rt 256 + 64 wr + 16 b + l % 16][j = ct 256 + 128 wc + 16 a + 4 (l / 16) + r]
+  const int i0 = rt * kFT + 64 * wr, j0 = ct * kFT + 128 * wc;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + a * 16 + 4 * (lane >> 4) + r;
+      if (j >= ncol) continue;
+      const long long co = cmap.off(j);
+      const long long eo = (E != nullptr) ? emap.off(j) : 0;
+      const double sc = alpha * cmap.colscale(j);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + b * 16 + (lane & 15);
+        if (i < M) {
+          double v = sc * (double)acc[a][b][r];
+          if (E != nullptr) v += E[eo + i];
+          C[co + i] = v;
+        }
+      }
+    }
+}
+
+static int frag_tiles(int R) { return (R + kFT - 1) / kFT; }
+
+size_t bf16_frag_elems(int R, int K) {
+  return (size_t)frag_tiles(R) * kFT * (size_t)((K + 31) / 32) * 32 * 2;
+}
+
+bool bf16x3_use_frag(int M, int ncol) {
+  const char* env = getenv("WC4D_BF16X3_KERNEL");
+  if (env != nullptr && strcmp(env, "frag") == 0) return true;
+  if (env != nullptr && strcmp(env, "tiled") == 0) return false;
+  // enough 256 x 256 tiles for two rounds of the 256 CUs (at one workgroup per CU)
+  return (long long)frag_tiles(M) * frag_tiles(ncol) >= 512;
+}
+
+hipError_t split_bf16_frag_rows(int M, int K, const double* S, long long lds, __bf16* F, hipStream_t s) {
+  const int nB = 16 * frag_tiles(M), nKB = (K + 31) / 32;
+  hipLaunchKernelGGL(k_split_bf16_frag<false>, dim3(2048), dim3(256), 0, s, M, K, nB, nKB, S, lds, plain_cols(0), F);
+  return hipGetLastError();
+}
+
+hipError_t bf16x3_set_lds_limit() {
+  return hipFuncSetAttribute((const void*)k_gemm_bf16x3_frag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             2 * kFStage * (int)sizeof(__bf16));
+}
+
+hipError_t gemm_bf16x3_frag(int M, int ncol, int K, double alpha, const __bf16* Sf, const double* B, ColMap bmap,
+                            __bf16* Xf, double* C, ColMap cmap, const double* E, ColMap emap, hipStream_t s) {
+  if (M <= 0 || ncol <= 0) return hipSuccess;
+  const int nRT = frag_tiles(M), nCT = frag_tiles(ncol), nKB = (K + 31) / 32;
+  hipLaunchKernelGGL(k_split_bf16_frag<true>, dim3(4096), dim3(256), 0, s, ncol, K, 16 * nCT, nKB, B, 0LL, bmap,
+                     Xf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gemm_bf16x3_frag, dim3(nRT * nCT), dim3(512), 2 * kFStage * sizeof(__bf16), s, M, ncol, nKB,
+                     nRT, nCT, alpha, Sf, Xf, C, cmap, E, emap);
   return hipGetLastError();
 }
 

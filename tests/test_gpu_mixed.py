@@ -42,10 +42,21 @@ MEDIUM = Workload(name="adv_n700_N30", model="advdiff", n=700, N=30, c=0.5, r=0.
                   sigma_o2=0.01, m=40, l=5, seed=9100)
 
 
-@pytest.mark.parametrize("w", [C1, C2, MEDIUM], ids=["C1", "C2", "adv700"])
-def test_bf16x3_apply_error(w):
+# B^{1/2} and Q^{1/2} with different length scales: level 0 takes its own product
+MEDIUM_BQ = Workload(name="adv_n700_N30_LbLq", model="advdiff", n=700, N=30, c=0.5, r=0.1, corr="soar", Lb=6.0,
+                     Lq=3.0, sigma_b=1.0, sigma_q=0.1, obs_var_stride=4, obs_time_stride=2,
+                     sigma_o2=0.01, m=40, l=5, seed=9200)
+
+
+# kernel: the size rule ("auto": the LDS-tiled kernel at these sizes) or the fragment-major
+# kernel forced on ragged shapes (n = 40, 80, 700 rows and K; 220 to 3100 columns)
+@pytest.mark.parametrize("kernel", ["auto", "frag"])
+@pytest.mark.parametrize("w", [C1, C2, MEDIUM, MEDIUM_BQ], ids=["C1", "C2", "adv700", "adv700_LbLq"])
+def test_bf16x3_apply_error(w, kernel, monkeypatch):
     from paper_2101_07249_amd import wc4d
-    print("[case] bf16x3 apply", w.name, flush=True)
+    print("[case] bf16x3 apply", w.name, kernel, flush=True)
+    if kernel != "auto":
+        monkeypatch.setenv("WC4D_BF16X3_KERNEL", kernel)
     gp, op = _pair(w, wc4d.PREC_SKETCH_BF16X3)
     G = sketch_block(op.n_A, w.m, w.seed)
     Yo = O.apply_A(op, G)
