@@ -60,7 +60,11 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *   WC4D_PREC_SKETCH_BF16X3: the D^{1/2} products of the block applies inside
  *     wc4d_lmp_build run as three bfloat16 MFMA products with float32 accumulation
  *     (S_hi X_hi + S_hi X_lo + S_lo X_hi, S = S_hi + S_lo); CholeskyQR2, the m x m
- *     eigenproblem and everything in wc4d_pcg stay float64.
+ *     eigenproblem and everything in wc4d_pcg stay float64.  Products with at least 512
+ *     output tiles of 256 x 256 take a kernel on operands pre-split into MFMA operand
+ *     pieces (a workspace of 4 bytes per block entry that the problem keeps), the others an
+ *     LDS-tiled kernel; both give the same bits.  The environment variable
+ *     WC4D_BF16X3_KERNEL=frag or =tiled, read at each product, forces one of them.
  *   WC4D_PREC_SKETCH_FP16X3: the same three products in float16 (11 significant bits
  *     per part instead of 8), with power-of-two scaling per row of S and per column of X
  *     (largest magnitude brought to [2^14, 2^15)) so that the parts fit float16's range;
