@@ -63,8 +63,9 @@ enum { WC4D_RES_TRUE = 0, WC4D_RES_PRECOND = 1 };
  *     eigenproblem and everything in wc4d_pcg stay float64.  Products with at least 512
  *     output tiles of 256 x 256 take a kernel on operands pre-split into MFMA operand
  *     pieces (a workspace of 4 bytes per block entry that the problem keeps), the others an
- *     LDS-tiled kernel; both give the same bits.  The environment variable
- *     WC4D_BF16X3_KERNEL=frag or =tiled, read at each product, forces one of them.
+ *     LDS-tiled kernel; both give the same bits (the same holds for the float16 form below).
+ *     The environment variable WC4D_SPLIT_GEMM_KERNEL=frag or =tiled, read at each product,
+ *     forces one of them.
  *   WC4D_PREC_SKETCH_FP16X3: the same three products in float16 (11 significant bits
  *     per part instead of 8), with power-of-two scaling per row of S and per column of X
  *     (largest magnitude brought to [2^14, 2^15)) so that the parts fit float16's range;

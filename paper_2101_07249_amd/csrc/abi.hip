@@ -144,6 +144,7 @@ int wc4d_destroy(wc4d_problem p) {
   dev_free(&p->dQhi);
   dev_free(&p->dQlo);
   dev_free(&p->dQf);
+  dev_free(&p->dQf16);
   dev_free(&p->dXf);
   p->xfCap = 0;
   dev_free(&p->dStages);
@@ -393,7 +394,7 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
     HIPCHK(p, split_bf16_rows(n, n, p->dB, n, p->dBhi, p->dBlo, s));
     HIPCHK(p, split_bf16_rows(n, n, p->dQ, n, p->dQhi, p->dQlo, s));
     if ((rc = dev_alloc(p, &p->dQf, bf16_frag_elems(n, n)))) return rc;
-    HIPCHK(p, bf16x3_set_lds_limit());
+    HIPCHK(p, split_frag_set_lds_limit());
     HIPCHK(p, split_bf16_frag_rows(n, n, p->dQ, n, p->dQf, s));
   }
   if (prec_mode & WC4D_PREC_SKETCH_FP16X3) {
@@ -404,6 +405,9 @@ int wc4d_finalize(wc4d_problem p, int prec_mode, hipStream_t s) {
       return rc;
     HIPCHK(p, split_f16_rows(n, n, p->dB, n, p->dBh16, p->dBl16, p->dBexp, s));
     HIPCHK(p, split_f16_rows(n, n, p->dQ, n, p->dQh16, p->dQl16, p->dQexp, s));
+    if ((rc = dev_alloc(p, &p->dQf16, bf16_frag_elems(n, n)))) return rc;
+    HIPCHK(p, split_frag_set_lds_limit());
+    HIPCHK(p, split_f16_frag_rows(n, n, p->dQ, n, p->dQexp, p->dQf16, s));
   }
   if ((rc = dev_alloc(p, &p->dStatus, 16))) return rc;
   // split-K partials: up to 512 workgroups' worth of n x 112 tiles
@@ -526,43 +530,50 @@ namespace {
 int dsqrt_apply(wc4d_problem p, const double* X, long long ldx, double* Y, long long ldy, int m,
                 const double* E, long long lde, const int* skip, hipStream_t s, int mixed = SPLIT_NONE) {
   const int n = p->n, N = p->N;
-  if (mixed == SPLIT_FP16) {
-    const size_t need = (size_t)m * (N + 1);
-    if (p->colExpCap < need) {
-      int rc = dev_alloc(p, &p->dColExp, need);
-      if (rc) return rc;
-      p->colExpCap = need;
+  if (mixed == SPLIT_FP16 || mixed == SPLIT_BF16) {
+    const bool f16 = mixed == SPLIT_FP16;
+    if (f16) {  // column exponents of the right operand, all levels
+      const size_t need = (size_t)m * (N + 1);
+      if (p->colExpCap < need) {
+        int rc = dev_alloc(p, &p->dColExp, need);
+        if (rc) return rc;
+        p->colExpCap = need;
+      }
     }
-    HIPCHK(p, gemm_fp16x3(n, m, n, 1.0, p->dBh16, p->dBl16, p->dBexp, X, ColMap{ldx, 1, 0, n}, p->dColExp, Y,
-                          ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
-    HIPCHK(p, gemm_fp16x3(n, m * N, n, 1.0, p->dQh16, p->dQl16, p->dQexp, X, ColMap{ldx, N, 1, n},
-                          p->dColExp + m, Y, ColMap{ldy, N, 1, n}, E, ColMap{lde, N, 1, n}, s));
-    return WC4D_OK;
-  }
-  if (mixed == SPLIT_BF16) {
-    // products with Q^{1/2}: the fragment-major kernel when the shape has enough tiles
-    auto q_product = [&](int ncol, ColMap xm, ColMap ym, ColMap em) -> int {
-      if (!bf16x3_use_frag(n, ncol)) {
-        HIPCHK(p, gemm_bf16x3(n, ncol, n, 1.0, p->dQhi, p->dQlo, X, xm, Y, ym, E, em, s));
+    // products with Q^{1/2} (columns c0 .. of the exponent workspace): the fragment-major
+    // kernel when the shape has enough tiles, else the LDS-tiled one
+    auto q_product = [&](int ncol, ColMap xm, ColMap ym, ColMap em, int c0) -> int {
+      if (!split_use_frag(n, ncol)) {
+        if (f16)
+          HIPCHK(p, gemm_fp16x3(n, ncol, n, 1.0, p->dQh16, p->dQl16, p->dQexp, X, xm, p->dColExp + c0, Y, ym, E,
+                                em, s));
+        else
+          HIPCHK(p, gemm_bf16x3(n, ncol, n, 1.0, p->dQhi, p->dQlo, X, xm, Y, ym, E, em, s));
         return WC4D_OK;
       }
       const size_t need = bf16_frag_elems(ncol, n);
       if (p->xfCap < need) {
-        dev_free(&p->dXf);
-        p->xfCap = 0;
         int rc = dev_alloc(p, &p->dXf, need);
         if (rc) return rc;
         p->xfCap = need;
       }
-      HIPCHK(p, gemm_bf16x3_frag(n, ncol, n, 1.0, p->dQf, X, xm, p->dXf, Y, ym, E, em, s));
+      if (f16)
+        HIPCHK(p, gemm_fp16x3_frag(n, ncol, n, 1.0, p->dQf16, p->dQexp, X, xm, p->dColExp + c0,
+                                   reinterpret_cast<_Float16*>(p->dXf), Y, ym, E, em, s));
+      else
+        HIPCHK(p, gemm_bf16x3_frag(n, ncol, n, 1.0, p->dQf, X, xm, p->dXf, Y, ym, E, em, s));
       return WC4D_OK;
     };
     if (p->scaledB)  // all levels in one product with Q^{1/2}, level 0 scaled by c in the epilogue
       return q_product(m * (N + 1), ColMap{ldx, N + 1, 0, n}, ColMap{ldy, N + 1, 0, n, p->bScale},
-                       ColMap{lde, N + 1, 0, n});
-    HIPCHK(p, gemm_bf16x3(n, m, n, 1.0, p->dBhi, p->dBlo, X, ColMap{ldx, 1, 0, n}, Y,
-                          ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
-    return q_product(m * N, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n}, ColMap{lde, N, 1, n});
+                       ColMap{lde, N + 1, 0, n}, 0);
+    if (f16)
+      HIPCHK(p, gemm_fp16x3(n, m, n, 1.0, p->dBh16, p->dBl16, p->dBexp, X, ColMap{ldx, 1, 0, n}, p->dColExp, Y,
+                            ColMap{ldy, 1, 0, n}, E, ColMap{lde, 1, 0, n}, s));
+    else
+      HIPCHK(p, gemm_bf16x3(n, m, n, 1.0, p->dBhi, p->dBlo, X, ColMap{ldx, 1, 0, n}, Y, ColMap{ldy, 1, 0, n}, E,
+                            ColMap{lde, 1, 0, n}, s));
+    return q_product(m * N, ColMap{ldx, N, 1, n}, ColMap{ldy, N, 1, n}, ColMap{lde, N, 1, n}, m);
   }
   if (m == 1 && p->ozSs != nullptr) {
     // one vector: all levels in one int8-sliced product with Q^{1/2}, level 0 scaled by c

@@ -5,13 +5,14 @@
 // and the bfloat16 rounding of the low parts are O(2^-16) relative; the float32 sum
 // over K adds O(sqrt(K) 2^-24).
 //
-// Two kernels.  The LDS-tiled one (k_gemm_bf16x3): S is pre-split once (split_bf16_rows)
-// into two row-major bf16 arrays (row i holds S(i, 0..K-1) contiguously), so an MFMA operand
-// row is one 16-byte load, and X is split while it is staged into LDS.  The fragment-major
-// one (k_gemm_bf16x3_frag, products with many 256 x 256 tiles such as the sketch block's
-// all-level product): both operands are pre-split into 1 KB MFMA operand pieces that are
-// copied global -> LDS without passing through registers (layout below).  Both form the same
-// three products in the same K order, so they give the same bits.
+// Two kernels for each form.  The LDS-tiled ones (k_gemm_bf16x3, k_gemm_fp16x3): S is
+// pre-split once (split_bf16_rows, split_f16_rows) into two row-major arrays (row i holds
+// S(i, 0..K-1) contiguously), so an MFMA operand row is one 16-byte load, and X is split
+// while it is staged into LDS.  The fragment-major one (k_gemm_x3_frag, products with many
+// 256 x 256 tiles such as the sketch block's all-level product): both operands are pre-split
+// into 1 KB MFMA operand pieces that are copied global -> LDS without passing through
+// registers (layout below).  Both form the same three products in the same K order, so they
+// give the same bits.
 //
 // The float16 form (gemm_fp16x3) has 11 significant bits per part instead of 8 but a
 // narrow exponent range, so both operands are scaled by powers of two: row i of S by
@@ -432,7 +433,8 @@ hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, 
 
 
 // ---- fragment-major form for large products (the sketch block's all-level D^{1/2} product).
-// Both operands are split once per call (S once per problem) into bf16 hi/lo parts stored as
+// Both operands are split (S once per problem, X per call) into bf16 hi/lo parts, or for the
+// float16 form into scaled float16 hi/lo parts with the row / column exponents above, stored as
 // 1 KB pieces in the MFMA operand order: piece (kb, blk, part) holds the 16 rows (columns of X)
 // 16 blk .. + 16 and K 32 kb .. + 32, lane l's 8 values (row 16 blk + l % 16, K 32 kb + 8 (l / 16)
 // + e) at 8 l; pieces ordered [kb][blk][part], rows / columns padded with zeros to a multiple
@@ -440,13 +442,33 @@ hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, 
 // the load-to-LDS instruction (no registers, no LDS writes by the waves) and every lane's
 // operand read is one conflict-free 16-byte LDS load.
 constexpr int kFT = 256;  // tile rows and columns
-constexpr int kFP = 512;  // bf16 per piece
+constexpr int kFP = 512;  // 16-bit values per piece
 constexpr int kFStage = 64 * kFP;  // one K step: 16 row blocks x 2 parts, then 16 column blocks x 2 parts
 
-// A(r, k) = XCOL ? A[amap.off(r) + k] : A[r + k lda], for r < R, k < K; zero outside.
-template <bool XCOL>
-__global__ __launch_bounds__(256) void k_split_bf16_frag(int R, int K, int nB, int nKB, const double* __restrict__ A,
-                                                         long long lda, ColMap amap, __bf16* __restrict__ F) {
+// the two 16-bit forms: element and operand types, the MFMA, and the hi/lo split (the
+// float16 form scales by 2^-e first)
+template <bool F16> struct Frag;
+template <> struct Frag<false> {
+  typedef __bf16 E;
+  typedef bf8 V;
+  static __device__ inline f4 mfma(V a, V b, f4 c) { return mfma_bf16(a, b, c); }
+  static __device__ inline void split(double x, int, E& h, E& l) { split2(x, h, l); }
+};
+template <> struct Frag<true> {
+  typedef _Float16 E;
+  typedef h8 V;
+  static __device__ inline f4 mfma(V a, V b, f4 c) { return mfma_f16(a, b, c); }
+  static __device__ inline void split(double x, int e, E& h, E& l) { split_f16(x, e, h, l); }
+};
+
+// A(r, k) = XCOL ? A[amap.off(r) + k] : A[r + k lda], for r < R, k < K; zero outside.  exps
+// (float16 form): the exponent of each r.
+template <bool XCOL, bool F16>
+__global__ __launch_bounds__(256) void k_split_frag(int R, int K, int nB, int nKB, const double* __restrict__ A,
+                                                    long long lda, ColMap amap, const int* __restrict__ exps,
+                                                    typename Frag<F16>::E* __restrict__ F) {
+  typedef typename Frag<F16>::E Et;
+  typedef typename Frag<F16>::V Vt;
   const long long tot = (long long)nB * nKB * 64;
   for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += (long long)gridDim.x * blockDim.x) {
@@ -455,7 +477,9 @@ __global__ __launch_bounds__(256) void k_split_bf16_frag(int R, int K, int nB, i
     const int blk = (int)(P / nKB), kb = (int)(P - (long long)blk * nKB);
     const int r = 16 * blk + (lane & 15), k0 = 32 * kb + 8 * (lane >> 4);
     double v[8];
+    int ex = 0;
     if (r < R) {
+      if (F16) ex = exps[r];
       if (XCOL) {
         const double* col = A + amap.off(r);
         if (k0 + 8 <= K && (reinterpret_cast<uintptr_t>(col + k0) & 15) == 0) {
@@ -477,17 +501,17 @@ __global__ __launch_bounds__(256) void k_split_bf16_frag(int R, int K, int nB, i
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[e] = 0.0;
     }
-    bf8 h, l;
+    Vt h, l;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      __bf16 a, b;
-      split2(v[e], a, b);
+      Et a, b;
+      Frag<F16>::split(v[e], ex, a, b);
       h[e] = a;
       l[e] = b;
     }
-    __bf16* dst = F + ((size_t)kb * nB + blk) * 2 * kFP + (size_t)lane * 8;
-    *reinterpret_cast<bf8*>(dst) = h;
-    *reinterpret_cast<bf8*>(dst + kFP) = l;
+    Et* dst = F + ((size_t)kb * nB + blk) * 2 * kFP + (size_t)lane * 8;
+    *reinterpret_cast<Vt*>(dst) = h;
+    *reinterpret_cast<Vt*>(dst + kFP) = l;
   }
 }
 
@@ -497,12 +521,19 @@ __global__ __launch_bounds__(256) void k_split_bf16_frag(int R, int K, int nB, i
 // (64 KB) are copied into LDS one step ahead, double buffered; every wave waits for all of its
 // copies and LDS reads before the barrier that hands a buffer over, so no ordering between
 // memory operations is assumed.  Tiles are ordered so that the workgroups one XCD runs at a
-// time share 4 row tiles (S) and a run of column tiles (X) in that XCD's L2.
-__global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_frag(int M, int ncol, int nKB, int nRT, int nCT, double alpha,
-                                                            const __bf16* __restrict__ Sf,
-                                                            const __bf16* __restrict__ Xf, double* __restrict__ C,
-                                                            ColMap cmap, const double* __restrict__ E, ColMap emap) {
-  extern __shared__ __align__(16) __bf16 fl[];  // [2][64][kFP]
+// time share 4 row tiles (S) and a run of column tiles (X) in that XCD's L2.  The float16 form
+// scales each output by 2^(rowexp_i + colexp_j).
+template <bool F16>
+__global__ __launch_bounds__(512, 1) void k_gemm_x3_frag(int M, int ncol, int nKB, int nRT, int nCT, double alpha,
+                                                        const typename Frag<F16>::E* __restrict__ Sf,
+                                                        const typename Frag<F16>::E* __restrict__ Xf,
+                                                        const int* __restrict__ rowexp,
+                                                        const int* __restrict__ colexp, double* __restrict__ C,
+                                                        ColMap cmap, const double* __restrict__ E, ColMap emap) {
+  typedef typename Frag<F16>::E Et;
+  typedef typename Frag<F16>::V Vt;
+  extern __shared__ __align__(16) char flb[];  // [2][64][kFP] 16-bit values
+  Et* fl = reinterpret_cast<Et*>(flb);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   // workgroup w runs on XCD w % 8: give each XCD a contiguous range of the tile order
@@ -520,9 +551,8 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_frag(int M, int ncol, in
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) {
       const int pc = wave + 8 * jj;  // jj < 4: S pieces (row block pc / 2, part pc % 2); else X
-      const __bf16* src =
-          jj < 4 ? Sf + (((size_t)kb * nRB + 16 * rt + (pc >> 1)) * 2 + (pc & 1)) * kFP
-                 : Xf + (((size_t)kb * nCB + 16 * ct + ((pc - 32) >> 1)) * 2 + (pc & 1)) * kFP;
+      const Et* src = jj < 4 ? Sf + (((size_t)kb * nRB + 16 * rt + (pc >> 1)) * 2 + (pc & 1)) * kFP
+                             : Xf + (((size_t)kb * nCB + 16 * ct + ((pc - 32) >> 1)) * 2 + (pc & 1)) * kFP;
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + lane * 8),
                                        (__attribute__((address_space(3))) void*)(fl + (stage * 64 + pc) * kFP), 16,
                                        0, 0);
@@ -543,27 +573,27 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_frag(int M, int ncol, in
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     if (kb + 1 < nKB) load_step(kb + 1, stage ^ 1);
-    const __bf16* base = fl + stage * kFStage + lane * 8;
-    bf8 sh[4], sl[4], xh[8], xl[8];
+    const Et* base = fl + stage * kFStage + lane * 8;
+    Vt sh[4], sl[4], xh[8], xl[8];
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      sh[b] = *reinterpret_cast<const bf8*>(base + (2 * (4 * wr + b)) * kFP);
-      sl[b] = *reinterpret_cast<const bf8*>(base + (2 * (4 * wr + b) + 1) * kFP);
+      sh[b] = *reinterpret_cast<const Vt*>(base + (2 * (4 * wr + b)) * kFP);
+      sl[b] = *reinterpret_cast<const Vt*>(base + (2 * (4 * wr + b) + 1) * kFP);
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int px = 32 + 2 * (8 * wc + a);
-      xh[a] = *reinterpret_cast<const bf8*>(base + px * kFP);
-      xl[a] = *reinterpret_cast<const bf8*>(base + (px + 1) * kFP);
+      xh[a] = *reinterpret_cast<const Vt*>(base + px * kFP);
+      xl[a] = *reinterpret_cast<const Vt*>(base + (px + 1) * kFP);
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xh[a], sh[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) acc[a][b] = Frag<F16>::mfma(xh[a], sh[b], acc[a][b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xl[a], sh[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) acc[a][b] = Frag<F16>::mfma(xl[a], sh[b], acc[a][b]);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = mfma_bf16(xh[a], sl[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) acc[a][b] = Frag<F16>::mfma(xh[a], sl[b], acc[a][b]);
     }
     // instruction order: the S pieces and the first X pair, then the 12 MFMAs of each X pair
     // with the next pair's two LDS reads issued halfway (measured 2.02 ms per C3 product
@@ -588,11 +618,14 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16x3_frag(int M, int ncol, in
       const long long co = cmap.off(j);
       const long long eo = (E != nullptr) ? emap.off(j) : 0;
       const double sc = alpha * cmap.colscale(j);
+      const int ej = F16 ? colexp[j] : 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int i = i0 + b * 16 + (lane & 15);
         if (i < M) {
-          double v = sc * (double)acc[a][b][r];
+          double v = (double)acc[a][b][r];
+          if (F16) v = ldexp(v, rowexp[i] + ej);
+          v *= sc;
           if (E != nullptr) v += E[eo + i];
           C[co + i] = v;
         }
@@ -606,8 +639,8 @@ size_t bf16_frag_elems(int R, int K) {
   return (size_t)frag_tiles(R) * kFT * (size_t)((K + 31) / 32) * 32 * 2;
 }
 
-bool bf16x3_use_frag(int M, int ncol) {
-  const char* env = getenv("WC4D_BF16X3_KERNEL");
+bool split_use_frag(int M, int ncol) {
+  const char* env = getenv("WC4D_SPLIT_GEMM_KERNEL");
   if (env != nullptr && strcmp(env, "frag") == 0) return true;
   if (env != nullptr && strcmp(env, "tiled") == 0) return false;
   // enough 256 x 256 tiles for two rounds of the 256 CUs (at one workgroup per CU)
@@ -616,25 +649,53 @@ bool bf16x3_use_frag(int M, int ncol) {
 
 hipError_t split_bf16_frag_rows(int M, int K, const double* S, long long lds, __bf16* F, hipStream_t s) {
   const int nB = 16 * frag_tiles(M), nKB = (K + 31) / 32;
-  hipLaunchKernelGGL(k_split_bf16_frag<false>, dim3(2048), dim3(256), 0, s, M, K, nB, nKB, S, lds, plain_cols(0), F);
+  hipLaunchKernelGGL((k_split_frag<false, false>), dim3(2048), dim3(256), 0, s, M, K, nB, nKB, S, lds, plain_cols(0),
+                     nullptr, F);
   return hipGetLastError();
 }
 
-hipError_t bf16x3_set_lds_limit() {
-  return hipFuncSetAttribute((const void*)k_gemm_bf16x3_frag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             2 * kFStage * (int)sizeof(__bf16));
+hipError_t split_f16_frag_rows(int M, int K, const double* S, long long lds, const int* rowexp, _Float16* F,
+                               hipStream_t s) {
+  const int nB = 16 * frag_tiles(M), nKB = (K + 31) / 32;
+  hipLaunchKernelGGL((k_split_frag<false, true>), dim3(2048), dim3(256), 0, s, M, K, nB, nKB, S, lds, plain_cols(0),
+                     rowexp, F);
+  return hipGetLastError();
+}
+
+hipError_t split_frag_set_lds_limit() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_gemm_x3_frag<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     2 * kFStage * 2);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_gemm_x3_frag<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * kFStage * 2);
+  return e;
 }
 
 hipError_t gemm_bf16x3_frag(int M, int ncol, int K, double alpha, const __bf16* Sf, const double* B, ColMap bmap,
                             __bf16* Xf, double* C, ColMap cmap, const double* E, ColMap emap, hipStream_t s) {
   if (M <= 0 || ncol <= 0) return hipSuccess;
   const int nRT = frag_tiles(M), nCT = frag_tiles(ncol), nKB = (K + 31) / 32;
-  hipLaunchKernelGGL(k_split_bf16_frag<true>, dim3(4096), dim3(256), 0, s, ncol, K, 16 * nCT, nKB, B, 0LL, bmap,
-                     Xf);
+  hipLaunchKernelGGL((k_split_frag<true, false>), dim3(4096), dim3(256), 0, s, ncol, K, 16 * nCT, nKB, B, 0LL, bmap,
+                     nullptr, Xf);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gemm_bf16x3_frag, dim3(nRT * nCT), dim3(512), 2 * kFStage * sizeof(__bf16), s, M, ncol, nKB,
-                     nRT, nCT, alpha, Sf, Xf, C, cmap, E, emap);
+  hipLaunchKernelGGL(k_gemm_x3_frag<false>, dim3(nRT * nCT), dim3(512), 2 * kFStage * 2, s, M, ncol, nKB, nRT, nCT,
+                     alpha, Sf, Xf, nullptr, nullptr, C, cmap, E, emap);
+  return hipGetLastError();
+}
+
+hipError_t gemm_fp16x3_frag(int M, int ncol, int K, double alpha, const _Float16* Sf, const int* rowexp,
+                            const double* B, ColMap bmap, int* colexp, _Float16* Xf, double* C, ColMap cmap,
+                            const double* E, ColMap emap, hipStream_t s) {
+  if (M <= 0 || ncol <= 0) return hipSuccess;
+  const int nRT = frag_tiles(M), nCT = frag_tiles(ncol), nKB = (K + 31) / 32;
+  hipLaunchKernelGGL(k_col_exponents, dim3(ncol < 4096 ? ncol : 4096), dim3(256), 0, s, ncol, K, B, bmap, colexp);
+  hipLaunchKernelGGL((k_split_frag<true, true>), dim3(4096), dim3(256), 0, s, ncol, K, 16 * nCT, nKB, B, 0LL, bmap,
+                     colexp, Xf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gemm_x3_frag<true>, dim3(nRT * nCT), dim3(512), 2 * kFStage * 2, s, M, ncol, nKB, nRT, nCT,
+                     alpha, Sf, Xf, rowexp, colexp, C, cmap, E, emap);
   return hipGetLastError();
 }
 

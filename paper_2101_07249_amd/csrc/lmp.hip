@@ -390,12 +390,14 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
 // totals go out column-major (part[c G + b], G workgroups) scaled back by 2^cexp[c].  With
 // pdot (PCG) every workgroup also sums pdot . x over its rows into dotpart[b].  Used with
 // JC = 4 columns per half-wave per chunk (8 converted columns per lane would take all the
-// registers: the compiler converts a chunk's halves to double before its FMAs).  Inside the
+// registers: the compiler converts a chunk's halves to double before its FMAs) and QU = 2
+// panels' loads in flight (inside the PCG at C3: 44.9 us per pass with its final sum against
+// 47.5 us for one panel at a time; 4 panels 45.8 us).  Inside the
 // PCG at n_A = 413,696, k = 251: 45.2 us with 4 panels per workgroup, against 53.1 us for 16
 // columns x 2 rows per thread (x re-read by every column group); JC = 2 with 2 panels
 // each ran 46.3 us, shapes whose grid is not resident at once 55-60 us.
 constexpr int kXP = 4;
-template <int JC>
+template <int JC, int QU>
 __global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k, long long pan_per,
                                                              const _Float16* __restrict__ P,
                                                              const int* __restrict__ cexp,
@@ -435,24 +437,35 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k
 #pragma unroll
       for (int j = 0; j < JC; ++j) aj[j] = 0.0;
 #pragma unroll 1
-      for (int q = 0; q < ng; ++q) {
-        const _Float16* Pp = P + (size_t)(g0 + q) * kPanel * k + r8;
-        // columns past k read column k - 1; their sums are never written out
-        h8 u[JC];
+      for (int q0 = 0; q0 < ng; q0 += QU) {
+        // QU panels' loads in flight before their products; columns past k read column
+        // k - 1 (their sums are never written out), panels past ng are skipped
+        h8 u[QU][JC];
 #pragma unroll
-        for (int j = 0; j < JC; ++j) {
-          const int c = min(cc + g + 8 * j, k - 1);
-          u[j] = *reinterpret_cast<const h8*>(Pp + (size_t)c * kPanel);
+        for (int qq = 0; qq < QU; ++qq) {
+          if (q0 + qq < ng) {
+            const _Float16* Pp = P + (size_t)(g0 + q0 + qq) * kPanel * k + r8;
+#pragma unroll
+            for (int j = 0; j < JC; ++j) {
+              const int c = min(cc + g + 8 * j, k - 1);
+              u[qq][j] = *reinterpret_cast<const h8*>(Pp + (size_t)c * kPanel);
+            }
+          }
         }
-        double xr[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xr[e] = xs[q][r8 + e];
+        for (int qq = 0; qq < QU; ++qq) {
+          if (q0 + qq < ng) {
+            double xr[8];
 #pragma unroll
-        for (int j = 0; j < JC; ++j) {
-          double a = 0.0;
+            for (int e = 0; e < 8; ++e) xr[e] = xs[q0 + qq][r8 + e];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) a += (double)(float)u[j][e] * xr[e];
-          aj[j] += a;
+            for (int j = 0; j < JC; ++j) {
+              double a = 0.0;
+#pragma unroll
+              for (int e = 0; e < 8; ++e) a += (double)(float)u[qq][j][e] * xr[e];
+              aj[j] += a;
+            }
+          }
         }
       }
       // butterfly from width 16 down: a lane keeps the lower (bit clear) or upper half of its
@@ -541,7 +554,7 @@ static int launch_pan_t_partial(long long nA, int k, const LmpU& U, const double
                                 long long* sb, long long* sc) {
   if (U.fmt == LMP_P16) {
     const int G = rows_grid(nA);
-    hipLaunchKernelGGL(k_lmp_pan_t16_rows<4>, dim3(G), dim3(kPanel), 0, s, nA, k, rows_pan_per(nA),
+    hipLaunchKernelGGL((k_lmp_pan_t16_rows<4, 2>), dim3(G), dim3(kPanel), 0, s, nA, k, rows_pan_per(nA),
                        (const _Float16*)U.p, U.cexp, x, part, skip, pdot, dotpart);
     *sb = 1;
     *sc = G;

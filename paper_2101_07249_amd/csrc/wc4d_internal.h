@@ -106,19 +106,26 @@ hipError_t oz_set_lds_limit();
 hipError_t gemm_bf16x3(int M, int ncol, int K, double alpha, const __bf16* Shi, const __bf16* Slo,
                        const double* B, ColMap bmap, double* C, ColMap cmap, const double* E,
                        ColMap emap, hipStream_t s);
-// Fragment-major form for products with many 256 x 256 tiles (see gemm_bf16x3.hip):
-// split_bf16_frag_rows splits S (M x K, column-major, ld lds) once into F
-// (bf16_frag_elems(M, K) elements); gemm_bf16x3_frag splits the columns of X into Xf
-// (bf16_frag_elems(ncol, K) elements of workspace) and forms C = alpha S X [+ E], with
-// cmap.colscale applied.  bf16x3_use_frag: whether a product of that shape takes this form
-// (environment WC4D_BF16X3_KERNEL=frag|tiled overrides the size rule).  bf16x3_set_lds_limit:
-// once per process before the first gemm_bf16x3_frag (its LDS exceeds the 64 KB default).
+// Fragment-major forms for products with many 256 x 256 tiles (see gemm_bf16x3.hip):
+// split_bf16_frag_rows / split_f16_frag_rows split S (M x K, column-major, ld lds; the
+// float16 form with the row exponents of split_f16_rows) once into F (bf16_frag_elems(M, K)
+// elements); gemm_bf16x3_frag / gemm_fp16x3_frag split the columns of X into Xf
+// (bf16_frag_elems(ncol, K) elements of workspace; the float16 form first fills colexp, ncol
+// ints) and form C = alpha S X [+ E], with cmap.colscale applied.  split_use_frag: whether a
+// product of that shape takes these forms (environment WC4D_SPLIT_GEMM_KERNEL=frag|tiled
+// overrides the size rule).  split_frag_set_lds_limit: once per process before the first
+// fragment-major product (its LDS exceeds the 64 KB default).
 size_t bf16_frag_elems(int R, int K);
-bool bf16x3_use_frag(int M, int ncol);
+bool split_use_frag(int M, int ncol);
 hipError_t split_bf16_frag_rows(int M, int K, const double* S, long long lds, __bf16* F, hipStream_t s);
+hipError_t split_f16_frag_rows(int M, int K, const double* S, long long lds, const int* rowexp, _Float16* F,
+                               hipStream_t s);
 hipError_t gemm_bf16x3_frag(int M, int ncol, int K, double alpha, const __bf16* Sf, const double* B, ColMap bmap,
                             __bf16* Xf, double* C, ColMap cmap, const double* E, ColMap emap, hipStream_t s);
-hipError_t bf16x3_set_lds_limit();
+hipError_t gemm_fp16x3_frag(int M, int ncol, int K, double alpha, const _Float16* Sf, const int* rowexp,
+                            const double* B, ColMap bmap, int* colexp, _Float16* Xf, double* C, ColMap cmap,
+                            const double* E, ColMap emap, hipStream_t s);
+hipError_t split_frag_set_lds_limit();
 // Float16 form: S split per row with power-of-two row exponents (rowexp, M ints), X per
 // column (colexp: ncol ints of workspace, filled by the call).  See gemm_bf16x3.hip.
 hipError_t split_f16_rows(int M, int K, const double* S, long long lds, _Float16* Shi, _Float16* Slo, int* rowexp,
@@ -431,7 +438,9 @@ struct wc4d_problem_s {
   __bf16* dQhi = nullptr;
   __bf16* dQlo = nullptr;
   __bf16* dQf = nullptr;      // fragment-major split-bf16 Q^{1/2} (large products)
-  __bf16* dXf = nullptr;      // fragment-major split of a product's right operand (workspace)
+  _Float16* dQf16 = nullptr;  // the same in split float16 (scaled rows)
+  __bf16* dXf = nullptr;      // fragment-major split of a product's right operand (workspace,
+                              // 16-bit values of either form)
   size_t xfCap = 0;
   _Float16* dBh16 = nullptr;  // split-float16 B^{1/2}, Q^{1/2} (row-major, scaled rows), when prec has FP16X3
   _Float16* dBl16 = nullptr;

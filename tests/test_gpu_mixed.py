@@ -56,7 +56,7 @@ def test_bf16x3_apply_error(w, kernel, monkeypatch):
     from paper_2101_07249_amd import wc4d
     print("[case] bf16x3 apply", w.name, kernel, flush=True)
     if kernel != "auto":
-        monkeypatch.setenv("WC4D_BF16X3_KERNEL", kernel)
+        monkeypatch.setenv("WC4D_SPLIT_GEMM_KERNEL", kernel)
     gp, op = _pair(w, wc4d.PREC_SKETCH_BF16X3)
     G = sketch_block(op.n_A, w.m, w.seed)
     Yo = O.apply_A(op, G)
@@ -260,10 +260,13 @@ def test_fp16_copy_keeps_c_positive_definite():
 # columns of X): per part 11 significant bits, so the dropped Sl Xl term is ~2^-22 relative
 # and the float32 sums over K = n add ~sqrt(n) 2^-24; the bound used is 1e-5 (the bfloat16
 # form's is 1e-4), and the float16 form must be the more accurate of the two.
-@pytest.mark.parametrize("w", [C1, C2, MEDIUM], ids=["C1", "C2", "adv700"])
-def test_fp16x3_apply_error(w):
+@pytest.mark.parametrize("kernel", ["auto", "frag"])
+@pytest.mark.parametrize("w", [C1, C2, MEDIUM, MEDIUM_BQ], ids=["C1", "C2", "adv700", "adv700_LbLq"])
+def test_fp16x3_apply_error(w, kernel, monkeypatch):
     from paper_2101_07249_amd import wc4d
-    print("[case] fp16x3 apply", w.name, flush=True)
+    print("[case] fp16x3 apply", w.name, kernel, flush=True)
+    if kernel != "auto":
+        monkeypatch.setenv("WC4D_SPLIT_GEMM_KERNEL", kernel)
     gh, op = _pair(w, wc4d.PREC_SKETCH_FP16X3)
     gb, _ = _pair(w, wc4d.PREC_SKETCH_BF16X3)
     G = sketch_block(op.n_A, w.m, w.seed)
@@ -277,12 +280,15 @@ def test_fp16x3_apply_error(w):
     assert e_h < e_b
 
 
-def test_fp16x3_scaling_extremes_and_zero_column():
+@pytest.mark.parametrize("kernel", ["auto", "frag"])
+def test_fp16x3_scaling_extremes_and_zero_column(kernel, monkeypatch):
     """Column exponents follow the data: blocks scaled by 1e-150 or 1e150 keep the same
-    relative error, and an all-zero column maps to an all-zero column."""
+    relative error, and an all-zero column maps to an all-zero column (both kernels)."""
     from paper_2101_07249_amd import wc4d
     w = MEDIUM
-    print("[case] fp16x3 scaling", flush=True)
+    print("[case] fp16x3 scaling", kernel, flush=True)
+    if kernel != "auto":
+        monkeypatch.setenv("WC4D_SPLIT_GEMM_KERNEL", kernel)
     gh, op = _pair(w, wc4d.PREC_SKETCH_FP16X3)
     G = sketch_block(op.n_A, 6, w.seed + 3)
     G[:, 2] = 0.0
@@ -351,3 +357,20 @@ def test_fp16x3_full_size_sampled_columns():
     e = float(col_errors(Y[cols].cpu().numpy().T, Yo).max())
     print("[result] full-size fp16x3 rel err", e, flush=True)
     assert 1e-12 < e <= 1e-5
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "fp16x3"])
+def test_split_kernels_give_the_same_bits(form, monkeypatch):
+    """The LDS-tiled and the fragment-major kernels form the same three products in the
+    same K order, so the block apply is bit-identical whichever one runs (ragged shape:
+    n = K = 700, 1240 columns)."""
+    from paper_2101_07249_amd import wc4d
+    prec = wc4d.PREC_SKETCH_BF16X3 if form == "bf16x3" else wc4d.PREC_SKETCH_FP16X3
+    print("[case] tiled vs fragment-major", form, flush=True)
+    gp, op = _pair(MEDIUM, prec)
+    G = _dev(sketch_block(op.n_A, MEDIUM.m, MEDIUM.seed + 7))
+    out = {}
+    for kernel in ("tiled", "frag"):
+        monkeypatch.setenv("WC4D_SPLIT_GEMM_KERNEL", kernel)
+        out[kernel] = gp.apply_A_prec(G, prec).cpu().numpy()
+    np.testing.assert_array_equal(out["tiled"], out["frag"])
