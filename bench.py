@@ -606,6 +606,12 @@ def main():
             "sweep_hbm_frac": (2 * sweep_bytes / ((stages[1] + stages[2]) * 1e-3) / 1e9) / HBM_PEAK_GBS,
             "dsqrt_gemm_TFLOPs": 2 * gemm_flops / ((stages[0] + stages[3]) * 1e-3) / 1e12,
             "stage_ms": [float(v) for v in stages]}
+    # composite roofline of the whole apply: each stage at its own bound (the two D^{1/2}
+    # products at the float64 MFMA peak, the two sweeps at the HBM peak), summed
+    comp = [gemm_flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3, sweep_bytes / (HBM_PEAK_GBS * 1e9) * 1e3,
+            sweep_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, gemm_flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3]
+    hess.update({"composite_roofline_ms": float(sum(comp)), "composite_roofline_stage_ms": comp,
+                 "composite_roofline_frac": float(sum(comp)) / float(stages.sum())})
 
     # roofline of the kernel class that takes the most time (timed live over the timed region)
     dom = dominant_class(results[head]["prof_classes"])
