@@ -108,7 +108,7 @@ def test_bf16x3_full_size_sampled_columns():
     op = O.make_problem(C3, pat)
     G = sketch_block(gp.n_A, C3.m, C3.seed)
     Y = gp.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_BF16X3)
-    cols = [3, 200]
+    cols = [0, 3, 200, 255]  # the first and last 256-column tiles of the all-level product too
     Yo = O.apply_A(op, G[:, cols])
     e = float(col_errors(Y[cols].cpu().numpy().T, Yo).max())
     print("[result] full-size bf16x3 rel err", e, flush=True)
@@ -352,7 +352,7 @@ def test_fp16x3_full_size_sampled_columns():
     op = O.make_problem(C3, pat)
     G = sketch_block(gp.n_A, C3.m, C3.seed)
     Y = gp.apply_A_prec(_dev(G), wc4d.PREC_SKETCH_FP16X3)
-    cols = [3, 200]
+    cols = [0, 3, 200, 255]  # the first and last 256-column tiles of the all-level product too
     Yo = O.apply_A(op, G[:, cols])
     e = float(col_errors(Y[cols].cpu().numpy().T, Yo).max())
     print("[result] full-size fp16x3 rel err", e, flush=True)
