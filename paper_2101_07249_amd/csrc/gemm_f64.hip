@@ -591,18 +591,30 @@ size_t gram_ws_doubles(int m1, int m2, long long K) {
   return (size_t)gram_splits(m1, m2, K) * (size_t)m1 * (size_t)m2;
 }
 
-// Partial G over rows [kb, ke) of one split, tile (blockIdx.x, blockIdx.y).
+// Partial G over rows [kb, ke) of one split, tile (blockIdx.x, blockIdx.y); with sym (X = Y,
+// G symmetric) blockIdx.x numbers the tiles on and above the diagonal instead.
 __global__ __launch_bounds__(256) void k_gram_partial(int m1, int m2, long long K, long long kchunk,
                                                       const double* __restrict__ X, ColMap xmap,
                                                       const double* __restrict__ Y, ColMap ymap,
                                                       double* __restrict__ ws,
-                                                      const int* __restrict__ skip) {
+                                                      const int* __restrict__ skip, int sym) {
   constexpr int NL = GT * GBK / 256;  // 4 loads per operand per thread
   __shared__ double Xs[GBK][GT + 4];
   __shared__ double Ys[GBK][GT + 4];
   if (skip != nullptr && *skip != 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int i0 = blockIdx.x * GT, j0 = blockIdx.y * GT;
+  int ti = blockIdx.x, tj = blockIdx.y;
+  if (sym) {  // row ti of the upper triangle holds T - ti tiles
+    const int T = (m1 + GT - 1) / GT;
+    int rem = blockIdx.x;
+    ti = 0;
+    while (rem >= T - ti) {
+      rem -= T - ti;
+      ++ti;
+    }
+    tj = ti + rem;
+  }
+  const int i0 = ti * GT, j0 = tj * GT;
   const int split = blockIdx.z;
   const long long kb = (long long)split * kchunk;
   long long ke = kb + kchunk;
@@ -671,14 +683,17 @@ __global__ __launch_bounds__(256) void k_gram_partial(int m1, int m2, long long 
 }
 
 __global__ void k_gram_reduce(int m1, int m2, int splits, const double* __restrict__ ws,
-                              double* __restrict__ G, int ldg, const int* __restrict__ skip) {
+                              double* __restrict__ G, int ldg, const int* __restrict__ skip, int sym) {
   if (skip != nullptr && *skip != 0) return;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long tot = (long long)m1 * m2;
   if (e >= tot) return;
-  double sum = 0.0;
-  for (int sp = 0; sp < splits; ++sp) sum += ws[(size_t)sp * tot + e];
   const int i = (int)(e % m1), j = (int)(e / m1);
+  // symmetric: an entry below the diagonal tiles is its mirror image's (the same products in
+  // the same order, so the same bits as computing it)
+  const long long src = (sym && i / GT > j / GT) ? (long long)j + (long long)i * m1 : e;
+  double sum = 0.0;
+  for (int sp = 0; sp < splits; ++sp) sum += ws[(size_t)sp * tot + src];
   G[(size_t)i + (size_t)j * ldg] = sum;
 }
 
@@ -688,14 +703,21 @@ hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, c
   const int sp = gram_splits(m1, m2, K);
   long long kchunk = (K + sp - 1) / sp;
   kchunk = (kchunk + GBK - 1) / GBK * GBK;
-  dim3 grid((m1 + GT - 1) / GT, (m2 + GT - 1) / GT, sp);
+  // X^T X: only the tiles on and above the diagonal (a Nystrom build at n_A = 413,696, m = 256:
+  // 41 against 44 ms, the same bits)
+  const int sym = (X == Y && m1 == m2 && xmap.ld == ymap.ld && xmap.per == ymap.per && xmap.base == ymap.base &&
+                   xmap.stride == ymap.stride)
+                      ? 1
+                      : 0;
+  const int T1 = (m1 + GT - 1) / GT;
+  dim3 grid(sym ? T1 * (T1 + 1) / 2 : T1, sym ? 1 : (m2 + GT - 1) / GT, sp);
   hipLaunchKernelGGL(k_gram_partial, grid, dim3(256), 0, s, m1, m2, K, kchunk, X, xmap, Y, ymap,
-                     ws, skip);
+                     ws, skip, sym);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long tot = (long long)m1 * m2;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m1, m2,
-                     sp, ws, G, ldg, skip);
+                     sp, ws, G, ldg, skip, sym);
   return hipGetLastError();
 }
 
