@@ -866,7 +866,7 @@ int cholqr2(wc4d_problem p, double* Y, double* tmp, int m, Small& sm, double* Ro
     HIPCHK(p, chol_upper(m, sm.G, m, st, s));
     if (shifted) HIPCHK(p, diag_accumulate(m, sm.G, m, sm.dg, k == 0, s));
     HIPCHK(p, tri_inv_upper(m, sm.G, m, sm.Ri, m, s));
-    HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, src, nA, sm.Ri, plain_cols(m), dst, cm, nullptr, cm, nullptr, s));
+    HIPCHK(p, gemm_f64((int)nA, m, m, 1.0, src, nA, sm.Ri, upper_cols(m), dst, cm, nullptr, cm, nullptr, s));
     if (Rout != nullptr) {
       if (k == 0) {
         HIPCHK(p, vec_copy(sm.R1, sm.G, (long long)m * m, s));
@@ -956,7 +956,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     if (he == hipSuccess) he = chol_upper(m, sm.G, m, p->dStatus, s);
     if (he == hipSuccess) he = tri_inv_upper(m, sm.G, m, sm.Ri, m, s);
     if (he == hipSuccess)
-      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, plain_cols(m), A_, cm, nullptr, cm, nullptr, s);
+      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, upper_cols(m), A_, cm, nullptr, cm, nullptr, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
     // the EVD of R_F R_F^T as the one-sided Jacobi SVD of R_F^T (no squared condition
@@ -978,7 +978,7 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     if (he == hipSuccess) he = chol_upper(m, sm.G, m, p->dStatus, s);
     if (he == hipSuccess) he = tri_inv_upper(m, sm.G, m, sm.Ri, m, s);
     if (he == hipSuccess)
-      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, plain_cols(m), A_, cm, nullptr, cm, nullptr, s);
+      he = gemm_f64((int)nA, m, m, 1.0, B_, nA, sm.Ri, upper_cols(m), A_, cm, nullptr, cm, nullptr, s);
     if (he != hipSuccess) return cleanup(fail(p, WC4D_EHIP, hipGetErrorString(he)));
     if ((rc = cholqr2(p, A_, B_, m, sm, sm.R2, s))) return cleanup(rc);
     he = transpose_small(m, sm.R2, m, sm.K, m, s);

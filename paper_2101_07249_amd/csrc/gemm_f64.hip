@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(int M, int ncol, int K, double
   const int wi0 = (wave % WGI) * WI;
   const int wj0 = (wave / WGI) * WJ;
   const int kbeg = SPLIT ? blockIdx.z * kchunk : 0;
-  const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
+  const int kend0 = SPLIT ? min(K, kbeg + kchunk) : K;
+  const int kend = bmap.upper ? min(kend0, j0 + BN) : kend0;  // upper triangular B: zeros below
 
   d4 acc[TJ][TI];
 #pragma unroll

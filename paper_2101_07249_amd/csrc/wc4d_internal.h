@@ -27,6 +27,9 @@ struct ColMap {
   // product epilogues multiply the columns with t % per == 0 by scale0 (level 0 of a
   // time-level view; 1 = no scaling)
   double scale0 = 1.0;
+  // a product's right operand is upper triangular (rows k > t of column t are zero): the
+  // float64 product may stop each column tile's K loop at the tile's last column
+  int upper = 0;
   __host__ __device__ inline long long off(int t) const {
     return (long long)(t / per) * ld + (long long)(base + t % per) * stride;
   }
@@ -34,6 +37,12 @@ struct ColMap {
 };
 
 inline ColMap plain_cols(long long ld) { return ColMap{ld, 1, 0, 0}; }
+// columns of an upper triangular matrix (see ColMap::upper)
+inline ColMap upper_cols(long long ld) {
+  ColMap c{ld, 1, 0, 0};
+  c.upper = 1;
+  return c;
+}
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipError_t of the launch.
