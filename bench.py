@@ -138,11 +138,13 @@ def parse():
     ap.add_argument("--realisations", type=int, default=50)
     ap.add_argument("--no-second-loop", action="store_true",
                     help="skip the Gauss-Newton second-loop comparison (Section 5.2)")
-    ap.add_argument("--second-loop-realisations", type=int, default=10)
+    ap.add_argument("--second-loop-realisations", type=int, default=5)
     ap.add_argument("--no-strong", action="store_true", help="skip the strong-constraint inner loop")
     ap.add_argument("--no-ritz", action="store_true", help="skip the Ritz-LMP cost study")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-problem batched solve")
     ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--batched-f32", action="store_true",
+                    help="also run the persistent batch with float32 sweeps (another ~60 s)")
     ap.add_argument("--batched-compare", action="store_true",
                     help="also time the host-worker batched solve on the same problems")
     ap.add_argument("--retune", action="store_true",
@@ -247,7 +249,8 @@ def batched_section(args):
     k_r, l = ws[0].k_r, ws[0].l
     out = {"problems": len(ws), "sum_n_A": int(sum(p.n_A for p in probs)), "m": k_r + l, "method": "nystrom",
            "n_range": [min(w.n for w in ws), max(w.n for w in ws)], "N_range": [min(w.N for w in ws), max(w.N for w in ws)]}
-    for name, f32 in (("persistent_f64", False), ("persistent_f32_sweeps", True)):
+    runs = [("persistent_f64", False)] + ([("persistent_f32_sweeps", True)] if args.batched_f32 else [])
+    for name, f32 in runs:
         x = [torch.zeros(p.n_A, dtype=torch.float64, device=p.torch_device) for p in probs]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -510,6 +513,7 @@ def main():
         sys.exit(1)
     from paper_2101_07249_amd import wc4d as W4
 
+    t_start = time.perf_counter()
     dev = torch.device("cuda", 0)
     w = WORKLOADS[args.workload]
     pat = obs_pattern(w)
@@ -670,21 +674,30 @@ def main():
         "hessian_apply": hess,
         "roofline": roof,
     }
+    sections_s = {"variants": time.perf_counter() - t_start}
+
+    def section(name, fn):
+        t = time.perf_counter()
+        out[name] = fn()
+        sections_s[name] = round(time.perf_counter() - t, 1)
+
     if not args.no_learned:
-        out["learned"] = learned_section(args)
+        section("learned", lambda: learned_section(args))
     if not args.no_second_loop:
-        out["second_loop"] = second_loop_section(args)
+        section("second_loop", lambda: second_loop_section(args))
     if not args.no_strong:
-        out["strong_constraint"] = strong_section(args)
+        section("strong_constraint", lambda: strong_section(args))
     if not args.no_ritz:
-        out["ritz_lmp"] = ritz_section(args)
+        section("ritz_lmp", lambda: ritz_section(args))
     if not args.no_batched:
-        out["batched"] = batched_section(args)
+        section("batched", lambda: batched_section(args))
     if not args.no_oversampling:
-        out["oversampling"] = oversampling_section(args)
+        section("oversampling", lambda: oversampling_section(args))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, pat, results["plain"]["pcg_iters"] if "plain" in results else None,
-                                           args)
+        section("cpu_baseline", lambda: cpu_baseline(w, pat, results["plain"]["pcg_iters"] if "plain" in results
+                                                     else None, args))
+    sections_s["variants"] = round(sections_s["variants"], 1)
+    out["sections_s"] = sections_s
     print(json.dumps(out), flush=True)
 
 
