@@ -94,7 +94,7 @@ hipError_t gram_f64(int m1, int m2, long long K, const double* X, ColMap xmap, c
 // given as row-major bf16 hi/lo parts (row i = S(i, 0..K-1)).
 hipError_t split_bf16_rows(int M, int K, const double* S, long long lds, __bf16* Shi, __bf16* Slo,
                            hipStream_t s);
-// Few-column products Y = S X on the int8 matrix cores by a 7-slice error-free splitting
+// Few-column products Y = S X on the int8 matrix cores by a 6-slice error-free splitting
 // (gemm_oz.hip).  oz_split_matrix: slices of S (n x n, column-major, ld lds) into Ss
 // (oz_slices_bytes(n)) and its row exponents es (oz_padded(n) ints), once.  oz_gemm:
 // Y(:, j) = E(:, j) + sc_j (S X)(:, j) for the L columns X + j ldc (sc_0 = scale0, else 1),
