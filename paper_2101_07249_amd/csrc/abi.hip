@@ -172,6 +172,8 @@ int wc4d_destroy(wc4d_problem p) {
   for (int q = 0; q < 2; ++q) {
     if (p->pcgPoll[q] != nullptr) (void)hipHostFree(p->pcgPoll[q]);
     if (p->pcgPollEv[q] != nullptr) (void)hipEventDestroy(p->pcgPollEv[q]);
+    if (p->evdPoll.host[q] != nullptr) (void)hipHostFree(p->evdPoll.host[q]);
+    if (p->evdPoll.ev[q] != nullptr) (void)hipEventDestroy(p->evdPoll.ev[q]);
   }
   for (auto& e : p->ev)
     if (e != nullptr) (void)hipEventDestroy(e);
@@ -1002,7 +1004,14 @@ int lmp_build_once(wc4d_problem p, int method, int k_r, int l, const double* G, 
     Zfinal = B_;
   }
   ProfScope ps_tail(p, s, PROF_BUILD, 8.0 * (double)nA * (m + k_r), 2.0 * (double)nA * m * k_r);
-  he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s, evd_sym);
+  // pinned flags for the EVD's convergence poll (made at the first build)
+  for (int q = 0; q < 2 && he == hipSuccess; ++q) {
+    if (p->evdPoll.host[q] == nullptr)
+      he = hipHostMalloc((void**)&p->evdPoll.host[q], sizeof(int), hipHostMallocDefault);
+    if (he == hipSuccess && p->evdPoll.ev[q] == nullptr)
+      he = hipEventCreateWithFlags(&p->evdPoll.ev[q], hipEventDisableTiming);
+  }
+  if (he == hipSuccess) he = jacobi_evd(m, sm.K, m, sm.lam, sm.V, m, p->dStatus + 4, s, evd_sym, &p->evdPoll);
   if (he == hipSuccess) he = ritz_finish(k_r, sm.lam, mode, L->theta, L->dcoef, s);
   if (he == hipSuccess)
     he = gemm_f64((int)nA, k_r, m, 1.0, Zfinal, nA, sm.V, plain_cols(m), L->U, plain_cols(L->ldu), nullptr,

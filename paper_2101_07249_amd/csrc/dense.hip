@@ -531,7 +531,7 @@ hipError_t shift_diag_trace(int m, double* G, int ldg, double c, hipStream_t s) 
 }
 
 hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
-                      hipStream_t s, bool sym) {
+                      hipStream_t s, bool sym, const EvdPoll* poll) {
   if (m > 512 || m < 1) return hipErrorInvalidValue;
   const OjCfg c = oj_cfg(m);
   const size_t lds = sizeof(double) * 4 * (size_t)c.bs * m;
@@ -546,6 +546,12 @@ hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv
   hipLaunchKernelGGL(k_oj_init, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, ctrl, sym ? 1 : 0);
   const int max_sweeps = 20;
   for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (poll != nullptr && sw >= 2) {
+      // the flag copied after sweep sw - 2; sweep sw - 1 keeps the device busy meanwhile
+      const hipError_t e = hipEventSynchronize(poll->ev[sw & 1]);
+      if (e != hipSuccess) return e;
+      if (*poll->host[sw & 1] != 0) break;
+    }
     for (int r = 0; r < c.nblk - 1; ++r) {
       if (m <= 256)
         hipLaunchKernelGGL(k_oj_round<4>, dim3(c.nblk / 2), dim3(kOJT), lds, s, m, c.bs, c.nblk, r, K, ldk, V, ldv,
@@ -555,6 +561,11 @@ hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv
                            ctrl, tol);
     }
     hipLaunchKernelGGL(k_oj_sweep_end, dim3(1), dim3(64), 0, s, ctrl);
+    if (poll != nullptr) {
+      hipError_t e = hipMemcpyAsync(poll->host[sw & 1], ctrl, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipEventRecord(poll->ev[sw & 1], s);
+      if (e != hipSuccess) return e;
+    }
   }
   hipLaunchKernelGGL(k_oj_finish, dim3(1), dim3(kOJT), 0, s, m, K, ldk, V, ldv, lam);
   return hipGetLastError();

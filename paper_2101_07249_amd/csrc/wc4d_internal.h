@@ -210,9 +210,17 @@ hipError_t small_gemm(int M, int N, int K, double alpha, const double* A, int ld
 // ldv), each vector's largest-magnitude entry positive.  K is overwritten; ctrl:
 // 2 device ints of scratch.  With sym = false K is taken as it is (any square F): the
 // same iteration then gives the singular values of F in lam and its right singular
-// vectors in V, i.e. the eigenpairs (lam^2, V) of F^T F without forming it.
+// vectors in V, i.e. the eigenpairs (lam^2, V) of F^T F without forming it.  With poll
+// (two pinned ints and two events, owned by the caller) the host keeps two sweeps in
+// flight and enqueues no more once a finished sweep has found the iteration converged
+// (it waits on the events); without it all 20 sweeps are enqueued, the ones after
+// convergence returning at once.  The results are the same either way.
+struct EvdPoll {
+  int* host[2];
+  hipEvent_t ev[2];
+};
 hipError_t jacobi_evd(int m, double* K, int ldk, double* lam, double* V, int ldv, int* ctrl,
-                      hipStream_t s, bool sym = true);
+                      hipStream_t s, bool sym = true, const EvdPoll* poll = nullptr);
 // B = A^T for m x m matrices (column-major).
 hipError_t transpose_small(int m, const double* A, int lda, double* B, int ldb, hipStream_t s);
 // theta[i] = f(lam[i]) for i < k: f = identity (mode 0), sqrt (mode 1) or square (mode 2);
@@ -501,6 +509,7 @@ struct wc4d_problem_s {
   wc4d::PcgState* pcgStateHost = nullptr;  // pinned
   wc4d::PcgState* pcgPoll[2] = {nullptr, nullptr};  // pinned copies read while the next chunk runs
   hipEvent_t pcgPollEv[2] = {nullptr, nullptr};
+  wc4d::EvdPoll evdPoll = {{nullptr, nullptr}, {nullptr, nullptr}};  // the build's Jacobi EVD
   // per-class kernel timing
   int kprof = 0;           // classes timed by ProfScope (bit c: class c)
   int kprofEvery = 1;      // ... one launch group in kprofEvery per class
