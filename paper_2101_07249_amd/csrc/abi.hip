@@ -804,6 +804,7 @@ void wc4d::lmp_release(wc4d_lmp L) {
   dev_free(&L->T);
   dev_free(&L->ws);
   dev_free(&L->wsv);
+  dev_free(&L->wsr);
   dev_free(&L->GU);
   dev_free(&L->fu);
   dev_free(&L->Up);
@@ -1372,6 +1373,12 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
   double* tvec = nullptr;
   const LmpU Us = (L == nullptr) ? LmpU() : L->streamed();
   const bool panels = Us.fmt != LMP_F64;
+  // float16 panels: the refresh of u = U^T r shares the p-update launch and the next
+  // iteration's final-sum launch (same arithmetic as the separate refresh launches)
+  const bool share_refresh = fused && Us.fmt == LMP_P16;
+  if (share_refresh && L->wsr == nullptr) {
+    if ((rc = dev_alloc(p, &L->wsr, lmp_pan16_refresh_doubles(nA, L->k)))) return rc;
+  }
   if (fused) {
     u = L->fu;
     d12 = L->fu + L->k;
@@ -1395,7 +1402,11 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
         if ((rc = apply_A_core(p, pv, nA, Ap, nA, 1, done, s))) return rc;
         {
           ProfScope ps(p, s, PROF_LMP_T, ub + 16.0 * nA, fl + 2.0 * nA);
-          HIPCHK(p, lmp_pan_t_partials(nA, L->k, Us, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
+          if (share_refresh)
+            HIPCHK(p, lmp_pan16_t_partials_refresh(nA, L->k, Us, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done,
+                                                   L->wsr, u, &st->no_refresh, s));
+          else
+            HIPCHK(p, lmp_pan_t_partials(nA, L->k, Us, Ap, pv, L->wsv, pcg_dot_slots(p->pcgRed), done, s));
         }
         HIPCHK(p, pcg_lmp_coeffs_pan(st, L->k, lmp_pan_t_splits(nA, L->k, Us.fmt), tvec, p->pcgRed, L->dcoef,
                                      L->GU, u, d12, s));
@@ -1403,8 +1414,12 @@ int pcg_run(wc4d_problem p, wc4d_lmp L, const double* b, double* x, const wc4d_p
           ProfScope ps(p, s, PROF_LMP_N, ub + 8.0 * 9.0 * nA, 2.0 * fl);
           HIPCHK(p, pcg_lmp_dual_pan(st, nA, L->k, Us, d12, Ap, r, z, x, sres, b, pv, p->pcgRed, p->pcgHist, s));
         }
-        HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
-        HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        if (share_refresh) {
+          HIPCHK(p, pcg_update_p_refresh16(st, pv, z, nA, L->k, Us, r, L->wsr, s));
+        } else {
+          HIPCHK(p, pcg_update_p(st, pv, z, nA, s));
+          HIPCHK(p, lmp_gemv_t(nA, L->k, Us, nullptr, r, L->wsv, &st->no_refresh, s, u));
+        }
         continue;
       }
       if (fused) {

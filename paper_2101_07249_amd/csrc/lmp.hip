@@ -137,18 +137,36 @@ __global__ __launch_bounds__(kLT) void k_lmp_gemv_t_partial(long long nA, int k,
 
 // Partial (split b, column c) at part[b sb + c sc]: (sb, sc) = (k, 1) for the split-major
 // partials, (1, splits) for the column-major ones of the row-owning float16 pass.
-__global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__ part,
-                                   const double* __restrict__ dcoef, double* __restrict__ t,
-                                   const int* __restrict__ skip, long long sb, long long sc) {
+__device__ __forceinline__ void gemv_t_final_body(int bid, int splits, int k, const double* __restrict__ part,
+                                                  const double* __restrict__ dcoef, double* __restrict__ t,
+                                                  const int* __restrict__ skip, long long sb, long long sc) {
   if (skip != nullptr && *skip != 0) return;
   // one wavefront per column: lanes stride the splits, then a fixed-order tree
-  const int c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const int c = bid * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= k) return;
   double s = 0.0;
   for (int b = lane; b < splits; b += 64) s += part[(size_t)b * sb + (size_t)c * sc];
   s = wave_sum_d(s);
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
+}
+
+__global__ void k_lmp_gemv_t_final(int splits, int k, const double* __restrict__ part,
+                                   const double* __restrict__ dcoef, double* __restrict__ t,
+                                   const int* __restrict__ skip, long long sb, long long sc) {
+  gemv_t_final_body(blockIdx.x, splits, k, part, dcoef, t, skip, sb, sc);
+}
+
+// Two such sums in one launch (workgroups [0, nb) the first, [nb, 2 nb) the second), each
+// with its own partials, output and skip flag; same split count and strides.
+__global__ void k_lmp_gemv_t_final2(int nb, int splits, int k, const double* __restrict__ part1,
+                                    double* __restrict__ t1, const int* __restrict__ skip1,
+                                    const double* __restrict__ part2, double* __restrict__ t2,
+                                    const int* __restrict__ skip2, long long sb, long long sc) {
+  if ((int)blockIdx.x < nb)
+    gemv_t_final_body(blockIdx.x, splits, k, part1, nullptr, t1, skip1, sb, sc);
+  else
+    gemv_t_final_body(blockIdx.x - nb, splits, k, part2, nullptr, t2, skip2, sb, sc);
 }
 
 // 4 consecutive rows per thread: two 16-byte loads per column; requires ldu % 4 == 0
@@ -396,16 +414,15 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t_partial(long long nA, int 
 // PCG at n_A = 413,696, k = 251: 45.2 us with 4 panels per workgroup, against 53.1 us for 16
 // columns x 2 rows per thread (x re-read by every column group); JC = 2 with 2 panels
 // each ran 46.3 us, shapes whose grid is not resident at once 55-60 us.
+// The body takes its workgroup's index bid among nblk workgroups of the pass, so that a
+// launch can also carry other work in workgroups past nblk.
 constexpr int kXP = 4;
 template <int JC, int QU>
-__global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k, long long pan_per,
-                                                             const _Float16* __restrict__ P,
-                                                             const int* __restrict__ cexp,
-                                                             const double* __restrict__ x,
-                                                             double* __restrict__ part,
-                                                             const int* __restrict__ skip,
-                                                             const double* __restrict__ pdot,
-                                                             double* __restrict__ dotpart) {
+__device__ __forceinline__ void pan_t16_rows_body(int bid, int nblk, long long nA, int k, long long pan_per,
+                                                  const _Float16* __restrict__ P, const int* __restrict__ cexp,
+                                                  const double* __restrict__ x, double* __restrict__ part,
+                                                  const int* __restrict__ skip, const double* __restrict__ pdot,
+                                                  double* __restrict__ dotpart) {
   typedef _Float16 h8 __attribute__((ext_vector_type(8)));
   constexpr int CW = 8 * JC;        // columns per chunk
   constexpr int LPC = 32 / JC;      // lanes that end up holding one column's sum
@@ -416,7 +433,7 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = 2 * wave + (lane >> 5), l32 = lane & 31, r8 = 8 * l32;
   const long long np = lmp_panels(nA);
-  const long long pb = (long long)blockIdx.x * pan_per;
+  const long long pb = (long long)bid * pan_per;
   long long pe = pb + pan_per;
   if (pe > np) pe = np;
   for (int c = threadIdx.x; c < k; c += kPanel) tsum[c] = 0.0;
@@ -487,13 +504,47 @@ __global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k
     }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < k; c += kPanel) part[(size_t)c * gridDim.x + blockIdx.x] = ldexp(tsum[c], cexp[c]);
+  for (int c = threadIdx.x; c < k; c += kPanel) part[(size_t)c * nblk + bid] = ldexp(tsum[c], cexp[c]);
   if (pdot != nullptr) {
     dv = wave_sum_d(dv);
     if (lane == 0) shd[wave] = dv;
     __syncthreads();
-    if (threadIdx.x == 0) dotpart[blockIdx.x] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
+    if (threadIdx.x == 0) dotpart[bid] = (shd[0] + shd[1]) + (shd[2] + shd[3]);
   }
+}
+
+template <int JC, int QU>
+__global__ __launch_bounds__(kPanel) void k_lmp_pan_t16_rows(long long nA, int k, long long pan_per,
+                                                             const _Float16* __restrict__ P,
+                                                             const int* __restrict__ cexp,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ part,
+                                                             const int* __restrict__ skip,
+                                                             const double* __restrict__ pdot,
+                                                             double* __restrict__ dotpart) {
+  pan_t16_rows_body<JC, QU>(blockIdx.x, gridDim.x, nA, k, pan_per, P, cexp, x, part, skip, pdot, dotpart);
+}
+
+// The end of a fused PCG iteration in one launch: workgroups [0, G) form the partials of
+// U^T r over the float16 panels when the iteration's beta kernel asked for a refresh of
+// u = U^T r (*no_refresh == 0; they return at once otherwise), the rest update p = z + beta p
+// (nothing once the solve is done).  r is not written and p not read by the pass.
+template <int JC, int QU>
+__global__ __launch_bounds__(kPanel) void k_update_p_refresh16(const PcgState* __restrict__ st, double* __restrict__ p,
+                                                               const double* __restrict__ z, long long nA, int k,
+                                                               long long pan_per, int G,
+                                                               const _Float16* __restrict__ P,
+                                                               const int* __restrict__ cexp,
+                                                               const double* __restrict__ r,
+                                                               double* __restrict__ rpart) {
+  if ((int)blockIdx.x < G) {
+    pan_t16_rows_body<JC, QU>(blockIdx.x, G, nA, k, pan_per, P, cexp, r, rpart, &st->no_refresh, nullptr, nullptr);
+    return;
+  }
+  if (st->done) return;
+  const double beta = st->beta;
+  const long long stride = (long long)(gridDim.x - G) * kPanel;
+  for (long long i = (long long)(blockIdx.x - G) * kPanel + threadIdx.x; i < nA; i += stride) p[i] = z[i] + beta * p[i];
 }
 
 // y = x + U t over panels: wave w of a 256-thread block takes columns w, w + 4, ...
@@ -575,6 +626,29 @@ hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* 
   const int sp = launch_pan_t_partial(nA, k, U, x, ws, skip, pdot, dotpart, s, &sb, &sc);
   hipLaunchKernelGGL(k_lmp_gemv_t_final, dim3((k + 3) / 4), dim3(256), 0, s, sp, k, ws, nullptr,
                      ws + lmp_gemv_t_offset(nA, k), skip, sb, sc);
+  return hipGetLastError();
+}
+
+hipError_t lmp_pan16_t_partials_refresh(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
+                                        double* ws, double* dotpart, const int* skip, const double* rpart,
+                                        double* u, const int* no_refresh, hipStream_t s) {
+  if (U.fmt != LMP_P16) return hipErrorInvalidValue;
+  long long sb, sc;
+  const int sp = launch_pan_t_partial(nA, k, U, x, ws, skip, pdot, dotpart, s, &sb, &sc);
+  const int nb = (k + 3) / 4;
+  hipLaunchKernelGGL(k_lmp_gemv_t_final2, dim3(2 * nb), dim3(256), 0, s, nb, sp, k, ws,
+                     ws + lmp_gemv_t_offset(nA, k), skip, rpart, u, no_refresh, sb, sc);
+  return hipGetLastError();
+}
+
+size_t lmp_pan16_refresh_doubles(long long nA, int k) { return (size_t)rows_grid(nA) * k; }
+
+hipError_t pcg_update_p_refresh16(const PcgState* st, double* p, const double* z, long long nA, int k,
+                                  const LmpU& U, const double* r, double* rpart, hipStream_t s) {
+  if (U.fmt != LMP_P16) return hipErrorInvalidValue;
+  const int G = rows_grid(nA);
+  hipLaunchKernelGGL((k_update_p_refresh16<4, 2>), dim3(G + 2048), dim3(kPanel), 0, s, st, p, z, nA, k,
+                     rows_pan_per(nA), G, (const _Float16*)U.p, U.cexp, r, rpart);
   return hipGetLastError();
 }
 

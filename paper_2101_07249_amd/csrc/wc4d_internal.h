@@ -348,6 +348,17 @@ int lmp_pan_t_splits(long long nA, int k, LmpFmt fmt);
 hipError_t lmp_pan_t_partials(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
                               double* ws, double* dotpart, const int* skip, hipStream_t s);
 double* pcg_dot_slots(double* red);
+// The fused PCG's launches over a float16 panel copy with the refresh of u = U^T r spread
+// over two launches (same arithmetic and order as lmp_gemv_t's): the partials of U^T r
+// (into rpart, lmp_pan16_refresh_doubles(nA, k)) ride in the p-update launch
+// (pcg_update_p_refresh16), and their sum into u in the launch that sums the next
+// iteration's U^T Ap partials (lmp_pan16_t_partials_refresh; u untouched when *no_refresh).
+hipError_t lmp_pan16_t_partials_refresh(long long nA, int k, const LmpU& U, const double* x, const double* pdot,
+                                        double* ws, double* dotpart, const int* skip, const double* rpart,
+                                        double* u, const int* no_refresh, hipStream_t s);
+size_t lmp_pan16_refresh_doubles(long long nA, int k);
+hipError_t pcg_update_p_refresh16(const PcgState* st, double* p, const double* z, long long nA, int k,
+                                  const LmpU& U, const double* r, double* rpart, hipStream_t s);
 hipError_t pcg_lmp_coeffs_pan(PcgState* st, int k, int sp, const double* t, const double* red,
                               const double* dcoef, const double* GU, double* u, double* d12,
                               hipStream_t s);
@@ -548,6 +559,7 @@ struct wc4d_lmp_s {
   size_t wsDoubles = 0;
   double* wsv = nullptr;    // single-vector workspace
   size_t wsvDoubles = 0;
+  double* wsr = nullptr;    // partials of the fused PCG's u = U^T r refresh (float16 copy)
   void* Up = nullptr;       // panel copy of U (WC4D_PREC_LMP_FP32 / _FP16), see kPanel
   wc4d::LmpFmt ufmt = wc4d::LMP_F64;  // format of the U the PCG streams
   int* cexp = nullptr;      // float16 copy: column exponents (k)
