@@ -229,7 +229,7 @@ def batched_section(args):
     """64 uneven advection-diffusion inner loops (n in [512, 8192], N in [10, 200], m = 64,
     Nystrom): every problem's LMP built from its seeded device Gaussian block, then all PCG
     iterations of all problems in one persistent launch (wc4d_batch_solve_persistent),
-    with float64 sweeps and with float32 sweeps; then the host-worker form (wc4d_batch_solve,
+    with float64 sweeps (and with float32 sweeps under --batched-f32); then the host-worker form (wc4d_batch_solve,
     4 workers) with the PCG's one-vector D^{1/2} products on the int8 matrix cores; wall time
     of the whole call (builds included), the persistent launch's own time, iterations and
     true residuals with the float64 operator.  With --batched-compare also the host-worker
