@@ -181,13 +181,41 @@ __global__ __launch_bounds__(kRT) void k_update_r(const PcgState* __restrict__ s
   if (threadIdx.x == 0) red[2 * kRB + blockIdx.x] = t;
 }
 
+// The three sums of kRB partials in one pass: every thread's loads of all three are in
+// flight together, and one pair of barriers combines the wavefronts (each sum in the same
+// order as final_sum's).
+static __device__ inline void final_sum3(const double* red, double* sh, double& s0, double& s1, double& s2) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int b = threadIdx.x; b < kRB; b += blockDim.x) {
+    v0 += red[b];
+    v1 += red[kRB + b];
+    v2 += red[2 * kRB + b];
+  }
+  v0 = wave_sum_d(v0);
+  v1 = wave_sum_d(v1);
+  v2 = wave_sum_d(v2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  __syncthreads();
+  if (lane == 0) {
+    sh[wave] = v0;
+    sh[nw + wave] = v1;
+    sh[2 * nw + wave] = v2;
+  }
+  __syncthreads();
+  s0 = s1 = s2 = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < nw; ++w) s0 += sh[w];
+    for (int w = 0; w < nw; ++w) s1 += sh[nw + w];
+    for (int w = 0; w < nw; ++w) s2 += sh[2 * nw + w];
+  }
+}
+
 __global__ __launch_bounds__(kRT) void k_beta_final(PcgState* st, const double* __restrict__ red,
                                                     double* __restrict__ hist) {
-  __shared__ double sh[16];
+  __shared__ double sh[3 * (kRT / 64)];
   if (st->done) return;
-  const double ss = final_sum(red, sh);
-  const double xbs = final_sum(red + kRB, sh);
-  const double rr = final_sum(red + 2 * kRB, sh);
+  double ss, xbs, rr;
+  final_sum3(red, sh, ss, xbs, rr);
   if (threadIdx.x == 0) {
     const int it = st->iter + 1;
     st->iter = it;
@@ -691,6 +719,21 @@ __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ s
   if (threadIdx.x == 0) s_done = st->done;
   __syncthreads();
   if (s_done) return;
+  // loads that do not wait for alpha first: t and d1 = dcoef .* t into LDS, this thread's
+  // entries of its GU row; then p.Ap from the pass's partials
+  for (int c = threadIdx.x; c < k; c += kRT) {
+    const double t = tv[c];
+    stv[c] = t;
+    sd1[c] = dcoef[c] * t;
+  }
+  const int c = blockIdx.x * kCR + (threadIdx.x >> 5), sub = threadIdx.x & 31;
+  constexpr int kGH = 16;  // GU entries held per thread (k <= 512)
+  double gr[kGH];
+#pragma unroll
+  for (int q = 0; q < kGH; ++q) {
+    const int j = sub + 32 * q;
+    gr[q] = (c < k && j < k) ? GU[(size_t)c * k + j] : 0.0;
+  }
   double v = 0.0;
   for (int b = threadIdx.x; b < sp; b += kRT) v += dotpart[b];
   const double pap = block_sum(v, sh);
@@ -712,17 +755,13 @@ __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ s
   __syncthreads();
   const double alpha = s_alpha;
   if (alpha < 0.0) return;
-  for (int c = threadIdx.x; c < k; c += kRT) {
-    const double t = tv[c];
-    stv[c] = t;
-    sd1[c] = dcoef[c] * t;
-  }
-  __syncthreads();
-  const int c = blockIdx.x * kCR + (threadIdx.x >> 5), sub = threadIdx.x & 31;
   double g = 0.0;
   if (c < k) {
-    const double* row = GU + (size_t)c * k;
-    for (int j = sub; j < k; j += 32) g += row[j] * sd1[j];
+#pragma unroll
+    for (int q = 0; q < kGH; ++q) {
+      const int j = sub + 32 * q;
+      if (j < k) g += gr[q] * sd1[j];
+    }
   }
 #pragma unroll
   for (int o = 16; o > 0; o >>= 1) g += __shfl_xor(g, o, 64);
