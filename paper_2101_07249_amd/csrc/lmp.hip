@@ -145,8 +145,19 @@ __device__ __forceinline__ void gemv_t_final_body(int bid, int splits, int k, co
   const int c = bid * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (c >= k) return;
+  // eight loads in flight per lane, then added in split order
   double s = 0.0;
-  for (int b = lane; b < splits; b += 64) s += part[(size_t)b * sb + (size_t)c * sc];
+  for (int b0 = lane; b0 < splits; b0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int b = b0 + 64 * q;
+      v[q] = b < splits ? part[(size_t)b * sb + (size_t)c * sc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (b0 + 64 * q < splits) s += v[q];
+  }
   s = wave_sum_d(s);
   if (lane == 0) t[c] = (dcoef != nullptr) ? dcoef[c] * s : s;
 }

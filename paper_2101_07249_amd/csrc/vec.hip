@@ -185,8 +185,10 @@ __global__ __launch_bounds__(kRT) void k_update_r(const PcgState* __restrict__ s
 // flight together, and one pair of barriers combines the wavefronts (each sum in the same
 // order as final_sum's).
 static __device__ inline void final_sum3(const double* red, double* sh, double& s0, double& s1, double& s2) {
+  // a block of kRT threads (the loop's trip count is then known, so all loads are in flight)
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-  for (int b = threadIdx.x; b < kRB; b += blockDim.x) {
+#pragma unroll
+  for (int b = threadIdx.x; b < kRB; b += kRT) {
     v0 += red[b];
     v1 += red[kRB + b];
     v2 += red[2 * kRB + b];
@@ -194,7 +196,7 @@ static __device__ inline void final_sum3(const double* red, double* sh, double& 
   v0 = wave_sum_d(v0);
   v1 = wave_sum_d(v1);
   v2 = wave_sum_d(v2);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = kRT / 64;
   __syncthreads();
   if (lane == 0) {
     sh[wave] = v0;
@@ -734,8 +736,17 @@ __global__ __launch_bounds__(kRT) void k_pcg_coeffs_pan(PcgState* __restrict__ s
     const int j = sub + 32 * q;
     gr[q] = (c < k && j < k) ? GU[(size_t)c * k + j] : 0.0;
   }
+  // sp <= kRB partials: all of a thread's loads in flight, then added in order
+  double pv[kRB / kRT];
+#pragma unroll
+  for (int q = 0; q < kRB / kRT; ++q) {
+    const int b = threadIdx.x + kRT * q;
+    pv[q] = b < sp ? dotpart[b] : 0.0;
+  }
   double v = 0.0;
-  for (int b = threadIdx.x; b < sp; b += kRT) v += dotpart[b];
+#pragma unroll
+  for (int q = 0; q < kRB / kRT; ++q)
+    if (threadIdx.x + kRT * q < sp) v += pv[q];
   const double pap = block_sum(v, sh);
   if (threadIdx.x == 0) {
     const bool ok = pap > 0.0 && isfinite(pap);
